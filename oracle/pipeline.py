@@ -1,0 +1,84 @@
+"""The parameter-search hot path composed end to end on the CPU.
+
+Test infrastructure only (see the package docstring).
+
+Sec. III.B: simulate views of the images over the (t, phi) grid, run ORB on
+every view, match views with a brute-force Hamming matcher and keep the view
+pair with the most matches; the matched points of that pair are mapped back
+to the original images (Sec. IV.B evaluates them with eqs. (5)-(6)).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import match as M
+from . import orb as O
+from . import plan as P
+from . import simulate as S
+
+
+@dataclass
+class OrbOptions:
+    n_levels: int = 8
+    scale: float = 1.2
+    n_features: int = 1000
+    fast_threshold: int = 20
+    ratio_num: int = 4
+    ratio_den: int = 5
+
+
+def plan_image(w: int, h: int, grid, psi: float = 0.0, s: float = 1.0):
+    return [P.plan_view(w, h, t, phi, psi, s) for (t, phi) in grid]
+
+
+def simulate_image(src_u8, views):
+    """Per view (V fp64, mask, u8)."""
+    return [S.simulate_view(src_u8, v) for v in views]
+
+
+def extract_image(sims, views, opts: OrbOptions, pattern):
+    quotas = P.level_quotas(opts.n_features, opts.n_levels, opts.scale)
+    feats = []
+    for (V, mask, U), v in zip(sims, views):
+        dims = P.level_dims(v.width, v.height, opts.n_levels, opts.scale)
+        feats.append(O.extract_view(U, mask, dims, quotas, opts.fast_threshold, pattern))
+    return feats
+
+
+def keypoints_to_source(feat, view, opts: OrbOptions):
+    dims = P.level_dims(view.width, view.height, opts.n_levels, opts.scale)
+    lw = np.array([d[0] for d in dims])
+    lh = np.array([d[1] for d in dims])
+    lv = feat["level"]
+    x0, y0 = M.level_to_view(feat["x"], feat["y"], lw[lv], lh[lv], view.width, view.height)
+    return M.view_to_source(view, x0, y0)
+
+
+def match_pair(A, B, grid_a, grid_b, opts: OrbOptions, pattern):
+    """Full path for one image pair.  Returns a dict with per-view features, the
+    pair counts, the best pair and its accepted matches in source coordinates."""
+    va = plan_image(A.shape[1], A.shape[0], grid_a)
+    vb = plan_image(B.shape[1], B.shape[0], grid_b)
+    sa = simulate_image(A, va)
+    sb = simulate_image(B, vb)
+    fa = extract_image(sa, va, opts, pattern)
+    fb = extract_image(sb, vb, opts, pattern)
+    results, counts, best = M.match_views([f["desc"] for f in fa], [f["desc"] for f in fb],
+                                          opts.ratio_num, opts.ratio_den)
+    k, i, j, c = best
+    out = dict(views_a=va, views_b=vb, sims_a=sa, sims_b=sb, feats_a=fa, feats_b=fb,
+               results=results, counts=counts, best=best)
+    if k >= 0:
+        idx, d1, d2, acc = results[k]
+        qa = np.flatnonzero(acc)
+        tb = idx[qa]
+        xa, ya = keypoints_to_source(fa[i], va[i], opts)
+        xb, yb = keypoints_to_source(fb[j], vb[j], opts)
+        out["pa"] = np.stack([xa[qa], ya[qa]], axis=1)
+        out["pb"] = np.stack([xb[tb], yb[tb]], axis=1)
+    else:
+        out["pa"] = np.zeros((0, 2))
+        out["pb"] = np.zeros((0, 2))
+    return out
