@@ -1,0 +1,237 @@
+/*
+ * xaffine -- affine view simulation, ORB extraction and all-view-pair Hamming
+ * matching on AMD Instinct MI355X (gfx950).
+ *
+ * The library computes the parameter-search stage of "Feature Point
+ * Extraction for Extra-Affine Image" (arXiv 2503.03479, Sec. III.B): views of
+ * an image are simulated over a grid of tilts t and longitudes phi (the
+ * camera model of eq. (2), resampled with the Lanczos kernel of eqs. (3)-(4)
+ * after an anti-alias blur along the tilt direction), ORB features are
+ * extracted on every view, every view of image A is matched against every
+ * view of image B with a brute-force Hamming matcher and a ratio test
+ * (Sec. IV.C), and the view pair with the most matches gives the optimal
+ * parameter group.
+ *
+ * Conventions for every entry point
+ *  - Pointers named d_* are device pointers owned by the caller.  The library
+ *    never allocates device memory; each call that needs scratch space takes a
+ *    workspace (d_ws, ws_bytes) whose minimum size a *_workspace_size query
+ *    returns.  Workspaces must be 256-byte aligned.
+ *  - Device work is enqueued on `stream` and is asynchronous: outputs are valid
+ *    once the stream has been synchronised.  No call synchronises the stream.
+ *  - A plan is a flat, relocatable byte blob written by xa_plan_image.  Calls
+ *    take it twice: plan_host (host memory, used for launch geometry) and
+ *    plan_dev (a byte-for-byte device copy made by the caller, read by kernels).
+ *  - Images are row-major uint8 with a row pitch in bytes.  All coordinates are
+ *    pixel centres: pixel (x, y) covers [x-1/2, x+1/2] x [y-1/2, y+1/2].
+ *  - Errors: every call returns an xa_status; on anything but XA_OK the outputs
+ *    are undefined and xa_last_error() returns a message (thread-local, valid
+ *    until the next call on the same thread).  Invalid arguments are detected
+ *    on the host before anything is enqueued.  Faults inside kernels surface as
+ *    XA_EHIP on a later call or on the caller's own stream synchronisation.
+ *  - No C++ exception crosses this interface.
+ */
+#ifndef XAFFINE_H
+#define XAFFINE_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    XA_OK = 0,
+    XA_EINVAL = -1,        /* bad argument (size, pointer, parameter range, plan magic) */
+    XA_ECAPACITY = -2,     /* a caller-provided buffer or workspace is too small */
+    XA_EHIP = -3,          /* the HIP runtime reported an error */
+    XA_EUNSUPPORTED = -4   /* a size beyond a documented library limit */
+} xa_status;
+
+#define XA_PLAN_MAGIC 0x58414650u   /* "XAFP" */
+#define XA_PLAN_VERSION 1u
+#define XA_MAX_LEVELS 12
+#define XA_MAX_QUOTA 2048           /* keypoints per pyramid level */
+#define XA_MAX_FEATURES 4096        /* keypoints per view */
+#define XA_DESC_BYTES 32            /* rBRIEF-256 */
+
+/* One simulated camera change, eq. (2): A = T R1(psi) S T_tau R2(phi).
+ * t >= 1 is the tilt (latitude theta = arccos 1/t), phi the longitude and
+ * psi the spin (radians), s > 0 the scale (s > 1 magnifies), (tx, ty) a
+ * translation of the content inside the view canvas (pixels). */
+typedef struct {
+    double t, phi, psi, s, tx, ty;
+} xa_affine_params;
+
+/* A planned view.  fwd maps source to view, inv view to source, both 2x3
+ * row-major (x' = m[0] x + m[1] y + m[2], y' = m[3] x + m[4] y + m[5]).
+ * The linear part is s R(psi) diag(1/t, 1) R(phi); the canvas is the bounding
+ * box of the source rectangle under it.  sigma is the standard deviation (in
+ * source pixels) of the anti-alias Gaussian applied along (ux, uy), the
+ * source direction the tilt compresses: sigma = 0.8 sqrt(t^2 - 1), 0 for t = 1. */
+typedef struct {
+    xa_affine_params p;
+    int32_t src_w, src_h;
+    int32_t width, height;      /* canvas W' x H' */
+    double fwd[6];
+    double inv[6];
+    double sigma;
+    double ux, uy;
+    int64_t offset;             /* byte offset of level 0 in the pyramid arena */
+    int64_t blur_offset;        /* float offset of the blurred source in the simulate workspace, -1 if none */
+    int32_t blur_major;         /* 0: taps step along x, 1: along y */
+    int32_t blur_tap0;          /* first entry in the tap table */
+    int32_t blur_ntaps;         /* 2K + 1, 0 if no blur */
+    int32_t pad;
+} xa_view_desc;
+
+/* One pyramid level of one view.  Level sizes are round(W' / scale^l);
+ * quota is the number of keypoints the level may contribute. */
+typedef struct {
+    int32_t width, height;
+    int64_t offset;             /* byte offset of this level in the pyramid arena */
+    int32_t quota;
+    int32_t kp_base;            /* sum of the quotas of the lower levels of the view */
+    int32_t view, level;
+    int64_t cand_offset;        /* first entry of this level in the candidate arena */
+    int64_t cand_cap;           /* ceil(W/2) ceil(H/2): bound on corners that survive 3x3 NMS */
+} xa_level_desc;
+
+/* Plan header; the blob holds the tables at the byte offsets given here. */
+typedef struct {
+    uint32_t magic, version;
+    int32_t src_w, src_h;
+    int32_t n_views, n_levels;
+    int32_t n_features, fast_threshold;
+    double level_scale;
+    int64_t total_bytes;        /* size of the blob */
+    int64_t arena_bytes;        /* u8 pyramid arena: every level of every view */
+    int64_t cand_total;         /* entries of the candidate arena */
+    int64_t blur_floats;        /* floats of blurred sources (simulate workspace) */
+    int32_t n_blur;             /* views with sigma > 0 */
+    int32_t n_taps_total;
+    int64_t off_views;          /* xa_view_desc[n_views] */
+    int64_t off_levels;         /* xa_level_desc[n_views * n_levels], view-major */
+    int64_t off_taps;           /* blur taps: n_taps_total x {float w; int32 dmaj; int32 dmin; float frac} */
+    int64_t off_blur_views;     /* int32[n_blur]: view index of each blurred view */
+    int64_t off_warp_prefix;    /* int32[n_views + 1]: first warp tile of each view */
+    int64_t off_level_prefix;   /* int32[n_levels][n_views + 1]: first tile of each view at each level */
+    int64_t off_vl_prefix;      /* int32[n_views * n_levels + 1]: first tile of each (view, level) */
+} xa_plan_header;
+
+/* A keypoint in canonical order within its view: level ascending, then Harris
+ * response descending, then raster position (y W_l + x) ascending.  (x, y)
+ * are level pixel coordinates; (xs, ys) the source-image coordinates of the
+ * keypoint, (x + 1/2) W'/W_l - 1/2 (likewise y) mapped through inv. */
+typedef struct {
+    int32_t x, y, level, bin;
+    int64_t harris;
+    double xs, ys;
+} xa_keypoint;
+
+/* Nearest neighbour of one query in one view pair: t = train index of the
+ * nearest descriptor (smallest index on ties), d1 its distance, d2 the
+ * smallest distance to any other train descriptor.  t = -1 and d1 = d2 =
+ * 65535 when the train set is empty; d2 = 65535 when it has one element. */
+typedef struct {
+    int32_t t;
+    uint16_t d1, d2;
+} xa_match;
+
+/* Outputs of xa_match_pair (device pointers, caller-allocated):
+ *  kp_a/desc_a/count_a : [n_views_a][n_features] keypoints, [..][32] bytes, [n_views_a] counts
+ *  kp_b/desc_b/count_b : same for image B
+ *  matches             : [n_views_a * n_views_b][n_features], pair k = i * n_views_b + j
+ *  pair_count          : [n_views_a * n_views_b] accepted matches per pair
+ *  best                : [4] = pair index, i, j, count of the pair with the most
+ *                        matches (the lowest pair index on ties) */
+typedef struct {
+    xa_keypoint* kp_a; uint8_t* desc_a; int32_t* count_a;
+    xa_keypoint* kp_b; uint8_t* desc_b; int32_t* count_b;
+    xa_match* matches; int32_t* pair_count; int32_t* best;
+} xa_pair_buffers;
+
+const char* xa_last_error(void);
+const char* xa_version(void);
+
+/* Sampling rule of Sec. III.B: for i = 0..n_tilt, t = sqrt(2)^i and
+ * phi = k b / t for k = 0, 1, ... while k b / t < 180 deg (b in degrees);
+ * psi = tx = ty = 0, s = 1.  Writes at most cap entries; *n_out receives the
+ * full count (XA_ECAPACITY if it exceeds cap).  Host only. */
+xa_status xa_sampling_grid(int32_t n_tilt, double b_deg, xa_affine_params* out, int32_t cap, int32_t* n_out);
+
+/* Plan the views of one src_w x src_h image (Sec. III.B, eq. (2)): canvases,
+ * maps, blur taps, pyramid levels (n_levels at factor level_scale), per-level
+ * quotas of n_features keypoints (proportional to level area) and the arena
+ * layout.  Host only.  With blob == NULL (or blob_cap too small) only
+ * *blob_bytes is set and XA_ECAPACITY is returned for a too-small buffer. */
+xa_status xa_plan_image(int32_t src_w, int32_t src_h, const xa_affine_params* params, int32_t n_views,
+                        int32_t n_levels, double level_scale, int32_t n_features, int32_t fast_threshold,
+                        void* blob, size_t blob_cap, size_t* blob_bytes);
+
+/* Simulate every planned view of d_src (anti-alias blur along the tilt
+ * direction, then Lanczos-4 resampling, eqs. (3)-(4)).  Writes level 0 of
+ * each view into d_arena (u8, round-half-even of the interpolated value,
+ * 0 outside the source), its content mask into d_mask (1 where the view pixel
+ * maps inside the source rectangle) and, if d_values is not NULL, the
+ * unquantised fp32 values at the same element offsets (d_values then holds
+ * arena_bytes floats).  Workspace: xa_simulate_workspace_size(plan_host). */
+size_t xa_simulate_workspace_size(const void* plan_host);
+xa_status xa_simulate_views(const void* plan_host, const void* plan_dev,
+                            const uint8_t* d_src, int32_t src_pitch,
+                            uint8_t* d_arena, uint8_t* d_mask, float* d_values,
+                            void* d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* ORB on every planned view (levels 1.. of the pyramid are written into
+ * d_arena and d_mask, whose level 0 must hold the simulated views): FAST-9
+ * at the plan's threshold with 3x3 non-maximum suppression and a content
+ * filter, integer Harris top-N per level, 30-bin intensity-centroid
+ * orientation and rBRIEF-256 with the caller's test pattern d_pattern
+ * (int8[256][4] = x1, y1, x2, y2 in [-15, 15]).  Outputs are
+ * [n_views][n_features] keypoints and descriptors (32 bytes, bit i in byte
+ * i/8 at position i%8) and [n_views] counts.  Workspace:
+ * xa_extract_workspace_size(plan_host). */
+size_t xa_extract_workspace_size(const void* plan_host);
+xa_status xa_extract_orb(const void* plan_host, const void* plan_dev,
+                         uint8_t* d_arena, uint8_t* d_mask, const int8_t* d_pattern,
+                         xa_keypoint* d_kp, uint8_t* d_desc, int32_t* d_count,
+                         void* d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* Brute-force Hamming matching of every view of A (queries) against every view
+ * of B (train), Sec. III.B, with the ratio test of Sec. IV.C evaluated exactly
+ * as ratio_den * d1 < ratio_num * d2 (and at least two train descriptors).
+ * d_matches: [n_a * n_b][n_features]; d_pair_count: [n_a * n_b]; d_best: [4]
+ * (see xa_pair_buffers).  No workspace. */
+xa_status xa_match_views(const uint8_t* d_desc_a, const int32_t* d_count_a, int32_t n_a,
+                         const uint8_t* d_desc_b, const int32_t* d_count_b, int32_t n_b,
+                         int32_t n_features, int32_t ratio_num, int32_t ratio_den,
+                         xa_match* d_matches, int32_t* d_pair_count, int32_t* d_best,
+                         hipStream_t stream);
+
+/* The whole parameter-search path for one image pair: simulate both images,
+ * extract ORB on every view, match all view pairs, pick the best pair.
+ * Both plans must use the same n_features.  Workspace:
+ * xa_match_pair_workspace_size(plan_a_host, plan_b_host). */
+size_t xa_match_pair_workspace_size(const void* plan_a_host, const void* plan_b_host);
+xa_status xa_match_pair(const void* plan_a_host, const void* plan_a_dev, const uint8_t* d_a, int32_t pitch_a,
+                        const void* plan_b_host, const void* plan_b_dev, const uint8_t* d_b, int32_t pitch_b,
+                        const int8_t* d_pattern, int32_t ratio_num, int32_t ratio_den,
+                        const xa_pair_buffers* out, void* d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* Precision of eqs. (5)-(6) for the best pair found by xa_match_views /
+ * xa_match_pair: among its accepted matches (query q of view i of A, train
+ * t of view j of B), count those with |H (xs_a, ys_a) - (xs_b, ys_b)| <= th,
+ * H a 3x3 row-major homography acting on source coordinates of A.
+ * d_out[0] = correct, d_out[1] = accepted.  H is read from host memory. */
+xa_status xa_pair_precision(const xa_keypoint* d_kp_a, const xa_keypoint* d_kp_b, const xa_match* d_matches,
+                            const int32_t* d_count_a, const int32_t* d_count_b, int32_t n_b,
+                            int32_t n_features, int32_t ratio_num, int32_t ratio_den,
+                            const int32_t* d_best, const double* H, double th, int32_t* d_out,
+                            hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XAFFINE_H */

@@ -1,0 +1,71 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "xaffine.h"
+
+namespace xa {
+
+// Tile shapes of the launch geometry (the plan's prefix tables are counted in these tiles).
+constexpr int kWarpTX = 64, kWarpTY = 4;    // warp: one thread per view pixel, 256 threads
+constexpr int kPyrTX = 64, kPyrTY = 4;      // pyramid down-sampling
+constexpr int kFastTX = 64, kFastTY = 8;    // FAST / NMS / smoothing tiles (256 threads, 2 rows each)
+constexpr int kBlurTX = 64, kBlurTY = 4;    // directional blur over the source
+constexpr int kBorder = 22;                 // detection border (rotated BRIEF tests reach 21 px)
+constexpr size_t kAlign = 256;
+
+struct BlurTap {
+    float w;        // normalised Gaussian weight
+    int32_t dmaj;   // step along the major axis (k)
+    int32_t dmin;   // floor(k m): whole-pixel step along the minor axis
+    float frac;     // k m - floor(k m): linear-interpolation weight of the next row / column
+};
+static_assert(sizeof(BlurTap) == 16, "tap layout");
+static_assert(sizeof(xa_view_desc) == 216, "view desc layout");
+static_assert(sizeof(xa_level_desc) == 48, "level desc layout");
+static_assert(sizeof(xa_keypoint) == 40, "keypoint layout");
+static_assert(sizeof(xa_match) == 8, "match layout");
+
+inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+
+// Status helpers (plan.cpp owns the thread-local message).
+xa_status fail(xa_status s, const char* fmt, ...);
+xa_status ok();
+xa_status hip_fail(int err, const char* what);
+
+// Validated view of a plan blob.
+struct PlanView {
+    const xa_plan_header* h = nullptr;
+    const xa_view_desc* views = nullptr;
+    const xa_level_desc* levels = nullptr;
+    const BlurTap* taps = nullptr;
+    const int32_t* blur_views = nullptr;
+    const int32_t* warp_prefix = nullptr;
+    const int32_t* level_prefix = nullptr;
+    const int32_t* vl_prefix = nullptr;
+};
+xa_status plan_host_view(const void* blob, PlanView* out);
+PlanView plan_dev_view(const void* blob_host, const void* blob_dev);
+
+// Workspace layouts.
+struct ExtractWs {
+    size_t smooth, cand, cand_count, harris, stage, stage_count, total;
+};
+ExtractWs extract_ws_layout(const xa_plan_header* h);
+size_t simulate_ws_bytes(const xa_plan_header* h);
+
+// Stage launchers (device work only, arguments already validated).
+xa_status launch_simulate(const PlanView& ph, const PlanView& pd, const uint8_t* src, int32_t pitch,
+                          uint8_t* arena, uint8_t* mask, float* values, float* blurred, hipStream_t st);
+xa_status launch_extract(const PlanView& ph, const PlanView& pd, uint8_t* arena, uint8_t* mask,
+                         const int8_t* pattern, xa_keypoint* kp, uint8_t* desc, int32_t* count,
+                         uint8_t* ws, hipStream_t st);
+xa_status launch_match(const uint8_t* desc_a, const int32_t* count_a, int32_t n_a,
+                       const uint8_t* desc_b, const int32_t* count_b, int32_t n_b, int32_t n_features,
+                       int32_t num, int32_t den, xa_match* matches, int32_t* pair_count, int32_t* best,
+                       hipStream_t st);
+
+}  // namespace xa

@@ -1,0 +1,323 @@
+// Host-side planning: the sampling grid of Sec. III.B, the view maps of eq. (2),
+// anti-alias taps, pyramid levels, keypoint quotas and the arena / tile layout.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace xa {
+
+static thread_local std::string g_error;
+
+xa_status fail(xa_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return s;
+}
+
+xa_status ok() {
+    g_error.clear();
+    return XA_OK;
+}
+
+xa_status plan_host_view(const void* blob, PlanView* out) {
+    if (!blob) return fail(XA_EINVAL, "plan is NULL");
+    const auto* h = static_cast<const xa_plan_header*>(blob);
+    if (h->magic != XA_PLAN_MAGIC || h->version != XA_PLAN_VERSION)
+        return fail(XA_EINVAL, "not an xaffine plan (magic %08x version %u)", h->magic, h->version);
+    const char* b = static_cast<const char*>(blob);
+    out->h = h;
+    out->views = reinterpret_cast<const xa_view_desc*>(b + h->off_views);
+    out->levels = reinterpret_cast<const xa_level_desc*>(b + h->off_levels);
+    out->taps = reinterpret_cast<const BlurTap*>(b + h->off_taps);
+    out->blur_views = reinterpret_cast<const int32_t*>(b + h->off_blur_views);
+    out->warp_prefix = reinterpret_cast<const int32_t*>(b + h->off_warp_prefix);
+    out->level_prefix = reinterpret_cast<const int32_t*>(b + h->off_level_prefix);
+    out->vl_prefix = reinterpret_cast<const int32_t*>(b + h->off_vl_prefix);
+    return XA_OK;
+}
+
+PlanView plan_dev_view(const void* blob_host, const void* blob_dev) {
+    const auto* h = static_cast<const xa_plan_header*>(blob_host);
+    const char* b = static_cast<const char*>(blob_dev);
+    PlanView p;
+    p.h = reinterpret_cast<const xa_plan_header*>(b);
+    p.views = reinterpret_cast<const xa_view_desc*>(b + h->off_views);
+    p.levels = reinterpret_cast<const xa_level_desc*>(b + h->off_levels);
+    p.taps = reinterpret_cast<const BlurTap*>(b + h->off_taps);
+    p.blur_views = reinterpret_cast<const int32_t*>(b + h->off_blur_views);
+    p.warp_prefix = reinterpret_cast<const int32_t*>(b + h->off_warp_prefix);
+    p.level_prefix = reinterpret_cast<const int32_t*>(b + h->off_level_prefix);
+    p.vl_prefix = reinterpret_cast<const int32_t*>(b + h->off_vl_prefix);
+    return p;
+}
+
+ExtractWs extract_ws_layout(const xa_plan_header* h) {
+    ExtractWs w{};
+    const size_t nvl = size_t(h->n_views) * h->n_levels;
+    size_t o = 0;
+    w.smooth = o;      o = align_up(o + size_t(h->arena_bytes));
+    w.cand = o;        o = align_up(o + size_t(h->cand_total) * 4);
+    w.cand_count = o;  o = align_up(o + nvl * 4);
+    w.harris = o;      o = align_up(o + size_t(h->cand_total) * 8);
+    w.stage = o;       o = align_up(o + size_t(h->n_views) * h->n_features * 16);
+    w.stage_count = o; o = align_up(o + nvl * 4);
+    w.total = o;
+    return w;
+}
+
+size_t simulate_ws_bytes(const xa_plan_header* h) { return align_up(size_t(h->blur_floats) * 4); }
+
+}  // namespace xa
+
+using namespace xa;
+
+extern "C" const char* xa_last_error(void) { return g_error.c_str(); }
+
+extern "C" const char* xa_version(void) { return "xaffine 1.0 (gfx950)"; }
+
+static double tilt_of(int i) {
+    // sqrt(2)^i, exact for even i so that the longitude-count test is decided exactly on its boundary
+    return std::ldexp(1.0, i / 2) * ((i & 1) ? std::sqrt(2.0) : 1.0);
+}
+
+extern "C" xa_status xa_sampling_grid(int32_t n_tilt, double b_deg, xa_affine_params* out, int32_t cap,
+                                      int32_t* n_out) {
+    if (n_tilt < 0 || n_tilt > 20) return fail(XA_EINVAL, "n_tilt %d out of range [0, 20]", n_tilt);
+    if (!(b_deg > 0.0) || !std::isfinite(b_deg)) return fail(XA_EINVAL, "longitude step must be > 0");
+    if (!n_out || cap < 0 || (cap > 0 && !out)) return fail(XA_EINVAL, "bad output arguments");
+    int32_t n = 0;
+    for (int i = 0; i <= n_tilt; ++i) {
+        const double t = tilt_of(i);
+        for (int k = 0; double(k) * b_deg < 180.0 * t; ++k) {
+            if (n < cap) {
+                const double deg = double(k) * b_deg / t;
+                out[n] = xa_affine_params{t, deg * (M_PI / 180.0), 0.0, 1.0, 0.0, 0.0};
+            }
+            ++n;
+        }
+    }
+    *n_out = n;
+    if (n > cap) return fail(XA_ECAPACITY, "grid has %d views, capacity %d", n, cap);
+    return ok();
+}
+
+namespace {
+
+struct Mat2 {
+    double a, b, c, d;  // [[a, b], [c, d]]
+};
+Mat2 mul(const Mat2& x, const Mat2& y) {
+    return {x.a * y.a + x.b * y.c, x.a * y.b + x.b * y.d, x.c * y.a + x.d * y.c, x.c * y.b + x.d * y.d};
+}
+Mat2 rot(double a) {
+    const double c = std::cos(a), s = std::sin(a);
+    return {c, -s, s, c};
+}
+
+struct Planned {
+    xa_view_desc v;
+    std::vector<BlurTap> taps;
+};
+
+Planned plan_one(int32_t W, int32_t H, const xa_affine_params& p) {
+    Planned out{};
+    xa_view_desc& v = out.v;
+    v.p = p;
+    v.src_w = W;
+    v.src_h = H;
+    // L = s R(psi) diag(1/t, 1) R(phi): R(phi) turns the longitude onto x, the tilt compresses x.
+    Mat2 L = mul(mul(rot(p.psi), Mat2{1.0 / p.t, 0.0, 0.0, 1.0}), rot(p.phi));
+    L = {L.a * p.s, L.b * p.s, L.c * p.s, L.d * p.s};
+    const double cx[4] = {-0.5, W - 0.5, -0.5, W - 0.5};
+    const double cy[4] = {-0.5, -0.5, H - 0.5, H - 0.5};
+    double lox = 1e300, loy = 1e300, hix = -1e300, hiy = -1e300;
+    for (int i = 0; i < 4; ++i) {
+        const double x = L.a * cx[i] + L.b * cy[i];
+        const double y = L.c * cx[i] + L.d * cy[i];
+        lox = std::min(lox, x); hix = std::max(hix, x);
+        loy = std::min(loy, y); hiy = std::max(hiy, y);
+    }
+    v.width = int32_t(std::ceil((hix - lox) - 1e-9));
+    v.height = int32_t(std::ceil((hiy - loy) - 1e-9));
+    const double tx = -lox - 0.5 + p.tx, ty = -loy - 0.5 + p.ty;
+    const double det = L.a * L.d - L.b * L.c;
+    const Mat2 Li{L.d / det, -L.b / det, -L.c / det, L.a / det};
+    v.fwd[0] = L.a; v.fwd[1] = L.b; v.fwd[2] = tx;
+    v.fwd[3] = L.c; v.fwd[4] = L.d; v.fwd[5] = ty;
+    v.inv[0] = Li.a; v.inv[1] = Li.b; v.inv[2] = -(Li.a * tx + Li.b * ty);
+    v.inv[3] = Li.c; v.inv[4] = Li.d; v.inv[5] = -(Li.c * tx + Li.d * ty);
+    v.sigma = p.t > 1.0 ? 0.8 * std::sqrt(p.t * p.t - 1.0) : 0.0;
+    v.ux = std::cos(p.phi);
+    v.uy = -std::sin(p.phi);
+    v.blur_offset = -1;
+    if (v.sigma > 0.0) {
+        // Sheared-line Gaussian: taps step one pixel along the major axis and m along the other.
+        double m;
+        if (std::fabs(v.ux) >= std::fabs(v.uy)) { v.blur_major = 0; m = v.uy / v.ux; }
+        else { v.blur_major = 1; m = v.ux / v.uy; }
+        const double sstep = v.sigma / std::sqrt(1.0 + m * m);
+        const int K = int(std::ceil(4.0 * sstep));
+        std::vector<double> g(2 * K + 1);
+        double sum = 0.0;
+        for (int k = -K; k <= K; ++k) {
+            g[k + K] = std::exp(-double(k) * double(k) / (2.0 * sstep * sstep));
+            sum += g[k + K];
+        }
+        for (int k = -K; k <= K; ++k) {
+            const double km = double(k) * m;
+            const double fl = std::floor(km);
+            out.taps.push_back(BlurTap{float(g[k + K] / sum), k, int32_t(fl), float(km - fl)});
+        }
+        v.blur_ntaps = 2 * K + 1;
+    }
+    return out;
+}
+
+}  // namespace
+
+extern "C" xa_status xa_plan_image(int32_t src_w, int32_t src_h, const xa_affine_params* params, int32_t n_views,
+                                   int32_t n_levels, double level_scale, int32_t n_features, int32_t fast_threshold,
+                                   void* blob, size_t blob_cap, size_t* blob_bytes) {
+    if (!blob_bytes) return fail(XA_EINVAL, "blob_bytes is NULL");
+    if (src_w < 1 || src_h < 1 || src_w > 32768 || src_h > 32768)
+        return fail(XA_EINVAL, "source size %dx%d out of range [1, 32768]", src_w, src_h);
+    if (n_views < 1 || !params) return fail(XA_EINVAL, "need at least one view");
+    if (n_levels < 1 || n_levels > XA_MAX_LEVELS) return fail(XA_EINVAL, "n_levels %d not in [1, %d]", n_levels, XA_MAX_LEVELS);
+    if (!(level_scale > 1.0) || !std::isfinite(level_scale)) return fail(XA_EINVAL, "level_scale must be > 1");
+    if (n_features < 1 || n_features > XA_MAX_FEATURES)
+        return fail(XA_EUNSUPPORTED, "n_features %d not in [1, %d]", n_features, XA_MAX_FEATURES);
+    if (fast_threshold < 0 || fast_threshold > 255) return fail(XA_EINVAL, "fast_threshold must be in [0, 255]");
+    for (int i = 0; i < n_views; ++i) {
+        const xa_affine_params& p = params[i];
+        if (!(p.t >= 1.0) || !(p.s > 0.0) || !std::isfinite(p.t) || !std::isfinite(p.s) || !std::isfinite(p.phi) ||
+            !std::isfinite(p.psi) || !std::isfinite(p.tx) || !std::isfinite(p.ty))
+            return fail(XA_EINVAL, "view %d: need finite parameters with t >= 1 and s > 0", i);
+    }
+    // Per-level keypoint quotas, proportional to level area; level 0 takes the remainder.
+    std::vector<int32_t> quota(n_levels, 0);
+    {
+        std::vector<double> r(n_levels);
+        double tot = 0.0;
+        for (int l = 0; l < n_levels; ++l) r[l] = std::pow(level_scale, double(-2 * l));
+        for (int l = 0; l < n_levels; ++l) tot += r[l];
+        int32_t rest = n_features;
+        for (int l = 1; l < n_levels; ++l) {
+            quota[l] = int32_t(std::floor(double(n_features) * r[l] / tot));
+            rest -= quota[l];
+        }
+        quota[0] = rest;
+        for (int l = 0; l < n_levels; ++l)
+            if (quota[l] > XA_MAX_QUOTA)
+                return fail(XA_EUNSUPPORTED, "level %d quota %d exceeds %d", l, quota[l], XA_MAX_QUOTA);
+    }
+
+    std::vector<Planned> pv(n_views);
+    int64_t total_px = 0;
+    for (int i = 0; i < n_views; ++i) {
+        pv[i] = plan_one(src_w, src_h, params[i]);
+        const auto& v = pv[i].v;
+        if (v.width < 1 || v.height < 1 || v.width > 32768 || v.height > 32768)
+            return fail(XA_EUNSUPPORTED, "view %d canvas %dx%d out of range", i, v.width, v.height);
+        total_px += int64_t(v.width) * v.height;
+        if (total_px > (int64_t(1) << 34)) return fail(XA_EUNSUPPORTED, "views exceed 2^34 pixels");
+    }
+
+    const int32_t nvl = n_views * n_levels;
+    std::vector<xa_level_desc> lv(nvl);
+    std::vector<BlurTap> taps;
+    std::vector<int32_t> blur_views;
+    std::vector<int32_t> warp_prefix(n_views + 1, 0);
+    std::vector<int32_t> level_prefix(size_t(n_levels) * (n_views + 1), 0);
+    std::vector<int32_t> vl_prefix(nvl + 1, 0);
+    int64_t arena = 0, cand = 0, blur_floats = 0;
+    int64_t warp_tiles = 0, vl_tiles = 0;
+    std::vector<int64_t> lvl_tiles(n_levels, 0);
+    for (int i = 0; i < n_views; ++i) {
+        xa_view_desc& v = pv[i].v;
+        if (v.sigma > 0.0) {
+            v.blur_offset = blur_floats;
+            blur_floats += int64_t(src_w) * src_h;
+            v.blur_tap0 = int32_t(taps.size());
+            taps.insert(taps.end(), pv[i].taps.begin(), pv[i].taps.end());
+            blur_views.push_back(i);
+        }
+        warp_prefix[i] = int32_t(warp_tiles);
+        warp_tiles += int64_t((v.width + kWarpTX - 1) / kWarpTX) * ((v.height + kWarpTY - 1) / kWarpTY);
+        int32_t kp_base = 0;
+        for (int l = 0; l < n_levels; ++l) {
+            xa_level_desc& d = lv[size_t(i) * n_levels + l];
+            const double f = std::pow(level_scale, double(l));
+            d.width = l == 0 ? v.width : std::max(1, int32_t(std::floor(v.width / f + 0.5)));
+            d.height = l == 0 ? v.height : std::max(1, int32_t(std::floor(v.height / f + 0.5)));
+            d.offset = arena;
+            if (l == 0) v.offset = arena;
+            arena = int64_t(align_up(size_t(arena + int64_t(d.width) * d.height), 128));
+            d.quota = quota[l];
+            d.kp_base = kp_base;
+            kp_base += quota[l];
+            d.view = i;
+            d.level = l;
+            d.cand_offset = cand;
+            const bool detect = d.width > 2 * kBorder && d.height > 2 * kBorder;
+            d.cand_cap = detect ? int64_t((d.width + 1) / 2) * ((d.height + 1) / 2) : 0;
+            cand += d.cand_cap;
+            level_prefix[size_t(l) * (n_views + 1) + i] = int32_t(lvl_tiles[l]);
+            lvl_tiles[l] += int64_t((d.width + kPyrTX - 1) / kPyrTX) * ((d.height + kPyrTY - 1) / kPyrTY);
+            vl_prefix[size_t(i) * n_levels + l] = int32_t(vl_tiles);
+            vl_tiles += int64_t((d.width + kFastTX - 1) / kFastTX) * ((d.height + kFastTY - 1) / kFastTY);
+        }
+    }
+    warp_prefix[n_views] = int32_t(warp_tiles);
+    for (int l = 0; l < n_levels; ++l) level_prefix[size_t(l) * (n_views + 1) + n_views] = int32_t(lvl_tiles[l]);
+    vl_prefix[nvl] = int32_t(vl_tiles);
+    if (warp_tiles > INT32_MAX / 2 || vl_tiles > INT32_MAX / 2)
+        return fail(XA_EUNSUPPORTED, "too many tiles for one launch");
+
+    xa_plan_header h{};
+    h.magic = XA_PLAN_MAGIC;
+    h.version = XA_PLAN_VERSION;
+    h.src_w = src_w;
+    h.src_h = src_h;
+    h.n_views = n_views;
+    h.n_levels = n_levels;
+    h.n_features = n_features;
+    h.fast_threshold = fast_threshold;
+    h.level_scale = level_scale;
+    h.arena_bytes = arena;
+    h.cand_total = cand;
+    h.blur_floats = blur_floats;
+    h.n_blur = int32_t(blur_views.size());
+    h.n_taps_total = int32_t(taps.size());
+    size_t o = align_up(sizeof(xa_plan_header), 64);
+    h.off_views = int64_t(o);        o = align_up(o + sizeof(xa_view_desc) * n_views, 64);
+    h.off_levels = int64_t(o);       o = align_up(o + sizeof(xa_level_desc) * nvl, 64);
+    h.off_taps = int64_t(o);         o = align_up(o + sizeof(BlurTap) * taps.size(), 64);
+    h.off_blur_views = int64_t(o);   o = align_up(o + 4 * blur_views.size(), 64);
+    h.off_warp_prefix = int64_t(o);  o = align_up(o + 4 * warp_prefix.size(), 64);
+    h.off_level_prefix = int64_t(o); o = align_up(o + 4 * level_prefix.size(), 64);
+    h.off_vl_prefix = int64_t(o);    o = align_up(o + 4 * vl_prefix.size(), 64);
+    h.total_bytes = int64_t(o);
+    *blob_bytes = o;
+    if (!blob) return ok();
+    if (blob_cap < o) return fail(XA_ECAPACITY, "plan needs %zu bytes, buffer has %zu", o, blob_cap);
+    char* b = static_cast<char*>(blob);
+    std::memset(b, 0, o);
+    std::memcpy(b, &h, sizeof(h));
+    for (int i = 0; i < n_views; ++i)
+        std::memcpy(b + h.off_views + sizeof(xa_view_desc) * i, &pv[i].v, sizeof(xa_view_desc));
+    std::memcpy(b + h.off_levels, lv.data(), sizeof(xa_level_desc) * nvl);
+    if (!taps.empty()) std::memcpy(b + h.off_taps, taps.data(), sizeof(BlurTap) * taps.size());
+    if (!blur_views.empty()) std::memcpy(b + h.off_blur_views, blur_views.data(), 4 * blur_views.size());
+    std::memcpy(b + h.off_warp_prefix, warp_prefix.data(), 4 * warp_prefix.size());
+    std::memcpy(b + h.off_level_prefix, level_prefix.data(), 4 * level_prefix.size());
+    std::memcpy(b + h.off_vl_prefix, vl_prefix.data(), 4 * vl_prefix.size());
+    return ok();
+}

@@ -1,0 +1,304 @@
+"""ctypes binding of libxaffine (include/xaffine.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  PyTorch provides device memory and the current stream.  If the
+library is missing the import of this module still works, but every call
+raises RuntimeError (there is no fallback implementation).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libxaffine.so")
+
+XA_OK, XA_EINVAL, XA_ECAPACITY, XA_EHIP, XA_EUNSUPPORTED = 0, -1, -2, -3, -4
+STATUS_NAMES = {0: "XA_OK", -1: "XA_EINVAL", -2: "XA_ECAPACITY", -3: "XA_EHIP", -4: "XA_EUNSUPPORTED"}
+DESC_BYTES = 32
+
+# numpy mirrors of the C structs
+PARAMS_DTYPE = np.dtype([("t", "f8"), ("phi", "f8"), ("psi", "f8"), ("s", "f8"), ("tx", "f8"), ("ty", "f8")])
+VIEW_DTYPE = np.dtype([("p", PARAMS_DTYPE), ("src_w", "i4"), ("src_h", "i4"), ("width", "i4"), ("height", "i4"),
+                       ("fwd", "f8", 6), ("inv", "f8", 6), ("sigma", "f8"), ("ux", "f8"), ("uy", "f8"),
+                       ("offset", "i8"), ("blur_offset", "i8"), ("blur_major", "i4"), ("blur_tap0", "i4"),
+                       ("blur_ntaps", "i4"), ("pad", "i4")])
+LEVEL_DTYPE = np.dtype([("width", "i4"), ("height", "i4"), ("offset", "i8"), ("quota", "i4"), ("kp_base", "i4"),
+                        ("view", "i4"), ("level", "i4"), ("cand_offset", "i8"), ("cand_cap", "i8")])
+HEADER_DTYPE = np.dtype([("magic", "u4"), ("version", "u4"), ("src_w", "i4"), ("src_h", "i4"), ("n_views", "i4"),
+                         ("n_levels", "i4"), ("n_features", "i4"), ("fast_threshold", "i4"), ("level_scale", "f8"),
+                         ("total_bytes", "i8"), ("arena_bytes", "i8"), ("cand_total", "i8"), ("blur_floats", "i8"),
+                         ("n_blur", "i4"), ("n_taps_total", "i4"), ("off_views", "i8"), ("off_levels", "i8"),
+                         ("off_taps", "i8"), ("off_blur_views", "i8"), ("off_warp_prefix", "i8"),
+                         ("off_level_prefix", "i8"), ("off_vl_prefix", "i8")])
+TAP_DTYPE = np.dtype([("w", "f4"), ("dmaj", "i4"), ("dmin", "i4"), ("frac", "f4")])
+KEYPOINT_DTYPE = np.dtype([("x", "i4"), ("y", "i4"), ("level", "i4"), ("bin", "i4"), ("harris", "i8"),
+                           ("xs", "f8"), ("ys", "f8")])
+MATCH_DTYPE = np.dtype([("t", "i4"), ("d1", "u2"), ("d2", "u2")])
+assert VIEW_DTYPE.itemsize == 216 and LEVEL_DTYPE.itemsize == 48 and KEYPOINT_DTYPE.itemsize == 40
+assert MATCH_DTYPE.itemsize == 8 and HEADER_DTYPE.itemsize == 136
+
+
+class XAError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("t", "phi", "psi", "s", "tx", "ty")]
+
+
+class _PairBuffers(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("kp_a", "desc_a", "count_a", "kp_b", "desc_b", "count_b",
+                                                 "matches", "pair_count", "best")]
+
+
+_c = ctypes
+_SIGS = {
+    "xa_last_error": (_c.c_char_p, []),
+    "xa_version": (_c.c_char_p, []),
+    "xa_sampling_grid": (_c.c_int, [_c.c_int32, _c.c_double, _c.c_void_p, _c.c_int32, _c.POINTER(_c.c_int32)]),
+    "xa_plan_image": (_c.c_int, [_c.c_int32, _c.c_int32, _c.c_void_p, _c.c_int32, _c.c_int32, _c.c_double,
+                                 _c.c_int32, _c.c_int32, _c.c_void_p, _c.c_size_t, _c.POINTER(_c.c_size_t)]),
+    "xa_simulate_workspace_size": (_c.c_size_t, [_c.c_void_p]),
+    "xa_simulate_views": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p,
+                                     _c.c_void_p, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "xa_extract_workspace_size": (_c.c_size_t, [_c.c_void_p]),
+    "xa_extract_orb": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                  _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "xa_match_views": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_int32,
+                                  _c.c_int32, _c.c_int32, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                  _c.c_void_p]),
+    "xa_match_pair_workspace_size": (_c.c_size_t, [_c.c_void_p, _c.c_void_p]),
+    "xa_match_pair": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p,
+                                 _c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_int32, _c.c_int32,
+                                 _c.POINTER(_PairBuffers), _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "xa_pair_precision": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32,
+                                     _c.c_int32, _c.c_int32, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_double,
+                                     _c.c_void_p, _c.c_void_p]),
+}
+EXPORTS = tuple(_SIGS)
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises RuntimeError if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2503_03479_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != XA_OK:
+        raise XAError(status, lib().xa_last_error().decode())
+
+
+def version() -> str:
+    return lib().xa_version().decode()
+
+
+# ---------------------------------------------------------------- planning (host only)
+
+def sampling_grid(n_tilt: int, b_deg: float = 72.0) -> np.ndarray:
+    n = ctypes.c_int32(0)
+    st = lib().xa_sampling_grid(n_tilt, b_deg, None, 0, ctypes.byref(n))
+    if st not in (XA_OK, XA_ECAPACITY):
+        _check(st)
+    out = np.zeros(n.value, PARAMS_DTYPE)
+    _check(lib().xa_sampling_grid(n_tilt, b_deg, out.ctypes.data, n.value, ctypes.byref(n)))
+    return out
+
+
+def make_params(rows) -> np.ndarray:
+    """Params array from (t, phi[, psi, s, tx, ty]) tuples."""
+    out = np.zeros(len(rows), PARAMS_DTYPE)
+    for i, r in enumerate(rows):
+        r = tuple(r) + (0.0, 1.0, 0.0, 0.0)[len(r) - 2:]
+        out[i] = r[:6]
+    return out
+
+
+@dataclass
+class Plan:
+    blob: np.ndarray          # uint8 host bytes
+    header: np.void
+    views: np.ndarray         # VIEW_DTYPE
+    levels: np.ndarray        # LEVEL_DTYPE, (n_views, n_levels)
+    _dev: object = None
+
+    @property
+    def n_views(self) -> int:
+        return int(self.header["n_views"])
+
+    @property
+    def n_levels(self) -> int:
+        return int(self.header["n_levels"])
+
+    @property
+    def n_features(self) -> int:
+        return int(self.header["n_features"])
+
+    @property
+    def arena_bytes(self) -> int:
+        return int(self.header["arena_bytes"])
+
+    def host_ptr(self) -> int:
+        return self.blob.ctypes.data
+
+    def device(self, device="cuda"):
+        """Device copy of the blob (cached)."""
+        import torch
+        if self._dev is None or str(self._dev.device) != str(torch.device(device)):
+            self._dev = torch.from_numpy(self.blob.copy()).to(device)
+        return self._dev
+
+    def taps(self) -> np.ndarray:
+        h = self.header
+        return np.frombuffer(self.blob, TAP_DTYPE, int(h["n_taps_total"]), int(h["off_taps"]))
+
+    def level_image(self, arena: np.ndarray, view: int, level: int) -> np.ndarray:
+        L = self.levels[view, level]
+        o = int(L["offset"])
+        return arena[o:o + int(L["width"]) * int(L["height"])].reshape(int(L["height"]), int(L["width"]))
+
+
+def plan_image(src_w: int, src_h: int, params: np.ndarray, n_levels: int = 8, level_scale: float = 1.2,
+               n_features: int = 1000, fast_threshold: int = 20) -> Plan:
+    params = np.ascontiguousarray(params, PARAMS_DTYPE)
+    n = ctypes.c_size_t(0)
+    st = lib().xa_plan_image(src_w, src_h, params.ctypes.data, len(params), n_levels, level_scale, n_features,
+                             fast_threshold, None, 0, ctypes.byref(n))
+    _check(st)
+    blob = np.zeros(n.value, np.uint8)
+    _check(lib().xa_plan_image(src_w, src_h, params.ctypes.data, len(params), n_levels, level_scale, n_features,
+                               fast_threshold, blob.ctypes.data, blob.size, ctypes.byref(n)))
+    h = np.frombuffer(blob, HEADER_DTYPE, 1)[0]
+    views = np.frombuffer(blob, VIEW_DTYPE, int(h["n_views"]), int(h["off_views"]))
+    levels = np.frombuffer(blob, LEVEL_DTYPE, int(h["n_views"]) * int(h["n_levels"]),
+                           int(h["off_levels"])).reshape(int(h["n_views"]), int(h["n_levels"]))
+    return Plan(blob, h, views, levels)
+
+
+# ---------------------------------------------------------------- device calls
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else t.data_ptr()
+
+
+def _empty(nbytes: int, device):
+    import torch
+    # 256-byte aligned (torch's caching allocator aligns to at least 512 bytes)
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def simulate_views(plan: Plan, src, values: bool = False, ws=None):
+    """Returns (arena u8, mask u8[, values f32]) device tensors of arena_bytes elements."""
+    import torch
+    dev = src.device
+    assert src.dtype == torch.uint8 and src.dim() == 2 and src.is_contiguous()
+    arena = torch.zeros(plan.arena_bytes, dtype=torch.uint8, device=dev)
+    mask = torch.zeros(plan.arena_bytes, dtype=torch.uint8, device=dev)
+    vals = torch.zeros(plan.arena_bytes, dtype=torch.float32, device=dev) if values else None
+    need = lib().xa_simulate_workspace_size(plan.host_ptr())
+    if ws is None:
+        ws = _empty(need, dev)
+    _check(lib().xa_simulate_views(plan.host_ptr(), _ptr(plan.device(dev)), _ptr(src), src.stride(0), _ptr(arena),
+                                   _ptr(mask), _ptr(vals), _ptr(ws), ws.numel(), _stream()))
+    return (arena, mask, vals) if values else (arena, mask)
+
+
+def extract_orb(plan: Plan, arena, mask, pattern, ws=None):
+    """ORB on every view.  Returns (kp u8[n_views, N, 40], desc u8[n_views, N, 32], count i32[n_views])."""
+    import torch
+    dev = arena.device
+    N = plan.n_features
+    kp = torch.zeros((plan.n_views, N, KEYPOINT_DTYPE.itemsize), dtype=torch.uint8, device=dev)
+    desc = torch.zeros((plan.n_views, N, DESC_BYTES), dtype=torch.uint8, device=dev)
+    count = torch.zeros(plan.n_views, dtype=torch.int32, device=dev)
+    need = lib().xa_extract_workspace_size(plan.host_ptr())
+    if ws is None:
+        ws = _empty(need, dev)
+    _check(lib().xa_extract_orb(plan.host_ptr(), _ptr(plan.device(dev)), _ptr(arena), _ptr(mask), _ptr(pattern),
+                                _ptr(kp), _ptr(desc), _ptr(count), _ptr(ws), ws.numel(), _stream()))
+    return kp, desc, count
+
+
+def match_views(desc_a, count_a, desc_b, count_b, ratio_num: int = 4, ratio_den: int = 5):
+    """All-pairs matching.  Returns (matches u8[n_a*n_b, N, 8], pair_count i32[n_a*n_b], best i32[4])."""
+    import torch
+    dev = desc_a.device
+    n_a, N = desc_a.shape[0], desc_a.shape[1]
+    n_b = desc_b.shape[0]
+    matches = torch.zeros((n_a * n_b, N, MATCH_DTYPE.itemsize), dtype=torch.uint8, device=dev)
+    pair_count = torch.zeros(n_a * n_b, dtype=torch.int32, device=dev)
+    best = torch.zeros(4, dtype=torch.int32, device=dev)
+    _check(lib().xa_match_views(_ptr(desc_a), _ptr(count_a), n_a, _ptr(desc_b), _ptr(count_b), n_b, N, ratio_num,
+                                ratio_den, _ptr(matches), _ptr(pair_count), _ptr(best), _stream()))
+    return matches, pair_count, best
+
+
+class PairRunner:
+    """Preallocated buffers for repeated xa_match_pair calls on images of fixed sizes."""
+
+    def __init__(self, plan_a: Plan, plan_b: Plan, device="cuda"):
+        import torch
+        self.plan_a, self.plan_b = plan_a, plan_b
+        self.device = torch.device(device)
+        N = plan_a.n_features
+        na, nb = plan_a.n_views, plan_b.n_views
+        z = lambda *s, dt=torch.uint8: torch.zeros(s, dtype=dt, device=self.device)  # noqa: E731
+        self.kp_a, self.desc_a, self.count_a = z(na, N, 40), z(na, N, 32), z(na, dt=torch.int32)
+        self.kp_b, self.desc_b, self.count_b = z(nb, N, 40), z(nb, N, 32), z(nb, dt=torch.int32)
+        self.matches, self.pair_count = z(na * nb, N, 8), z(na * nb, dt=torch.int32)
+        self.best = z(4, dt=torch.int32)
+        need = lib().xa_match_pair_workspace_size(plan_a.host_ptr(), plan_b.host_ptr())
+        self.ws = _empty(need, self.device)
+        self.bufs = _PairBuffers(*[_ptr(t) for t in (self.kp_a, self.desc_a, self.count_a, self.kp_b, self.desc_b,
+                                                     self.count_b, self.matches, self.pair_count, self.best)])
+        self.dev_a = plan_a.device(self.device)
+        self.dev_b = plan_b.device(self.device)
+
+    def run(self, A, B, pattern, ratio_num: int = 4, ratio_den: int = 5):
+        _check(lib().xa_match_pair(self.plan_a.host_ptr(), _ptr(self.dev_a), _ptr(A), A.stride(0),
+                                   self.plan_b.host_ptr(), _ptr(self.dev_b), _ptr(B), B.stride(0), _ptr(pattern),
+                                   ratio_num, ratio_den, ctypes.byref(self.bufs), _ptr(self.ws), self.ws.numel(),
+                                   _stream()))
+
+    def precision(self, H, th: float = 2.0, ratio_num: int = 4, ratio_den: int = 5):
+        import torch
+        out = torch.zeros(2, dtype=torch.int32, device=self.device)
+        Hc = np.ascontiguousarray(H, np.float64).reshape(9)
+        _check(lib().xa_pair_precision(_ptr(self.kp_a), _ptr(self.kp_b), _ptr(self.matches), _ptr(self.count_a),
+                                       _ptr(self.count_b), self.plan_b.n_views, self.plan_a.n_features, ratio_num,
+                                       ratio_den, _ptr(self.best), Hc.ctypes.data, th, _ptr(out), _stream()))
+        return out
+
+
+def keypoints_np(kp_tensor) -> np.ndarray:
+    """Device keypoint buffer -> numpy structured array (n_views, N)."""
+    a = kp_tensor.cpu().numpy()
+    return a.reshape(a.shape[0], a.shape[1] * a.shape[2]).view(KEYPOINT_DTYPE)
+
+
+def matches_np(m_tensor) -> np.ndarray:
+    a = m_tensor.cpu().numpy()
+    return a.reshape(a.shape[0], a.shape[1] * a.shape[2]).view(MATCH_DTYPE)

@@ -1,0 +1,301 @@
+"""GPU parity: every stage of the HIP path against the CPU oracle on the same seeded inputs.
+
+Tolerances: ORB (FAST, Harris, orientation, rBRIEF, order, counts) and matching
+(indices, distances, counts, best pair) are exact given the same uint8 views;
+the warp's fp32 values agree with the oracle's fp64 values within 1e-4 on
+intensities normalised to [0, 1] (0.0255 gray levels), and the quantised
+views differ by at most one gray level on at most 1e-4 of the pixels."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import match as OM
+from oracle import orb as OO
+from oracle import pipeline as OPL
+from oracle import plan as OP
+from oracle import simulate as OS
+
+torch = pytest.importorskip("torch")
+X = pytest.importorskip("paper_2503_03479_amd.xaffine")
+
+pytestmark = pytest.mark.gpu
+
+WARP_TOL = 1e-4 * 255.0
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    X.lib()
+    return torch.device("cuda:0")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return synth.make_pair(**synth.PAIR_CONFIGS["tiny"])
+
+
+def _params(n_tilt, extra=()):
+    rows = [(t, f, 0.0, 1.0) for t, f in OP.sampling_grid(n_tilt)] + list(extra)
+    return rows, X.make_params(rows)
+
+
+def _oracle_views(img, rows):
+    out = []
+    for r in rows:
+        v = OP.plan_view(img.shape[1], img.shape[0], *r)
+        V, mask, U = OS.simulate_view(img, v)
+        out.append((v, V, mask, U))
+    return out
+
+
+def _check_simulate(img, rows, plan, dev, label):
+    src = torch.from_numpy(np.ascontiguousarray(img)).to(dev)
+    arena, mask, vals = X.simulate_views(plan, src, values=True)
+    torch.cuda.synchronize()
+    arena, mask, vals = arena.cpu().numpy(), mask.cpu().numpy(), vals.cpu().numpy()
+    ref = _oracle_views(img, rows)
+    worst = 0.0
+    n_px = n_bad_u8 = 0
+    for i, (v, V, M, U) in enumerate(ref):
+        gm = X.Plan.level_image(plan, mask, i, 0).astype(bool)
+        gu = X.Plan.level_image(plan, arena, i, 0)
+        gv = X.Plan.level_image(plan, vals, i, 0)
+        assert gm.shape == M.shape, (label, i)
+        px, py = OS.view_coords(v)
+        edge = (np.minimum(np.abs(px + 0.5), np.abs(px - (v.src_w - 0.5))) < 1e-9) | \
+               (np.minimum(np.abs(py + 0.5), np.abs(py - (v.src_h - 0.5))) < 1e-9)
+        assert np.all((gm == M) | edge), (label, i)
+        both = gm & M
+        err = np.abs(gv[both].astype(np.float64) - V[both])
+        worst = max(worst, float(err.max()) if err.size else 0.0)
+        assert np.all(gu[~gm] == 0) and np.all(gv[~gm] == 0)
+        du = np.abs(gu[both].astype(np.int64) - U[both].astype(np.int64))
+        assert du.max(initial=0) <= 1, (label, i)
+        n_px += int(both.sum())
+        n_bad_u8 += int((du > 0).sum())
+    say(f"[{label}] warp max |err| = {worst:.3e} gray ({worst / 255:.2e} normalised); "
+        f"u8 mismatches {n_bad_u8}/{n_px} = {n_bad_u8 / max(n_px, 1):.2e}")
+    assert worst <= WARP_TOL
+    assert n_bad_u8 <= max(1, 1e-4 * n_px)
+    return ref
+
+
+def test_simulate_tiny_a(dev, tiny):
+    say("case: simulate tiny A 256x256, 12 grid views + 2 general maps")
+    rows, params = _params(2, [(1.7, 0.4, 0.3, 0.8), (2.5, 2.9, -1.2, 1.3)])
+    plan = X.plan_image(256, 256, params, 3, 1.2, 300, 20)
+    _check_simulate(tiny.A, rows, plan, dev, "tiny A")
+
+
+def test_simulate_ragged_b(dev, tiny):
+    say("case: simulate tiny B 239x286 (odd sizes)")
+    rows, params = _params(2)
+    B = tiny.B
+    plan = X.plan_image(B.shape[1], B.shape[0], params, 3, 1.2, 300, 20)
+    _check_simulate(B, rows, plan, dev, "tiny B")
+
+
+def test_identity_view_is_exact(dev):
+    say("case: identity view reproduces the input")
+    img = np.random.default_rng(3).integers(0, 256, (77, 131)).astype(np.uint8)
+    plan = X.plan_image(131, 77, X.make_params([(1.0, 0.0)]), 1, 1.2, 100, 20)
+    arena, mask = X.simulate_views(plan, torch.from_numpy(img).to(dev))
+    torch.cuda.synchronize()
+    assert np.array_equal(plan.level_image(arena.cpu().numpy(), 0, 0), img)
+    assert plan.level_image(mask.cpu().numpy(), 0, 0).all()
+
+
+def _gpu_extract_from_views(plan, views_u8, masks, pattern, dev):
+    arena = np.zeros(plan.arena_bytes, np.uint8)
+    mask = np.zeros(plan.arena_bytes, np.uint8)
+    for i, (U, M) in enumerate(zip(views_u8, masks)):
+        L0 = plan.levels[i, 0]
+        o, n = int(L0["offset"]), U.size
+        arena[o:o + n] = U.reshape(-1)
+        mask[o:o + n] = M.reshape(-1).astype(np.uint8)
+    ta = torch.from_numpy(arena).to(dev)
+    tm = torch.from_numpy(mask).to(dev)
+    pat = torch.from_numpy(pattern).to(dev)
+    kp, desc, count = X.extract_orb(plan, ta, tm, pat)
+    torch.cuda.synchronize()
+    return X.keypoints_np(kp), desc.cpu().numpy(), count.cpu().numpy(), ta.cpu().numpy(), tm.cpu().numpy()
+
+
+def _check_extract(img, rows, n_levels, N, dev, label, T=20):
+    pattern = synth.brief_pattern()
+    params = X.make_params(rows)
+    plan = X.plan_image(img.shape[1], img.shape[0], params, n_levels, 1.2, N, T)
+    ref = _oracle_views(img, rows)
+    kp, desc, count, arena, mask = _gpu_extract_from_views(plan, [r[3] for r in ref], [r[2] for r in ref],
+                                                          pattern, dev)
+    quotas = OP.level_quotas(N, n_levels)
+    total = 0
+    for i, (v, V, M, U) in enumerate(ref):
+        dims = OP.level_dims(v.width, v.height, n_levels)
+        # pyramid levels are bit-exact
+        lv = OO.build_pyramid(U, M, dims)
+        for l in range(1, n_levels):
+            assert np.array_equal(plan.level_image(arena, i, l), lv[l][0]), (label, i, l)
+            assert np.array_equal(plan.level_image(mask, i, l).astype(bool), lv[l][1]), (label, i, l)
+        f = OO.extract_view(U, M, dims, quotas, T, pattern)
+        n = len(f["x"])
+        assert count[i] == n, (label, i, count[i], n)
+        g = kp[i][:n]
+        assert np.array_equal(g["x"], f["x"]) and np.array_equal(g["y"], f["y"]), (label, i)
+        assert np.array_equal(g["level"], f["level"]), (label, i)
+        assert np.array_equal(g["harris"], f["harris"]), (label, i)
+        assert np.array_equal(g["bin"], f["bin"]), (label, i)
+        assert np.array_equal(desc[i][:n], f["desc"]), (label, i)
+        xs, ys = OPL.keypoints_to_source(f, v, OPL.OrbOptions(n_levels=n_levels, n_features=N))
+        assert np.allclose(g["xs"], xs, atol=1e-9) and np.allclose(g["ys"], ys, atol=1e-9), (label, i)
+        total += n
+    say(f"[{label}] ORB exact on {len(rows)} views, {total} keypoints")
+    return total
+
+
+def test_extract_exact_tiny(dev, tiny):
+    say("case: extract tiny A, 12 views, 3 levels, 300 keypoints")
+    rows, _ = _params(2)
+    assert _check_extract(tiny.A, rows, 3, 300, dev, "tiny A") > 1000
+
+
+def test_extract_exact_ragged_quota_overflow(dev, tiny):
+    say("case: extract tiny B with 8 levels and a small quota (selection path)")
+    rows, _ = _params(1, [(2.2, 1.0, 0.5, 1.1)])
+    assert _check_extract(tiny.B, rows, 8, 64, dev, "tiny B / N=64", T=10) > 100
+
+
+def test_extract_constant_image_has_no_keypoints(dev):
+    say("case: extract on a constant image")
+    img = np.full((120, 140), 90, np.uint8)
+    rows, _ = _params(1)
+    assert _check_extract(img, rows, 3, 200, dev, "constant") == 0
+
+
+def test_extract_too_small_for_detection(dev):
+    say("case: extract on views smaller than the detection border")
+    img = np.random.default_rng(9).integers(0, 256, (40, 44)).astype(np.uint8)
+    rows, _ = _params(1)
+    assert _check_extract(img, rows, 2, 50, dev, "small") == 0
+
+
+def _pad_desc(feats, N):
+    D = np.zeros((len(feats), N, 32), np.uint8)
+    C = np.zeros(len(feats), np.int32)
+    for i, f in enumerate(feats):
+        D[i, :len(f)] = f
+        C[i] = len(f)
+    return D, C
+
+
+def _check_match(da, db, N, dev, label, num=4, den=5):
+    Da, Ca = _pad_desc(da, N)
+    Db, Cb = _pad_desc(db, N)
+    t = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
+    m, pc, best = X.match_views(t(Da), t(Ca), t(Db), t(Cb), num, den)
+    torch.cuda.synchronize()
+    m = X.matches_np(m)
+    pc = pc.cpu().numpy()
+    best = best.cpu().numpy()
+    res, counts, rbest = OM.match_views(da, db, num, den)
+    for k, (idx, d1, d2, acc) in enumerate(res):
+        i, j = divmod(k, len(db))
+        nq = len(da[i])
+        assert np.array_equal(m[k][:nq]["t"], idx), (label, k)
+        assert np.array_equal(m[k][:nq]["d1"], d1), (label, k)
+        assert np.array_equal(m[k][:nq]["d2"], d2), (label, k)
+    assert np.array_equal(pc, counts), label
+    assert tuple(best.tolist()) == tuple(rbest), (label, best, rbest)
+    say(f"[{label}] matching exact on {len(res)} view pairs, best {tuple(best.tolist())}")
+
+
+def test_match_exact_random(dev):
+    say("case: match random descriptors with duplicates and ragged counts")
+    g = np.random.default_rng(21)
+    da = [g.integers(0, 256, (n, 32)).astype(np.uint8) for n in (300, 17, 0, 256, 1)]
+    db = [g.integers(0, 256, (n, 32)).astype(np.uint8) for n in (299, 1, 0, 513, 64)]
+    db[3][100] = db[3][7]            # duplicated train descriptor
+    da[0][5] = db[3][7]              # query equal to both copies -> d1 == d2, rejected
+    da[3][:40] = db[0][:40] ^ np.uint8(1)   # near copies -> accepted
+    _check_match(da, db, 600, dev, "random N=600")
+    _check_match(da[:2], db[:3], 300, dev, "random N=300 (one query block)")
+
+
+def test_match_exact_large_blocks(dev):
+    say("case: match with N=2000 (two query blocks, four train chunks)")
+    g = np.random.default_rng(22)
+    da = [g.integers(0, 256, (n, 32)).astype(np.uint8) for n in (2000, 1500)]
+    db = [g.integers(0, 256, (n, 32)).astype(np.uint8) for n in (2000, 700, 1999)]
+    db[0][:500] = da[0][:500] ^ np.uint8(2)
+    _check_match(da, db, 2000, dev, "random N=2000")
+
+
+def test_match_exact_on_oracle_features(dev, tiny):
+    say("case: match oracle ORB descriptors of the tiny pair (all 144 view pairs)")
+    rows, _ = _params(2)
+    opts = OPL.OrbOptions(n_levels=3, n_features=300)
+    pattern = synth.brief_pattern()
+    va = OPL.plan_image(256, 256, OP.sampling_grid(2))
+    vb = OPL.plan_image(tiny.B.shape[1], tiny.B.shape[0], OP.sampling_grid(2))
+    fa = OPL.extract_image(OPL.simulate_image(tiny.A, va), va, opts, pattern)
+    fb = OPL.extract_image(OPL.simulate_image(tiny.B, vb), vb, opts, pattern)
+    _check_match([f["desc"] for f in fa], [f["desc"] for f in fb], 300, dev, "tiny features")
+
+
+def test_pair_end_to_end_tiny(dev, tiny):
+    say("case: xa_match_pair on the tiny pair vs the oracle pipeline")
+    grid = OP.sampling_grid(2)
+    params = X.make_params([(t, f) for t, f in grid])
+    pa = X.plan_image(256, 256, params, 3, 1.2, 300, 20)
+    pb = X.plan_image(tiny.B.shape[1], tiny.B.shape[0], params, 3, 1.2, 300, 20)
+    run = X.PairRunner(pa, pb, dev)
+    pat = torch.from_numpy(synth.brief_pattern()).to(dev)
+    A = torch.from_numpy(tiny.A).to(dev)
+    B = torch.from_numpy(np.ascontiguousarray(tiny.B)).to(dev)
+    run.run(A, B, pat)
+    pr = run.precision(tiny.H, 2.0)
+    torch.cuda.synchronize()
+    best = run.best.cpu().numpy()
+    ok, n = pr.cpu().numpy()
+    ref = OPL.match_pair(tiny.A, tiny.B, grid, grid, OPL.OrbOptions(n_levels=3, n_features=300),
+                         synth.brief_pattern())
+    rfrac, rok = OM.precision(ref["pa"], ref["pb"], tiny.H, 2.0)
+    say(f"[pair tiny] gpu best {best.tolist()} precision {ok}/{n}; oracle best {ref['best']} precision {rfrac:.3f}")
+    assert n == best[3] and n >= 40
+    assert ok / n >= 0.8
+    # the quantised views may differ by a gray level on a few pixels, so the counts are close, not equal
+    assert abs(int(best[3]) - int(ref["best"][3])) <= max(5, 0.1 * ref["best"][3])
+    counts = run.pair_count.cpu().numpy()
+    assert np.corrcoef(counts, ref["counts"])[0, 1] > 0.95
+    # determinism: a second run gives identical bytes
+    kp1, d1, m1 = run.kp_a.clone(), run.desc_a.clone(), run.matches.clone()
+    run.run(A, B, pat)
+    torch.cuda.synchronize()
+    assert torch.equal(kp1, run.kp_a) and torch.equal(d1, run.desc_a) and torch.equal(m1, run.matches)
+
+
+def test_single_image_mode(dev, tiny):
+    """The paper's own search: simulated views of A against the unsimulated target B."""
+    say("case: single-image mode (B has only the identity view)")
+    params_a = X.make_params([(t, f) for t, f in OP.sampling_grid(2)])
+    params_b = X.make_params([(1.0, 0.0)])
+    pa = X.plan_image(256, 256, params_a, 3, 1.2, 300, 20)
+    pb = X.plan_image(tiny.B.shape[1], tiny.B.shape[0], params_b, 3, 1.2, 300, 20)
+    run = X.PairRunner(pa, pb, dev)
+    run.run(torch.from_numpy(tiny.A).to(dev), torch.from_numpy(np.ascontiguousarray(tiny.B)).to(dev),
+            torch.from_numpy(synth.brief_pattern()).to(dev))
+    pr = run.precision(tiny.H, 2.0).cpu().numpy()
+    best = run.best.cpu().numpy()
+    say(f"[single-image] best {best.tolist()} precision {pr.tolist()}")
+    assert best[2] == 0 and best[3] == pr[1] and pr[1] > 20
+    assert pr[0] / pr[1] >= 0.8

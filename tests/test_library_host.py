@@ -1,0 +1,136 @@
+"""Host-side checks of libxaffine: exports, the planner against the oracle, argument errors.
+
+No GPU work is launched here; the planner and the argument checks run on the host."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import plan as OP
+from oracle import simulate as OS
+
+X = pytest.importorskip("paper_2503_03479_amd.xaffine")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(X.LIB_PATH):
+        pytest.skip("libxaffine.so not built")
+    return X.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    hdr = open(os.path.join(ROOT, "include", "xaffine.h")).read()
+    declared = set(re.findall(r"\b(xa_[a-z0-9_]+)\s*\(", hdr))
+    assert declared, "no declarations found"
+    for name in declared:
+        assert hasattr(L, name), name
+    assert declared == set(X.EXPORTS)
+
+
+def test_sampling_grid_equals_oracle(L):
+    for n in range(0, 8):
+        got = X.sampling_grid(n)
+        ref = OP.sampling_grid(n)
+        assert len(got) == len(ref)
+        assert np.array_equal(got["t"], [t for t, _ in ref])
+        assert np.array_equal(got["phi"], [f for _, f in ref])
+    assert len(X.sampling_grid(5)) == 45
+
+
+@pytest.mark.parametrize("w,h,n_tilt", [(256, 256, 2), (1024, 768, 5), (239, 286, 2), (97, 53, 7)])
+def test_plan_matches_oracle(L, w, h, n_tilt):
+    grid = OP.sampling_grid(n_tilt)
+    rows = [(t, f, 0.0, 1.0) for t, f in grid] + [(1.7, 0.4, 0.3, 0.8), (2.5, 2.9, -1.2, 1.3)]
+    params = X.make_params(rows)
+    N, Lv = 1000, 8
+    p = X.plan_image(w, h, params, Lv, 1.2, N, 20)
+    quotas = OP.level_quotas(N, Lv)
+    for i, r in enumerate(rows):
+        v = OP.plan_view(w, h, *r)
+        pv = p.views[i]
+        assert (pv["width"], pv["height"]) == (v.width, v.height)
+        assert np.allclose(pv["fwd"].reshape(2, 3), v.fwd, rtol=0, atol=1e-10)
+        assert np.allclose(pv["inv"].reshape(2, 3), v.inv, rtol=0, atol=1e-9)
+        assert pv["sigma"] == pytest.approx(v.sigma, abs=1e-15)
+        assert (pv["ux"], pv["uy"]) == pytest.approx(v.u, abs=1e-16)
+        dims = OP.level_dims(v.width, v.height, Lv)
+        assert [(int(a), int(b)) for a, b in zip(p.levels[i]["width"], p.levels[i]["height"])] == dims
+        assert p.levels[i]["quota"].tolist() == quotas
+        assert p.levels[i]["kp_base"].tolist() == [sum(quotas[:l]) for l in range(Lv)]
+        if v.sigma > 0:
+            major, m, ks, g = OS.blur_taps(v.sigma, v.u)
+            assert pv["blur_major"] == major and pv["blur_ntaps"] == len(ks)
+            taps = p.taps()[pv["blur_tap0"]:pv["blur_tap0"] + pv["blur_ntaps"]]
+            assert np.array_equal(taps["dmaj"], ks)
+            assert np.allclose(taps["w"], g, rtol=1e-6, atol=1e-9)
+            km = ks * m
+            assert np.array_equal(taps["dmin"], np.floor(km).astype(np.int64))
+            assert np.allclose(taps["frac"], km - np.floor(km), atol=1e-6)
+        else:
+            assert pv["blur_ntaps"] == 0 and pv["blur_offset"] == -1
+    # arena layout: levels do not overlap and fit the arena
+    ends = []
+    for lv in p.levels.reshape(-1):
+        ends.append((int(lv["offset"]), int(lv["offset"]) + int(lv["width"]) * int(lv["height"])))
+    ends.sort()
+    assert all(a[1] <= b[0] for a, b in zip(ends, ends[1:]))
+    assert ends[-1][1] <= p.arena_bytes
+
+
+def test_plan_rejects_bad_arguments(L):
+    good = X.make_params([(1.0, 0.0)])
+    for rows in ([(0.5, 0.0)], [(1.0, 0.0, 0.0, 0.0)], [(float("nan"), 0.0)], [(2.0, float("inf"))]):
+        with pytest.raises(X.XAError) as e:
+            X.plan_image(64, 64, X.make_params(rows))
+        assert e.value.status == X.XA_EINVAL
+    with pytest.raises(X.XAError) as e:
+        X.plan_image(0, 64, good)
+    assert e.value.status == X.XA_EINVAL
+    with pytest.raises(X.XAError) as e:
+        X.plan_image(64, 64, good, n_levels=0)
+    assert e.value.status == X.XA_EINVAL
+    with pytest.raises(X.XAError) as e:
+        X.plan_image(64, 64, good, n_features=5000)
+    assert e.value.status == X.XA_EUNSUPPORTED
+    with pytest.raises(X.XAError) as e:
+        X.plan_image(64, 64, good, fast_threshold=300)
+    assert e.value.status == X.XA_EINVAL
+
+
+def test_grid_capacity_error(L):
+    import ctypes
+    n = ctypes.c_int32(0)
+    buf = np.zeros(3, X.PARAMS_DTYPE)
+    st = L.xa_sampling_grid(5, 72.0, buf.ctypes.data, 3, ctypes.byref(n))
+    assert st == X.XA_ECAPACITY and n.value == 45
+    assert b"capacity" in L.xa_last_error()
+    assert L.xa_sampling_grid(-1, 72.0, None, 0, ctypes.byref(n)) == X.XA_EINVAL
+
+
+def test_workspace_queries_and_bad_plan(L):
+    p = X.plan_image(128, 96, X.sampling_grid(2), 3, 1.2, 300, 20)
+    assert L.xa_simulate_workspace_size(p.host_ptr()) == 4 * 9 * 128 * 96    # nine blurred views
+    assert L.xa_extract_workspace_size(p.host_ptr()) > p.arena_bytes
+    assert L.xa_match_pair_workspace_size(p.host_ptr(), p.host_ptr()) > 4 * p.arena_bytes
+    junk = np.zeros(256, np.uint8)
+    assert L.xa_simulate_workspace_size(junk.ctypes.data) == 0
+    st = L.xa_simulate_views(junk.ctypes.data, None, None, 0, None, None, None, None, 0, None)
+    assert st == X.XA_EINVAL
+
+
+def test_device_calls_validate_before_launch(L):
+    """Argument errors are reported on the host, before anything is enqueued."""
+    p = X.plan_image(64, 64, X.sampling_grid(1), 2, 1.2, 100, 20)
+    hp = p.host_ptr()
+    # NULL device pointers
+    assert L.xa_simulate_views(hp, hp, None, 64, None, None, None, None, 0, None) == X.XA_EINVAL
+    # too-small workspace (non-NULL dummy pointers are never dereferenced on the host)
+    st = L.xa_extract_orb(hp, hp, 256, 256, 256, 256, 256, 256, 256, 0, None)
+    assert st == X.XA_ECAPACITY
+    assert L.xa_match_views(256, 256, 0, 256, 256, 1, 100, 4, 5, 256, 256, 256, None) == X.XA_EINVAL
+    assert L.xa_match_views(256, 256, 1, 256, 256, 1, 100, 4, 0, 256, 256, 256, None) == X.XA_EINVAL
