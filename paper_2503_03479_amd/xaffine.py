@@ -162,8 +162,11 @@ class Plan:
     def device(self, device="cuda"):
         """Device copy of the blob (cached)."""
         import torch
-        if self._dev is None or str(self._dev.device) != str(torch.device(device)):
-            self._dev = torch.from_numpy(self.blob.copy()).to(device)
+        want = torch.device(device)
+        if want.type == "cuda" and want.index is None:
+            want = torch.device("cuda", torch.cuda.current_device())
+        if self._dev is None or self._dev.device != want:
+            self._dev = torch.from_numpy(self.blob.copy()).to(want)
         return self._dev
 
     def taps(self) -> np.ndarray:
@@ -302,3 +305,49 @@ def keypoints_np(kp_tensor) -> np.ndarray:
 def matches_np(m_tensor) -> np.ndarray:
     a = m_tensor.cpu().numpy()
     return a.reshape(a.shape[0], a.shape[1] * a.shape[2]).view(MATCH_DTYPE)
+
+
+class StageRunner:
+    """Preallocated buffers to run the path stage by stage (simulate, extract, match) for one
+    image pair, each stage one C-ABI call on the current stream."""
+
+    def __init__(self, plan_a: Plan, plan_b: Plan, device="cuda"):
+        import torch
+        self.plan_a, self.plan_b = plan_a, plan_b
+        self.device = torch.device(device)
+        L = lib()
+        z = lambda n, dt=torch.uint8: torch.zeros(max(int(n), 1), dtype=dt, device=self.device)  # noqa: E731
+        self.side = {}
+        for key, p in (("a", plan_a), ("b", plan_b)):
+            N = p.n_features
+            self.side[key] = dict(
+                plan=p, dev=p.device(self.device), arena=z(p.arena_bytes), mask=z(p.arena_bytes),
+                sim_ws=_empty(L.xa_simulate_workspace_size(p.host_ptr()), self.device),
+                ext_ws=_empty(L.xa_extract_workspace_size(p.host_ptr()), self.device),
+                kp=torch.zeros((p.n_views, N, 40), dtype=torch.uint8, device=self.device),
+                desc=torch.zeros((p.n_views, N, 32), dtype=torch.uint8, device=self.device),
+                count=torch.zeros(p.n_views, dtype=torch.int32, device=self.device))
+        n_pairs = plan_a.n_views * plan_b.n_views
+        self.matches = torch.zeros((n_pairs, plan_a.n_features, 8), dtype=torch.uint8, device=self.device)
+        self.pair_count = torch.zeros(n_pairs, dtype=torch.int32, device=self.device)
+        self.best = torch.zeros(4, dtype=torch.int32, device=self.device)
+
+    def simulate(self, key: str, img):
+        s = self.side[key]
+        p = s["plan"]
+        _check(lib().xa_simulate_views(p.host_ptr(), _ptr(s["dev"]), _ptr(img), img.stride(0), _ptr(s["arena"]),
+                                       _ptr(s["mask"]), None, _ptr(s["sim_ws"]), s["sim_ws"].numel(), _stream()))
+
+    def extract(self, key: str, pattern):
+        s = self.side[key]
+        p = s["plan"]
+        _check(lib().xa_extract_orb(p.host_ptr(), _ptr(s["dev"]), _ptr(s["arena"]), _ptr(s["mask"]), _ptr(pattern),
+                                    _ptr(s["kp"]), _ptr(s["desc"]), _ptr(s["count"]), _ptr(s["ext_ws"]),
+                                    s["ext_ws"].numel(), _stream()))
+
+    def match(self, ratio_num: int = 4, ratio_den: int = 5):
+        a, b = self.side["a"], self.side["b"]
+        _check(lib().xa_match_views(_ptr(a["desc"]), _ptr(a["count"]), self.plan_a.n_views, _ptr(b["desc"]),
+                                    _ptr(b["count"]), self.plan_b.n_views, self.plan_a.n_features, ratio_num,
+                                    ratio_den, _ptr(self.matches), _ptr(self.pair_count), _ptr(self.best),
+                                    _stream()))
