@@ -84,7 +84,7 @@ typedef struct {
     int32_t blur_major;         /* 0: taps step along x, 1: along y */
     int32_t blur_tap0;          /* first entry in the tap table */
     int32_t blur_ntaps;         /* 2K + 1, 0 if no blur */
-    int32_t pad;
+    int32_t warp_tile_w;        /* width of the warp's output tiles (tiles hold 256 pixels) */
 } xa_view_desc;
 
 /* One pyramid level of one view.  Level sizes are round(W' / scale^l);

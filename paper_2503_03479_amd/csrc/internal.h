@@ -10,10 +10,19 @@
 namespace xa {
 
 // Tile shapes of the launch geometry (the plan's prefix tables are counted in these tiles).
-constexpr int kWarpTX = 64, kWarpTY = 4;    // warp: one thread per view pixel, 256 threads
+constexpr int kWarpThreads = 256;           // warp: one thread per view pixel, tiles of 256 pixels
+constexpr int kWarpLds = 8192;              // floats of source footprint a warp tile can stage in LDS
 constexpr int kPyrTX = 64, kPyrTY = 4;      // pyramid down-sampling
 constexpr int kFastTX = 64, kFastTY = 8;    // FAST / NMS / smoothing tiles (256 threads, 2 rows each)
-constexpr int kBlurTX = 64, kBlurTY = 4;    // directional blur over the source
+constexpr int kBlurTX = 64, kBlurTY = 16;   // directional blur over the source (4 rows per thread)
+constexpr int kBlurLds = 16384;             // bytes of source a blur tile can stage in LDS
+
+// Warp tile width for a view: the output tile is w x (256 / w), narrow along the compressed
+// axis so that its source footprint stays compact (about 16 t x 16 for a 16 x 16 tile).
+inline int warp_tile_w(double t, double s) {
+    const double c = t / s;
+    return c < 2.0 ? 16 : (c < 8.0 ? 8 : 4);
+}
 constexpr int kBorder = 22;                 // detection border (rotated BRIEF tests reach 21 px)
 constexpr size_t kAlign = 256;
 

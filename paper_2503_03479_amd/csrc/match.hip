@@ -10,9 +10,23 @@
 namespace xa {
 namespace {
 
-constexpr int kMatchThreads = 256;
+constexpr int kMatchThreads = 128;   // two waves per block; a block owns 128 * Q queries of one view pair
 constexpr int kMatchChunk = 512;     // train descriptors per LDS chunk (16 KiB)
 constexpr int kIdxBits = 13;         // train index field of the packed (distance, index) key
+
+// popcount(x) + acc in one v_bcnt_u32_b32 (keeps the eight popcounts of a 256-bit distance a chain)
+__device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
+    uint32_t r;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+    return r;
+}
+
+// median of three: with m1 <= m2, med3(m1, key, m2) = min(m2, max(m1, key))
+__device__ __forceinline__ uint32_t med3_u32(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
 
 __global__ void k_fill_i32(int32_t* p, int n, int32_t v) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -59,21 +73,22 @@ __global__ void __launch_bounds__(kMatchThreads) k_match(const uint32_t* __restr
         __syncthreads();
         for (int e = threadIdx.x; e < cn * 2; e += kMatchThreads) tr[e] = tb[size_t(c0) * 2 + e];
         __syncthreads();
+#pragma unroll 2
         for (int r = 0; r < cn; ++r) {
             const uint4 t0 = tr[2 * r], t1 = tr[2 * r + 1];
             const uint32_t idx = uint32_t(c0 + r);
 #pragma unroll
             for (int a = 0; a < Q; ++a) {
                 uint32_t d = __popc(q[a][0] ^ t0.x);
-                d += __popc(q[a][1] ^ t0.y);
-                d += __popc(q[a][2] ^ t0.z);
-                d += __popc(q[a][3] ^ t0.w);
-                d += __popc(q[a][4] ^ t1.x);
-                d += __popc(q[a][5] ^ t1.y);
-                d += __popc(q[a][6] ^ t1.z);
-                d += __popc(q[a][7] ^ t1.w);
+                d = bcnt_acc(q[a][1] ^ t0.y, d);
+                d = bcnt_acc(q[a][2] ^ t0.z, d);
+                d = bcnt_acc(q[a][3] ^ t0.w, d);
+                d = bcnt_acc(q[a][4] ^ t1.x, d);
+                d = bcnt_acc(q[a][5] ^ t1.y, d);
+                d = bcnt_acc(q[a][6] ^ t1.z, d);
+                d = bcnt_acc(q[a][7] ^ t1.w, d);
                 const uint32_t key = (d << kIdxBits) | idx;
-                m2[a] = min(m2[a], max(m1[a], key));
+                m2[a] = med3_u32(m1[a], key, m2[a]);
                 m1[a] = min(m1[a], key);
             }
         }
@@ -173,6 +188,8 @@ xa_status launch_match(const uint8_t* desc_a, const int32_t* count_a, int32_t n_
     hipLaunchKernelGGL(k_fill_i32, dim3((n_pairs + 255) / 256), dim3(256), 0, st, pair_count, n_pairs, 0);
     const uint32_t* da = reinterpret_cast<const uint32_t*>(desc_a);
     const uint32_t* db = reinterpret_cast<const uint32_t*>(desc_b);
+    // Q queries per lane: 4 amortises each LDS broadcast of a train descriptor over 4 comparisons;
+    // fewer for small N so that padding lanes do not dominate
     if (N > 2 * kMatchThreads) {
         const int gy = (N + 4 * kMatchThreads - 1) / (4 * kMatchThreads);
         hipLaunchKernelGGL(k_match<4>, dim3(n_pairs, gy), dim3(kMatchThreads), 0, st, da, count_a, db, count_b, n_b, N,

@@ -147,13 +147,26 @@ constexpr int kFastHalo = 4;                                  // circle radius 3
 constexpr int kFastLW = kFastTX + 2 * kFastHalo;              // 72
 constexpr int kFastLH = kFastTY + 2 * kFastHalo;              // 16
 constexpr int kScoreW = kFastTX + 2, kScoreH = kFastTY + 2;   // 66 x 10
+constexpr int kSmRows = kFastTY + 6;                          // rows of horizontal smoothing sums
 
+// One block per 64 x 8 tile of one (view, level), levels that can hold detections only:
+//  1. the tile plus a 4-pixel halo is staged in LDS (border replicated);
+//  2. the 7-tap smoothing [18 34 49 54 49 34 18] / 256 of the tile is written out
+//     (exact horizontal sums, vertical pass (sum + 2^15) >> 16);
+//  3. FAST-9 scores on the tile plus a one-pixel ring: an exact pre-test on the four
+//     compass pixels (any 9-pixel arc contains two of them) queues the pixels that can be
+//     corners, and only those get the full score;
+//  4. 3x3 non-maximum suppression (ties to the earlier raster position), the content
+//     filter on the corners of the +-B box, and ballot compaction of the survivors.
 __global__ void __launch_bounds__(256) k_fast(const xa_level_desc* __restrict__ levels, const int32_t* __restrict__ prefix,
                                               int nvl, int T, const uint8_t* __restrict__ arena,
                                               const uint8_t* __restrict__ mask, uint32_t* __restrict__ cand,
-                                              int32_t* __restrict__ cand_count) {
+                                              int32_t* __restrict__ cand_count, uint8_t* __restrict__ smooth) {
     __shared__ uint8_t img[kFastLH * kFastLW];
     __shared__ int score[kScoreH * kScoreW];
+    __shared__ int hs[kSmRows * kFastTX];
+    __shared__ int16_t queue[kScoreH * kScoreW];
+    __shared__ int qn;
     const int b = blockIdx.x;
     const int vl = find_segment(prefix, nvl, b);
     const xa_level_desc d = levels[vl];
@@ -162,23 +175,59 @@ __global__ void __launch_bounds__(256) k_fast(const xa_level_desc* __restrict__ 
     const int local = b - prefix[vl];
     const int tiles_x = (W + kFastTX - 1) / kFastTX;
     const int x0 = (local % tiles_x) * kFastTX, y0 = (local / tiles_x) * kFastTY;
-    // the tile's pixels that can be detections: [B, W-B) x [B, H-B)
-    if (x0 + kFastTX <= kBorder || x0 >= W - kBorder || y0 + kFastTY <= kBorder || y0 >= H - kBorder) return;
     const uint8_t* P = arena + d.offset;
     for (int e = threadIdx.x; e < kFastLH * kFastLW; e += 256) {
-        const int ly = e / kFastLW, lx = e % kFastLW;
+        const int ly = e / kFastLW, lx = e - (e / kFastLW) * kFastLW;
         const int gx = clampi(x0 - kFastHalo + lx, 0, W - 1), gy = clampi(y0 - kFastHalo + ly, 0, H - 1);
         img[e] = P[size_t(gy) * W + gx];
     }
+    if (threadIdx.x == 0) qn = 0;
     __syncthreads();
-    // scores on the tile plus a one-pixel ring; only positions in [B-1, W-B] x [B-1, H-B] are ever compared
-    for (int e = threadIdx.x; e < kScoreH * kScoreW; e += 256) {
-        const int sy = e / kScoreW, sx = e % kScoreW;
-        const int gx = x0 - 1 + sx, gy = y0 - 1 + sy;
-        int v = kNegV;
-        if (gx >= kBorder - 1 && gx <= W - kBorder && gy >= kBorder - 1 && gy <= H - kBorder)
-            v = fast_score_lds(img, kFastLW, sx + kFastHalo - 1, sy + kFastHalo - 1, T);
-        score[e] = v;
+    // smoothing: horizontal sums for rows y0-3 .. y0+10, then the vertical pass
+    const int w7[7] = {18, 34, 49, 54, 49, 34, 18};
+    for (int e = threadIdx.x; e < kSmRows * kFastTX; e += 256) {
+        const int r = e / kFastTX, c = e - (e / kFastTX) * kFastTX;
+        const uint8_t* row = img + (r + 1) * kFastLW + c + 1;
+        int sum = 0;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) sum += w7[k] * int(row[k]);
+        hs[e] = sum;
+    }
+    // FAST pre-test over the tile and its ring; positions that cannot be compared stay non-corners
+    const bool detect = !(x0 + kFastTX <= kBorder || x0 >= W - kBorder || y0 + kFastTY <= kBorder || y0 >= H - kBorder);
+    if (detect) {
+        for (int e = threadIdx.x; e < kScoreH * kScoreW; e += 256) {
+            const int sy = e / kScoreW, sx = e - (e / kScoreW) * kScoreW;
+            const int gx = x0 - 1 + sx, gy = y0 - 1 + sy;
+            score[e] = kNegV;
+            if (gx >= kBorder - 1 && gx <= W - kBorder && gy >= kBorder - 1 && gy <= H - kBorder) {
+                const uint8_t* p = img + (sy + kFastHalo - 1) * kFastLW + sx + kFastHalo - 1;
+                const int c = p[0];
+                const int n = p[-3 * kFastLW], e3 = p[3], s3 = p[3 * kFastLW], w3 = p[-3];
+                const int nb = (n > c + T) + (e3 > c + T) + (s3 > c + T) + (w3 > c + T);
+                const int nd = (n < c - T) + (e3 < c - T) + (s3 < c - T) + (w3 < c - T);
+                if (nb >= 2 || nd >= 2) queue[atomicAdd(&qn, 1)] = int16_t(e);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < kFastTY / 4; ++rr) {
+        const int tx = threadIdx.x % kFastTX, ty = threadIdx.x / kFastTX + 4 * rr;
+        const int x = x0 + tx, y = y0 + ty;
+        if (x < W && y < H) {
+            int sum = 0;
+#pragma unroll
+            for (int k = 0; k < 7; ++k) sum += w7[k] * hs[(ty + k) * kFastTX + tx];
+            smooth[size_t(d.offset) + size_t(y) * W + x] = uint8_t((sum + (1 << 15)) >> 16);
+        }
+    }
+    if (!detect) return;
+    const int nq = qn;
+    for (int q = threadIdx.x; q < nq; q += 256) {
+        const int e = queue[q];
+        const int sy = e / kScoreW, sx = e - (e / kScoreW) * kScoreW;
+        score[e] = fast_score_lds(img, kFastLW, sx + kFastHalo - 1, sy + kFastHalo - 1, T);
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
@@ -369,51 +418,6 @@ __global__ void __launch_bounds__(kSelThreads) k_select(const xa_level_desc* __r
     if (threadIdx.x == 0) stage_count[vl] = n;
 }
 
-// ------------------------------------------------------------------ smoothing
-
-constexpr int kSmLW = kFastTX + 6, kSmLH = kFastTY + 6;
-
-// Separable [18 34 49 54 49 34 18] / 256, border replicated: exact horizontal sums,
-// vertical pass rounded, (sum + 2^15) >> 16.
-__global__ void __launch_bounds__(256) k_smooth(const xa_level_desc* __restrict__ levels, const int32_t* __restrict__ prefix,
-                                                int nvl, const uint8_t* __restrict__ arena, uint8_t* __restrict__ smooth) {
-    __shared__ uint8_t img[kSmLH * kSmLW];
-    __shared__ int hs[kSmLH * kFastTX];
-    const int b = blockIdx.x;
-    const int vl = find_segment(prefix, nvl, b);
-    const xa_level_desc d = levels[vl];
-    if (d.cand_cap == 0) return;
-    const int W = d.width, H = d.height;
-    const int local = b - prefix[vl];
-    const int tiles_x = (W + kFastTX - 1) / kFastTX;
-    const int x0 = (local % tiles_x) * kFastTX, y0 = (local / tiles_x) * kFastTY;
-    const uint8_t* P = arena + d.offset;
-    for (int e = threadIdx.x; e < kSmLH * kSmLW; e += 256) {
-        const int ly = e / kSmLW, lx = e % kSmLW;
-        img[e] = P[size_t(clampi(y0 - 3 + ly, 0, H - 1)) * W + clampi(x0 - 3 + lx, 0, W - 1)];
-    }
-    __syncthreads();
-    const int w[7] = {18, 34, 49, 54, 49, 34, 18};
-    for (int e = threadIdx.x; e < kSmLH * kFastTX; e += 256) {
-        const int ly = e / kFastTX, lx = e % kFastTX;
-        int s = 0;
-#pragma unroll
-        for (int k = 0; k < 7; ++k) s += w[k] * int(img[ly * kSmLW + lx + k]);
-        hs[e] = s;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int rr = 0; rr < kFastTY / 4; ++rr) {
-        const int tx = threadIdx.x % kFastTX, ty = threadIdx.x / kFastTX + 4 * rr;
-        const int x = x0 + tx, y = y0 + ty;
-        if (x >= W || y >= H) continue;
-        int s = 0;
-#pragma unroll
-        for (int k = 0; k < 7; ++k) s += w[k] * hs[(ty + k) * kFastTX + tx];
-        smooth[size_t(d.offset) + size_t(y) * W + x] = uint8_t((s + (1 << 15)) >> 16);
-    }
-}
-
 // ------------------------------------------------------------------ orientation + rBRIEF
 
 __device__ __forceinline__ int rnd20(int v) {
@@ -529,8 +533,7 @@ xa_status launch_extract(const PlanView& ph, const PlanView& pd, uint8_t* arena,
     const int vt = ph.vl_prefix[nvl];
     if (vt > 0) {
         hipLaunchKernelGGL(k_fast, dim3(vt), dim3(256), 0, st, pd.levels, pd.vl_prefix, nvl, h->fast_threshold,
-                           arena, mask, cand, cand_count);
-        hipLaunchKernelGGL(k_smooth, dim3(vt), dim3(256), 0, st, pd.levels, pd.vl_prefix, nvl, arena, smooth);
+                           arena, mask, cand, cand_count, smooth);
     }
     hipLaunchKernelGGL(k_select, dim3(nvl), dim3(kSelThreads), 0, st, pd.levels, N, arena, cand, cand_count, harris,
                        stage, stage_count);

@@ -250,7 +250,9 @@ extern "C" xa_status xa_plan_image(int32_t src_w, int32_t src_h, const xa_affine
             blur_views.push_back(i);
         }
         warp_prefix[i] = int32_t(warp_tiles);
-        warp_tiles += int64_t((v.width + kWarpTX - 1) / kWarpTX) * ((v.height + kWarpTY - 1) / kWarpTY);
+        v.warp_tile_w = warp_tile_w(v.p.t, v.p.s);
+        const int th = kWarpThreads / v.warp_tile_w;
+        warp_tiles += int64_t((v.width + v.warp_tile_w - 1) / v.warp_tile_w) * ((v.height + th - 1) / th);
         int32_t kp_base = 0;
         for (int l = 0; l < n_levels; ++l) {
             xa_level_desc& d = lv[size_t(i) * n_levels + l];

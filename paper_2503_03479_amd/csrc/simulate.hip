@@ -21,41 +21,86 @@ __device__ __forceinline__ int find_segment(const int32_t* __restrict__ prefix, 
     return lo;
 }
 
-// Directional Gaussian over the source: one thread per source pixel of one blurred view.
-// out(p) = sum_k w_k lerp(I, p + k v) with v = (1, m) (major x) or (m, 1) (major y).
+// Directional Gaussian over the source, one block per 64 x 16 tile of one blurred view.
+// out(p) = sum_k w_k lerp(I, p + k v), v = (1, m) (major x) or (m, 1) (major y).  The
+// tile's source footprint (the tile grown by the tap offsets) is staged in LDS with the
+// border replicated at load time, which is the same clamping as clamping each tap.
 __global__ void __launch_bounds__(256) k_blur(const uint8_t* __restrict__ src, int W, int H, int pitch,
                                               const xa_view_desc* __restrict__ views,
                                               const int32_t* __restrict__ blur_views,
                                               const BlurTap* __restrict__ taps, float* __restrict__ out) {
+    __shared__ uint8_t tile[kBlurLds];
     const int tiles_x = (W + kBlurTX - 1) / kBlurTX;
-    const int x = (blockIdx.x % tiles_x) * kBlurTX + (threadIdx.x % kBlurTX);
-    const int y = (blockIdx.x / tiles_x) * kBlurTY + (threadIdx.x / kBlurTX);
-    if (x >= W || y >= H) return;
+    const int x0 = (blockIdx.x % tiles_x) * kBlurTX, y0 = (blockIdx.x / tiles_x) * kBlurTY;
+    const int tx = threadIdx.x % kBlurTX, ty0 = threadIdx.x / kBlurTX;
     const xa_view_desc& v = views[blur_views[blockIdx.y]];
     const BlurTap* tp = taps + v.blur_tap0;
-    const int n = v.blur_ntaps;
-    float acc = 0.0f;
+    const int n = v.blur_ntaps, K = (n - 1) / 2;
+    const int dlo = min(tp[0].dmin, tp[n - 1].dmin), dhi = max(tp[0].dmin, tp[n - 1].dmin) + 1;
+    int rx0, ry0, rw, rh;
     if (v.blur_major == 0) {
-        for (int k = 0; k < n; ++k) {
-            const BlurTap t = tp[k];
-            const int xk = clampi(x + t.dmaj, 0, W - 1);
-            const int y0 = y + t.dmin;
-            const float a = float(src[size_t(clampi(y0, 0, H - 1)) * pitch + xk]);
-            const float b = float(src[size_t(clampi(y0 + 1, 0, H - 1)) * pitch + xk]);
-            acc += t.w * ((1.0f - t.frac) * a + t.frac * b);
-        }
+        rx0 = x0 - K; rw = kBlurTX + 2 * K;
+        ry0 = y0 + dlo; rh = kBlurTY - 1 + dhi - dlo + 1;
     } else {
-        for (int k = 0; k < n; ++k) {
-            const BlurTap t = tp[k];
-            const int yk = clampi(y + t.dmaj, 0, H - 1);
-            const int x0 = x + t.dmin;
-            const uint8_t* row = src + size_t(yk) * pitch;
-            const float a = float(row[clampi(x0, 0, W - 1)]);
-            const float b = float(row[clampi(x0 + 1, 0, W - 1)]);
-            acc += t.w * ((1.0f - t.frac) * a + t.frac * b);
-        }
+        rx0 = x0 + dlo; rw = kBlurTX - 1 + dhi - dlo + 1;
+        ry0 = y0 - K; rh = kBlurTY + 2 * K;
     }
-    out[v.blur_offset + size_t(y) * W + x] = acc;
+    float* o = out + v.blur_offset;
+    if (rw * rh <= kBlurLds) {
+        for (int e = threadIdx.x; e < rw * rh; e += 256) {
+            const int r = e / rw, c = e - (e / rw) * rw;
+            tile[e] = src[size_t(clampi(ry0 + r, 0, H - 1)) * pitch + clampi(rx0 + c, 0, W - 1)];
+        }
+        __syncthreads();
+        for (int j = 0; j < kBlurTY / 4; ++j) {
+            const int x = x0 + tx, y = y0 + ty0 + 4 * j;
+            if (x >= W || y >= H) continue;
+            float acc = 0.0f;
+            if (v.blur_major == 0) {
+                for (int k = 0; k < n; ++k) {
+                    const BlurTap t = tp[k];
+                    const uint8_t* r = tile + (y + t.dmin - ry0) * rw + (x + t.dmaj - rx0);
+                    const float a = float(r[0]), b = float(r[rw]);
+                    acc += t.w * ((1.0f - t.frac) * a + t.frac * b);
+                }
+            } else {
+                for (int k = 0; k < n; ++k) {
+                    const BlurTap t = tp[k];
+                    const uint8_t* r = tile + (y + t.dmaj - ry0) * rw + (x + t.dmin - rx0);
+                    const float a = float(r[0]), b = float(r[1]);
+                    acc += t.w * ((1.0f - t.frac) * a + t.frac * b);
+                }
+            }
+            o[size_t(y) * W + x] = acc;
+        }
+        return;
+    }
+    // footprint larger than the LDS tile (very large sigma): read the taps from global memory
+    for (int j = 0; j < kBlurTY / 4; ++j) {
+        const int x = x0 + tx, y = y0 + ty0 + 4 * j;
+        if (x >= W || y >= H) continue;
+        float acc = 0.0f;
+        if (v.blur_major == 0) {
+            for (int k = 0; k < n; ++k) {
+                const BlurTap t = tp[k];
+                const int xk = clampi(x + t.dmaj, 0, W - 1);
+                const int yk = y + t.dmin;
+                const float a = float(src[size_t(clampi(yk, 0, H - 1)) * pitch + xk]);
+                const float b = float(src[size_t(clampi(yk + 1, 0, H - 1)) * pitch + xk]);
+                acc += t.w * ((1.0f - t.frac) * a + t.frac * b);
+            }
+        } else {
+            for (int k = 0; k < n; ++k) {
+                const BlurTap t = tp[k];
+                const uint8_t* row = src + size_t(clampi(y + t.dmaj, 0, H - 1)) * pitch;
+                const int xk = x + t.dmin;
+                const float a = float(row[clampi(xk, 0, W - 1)]);
+                const float b = float(row[clampi(xk + 1, 0, W - 1)]);
+                acc += t.w * ((1.0f - t.frac) * a + t.frac * b);
+            }
+        }
+        o[size_t(y) * W + x] = acc;
+    }
 }
 
 // Weights L4(i - f), i = -3..4, of eq. (4) (a = 4), normalised to sum 1.
@@ -95,37 +140,71 @@ __device__ __forceinline__ double affine_x(const double* m, double qx, double qy
     return __dadd_rn(__dadd_rn(__dmul_rn(m[0], qx), __dmul_rn(m[1], qy)), m[2]);
 }
 
-template <typename T>
-__device__ __forceinline__ float lanczos_sample(const T* __restrict__ S, int W, int H, int ix, int iy,
-                                                const float wx[8], const float wy[8]) {
-    int cols[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) cols[i] = clampi(ix - 3 + i, 0, W - 1);
+// 8 x 8 Lanczos sum of eq. (3) with normalised weights; row(j) returns a pointer such
+// that row(j)[c] is the source sample at clamped column c of clamped row iy - 3 + j.
+template <typename Row>
+__device__ __forceinline__ float lanczos_sum(Row row, const int cols[8], const float wx[8], const float wy[8]) {
     float acc = 0.0f;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-        const T* row = S + size_t(clampi(iy - 3 + j, 0, H - 1)) * W;
-        float r = 0.0f;
+        const auto* r = row(j);
+        float s = 0.0f;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) r += wx[i] * float(row[cols[i]]);
-        acc += wy[j] * r;
+        for (int i = 0; i < 8; ++i) s += wx[i] * float(r[cols[i]]);
+        acc += wy[j] * s;
     }
     return acc;
 }
 
-// One thread per view pixel; all views of the plan in one launch (block -> view by prefix search).
-__global__ void __launch_bounds__(256) k_warp(const uint8_t* __restrict__ src, int W, int H, int pitch,
-                                              const float* __restrict__ blurred,
-                                              const xa_view_desc* __restrict__ views, int n_views,
-                                              const int32_t* __restrict__ prefix, uint8_t* __restrict__ arena,
-                                              uint8_t* __restrict__ mask, float* __restrict__ values) {
+// One thread per view pixel, one block per 256-pixel output tile (w x 256/w, w per view);
+// all views of the plan in one launch (block -> view by prefix search).  The tile's source
+// footprint (bounding box of its pixel centres mapped through inv, grown by the 8-tap
+// window) is staged in LDS as fp32 when it fits; otherwise taps are read from global memory.
+__global__ void __launch_bounds__(kWarpThreads) k_warp(const uint8_t* __restrict__ src, int W, int H, int pitch,
+                                                       const float* __restrict__ blurred,
+                                                       const xa_view_desc* __restrict__ views, int n_views,
+                                                       const int32_t* __restrict__ prefix, uint8_t* __restrict__ arena,
+                                                       uint8_t* __restrict__ mask, float* __restrict__ values) {
+    __shared__ float tile[kWarpLds];
     const int b = blockIdx.x;
     const int vi = find_segment(prefix, n_views, b);
     const xa_view_desc& v = views[vi];
     const int local = b - prefix[vi];
-    const int tiles_x = (v.width + kWarpTX - 1) / kWarpTX;
-    const int qx = (local % tiles_x) * kWarpTX + (threadIdx.x % kWarpTX);
-    const int qy = (local / tiles_x) * kWarpTY + (threadIdx.x / kWarpTX);
+    const int tw = v.warp_tile_w, th = kWarpThreads / tw;
+    const int tiles_x = (v.width + tw - 1) / tw;
+    const int x0 = (local % tiles_x) * tw, y0 = (local / tiles_x) * th;
+    const int qx = x0 + int(threadIdx.x) % tw, qy = y0 + int(threadIdx.x) / tw;
+    // bounding box of the footprint, in clamped source indices
+    double pxl = 1e300, pxh = -1e300, pyl = 1e300, pyh = -1e300;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const double cx = double(x0 + ((c & 1) ? tw - 1 : 0)), cy = double(y0 + ((c & 2) ? th - 1 : 0));
+        const double px = affine_x(v.inv, cx, cy), py = affine_x(v.inv + 3, cx, cy);
+        pxl = fmin(pxl, px); pxh = fmax(pxh, px);
+        pyl = fmin(pyl, py); pyh = fmax(pyh, py);
+    }
+    const int bx0 = max(int(fmax(floor(pxl - 1e-6), -1e9)) - 3, 0);
+    const int bx1 = min(int(fmin(floor(pxh + 1e-6), 1e9)) + 4, W - 1);
+    const int by0 = max(int(fmax(floor(pyl - 1e-6), -1e9)) - 3, 0);
+    const int by1 = min(int(fmin(floor(pyh + 1e-6), 1e9)) + 4, H - 1);
+    const int bw = bx1 - bx0 + 1, bh = by1 - by0 + 1;
+    const bool use_lds = bw > 0 && bh > 0 && (long long)bw * bh <= kWarpLds;
+    const bool blur = v.blur_offset >= 0;
+    const float* bsrc = blurred + (blur ? v.blur_offset : 0);
+    if (use_lds) {
+        if (blur) {
+            for (int e = threadIdx.x; e < bw * bh; e += kWarpThreads) {
+                const int r = e / bw, c = e - (e / bw) * bw;
+                tile[e] = bsrc[size_t(by0 + r) * W + bx0 + c];
+            }
+        } else {
+            for (int e = threadIdx.x; e < bw * bh; e += kWarpThreads) {
+                const int r = e / bw, c = e - (e / bw) * bw;
+                tile[e] = float(src[size_t(by0 + r) * pitch + bx0 + c]);
+            }
+        }
+    }
+    __syncthreads();
     if (qx >= v.width || qy >= v.height) return;
     const size_t o = size_t(v.offset) + size_t(qy) * v.width + qx;
     const double px = affine_x(v.inv, double(qx), double(qy));
@@ -142,22 +221,21 @@ __global__ void __launch_bounds__(256) k_warp(const uint8_t* __restrict__ src, i
     float wx[8], wy[8];
     lanczos4_weights(float(px - fxd), wx);
     lanczos4_weights(float(py - fyd), wy);
+    int cols[8];
     float val;
-    if (v.blur_offset >= 0) {
-        val = lanczos_sample(blurred + v.blur_offset, W, H, ix, iy, wx, wy);
-    } else if (pitch == W) {
-        val = lanczos_sample(src, W, H, ix, iy, wx, wy);
+    if (use_lds) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) cols[i] = clampi(clampi(ix - 3 + i, 0, W - 1) - bx0, 0, bw - 1);
+        val = lanczos_sum([&](int j) { return tile + clampi(clampi(iy - 3 + j, 0, H - 1) - by0, 0, bh - 1) * bw; },
+                          cols, wx, wy);
     } else {
-        // general pitch: row addressing through the pitch
-        int cols[8];
+#pragma unroll
         for (int i = 0; i < 8; ++i) cols[i] = clampi(ix - 3 + i, 0, W - 1);
-        val = 0.0f;
-        for (int j = 0; j < 8; ++j) {
-            const uint8_t* row = src + size_t(clampi(iy - 3 + j, 0, H - 1)) * pitch;
-            float r = 0.0f;
-            for (int i = 0; i < 8; ++i) r += wx[i] * float(row[cols[i]]);
-            val += wy[j] * r;
-        }
+        if (blur)
+            val = lanczos_sum([&](int j) { return bsrc + size_t(clampi(iy - 3 + j, 0, H - 1)) * W; }, cols, wx, wy);
+        else
+            val = lanczos_sum([&](int j) { return src + size_t(clampi(iy - 3 + j, 0, H - 1)) * pitch; }, cols, wx,
+                              wy);
     }
     const float q = rintf(val);
     arena[o] = uint8_t(q < 0.0f ? 0.0f : (q > 255.0f ? 255.0f : q));
@@ -176,7 +254,7 @@ xa_status launch_simulate(const PlanView& ph, const PlanView& pd, const uint8_t*
     const xa_plan_header* h = ph.h;
     const int W = h->src_w, H = h->src_h;
     if (h->n_blur > 0) {
-        const int tiles = ((W + kBlurTX - 1) / kBlurTX) * ((H + kBlurTY - 1) / kBlurTY);
+        const int tiles = ((W + kBlurTX - 1) / kBlurTX) * ((H + kBlurTY - 1) / kBlurTY);  // 4 rows per thread
         hipLaunchKernelGGL(k_blur, dim3(tiles, h->n_blur), dim3(256), 0, st, src, W, H, pitch, pd.views,
                            pd.blur_views, pd.taps, blurred);
         hipError_t e = hipGetLastError();
@@ -184,7 +262,7 @@ xa_status launch_simulate(const PlanView& ph, const PlanView& pd, const uint8_t*
     }
     const int tiles = ph.warp_prefix[h->n_views];
     if (tiles > 0) {
-        hipLaunchKernelGGL(k_warp, dim3(tiles), dim3(256), 0, st, src, W, H, pitch, blurred, pd.views, h->n_views,
+        hipLaunchKernelGGL(k_warp, dim3(tiles), dim3(kWarpThreads), 0, st, src, W, H, pitch, blurred, pd.views, h->n_views,
                            pd.warp_prefix, arena, mask, values);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "warp launch");

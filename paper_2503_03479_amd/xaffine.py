@@ -25,7 +25,7 @@ PARAMS_DTYPE = np.dtype([("t", "f8"), ("phi", "f8"), ("psi", "f8"), ("s", "f8"),
 VIEW_DTYPE = np.dtype([("p", PARAMS_DTYPE), ("src_w", "i4"), ("src_h", "i4"), ("width", "i4"), ("height", "i4"),
                        ("fwd", "f8", 6), ("inv", "f8", 6), ("sigma", "f8"), ("ux", "f8"), ("uy", "f8"),
                        ("offset", "i8"), ("blur_offset", "i8"), ("blur_major", "i4"), ("blur_tap0", "i4"),
-                       ("blur_ntaps", "i4"), ("pad", "i4")])
+                       ("blur_ntaps", "i4"), ("warp_tile_w", "i4")])
 LEVEL_DTYPE = np.dtype([("width", "i4"), ("height", "i4"), ("offset", "i8"), ("quota", "i4"), ("kp_base", "i4"),
                         ("view", "i4"), ("level", "i4"), ("cand_offset", "i8"), ("cand_cap", "i8")])
 HEADER_DTYPE = np.dtype([("magic", "u4"), ("version", "u4"), ("src_w", "i4"), ("src_h", "i4"), ("n_views", "i4"),
