@@ -51,7 +51,7 @@ typedef enum {
 } xa_status;
 
 #define XA_PLAN_MAGIC 0x58414650u   /* "XAFP" */
-#define XA_PLAN_VERSION 1u
+#define XA_PLAN_VERSION 2u
 #define XA_MAX_LEVELS 12
 #define XA_MAX_QUOTA 2048           /* keypoints per pyramid level */
 #define XA_MAX_FEATURES 4096        /* keypoints per view */
@@ -85,16 +85,22 @@ typedef struct {
     int32_t blur_tap0;          /* first entry in the tap table */
     int32_t blur_ntaps;         /* 2K + 1, 0 if no blur */
     int32_t warp_tile_w;        /* width of the warp's output tiles (tiles hold 256 pixels) */
+    int32_t pitch;              /* row pitch of level 0 in the arena (bytes) */
+    int32_t pad;
 } xa_view_desc;
 
 /* One pyramid level of one view.  Level sizes are round(W' / scale^l);
- * quota is the number of keypoints the level may contribute. */
+ * quota is the number of keypoints the level may contribute.  Pixel (x, y)
+ * of the level is byte offset + y * pitch + x of the arena; pitch is the
+ * width rounded up to a multiple of 16 (the padding bytes are unspecified). */
 typedef struct {
     int32_t width, height;
-    int64_t offset;             /* byte offset of this level in the pyramid arena */
+    int32_t pitch;
     int32_t quota;
+    int64_t offset;             /* byte offset of this level in the pyramid arena */
     int32_t kp_base;            /* sum of the quotas of the lower levels of the view */
     int32_t view, level;
+    int32_t pad;
     int64_t cand_offset;        /* first entry of this level in the candidate arena */
     int64_t cand_cap;           /* ceil(W/2) ceil(H/2): bound on corners that survive 3x3 NMS */
 } xa_level_desc;
@@ -177,7 +183,9 @@ xa_status xa_plan_image(int32_t src_w, int32_t src_h, const xa_affine_params* pa
  * 0 outside the source), its content mask into d_mask (1 where the view pixel
  * maps inside the source rectangle) and, if d_values is not NULL, the
  * unquantised fp32 values at the same element offsets (d_values then holds
- * arena_bytes floats).  Workspace: xa_simulate_workspace_size(plan_host). */
+ * arena_bytes floats).  Pixel (x, y) of view v is element offset + y * pitch + x
+ * (xa_view_desc).  d_arena and d_mask must be 128-byte aligned.
+ * Workspace: xa_simulate_workspace_size(plan_host). */
 size_t xa_simulate_workspace_size(const void* plan_host);
 xa_status xa_simulate_views(const void* plan_host, const void* plan_dev,
                             const uint8_t* d_src, int32_t src_pitch,

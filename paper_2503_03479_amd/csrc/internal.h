@@ -12,8 +12,8 @@ namespace xa {
 // Tile shapes of the launch geometry (the plan's prefix tables are counted in these tiles).
 constexpr int kWarpThreads = 256;           // warp: one thread per view pixel, tiles of 256 pixels
 constexpr int kWarpLds = 8192;              // floats of source footprint a warp tile can stage in LDS
-constexpr int kPyrTX = 64, kPyrTY = 4;      // pyramid down-sampling
-constexpr int kFastTX = 64, kFastTY = 8;    // FAST / NMS / smoothing tiles (256 threads, 2 rows each)
+constexpr int kPyrTX = 256, kPyrTY = 4;     // pyramid down-sampling (4 output pixels per thread)
+constexpr int kFastTX = 64, kFastTY = 32;   // FAST / NMS / smoothing / Harris tiles (256 threads, 8 rows each)
 constexpr int kBlurTX = 64, kBlurTY = 16;   // directional blur over the source (4 rows per thread)
 constexpr int kBlurLds = 16384;             // bytes of source a blur tile can stage in LDS
 
@@ -33,12 +33,21 @@ struct BlurTap {
     float frac;     // k m - floor(k m): linear-interpolation weight of the next row / column
 };
 static_assert(sizeof(BlurTap) == 16, "tap layout");
-static_assert(sizeof(xa_view_desc) == 216, "view desc layout");
-static_assert(sizeof(xa_level_desc) == 48, "level desc layout");
+static_assert(sizeof(xa_view_desc) == 224, "view desc layout");
+static_assert(sizeof(xa_level_desc) == 56, "level desc layout");
 static_assert(sizeof(xa_keypoint) == 40, "keypoint layout");
 static_assert(sizeof(xa_match) == 8, "match layout");
 
 inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+inline int32_t level_pitch(int32_t w) { return (w + 15) / 16 * 16; }
+
+// Candidate record written by the FAST kernel: raster position y * W + x and Harris response.
+struct Cand {
+    uint32_t raster;
+    uint32_t pad;
+    long long harris;
+};
+static_assert(sizeof(Cand) == 16, "candidate layout");
 
 // Status helpers (plan.cpp owns the thread-local message).
 xa_status fail(xa_status s, const char* fmt, ...);

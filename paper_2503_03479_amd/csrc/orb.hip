@@ -1,8 +1,9 @@
 // ORB on every simulated view, on gfx950: fixed-point pyramid, FAST-9 with 3x3
-// non-maximum suppression and wave-ballot compaction, integer Harris response with
-// per-level top-N selection, 7-tap integer smoothing, intensity-centroid
-// orientation (30 bins) and rBRIEF-256 packed by wave ballots.  All arithmetic
-// is integer, so the results are exact.
+// non-maximum suppression, integer Harris response, per-level top-N selection,
+// 7-tap integer smoothing, intensity-centroid orientation (30 bins) and
+// rBRIEF-256 packed by wave ballots.  All arithmetic is integer, so the results
+// are exact.  Levels live in one arena with 16-byte aligned rows, so tiles move
+// between HBM and LDS in 16-byte chunks.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -29,11 +30,19 @@ __constant__ int32_t c_sin[30] = {0, 218011, 426494, 616338, 779244, 908093, 997
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-__device__ __forceinline__ int find_segment(const int32_t* __restrict__ prefix, int n, int b) {
+// Largest i in [0, n) with prefix[i] <= b, searched 64 entries at a time by the whole
+// wave (every lane must be active); prefix[0] == 0 <= b < prefix[n].
+__device__ __forceinline__ int find_segment_wave(const int32_t* __restrict__ prefix, int n, int b) {
+    const int lane = threadIdx.x & 63;
     int lo = 0, hi = n;
     while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (prefix[mid] <= b) lo = mid; else hi = mid;
+        const int step = (hi - lo + 63) >> 6;
+        const int p = lo + lane * step;
+        const bool le = p < hi && prefix[p] <= b;
+        const unsigned long long bal = __ballot(le);
+        const int k = 63 - __clzll(bal);            // lane 0 always qualifies (prefix[lo] <= b)
+        lo = lo + k * step;
+        hi = min(hi, lo + step);
     }
     return lo;
 }
@@ -48,57 +57,99 @@ __global__ void k_fill_i32(int32_t* p, int n, int32_t v) {
 // Bilinear source position of destination index d for an n_src -> n_dst resize:
 // src = (d + 1/2) n_src / n_dst - 1/2 in 1/2048 units, rounded half up, in exact
 // unsigned arithmetic (1024 ((2d+1) n_src - n_dst) / n_dst split into quotient and remainder).
-__device__ __forceinline__ void resample_index(int d, int n_dst, int n_src, int& i0, int& i1, int& w1) {
+// Returns i0 << 11 | w1 (the second sample is min(i0 + 1, n_src - 1) with weight w1).
+__device__ __forceinline__ int resample_index(int d, int n_dst, int n_src) {
     const uint32_t A = uint32_t(2 * d + 1) * uint32_t(n_src) - uint32_t(n_dst);
     const uint32_t qa = A / uint32_t(n_dst);
     const uint32_t ra = A - qa * uint32_t(n_dst);
     const uint32_t q = 1024u * qa + (2048u * ra + uint32_t(n_dst)) / (2u * uint32_t(n_dst));
     int a = int(q >> 11), w = int(q & 2047u);
     if (a >= n_src - 1) { a = n_src - 1; w = 0; }
-    i0 = a;
-    w1 = w;
-    i1 = a + 1 < n_src ? a + 1 : n_src - 1;
+    return (a << 11) | w;
 }
 
+constexpr int kPyrLW = 640;        // LDS row stride of the staged source rows (bytes)
+constexpr int kPyrLH = 16;         // staged source rows
+
 // Level l of every view from level l-1: (sum_{2x2} wy wx pix + 2^21) >> 22; the content
-// mask of a level pixel is the AND over its 2x2 footprint.
+// mask of a level pixel is the AND over its 2x2 footprint.  One block per 256 x 4 output
+// tile, four output pixels (one 32-bit store) per thread; the source rows the tile reads
+// are staged in LDS in 16-byte chunks.
 __global__ void __launch_bounds__(256) k_pyr(const xa_level_desc* __restrict__ levels, int n_levels, int l,
                                              const int32_t* __restrict__ prefix, int n_views,
                                              uint8_t* __restrict__ arena, uint8_t* __restrict__ mask) {
-    __shared__ int sx0[kPyrTX], sx1[kPyrTX], swx[kPyrTX];
-    __shared__ int sy0[kPyrTY], sy1[kPyrTY], swy[kPyrTY];
+    __shared__ int scol[kPyrTX], srow[kPyrTY];
+    __shared__ __align__(16) uint8_t simg[kPyrLH * kPyrLW];
+    __shared__ __align__(16) uint8_t smsk[kPyrLH * kPyrLW];
     const int b = blockIdx.x;
-    const int vi = find_segment(prefix, n_views, b);
+    const int vi = find_segment_wave(prefix, n_views, b);
     const xa_level_desc d = levels[vi * n_levels + l];
     const xa_level_desc p = levels[vi * n_levels + l - 1];
     const int local = b - prefix[vi];
     const int tiles_x = (d.width + kPyrTX - 1) / kPyrTX;
-    const int x0 = (local % tiles_x) * kPyrTX, y0 = (local / tiles_x) * kPyrTY;
+    const int X0 = (local % tiles_x) * kPyrTX, Y0 = (local / tiles_x) * kPyrTY;
     const int t = threadIdx.x;
-    if (t < kPyrTX) {
-        if (x0 + t < d.width) resample_index(x0 + t, d.width, p.width, sx0[t], sx1[t], swx[t]);
-    } else if (t < kPyrTX + kPyrTY) {
-        const int r = t - kPyrTX;
-        if (y0 + r < d.height) resample_index(y0 + r, d.height, p.height, sy0[r], sy1[r], swy[r]);
-    }
+    scol[t] = X0 + t < d.width ? resample_index(X0 + t, d.width, p.width) : -1;
+    if (t < kPyrTY) srow[t] = Y0 + t < d.height ? resample_index(Y0 + t, d.height, p.height) : -1;
     __syncthreads();
-    const int tx = t % kPyrTX, ty = t / kPyrTX;
-    const int x = x0 + tx, y = y0 + ty;
-    if (x >= d.width || y >= d.height) return;
+    const int xl = min(X0 + kPyrTX, d.width) - 1 - X0, yl = min(Y0 + kPyrTY, d.height) - 1 - Y0;
+    const int c_lo = scol[0] >> 11, c_hi = min((scol[xl] >> 11) + 1, p.width - 1);
+    const int r_lo = srow[0] >> 11, r_hi = min((srow[yl] >> 11) + 1, p.height - 1);
+    const int cb = c_lo & ~15, nch = (((c_hi + 16) & ~15) - cb) >> 4, nr = r_hi - r_lo + 1;
     const uint8_t* P = arena + p.offset;
     const uint8_t* M = mask + p.offset;
-    const int r0 = sy0[ty] * p.width, r1 = sy1[ty] * p.width;
-    const int c0 = sx0[tx], c1 = sx1[tx];
-    const int wx1 = swx[tx], wx0 = 2048 - wx1, wy1 = swy[ty], wy0 = 2048 - wy1;
-    const int top = wx0 * int(P[r0 + c0]) + wx1 * int(P[r0 + c1]);
-    const int bot = wx0 * int(P[r1 + c0]) + wx1 * int(P[r1 + c1]);
-    const int out = (wy0 * top + wy1 * bot + (1 << 21)) >> 22;
-    const size_t o = size_t(d.offset) + size_t(y) * d.width + x;
-    arena[o] = uint8_t(out);
-    mask[o] = uint8_t(M[r0 + c0] & M[r0 + c1] & M[r1 + c0] & M[r1 + c1]);
+    const bool staged = nch * 16 <= kPyrLW && nr <= kPyrLH;
+    if (staged) {
+        for (int e = t; e < nr * nch; e += 256) {
+            const int r = e / nch, k = e - (e / nch) * nch;
+            const size_t g = size_t(r_lo + r) * p.pitch + cb + 16 * k;
+            *reinterpret_cast<uint4*>(simg + r * kPyrLW + 16 * k) = *reinterpret_cast<const uint4*>(P + g);
+            *reinterpret_cast<uint4*>(smsk + r * kPyrLW + 16 * k) = *reinterpret_cast<const uint4*>(M + g);
+        }
+    }
+    __syncthreads();
+    const int tx = t & 63, ty = t >> 6;
+    const int y = Y0 + ty;
+    if (y >= d.height) return;
+    const int xb = X0 + 4 * tx;
+    if (xb >= d.width) return;
+    const int rv = srow[ty];
+    const int y0 = rv >> 11, wy1 = rv & 2047, wy0 = 2048 - wy1, y1 = min(y0 + 1, p.height - 1);
+    uint32_t pix = 0, msk = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (xb + k >= d.width) break;
+        const int cv = scol[4 * tx + k];
+        const int x0 = cv >> 11, wx1 = cv & 2047, wx0 = 2048 - wx1, x1 = min(x0 + 1, p.width - 1);
+        int p00, p01, p10, p11, m;
+        if (staged) {
+            const uint8_t* r0 = simg + (y0 - r_lo) * kPyrLW - cb;
+            const uint8_t* r1 = simg + (y1 - r_lo) * kPyrLW - cb;
+            const uint8_t* q0 = smsk + (y0 - r_lo) * kPyrLW - cb;
+            const uint8_t* q1 = smsk + (y1 - r_lo) * kPyrLW - cb;
+            p00 = r0[x0]; p01 = r0[x1]; p10 = r1[x0]; p11 = r1[x1];
+            m = q0[x0] & q0[x1] & q1[x0] & q1[x1];
+        } else {
+            const uint8_t* r0 = P + size_t(y0) * p.pitch;
+            const uint8_t* r1 = P + size_t(y1) * p.pitch;
+            const uint8_t* q0 = M + size_t(y0) * p.pitch;
+            const uint8_t* q1 = M + size_t(y1) * p.pitch;
+            p00 = r0[x0]; p01 = r0[x1]; p10 = r1[x0]; p11 = r1[x1];
+            m = q0[x0] & q0[x1] & q1[x0] & q1[x1];
+        }
+        const int top = wx0 * p00 + wx1 * p01;
+        const int bot = wx0 * p10 + wx1 * p11;
+        const int out = (wy0 * top + wy1 * bot + (1 << 21)) >> 22;
+        pix |= uint32_t(out) << (8 * k);
+        msk |= uint32_t(m & 1) << (8 * k);
+    }
+    // xb is a multiple of 4 below the width, so the word lies inside the 16-byte padded row
+    const size_t o = size_t(d.offset) + size_t(y) * d.pitch + xb;
+    *reinterpret_cast<uint32_t*>(arena + o) = pix;
+    *reinterpret_cast<uint32_t*>(mask + o) = msk;
 }
 
-// ------------------------------------------------------------------ FAST-9 + NMS + compaction
+// ------------------------------------------------------------------ FAST-9 + NMS + Harris + smoothing
 
 // Bresenham circle of radius 3, clockwise from 12 o'clock (x right, y down).
 __constant__ int8_t c_circle_x[16] = {0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3, -3, -3, -2, -1};
@@ -114,174 +165,60 @@ __device__ __forceinline__ bool has_run9(uint32_t m) {
     return (r & 0xFFFFu) != 0;
 }
 
-// FAST-9 score of the pixel at (cx, cy) of an LDS tile: V = max over the 16 arcs of 9
-// contiguous circle pixels and both polarities of the arc minimum of the signed
-// difference; returns kNegV unless V > T (i.e. unless the pixel is a corner).
-__device__ __forceinline__ int fast_score_lds(const uint8_t* t, int stride, int cx, int cy, int T) {
-    const int c = t[cy * stride + cx];
+// FAST-9 score of an LDS pixel: V = max over the 16 arcs of 9 contiguous circle pixels and
+// both polarities of the arc minimum of the signed difference; kNegV unless V > T.  Both
+// polarities cannot have a 9-arc at once, so only the polarity that has one is scored.
+__device__ __forceinline__ int fast_score_lds(const uint8_t* p, int stride, int T) {
+    const int c = p[0];
     int d[16];
     uint32_t bm = 0, dm = 0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-        d[k] = int(t[(cy + c_circle_y[k]) * stride + cx + c_circle_x[k]]) - c;
+        d[k] = int(p[c_circle_y[k] * stride + c_circle_x[k]]) - c;
         bm |= uint32_t(d[k] > T) << k;
         dm |= uint32_t(d[k] < -T) << k;
     }
-    if (!has_run9(bm) && !has_run9(dm)) return kNegV;
+    const bool bright = has_run9(bm);
+    if (!bright && !has_run9(dm)) return kNegV;
+    if (!bright) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) d[k] = -d[k];
+    }
+    int m3[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) m3[k] = min(min(d[k], d[(k + 1) & 15]), d[(k + 2) & 15]);
     int best = INT_MIN;
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-        int mn = d[s], mx = d[s];
-#pragma unroll
-        for (int j = 1; j < 9; ++j) {
-            const int v = d[(s + j) & 15];
-            mn = min(mn, v);
-            mx = max(mx, v);
-        }
-        best = max(best, max(mn, -mx));
-    }
+    for (int k = 0; k < 16; ++k) best = max(best, min(min(m3[k], m3[(k + 3) & 15]), m3[(k + 6) & 15]));
     return best;
 }
 
-constexpr int kFastHalo = 4;                                  // circle radius 3 + 1 for the NMS ring
-constexpr int kFastLW = kFastTX + 2 * kFastHalo;              // 72
-constexpr int kFastLH = kFastTY + 2 * kFastHalo;              // 16
-constexpr int kScoreW = kFastTX + 2, kScoreH = kFastTY + 2;   // 66 x 10
-constexpr int kSmRows = kFastTY + 6;                          // rows of horizontal smoothing sums
+constexpr int kFH = 4;                              // halo rows above and below the tile
+constexpr int kFLW = kFastTX + 32;                  // LDS row: x0 - 16 .. x0 + 79 (6 chunks of 16)
+constexpr int kFLH = kFastTY + 2 * kFH;             // 40 rows
+constexpr int kFChunks = kFLW / 16;
+constexpr int kSW = kFastTX + 2, kSH = kFastTY + 2; // FAST scores: the tile plus a one-pixel ring
+constexpr int kMaxBlockCand = kFastTX * kFastTY / 4;
 
-// One block per 64 x 8 tile of one (view, level), levels that can hold detections only:
-//  1. the tile plus a 4-pixel halo is staged in LDS (border replicated);
-//  2. the 7-tap smoothing [18 34 49 54 49 34 18] / 256 of the tile is written out
-//     (exact horizontal sums, vertical pass (sum + 2^15) >> 16);
-//  3. FAST-9 scores on the tile plus a one-pixel ring: an exact pre-test on the four
-//     compass pixels (any 9-pixel arc contains two of them) queues the pixels that can be
-//     corners, and only those get the full score;
-//  4. 3x3 non-maximum suppression (ties to the earlier raster position), the content
-//     filter on the corners of the +-B box, and ballot compaction of the survivors.
-__global__ void __launch_bounds__(256) k_fast(const xa_level_desc* __restrict__ levels, const int32_t* __restrict__ prefix,
-                                              int nvl, int T, const uint8_t* __restrict__ arena,
-                                              const uint8_t* __restrict__ mask, uint32_t* __restrict__ cand,
-                                              int32_t* __restrict__ cand_count, uint8_t* __restrict__ smooth) {
-    __shared__ uint8_t img[kFastLH * kFastLW];
-    __shared__ int score[kScoreH * kScoreW];
-    __shared__ int hs[kSmRows * kFastTX];
-    __shared__ int16_t queue[kScoreH * kScoreW];
-    __shared__ int qn;
-    const int b = blockIdx.x;
-    const int vl = find_segment(prefix, nvl, b);
-    const xa_level_desc d = levels[vl];
-    if (d.cand_cap == 0) return;
-    const int W = d.width, H = d.height;
-    const int local = b - prefix[vl];
-    const int tiles_x = (W + kFastTX - 1) / kFastTX;
-    const int x0 = (local % tiles_x) * kFastTX, y0 = (local / tiles_x) * kFastTY;
-    const uint8_t* P = arena + d.offset;
-    for (int e = threadIdx.x; e < kFastLH * kFastLW; e += 256) {
-        const int ly = e / kFastLW, lx = e - (e / kFastLW) * kFastLW;
-        const int gx = clampi(x0 - kFastHalo + lx, 0, W - 1), gy = clampi(y0 - kFastHalo + ly, 0, H - 1);
-        img[e] = P[size_t(gy) * W + gx];
-    }
-    if (threadIdx.x == 0) qn = 0;
-    __syncthreads();
-    // smoothing: horizontal sums for rows y0-3 .. y0+10, then the vertical pass
-    const int w7[7] = {18, 34, 49, 54, 49, 34, 18};
-    for (int e = threadIdx.x; e < kSmRows * kFastTX; e += 256) {
-        const int r = e / kFastTX, c = e - (e / kFastTX) * kFastTX;
-        const uint8_t* row = img + (r + 1) * kFastLW + c + 1;
-        int sum = 0;
-#pragma unroll
-        for (int k = 0; k < 7; ++k) sum += w7[k] * int(row[k]);
-        hs[e] = sum;
-    }
-    // FAST pre-test over the tile and its ring; positions that cannot be compared stay non-corners
-    const bool detect = !(x0 + kFastTX <= kBorder || x0 >= W - kBorder || y0 + kFastTY <= kBorder || y0 >= H - kBorder);
-    if (detect) {
-        for (int e = threadIdx.x; e < kScoreH * kScoreW; e += 256) {
-            const int sy = e / kScoreW, sx = e - (e / kScoreW) * kScoreW;
-            const int gx = x0 - 1 + sx, gy = y0 - 1 + sy;
-            score[e] = kNegV;
-            if (gx >= kBorder - 1 && gx <= W - kBorder && gy >= kBorder - 1 && gy <= H - kBorder) {
-                const uint8_t* p = img + (sy + kFastHalo - 1) * kFastLW + sx + kFastHalo - 1;
-                const int c = p[0];
-                const int n = p[-3 * kFastLW], e3 = p[3], s3 = p[3 * kFastLW], w3 = p[-3];
-                const int nb = (n > c + T) + (e3 > c + T) + (s3 > c + T) + (w3 > c + T);
-                const int nd = (n < c - T) + (e3 < c - T) + (s3 < c - T) + (w3 < c - T);
-                if (nb >= 2 || nd >= 2) queue[atomicAdd(&qn, 1)] = int16_t(e);
-            }
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int rr = 0; rr < kFastTY / 4; ++rr) {
-        const int tx = threadIdx.x % kFastTX, ty = threadIdx.x / kFastTX + 4 * rr;
-        const int x = x0 + tx, y = y0 + ty;
-        if (x < W && y < H) {
-            int sum = 0;
-#pragma unroll
-            for (int k = 0; k < 7; ++k) sum += w7[k] * hs[(ty + k) * kFastTX + tx];
-            smooth[size_t(d.offset) + size_t(y) * W + x] = uint8_t((sum + (1 << 15)) >> 16);
-        }
-    }
-    if (!detect) return;
-    const int nq = qn;
-    for (int q = threadIdx.x; q < nq; q += 256) {
-        const int e = queue[q];
-        const int sy = e / kScoreW, sx = e - (e / kScoreW) * kScoreW;
-        score[e] = fast_score_lds(img, kFastLW, sx + kFastHalo - 1, sy + kFastHalo - 1, T);
-    }
-    __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const uint8_t* M = mask + d.offset;
-#pragma unroll
-    for (int rr = 0; rr < kFastTY / 4; ++rr) {
-        const int tx = threadIdx.x % kFastTX, ty = threadIdx.x / kFastTX + 4 * rr;
-        const int x = x0 + tx, y = y0 + ty;
-        bool keep = false;
-        if (x >= kBorder && x < W - kBorder && y >= kBorder && y < H - kBorder) {
-            const int vp = score[(ty + 1) * kScoreW + tx + 1];
-            if (vp > T) {
-                keep = true;
-#pragma unroll
-                for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-                    for (int dx = -1; dx <= 1; ++dx) {
-                        if (dx == 0 && dy == 0) continue;
-                        const int vq = score[(ty + 1 + dy) * kScoreW + tx + 1 + dx];
-                        const bool q_after = dy > 0 || (dy == 0 && dx > 0);
-                        keep = keep && (vp > vq || (vp == vq && q_after));
-                    }
-                if (keep) {
-                    const size_t r0 = size_t(y - kBorder) * W, r1 = size_t(y + kBorder) * W;
-                    keep = M[r0 + x - kBorder] && M[r0 + x + kBorder] && M[r1 + x - kBorder] && M[r1 + x + kBorder];
-                }
-            }
-        }
-        const unsigned long long bal = __ballot(keep);
-        if (bal) {
-            const int n = __popcll(bal);
-            int base = 0;
-            if (lane == 0) base = atomicAdd(&cand_count[vl], n);
-            base = __shfl(base, 0);
-            const int pos = __popcll(bal & ((1ull << lane) - 1ull));
-            if (keep && base + pos < d.cand_cap) cand[d.cand_offset + base + pos] = uint32_t(y) * uint32_t(W) + uint32_t(x);
-        }
-    }
-}
-
-// ------------------------------------------------------------------ Harris + top-N per level
-
-__device__ __forceinline__ long long harris_at(const uint8_t* __restrict__ P, int W, int x, int y) {
+// Harris response at LDS pixel p (stride s): 3x3 Sobel, 7x7 structure tensor,
+// R = 25 (a b - c^2) - (a + b)^2 in int64.
+__device__ __forceinline__ long long harris_lds(const uint8_t* p, int s) {
     int a = 0, b = 0, c = 0;
     for (int dy = -3; dy <= 3; ++dy) {
-        const uint8_t* r0 = P + size_t(y + dy - 1) * W + x;
-        const uint8_t* r1 = r0 + W;
-        const uint8_t* r2 = r1 + W;
+        const uint8_t* r0 = p + (dy - 1) * s;
+        const uint8_t* r1 = r0 + s;
+        const uint8_t* r2 = r1 + s;
+        int v0[9], v1[9], v2[9];
 #pragma unroll
-        for (int dx = -3; dx <= 3; ++dx) {
-            const int ix = (int(r0[dx + 1]) + 2 * int(r1[dx + 1]) + int(r2[dx + 1])) -
-                           (int(r0[dx - 1]) + 2 * int(r1[dx - 1]) + int(r2[dx - 1]));
-            const int iy = (int(r2[dx - 1]) + 2 * int(r2[dx]) + int(r2[dx + 1])) -
-                           (int(r0[dx - 1]) + 2 * int(r0[dx]) + int(r0[dx + 1]));
+        for (int k = 0; k < 9; ++k) {
+            v0[k] = r0[k - 4];
+            v1[k] = r1[k - 4];
+            v2[k] = r2[k - 4];
+        }
+#pragma unroll
+        for (int dx = 1; dx <= 7; ++dx) {
+            const int ix = (v0[dx + 1] + 2 * v1[dx + 1] + v2[dx + 1]) - (v0[dx - 1] + 2 * v1[dx - 1] + v2[dx - 1]);
+            const int iy = (v2[dx - 1] + 2 * v2[dx] + v2[dx + 1]) - (v0[dx - 1] + 2 * v0[dx] + v0[dx + 1]);
             a += ix * ix;
             b += iy * iy;
             c += ix * iy;
@@ -291,18 +228,196 @@ __device__ __forceinline__ long long harris_at(const uint8_t* __restrict__ P, in
     return 25LL * ((long long)a * b - (long long)c * c) - tr * tr;
 }
 
+// One block per 64 x 32 tile of one (view, level) that can hold detections:
+//  1. the tile plus a 4-row / 16-column halo is staged in LDS in 16-byte chunks (border
+//     replicated, byte by byte, for chunks that leave the image);
+//  2. the 7-tap smoothing [18 34 49 54 49 34 18] / 256 of the tile is written out (exact
+//     horizontal sums by v_dot4 over byte windows, rounded vertical pass);
+//  3. FAST-9 scores on the tile plus a one-pixel ring: an exact pre-test on the four compass
+//     pixels (any 9-pixel arc contains two of them) queues the pixels that can be corners;
+//  4. 3x3 non-maximum suppression (ties go to the earlier raster position), the content
+//     filter on the corners of the +-B box, the Harris response of each survivor from the
+//     LDS tile, and one atomic reservation per block in the candidate arena.
+__global__ void __launch_bounds__(256) k_fast(const xa_level_desc* __restrict__ levels, const int32_t* __restrict__ prefix,
+                                              int nvl, int T, const uint8_t* __restrict__ arena,
+                                              const uint8_t* __restrict__ mask, Cand* __restrict__ cand,
+                                              int32_t* __restrict__ cand_count, uint8_t* __restrict__ smooth) {
+    __shared__ __align__(16) uint8_t img[kFLH * kFLW];
+    __shared__ __align__(16) uint8_t sm[kFastTY * kFastTX];
+    __shared__ int16_t score[kSH * kSW];
+    __shared__ int16_t queue[kSH * kSW];
+    __shared__ int16_t cxy[2 * kMaxBlockCand];
+    __shared__ int qn, cn, cbase;
+    const int b = blockIdx.x;
+    const int vl = find_segment_wave(prefix, nvl, b);
+    const xa_level_desc d = levels[vl];
+    if (d.cand_cap == 0) return;
+    const int W = d.width, H = d.height, pitch = d.pitch;
+    const int local = b - prefix[vl];
+    const int tiles_x = (W + kFastTX - 1) / kFastTX;
+    const int x0 = (local % tiles_x) * kFastTX, y0 = (local / tiles_x) * kFastTY;
+    const uint8_t* P = arena + d.offset;
+    const int t = threadIdx.x;
+    for (int e = t; e < kFLH * kFChunks; e += 256) {
+        const int r = e / kFChunks, k = e - (e / kFChunks) * kFChunks;
+        const int gy = clampi(y0 - kFH + r, 0, H - 1);
+        const int gx = x0 - 16 + 16 * k;
+        uint4 v;
+        if (gx >= 0 && gx + 16 <= W) {
+            v = *reinterpret_cast<const uint4*>(P + size_t(gy) * pitch + gx);
+        } else {
+            uint32_t w[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint32_t acc = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc |= uint32_t(P[size_t(gy) * pitch + clampi(gx + 4 * q + j, 0, W - 1)]) << (8 * j);
+                w[q] = acc;
+            }
+            v = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+        *reinterpret_cast<uint4*>(img + r * kFLW + 16 * k) = v;
+    }
+    if (t == 0) { qn = 0; cn = 0; }
+    __syncthreads();
+
+    // ---- smoothing: thread = column c, rows 8g .. 8g + 7 of the tile
+    {
+        const int c = t & 63, g = t >> 6;
+        const int lx = c + 16 - 3;                 // first byte of the 7-tap window
+        const int a = lx & ~3, o = lx & 3;
+        const uint32_t w03 = 18u | (34u << 8) | (49u << 16) | (54u << 24);
+        const uint32_t w46 = 49u | (34u << 8) | (18u << 16);
+        int h[14];
+#pragma unroll
+        for (int j = 0; j < 14; ++j) {
+            const uint32_t* row = reinterpret_cast<const uint32_t*>(img + (kFH + 8 * g - 3 + j) * kFLW + a);
+            const uint32_t d0 = row[0], d1 = row[1], d2 = row[2];
+            const uint32_t lo = __builtin_amdgcn_alignbyte(d1, d0, o);
+            const uint32_t hi = __builtin_amdgcn_alignbyte(d2, d1, o) & 0x00FFFFFFu;
+            h[j] = int(__builtin_amdgcn_udot4(lo, w03, __builtin_amdgcn_udot4(hi, w46, 0u, false), false));
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int s = 18 * h[j] + 34 * h[j + 1] + 49 * h[j + 2] + 54 * h[j + 3] + 49 * h[j + 4] + 34 * h[j + 5] +
+                          18 * h[j + 6];
+            sm[(8 * g + j) * kFastTX + c] = uint8_t((s + (1 << 15)) >> 16);
+        }
+    }
+    // ---- FAST pre-test over the tile and its ring
+    const bool detect = !(x0 + kFastTX <= kBorder - 1 || x0 - 1 >= W - kBorder || y0 + kFastTY <= kBorder - 1 ||
+                          y0 - 1 >= H - kBorder);
+    if (detect) {
+        for (int e = t; e < kSH * kSW; e += 256) {
+            const int sy = e / kSW, sx = e - (e / kSW) * kSW;
+            const int gx = x0 - 1 + sx, gy = y0 - 1 + sy;
+            if (gx >= kBorder - 1 && gx <= W - kBorder && gy >= kBorder - 1 && gy <= H - kBorder) {
+                const uint8_t* p = img + (sy - 1 + kFH) * kFLW + sx - 1 + 16;
+                const int cc = p[0];
+                const int n = p[-3 * kFLW], e3 = p[3], s3 = p[3 * kFLW], w3 = p[-3];
+                const int nb = (n > cc + T) + (e3 > cc + T) + (s3 > cc + T) + (w3 > cc + T);
+                const int nd = (n < cc - T) + (e3 < cc - T) + (s3 < cc - T) + (w3 < cc - T);
+                if (nb >= 2 || nd >= 2) queue[atomicAdd(&qn, 1)] = int16_t(e);
+            }
+            score[e] = kNegV;
+        }
+    }
+    __syncthreads();
+    // ---- smoothed tile out, 16 bytes per store (rows are padded to 16 bytes)
+    for (int e = t; e < kFastTY * (kFastTX / 16); e += 256) {
+        const int r = e >> 2, k = e & 3;
+        const int y = y0 + r, x = x0 + 16 * k;
+        if (y < H && x < W)
+            *reinterpret_cast<uint4*>(smooth + d.offset + size_t(y) * pitch + x) =
+                *reinterpret_cast<const uint4*>(sm + r * kFastTX + 16 * k);
+    }
+    if (!detect) return;
+    // ---- full scores of the queued pixels
+    const int nq = qn;
+    for (int q = t; q < nq; q += 256) {
+        const int e = queue[q];
+        const int sy = e / kSW, sx = e - (e / kSW) * kSW;
+        score[e] = int16_t(fast_score_lds(img + (sy - 1 + kFH) * kFLW + sx - 1 + 16, kFLW, T));
+    }
+    __syncthreads();
+    // ---- NMS + content filter -> block candidate list
+    const uint8_t* Mk = mask + d.offset;
+    for (int e = t; e < kFastTX * kFastTY; e += 256) {
+        const int ty = e >> 6, tx = e & 63;
+        const int x = x0 + tx, y = y0 + ty;
+        if (x < kBorder || x >= W - kBorder || y < kBorder || y >= H - kBorder) continue;
+        const int vp = score[(ty + 1) * kSW + tx + 1];
+        if (vp <= T) continue;
+        bool keep = true;
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (dx == 0 && dy == 0) continue;
+                const int vq = score[(ty + 1 + dy) * kSW + tx + 1 + dx];
+                const bool q_after = dy > 0 || (dy == 0 && dx > 0);
+                keep = keep && (vp > vq || (vp == vq && q_after));
+            }
+        if (!keep) continue;
+        const size_t r0 = size_t(y - kBorder) * pitch, r1 = size_t(y + kBorder) * pitch;
+        if (!(Mk[r0 + x - kBorder] && Mk[r0 + x + kBorder] && Mk[r1 + x - kBorder] && Mk[r1 + x + kBorder])) continue;
+        const int s = atomicAdd(&cn, 1);
+        cxy[2 * s] = int16_t(tx);
+        cxy[2 * s + 1] = int16_t(ty);
+    }
+    __syncthreads();
+    const int nc = cn;
+    if (nc == 0) return;
+    if (t == 0) cbase = atomicAdd(&cand_count[vl], nc);
+    __syncthreads();
+    const int base = cbase;
+    for (int s = t; s < nc; s += 256) {
+        const int tx = cxy[2 * s], ty = cxy[2 * s + 1];
+        const long long R = harris_lds(img + (ty + kFH) * kFLW + tx + 16, kFLW);
+        if (base + s < d.cand_cap) {
+            Cand cd;
+            cd.raster = uint32_t(y0 + ty) * uint32_t(W) + uint32_t(x0 + tx);
+            cd.pad = 0;
+            cd.harris = R;
+            cand[d.cand_offset + base + s] = cd;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ top-N per level
+
 // order-preserving map int64 -> uint64
 __device__ __forceinline__ unsigned long long okey(long long r) { return (unsigned long long)r ^ 0x8000000000000000ull; }
 
-// k-th largest (descending = true) or k-th smallest value among the items i < C whose
-// `pred` holds, by 8-bit digit histograms from the top digit down; returns the value and
-// leaves in *k_rem how many items equal to it are needed to make k.
+// Digit (0..255) holding the k-th item, counting from the top bin when descending and from
+// the bottom bin otherwise, of a 256-bin histogram; every thread of a 256-thread block takes
+// part.  *s_k receives the rank of the item inside that bin.
+__device__ int pick_digit(const int* hist, int* scan, bool descending, int k, int* s_digit, int* s_k) {
+    const int t = threadIdx.x;
+    const int g = descending ? 255 - t : t;
+    scan[t] = hist[g];
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int v = t >= off ? scan[t - off] : 0;
+        __syncthreads();
+        scan[t] += v;
+        __syncthreads();
+    }
+    const int before = t > 0 ? scan[t - 1] : 0;
+    if (before < k && k <= scan[t]) { *s_digit = g; *s_k = k - before; }
+    __syncthreads();
+    return *s_digit;
+}
+
+// k-th value in the order given by `descending` among items i < C with pred(i), by 8-bit
+// digits from bit top_bit down; *k_rem receives how many items equal to it complete k.
 template <typename Get, typename Pred>
-__device__ unsigned long long radix_select(int C, int k, int top_bit, bool descending, Get get, Pred pred,
-                                           int* hist, int* k_rem, int* s_digit, int* s_k) {
+__device__ unsigned long long radix_select(int C, int k, int top_bit, bool descending, Get get, Pred pred, int* hist,
+                                           int* scan, int* k_rem, int* s_digit, int* s_k) {
     unsigned long long prefix = 0, pmask = 0;
     for (int shift = top_bit - 7; shift >= 0; shift -= 8) {
-        for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
+        hist[threadIdx.x] = 0;
         __syncthreads();
         for (int i = threadIdx.x; i < C; i += blockDim.x) {
             if (!pred(i)) continue;
@@ -311,18 +426,8 @@ __device__ unsigned long long radix_select(int C, int k, int top_bit, bool desce
             atomicAdd(&hist[(u >> shift) & 0xFF], 1);
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            int acc = 0, g = 0;
-            for (int s = 0; s < 256; ++s) {
-                g = descending ? 255 - s : s;
-                if (acc + hist[g] >= k) break;
-                acc += hist[g];
-            }
-            *s_digit = g;
-            *s_k = k - acc;
-        }
-        __syncthreads();
-        prefix |= (unsigned long long)(*s_digit) << shift;
+        const int dgt = pick_digit(hist, scan, descending, k, s_digit, s_k);
+        prefix |= (unsigned long long)dgt << shift;
         pmask |= 0xFFull << shift;
         k = *s_k;
         __syncthreads();
@@ -331,65 +436,62 @@ __device__ unsigned long long radix_select(int C, int k, int top_bit, bool desce
     return prefix;
 }
 
-// One block per (view, level): Harris at every candidate, then the top `quota` by
-// (response descending, raster ascending), sorted in that order, into the staging slots.
+// One block per (view, level): the top `quota` candidates by (Harris response descending,
+// raster ascending), sorted in that order, into the staging slots.  Up to kSelMax
+// candidates are sorted directly in LDS; more are first cut down to the quota by radix
+// selection of the response (and, among equal responses, of the raster position).
 __global__ void __launch_bounds__(kSelThreads) k_select(const xa_level_desc* __restrict__ levels, int n_features,
-                                                        const uint8_t* __restrict__ arena, const uint32_t* __restrict__ cand,
+                                                        const Cand* __restrict__ cand,
                                                         const int32_t* __restrict__ cand_count,
-                                                        long long* __restrict__ harris, int4* __restrict__ stage,
-                                                        int32_t* __restrict__ stage_count) {
+                                                        int4* __restrict__ stage, int32_t* __restrict__ stage_count) {
     __shared__ unsigned long long s_key[kSelMax];
     __shared__ uint32_t s_ras[kSelMax];
-    __shared__ int hist[256];
+    __shared__ int hist[256], scan[256];
     __shared__ int s_digit, s_k, s_n;
     const int vl = blockIdx.x;
     const xa_level_desc d = levels[vl];
     const int C = int(min((long long)cand_count[vl], (long long)d.cand_cap));
     const int quota = d.quota;
-    const uint8_t* P = arena + d.offset;
-    const uint32_t* cd = cand + d.cand_offset;
-    long long* hr = harris + d.cand_offset;
-    for (int i = threadIdx.x; i < C; i += blockDim.x) {
-        const uint32_t r = cd[i];
-        hr[i] = harris_at(P, d.width, int(r % uint32_t(d.width)), int(r / uint32_t(d.width)));
-    }
-    __syncthreads();
+    const Cand* cd = cand + d.cand_offset;
     const int n = min(C, quota);
     if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
-    if (C <= quota) {
+    if (C <= kSelMax) {
         for (int i = threadIdx.x; i < C; i += blockDim.x) {
-            const int slot = atomicAdd(&s_n, 1);
-            s_key[slot] = okey(hr[i]);
-            s_ras[slot] = cd[i];
+            const Cand c = cd[i];
+            s_key[i] = okey(c.harris);
+            s_ras[i] = c.raster;
         }
+        if (threadIdx.x == 0) s_n = C;
     } else if (n > 0) {
         int k_eq;
         const unsigned long long K = radix_select(
-            C, n, 63, true, [&](int i) { return okey(hr[i]); }, [](int) { return true; }, hist, &k_eq, &s_digit, &s_k);
-        // among the candidates with response exactly K, the k_eq smallest raster positions
+            C, n, 63, true, [&](int i) { return okey(cd[i].harris); }, [](int) { return true; }, hist, scan, &k_eq,
+            &s_digit, &s_k);
         int k_r;
         const unsigned long long Rthr = radix_select(
-            C, k_eq, 31, false, [&](int i) { return (unsigned long long)cd[i]; },
-            [&](int i) { return okey(hr[i]) == K; }, hist, &k_r, &s_digit, &s_k);
+            C, k_eq, 31, false, [&](int i) { return (unsigned long long)cd[i].raster; },
+            [&](int i) { return okey(cd[i].harris) == K; }, hist, scan, &k_r, &s_digit, &s_k);
         for (int i = threadIdx.x; i < C; i += blockDim.x) {
-            const unsigned long long u = okey(hr[i]);
-            if (u > K || (u == K && cd[i] <= Rthr)) {
+            const Cand c = cd[i];
+            const unsigned long long u = okey(c.harris);
+            if (u > K || (u == K && c.raster <= Rthr)) {
                 const int slot = atomicAdd(&s_n, 1);
                 s_key[slot] = u;
-                s_ras[slot] = cd[i];
+                s_ras[slot] = c.raster;
             }
         }
     }
     __syncthreads();
-    // bitonic sort of n entries padded to a power of two: key descending, raster ascending
+    const int m = s_n;              // entries to sort (all candidates, or exactly the quota)
     int M = 1;
-    while (M < n) M <<= 1;
-    for (int i = n + threadIdx.x; i < M; i += blockDim.x) {
+    while (M < m) M <<= 1;
+    for (int i = m + threadIdx.x; i < M; i += blockDim.x) {
         s_key[i] = 0ull;
         s_ras[i] = 0xFFFFFFFFu;
     }
     __syncthreads();
+    // bitonic sort: key descending, raster ascending
     for (int k = 2; k <= M; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
             for (int i = threadIdx.x; i < M; i += blockDim.x) {
@@ -451,7 +553,7 @@ __global__ void __launch_bounds__(256) k_orient_brief(const xa_view_desc* __rest
     const int4 s = stage[size_t(v) * n_features + d.kp_base + rank];
     const int x = s.x, y = s.y;
     const long long R = (long long)(((unsigned long long)(uint32_t)s.w << 32) | (uint32_t)s.z);
-    const int W = d.width;
+    const int pitch = d.pitch;
     const uint8_t* P = arena + d.offset;
     int m10 = 0, m01 = 0;
     {
@@ -459,7 +561,7 @@ __global__ void __launch_bounds__(256) k_orient_brief(const xa_view_desc* __rest
         for (int it = 0; it < 16; ++it) {
             const int dy = -15 + 2 * it + (lane >> 5);
             if (dy <= 15 && dx * dx + dy * dy <= 225) {
-                const int I = P[size_t(y + dy) * W + x + dx];
+                const int I = P[size_t(y + dy) * pitch + x + dx];
                 m10 += dx * I;
                 m01 += dy * I;
             }
@@ -490,7 +592,7 @@ __global__ void __launch_bounds__(256) k_orient_brief(const xa_view_desc* __rest
         const int x2 = clampi(pattern[4 * i + 2], -15, 15), y2 = clampi(pattern[4 * i + 3], -15, 15);
         const int ax = rnd20(x1 * Cb - y1 * Sb), ay = rnd20(x1 * Sb + y1 * Cb);
         const int bx = rnd20(x2 * Cb - y2 * Sb), by = rnd20(x2 * Sb + y2 * Cb);
-        const bool bit = Sm[size_t(y + ay) * W + x + ax] < Sm[size_t(y + by) * W + x + bx];
+        const bool bit = Sm[size_t(y + ay) * pitch + x + ax] < Sm[size_t(y + by) * pitch + x + bx];
         words[g] = __ballot(bit);
     }
     const size_t slot = size_t(v) * n_features + k;
@@ -498,7 +600,7 @@ __global__ void __launch_bounds__(256) k_orient_brief(const xa_view_desc* __rest
     if (lane == 0) {
         const xa_view_desc& vd = views[v];
         const xa_level_desc& l0 = levels[v * n_levels];
-        const double x0 = __dadd_rn(__dmul_rn(__dadd_rn(double(x), 0.5), double(l0.width) / double(W)), -0.5);
+        const double x0 = __dadd_rn(__dmul_rn(__dadd_rn(double(x), 0.5), double(l0.width) / double(d.width)), -0.5);
         const double y0 = __dadd_rn(__dmul_rn(__dadd_rn(double(y), 0.5), double(l0.height) / double(d.height)), -0.5);
         xa_keypoint o;
         o.x = x; o.y = y; o.level = lev; o.bin = bin; o.harris = R;
@@ -517,9 +619,8 @@ xa_status launch_extract(const PlanView& ph, const PlanView& pd, uint8_t* arena,
     const int nv = h->n_views, L = h->n_levels, nvl = nv * L, N = h->n_features;
     const ExtractWs w = extract_ws_layout(h);
     uint8_t* smooth = ws + w.smooth;
-    uint32_t* cand = reinterpret_cast<uint32_t*>(ws + w.cand);
+    Cand* cand = reinterpret_cast<Cand*>(ws + w.cand);
     int32_t* cand_count = reinterpret_cast<int32_t*>(ws + w.cand_count);
-    long long* harris = reinterpret_cast<long long*>(ws + w.harris);
     int4* stage = reinterpret_cast<int4*>(ws + w.stage);
     int32_t* stage_count = reinterpret_cast<int32_t*>(ws + w.stage_count);
     hipLaunchKernelGGL(k_fill_i32, dim3((nvl + 255) / 256), dim3(256), 0, st, cand_count, nvl, 0);
@@ -531,12 +632,11 @@ xa_status launch_extract(const PlanView& ph, const PlanView& pd, uint8_t* arena,
                                pd.level_prefix + size_t(l) * (nv + 1), nv, arena, mask);
     }
     const int vt = ph.vl_prefix[nvl];
-    if (vt > 0) {
+    if (vt > 0)
         hipLaunchKernelGGL(k_fast, dim3(vt), dim3(256), 0, st, pd.levels, pd.vl_prefix, nvl, h->fast_threshold,
                            arena, mask, cand, cand_count, smooth);
-    }
-    hipLaunchKernelGGL(k_select, dim3(nvl), dim3(kSelThreads), 0, st, pd.levels, N, arena, cand, cand_count, harris,
-                       stage, stage_count);
+    hipLaunchKernelGGL(k_select, dim3(nvl), dim3(kSelThreads), 0, st, pd.levels, N, cand, cand_count, stage,
+                       stage_count);
     hipLaunchKernelGGL(k_orient_brief, dim3((N + 3) / 4, nv), dim3(256), 0, st, pd.views, pd.levels, L, N, arena,
                        smooth, stage, stage_count, pattern, kp, desc, count);
     hipError_t e = hipGetLastError();
@@ -562,6 +662,8 @@ extern "C" xa_status xa_extract_orb(const void* plan_host, const void* plan_dev,
     if (s != XA_OK) return s;
     if (!plan_dev || !d_arena || !d_mask || !d_pattern || !d_kp || !d_desc || !d_count)
         return fail(XA_EINVAL, "NULL device pointer");
+    if ((reinterpret_cast<uintptr_t>(d_arena) | reinterpret_cast<uintptr_t>(d_mask)) % 128)
+        return fail(XA_EINVAL, "arena and mask must be 128-byte aligned");
     const size_t need = extract_ws_layout(ph.h).total;
     if (ws_bytes < need) return fail(XA_ECAPACITY, "extract workspace needs %zu bytes, got %zu", need, ws_bytes);
     if (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) % kAlign))

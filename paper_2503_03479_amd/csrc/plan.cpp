@@ -64,9 +64,9 @@ ExtractWs extract_ws_layout(const xa_plan_header* h) {
     const size_t nvl = size_t(h->n_views) * h->n_levels;
     size_t o = 0;
     w.smooth = o;      o = align_up(o + size_t(h->arena_bytes));
-    w.cand = o;        o = align_up(o + size_t(h->cand_total) * 4);
+    w.cand = o;        o = align_up(o + size_t(h->cand_total) * sizeof(Cand));
     w.cand_count = o;  o = align_up(o + nvl * 4);
-    w.harris = o;      o = align_up(o + size_t(h->cand_total) * 8);
+    w.harris = o;
     w.stage = o;       o = align_up(o + size_t(h->n_views) * h->n_features * 16);
     w.stage_count = o; o = align_up(o + nvl * 4);
     w.total = o;
@@ -259,9 +259,10 @@ extern "C" xa_status xa_plan_image(int32_t src_w, int32_t src_h, const xa_affine
             const double f = std::pow(level_scale, double(l));
             d.width = l == 0 ? v.width : std::max(1, int32_t(std::floor(v.width / f + 0.5)));
             d.height = l == 0 ? v.height : std::max(1, int32_t(std::floor(v.height / f + 0.5)));
+            d.pitch = level_pitch(d.width);
             d.offset = arena;
-            if (l == 0) v.offset = arena;
-            arena = int64_t(align_up(size_t(arena + int64_t(d.width) * d.height), 128));
+            if (l == 0) { v.offset = arena; v.pitch = d.pitch; }
+            arena = int64_t(align_up(size_t(arena + int64_t(d.pitch) * d.height), 128));
             d.quota = quota[l];
             d.kp_base = kp_base;
             kp_base += quota[l];

@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(kWarpThreads) k_warp(const uint8_t* __restrict
     }
     __syncthreads();
     if (qx >= v.width || qy >= v.height) return;
-    const size_t o = size_t(v.offset) + size_t(qy) * v.width + qx;
+    const size_t o = size_t(v.offset) + size_t(qy) * v.pitch + qx;
     const double px = affine_x(v.inv, double(qx), double(qy));
     const double py = affine_x(v.inv + 3, double(qx), double(qy));
     const bool inside = px >= -0.5 && px <= W - 0.5 && py >= -0.5 && py <= H - 0.5;
@@ -287,6 +287,8 @@ extern "C" xa_status xa_simulate_views(const void* plan_host, const void* plan_d
     xa_status s = plan_host_view(plan_host, &ph);
     if (s != XA_OK) return s;
     if (!plan_dev || !d_src || !d_arena || !d_mask) return fail(XA_EINVAL, "NULL device pointer");
+    if ((reinterpret_cast<uintptr_t>(d_arena) | reinterpret_cast<uintptr_t>(d_mask)) % 128)
+        return fail(XA_EINVAL, "arena and mask must be 128-byte aligned");
     if (src_pitch < ph.h->src_w) return fail(XA_EINVAL, "pitch %d < width %d", src_pitch, ph.h->src_w);
     const size_t need = simulate_ws_bytes(ph.h);
     if (ws_bytes < need) return fail(XA_ECAPACITY, "simulate workspace needs %zu bytes, got %zu", need, ws_bytes);

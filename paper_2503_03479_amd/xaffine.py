@@ -25,9 +25,11 @@ PARAMS_DTYPE = np.dtype([("t", "f8"), ("phi", "f8"), ("psi", "f8"), ("s", "f8"),
 VIEW_DTYPE = np.dtype([("p", PARAMS_DTYPE), ("src_w", "i4"), ("src_h", "i4"), ("width", "i4"), ("height", "i4"),
                        ("fwd", "f8", 6), ("inv", "f8", 6), ("sigma", "f8"), ("ux", "f8"), ("uy", "f8"),
                        ("offset", "i8"), ("blur_offset", "i8"), ("blur_major", "i4"), ("blur_tap0", "i4"),
-                       ("blur_ntaps", "i4"), ("warp_tile_w", "i4")])
-LEVEL_DTYPE = np.dtype([("width", "i4"), ("height", "i4"), ("offset", "i8"), ("quota", "i4"), ("kp_base", "i4"),
-                        ("view", "i4"), ("level", "i4"), ("cand_offset", "i8"), ("cand_cap", "i8")])
+                       ("blur_ntaps", "i4"), ("warp_tile_w", "i4"),
+                       ("pitch", "i4"), ("pad", "i4")])
+LEVEL_DTYPE = np.dtype([("width", "i4"), ("height", "i4"), ("pitch", "i4"), ("quota", "i4"), ("offset", "i8"),
+                        ("kp_base", "i4"), ("view", "i4"), ("level", "i4"), ("pad", "i4"), ("cand_offset", "i8"),
+                        ("cand_cap", "i8")])
 HEADER_DTYPE = np.dtype([("magic", "u4"), ("version", "u4"), ("src_w", "i4"), ("src_h", "i4"), ("n_views", "i4"),
                          ("n_levels", "i4"), ("n_features", "i4"), ("fast_threshold", "i4"), ("level_scale", "f8"),
                          ("total_bytes", "i8"), ("arena_bytes", "i8"), ("cand_total", "i8"), ("blur_floats", "i8"),
@@ -38,7 +40,7 @@ TAP_DTYPE = np.dtype([("w", "f4"), ("dmaj", "i4"), ("dmin", "i4"), ("frac", "f4"
 KEYPOINT_DTYPE = np.dtype([("x", "i4"), ("y", "i4"), ("level", "i4"), ("bin", "i4"), ("harris", "i8"),
                            ("xs", "f8"), ("ys", "f8")])
 MATCH_DTYPE = np.dtype([("t", "i4"), ("d1", "u2"), ("d2", "u2")])
-assert VIEW_DTYPE.itemsize == 216 and LEVEL_DTYPE.itemsize == 48 and KEYPOINT_DTYPE.itemsize == 40
+assert VIEW_DTYPE.itemsize == 224 and LEVEL_DTYPE.itemsize == 56 and KEYPOINT_DTYPE.itemsize == 40
 assert MATCH_DTYPE.itemsize == 8 and HEADER_DTYPE.itemsize == 136
 
 
@@ -174,9 +176,10 @@ class Plan:
         return np.frombuffer(self.blob, TAP_DTYPE, int(h["n_taps_total"]), int(h["off_taps"]))
 
     def level_image(self, arena: np.ndarray, view: int, level: int) -> np.ndarray:
+        """(H, W) view of one level inside a host copy of an arena (u8 or the fp32 values)."""
         L = self.levels[view, level]
-        o = int(L["offset"])
-        return arena[o:o + int(L["width"]) * int(L["height"])].reshape(int(L["height"]), int(L["width"]))
+        o, w, h, p = int(L["offset"]), int(L["width"]), int(L["height"]), int(L["pitch"])
+        return arena[o:o + p * h].reshape(h, p)[:, :w]
 
 
 def plan_image(src_w: int, src_h: int, params: np.ndarray, n_levels: int = 8, level_scale: float = 1.2,

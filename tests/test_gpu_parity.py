@@ -119,10 +119,8 @@ def _gpu_extract_from_views(plan, views_u8, masks, pattern, dev):
     arena = np.zeros(plan.arena_bytes, np.uint8)
     mask = np.zeros(plan.arena_bytes, np.uint8)
     for i, (U, M) in enumerate(zip(views_u8, masks)):
-        L0 = plan.levels[i, 0]
-        o, n = int(L0["offset"]), U.size
-        arena[o:o + n] = U.reshape(-1)
-        mask[o:o + n] = M.reshape(-1).astype(np.uint8)
+        plan.level_image(arena, i, 0)[:] = U
+        plan.level_image(mask, i, 0)[:] = M.astype(np.uint8)
     ta = torch.from_numpy(arena).to(dev)
     tm = torch.from_numpy(mask).to(dev)
     pat = torch.from_numpy(pattern).to(dev)

@@ -76,7 +76,8 @@ def test_plan_matches_oracle(L, w, h, n_tilt):
     # arena layout: levels do not overlap and fit the arena
     ends = []
     for lv in p.levels.reshape(-1):
-        ends.append((int(lv["offset"]), int(lv["offset"]) + int(lv["width"]) * int(lv["height"])))
+        assert lv["pitch"] >= lv["width"] and lv["pitch"] % 16 == 0 and lv["offset"] % 128 == 0
+        ends.append((int(lv["offset"]), int(lv["offset"]) + int(lv["pitch"]) * int(lv["height"])))
     ends.sort()
     assert all(a[1] <= b[0] for a, b in zip(ends, ends[1:]))
     assert ends[-1][1] <= p.arena_bytes
