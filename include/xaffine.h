@@ -120,7 +120,8 @@ typedef struct {
     int32_t n_taps_total;
     int64_t off_views;          /* xa_view_desc[n_views] */
     int64_t off_levels;         /* xa_level_desc[n_views * n_levels], view-major */
-    int64_t off_taps;           /* blur taps: n_taps_total x {float w; int32 dmaj; int32 dmin; float frac} */
+    int64_t off_taps;           /* blur taps: n_taps_total x {float wa, wb; int32 dmaj, dmin}: the tap k
+                                   adds wa I(p + k v_whole) + wb I(next row / column) */
     int64_t off_blur_views;     /* int32[n_blur]: view index of each blurred view */
     int64_t off_warp_prefix;    /* int32[n_views + 1]: first warp tile of each view */
     int64_t off_level_prefix;   /* int32[n_levels][n_views + 1]: first tile of each view at each level */

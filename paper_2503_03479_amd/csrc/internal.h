@@ -15,7 +15,8 @@ constexpr int kWarpLds = 8192;              // floats of source footprint a warp
 constexpr int kPyrTX = 256, kPyrTY = 4;     // pyramid down-sampling (4 output pixels per thread)
 constexpr int kFastTX = 64, kFastTY = 32;   // FAST / NMS / smoothing / Harris tiles (256 threads, 8 rows each)
 constexpr int kBlurTX = 64, kBlurTY = 16;   // directional blur over the source (4 rows per thread)
-constexpr int kBlurLds = 16384;             // bytes of source a blur tile can stage in LDS
+constexpr int kBlurStride = 128;            // LDS row stride (floats) of a major-x blur tile
+constexpr int kBlurLdsMax = 16384;          // floats of source a blur tile may stage in LDS (64 KiB)
 
 // Warp tile width for a view: the output tile is w x (256 / w), narrow along the compressed
 // axis so that its source footprint stays compact (about 16 t x 16 for a 16 x 16 tile).
@@ -27,10 +28,10 @@ constexpr int kBorder = 22;                 // detection border (rotated BRIEF t
 constexpr size_t kAlign = 256;
 
 struct BlurTap {
-    float w;        // normalised Gaussian weight
+    float wa;       // w (1 - f): weight of the sample at the whole-pixel minor offset
+    float wb;       // w f: weight of the next row / column (f = k m - floor(k m))
     int32_t dmaj;   // step along the major axis (k)
     int32_t dmin;   // floor(k m): whole-pixel step along the minor axis
-    float frac;     // k m - floor(k m): linear-interpolation weight of the next row / column
 };
 static_assert(sizeof(BlurTap) == 16, "tap layout");
 static_assert(sizeof(xa_view_desc) == 224, "view desc layout");

@@ -10,7 +10,7 @@
 namespace xa {
 namespace {
 
-constexpr int kMatchThreads = 128;   // two waves per block; a block owns 128 * Q queries of one view pair
+constexpr int kMatchThreads = 256;   // four waves per block; a block owns 256 * Q queries of one view pair
 constexpr int kMatchChunk = 512;     // train descriptors per LDS chunk (16 KiB)
 constexpr int kIdxBits = 13;         // train index field of the packed (distance, index) key
 
@@ -37,7 +37,7 @@ __global__ void k_fill_i32(int32_t* p, int n, int32_t v) {
 // per query, the two smallest packed keys (d << 13 | train index): the smallest key gives
 // d1 and the smallest index attaining it, the second smallest gives d2 over the others.
 template <int Q>
-__global__ void __launch_bounds__(kMatchThreads) k_match(const uint32_t* __restrict__ desc_a,
+__global__ void __launch_bounds__(kMatchThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) k_match(const uint32_t* __restrict__ desc_a,
                                                          const int32_t* __restrict__ count_a,
                                                          const uint32_t* __restrict__ desc_b,
                                                          const int32_t* __restrict__ count_b, int n_b, int N,

@@ -174,9 +174,12 @@ Planned plan_one(int32_t W, int32_t H, const xa_affine_params& p) {
         for (int k = -K; k <= K; ++k) {
             const double km = double(k) * m;
             const double fl = std::floor(km);
-            out.taps.push_back(BlurTap{float(g[k + K] / sum), k, int32_t(fl), float(km - fl)});
+            const double w = g[k + K] / sum, f = km - fl;
+            out.taps.push_back(BlurTap{float(w * (1.0 - f)), float(w * f), k, int32_t(fl)});
         }
         v.blur_ntaps = 2 * K + 1;
+        // zero taps up to a multiple of 4 (the kernel reads taps in groups of 4)
+        while (out.taps.size() % 4) out.taps.push_back(BlurTap{0.0f, 0.0f, 0, 0});
     }
     return out;
 }

@@ -2,6 +2,7 @@
 // Lanczos-4 affine resampling (eqs. (3)-(4), 8x8 window per Sec. IV.C).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "internal.h"
@@ -21,54 +22,93 @@ __device__ __forceinline__ int find_segment(const int32_t* __restrict__ prefix, 
     return lo;
 }
 
+// Source region a blur tile reads: the 64 x 16 tile grown by the tap offsets.  Taps step
+// one pixel along the major axis (k = -K..K) and floor(k m) (+1 for the interpolation
+// partner) along the minor axis, and floor(k m) is monotonic in k.
+struct BlurRegion {
+    int rx0, ry0, rw, rh, stride, floats;
+};
+__host__ __device__ inline BlurRegion blur_region(const xa_view_desc& v, const BlurTap* tp, int x0, int y0) {
+    const int n = v.blur_ntaps, K = (n - 1) / 2;
+    const int dlo = min(tp[0].dmin, tp[n - 1].dmin), dhi = max(tp[0].dmin, tp[n - 1].dmin) + 1;
+    BlurRegion r;
+    if (v.blur_major == 0) {
+        r.rx0 = x0 - K; r.rw = kBlurTX + 2 * K;
+        r.ry0 = y0 + dlo; r.rh = kBlurTY + dhi - dlo;
+        r.stride = kBlurStride;           // the interpolation partner is one row down: a fixed offset
+    } else {
+        r.rx0 = x0 + dlo; r.rw = kBlurTX + dhi - dlo;
+        r.ry0 = y0 - K; r.rh = kBlurTY + 2 * K;
+        r.stride = r.rw;                  // the partner is the next column
+    }
+    r.floats = (v.blur_major == 0 && r.rw > kBlurStride) ? (1 << 30) : r.stride * r.rh;
+    return r;
+}
+
 // Directional Gaussian over the source, one block per 64 x 16 tile of one blurred view.
-// out(p) = sum_k w_k lerp(I, p + k v), v = (1, m) (major x) or (m, 1) (major y).  The
-// tile's source footprint (the tile grown by the tap offsets) is staged in LDS with the
-// border replicated at load time, which is the same clamping as clamping each tap.
+// out(p) = sum_k w_k lerp(I, p + k v), v = (1, m) (major x) or (m, 1) (major y), written as
+// sum_k wa_k I(p + k v_whole) + wb_k I(p + k v_whole + e_minor).  The tile's source footprint
+// is staged in LDS as fp32 with the border replicated at load time (the same as clamping
+// each tap), so each tap is one paired LDS read and two FMAs.
 __global__ void __launch_bounds__(256) k_blur(const uint8_t* __restrict__ src, int W, int H, int pitch,
                                               const xa_view_desc* __restrict__ views,
                                               const int32_t* __restrict__ blur_views,
-                                              const BlurTap* __restrict__ taps, float* __restrict__ out) {
-    __shared__ uint8_t tile[kBlurLds];
+                                              const BlurTap* __restrict__ taps, float* __restrict__ out,
+                                              int lds_floats) {
+    extern __shared__ float btile[];
     const int tiles_x = (W + kBlurTX - 1) / kBlurTX;
     const int x0 = (blockIdx.x % tiles_x) * kBlurTX, y0 = (blockIdx.x / tiles_x) * kBlurTY;
     const int tx = threadIdx.x % kBlurTX, ty0 = threadIdx.x / kBlurTX;
     const xa_view_desc& v = views[blur_views[blockIdx.y]];
     const BlurTap* tp = taps + v.blur_tap0;
-    const int n = v.blur_ntaps, K = (n - 1) / 2;
-    const int dlo = min(tp[0].dmin, tp[n - 1].dmin), dhi = max(tp[0].dmin, tp[n - 1].dmin) + 1;
-    int rx0, ry0, rw, rh;
-    if (v.blur_major == 0) {
-        rx0 = x0 - K; rw = kBlurTX + 2 * K;
-        ry0 = y0 + dlo; rh = kBlurTY - 1 + dhi - dlo + 1;
-    } else {
-        rx0 = x0 + dlo; rw = kBlurTX - 1 + dhi - dlo + 1;
-        ry0 = y0 - K; rh = kBlurTY + 2 * K;
-    }
+    const int n = v.blur_ntaps;
+    const BlurRegion g = blur_region(v, tp, x0, y0);
     float* o = out + v.blur_offset;
-    if (rw * rh <= kBlurLds) {
-        for (int e = threadIdx.x; e < rw * rh; e += 256) {
-            const int r = e / rw, c = e - (e / rw) * rw;
-            tile[e] = src[size_t(clampi(ry0 + r, 0, H - 1)) * pitch + clampi(rx0 + c, 0, W - 1)];
+    if (g.floats <= lds_floats) {
+        // loads are issued 8 per thread before any is stored, so their latencies overlap;
+        // r = e / rw through a float reciprocal is exact for e < 2^14 (see the warp's staging)
+        const int n_el = g.rw * g.rh;
+        const float rrw = 1.0f / float(g.rw);
+        for (int e0 = 0; e0 < n_el; e0 += 8 * 256) {
+            float val[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * 256 + int(threadIdx.x);
+                const int r = int((float(e) + 0.5f) * rrw), c = e - r * g.rw;
+                if (e < n_el) val[u] = float(src[size_t(clampi(g.ry0 + r, 0, H - 1)) * pitch + clampi(g.rx0 + c, 0, W - 1)]);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * 256 + int(threadIdx.x);
+                const int r = int((float(e) + 0.5f) * rrw), c = e - r * g.rw;
+                if (e < n_el) btile[r * g.stride + c] = val[u];
+            }
         }
         __syncthreads();
         for (int j = 0; j < kBlurTY / 4; ++j) {
             const int x = x0 + tx, y = y0 + ty0 + 4 * j;
             if (x >= W || y >= H) continue;
+            const float* base = btile + (y - g.ry0) * g.stride + (x - g.rx0);
             float acc = 0.0f;
+            // the tap table is padded with zero taps to a multiple of 4, so taps load 4 at a time
+            const int n4 = (n + 3) & ~3;
             if (v.blur_major == 0) {
-                for (int k = 0; k < n; ++k) {
-                    const BlurTap t = tp[k];
-                    const uint8_t* r = tile + (y + t.dmin - ry0) * rw + (x + t.dmaj - rx0);
-                    const float a = float(r[0]), b = float(r[rw]);
-                    acc += t.w * ((1.0f - t.frac) * a + t.frac * b);
+                for (int k = 0; k < n4; k += 4) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const BlurTap t = tp[k + u];
+                        const float* q = base + t.dmin * kBlurStride + t.dmaj;
+                        acc = fmaf(t.wb, q[kBlurStride], fmaf(t.wa, q[0], acc));
+                    }
                 }
             } else {
-                for (int k = 0; k < n; ++k) {
-                    const BlurTap t = tp[k];
-                    const uint8_t* r = tile + (y + t.dmaj - ry0) * rw + (x + t.dmin - rx0);
-                    const float a = float(r[0]), b = float(r[1]);
-                    acc += t.w * ((1.0f - t.frac) * a + t.frac * b);
+                for (int k = 0; k < n4; k += 4) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const BlurTap t = tp[k + u];
+                        const float* q = base + t.dmaj * g.stride + t.dmin;
+                        acc = fmaf(t.wb, q[1], fmaf(t.wa, q[0], acc));
+                    }
                 }
             }
             o[size_t(y) * W + x] = acc;
@@ -87,7 +127,7 @@ __global__ void __launch_bounds__(256) k_blur(const uint8_t* __restrict__ src, i
                 const int yk = y + t.dmin;
                 const float a = float(src[size_t(clampi(yk, 0, H - 1)) * pitch + xk]);
                 const float b = float(src[size_t(clampi(yk + 1, 0, H - 1)) * pitch + xk]);
-                acc += t.w * ((1.0f - t.frac) * a + t.frac * b);
+                acc += t.wa * a + t.wb * b;
             }
         } else {
             for (int k = 0; k < n; ++k) {
@@ -96,42 +136,41 @@ __global__ void __launch_bounds__(256) k_blur(const uint8_t* __restrict__ src, i
                 const int xk = x + t.dmin;
                 const float a = float(row[clampi(xk, 0, W - 1)]);
                 const float b = float(row[clampi(xk + 1, 0, W - 1)]);
-                acc += t.w * ((1.0f - t.frac) * a + t.frac * b);
+                acc += t.wa * a + t.wb * b;
             }
         }
         o[size_t(y) * W + x] = acc;
     }
 }
 
-// Weights L4(i - f), i = -3..4, of eq. (4) (a = 4), normalised to sum 1.
+// Weights L4(i - f), i = -3..4, of eq. (4) (a = 4), unnormalised; returns their sum.
 // sin(pi (i - f)) = (-1)^(i+1) sin(pi f) and sin(pi (i - f)/4) expands with the
-// angle-difference formula, so three transcendental evaluations serve all 8 taps;
-// f == 0 gives the exact one-hot weights of an on-grid sample.
-__device__ __forceinline__ void lanczos4_weights(float f, float w[8]) {
+// angle-difference formula, so three transcendental evaluations serve all 8 taps:
+// L4(i - f) = (A_i sin(pi f) cos(pi f/4) + B_i sin(pi f) sin(pi f/4)) / (i - f)^2 with
+// A_i = (4/pi^2) (-1)^(i+1) sin(pi i/4), B_i = -(4/pi^2) (-1)^(i+1) cos(pi i/4).  The hardware
+// sine / cosine (argument in revolutions, absolute error ~1e-6, far below what moves an
+// 8-bit intensity) and reciprocal are used.  f == 0 gives the exact one-hot weights.
+__device__ __forceinline__ float lanczos4_weights(float f, float w[8]) {
     if (f == 0.0f) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) w[i] = (i == 3) ? 1.0f : 0.0f;
-        return;
+        return 1.0f;
     }
-    const float sp = sinpif(f);
-    const float s4 = sinpif(0.25f * f), c4 = cospif(0.25f * f);
-    // sin(pi i / 4), cos(pi i / 4) for i = -3..4
-    const float si[8] = {-0.70710678f, -1.0f, -0.70710678f, 0.0f, 0.70710678f, 1.0f, 0.70710678f, 0.0f};
-    const float ci[8] = {-0.70710678f, 0.0f, 0.70710678f, 1.0f, 0.70710678f, 0.0f, -0.70710678f, -1.0f};
-    const float k = 4.0f / (float(M_PI) * float(M_PI));
+    const float sp = __builtin_amdgcn_sinf(0.5f * f);            // sin(pi f)
+    const float u = sp * __builtin_amdgcn_cosf(0.125f * f);      // sin(pi f) cos(pi f / 4)
+    const float v = sp * __builtin_amdgcn_sinf(0.125f * f);      // sin(pi f) sin(pi f / 4)
+    constexpr float k = 0.40528473456935108578f;                 // 4 / pi^2
+    constexpr float h = 0.70710678118654752440f;
+    const float A[8] = {-k * h, k, -k * h, 0.0f, k * h, -k, k * h, 0.0f};
+    const float B[8] = {k * h, 0.0f, -k * h, k, -k * h, 0.0f, k * h, -k};
     float sum = 0.0f;
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-        const int i = t - 3;
-        const float x = float(i) - f;
-        const float sgn = (i & 1) ? 1.0f : -1.0f;           // (-1)^(i+1)
-        const float num = sgn * sp * (si[t] * c4 - ci[t] * s4);
-        w[t] = k * num / (x * x);
+        const float x = float(t - 3) - f;
+        w[t] = (A[t] * u + B[t] * v) * __builtin_amdgcn_rcpf(x * x);
         sum += w[t];
     }
-    const float r = 1.0f / sum;
-#pragma unroll
-    for (int t = 0; t < 8; ++t) w[t] *= r;
+    return sum;
 }
 
 // Source coordinate of a view pixel, evaluated term by term in fp64 without contraction
@@ -174,7 +213,8 @@ __global__ void __launch_bounds__(kWarpThreads) k_warp(const uint8_t* __restrict
     const int tiles_x = (v.width + tw - 1) / tw;
     const int x0 = (local % tiles_x) * tw, y0 = (local / tiles_x) * th;
     const int qx = x0 + int(threadIdx.x) % tw, qy = y0 + int(threadIdx.x) / tw;
-    // bounding box of the footprint, in clamped source indices
+    // bounding box of the footprint (the tile's pixel centres through inv, grown by the
+    // 8-tap window, clamped to the source); every thread derives the same box
     double pxl = 1e300, pxh = -1e300, pyl = 1e300, pyh = -1e300;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -188,19 +228,29 @@ __global__ void __launch_bounds__(kWarpThreads) k_warp(const uint8_t* __restrict
     const int by0 = max(int(fmax(floor(pyl - 1e-6), -1e9)) - 3, 0);
     const int by1 = min(int(fmin(floor(pyh + 1e-6), 1e9)) + 4, H - 1);
     const int bw = bx1 - bx0 + 1, bh = by1 - by0 + 1;
-    const bool use_lds = bw > 0 && bh > 0 && (long long)bw * bh <= kWarpLds;
+    const int ls = bw | 1;                  // odd LDS row stride: vertically adjacent taps fall in different banks
+    const bool use_lds = bw > 0 && bh > 0 && (long long)ls * bh <= kWarpLds;
     const bool blur = v.blur_offset >= 0;
     const float* bsrc = blurred + (blur ? v.blur_offset : 0);
     if (use_lds) {
-        if (blur) {
-            for (int e = threadIdx.x; e < bw * bh; e += kWarpThreads) {
-                const int r = e / bw, c = e - (e / bw) * bw;
-                tile[e] = bsrc[size_t(by0 + r) * W + bx0 + c];
+        // flattened staging; r = e / bw through a float reciprocal is exact here because
+        // (e + 1/2) / bw stays at least 1/(2 bw) away from an integer and e < 2^13
+        // loads are issued 8 per thread before any is stored, so their latencies overlap
+        const float rbw = 1.0f / float(bw);
+        const int n = bw * bh;
+        for (int e0 = 0; e0 < n; e0 += 8 * kWarpThreads) {
+            float val[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * kWarpThreads + int(threadIdx.x);
+                const int r = int((float(e) + 0.5f) * rbw), c = e - r * bw;
+                if (e < n) val[u] = blur ? bsrc[size_t(by0 + r) * W + bx0 + c] : float(src[size_t(by0 + r) * pitch + bx0 + c]);
             }
-        } else {
-            for (int e = threadIdx.x; e < bw * bh; e += kWarpThreads) {
-                const int r = e / bw, c = e - (e / bw) * bw;
-                tile[e] = float(src[size_t(by0 + r) * pitch + bx0 + c]);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * kWarpThreads + int(threadIdx.x);
+                const int r = int((float(e) + 0.5f) * rbw), c = e - r * bw;
+                if (e < n) tile[r * ls + c] = val[u];
             }
         }
     }
@@ -219,14 +269,26 @@ __global__ void __launch_bounds__(kWarpThreads) k_warp(const uint8_t* __restrict
     const double fxd = floor(px), fyd = floor(py);
     const int ix = int(fxd), iy = int(fyd);
     float wx[8], wy[8];
-    lanczos4_weights(float(px - fxd), wx);
-    lanczos4_weights(float(py - fyd), wy);
+    const float sx = lanczos4_weights(float(px - fxd), wx);
+    const float sy = lanczos4_weights(float(py - fyd), wy);
     int cols[8];
     float val;
-    if (use_lds) {
+    if (use_lds && ix >= 3 && ix + 4 <= W - 1 && iy >= 3 && iy + 4 <= H - 1) {
+        // interior: the 8 x 8 window needs no clamping; rows are read at immediate offsets
+        const float* base = tile + (iy - 3 - by0) * ls + (ix - 3 - bx0);
+        val = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float* r = base + j * ls;
+            float sacc = 0.0f;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) sacc += wx[i] * r[i];
+            val += wy[j] * sacc;
+        }
+    } else if (use_lds) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) cols[i] = clampi(clampi(ix - 3 + i, 0, W - 1) - bx0, 0, bw - 1);
-        val = lanczos_sum([&](int j) { return tile + clampi(clampi(iy - 3 + j, 0, H - 1) - by0, 0, bh - 1) * bw; },
+        val = lanczos_sum([&](int j) { return tile + clampi(clampi(iy - 3 + j, 0, H - 1) - by0, 0, bh - 1) * ls; },
                           cols, wx, wy);
     } else {
 #pragma unroll
@@ -237,6 +299,7 @@ __global__ void __launch_bounds__(kWarpThreads) k_warp(const uint8_t* __restrict
             val = lanczos_sum([&](int j) { return src + size_t(clampi(iy - 3 + j, 0, H - 1)) * pitch; }, cols, wx,
                               wy);
     }
+    val *= __builtin_amdgcn_rcpf(sx * sy);    // eq. (3) divided by the sum of the weights
     const float q = rintf(val);
     arena[o] = uint8_t(q < 0.0f ? 0.0f : (q > 255.0f ? 255.0f : q));
     mask[o] = 1;
@@ -255,8 +318,16 @@ xa_status launch_simulate(const PlanView& ph, const PlanView& pd, const uint8_t*
     const int W = h->src_w, H = h->src_h;
     if (h->n_blur > 0) {
         const int tiles = ((W + kBlurTX - 1) / kBlurTX) * ((H + kBlurTY - 1) / kBlurTY);  // 4 rows per thread
-        hipLaunchKernelGGL(k_blur, dim3(tiles, h->n_blur), dim3(256), 0, st, src, W, H, pitch, pd.views,
-                           pd.blur_views, pd.taps, blurred);
+        // LDS sized for the largest footprint among the blurred views (tiles away from the border
+        // have the same footprint size as the first); larger ones fall back to global reads
+        int lds = 0;
+        for (int i = 0; i < h->n_blur; ++i) {
+            const xa_view_desc& v = ph.views[ph.blur_views[i]];
+            const BlurRegion g = blur_region(v, ph.taps + v.blur_tap0, 0, 0);
+            if (g.floats <= kBlurLdsMax) lds = std::max(lds, g.floats);
+        }
+        hipLaunchKernelGGL(k_blur, dim3(tiles, h->n_blur), dim3(256), size_t(lds) * sizeof(float), st, src, W, H,
+                           pitch, pd.views, pd.blur_views, pd.taps, blurred, lds);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "blur launch");
     }

@@ -67,10 +67,11 @@ def test_plan_matches_oracle(L, w, h, n_tilt):
             assert pv["blur_major"] == major and pv["blur_ntaps"] == len(ks)
             taps = p.taps()[pv["blur_tap0"]:pv["blur_tap0"] + pv["blur_ntaps"]]
             assert np.array_equal(taps["dmaj"], ks)
-            assert np.allclose(taps["w"], g, rtol=1e-6, atol=1e-9)
             km = ks * m
+            f = km - np.floor(km)
             assert np.array_equal(taps["dmin"], np.floor(km).astype(np.int64))
-            assert np.allclose(taps["frac"], km - np.floor(km), atol=1e-6)
+            assert np.allclose(taps["wa"], g * (1 - f), rtol=1e-6, atol=1e-9)
+            assert np.allclose(taps["wb"], g * f, rtol=1e-6, atol=1e-9)
         else:
             assert pv["blur_ntaps"] == 0 and pv["blur_offset"] == -1
     # arena layout: levels do not overlap and fit the arena
