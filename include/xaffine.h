@@ -19,7 +19,7 @@
  *    returns.  Workspaces must be 256-byte aligned.
  *  - Device work is enqueued on `stream` and is asynchronous: outputs are valid
  *    once the stream has been synchronised.  No call synchronises the stream.
- *  - A plan is a flat, relocatable byte blob written by xa_plan_image.  Calls
+ *  - A plan is a flat, relocatable byte blob written by xa_plan_views.  Calls
  *    take it twice: plan_host (host memory, used for launch geometry) and
  *    plan_dev (a byte-for-byte device copy made by the caller, read by kernels).
  *  - Images are row-major uint8 with a row pitch in bytes.  All coordinates are
@@ -51,7 +51,7 @@ typedef enum {
 } xa_status;
 
 #define XA_PLAN_MAGIC 0x58414650u   /* "XAFP" */
-#define XA_PLAN_VERSION 2u
+#define XA_PLAN_VERSION 3u
 #define XA_MAX_LEVELS 12
 #define XA_MAX_QUOTA 2048           /* keypoints per pyramid level */
 #define XA_MAX_FEATURES 4096        /* keypoints per view */
@@ -65,16 +65,34 @@ typedef struct {
     double t, phi, psi, s, tx, ty;
 } xa_affine_params;
 
-/* A planned view.  fwd maps source to view, inv view to source, both 2x3
- * row-major (x' = m[0] x + m[1] y + m[2], y' = m[3] x + m[4] y + m[5]).
+/* A source image inside a caller-owned sources buffer (uint8, row-major).
+ * scale relates its pixel coordinates to the original image the caller
+ * matches: p_original = (p + 1/2) / scale - 1/2 (1 for an original image,
+ * s for the output of the scale stage at scale s). */
+typedef struct {
+    int32_t width, height;
+    int32_t pitch;              /* bytes between rows */
+    int32_t pad;
+    int64_t offset;             /* byte offset of pixel (0, 0) in the sources buffer */
+    double scale;
+} xa_source_desc;
+
+/* A planned view of one source.  fwd maps source to view, inv view to source,
+ * both 2x3 row-major (x' = m[0] x + m[1] y + m[2], y' = m[3] x + m[4] y + m[5]).
  * The linear part is s R(psi) diag(1/t, 1) R(phi); the canvas is the bounding
  * box of the source rectangle under it.  sigma is the standard deviation (in
  * source pixels) of the anti-alias Gaussian applied along (ux, uy), the
- * source direction the tilt compresses: sigma = 0.8 sqrt(t^2 - 1), 0 for t = 1. */
+ * source direction the map compresses: sigma = 0.8 sqrt((t/s)^2 - 1) when
+ * t/s > 1, else 0. */
 typedef struct {
     xa_affine_params p;
-    int32_t src_w, src_h;
+    int32_t source;             /* index into the plan's source table */
+    int32_t src_w, src_h, src_pitch;
+    int64_t src_offset;         /* byte offset of the source in the sources buffer */
+    double src_scale;           /* source -> original coordinates, see xa_source_desc */
     int32_t width, height;      /* canvas W' x H' */
+    int32_t pitch;              /* row pitch of level 0 in the arena (bytes) */
+    int32_t warp_tile_w;        /* width of the warp's output tiles (tiles hold 256 pixels) */
     double fwd[6];
     double inv[6];
     double sigma;
@@ -84,8 +102,6 @@ typedef struct {
     int32_t blur_major;         /* 0: taps step along x, 1: along y */
     int32_t blur_tap0;          /* first entry in the tap table */
     int32_t blur_ntaps;         /* 2K + 1, 0 if no blur */
-    int32_t warp_tile_w;        /* width of the warp's output tiles (tiles hold 256 pixels) */
-    int32_t pitch;              /* row pitch of level 0 in the arena (bytes) */
     int32_t pad;
 } xa_view_desc;
 
@@ -126,6 +142,10 @@ typedef struct {
     int64_t off_warp_prefix;    /* int32[n_views + 1]: first warp tile of each view */
     int64_t off_level_prefix;   /* int32[n_levels][n_views + 1]: first tile of each view at each level */
     int64_t off_vl_prefix;      /* int32[n_views * n_levels + 1]: first tile of each (view, level) */
+    int64_t off_blur_prefix;    /* int32[n_blur + 1]: first blur tile of each blurred view */
+    int64_t off_sources;        /* xa_source_desc[n_sources] */
+    int32_t n_sources;
+    int32_t pad;
 } xa_plan_header;
 
 /* A keypoint in canonical order within its view: level ascending, then Harris
@@ -169,29 +189,58 @@ const char* xa_version(void);
  * full count (XA_ECAPACITY if it exceeds cap).  Host only. */
 xa_status xa_sampling_grid(int32_t n_tilt, double b_deg, xa_affine_params* out, int32_t cap, int32_t* n_out);
 
-/* Plan the views of one src_w x src_h image (Sec. III.B, eq. (2)): canvases,
- * maps, blur taps, pyramid levels (n_levels at factor level_scale), per-level
- * quotas of n_features keypoints (proportional to level area) and the arena
- * layout.  Host only.  With blob == NULL (or blob_cap too small) only
- * *blob_bytes is set and XA_ECAPACITY is returned for a too-small buffer. */
-xa_status xa_plan_image(int32_t src_w, int32_t src_h, const xa_affine_params* params, int32_t n_views,
-                        int32_t n_levels, double level_scale, int32_t n_features, int32_t fast_threshold,
-                        void* blob, size_t blob_cap, size_t* blob_bytes);
+/* Plan simulated views of one or more source images (Sec. III.B, eq. (2)):
+ * canvases, maps, blur taps, pyramid levels (n_levels at factor level_scale),
+ * per-level quotas of n_features keypoints (proportional to level area) and
+ * the arena layout.  View i simulates sources[view_source[i]] with params[i];
+ * parameters need t >= 1 and s >= 1 (reductions go through the scale stage,
+ * xa_scale_sources, whose output is then a source with scale < 1).  Host
+ * only.  With blob == NULL (or blob_cap too small) only *blob_bytes is set
+ * (XA_ECAPACITY for a buffer that is too small). */
+xa_status xa_plan_views(const xa_source_desc* sources, int32_t n_sources, const int32_t* view_source,
+                        const xa_affine_params* params, int32_t n_views, int32_t n_levels, double level_scale,
+                        int32_t n_features, int32_t fast_threshold, void* blob, size_t blob_cap, size_t* blob_bytes);
 
-/* Simulate every planned view of d_src (anti-alias blur along the tilt
- * direction, then Lanczos-4 resampling, eqs. (3)-(4)).  Writes level 0 of
- * each view into d_arena (u8, round-half-even of the interpolated value,
- * 0 outside the source), its content mask into d_mask (1 where the view pixel
- * maps inside the source rectangle) and, if d_values is not NULL, the
- * unquantised fp32 values at the same element offsets (d_values then holds
- * arena_bytes floats).  Pixel (x, y) of view v is element offset + y * pitch + x
- * (xa_view_desc).  d_arena and d_mask must be 128-byte aligned.
- * Workspace: xa_simulate_workspace_size(plan_host). */
+/* xa_plan_views for one src_w x src_h image at offset 0 of its buffer. */
+xa_status xa_plan_image(int32_t src_w, int32_t src_h, int32_t src_pitch, const xa_affine_params* params,
+                        int32_t n_views, int32_t n_levels, double level_scale, int32_t n_features,
+                        int32_t fast_threshold, void* blob, size_t blob_cap, size_t* blob_bytes);
+
+/* Simulate every planned view (anti-alias blur along the compressed direction,
+ * then Lanczos-4 resampling, eqs. (3)-(4)) from the sources in d_sources.
+ * Writes level 0 of each view into d_arena (u8, round-half-even of the
+ * interpolated value, 0 outside the source), its content mask into d_mask
+ * (1 where the view pixel maps inside the source rectangle) and, if d_values
+ * is not NULL, the unquantised fp32 values at the same element offsets
+ * (d_values then holds arena_bytes floats).  Pixel (x, y) of view v is element
+ * offset + y * pitch + x (xa_view_desc).  d_arena and d_mask must be 128-byte
+ * aligned.  Workspace: xa_simulate_workspace_size(plan_host). */
 size_t xa_simulate_workspace_size(const void* plan_host);
-xa_status xa_simulate_views(const void* plan_host, const void* plan_dev,
-                            const uint8_t* d_src, int32_t src_pitch,
+xa_status xa_simulate_views(const void* plan_host, const void* plan_dev, const uint8_t* d_sources,
                             uint8_t* d_arena, uint8_t* d_mask, float* d_values,
                             void* d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* Scale stage for the scale parameter of the sampling group (Sec. III.B).  A
+ * job resamples src into dst at factor s: for s < 1 an isotropic anti-alias
+ * Gaussian of standard deviation 0.8 sqrt(1/s^2 - 1) first, then Lanczos-4
+ * (eqs. (3)-(4)) at p = (q + 1/2)/s - 1/2, taps clamped to the image, rounded
+ * half to even.  dst must be xa_scaled_size(src, s) = round(s W) x round(s H)
+ * and should carry scale = s * src.scale, so that keypoints found on views of
+ * it map back to the original image.  Supported: 1/8 <= s, outputs up to
+ * 32768 pixels a side.  Both images live in the same caller-owned sources
+ * buffer (d_sources); all jobs run in two launches.  If d_values is not NULL
+ * it receives the unquantised fp32 output at the destination's element
+ * offsets (it must span the sources buffer's element count).
+ * Workspace: xa_scale_workspace_size(splan_host). */
+typedef struct {
+    xa_source_desc src, dst;
+    double s;
+} xa_scale_job;
+xa_status xa_scaled_size(int32_t w, int32_t h, double s, int32_t* out_w, int32_t* out_h);
+xa_status xa_plan_scales(const xa_scale_job* jobs, int32_t n_jobs, void* blob, size_t blob_cap, size_t* blob_bytes);
+size_t xa_scale_workspace_size(const void* splan_host);
+xa_status xa_scale_sources(const void* splan_host, const void* splan_dev, uint8_t* d_sources, float* d_values,
+                           void* d_ws, size_t ws_bytes, hipStream_t stream);
 
 /* ORB on every planned view (levels 1.. of the pyramid are written into
  * d_arena and d_mask, whose level 0 must hold the simulated views): FAST-9
@@ -224,8 +273,8 @@ xa_status xa_match_views(const uint8_t* d_desc_a, const int32_t* d_count_a, int3
  * Both plans must use the same n_features.  Workspace:
  * xa_match_pair_workspace_size(plan_a_host, plan_b_host). */
 size_t xa_match_pair_workspace_size(const void* plan_a_host, const void* plan_b_host);
-xa_status xa_match_pair(const void* plan_a_host, const void* plan_a_dev, const uint8_t* d_a, int32_t pitch_a,
-                        const void* plan_b_host, const void* plan_b_dev, const uint8_t* d_b, int32_t pitch_b,
+xa_status xa_match_pair(const void* plan_a_host, const void* plan_a_dev, const uint8_t* d_a,
+                        const void* plan_b_host, const void* plan_b_dev, const uint8_t* d_b,
                         const int8_t* d_pattern, int32_t ratio_num, int32_t ratio_den,
                         const xa_pair_buffers* out, void* d_ws, size_t ws_bytes, hipStream_t stream);
 

@@ -67,7 +67,7 @@ class View:
     height: int
     fwd: np.ndarray      # 2x3: q = fwd[:, :2] @ p + fwd[:, 2]
     inv: np.ndarray      # 2x3: p = inv[:, :2] @ q + inv[:, 2]
-    sigma: float         # anti-alias sigma (source pixels) along u; 0 = none
+    sigma: float         # anti-alias sigma (source pixels) along u, 0.8 sqrt((t/s)^2 - 1); 0 = none
     u: tuple             # unit direction in source coordinates compressed by the tilt
 
 
@@ -90,7 +90,9 @@ def plan_view(src_w: int, src_h: int, t: float, phi: float, psi: float = 0.0, s:
     Li = np.linalg.inv(L)
     fwd = np.concatenate([L, tau[:, None]], axis=1)
     inv = np.concatenate([Li, (-Li @ tau)[:, None]], axis=1)
-    sigma = AA_C * math.sqrt(t * t - 1.0) if t > 1.0 else 0.0
+    # anti-alias for the net compression t/s along u (for s = 1 this is 0.8 sqrt(t^2 - 1))
+    r = t / s
+    sigma = AA_C * math.sqrt(r * r - 1.0) if r > 1.0 else 0.0
     # R(phi) maps this source direction onto the view's x axis, which diag(1/t, 1) compresses.
     u = (math.cos(phi), -math.sin(phi))
     return View(t, phi, psi, s, src_w, src_h, width, height, fwd, inv, sigma, u)
@@ -117,3 +119,8 @@ def level_quotas(n_features: int, n_levels: int, scale: float = 1.2):
         q[l] = int(math.floor(n_features * r[l] / tot))
     q[0] = n_features - sum(q[1:])
     return q
+
+
+def scaled_size(width: int, height: int, s: float):
+    """Size of the scale-stage image: round(s W), round(s H) (half up), at least 1."""
+    return max(1, int(math.floor(s * width + 0.5))), max(1, int(math.floor(s * height + 0.5)))

@@ -150,3 +150,29 @@ def simulate_view(src_u8, view: View):
     U = quantize(V)
     U[~mask] = 0
     return V, mask, U
+
+
+def scale_image(src_u8, s: float):
+    """Scale stage for the scale parameter of the sampling group (Sec. III.B): an isotropic
+    anti-alias Gaussian of standard deviation 0.8 sqrt(1/s^2 - 1) for a reduction (s < 1;
+    none for s >= 1), then Lanczos-4 resampling at p = (q + 1/2) / s - 1/2 onto a
+    round(s W) x round(s H) grid, taps clamped to the image, rounded half to even.
+
+    Returns (V fp64, u8).  The output grid is chosen so that every output pixel maps inside
+    the source, and views of the scaled image use it as their source (s = 1 in their map)."""
+    from .plan import scaled_size
+    I = np.asarray(src_u8, np.float64)
+    H, W = I.shape
+    if s == 1.0:
+        return I.copy(), np.asarray(src_u8, np.uint8).copy()
+    if s < 1.0:
+        sigma = 0.8 * math.sqrt(1.0 / (s * s) - 1.0)
+        B = directional_blur(directional_blur(I, sigma, (1.0, 0.0)), sigma, (0.0, 1.0))
+    else:
+        B = I
+    ws, hs = scaled_size(W, H, s)
+    qy, qx = np.mgrid[0:hs, 0:ws].astype(np.float64)
+    px = (qx + 0.5) / s - 0.5
+    py = (qy + 0.5) / s - 0.5
+    V = lanczos_sample(B, px.ravel(), py.ravel()).reshape(hs, ws)
+    return V, quantize(V)

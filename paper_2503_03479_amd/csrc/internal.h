@@ -34,7 +34,8 @@ struct BlurTap {
     int32_t dmin;   // floor(k m): whole-pixel step along the minor axis
 };
 static_assert(sizeof(BlurTap) == 16, "tap layout");
-static_assert(sizeof(xa_view_desc) == 224, "view desc layout");
+static_assert(sizeof(xa_view_desc) == 248, "view desc layout");
+static_assert(sizeof(xa_source_desc) == 32, "source desc layout");
 static_assert(sizeof(xa_level_desc) == 56, "level desc layout");
 static_assert(sizeof(xa_keypoint) == 40, "keypoint layout");
 static_assert(sizeof(xa_match) == 8, "match layout");
@@ -65,6 +66,8 @@ struct PlanView {
     const int32_t* warp_prefix = nullptr;
     const int32_t* level_prefix = nullptr;
     const int32_t* vl_prefix = nullptr;
+    const int32_t* blur_prefix = nullptr;
+    const xa_source_desc* sources = nullptr;
 };
 xa_status plan_host_view(const void* blob, PlanView* out);
 PlanView plan_dev_view(const void* blob_host, const void* blob_dev);
@@ -77,7 +80,7 @@ ExtractWs extract_ws_layout(const xa_plan_header* h);
 size_t simulate_ws_bytes(const xa_plan_header* h);
 
 // Stage launchers (device work only, arguments already validated).
-xa_status launch_simulate(const PlanView& ph, const PlanView& pd, const uint8_t* src, int32_t pitch,
+xa_status launch_simulate(const PlanView& ph, const PlanView& pd, const uint8_t* sources,
                           uint8_t* arena, uint8_t* mask, float* values, float* blurred, hipStream_t st);
 xa_status launch_extract(const PlanView& ph, const PlanView& pd, uint8_t* arena, uint8_t* mask,
                          const int8_t* pattern, xa_keypoint* kp, uint8_t* desc, int32_t* count,

@@ -606,6 +606,10 @@ __global__ void __launch_bounds__(256) k_orient_brief(const xa_view_desc* __rest
         o.x = x; o.y = y; o.level = lev; o.bin = bin; o.harris = R;
         o.xs = __dadd_rn(__dadd_rn(__dmul_rn(vd.inv[0], x0), __dmul_rn(vd.inv[1], y0)), vd.inv[2]);
         o.ys = __dadd_rn(__dadd_rn(__dmul_rn(vd.inv[3], x0), __dmul_rn(vd.inv[4], y0)), vd.inv[5]);
+        if (vd.src_scale != 1.0) {     // scale-stage source: back to the original image
+            o.xs = __dadd_rn(__dadd_rn(o.xs, 0.5) / vd.src_scale, -0.5);
+            o.ys = __dadd_rn(__dadd_rn(o.ys, 0.5) / vd.src_scale, -0.5);
+        }
         kp[slot] = o;
     }
 }

@@ -38,8 +38,8 @@ extern "C" size_t xa_match_pair_workspace_size(const void* plan_a_host, const vo
     return pair_layout(a.h, b.h).total;
 }
 
-extern "C" xa_status xa_match_pair(const void* plan_a_host, const void* plan_a_dev, const uint8_t* d_a, int32_t pitch_a,
-                                   const void* plan_b_host, const void* plan_b_dev, const uint8_t* d_b, int32_t pitch_b,
+extern "C" xa_status xa_match_pair(const void* plan_a_host, const void* plan_a_dev, const uint8_t* d_a,
+                                   const void* plan_b_host, const void* plan_b_dev, const uint8_t* d_b,
                                    const int8_t* d_pattern, int32_t ratio_num, int32_t ratio_den,
                                    const xa_pair_buffers* out, void* d_ws, size_t ws_bytes, hipStream_t stream) {
     PlanView ha, hb;
@@ -52,7 +52,6 @@ extern "C" xa_status xa_match_pair(const void* plan_a_host, const void* plan_a_d
     if (!out->kp_a || !out->desc_a || !out->count_a || !out->kp_b || !out->desc_b || !out->count_b || !out->matches ||
         !out->pair_count || !out->best)
         return fail(XA_EINVAL, "NULL output buffer");
-    if (pitch_a < ha.h->src_w || pitch_b < hb.h->src_w) return fail(XA_EINVAL, "pitch smaller than width");
     if (ratio_num < 0 || ratio_den < 1 || ratio_num > (1 << 20) || ratio_den > (1 << 20))
         return fail(XA_EINVAL, "bad ratio");
     const PairWs w = pair_layout(ha.h, hb.h);
@@ -60,10 +59,10 @@ extern "C" xa_status xa_match_pair(const void* plan_a_host, const void* plan_a_d
     if (!d_ws || reinterpret_cast<uintptr_t>(d_ws) % kAlign) return fail(XA_EINVAL, "workspace must be 256-byte aligned");
     uint8_t* ws = static_cast<uint8_t*>(d_ws);
     const PlanView da = plan_dev_view(plan_a_host, plan_a_dev), db = plan_dev_view(plan_b_host, plan_b_dev);
-    s = launch_simulate(ha, da, d_a, pitch_a, ws + w.arena_a, ws + w.mask_a, nullptr,
+    s = launch_simulate(ha, da, d_a, ws + w.arena_a, ws + w.mask_a, nullptr,
                         reinterpret_cast<float*>(ws + w.sim_a), stream);
     if (s != XA_OK) return s;
-    s = launch_simulate(hb, db, d_b, pitch_b, ws + w.arena_b, ws + w.mask_b, nullptr,
+    s = launch_simulate(hb, db, d_b, ws + w.arena_b, ws + w.mask_b, nullptr,
                         reinterpret_cast<float*>(ws + w.sim_b), stream);
     if (s != XA_OK) return s;
     s = launch_extract(ha, da, ws + w.arena_a, ws + w.mask_a, d_pattern, out->kp_a, out->desc_a, out->count_a,

@@ -41,6 +41,8 @@ xa_status plan_host_view(const void* blob, PlanView* out) {
     out->warp_prefix = reinterpret_cast<const int32_t*>(b + h->off_warp_prefix);
     out->level_prefix = reinterpret_cast<const int32_t*>(b + h->off_level_prefix);
     out->vl_prefix = reinterpret_cast<const int32_t*>(b + h->off_vl_prefix);
+    out->blur_prefix = reinterpret_cast<const int32_t*>(b + h->off_blur_prefix);
+    out->sources = reinterpret_cast<const xa_source_desc*>(b + h->off_sources);
     return XA_OK;
 }
 
@@ -56,6 +58,8 @@ PlanView plan_dev_view(const void* blob_host, const void* blob_dev) {
     p.warp_prefix = reinterpret_cast<const int32_t*>(b + h->off_warp_prefix);
     p.level_prefix = reinterpret_cast<const int32_t*>(b + h->off_level_prefix);
     p.vl_prefix = reinterpret_cast<const int32_t*>(b + h->off_vl_prefix);
+    p.blur_prefix = reinterpret_cast<const int32_t*>(b + h->off_blur_prefix);
+    p.sources = reinterpret_cast<const xa_source_desc*>(b + h->off_sources);
     return p;
 }
 
@@ -127,12 +131,17 @@ struct Planned {
     std::vector<BlurTap> taps;
 };
 
-Planned plan_one(int32_t W, int32_t H, const xa_affine_params& p) {
+Planned plan_one(const xa_source_desc& src, int32_t source, const xa_affine_params& p) {
     Planned out{};
     xa_view_desc& v = out.v;
+    const int32_t W = src.width, H = src.height;
     v.p = p;
+    v.source = source;
     v.src_w = W;
     v.src_h = H;
+    v.src_pitch = src.pitch;
+    v.src_offset = src.offset;
+    v.src_scale = src.scale;
     // L = s R(psi) diag(1/t, 1) R(phi): R(phi) turns the longitude onto x, the tilt compresses x.
     Mat2 L = mul(mul(rot(p.psi), Mat2{1.0 / p.t, 0.0, 0.0, 1.0}), rot(p.phi));
     L = {L.a * p.s, L.b * p.s, L.c * p.s, L.d * p.s};
@@ -154,7 +163,9 @@ Planned plan_one(int32_t W, int32_t H, const xa_affine_params& p) {
     v.fwd[3] = L.c; v.fwd[4] = L.d; v.fwd[5] = ty;
     v.inv[0] = Li.a; v.inv[1] = Li.b; v.inv[2] = -(Li.a * tx + Li.b * ty);
     v.inv[3] = Li.c; v.inv[4] = Li.d; v.inv[5] = -(Li.c * tx + Li.d * ty);
-    v.sigma = p.t > 1.0 ? 0.8 * std::sqrt(p.t * p.t - 1.0) : 0.0;
+    // anti-alias for the net compression t/s along u (0.8 sqrt(t^2 - 1) for s = 1)
+    const double r = p.t / p.s;
+    v.sigma = r > 1.0 ? 0.8 * std::sqrt(r * r - 1.0) : 0.0;
     v.ux = std::cos(p.phi);
     v.uy = -std::sin(p.phi);
     v.blur_offset = -1;
@@ -186,13 +197,20 @@ Planned plan_one(int32_t W, int32_t H, const xa_affine_params& p) {
 
 }  // namespace
 
-extern "C" xa_status xa_plan_image(int32_t src_w, int32_t src_h, const xa_affine_params* params, int32_t n_views,
-                                   int32_t n_levels, double level_scale, int32_t n_features, int32_t fast_threshold,
-                                   void* blob, size_t blob_cap, size_t* blob_bytes) {
+extern "C" xa_status xa_plan_views(const xa_source_desc* sources, int32_t n_sources, const int32_t* view_source,
+                                   const xa_affine_params* params, int32_t n_views, int32_t n_levels, double level_scale,
+                                   int32_t n_features, int32_t fast_threshold, void* blob, size_t blob_cap,
+                                   size_t* blob_bytes) {
     if (!blob_bytes) return fail(XA_EINVAL, "blob_bytes is NULL");
-    if (src_w < 1 || src_h < 1 || src_w > 32768 || src_h > 32768)
-        return fail(XA_EINVAL, "source size %dx%d out of range [1, 32768]", src_w, src_h);
-    if (n_views < 1 || !params) return fail(XA_EINVAL, "need at least one view");
+    if (n_sources < 1 || !sources) return fail(XA_EINVAL, "need at least one source");
+    for (int i = 0; i < n_sources; ++i) {
+        const xa_source_desc& sd = sources[i];
+        if (sd.width < 1 || sd.height < 1 || sd.width > 32768 || sd.height > 32768)
+            return fail(XA_EINVAL, "source %d size %dx%d out of range [1, 32768]", i, sd.width, sd.height);
+        if (sd.pitch < sd.width || sd.offset < 0) return fail(XA_EINVAL, "source %d: pitch < width or offset < 0", i);
+        if (!(sd.scale > 0.0) || !std::isfinite(sd.scale)) return fail(XA_EINVAL, "source %d: scale must be > 0", i);
+    }
+    if (n_views < 1 || !params || !view_source) return fail(XA_EINVAL, "need at least one view");
     if (n_levels < 1 || n_levels > XA_MAX_LEVELS) return fail(XA_EINVAL, "n_levels %d not in [1, %d]", n_levels, XA_MAX_LEVELS);
     if (!(level_scale > 1.0) || !std::isfinite(level_scale)) return fail(XA_EINVAL, "level_scale must be > 1");
     if (n_features < 1 || n_features > XA_MAX_FEATURES)
@@ -200,9 +218,10 @@ extern "C" xa_status xa_plan_image(int32_t src_w, int32_t src_h, const xa_affine
     if (fast_threshold < 0 || fast_threshold > 255) return fail(XA_EINVAL, "fast_threshold must be in [0, 255]");
     for (int i = 0; i < n_views; ++i) {
         const xa_affine_params& p = params[i];
-        if (!(p.t >= 1.0) || !(p.s > 0.0) || !std::isfinite(p.t) || !std::isfinite(p.s) || !std::isfinite(p.phi) ||
+        if (view_source[i] < 0 || view_source[i] >= n_sources) return fail(XA_EINVAL, "view %d: bad source index", i);
+        if (!(p.t >= 1.0) || !(p.s >= 1.0) || !std::isfinite(p.t) || !std::isfinite(p.s) || !std::isfinite(p.phi) ||
             !std::isfinite(p.psi) || !std::isfinite(p.tx) || !std::isfinite(p.ty))
-            return fail(XA_EINVAL, "view %d: need finite parameters with t >= 1 and s > 0", i);
+            return fail(XA_EINVAL, "view %d: need finite parameters with t >= 1 and s >= 1 (reduce with the scale stage)", i);
     }
     // Per-level keypoint quotas, proportional to level area; level 0 takes the remainder.
     std::vector<int32_t> quota(n_levels, 0);
@@ -225,7 +244,7 @@ extern "C" xa_status xa_plan_image(int32_t src_w, int32_t src_h, const xa_affine
     std::vector<Planned> pv(n_views);
     int64_t total_px = 0;
     for (int i = 0; i < n_views; ++i) {
-        pv[i] = plan_one(src_w, src_h, params[i]);
+        pv[i] = plan_one(sources[view_source[i]], view_source[i], params[i]);
         const auto& v = pv[i].v;
         if (v.width < 1 || v.height < 1 || v.width > 32768 || v.height > 32768)
             return fail(XA_EUNSUPPORTED, "view %d canvas %dx%d out of range", i, v.width, v.height);
@@ -236,21 +255,23 @@ extern "C" xa_status xa_plan_image(int32_t src_w, int32_t src_h, const xa_affine
     const int32_t nvl = n_views * n_levels;
     std::vector<xa_level_desc> lv(nvl);
     std::vector<BlurTap> taps;
-    std::vector<int32_t> blur_views;
+    std::vector<int32_t> blur_views, blur_prefix;
     std::vector<int32_t> warp_prefix(n_views + 1, 0);
     std::vector<int32_t> level_prefix(size_t(n_levels) * (n_views + 1), 0);
     std::vector<int32_t> vl_prefix(nvl + 1, 0);
     int64_t arena = 0, cand = 0, blur_floats = 0;
-    int64_t warp_tiles = 0, vl_tiles = 0;
+    int64_t warp_tiles = 0, vl_tiles = 0, blur_tiles = 0;
     std::vector<int64_t> lvl_tiles(n_levels, 0);
     for (int i = 0; i < n_views; ++i) {
         xa_view_desc& v = pv[i].v;
         if (v.sigma > 0.0) {
             v.blur_offset = blur_floats;
-            blur_floats += int64_t(src_w) * src_h;
+            blur_floats += int64_t(v.src_w) * v.src_h;
             v.blur_tap0 = int32_t(taps.size());
             taps.insert(taps.end(), pv[i].taps.begin(), pv[i].taps.end());
             blur_views.push_back(i);
+            blur_prefix.push_back(int32_t(blur_tiles));
+            blur_tiles += int64_t((v.src_w + kBlurTX - 1) / kBlurTX) * ((v.src_h + kBlurTY - 1) / kBlurTY);
         }
         warp_prefix[i] = int32_t(warp_tiles);
         v.warp_tile_w = warp_tile_w(v.p.t, v.p.s);
@@ -284,14 +305,15 @@ extern "C" xa_status xa_plan_image(int32_t src_w, int32_t src_h, const xa_affine
     warp_prefix[n_views] = int32_t(warp_tiles);
     for (int l = 0; l < n_levels; ++l) level_prefix[size_t(l) * (n_views + 1) + n_views] = int32_t(lvl_tiles[l]);
     vl_prefix[nvl] = int32_t(vl_tiles);
-    if (warp_tiles > INT32_MAX / 2 || vl_tiles > INT32_MAX / 2)
+    blur_prefix.push_back(int32_t(blur_tiles));
+    if (warp_tiles > INT32_MAX / 2 || vl_tiles > INT32_MAX / 2 || blur_tiles > INT32_MAX / 2)
         return fail(XA_EUNSUPPORTED, "too many tiles for one launch");
 
     xa_plan_header h{};
     h.magic = XA_PLAN_MAGIC;
     h.version = XA_PLAN_VERSION;
-    h.src_w = src_w;
-    h.src_h = src_h;
+    h.src_w = sources[0].width;
+    h.src_h = sources[0].height;
     h.n_views = n_views;
     h.n_levels = n_levels;
     h.n_features = n_features;
@@ -302,6 +324,7 @@ extern "C" xa_status xa_plan_image(int32_t src_w, int32_t src_h, const xa_affine
     h.blur_floats = blur_floats;
     h.n_blur = int32_t(blur_views.size());
     h.n_taps_total = int32_t(taps.size());
+    h.n_sources = n_sources;
     size_t o = align_up(sizeof(xa_plan_header), 64);
     h.off_views = int64_t(o);        o = align_up(o + sizeof(xa_view_desc) * n_views, 64);
     h.off_levels = int64_t(o);       o = align_up(o + sizeof(xa_level_desc) * nvl, 64);
@@ -310,6 +333,8 @@ extern "C" xa_status xa_plan_image(int32_t src_w, int32_t src_h, const xa_affine
     h.off_warp_prefix = int64_t(o);  o = align_up(o + 4 * warp_prefix.size(), 64);
     h.off_level_prefix = int64_t(o); o = align_up(o + 4 * level_prefix.size(), 64);
     h.off_vl_prefix = int64_t(o);    o = align_up(o + 4 * vl_prefix.size(), 64);
+    h.off_blur_prefix = int64_t(o);  o = align_up(o + 4 * blur_prefix.size(), 64);
+    h.off_sources = int64_t(o);      o = align_up(o + sizeof(xa_source_desc) * n_sources, 64);
     h.total_bytes = int64_t(o);
     *blob_bytes = o;
     if (!blob) return ok();
@@ -325,5 +350,16 @@ extern "C" xa_status xa_plan_image(int32_t src_w, int32_t src_h, const xa_affine
     std::memcpy(b + h.off_warp_prefix, warp_prefix.data(), 4 * warp_prefix.size());
     std::memcpy(b + h.off_level_prefix, level_prefix.data(), 4 * level_prefix.size());
     std::memcpy(b + h.off_vl_prefix, vl_prefix.data(), 4 * vl_prefix.size());
+    std::memcpy(b + h.off_blur_prefix, blur_prefix.data(), 4 * blur_prefix.size());
+    std::memcpy(b + h.off_sources, sources, sizeof(xa_source_desc) * n_sources);
     return ok();
+}
+
+extern "C" xa_status xa_plan_image(int32_t src_w, int32_t src_h, int32_t src_pitch, const xa_affine_params* params,
+                                   int32_t n_views, int32_t n_levels, double level_scale, int32_t n_features,
+                                   int32_t fast_threshold, void* blob, size_t blob_cap, size_t* blob_bytes) {
+    const xa_source_desc src{src_w, src_h, src_pitch, 0, 0, 1.0};
+    std::vector<int32_t> vs(n_views > 0 ? n_views : 0, 0);
+    return xa_plan_views(&src, 1, vs.data(), params, n_views, n_levels, level_scale, n_features, fast_threshold, blob,
+                         blob_cap, blob_bytes);
 }

@@ -12,12 +12,19 @@ namespace {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// Largest i in [0, n) with prefix[i] <= b (prefix[0] == 0, prefix non-decreasing).
-__device__ __forceinline__ int find_segment(const int32_t* __restrict__ prefix, int n, int b) {
+// Largest i in [0, n) with prefix[i] <= b, searched 64 entries at a time by the whole
+// wave (every lane must be active); prefix[0] == 0 <= b < prefix[n].
+__device__ __forceinline__ int find_segment_wave(const int32_t* __restrict__ prefix, int n, int b) {
+    const int lane = threadIdx.x & 63;
     int lo = 0, hi = n;
     while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (prefix[mid] <= b) lo = mid; else hi = mid;
+        const int step = (hi - lo + 63) >> 6;
+        const int p = lo + lane * step;
+        const bool le = p < hi && prefix[p] <= b;
+        const unsigned long long bal = __ballot(le);
+        const int k = 63 - __clzll(bal);
+        lo = lo + k * step;
+        hi = min(hi, lo + step);
     }
     return lo;
 }
@@ -50,16 +57,21 @@ __host__ __device__ inline BlurRegion blur_region(const xa_view_desc& v, const B
 // sum_k wa_k I(p + k v_whole) + wb_k I(p + k v_whole + e_minor).  The tile's source footprint
 // is staged in LDS as fp32 with the border replicated at load time (the same as clamping
 // each tap), so each tap is one paired LDS read and two FMAs.
-__global__ void __launch_bounds__(256) k_blur(const uint8_t* __restrict__ src, int W, int H, int pitch,
+__global__ void __launch_bounds__(256) k_blur(const uint8_t* __restrict__ sources,
                                               const xa_view_desc* __restrict__ views,
                                               const int32_t* __restrict__ blur_views,
+                                              const int32_t* __restrict__ blur_prefix, int n_blur,
                                               const BlurTap* __restrict__ taps, float* __restrict__ out,
                                               int lds_floats) {
     extern __shared__ float btile[];
+    const int bi = find_segment_wave(blur_prefix, n_blur, blockIdx.x);
+    const xa_view_desc& v = views[blur_views[bi]];
+    const int W = v.src_w, H = v.src_h, pitch = v.src_pitch;
+    const uint8_t* src = sources + v.src_offset;
+    const int local = blockIdx.x - blur_prefix[bi];
     const int tiles_x = (W + kBlurTX - 1) / kBlurTX;
-    const int x0 = (blockIdx.x % tiles_x) * kBlurTX, y0 = (blockIdx.x / tiles_x) * kBlurTY;
+    const int x0 = (local % tiles_x) * kBlurTX, y0 = (local / tiles_x) * kBlurTY;
     const int tx = threadIdx.x % kBlurTX, ty0 = threadIdx.x / kBlurTX;
-    const xa_view_desc& v = views[blur_views[blockIdx.y]];
     const BlurTap* tp = taps + v.blur_tap0;
     const int n = v.blur_ntaps;
     const BlurRegion g = blur_region(v, tp, x0, y0);
@@ -199,15 +211,17 @@ __device__ __forceinline__ float lanczos_sum(Row row, const int cols[8], const f
 // all views of the plan in one launch (block -> view by prefix search).  The tile's source
 // footprint (bounding box of its pixel centres mapped through inv, grown by the 8-tap
 // window) is staged in LDS as fp32 when it fits; otherwise taps are read from global memory.
-__global__ void __launch_bounds__(kWarpThreads) k_warp(const uint8_t* __restrict__ src, int W, int H, int pitch,
+__global__ void __launch_bounds__(kWarpThreads) k_warp(const uint8_t* __restrict__ sources,
                                                        const float* __restrict__ blurred,
                                                        const xa_view_desc* __restrict__ views, int n_views,
                                                        const int32_t* __restrict__ prefix, uint8_t* __restrict__ arena,
                                                        uint8_t* __restrict__ mask, float* __restrict__ values) {
     __shared__ float tile[kWarpLds];
     const int b = blockIdx.x;
-    const int vi = find_segment(prefix, n_views, b);
+    const int vi = find_segment_wave(prefix, n_views, b);
     const xa_view_desc& v = views[vi];
+    const int W = v.src_w, H = v.src_h, pitch = v.src_pitch;
+    const uint8_t* src = sources + v.src_offset;
     const int local = b - prefix[vi];
     const int tw = v.warp_tile_w, th = kWarpThreads / tw;
     const int tiles_x = (v.width + tw - 1) / tw;
@@ -312,12 +326,11 @@ xa_status hip_fail(int err, const char* what) {
     return fail(XA_EHIP, "%s: %s", what, hipGetErrorString(hipError_t(err)));
 }
 
-xa_status launch_simulate(const PlanView& ph, const PlanView& pd, const uint8_t* src, int32_t pitch,
+xa_status launch_simulate(const PlanView& ph, const PlanView& pd, const uint8_t* sources,
                           uint8_t* arena, uint8_t* mask, float* values, float* blurred, hipStream_t st) {
     const xa_plan_header* h = ph.h;
-    const int W = h->src_w, H = h->src_h;
     if (h->n_blur > 0) {
-        const int tiles = ((W + kBlurTX - 1) / kBlurTX) * ((H + kBlurTY - 1) / kBlurTY);  // 4 rows per thread
+        const int tiles = ph.blur_prefix[h->n_blur];
         // LDS sized for the largest footprint among the blurred views (tiles away from the border
         // have the same footprint size as the first); larger ones fall back to global reads
         int lds = 0;
@@ -326,14 +339,14 @@ xa_status launch_simulate(const PlanView& ph, const PlanView& pd, const uint8_t*
             const BlurRegion g = blur_region(v, ph.taps + v.blur_tap0, 0, 0);
             if (g.floats <= kBlurLdsMax) lds = std::max(lds, g.floats);
         }
-        hipLaunchKernelGGL(k_blur, dim3(tiles, h->n_blur), dim3(256), size_t(lds) * sizeof(float), st, src, W, H,
-                           pitch, pd.views, pd.blur_views, pd.taps, blurred, lds);
+        hipLaunchKernelGGL(k_blur, dim3(tiles), dim3(256), size_t(lds) * sizeof(float), st, sources, pd.views,
+                           pd.blur_views, pd.blur_prefix, h->n_blur, pd.taps, blurred, lds);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "blur launch");
     }
     const int tiles = ph.warp_prefix[h->n_views];
     if (tiles > 0) {
-        hipLaunchKernelGGL(k_warp, dim3(tiles), dim3(kWarpThreads), 0, st, src, W, H, pitch, blurred, pd.views, h->n_views,
+        hipLaunchKernelGGL(k_warp, dim3(tiles), dim3(kWarpThreads), 0, st, sources, blurred, pd.views, h->n_views,
                            pd.warp_prefix, arena, mask, values);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "warp launch");
@@ -351,21 +364,20 @@ extern "C" size_t xa_simulate_workspace_size(const void* plan_host) {
     return simulate_ws_bytes(p.h);
 }
 
-extern "C" xa_status xa_simulate_views(const void* plan_host, const void* plan_dev, const uint8_t* d_src,
-                                       int32_t src_pitch, uint8_t* d_arena, uint8_t* d_mask, float* d_values,
-                                       void* d_ws, size_t ws_bytes, hipStream_t stream) {
+extern "C" xa_status xa_simulate_views(const void* plan_host, const void* plan_dev, const uint8_t* d_sources,
+                                       uint8_t* d_arena, uint8_t* d_mask, float* d_values, void* d_ws,
+                                       size_t ws_bytes, hipStream_t stream) {
     PlanView ph;
     xa_status s = plan_host_view(plan_host, &ph);
     if (s != XA_OK) return s;
-    if (!plan_dev || !d_src || !d_arena || !d_mask) return fail(XA_EINVAL, "NULL device pointer");
+    if (!plan_dev || !d_sources || !d_arena || !d_mask) return fail(XA_EINVAL, "NULL device pointer");
     if ((reinterpret_cast<uintptr_t>(d_arena) | reinterpret_cast<uintptr_t>(d_mask)) % 128)
         return fail(XA_EINVAL, "arena and mask must be 128-byte aligned");
-    if (src_pitch < ph.h->src_w) return fail(XA_EINVAL, "pitch %d < width %d", src_pitch, ph.h->src_w);
     const size_t need = simulate_ws_bytes(ph.h);
     if (ws_bytes < need) return fail(XA_ECAPACITY, "simulate workspace needs %zu bytes, got %zu", need, ws_bytes);
     if (need > 0 && (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) % kAlign)))
         return fail(XA_EINVAL, "workspace must be non-NULL and 256-byte aligned");
     const PlanView pd = plan_dev_view(plan_host, plan_dev);
-    s = launch_simulate(ph, pd, d_src, src_pitch, d_arena, d_mask, d_values, static_cast<float*>(d_ws), stream);
+    s = launch_simulate(ph, pd, d_sources, d_arena, d_mask, d_values, static_cast<float*>(d_ws), stream);
     return s == XA_OK ? ok() : s;
 }

@@ -22,11 +22,13 @@ DESC_BYTES = 32
 
 # numpy mirrors of the C structs
 PARAMS_DTYPE = np.dtype([("t", "f8"), ("phi", "f8"), ("psi", "f8"), ("s", "f8"), ("tx", "f8"), ("ty", "f8")])
-VIEW_DTYPE = np.dtype([("p", PARAMS_DTYPE), ("src_w", "i4"), ("src_h", "i4"), ("width", "i4"), ("height", "i4"),
-                       ("fwd", "f8", 6), ("inv", "f8", 6), ("sigma", "f8"), ("ux", "f8"), ("uy", "f8"),
-                       ("offset", "i8"), ("blur_offset", "i8"), ("blur_major", "i4"), ("blur_tap0", "i4"),
-                       ("blur_ntaps", "i4"), ("warp_tile_w", "i4"),
-                       ("pitch", "i4"), ("pad", "i4")])
+SOURCE_DTYPE = np.dtype([("width", "i4"), ("height", "i4"), ("pitch", "i4"), ("pad", "i4"), ("offset", "i8"),
+                         ("scale", "f8")])
+VIEW_DTYPE = np.dtype([("p", PARAMS_DTYPE), ("source", "i4"), ("src_w", "i4"), ("src_h", "i4"), ("src_pitch", "i4"),
+                       ("src_offset", "i8"), ("src_scale", "f8"), ("width", "i4"), ("height", "i4"), ("pitch", "i4"),
+                       ("warp_tile_w", "i4"), ("fwd", "f8", 6), ("inv", "f8", 6), ("sigma", "f8"), ("ux", "f8"),
+                       ("uy", "f8"), ("offset", "i8"), ("blur_offset", "i8"), ("blur_major", "i4"), ("blur_tap0", "i4"),
+                       ("blur_ntaps", "i4"), ("pad", "i4")])
 LEVEL_DTYPE = np.dtype([("width", "i4"), ("height", "i4"), ("pitch", "i4"), ("quota", "i4"), ("offset", "i8"),
                         ("kp_base", "i4"), ("view", "i4"), ("level", "i4"), ("pad", "i4"), ("cand_offset", "i8"),
                         ("cand_cap", "i8")])
@@ -35,13 +37,14 @@ HEADER_DTYPE = np.dtype([("magic", "u4"), ("version", "u4"), ("src_w", "i4"), ("
                          ("total_bytes", "i8"), ("arena_bytes", "i8"), ("cand_total", "i8"), ("blur_floats", "i8"),
                          ("n_blur", "i4"), ("n_taps_total", "i4"), ("off_views", "i8"), ("off_levels", "i8"),
                          ("off_taps", "i8"), ("off_blur_views", "i8"), ("off_warp_prefix", "i8"),
-                         ("off_level_prefix", "i8"), ("off_vl_prefix", "i8")])
+                         ("off_level_prefix", "i8"), ("off_vl_prefix", "i8"), ("off_blur_prefix", "i8"),
+                         ("off_sources", "i8"), ("n_sources", "i4"), ("pad", "i4")])
 TAP_DTYPE = np.dtype([("wa", "f4"), ("wb", "f4"), ("dmaj", "i4"), ("dmin", "i4")])
 KEYPOINT_DTYPE = np.dtype([("x", "i4"), ("y", "i4"), ("level", "i4"), ("bin", "i4"), ("harris", "i8"),
                            ("xs", "f8"), ("ys", "f8")])
 MATCH_DTYPE = np.dtype([("t", "i4"), ("d1", "u2"), ("d2", "u2")])
-assert VIEW_DTYPE.itemsize == 224 and LEVEL_DTYPE.itemsize == 56 and KEYPOINT_DTYPE.itemsize == 40
-assert MATCH_DTYPE.itemsize == 8 and HEADER_DTYPE.itemsize == 136
+assert VIEW_DTYPE.itemsize == 248 and LEVEL_DTYPE.itemsize == 56 and KEYPOINT_DTYPE.itemsize == 40
+assert MATCH_DTYPE.itemsize == 8 and HEADER_DTYPE.itemsize == 160 and SOURCE_DTYPE.itemsize == 32
 
 
 class XAError(RuntimeError):
@@ -65,10 +68,19 @@ _SIGS = {
     "xa_last_error": (_c.c_char_p, []),
     "xa_version": (_c.c_char_p, []),
     "xa_sampling_grid": (_c.c_int, [_c.c_int32, _c.c_double, _c.c_void_p, _c.c_int32, _c.POINTER(_c.c_int32)]),
-    "xa_plan_image": (_c.c_int, [_c.c_int32, _c.c_int32, _c.c_void_p, _c.c_int32, _c.c_int32, _c.c_double,
+    "xa_plan_views": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_int32,
+                                 _c.c_double, _c.c_int32, _c.c_int32, _c.c_void_p, _c.c_size_t,
+                                 _c.POINTER(_c.c_size_t)]),
+    "xa_plan_image": (_c.c_int, [_c.c_int32, _c.c_int32, _c.c_int32, _c.c_void_p, _c.c_int32, _c.c_int32, _c.c_double,
                                  _c.c_int32, _c.c_int32, _c.c_void_p, _c.c_size_t, _c.POINTER(_c.c_size_t)]),
+    "xa_scaled_size": (_c.c_int, [_c.c_int32, _c.c_int32, _c.c_double, _c.POINTER(_c.c_int32),
+                                  _c.POINTER(_c.c_int32)]),
+    "xa_plan_scales": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_size_t, _c.POINTER(_c.c_size_t)]),
+    "xa_scale_workspace_size": (_c.c_size_t, [_c.c_void_p]),
+    "xa_scale_sources": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_size_t,
+                                    _c.c_void_p]),
     "xa_simulate_workspace_size": (_c.c_size_t, [_c.c_void_p]),
-    "xa_simulate_views": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p,
+    "xa_simulate_views": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                      _c.c_void_p, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
     "xa_extract_workspace_size": (_c.c_size_t, [_c.c_void_p]),
     "xa_extract_orb": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
@@ -77,8 +89,8 @@ _SIGS = {
                                   _c.c_int32, _c.c_int32, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                   _c.c_void_p]),
     "xa_match_pair_workspace_size": (_c.c_size_t, [_c.c_void_p, _c.c_void_p]),
-    "xa_match_pair": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p,
-                                 _c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_int32, _c.c_int32,
+    "xa_match_pair": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                 _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_int32,
                                  _c.POINTER(_PairBuffers), _c.c_void_p, _c.c_size_t, _c.c_void_p]),
     "xa_pair_precision": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32,
                                      _c.c_int32, _c.c_int32, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_double,
@@ -182,21 +194,119 @@ class Plan:
         return arena[o:o + p * h].reshape(h, p)[:, :w]
 
 
-def plan_image(src_w: int, src_h: int, params: np.ndarray, n_levels: int = 8, level_scale: float = 1.2,
-               n_features: int = 1000, fast_threshold: int = 20) -> Plan:
-    params = np.ascontiguousarray(params, PARAMS_DTYPE)
-    n = ctypes.c_size_t(0)
-    st = lib().xa_plan_image(src_w, src_h, params.ctypes.data, len(params), n_levels, level_scale, n_features,
-                             fast_threshold, None, 0, ctypes.byref(n))
-    _check(st)
-    blob = np.zeros(n.value, np.uint8)
-    _check(lib().xa_plan_image(src_w, src_h, params.ctypes.data, len(params), n_levels, level_scale, n_features,
-                               fast_threshold, blob.ctypes.data, blob.size, ctypes.byref(n)))
+def _wrap_plan(blob: np.ndarray) -> Plan:
     h = np.frombuffer(blob, HEADER_DTYPE, 1)[0]
     views = np.frombuffer(blob, VIEW_DTYPE, int(h["n_views"]), int(h["off_views"]))
     levels = np.frombuffer(blob, LEVEL_DTYPE, int(h["n_views"]) * int(h["n_levels"]),
                            int(h["off_levels"])).reshape(int(h["n_views"]), int(h["n_levels"]))
     return Plan(blob, h, views, levels)
+
+
+def plan_views(sources: np.ndarray, view_source, params: np.ndarray, n_levels: int = 8, level_scale: float = 1.2,
+               n_features: int = 1000, fast_threshold: int = 20) -> Plan:
+    """Plan views of several sources (SOURCE_DTYPE array); view i simulates sources[view_source[i]]."""
+    sources = np.ascontiguousarray(sources, SOURCE_DTYPE)
+    vs = np.ascontiguousarray(view_source, np.int32)
+    params = np.ascontiguousarray(params, PARAMS_DTYPE)
+    assert len(vs) == len(params)
+    n = ctypes.c_size_t(0)
+    args = (sources.ctypes.data, len(sources), vs.ctypes.data, params.ctypes.data, len(params), n_levels, level_scale,
+            n_features, fast_threshold)
+    _check(lib().xa_plan_views(*args, None, 0, ctypes.byref(n)))
+    blob = np.zeros(n.value, np.uint8)
+    _check(lib().xa_plan_views(*args, blob.ctypes.data, blob.size, ctypes.byref(n)))
+    return _wrap_plan(blob)
+
+
+def plan_image(src_w: int, src_h: int, params: np.ndarray, n_levels: int = 8, level_scale: float = 1.2,
+               n_features: int = 1000, fast_threshold: int = 20, src_pitch: int | None = None) -> Plan:
+    """Plan views of one image stored at offset 0 of its buffer with the given row pitch."""
+    params = np.ascontiguousarray(params, PARAMS_DTYPE)
+    pitch = src_w if src_pitch is None else src_pitch
+    n = ctypes.c_size_t(0)
+    args = (src_w, src_h, pitch, params.ctypes.data, len(params), n_levels, level_scale, n_features, fast_threshold)
+    _check(lib().xa_plan_image(*args, None, 0, ctypes.byref(n)))
+    blob = np.zeros(n.value, np.uint8)
+    _check(lib().xa_plan_image(*args, blob.ctypes.data, blob.size, ctypes.byref(n)))
+    return _wrap_plan(blob)
+
+
+SCALE_JOB_DTYPE = np.dtype([("src", SOURCE_DTYPE), ("dst", SOURCE_DTYPE), ("s", "f8")])
+
+
+def scaled_size(w: int, h: int, s: float):
+    ow, oh = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib().xa_scaled_size(w, h, s, ctypes.byref(ow), ctypes.byref(oh)))
+    return ow.value, oh.value
+
+
+@dataclass
+class ScalePlan:
+    blob: np.ndarray
+    jobs: np.ndarray
+    _dev: object = None
+
+    def host_ptr(self) -> int:
+        return self.blob.ctypes.data
+
+    def device(self, device="cuda"):
+        import torch
+        if self._dev is None:
+            self._dev = torch.from_numpy(self.blob.copy()).to(device)
+        return self._dev
+
+
+def plan_scales(jobs: np.ndarray) -> ScalePlan:
+    jobs = np.ascontiguousarray(jobs, SCALE_JOB_DTYPE)
+    n = ctypes.c_size_t(0)
+    _check(lib().xa_plan_scales(jobs.ctypes.data, len(jobs), None, 0, ctypes.byref(n)))
+    blob = np.zeros(n.value, np.uint8)
+    _check(lib().xa_plan_scales(jobs.ctypes.data, len(jobs), blob.ctypes.data, blob.size, ctypes.byref(n)))
+    return ScalePlan(blob, jobs)
+
+
+class SourceArena:
+    """Host-side layout of a sources buffer: images appended at 256-byte aligned offsets with
+    16-byte aligned pitches, plus scale-stage outputs."""
+
+    def __init__(self):
+        self.descs = []
+        self.size = 0
+
+    def add(self, width: int, height: int, scale: float = 1.0) -> int:
+        pitch = (width + 15) // 16 * 16
+        off = (self.size + 255) // 256 * 256
+        self.descs.append((width, height, pitch, 0, off, scale))
+        self.size = off + pitch * height
+        return len(self.descs) - 1
+
+    def table(self) -> np.ndarray:
+        return np.array(self.descs, SOURCE_DTYPE)
+
+    def pack(self, images: dict) -> np.ndarray:
+        """Host buffer with the given {index: uint8 image} written at their offsets."""
+        buf = np.zeros(max(self.size, 1), np.uint8)
+        for i, img in images.items():
+            w, h, p, _, o, _ = self.descs[i]
+            buf[o:o + p * h].reshape(h, p)[:, :w] = img
+        return buf
+
+    def view(self, buf: np.ndarray, i: int) -> np.ndarray:
+        w, h, p, _, o, _ = self.descs[i]
+        return buf[o:o + p * h].reshape(h, p)[:, :w]
+
+
+def scale_sources(splan: ScalePlan, sources, values: bool = False, ws=None):
+    """Run the scale stage in place on a device sources buffer; optional fp32 values (same offsets)."""
+    import torch
+    dev = sources.device
+    vals = torch.zeros(sources.numel(), dtype=torch.float32, device=dev) if values else None
+    need = lib().xa_scale_workspace_size(splan.host_ptr())
+    if ws is None:
+        ws = _empty(need, dev)
+    _check(lib().xa_scale_sources(splan.host_ptr(), _ptr(splan.device(dev)), _ptr(sources), _ptr(vals), _ptr(ws),
+                                  ws.numel(), _stream()))
+    return vals
 
 
 # ---------------------------------------------------------------- device calls
@@ -220,14 +330,14 @@ def simulate_views(plan: Plan, src, values: bool = False, ws=None):
     """Returns (arena u8, mask u8[, values f32]) device tensors of arena_bytes elements."""
     import torch
     dev = src.device
-    assert src.dtype == torch.uint8 and src.dim() == 2 and src.is_contiguous()
+    assert src.dtype == torch.uint8 and src.is_contiguous()
     arena = torch.zeros(plan.arena_bytes, dtype=torch.uint8, device=dev)
     mask = torch.zeros(plan.arena_bytes, dtype=torch.uint8, device=dev)
     vals = torch.zeros(plan.arena_bytes, dtype=torch.float32, device=dev) if values else None
     need = lib().xa_simulate_workspace_size(plan.host_ptr())
     if ws is None:
         ws = _empty(need, dev)
-    _check(lib().xa_simulate_views(plan.host_ptr(), _ptr(plan.device(dev)), _ptr(src), src.stride(0), _ptr(arena),
+    _check(lib().xa_simulate_views(plan.host_ptr(), _ptr(plan.device(dev)), _ptr(src), _ptr(arena),
                                    _ptr(mask), _ptr(vals), _ptr(ws), ws.numel(), _stream()))
     return (arena, mask, vals) if values else (arena, mask)
 
@@ -284,8 +394,8 @@ class PairRunner:
         self.dev_b = plan_b.device(self.device)
 
     def run(self, A, B, pattern, ratio_num: int = 4, ratio_den: int = 5):
-        _check(lib().xa_match_pair(self.plan_a.host_ptr(), _ptr(self.dev_a), _ptr(A), A.stride(0),
-                                   self.plan_b.host_ptr(), _ptr(self.dev_b), _ptr(B), B.stride(0), _ptr(pattern),
+        _check(lib().xa_match_pair(self.plan_a.host_ptr(), _ptr(self.dev_a), _ptr(A),
+                                   self.plan_b.host_ptr(), _ptr(self.dev_b), _ptr(B), _ptr(pattern),
                                    ratio_num, ratio_den, ctypes.byref(self.bufs), _ptr(self.ws), self.ws.numel(),
                                    _stream()))
 
@@ -338,7 +448,7 @@ class StageRunner:
     def simulate(self, key: str, img):
         s = self.side[key]
         p = s["plan"]
-        _check(lib().xa_simulate_views(p.host_ptr(), _ptr(s["dev"]), _ptr(img), img.stride(0), _ptr(s["arena"]),
+        _check(lib().xa_simulate_views(p.host_ptr(), _ptr(s["dev"]), _ptr(img), _ptr(s["arena"]),
                                        _ptr(s["mask"]), None, _ptr(s["sim_ws"]), s["sim_ws"].numel(), _stream()))
 
     def extract(self, key: str, pattern):

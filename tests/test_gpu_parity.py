@@ -92,7 +92,7 @@ def _check_simulate(img, rows, plan, dev, label):
 
 def test_simulate_tiny_a(dev, tiny):
     say("case: simulate tiny A 256x256, 12 grid views + 2 general maps")
-    rows, params = _params(2, [(1.7, 0.4, 0.3, 0.8), (2.5, 2.9, -1.2, 1.3)])
+    rows, params = _params(2, [(1.7, 0.4, 0.3, 1.2), (2.5, 2.9, -1.2, 1.3)])
     plan = X.plan_image(256, 256, params, 3, 1.2, 300, 20)
     _check_simulate(tiny.A, rows, plan, dev, "tiny A")
 
@@ -297,3 +297,83 @@ def test_single_image_mode(dev, tiny):
     say(f"[single-image] best {best.tolist()} precision {pr.tolist()}")
     assert best[2] == 0 and best[3] == pr[1] and pr[1] > 20
     assert pr[0] / pr[1] >= 0.8
+
+
+# ---------------------------------------------------------------------------- scale stage
+
+def _scale_case(img, scales, dev, label):
+    arena = X.SourceArena()
+    si = arena.add(img.shape[1], img.shape[0])
+    jobs = []
+    outs = []
+    for s in scales:
+        w, h = X.scaled_size(img.shape[1], img.shape[0], s)
+        assert (w, h) == OP.scaled_size(img.shape[1], img.shape[0], s)
+        di = arena.add(w, h, s)
+        jobs.append((arena.descs[si], arena.descs[di], s))
+        outs.append(di)
+    splan = X.plan_scales(np.array(jobs, X.SCALE_JOB_DTYPE))
+    buf = torch.from_numpy(arena.pack({si: img})).to(dev)
+    vals = X.scale_sources(splan, buf, values=True)
+    torch.cuda.synchronize()
+    hb, hv = buf.cpu().numpy(), vals.cpu().numpy()
+    worst, bad, npx = 0.0, 0, 0
+    for s, di in zip(scales, outs):
+        V, U = OS.scale_image(img, s)
+        gu = arena.view(hb, di)
+        gv = arena.view(hv, di)
+        err = np.abs(gv.astype(np.float64) - V)
+        worst = max(worst, float(err.max()))
+        du = np.abs(gu.astype(np.int64) - U.astype(np.int64))
+        assert du.max() <= 1, (label, s)
+        bad += int((du > 0).sum())
+        npx += du.size
+    say(f"[{label}] scale stage max |err| = {worst:.3e} gray; u8 mismatches {bad}/{npx}")
+    assert worst <= WARP_TOL and bad <= max(1, 1e-4 * npx)
+
+
+def test_scale_stage_parity(dev, tiny):
+    say("case: scale stage s in {0.5, 0.25, 0.8, 1.5} on the tiny A and B images")
+    _scale_case(tiny.A, [0.5, 0.25, 0.8, 1.5], dev, "scale A")
+    _scale_case(np.ascontiguousarray(tiny.B), [0.5, 0.25], dev, "scale B (odd sizes)")
+
+
+def test_views_of_scaled_and_multiple_sources(dev, tiny):
+    """One plan over two sources (the image and the oracle's scale-0.5 image): simulate and
+    ORB are checked view by view, and keypoints map back to original-image coordinates."""
+    say("case: multi-source plan (original + scale 0.5), simulate + extract + back-map")
+    V5, U5 = OS.scale_image(tiny.A, 0.5)
+    arena = X.SourceArena()
+    s0 = arena.add(256, 256)
+    s1 = arena.add(U5.shape[1], U5.shape[0], 0.5)
+    grid = OP.sampling_grid(2)
+    rows = [(t, f, 0.0, 1.0) for t, f in grid]
+    params = X.make_params(rows + rows)
+    vsrc = [s0] * len(rows) + [s1] * len(rows)
+    plan = X.plan_views(arena.table(), vsrc, params, 3, 1.2, 300, 20)
+    buf = torch.from_numpy(arena.pack({s0: tiny.A, s1: U5})).to(dev)
+    ar, mk, vals = X.simulate_views(plan, buf, values=True)
+    torch.cuda.synchronize()
+    mk, vals = mk.cpu().numpy(), vals.cpu().numpy()
+    quotas = OP.level_quotas(300, 3)
+    cases = [(r, tiny.A, 1.0) for r in rows] + [(r, U5, 0.5) for r in rows]
+    ref = []
+    for i, (r, src_img, sc) in enumerate(cases):
+        v = OP.plan_view(src_img.shape[1], src_img.shape[0], *r)
+        V, M, U = OS.simulate_view(src_img, v)
+        gm = plan.level_image(mk, i, 0).astype(bool)
+        both = gm & M
+        assert np.abs(plan.level_image(vals, i, 0)[both] - V[both]).max() <= WARP_TOL
+        ref.append((v, M, U, sc))
+    # ORB on the oracle's views of both sources, through the same multi-source plan
+    kp, desc, count, _, _ = _gpu_extract_from_views(plan, [r[2] for r in ref], [r[1] for r in ref],
+                                                   synth.brief_pattern(), dev)
+    for i, (v, M, U, sc) in enumerate(ref):
+        dims = OP.level_dims(v.width, v.height, 3)
+        f = OO.extract_view(U, M, dims, quotas, 20, synth.brief_pattern())
+        n = len(f["x"])
+        assert count[i] == n and np.array_equal(desc[i][:n], f["desc"])
+        xs, ys = OPL.keypoints_to_source(f, v, OPL.OrbOptions(n_levels=3, n_features=300))
+        xs, ys = (xs + 0.5) / sc - 0.5, (ys + 0.5) / sc - 0.5
+        assert np.allclose(kp[i][:n]["xs"], xs, atol=1e-9) and np.allclose(kp[i][:n]["ys"], ys, atol=1e-9)
+    say("[multi-source] views and ORB exact on 24 views of two sources")

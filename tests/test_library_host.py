@@ -45,7 +45,7 @@ def test_sampling_grid_equals_oracle(L):
 @pytest.mark.parametrize("w,h,n_tilt", [(256, 256, 2), (1024, 768, 5), (239, 286, 2), (97, 53, 7)])
 def test_plan_matches_oracle(L, w, h, n_tilt):
     grid = OP.sampling_grid(n_tilt)
-    rows = [(t, f, 0.0, 1.0) for t, f in grid] + [(1.7, 0.4, 0.3, 0.8), (2.5, 2.9, -1.2, 1.3)]
+    rows = [(t, f, 0.0, 1.0) for t, f in grid] + [(1.7, 0.4, 0.3, 1.4), (2.5, 2.9, -1.2, 1.3), (3.0, 1.1, 0.2, 4.0)]
     params = X.make_params(rows)
     N, Lv = 1000, 8
     p = X.plan_image(w, h, params, Lv, 1.2, N, 20)
@@ -86,7 +86,8 @@ def test_plan_matches_oracle(L, w, h, n_tilt):
 
 def test_plan_rejects_bad_arguments(L):
     good = X.make_params([(1.0, 0.0)])
-    for rows in ([(0.5, 0.0)], [(1.0, 0.0, 0.0, 0.0)], [(float("nan"), 0.0)], [(2.0, float("inf"))]):
+    for rows in ([(0.5, 0.0)], [(1.0, 0.0, 0.0, 0.0)], [(1.0, 0.0, 0.0, 0.5)], [(float("nan"), 0.0)],
+                 [(2.0, float("inf"))]):
         with pytest.raises(X.XAError) as e:
             X.plan_image(64, 64, X.make_params(rows))
         assert e.value.status == X.XA_EINVAL
@@ -121,7 +122,7 @@ def test_workspace_queries_and_bad_plan(L):
     assert L.xa_match_pair_workspace_size(p.host_ptr(), p.host_ptr()) > 4 * p.arena_bytes
     junk = np.zeros(256, np.uint8)
     assert L.xa_simulate_workspace_size(junk.ctypes.data) == 0
-    st = L.xa_simulate_views(junk.ctypes.data, None, None, 0, None, None, None, None, 0, None)
+    st = L.xa_simulate_views(junk.ctypes.data, None, None, None, None, None, None, 0, None)
     assert st == X.XA_EINVAL
 
 
@@ -130,7 +131,7 @@ def test_device_calls_validate_before_launch(L):
     p = X.plan_image(64, 64, X.sampling_grid(1), 2, 1.2, 100, 20)
     hp = p.host_ptr()
     # NULL device pointers
-    assert L.xa_simulate_views(hp, hp, None, 64, None, None, None, None, 0, None) == X.XA_EINVAL
+    assert L.xa_simulate_views(hp, hp, None, None, None, None, None, 0, None) == X.XA_EINVAL
     # too-small workspace (non-NULL dummy pointers are never dereferenced on the host)
     st = L.xa_extract_orb(hp, hp, 256, 256, 256, 256, 256, 256, 256, 0, None)
     assert st == X.XA_ECAPACITY

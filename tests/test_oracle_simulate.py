@@ -167,3 +167,52 @@ def test_blur_impulse_response_is_along_u(phi):
 def test_quantize_rounds_half_to_even_and_clamps():
     got = S.quantize(np.array([0.5, 1.5, 2.5, -3.0, 300.0, 254.5, 7.49]))
     assert got.tolist() == [0, 2, 2, 0, 255, 254, 7]
+
+
+# ---------------------------------------------------------------------------- scale stage
+
+def test_scale_identity_and_constant():
+    A = _img(11, 30, 41)
+    V, U = S.scale_image(A, 1.0)
+    assert np.array_equal(U, A)
+    for s in (0.5, 0.25, 0.8, 1.5):
+        V, U = S.scale_image(np.full((40, 52), 61, np.uint8), s)
+        assert np.abs(V - 61).max() < 1e-9 and U.shape == P.scaled_size(52, 40, s)[::-1]
+
+
+def test_scale_half_on_block_constant_image():
+    """s = 1/2 of an image that is constant on 2x2 blocks: output pixel q samples the source
+    at 2q + 1/2, between the two pixels of its block; interior values reproduce the blocks up
+    to the anti-alias blur, which is exact on constants."""
+    rng = np.random.default_rng(12)
+    blocks = rng.integers(60, 200, (12, 14)).astype(np.float64)
+    A = np.kron(blocks, np.ones((2, 2))).astype(np.uint8)
+    # smooth variation only: the blur and the interpolation reproduce a linear ramp exactly
+    yy, xx = np.mgrid[0:24, 0:28].astype(np.float64)
+    ramp = 2.0 * xx + 3.0 * yy + 10.0
+    V, U = S.scale_image(ramp.astype(np.uint8), 0.5)
+    qy, qx = np.mgrid[0:12, 0:14].astype(np.float64)
+    exp = 2.0 * (2 * qx + 0.5) + 3.0 * (2 * qy + 0.5) + 10.0
+    inner = (slice(4, 8), slice(4, 10))
+    assert np.abs(V[inner] - exp[inner]).max() < 0.35     # Lanczos-4 ripple on a ramp + blur rounding
+    assert V.shape == (12, 14)
+
+
+def test_scale_maps_points_consistently():
+    """A bright square moves to the scaled position: centroid of the scaled image = (c + 1/2) s - 1/2."""
+    A = np.zeros((80, 80), np.uint8)
+    A[30:40, 44:54] = 200
+    for s in (0.5, 0.25, 2.0):
+        V, U = S.scale_image(A, s)
+        yy, xx = np.mgrid[0:V.shape[0], 0:V.shape[1]].astype(np.float64)
+        w = np.clip(V, 0, None)
+        cx, cy = (w * xx).sum() / w.sum(), (w * yy).sum() / w.sum()
+        assert abs(cx - ((48.5 + 0.5) * s - 0.5)) < 0.05 * max(1, s) + 0.02
+        assert abs(cy - ((34.5 + 0.5) * s - 0.5)) < 0.05 * max(1, s) + 0.02
+
+
+def test_sigma_follows_net_compression():
+    v = P.plan_view(64, 64, 4.0, 0.3, s=2.0)
+    assert v.sigma == pytest.approx(0.8 * math.sqrt(3.0))
+    assert P.plan_view(64, 64, 2.0, 0.3, s=2.0).sigma == 0.0
+    assert P.plan_view(64, 64, 1.0, 0.0, s=3.0).sigma == 0.0
