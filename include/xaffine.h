@@ -268,6 +268,30 @@ xa_status xa_match_views(const uint8_t* d_desc_a, const int32_t* d_count_a, int3
                          xa_match* d_matches, int32_t* d_pair_count, int32_t* d_best,
                          hipStream_t stream);
 
+/* Matching over groups of view pairs, for many image pairs in one launch: group
+ * g matches query views [a0, a0 + na) against train views [b0, b0 + nb) of one
+ * descriptor set (d_desc [n_views][n_features][32], d_count [n_views]) and
+ * writes its na * nb view pairs from index pair_base on (pair pair_base + i * nb
+ * + j) of d_matches [P][n_features] and d_pair_count [P], P = the largest
+ * pair_base + na * nb; d_best [n_groups][4] = (i * nb + j, i, j, count) of the
+ * group's best pair, lowest index on ties, (-1, -1, -1, 0) for an empty group.
+ * The groups' pair ranges must not overlap and their views must lie inside the
+ * descriptor set (n_views): xa_plan_matches and xa_match_groups reject plans
+ * that break either rule with XA_EINVAL, and xa_match_batch checks the views
+ * against its view plan.  queries_per_lane (0 = choose from n_features, else 1,
+ * 2 or 4) selects the matcher variant the autotuner times.  Match plans are
+ * blobs like view plans (host and device copies). */
+typedef struct {
+    int32_t a0, na;
+    int32_t b0, nb;
+    int64_t pair_base;
+} xa_match_group;
+xa_status xa_plan_matches(const xa_match_group* groups, int32_t n_groups, int32_t n_features, int32_t queries_per_lane,
+                          void* blob, size_t blob_cap, size_t* blob_bytes);
+xa_status xa_match_groups(const void* mplan_host, const void* mplan_dev, const uint8_t* d_desc, const int32_t* d_count,
+                          int32_t n_views, int32_t ratio_num, int32_t ratio_den, xa_match* d_matches,
+                          int32_t* d_pair_count, int32_t* d_best, hipStream_t stream);
+
 /* The whole parameter-search path for one image pair: simulate both images,
  * extract ORB on every view, match all view pairs, pick the best pair.
  * Both plans must use the same n_features.  Workspace:
@@ -277,6 +301,34 @@ xa_status xa_match_pair(const void* plan_a_host, const void* plan_a_dev, const u
                         const void* plan_b_host, const void* plan_b_dev, const uint8_t* d_b,
                         const int8_t* d_pattern, int32_t ratio_num, int32_t ratio_den,
                         const xa_pair_buffers* out, void* d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* Many image pairs at once: the scale stage (optional: splan may be NULL), the
+ * simulation and ORB of every view of every image (one view plan over all
+ * sources), and the group matching of every image pair (one match plan), as
+ * one sequence of batched launches on `stream` (each stage is a single launch
+ * over all images; blocks find their work through the plans' prefix tables).
+ * Outputs: kp/desc/count for the view plan's views ([n_views][n_features]...),
+ * matches/pair_count for the match plan's view pairs, best [n_groups][4].
+ * xa_match_batch_capture records the same sequence into a HIP graph (on a
+ * private stream, nothing is executed) that xa_graph_launch replays on any
+ * stream; the graph keeps every pointer it was captured with.
+ * Workspace: xa_match_batch_workspace_size(splan_host, vplan_host). */
+typedef struct {
+    xa_keypoint* kp; uint8_t* desc; int32_t* count;
+    xa_match* matches; int32_t* pair_count; int32_t* best;
+} xa_batch_buffers;
+typedef struct xa_graph xa_graph;
+size_t xa_match_batch_workspace_size(const void* splan_host, const void* vplan_host);
+xa_status xa_match_batch(const void* splan_host, const void* splan_dev, const void* vplan_host, const void* vplan_dev,
+                         const void* mplan_host, const void* mplan_dev, uint8_t* d_sources, const int8_t* d_pattern,
+                         int32_t ratio_num, int32_t ratio_den, const xa_batch_buffers* out, void* d_ws,
+                         size_t ws_bytes, hipStream_t stream);
+xa_status xa_match_batch_capture(const void* splan_host, const void* splan_dev, const void* vplan_host,
+                                 const void* vplan_dev, const void* mplan_host, const void* mplan_dev,
+                                 uint8_t* d_sources, const int8_t* d_pattern, int32_t ratio_num, int32_t ratio_den,
+                                 const xa_batch_buffers* out, void* d_ws, size_t ws_bytes, xa_graph** graph);
+xa_status xa_graph_launch(xa_graph* graph, hipStream_t stream);
+xa_status xa_graph_destroy(xa_graph* graph);
 
 /* Precision of eqs. (5)-(6) for the best pair found by xa_match_views /
  * xa_match_pair: among its accepted matches (query q of view i of A, train

@@ -47,24 +47,39 @@ def extract_image(sims, views, opts: OrbOptions, pattern):
     return feats
 
 
-def keypoints_to_source(feat, view, opts: OrbOptions):
+def keypoints_to_source(feat, view, opts: OrbOptions, src_scale: float = 1.0):
+    """Keypoints -> coordinates of the original image (through the scale-stage factor)."""
     dims = P.level_dims(view.width, view.height, opts.n_levels, opts.scale)
     lw = np.array([d[0] for d in dims])
     lh = np.array([d[1] for d in dims])
     lv = feat["level"]
     x0, y0 = M.level_to_view(feat["x"], feat["y"], lw[lv], lh[lv], view.width, view.height)
-    return M.view_to_source(view, x0, y0)
+    xs, ys = M.view_to_source(view, x0, y0)
+    if src_scale != 1.0:
+        xs, ys = (xs + 0.5) / src_scale - 0.5, (ys + 0.5) / src_scale - 0.5
+    return xs, ys
 
 
-def match_pair(A, B, grid_a, grid_b, opts: OrbOptions, pattern):
+def simulate_and_extract(img, grid, opts: OrbOptions, pattern, scales=(1.0,)):
+    """Views of an image over the grid at every scale of the sampling group (Sec. III.B):
+    scale s != 1 goes through the scale stage first and its views use s = 1 in their map."""
+    views, sims, feats, vscale = [], [], [], []
+    for s in scales:
+        src = img if s == 1.0 else S.scale_image(img, s)[1]
+        vs = plan_image(src.shape[1], src.shape[0], grid)
+        sm = simulate_image(src, vs)
+        views += vs
+        sims += sm
+        feats += extract_image(sm, vs, opts, pattern)
+        vscale += [s] * len(vs)
+    return views, sims, feats, vscale
+
+
+def match_pair(A, B, grid_a, grid_b, opts: OrbOptions, pattern, scales_a=(1.0,), scales_b=(1.0,)):
     """Full path for one image pair.  Returns a dict with per-view features, the
-    pair counts, the best pair and its accepted matches in source coordinates."""
-    va = plan_image(A.shape[1], A.shape[0], grid_a)
-    vb = plan_image(B.shape[1], B.shape[0], grid_b)
-    sa = simulate_image(A, va)
-    sb = simulate_image(B, vb)
-    fa = extract_image(sa, va, opts, pattern)
-    fb = extract_image(sb, vb, opts, pattern)
+    pair counts, the best pair and its accepted matches in original-image coordinates."""
+    va, sa, fa, ka = simulate_and_extract(A, grid_a, opts, pattern, scales_a)
+    vb, sb, fb, kb = simulate_and_extract(B, grid_b, opts, pattern, scales_b)
     results, counts, best = M.match_views([f["desc"] for f in fa], [f["desc"] for f in fb],
                                           opts.ratio_num, opts.ratio_den)
     k, i, j, c = best
@@ -74,8 +89,8 @@ def match_pair(A, B, grid_a, grid_b, opts: OrbOptions, pattern):
         idx, d1, d2, acc = results[k]
         qa = np.flatnonzero(acc)
         tb = idx[qa]
-        xa, ya = keypoints_to_source(fa[i], va[i], opts)
-        xb, yb = keypoints_to_source(fb[j], vb[j], opts)
+        xa, ya = keypoints_to_source(fa[i], va[i], opts, ka[i])
+        xb, yb = keypoints_to_source(fb[j], vb[j], opts, kb[j])
         out["pa"] = np.stack([xa[qa], ya[qa]], axis=1)
         out["pb"] = np.stack([xb[tb], yb[tb]], axis=1)
     else:

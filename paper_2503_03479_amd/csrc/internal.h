@@ -85,6 +85,24 @@ xa_status launch_simulate(const PlanView& ph, const PlanView& pd, const uint8_t*
 xa_status launch_extract(const PlanView& ph, const PlanView& pd, uint8_t* arena, uint8_t* mask,
                          const int8_t* pattern, xa_keypoint* kp, uint8_t* desc, int32_t* count,
                          uint8_t* ws, hipStream_t st);
+xa_status launch_scale(const void* splan_host, const void* splan_dev, uint8_t* d_sources, float* d_values,
+                       void* d_ws, hipStream_t stream);
+bool is_scale_plan(const void* blob);
+
+constexpr uint32_t kMatchMagic = 0x5841464Du;   // "XAFM"
+struct MatchPlanHeader {
+    uint32_t magic;
+    int32_t n_groups, n_features, q, views_needed;  // views_needed = max over groups of a0 + na, b0 + nb
+    long long total_blocks, total_pairs;
+    int64_t off_groups, off_prefix, total_bytes;
+};
+struct MatchPlanView {
+    const MatchPlanHeader* h = nullptr;
+};
+xa_status match_plan_view(const void* blob, MatchPlanView* out);
+xa_status launch_match_plan(const void* mplan_host, const void* mplan_dev, const uint8_t* desc, const int32_t* count,
+                            int32_t num, int32_t den, xa_match* matches, int32_t* pair_count, int32_t* best,
+                            hipStream_t st);
 xa_status launch_match(const uint8_t* desc_a, const int32_t* count_a, int32_t n_a,
                        const uint8_t* desc_b, const int32_t* count_b, int32_t n_b, int32_t n_features,
                        int32_t num, int32_t den, xa_match* matches, int32_t* pair_count, int32_t* best,

@@ -5,6 +5,10 @@
 // read as wave-uniform broadcasts.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
 #include "internal.h"
 
 namespace xa {
@@ -33,22 +37,47 @@ __global__ void k_fill_i32(int32_t* p, int n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
-// Block = one view pair x (kMatchThreads * Q) queries.  Each lane keeps Q queries and,
-// per query, the two smallest packed keys (d << 13 | train index): the smallest key gives
-// d1 and the smallest index attaining it, the second smallest gives d2 over the others.
+__device__ __forceinline__ int find_segment_wave(const int32_t* __restrict__ prefix, int n, int b) {
+    const int lane = threadIdx.x & 63;
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int step = (hi - lo + 63) >> 6;
+        const int p = lo + lane * step;
+        const bool le = p < hi && prefix[p] <= b;
+        const unsigned long long bal = __ballot(le);
+        const int k = 63 - __clzll(bal);
+        lo = lo + k * step;
+        hi = min(hi, lo + step);
+    }
+    return lo;
+}
+
+// Block = one view pair x (kMatchThreads * Q) queries.  A group is a cross product of query
+// views [a0, a0 + na) and train views [b0, b0 + nb); blocks map to (group, pair, query block)
+// through a prefix table (groups == nullptr: the single group `one`).  Each lane keeps Q
+// queries and, per query, the two smallest packed keys (d << 13 | train index): the smallest
+// key gives d1 and the smallest index attaining it, the second smallest gives d2 over the others.
 template <int Q>
-__global__ void __launch_bounds__(kMatchThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) k_match(const uint32_t* __restrict__ desc_a,
-                                                         const int32_t* __restrict__ count_a,
-                                                         const uint32_t* __restrict__ desc_b,
-                                                         const int32_t* __restrict__ count_b, int n_b, int N,
-                                                         int num, int den, xa_match* __restrict__ matches,
-                                                         int32_t* __restrict__ pair_count) {
+__global__ void __launch_bounds__(kMatchThreads) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_match(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ count_q, const uint32_t* __restrict__ desc_t,
+        const int32_t* __restrict__ count_t, const xa_match_group* __restrict__ groups,
+        const int32_t* __restrict__ block_prefix, int n_groups, xa_match_group one, int qblocks, int N, int num,
+        int den, xa_match* __restrict__ matches, int32_t* __restrict__ pair_count) {
     __shared__ uint4 tr[kMatchChunk * 2];
     __shared__ int s_acc;
-    const int pair = blockIdx.x;
-    const int i = pair / n_b, j = pair - (pair / n_b) * n_b;
-    const int nq = min(max(count_a[i], 0), N), nt = min(max(count_b[j], 0), N);
-    const int q0 = blockIdx.y * kMatchThreads * Q;
+    xa_match_group G = one;
+    int local = blockIdx.x;
+    if (groups) {
+        const int gi = find_segment_wave(block_prefix, n_groups, blockIdx.x);
+        G = groups[gi];
+        local = blockIdx.x - block_prefix[gi];
+    }
+    const int qb = local % qblocks, pr = local / qblocks;
+    const int i = pr / G.nb, j = pr - (pr / G.nb) * G.nb;
+    const long long pair = G.pair_base + pr;
+    const int va = G.a0 + i, vb = G.b0 + j;
+    const int nq = min(max(count_q[va], 0), N), nt = min(max(count_t[vb], 0), N);
+    const int q0 = qb * kMatchThreads * Q;
     if (q0 >= nq) return;
     uint32_t q[Q][8];
     uint32_t m1[Q], m2[Q];
@@ -56,7 +85,7 @@ __global__ void __launch_bounds__(kMatchThreads) __attribute__((amdgpu_waves_per
     for (int a = 0; a < Q; ++a) {
         const int qi = q0 + a * kMatchThreads + threadIdx.x;
         if (qi < nq) {
-            const uint4* p = reinterpret_cast<const uint4*>(desc_a + (size_t(i) * N + qi) * 8);
+            const uint4* p = reinterpret_cast<const uint4*>(desc_q + (size_t(va) * N + qi) * 8);
             const uint4 u0 = p[0], u1 = p[1];
             q[a][0] = u0.x; q[a][1] = u0.y; q[a][2] = u0.z; q[a][3] = u0.w;
             q[a][4] = u1.x; q[a][5] = u1.y; q[a][6] = u1.z; q[a][7] = u1.w;
@@ -67,7 +96,7 @@ __global__ void __launch_bounds__(kMatchThreads) __attribute__((amdgpu_waves_per
         m1[a] = 0xFFFFFFFFu;
         m2[a] = 0xFFFFFFFFu;
     }
-    const uint4* tb = reinterpret_cast<const uint4*>(desc_b + size_t(j) * N * 8);
+    const uint4* tb = reinterpret_cast<const uint4*>(desc_t + size_t(vb) * N * 8);
     for (int c0 = 0; c0 < nt; c0 += kMatchChunk) {
         const int cn = min(kMatchChunk, nt - c0);
         __syncthreads();
@@ -116,13 +145,18 @@ __global__ void __launch_bounds__(kMatchThreads) __attribute__((amdgpu_waves_per
     if (threadIdx.x == 0 && s_acc) atomicAdd(&pair_count[pair], s_acc);
 }
 
-// Argmax of the pair counts, lowest pair index on ties: max over (count << 32 | ~pair).
-__global__ void __launch_bounds__(1024) k_best(const int32_t* __restrict__ pair_count, int n_pairs, int n_b,
+// Per group: argmax of the pair counts, lowest pair index on ties, as the max over
+// (count << 32 | ~local pair); best[4 g ..] = local pair, i, j, count.
+__global__ void __launch_bounds__(1024) k_best(const int32_t* __restrict__ pair_count,
+                                               const xa_match_group* __restrict__ groups, xa_match_group one,
                                                int32_t* __restrict__ best) {
     __shared__ unsigned long long s[16];
+    const xa_match_group G = groups ? groups[blockIdx.x] : one;
+    const int n_pairs = G.na * G.nb;
     unsigned long long key = 0;
     for (int p = threadIdx.x; p < n_pairs; p += blockDim.x) {
-        const unsigned long long k = ((unsigned long long)(uint32_t)pair_count[p] << 32) | (0xFFFFFFFFu - uint32_t(p));
+        const unsigned long long k =
+            ((unsigned long long)(uint32_t)pair_count[G.pair_base + p] << 32) | (0xFFFFFFFFu - uint32_t(p));
         key = key > k ? key : k;
     }
 #pragma unroll
@@ -135,11 +169,17 @@ __global__ void __launch_bounds__(1024) k_best(const int32_t* __restrict__ pair_
     if (threadIdx.x == 0) {
         unsigned long long m = 0;
         for (int w = 0; w < int(blockDim.x >> 6); ++w) m = m > s[w] ? m : s[w];
-        const int p = int(0xFFFFFFFFu - uint32_t(m & 0xFFFFFFFFull));
-        best[0] = p;
-        best[1] = p / n_b;
-        best[2] = p % n_b;
-        best[3] = int(m >> 32);
+        int32_t* b = best + 4 * size_t(blockIdx.x);
+        if (n_pairs > 0) {
+            const int p = int(0xFFFFFFFFu - uint32_t(m & 0xFFFFFFFFull));
+            b[0] = p;
+            b[1] = p / G.nb;
+            b[2] = p % G.nb;
+            b[3] = int(m >> 32);
+        } else {  // no view pairs: no best pair
+            b[0] = b[1] = b[2] = -1;
+            b[3] = 0;
+        }
     }
 }
 
@@ -181,30 +221,66 @@ __global__ void __launch_bounds__(256) k_precision(const xa_keypoint* __restrict
 
 }  // namespace
 
-xa_status launch_match(const uint8_t* desc_a, const int32_t* count_a, int32_t n_a, const uint8_t* desc_b,
-                       const int32_t* count_b, int32_t n_b, int32_t N, int32_t num, int32_t den, xa_match* matches,
-                       int32_t* pair_count, int32_t* best, hipStream_t st) {
-    const int n_pairs = n_a * n_b;
-    hipLaunchKernelGGL(k_fill_i32, dim3((n_pairs + 255) / 256), dim3(256), 0, st, pair_count, n_pairs, 0);
-    const uint32_t* da = reinterpret_cast<const uint32_t*>(desc_a);
-    const uint32_t* db = reinterpret_cast<const uint32_t*>(desc_b);
-    // Q queries per lane: 4 amortises each LDS broadcast of a train descriptor over 4 comparisons;
-    // fewer for small N so that padding lanes do not dominate
-    if (N > 2 * kMatchThreads) {
-        const int gy = (N + 4 * kMatchThreads - 1) / (4 * kMatchThreads);
-        hipLaunchKernelGGL(k_match<4>, dim3(n_pairs, gy), dim3(kMatchThreads), 0, st, da, count_a, db, count_b, n_b, N,
-                           num, den, matches, pair_count);
-    } else if (N > kMatchThreads) {
-        hipLaunchKernelGGL(k_match<2>, dim3(n_pairs, 1), dim3(kMatchThreads), 0, st, da, count_a, db, count_b, n_b, N,
-                           num, den, matches, pair_count);
-    } else {
-        hipLaunchKernelGGL(k_match<1>, dim3(n_pairs, 1), dim3(kMatchThreads), 0, st, da, count_a, db, count_b, n_b, N,
-                           num, den, matches, pair_count);
+static int pick_q(int N) { return N > 2 * kMatchThreads ? 4 : (N > kMatchThreads ? 2 : 1); }
+
+xa_status launch_match_any(const uint8_t* desc_q, const int32_t* count_q, const uint8_t* desc_t,
+                           const int32_t* count_t, const xa_match_group* groups_dev, const int32_t* prefix_dev,
+                           int n_groups, const xa_match_group& one, long long total_pairs, long long total_blocks,
+                           int N, int Q, int num, int den, xa_match* matches, int32_t* pair_count, int32_t* best,
+                           hipStream_t st) {
+    if (total_blocks > INT32_MAX || total_pairs > INT32_MAX) return fail(XA_EUNSUPPORTED, "too many view pairs");
+    if (total_pairs > 0)
+        hipLaunchKernelGGL(k_fill_i32, dim3(unsigned((total_pairs + 255) / 256)), dim3(256), 0, st, pair_count,
+                           int(total_pairs), 0);
+    const uint32_t* dq = reinterpret_cast<const uint32_t*>(desc_q);
+    const uint32_t* dt = reinterpret_cast<const uint32_t*>(desc_t);
+    const int qblocks = (N + kMatchThreads * Q - 1) / (kMatchThreads * Q);
+    if (total_blocks > 0) {
+        if (Q == 4)
+            hipLaunchKernelGGL(k_match<4>, dim3(unsigned(total_blocks)), dim3(kMatchThreads), 0, st, dq, count_q, dt,
+                               count_t, groups_dev, prefix_dev, n_groups, one, qblocks, N, num, den, matches, pair_count);
+        else if (Q == 2)
+            hipLaunchKernelGGL(k_match<2>, dim3(unsigned(total_blocks)), dim3(kMatchThreads), 0, st, dq, count_q, dt,
+                               count_t, groups_dev, prefix_dev, n_groups, one, qblocks, N, num, den, matches, pair_count);
+        else
+            hipLaunchKernelGGL(k_match<1>, dim3(unsigned(total_blocks)), dim3(kMatchThreads), 0, st, dq, count_q, dt,
+                               count_t, groups_dev, prefix_dev, n_groups, one, qblocks, N, num, den, matches, pair_count);
     }
-    hipLaunchKernelGGL(k_best, dim3(1), dim3(1024), 0, st, pair_count, n_pairs, n_b, best);
+    hipLaunchKernelGGL(k_best, dim3(groups_dev ? n_groups : 1), dim3(1024), 0, st, pair_count, groups_dev, one, best);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "match launch");
     return XA_OK;
+}
+
+xa_status launch_match(const uint8_t* desc_a, const int32_t* count_a, int32_t n_a, const uint8_t* desc_b,
+                       const int32_t* count_b, int32_t n_b, int32_t N, int32_t num, int32_t den, xa_match* matches,
+                       int32_t* pair_count, int32_t* best, hipStream_t st) {
+    const int Q = pick_q(N);
+    const int qblocks = (N + kMatchThreads * Q - 1) / (kMatchThreads * Q);
+    const xa_match_group one{0, n_a, 0, n_b, 0};
+    return launch_match_any(desc_a, count_a, desc_b, count_b, nullptr, nullptr, 1, one, (long long)n_a * n_b,
+                            (long long)n_a * n_b * qblocks, N, Q, num, den, matches, pair_count, best, st);
+}
+
+// ------------------------------------------------------------------ match plans
+
+xa_status match_plan_view(const void* blob, MatchPlanView* out) {
+    if (!blob) return fail(XA_EINVAL, "match plan is NULL");
+    const auto* h = static_cast<const MatchPlanHeader*>(blob);
+    if (h->magic != kMatchMagic) return fail(XA_EINVAL, "not a match plan");
+    out->h = h;
+    return XA_OK;
+}
+
+xa_status launch_match_plan(const void* mplan_host, const void* mplan_dev, const uint8_t* desc, const int32_t* count,
+                            int32_t num, int32_t den, xa_match* matches, int32_t* pair_count, int32_t* best,
+                            hipStream_t st) {
+    const auto* h = static_cast<const MatchPlanHeader*>(mplan_host);
+    const char* d = static_cast<const char*>(mplan_dev);
+    const xa_match_group one{0, 0, 0, 0, 0};
+    return launch_match_any(desc, count, desc, count, reinterpret_cast<const xa_match_group*>(d + h->off_groups),
+                            reinterpret_cast<const int32_t*>(d + h->off_prefix), h->n_groups, one, h->total_pairs,
+                            h->total_blocks, h->n_features, h->q, num, den, matches, pair_count, best, st);
 }
 
 }  // namespace xa
@@ -243,4 +319,75 @@ extern "C" xa_status xa_pair_precision(const xa_keypoint* d_kp_a, const xa_keypo
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "precision launch");
     return ok();
+}
+
+extern "C" xa_status xa_plan_matches(const xa_match_group* groups, int32_t n_groups, int32_t n_features,
+                                     int32_t queries_per_lane, void* blob, size_t blob_cap, size_t* blob_bytes) {
+    if (!blob_bytes || !groups || n_groups < 1) return fail(XA_EINVAL, "need at least one group");
+    if (n_features < 1 || n_features > XA_MAX_FEATURES) return fail(XA_EUNSUPPORTED, "n_features out of range");
+    const int Q = queries_per_lane == 0 ? pick_q(n_features) : queries_per_lane;
+    if (Q != 1 && Q != 2 && Q != 4) return fail(XA_EINVAL, "queries_per_lane must be 0 (auto), 1, 2 or 4");
+    const int qblocks = (n_features + kMatchThreads * Q - 1) / (kMatchThreads * Q);
+    std::vector<int32_t> prefix(n_groups + 1, 0);
+    long long blocks = 0, pairs = 0, views = 0;
+    for (int g = 0; g < n_groups; ++g) {
+        const xa_match_group& G = groups[g];
+        if (G.na < 0 || G.nb < 0 || G.a0 < 0 || G.b0 < 0 || G.pair_base < 0)
+            return fail(XA_EINVAL, "group %d: negative field", g);
+        views = std::max(views, std::max((long long)G.a0 + G.na, (long long)G.b0 + G.nb));
+        if (views > INT32_MAX) return fail(XA_EINVAL, "group %d: view index overflow", g);
+        prefix[g] = int32_t(blocks);
+        blocks += (long long)G.na * G.nb * qblocks;
+        pairs = std::max(pairs, (long long)G.pair_base + (long long)G.na * G.nb);
+        if (blocks > INT32_MAX / 2) return fail(XA_EUNSUPPORTED, "too many view pairs for one launch");
+    }
+    prefix[n_groups] = int32_t(blocks);
+    {   // disjoint pair ranges: no two groups write the same view pair
+        std::vector<std::pair<long long, long long>> r;
+        for (int g = 0; g < n_groups; ++g)
+            if (groups[g].na > 0 && groups[g].nb > 0)
+                r.emplace_back(groups[g].pair_base, groups[g].pair_base + (long long)groups[g].na * groups[g].nb);
+        std::sort(r.begin(), r.end());
+        for (size_t i = 1; i < r.size(); ++i)
+            if (r[i].first < r[i - 1].second) return fail(XA_EINVAL, "groups write overlapping pair ranges");
+    }
+    MatchPlanHeader h{};
+    h.magic = kMatchMagic;
+    h.n_groups = n_groups;
+    h.n_features = n_features;
+    h.q = Q;
+    h.views_needed = int32_t(views);
+    h.total_blocks = blocks;
+    h.total_pairs = pairs;
+    size_t o = align_up(sizeof(h), 64);
+    h.off_groups = int64_t(o); o = align_up(o + sizeof(xa_match_group) * n_groups, 64);
+    h.off_prefix = int64_t(o); o = align_up(o + 4 * prefix.size(), 64);
+    h.total_bytes = int64_t(o);
+    *blob_bytes = o;
+    if (!blob) return ok();
+    if (blob_cap < o) return fail(XA_ECAPACITY, "match plan needs %zu bytes, buffer has %zu", o, blob_cap);
+    char* b = static_cast<char*>(blob);
+    std::memset(b, 0, o);
+    std::memcpy(b, &h, sizeof(h));
+    std::memcpy(b + h.off_groups, groups, sizeof(xa_match_group) * n_groups);
+    std::memcpy(b + h.off_prefix, prefix.data(), 4 * prefix.size());
+    return ok();
+}
+
+extern "C" xa_status xa_match_groups(const void* mplan_host, const void* mplan_dev, const uint8_t* d_desc,
+                                     const int32_t* d_count, int32_t n_views, int32_t ratio_num, int32_t ratio_den,
+                                     xa_match* d_matches, int32_t* d_pair_count, int32_t* d_best, hipStream_t stream) {
+    MatchPlanView mv;
+    xa_status s = match_plan_view(mplan_host, &mv);
+    if (s != XA_OK) return s;
+    if (mv.h->views_needed > n_views)
+        return fail(XA_EINVAL, "match plan reads %d views, descriptor set has %d", mv.h->views_needed, n_views);
+    if (!mplan_dev || !d_desc || !d_count || !d_matches || !d_pair_count || !d_best)
+        return fail(XA_EINVAL, "NULL device pointer");
+    if (reinterpret_cast<uintptr_t>(d_desc) % 16) return fail(XA_EINVAL, "descriptors must be 16-byte aligned");
+    if (ratio_num < 0 || ratio_den < 1 || ratio_num > (1 << 20) || ratio_den > (1 << 20))
+        return fail(XA_EINVAL, "ratio must be num/den with 0 <= num, 1 <= den <= 2^20");
+    s = launch_match_plan(mplan_host, mplan_dev, d_desc, d_count, ratio_num, ratio_den, d_matches, d_pair_count,
+                          d_best, stream);
+    return s == XA_OK ? ok() : s;
 }

@@ -3,6 +3,8 @@
 // the best one, as one asynchronous sequence of launches on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <new>
+
 #include "internal.h"
 
 namespace xa {
@@ -74,4 +76,163 @@ extern "C" xa_status xa_match_pair(const void* plan_a_host, const void* plan_a_d
     s = launch_match(out->desc_a, out->count_a, ha.h->n_views, out->desc_b, out->count_b, hb.h->n_views,
                      ha.h->n_features, ratio_num, ratio_den, out->matches, out->pair_count, out->best, stream);
     return s == XA_OK ? ok() : s;
+}
+
+// ------------------------------------------------------------------ batches
+
+namespace xa {
+namespace {
+
+struct BatchWs {
+    size_t scale, arena, mask, sim, ext, total;
+};
+
+BatchWs batch_layout(const void* splan_host, const xa_plan_header* h) {
+    BatchWs w{};
+    size_t o = 0;
+    w.scale = o; o = align_up(o + (splan_host ? xa_scale_workspace_size(splan_host) : 0));
+    w.arena = o; o = align_up(o + size_t(h->arena_bytes));
+    w.mask = o;  o = align_up(o + size_t(h->arena_bytes));
+    w.sim = o;   o = align_up(o + simulate_ws_bytes(h));
+    w.ext = o;   o = align_up(o + extract_ws_layout(h).total);
+    w.total = o;
+    return w;
+}
+
+struct BatchArgs {
+    const void *splan_host, *splan_dev, *vplan_host, *vplan_dev, *mplan_host, *mplan_dev;
+    uint8_t* sources;
+    const int8_t* pattern;
+    int32_t num, den;
+    xa_batch_buffers out;
+    uint8_t* ws;
+    size_t ws_bytes;
+};
+
+xa_status batch_check(const BatchArgs& a, PlanView* ph, BatchWs* w) {
+    if (a.splan_host && !is_scale_plan(a.splan_host)) return fail(XA_EINVAL, "not a scale plan");
+    if (a.splan_host && !a.splan_dev) return fail(XA_EINVAL, "scale plan without a device copy");
+    xa_status s = plan_host_view(a.vplan_host, ph);
+    if (s != XA_OK) return s;
+    MatchPlanView mv;
+    s = match_plan_view(a.mplan_host, &mv);
+    if (s != XA_OK) return s;
+    if (mv.h->n_features != ph->h->n_features) return fail(XA_EINVAL, "view and match plans disagree on n_features");
+    if (mv.h->views_needed > ph->h->n_views)
+        return fail(XA_EINVAL, "match plan reads %d views, view plan has %d", mv.h->views_needed, ph->h->n_views);
+    if (!a.vplan_dev || !a.mplan_dev || !a.sources || !a.pattern) return fail(XA_EINVAL, "NULL pointer");
+    const xa_batch_buffers& o = a.out;
+    if (!o.kp || !o.desc || !o.count || !o.matches || !o.pair_count || !o.best)
+        return fail(XA_EINVAL, "NULL output buffer");
+    if (a.num < 0 || a.den < 1 || a.num > (1 << 20) || a.den > (1 << 20)) return fail(XA_EINVAL, "bad ratio");
+    *w = batch_layout(a.splan_host, ph->h);
+    if (a.ws_bytes < w->total) return fail(XA_ECAPACITY, "batch workspace needs %zu bytes, got %zu", w->total, a.ws_bytes);
+    if (!a.ws || reinterpret_cast<uintptr_t>(a.ws) % kAlign) return fail(XA_EINVAL, "workspace must be 256-byte aligned");
+    return XA_OK;
+}
+
+xa_status batch_launch(const BatchArgs& a, const PlanView& ph, const BatchWs& w, hipStream_t st) {
+    xa_status s = XA_OK;
+    if (a.splan_host) s = launch_scale(a.splan_host, a.splan_dev, a.sources, nullptr, a.ws + w.scale, st);
+    if (s != XA_OK) return s;
+    const PlanView pd = plan_dev_view(a.vplan_host, a.vplan_dev);
+    s = launch_simulate(ph, pd, a.sources, a.ws + w.arena, a.ws + w.mask, nullptr,
+                        reinterpret_cast<float*>(a.ws + w.sim), st);
+    if (s != XA_OK) return s;
+    s = launch_extract(ph, pd, a.ws + w.arena, a.ws + w.mask, a.pattern, a.out.kp, a.out.desc, a.out.count,
+                       a.ws + w.ext, st);
+    if (s != XA_OK) return s;
+    return launch_match_plan(a.mplan_host, a.mplan_dev, a.out.desc, a.out.count, a.num, a.den, a.out.matches,
+                             a.out.pair_count, a.out.best, st);
+}
+
+}  // namespace
+}  // namespace xa
+
+struct xa_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" size_t xa_match_batch_workspace_size(const void* splan_host, const void* vplan_host) {
+    PlanView ph;
+    if (plan_host_view(vplan_host, &ph) != XA_OK) return 0;
+    if (splan_host && !is_scale_plan(splan_host)) return 0;
+    return batch_layout(splan_host, ph.h).total;
+}
+
+extern "C" xa_status xa_match_batch(const void* splan_host, const void* splan_dev, const void* vplan_host,
+                                    const void* vplan_dev, const void* mplan_host, const void* mplan_dev,
+                                    uint8_t* d_sources, const int8_t* d_pattern, int32_t ratio_num, int32_t ratio_den,
+                                    const xa_batch_buffers* out, void* d_ws, size_t ws_bytes, hipStream_t stream) {
+    if (!out) return fail(XA_EINVAL, "NULL output buffers");
+    const BatchArgs a{splan_host, splan_dev, vplan_host, vplan_dev, mplan_host, mplan_dev, d_sources, d_pattern,
+                      ratio_num, ratio_den, *out, static_cast<uint8_t*>(d_ws), ws_bytes};
+    PlanView ph;
+    BatchWs w;
+    xa_status s = batch_check(a, &ph, &w);
+    if (s != XA_OK) return s;
+    s = batch_launch(a, ph, w, stream);
+    return s == XA_OK ? ok() : s;
+}
+
+extern "C" xa_status xa_match_batch_capture(const void* splan_host, const void* splan_dev, const void* vplan_host,
+                                            const void* vplan_dev, const void* mplan_host, const void* mplan_dev,
+                                            uint8_t* d_sources, const int8_t* d_pattern, int32_t ratio_num,
+                                            int32_t ratio_den, const xa_batch_buffers* out, void* d_ws,
+                                            size_t ws_bytes, xa_graph** graph) {
+    if (!out || !graph) return fail(XA_EINVAL, "NULL pointer");
+    *graph = nullptr;
+    const BatchArgs a{splan_host, splan_dev, vplan_host, vplan_dev, mplan_host, mplan_dev, d_sources, d_pattern,
+                      ratio_num, ratio_den, *out, static_cast<uint8_t*>(d_ws), ws_bytes};
+    PlanView ph;
+    BatchWs w;
+    xa_status s = batch_check(a, &ph, &w);
+    if (s != XA_OK) return s;
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
+    auto* g = new (std::nothrow) xa_graph;
+    if (!g) {
+        hipStreamDestroy(cs);
+        return fail(XA_EHIP, "out of host memory");
+    }
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        s = batch_launch(a, ph, w, cs);
+        hipGraph_t graph_obj = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(cs, &graph_obj);
+        g->graph = graph_obj;
+        if (s == XA_OK && e2 != hipSuccess) s = hip_fail(e2, "end capture");
+        if (s == XA_OK) {
+            const hipError_t e3 = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+            if (e3 != hipSuccess) s = hip_fail(e3, "graph instantiate");
+        }
+    } else {
+        s = hip_fail(e, "begin capture");
+    }
+    hipStreamDestroy(cs);
+    if (s != XA_OK) {
+        if (g->exec) hipGraphExecDestroy(g->exec);
+        if (g->graph) hipGraphDestroy(g->graph);
+        delete g;
+        return s;
+    }
+    *graph = g;
+    return ok();
+}
+
+extern "C" xa_status xa_graph_launch(xa_graph* graph, hipStream_t stream) {
+    if (!graph || !graph->exec) return fail(XA_EINVAL, "NULL graph");
+    const hipError_t e = hipGraphLaunch(graph->exec, stream);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    return ok();
+}
+
+extern "C" xa_status xa_graph_destroy(xa_graph* graph) {
+    if (!graph) return ok();
+    if (graph->exec) hipGraphExecDestroy(graph->exec);
+    if (graph->graph) hipGraphDestroy(graph->graph);
+    delete graph;
+    return ok();
 }

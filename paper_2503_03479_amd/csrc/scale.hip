@@ -288,16 +288,10 @@ extern "C" size_t xa_scale_workspace_size(const void* splan_host) {
     return align_up(size_t(static_cast<const ScaleHeader*>(splan_host)->blur_floats) * 4);
 }
 
-extern "C" xa_status xa_scale_sources(const void* splan_host, const void* splan_dev, uint8_t* d_sources,
-                                      float* d_values, void* d_ws, size_t ws_bytes, hipStream_t stream) {
-    if (!splan_host || static_cast<const ScaleHeader*>(splan_host)->magic != kScaleMagic)
-        return fail(XA_EINVAL, "not a scale plan");
-    if (!splan_dev || !d_sources) return fail(XA_EINVAL, "NULL device pointer");
+namespace xa {
+xa_status launch_scale(const void* splan_host, const void* splan_dev, uint8_t* d_sources, float* d_values,
+                       void* d_ws, hipStream_t stream) {
     const ScaleView hv = scale_view(splan_host, splan_host), dv = scale_view(splan_host, splan_dev);
-    const size_t need = xa_scale_workspace_size(splan_host);
-    if (ws_bytes < need) return fail(XA_ECAPACITY, "scale workspace needs %zu bytes, got %zu", need, ws_bytes);
-    if (need > 0 && (!d_ws || reinterpret_cast<uintptr_t>(d_ws) % kAlign))
-        return fail(XA_EINVAL, "workspace must be non-NULL and 256-byte aligned");
     const int n = hv.h->n_jobs;
     const int bt = hv.blur_prefix[n], wt = hv.warp_prefix[n];
     float* blurred = static_cast<float*>(d_ws);
@@ -309,5 +303,22 @@ extern "C" xa_status xa_scale_sources(const void* splan_host, const void* splan_
                            d_values);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "scale launch");
-    return ok();
+    return XA_OK;
+}
+bool is_scale_plan(const void* blob) {
+    return blob && static_cast<const ScaleHeader*>(blob)->magic == kScaleMagic;
+}
+}  // namespace xa
+
+extern "C" xa_status xa_scale_sources(const void* splan_host, const void* splan_dev, uint8_t* d_sources,
+                                      float* d_values, void* d_ws, size_t ws_bytes, hipStream_t stream) {
+    if (!splan_host || static_cast<const ScaleHeader*>(splan_host)->magic != kScaleMagic)
+        return fail(XA_EINVAL, "not a scale plan");
+    if (!splan_dev || !d_sources) return fail(XA_EINVAL, "NULL device pointer");
+    const size_t need = xa_scale_workspace_size(splan_host);
+    if (ws_bytes < need) return fail(XA_ECAPACITY, "scale workspace needs %zu bytes, got %zu", need, ws_bytes);
+    if (need > 0 && (!d_ws || reinterpret_cast<uintptr_t>(d_ws) % kAlign))
+        return fail(XA_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+    const xa_status s = launch_scale(splan_host, splan_dev, d_sources, d_values, d_ws, stream);
+    return s == XA_OK ? ok() : s;
 }

@@ -58,6 +58,10 @@ class _Params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in ("t", "phi", "psi", "s", "tx", "ty")]
 
 
+class _BatchBuffers(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("kp", "desc", "count", "matches", "pair_count", "best")]
+
+
 class _PairBuffers(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("kp_a", "desc_a", "count_a", "kp_b", "desc_b", "count_b",
                                                  "matches", "pair_count", "best")]
@@ -88,6 +92,17 @@ _SIGS = {
     "xa_match_views": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_int32,
                                   _c.c_int32, _c.c_int32, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                   _c.c_void_p]),
+    "xa_plan_matches": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_void_p, _c.c_size_t,
+                                   _c.POINTER(_c.c_size_t)]),
+    "xa_match_groups": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_int32,
+                                   _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p]),
+    "xa_match_batch_workspace_size": (_c.c_size_t, [_c.c_void_p, _c.c_void_p]),
+    "xa_match_batch": (_c.c_int, [_c.c_void_p] * 8 + [_c.c_int32, _c.c_int32, _c.c_void_p, _c.c_void_p,
+                                                      _c.c_size_t, _c.c_void_p]),
+    "xa_match_batch_capture": (_c.c_int, [_c.c_void_p] * 8 + [_c.c_int32, _c.c_int32, _c.c_void_p, _c.c_void_p,
+                                                              _c.c_size_t, _c.POINTER(_c.c_void_p)]),
+    "xa_graph_launch": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
+    "xa_graph_destroy": (_c.c_int, [_c.c_void_p]),
     "xa_match_pair_workspace_size": (_c.c_size_t, [_c.c_void_p, _c.c_void_p]),
     "xa_match_pair": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                  _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_int32,
@@ -464,3 +479,149 @@ class StageRunner:
                                     _ptr(b["count"]), self.plan_b.n_views, self.plan_a.n_features, ratio_num,
                                     ratio_den, _ptr(self.matches), _ptr(self.pair_count), _ptr(self.best),
                                     _stream()))
+
+
+# ---------------------------------------------------------------- match plans and batches
+
+GROUP_DTYPE = np.dtype([("a0", "i4"), ("na", "i4"), ("b0", "i4"), ("nb", "i4"), ("pair_base", "i8")])
+
+
+@dataclass
+class MatchPlan:
+    blob: np.ndarray
+    groups: np.ndarray
+    n_features: int
+    _dev: object = None
+
+    def host_ptr(self) -> int:
+        return self.blob.ctypes.data
+
+    @property
+    def total_pairs(self) -> int:
+        g = self.groups
+        return int((g["pair_base"] + g["na"].astype(np.int64) * g["nb"]).max())
+
+    def device(self, device="cuda"):
+        import torch
+        if self._dev is None:
+            self._dev = torch.from_numpy(self.blob.copy()).to(device)
+        return self._dev
+
+
+def plan_matches(groups, n_features: int, queries_per_lane: int = 0) -> MatchPlan:
+    groups = np.ascontiguousarray(groups, GROUP_DTYPE)
+    n = ctypes.c_size_t(0)
+    _check(lib().xa_plan_matches(groups.ctypes.data, len(groups), n_features, queries_per_lane, None, 0,
+                                 ctypes.byref(n)))
+    blob = np.zeros(n.value, np.uint8)
+    _check(lib().xa_plan_matches(groups.ctypes.data, len(groups), n_features, queries_per_lane, blob.ctypes.data,
+                                 blob.size, ctypes.byref(n)))
+    return MatchPlan(blob, groups, n_features)
+
+
+def match_groups(mplan: MatchPlan, desc, count, ratio_num: int = 4, ratio_den: int = 5):
+    """Group matching over one descriptor set.  Returns (matches u8[P, N, 8], pair_count i32[P], best i32[G, 4])."""
+    import torch
+    dev = desc.device
+    P, N, G = mplan.total_pairs, mplan.n_features, len(mplan.groups)
+    matches = torch.zeros((P, N, 8), dtype=torch.uint8, device=dev)
+    pc = torch.zeros(P, dtype=torch.int32, device=dev)
+    best = torch.zeros((G, 4), dtype=torch.int32, device=dev)
+    _check(lib().xa_match_groups(mplan.host_ptr(), _ptr(mplan.device(dev)), _ptr(desc), _ptr(count), count.numel(),
+                                 ratio_num, ratio_den, _ptr(matches), _ptr(pc), _ptr(best), _stream()))
+    return matches, pc, best
+
+
+class BatchRunner:
+    """Many image pairs through the batched path: one sources buffer (originals + scale-stage
+    outputs), one view plan over all images, one match plan with a group per image pair."""
+
+    def __init__(self, pairs, grid, scales=(1.0,), n_levels: int = 8, n_features: int = 500,
+                 fast_threshold: int = 20, device="cuda", queries_per_lane: int = 0):
+        import torch
+        self.device = torch.device(device)
+        arena = SourceArena()
+        jobs, vsrc, params, groups = [], [], [], []
+        rows = [(float(r["t"]), float(r["phi"])) for r in grid] if isinstance(grid, np.ndarray) else list(grid)
+        self.image_index = []        # (pair, side) -> original source index
+        images = {}
+        view_base = 0
+        for pi, (A, B) in enumerate(pairs):
+            ranges = []
+            for img in (A, B):
+                si = arena.add(img.shape[1], img.shape[0])
+                images[si] = img
+                srcs = []
+                for s in scales:
+                    if s == 1.0:
+                        srcs.append(si)
+                    else:
+                        w, h = scaled_size(img.shape[1], img.shape[0], s)
+                        di = arena.add(w, h, s)
+                        jobs.append((arena.descs[si], arena.descs[di], s))
+                        srcs.append(di)
+                start = view_base
+                for src in srcs:
+                    for (t, phi) in rows:
+                        vsrc.append(src)
+                        params.append((t, phi, 0.0, 1.0, 0.0, 0.0))
+                        view_base += 1
+                ranges.append((start, view_base - start))
+            (a0, na), (b0, nb) = ranges
+            groups.append((a0, na, b0, nb, 0))
+        base = 0
+        for i, g in enumerate(groups):
+            groups[i] = g[:4] + (base,)
+            base += g[1] * g[3]
+        self.arena = arena
+        self.splan = plan_scales(np.array(jobs, SCALE_JOB_DTYPE)) if jobs else None
+        self.vplan = plan_views(arena.table(), vsrc, np.array(params, PARAMS_DTYPE), n_levels, 1.2, n_features,
+                                fast_threshold)
+        self.mplan = plan_matches(np.array(groups, GROUP_DTYPE), n_features, queries_per_lane)
+        self.view_scale = np.array([arena.descs[s][5] for s in vsrc])
+        dev = self.device
+        self.sources = torch.from_numpy(arena.pack(images)).to(dev)
+        nv, N = self.vplan.n_views, n_features
+        z = lambda *sh, dt=torch.uint8: torch.zeros(sh, dtype=dt, device=dev)  # noqa: E731
+        self.kp, self.desc, self.count = z(nv, N, 40), z(nv, N, 32), z(nv, dt=torch.int32)
+        P = self.mplan.total_pairs
+        self.matches, self.pair_count = z(P, N, 8), z(P, dt=torch.int32)
+        self.best = z(len(groups), 4, dt=torch.int32)
+        sp = self.splan.host_ptr() if self.splan else None
+        need = lib().xa_match_batch_workspace_size(sp, self.vplan.host_ptr())
+        self.ws = _empty(need, dev)
+        self.bufs = _BatchBuffers(*[_ptr(t) for t in (self.kp, self.desc, self.count, self.matches,
+                                                      self.pair_count, self.best)])
+        self._args = None
+        self.graph = None
+
+    def _call_args(self):
+        sp = self.splan.host_ptr() if self.splan else None
+        sd = _ptr(self.splan.device(self.device)) if self.splan else None
+        return (sp, sd, self.vplan.host_ptr(), _ptr(self.vplan.device(self.device)), self.mplan.host_ptr(),
+                _ptr(self.mplan.device(self.device)), _ptr(self.sources))
+
+    def run(self, pattern, ratio_num: int = 4, ratio_den: int = 5):
+        _check(lib().xa_match_batch(*self._call_args(), _ptr(pattern), ratio_num, ratio_den, ctypes.byref(self.bufs),
+                                    _ptr(self.ws), self.ws.numel(), _stream()))
+
+    def capture(self, pattern, ratio_num: int = 4, ratio_den: int = 5):
+        g = ctypes.c_void_p(0)
+        _check(lib().xa_match_batch_capture(*self._call_args(), _ptr(pattern), ratio_num, ratio_den,
+                                            ctypes.byref(self.bufs), _ptr(self.ws), self.ws.numel(), ctypes.byref(g)))
+        self.graph = g
+        self._pattern = pattern       # the graph reads this buffer on every replay
+
+    def replay(self):
+        _check(lib().xa_graph_launch(self.graph, _stream()))
+
+    def close(self):
+        if self.graph:
+            lib().xa_graph_destroy(self.graph)
+            self.graph = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,6 +1,7 @@
 """Host-side checks of libxaffine: exports, the planner against the oracle, argument errors.
 
 No GPU work is launched here; the planner and the argument checks run on the host."""
+import ctypes
 import math
 import os
 import re
@@ -137,3 +138,26 @@ def test_device_calls_validate_before_launch(L):
     assert st == X.XA_ECAPACITY
     assert L.xa_match_views(256, 256, 0, 256, 256, 1, 100, 4, 5, 256, 256, 256, None) == X.XA_EINVAL
     assert L.xa_match_views(256, 256, 1, 256, 256, 1, 100, 4, 0, 256, 256, 256, None) == X.XA_EINVAL
+
+
+def test_match_plan_rules():
+    G = X.GROUP_DTYPE
+    mp = X.plan_matches(np.array([(0, 3, 3, 4, 0), (7, 2, 0, 2, 12)], G), 500)
+    assert mp.total_pairs == 16
+    with pytest.raises(X.XAError):          # overlapping pair ranges
+        X.plan_matches(np.array([(0, 3, 3, 4, 0), (7, 2, 0, 2, 11)], G), 500)
+    with pytest.raises(X.XAError):          # negative field
+        X.plan_matches(np.array([(0, -1, 3, 4, 0)], G), 500)
+    with pytest.raises(X.XAError):          # bad variant
+        X.plan_matches(np.array([(0, 1, 1, 1, 0)], G), 500, 3)
+    with pytest.raises(X.XAError):          # n_features out of range
+        X.plan_matches(np.array([(0, 1, 1, 1, 0)], G), 0)
+    # empty groups may share a pair_base
+    X.plan_matches(np.array([(0, 0, 3, 4, 0), (7, 2, 0, 2, 0)], G), 500)
+
+
+def test_match_groups_rejects_views_outside_the_set():
+    mp = X.plan_matches(np.array([(0, 3, 3, 4, 0)], X.GROUP_DTYPE), 64)
+    fake = ctypes.c_void_p(256)               # never dereferenced: the check comes first
+    st = X.lib().xa_match_groups(mp.host_ptr(), fake, fake, fake, 6, 4, 5, fake, fake, fake, None)
+    assert st == -1 and b"views" in X.lib().xa_last_error()
