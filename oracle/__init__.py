@@ -16,5 +16,7 @@ Modules
   match     -- brute-force Hamming nearest neighbour with ratio test (Sec. III.B,
                Sec. IV.C), best view pair, back-mapping and precision (eqs. (5)-(6))
   pipeline  -- the composition: simulate both images, extract, match all view pairs
+  diffwarp  -- the Lanczos-4 warp of an fp image as a function of the six camera
+               parameters, and its adjoint (image and parameter gradients)
 """
-from . import plan, simulate, orb, match, pipeline  # noqa: F401
+from . import plan, simulate, orb, match, pipeline, diffwarp  # noqa: F401
