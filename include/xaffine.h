@@ -341,6 +341,31 @@ xa_status xa_pair_precision(const xa_keypoint* d_kp_a, const xa_keypoint* d_kp_b
                             const int32_t* d_best, const double* H, double th, int32_t* d_out,
                             hipStream_t stream);
 
+/* The Lanczos-4 warp of eqs. (3)-(4) as a differentiable map of fp32 crops and of
+ * the camera parameters of eq. (2), for photometric refinement of the grid
+ * search's (t, phi).  n crops of h x w fp32 values (d_img [n][h][w], row-major,
+ * no padding) and one xa_affine_params per crop (d_params [n], device memory, so
+ * that an optimiser can update them without a host round trip).  The map is
+ * centred: view pixel q samples the crop at p = L^-1 (q - c - T) + c with
+ * L = s R(psi) diag(1/t, 1) R(phi), c = ((w - 1)/2, (h - 1)/2), T = (tx, ty);
+ * the view has the crop's size.  A view pixel is valid iff p lies in
+ * [-1/2, w - 1/2] x [-1/2, h - 1/2]; invalid pixels are 0 and carry no gradient.
+ * Taps outside the crop are clamped; weights are normalised to sum one.
+ *
+ * xa_warp_f32_fwd: d_out [n][h][w] fp32, d_mask [n][h][w] u8 (nullable).
+ * xa_warp_f32_bwd: given dLoss/dout (d_gout [n][h][w]), writes dLoss/dimg to
+ * d_gimg [n][h][w] (overwritten; nullable) and dLoss/d(t, phi, psi, s, tx, ty)
+ * to d_gparams [n][6] fp64 (nullable).  The parameter gradient is summed over
+ * each crop in a fixed order (deterministic); the image gradient is scattered
+ * with fp32 atomics, so its last bits depend on the order of arrival.
+ * Workspace (needed when d_gparams is given): xa_warp_f32_bwd_workspace_size. */
+xa_status xa_warp_f32_fwd(const float* d_img, int32_t n, int32_t h, int32_t w, const xa_affine_params* d_params,
+                          float* d_out, uint8_t* d_mask, hipStream_t stream);
+size_t xa_warp_f32_bwd_workspace_size(int32_t n, int32_t h, int32_t w);
+xa_status xa_warp_f32_bwd(const float* d_img, const float* d_gout, const xa_affine_params* d_params, int32_t n,
+                          int32_t h, int32_t w, float* d_gimg, double* d_gparams, void* d_ws, size_t ws_bytes,
+                          hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,6 +8,7 @@ raises RuntimeError (there is no fallback implementation).
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from dataclasses import dataclass
 
@@ -103,6 +104,11 @@ _SIGS = {
                                                               _c.c_size_t, _c.POINTER(_c.c_void_p)]),
     "xa_graph_launch": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
     "xa_graph_destroy": (_c.c_int, [_c.c_void_p]),
+    "xa_warp_f32_fwd": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_void_p, _c.c_void_p,
+                                   _c.c_void_p, _c.c_void_p]),
+    "xa_warp_f32_bwd_workspace_size": (_c.c_size_t, [_c.c_int32, _c.c_int32, _c.c_int32]),
+    "xa_warp_f32_bwd": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_int32, _c.c_int32,
+                                   _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
     "xa_match_pair_workspace_size": (_c.c_size_t, [_c.c_void_p, _c.c_void_p]),
     "xa_match_pair": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                  _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_int32,
@@ -625,3 +631,149 @@ class BatchRunner:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- differentiable warp
+
+def _check_crops(img, params):
+    import torch
+    if img.dtype != torch.float32 or img.dim() != 3 or not img.is_contiguous():
+        raise XAError(-1, "img must be a contiguous float32 tensor [n, h, w]")
+    if params.dtype != torch.float64 or tuple(params.shape) != (img.shape[0], 6) or not params.is_contiguous():
+        raise XAError(-1, "params must be a contiguous float64 tensor [n, 6] (t, phi, psi, s, tx, ty)")
+    if params.device != img.device:
+        raise XAError(-1, "img and params must be on the same device")
+
+
+def warp_f32_fwd(img, params):
+    """(out [n, h, w] fp32, mask [n, h, w] u8) for crops img [n, h, w] and params [n, 6] fp64."""
+    import torch
+    _check_crops(img, params)
+    n, h, w = img.shape
+    out = torch.empty_like(img)
+    mask = torch.empty((n, h, w), dtype=torch.uint8, device=img.device)
+    _check(lib().xa_warp_f32_fwd(_ptr(img), n, h, w, _ptr(params), _ptr(out), _ptr(mask), _stream()))
+    return out, mask
+
+
+def warp_f32_bwd(img, gout, params, need_img: bool = True, need_params: bool = True):
+    """(d/dimg [n, h, w] fp32 or None, d/dparams [n, 6] fp64 or None) for dLoss/dout = gout."""
+    import torch
+    _check_crops(img, params)
+    gout = gout.contiguous()
+    if gout.shape != img.shape or gout.dtype != torch.float32:
+        raise XAError(-1, "gout must be float32 with the shape of img")
+    n, h, w = img.shape
+    gimg = torch.empty_like(img) if need_img else None
+    gpar = torch.empty((n, 6), dtype=torch.float64, device=img.device) if need_params else None
+    ws = _empty(lib().xa_warp_f32_bwd_workspace_size(n, h, w), img.device) if need_params else None
+    _check(lib().xa_warp_f32_bwd(_ptr(img), _ptr(gout), _ptr(params), n, h, w, _ptr(gimg), _ptr(gpar), _ptr(ws),
+                                 0 if ws is None else ws.numel(), _stream()))
+    return gimg, gpar
+
+
+def _warp_function():
+    import torch
+
+    class WarpF32(torch.autograd.Function):
+        """Lanczos-4 affine warp of fp32 crops; differentiable in the crops and the
+        six camera parameters (forward and adjoint are the library's kernels)."""
+
+        @staticmethod
+        def forward(ctx, img, params):
+            out, mask = warp_f32_fwd(img, params)
+            ctx.save_for_backward(img, params)
+            ctx.mark_non_differentiable(mask)
+            return out, mask
+
+        @staticmethod
+        def backward(ctx, gout, _gmask):
+            img, params = ctx.saved_tensors
+            gi, gp = warp_f32_bwd(img, gout, params, ctx.needs_input_grad[0], ctx.needs_input_grad[1])
+            return gi, gp
+
+    return WarpF32
+
+
+_WARP_FN = None
+
+
+def warp_f32(img, params):
+    """Differentiable warp: returns (out, mask); gradients flow to img and params."""
+    global _WARP_FN
+    if _WARP_FN is None:
+        _WARP_FN = _warp_function()
+    return _WARP_FN.apply(img.contiguous(), params.contiguous())
+
+
+def _gauss_blur(x, sigma: float):
+    """Separable Gaussian (replicated border) of fp32 crops [n, h, w]; sigma 0 = none."""
+    import torch
+    import torch.nn.functional as F
+    if sigma <= 0:
+        return x
+    r = max(1, int(math.ceil(3 * sigma)))
+    k = torch.exp(-(torch.arange(-r, r + 1, dtype=torch.float64, device=x.device) ** 2) / (2 * sigma * sigma))
+    k = (k / k.sum()).to(x.dtype)
+    y = F.pad(x[:, None], (r, r, 0, 0), mode="replicate")
+    y = F.conv2d(y, k.view(1, 1, 1, -1))
+    y = F.pad(y, (0, 0, r, r), mode="replicate")
+    return F.conv2d(y, k.view(1, 1, -1, 1))[:, 0]
+
+
+def refine_tilt(img, target, params, grid, target_mask=None, steps: int = 20, lr: float = 0.03, sigmas=None):
+    """Photometric refinement of (t, phi) for each crop.
+
+    The grid search comes first: every (t, phi) of `grid` is warped (one batched
+    forward per grid point) and the one with the lowest mean squared error over the
+    pixels valid in both the warped crop and the target is kept.  Then `steps` Adam
+    steps on (log t, phi) start from it, coarse to fine (crop and target smoothed by a
+    Gaussian of sigma 4 px for the first half of the steps and 1 px for the rest,
+    unless `sigmas` gives one sigma per step), with the other four parameters held.
+    The grid point is the judge: a crop keeps its refined (t, phi) only if the refined
+    loss on the unsmoothed crops is lower.
+    Returns (params [n, 6], grid_loss [n], refined_loss [n])."""
+    import torch
+    n = img.shape[0]
+    base = params.detach().clone()
+    tmask = torch.ones_like(target) if target_mask is None else target_mask.to(target.dtype)
+    if sigmas is None:
+        sigmas = [4.0] * (steps // 2) + [1.0] * (steps - steps // 2)
+    if len(sigmas) != steps:
+        raise XAError(-1, "need one sigma per step")
+
+    def losses(im, tg, p):
+        out, mask = warp_f32(im, p)
+        m = mask.to(im.dtype) * tmask
+        r = (out - tg) * m
+        return (r * r).sum(dim=(1, 2)) / m.sum(dim=(1, 2)).clamp_min(1.0)
+
+    with torch.no_grad():
+        best = torch.full((n,), float("inf"), dtype=torch.float64, device=img.device)
+        best_p = base.clone()
+        for (t, phi) in grid:
+            p = base.clone()
+            p[:, 0] = t
+            p[:, 1] = phi
+            l = losses(img, target, p).double()
+            better = l < best
+            best = torch.where(better, l, best)
+            best_p[better] = p[better]
+    logt = best_p[:, 0].log().clone().requires_grad_(True)
+    phi = best_p[:, 1].clone().requires_grad_(True)
+    opt = torch.optim.Adam([logt, phi], lr=lr)
+    smoothed = {}
+    for sg in sigmas:
+        if sg not in smoothed:
+            smoothed[sg] = (_gauss_blur(img, sg).contiguous(), _gauss_blur(target * tmask, sg))
+        im, tg = smoothed[sg]
+        opt.zero_grad()
+        p = torch.cat([logt.exp()[:, None], phi[:, None], best_p[:, 2:]], dim=1)
+        losses(im, tg, p).sum().backward()
+        opt.step()
+    with torch.no_grad():
+        p = torch.cat([logt.exp()[:, None], phi[:, None], best_p[:, 2:]], dim=1)
+        refined = losses(img, target, p).double()
+        keep = refined < best
+        out = torch.where(keep[:, None], p, best_p)
+    return out, best, refined

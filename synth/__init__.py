@@ -23,7 +23,8 @@ import numpy as np
 
 __all__ = [
     "Scene", "make_scene", "render", "affine_canvas", "tilt_rotation",
-    "brief_pattern", "PairCase", "make_pair", "PAIR_CONFIGS", "rng",
+    "brief_pattern", "PairCase", "make_pair", "PAIR_CONFIGS", "rng", "make_crops", "crop_params",
+    "batch_pairs",
 ]
 
 
@@ -207,3 +208,57 @@ PAIR_CONFIGS = {
     # 1024x768, 400 blobs, 300 rectangles; B: absolute tilt 4 (~75.5 deg), rotation 45 deg.
     "full": dict(width=1024, height=768, n_blobs=400, n_rects=300, seed=2, t=4.0, phi=0.0, psi=math.radians(45.0)),
 }
+
+
+def make_crops(n: int, size: int, seed: int, distinct: int = 0, supersample: int = 4) -> np.ndarray:
+    """n fp32 crops of size x size with values in [0, 1] (the scene generator, u8 / 255).
+
+    Scene density scales with area (133 blobs and 100 rectangles at 512 x 512).
+    distinct > 0 renders only that many scenes and repeats them (for timing runs,
+    where the content does not change the work)."""
+    m = n if distinct <= 0 else min(distinct, n)
+    area = size * size / (512.0 * 512.0)
+    nb, nr = max(4, int(round(133 * area))), max(3, int(round(100 * area)))
+    out = np.empty((n, size, size), np.float32)
+    for i in range(m):
+        sc = make_scene(size, size, nb, nr, seed + i)
+        out[i] = render(sc, np.eye(2), np.zeros(2), size, size, noise_seed=(seed + i) * 7919 + 3,
+                        supersample=supersample).astype(np.float32) / 255.0
+    for i in range(m, n):
+        out[i] = out[i % m]
+    return out
+
+
+def crop_params(n: int, seed: int, max_shift: float = 16.0) -> np.ndarray:
+    """Camera parameters per crop, [n, 6] fp64 (t, phi, psi, s, tx, ty): t ~ U[1, 6],
+    phi ~ U[0, pi), psi ~ U[-pi, pi), s ~ U[0.5, 1], tx, ty ~ U[-max_shift, max_shift]."""
+    g = rng(seed)
+    P = np.empty((n, 6))
+    P[:, 0] = g.uniform(1.0, 6.0, n)
+    P[:, 1] = g.uniform(0.0, math.pi, n)
+    P[:, 2] = g.uniform(-math.pi, math.pi, n)
+    P[:, 3] = g.uniform(0.5, 1.0, n)
+    P[:, 4] = g.uniform(-max_shift, max_shift, n)
+    P[:, 5] = g.uniform(-max_shift, max_shift, n)
+    return P
+
+
+def batch_pairs(n: int, seed: int = 3000, side_min: int = 480, side_max: int = 2048, supersample: int = 1):
+    """n pairs of uneven sizes: width ~ U{side_min..side_max}, aspect ~ U[0.6, 1.6],
+    height = clip(round(width / aspect), side_min, side_max); scene density scaled by
+    area from 400 blobs / 300 rectangles at 1024 x 768; B = the scene under an absolute
+    tilt ~ U[0, 80] degrees (t = 1 / cos), longitude ~ U[0, pi) and rotation ~ U[0, 2 pi).
+    Pair k uses seed + k."""
+    out = []
+    for k in range(n):
+        g = rng(seed + k)
+        w = int(g.integers(side_min, side_max + 1))
+        aspect = float(g.uniform(0.6, 1.6))
+        h = int(np.clip(round(w / aspect), side_min, side_max))
+        theta = math.radians(float(g.uniform(0.0, 80.0)))
+        phi = float(g.uniform(0.0, math.pi))
+        psi = float(g.uniform(0.0, 2.0 * math.pi))
+        area = w * h / (1024.0 * 768.0)
+        out.append(make_pair(w, h, max(8, int(round(400 * area))), max(6, int(round(300 * area))), seed + k,
+                             1.0 / math.cos(theta), phi, psi, supersample=supersample, name=f"batch{k}"))
+    return out

@@ -1,0 +1,225 @@
+"""GPU: the differentiable Lanczos-4 warp against the fp64 oracle.
+
+Forward: |out - oracle| <= 1e-4 on values in [0, 1] and identical validity masks
+(away from points within 1e-9 of the domain edge).  Adjoint: each of the six
+parameter gradients within 1e-3 relative of the oracle's (relative to the largest
+of the crop's six when a component is tiny), and the image gradient within 1e-3 of
+the oracle's largest entry.  On a smooth crop, the GPU adjoint agrees within 1e-3 (as a
+vector, max-norm) with central finite differences at h = 1e-3 of the loss on the GPU's
+fp32 forward and on the oracle's fp64 forward, and component by component within 1e-4
+with fp64 differences at h = 1e-5 (at h = 1e-3 the truncation error is a few 1e-3 in
+absolute terms, large for components hundreds of times smaller than the largest)."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import diffwarp as OD
+from oracle import plan as OP
+
+torch = pytest.importorskip("torch")
+X = pytest.importorskip("paper_2503_03479_amd.xaffine")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    X.lib()
+    return torch.device("cuda:0")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _edge(params, w, h):
+    px, py, _, _, _ = OD.sample_points(params, w, h)
+    return (np.minimum(np.abs(px + 0.5), np.abs(px - (w - 0.5))) < 1e-9) | \
+           (np.minimum(np.abs(py + 0.5), np.abs(py - (h - 0.5))) < 1e-9)
+
+
+def _check(crops, P, dev, label, gseed=11):
+    n, h, w = crops.shape
+    img = torch.from_numpy(crops).to(dev)
+    par = torch.from_numpy(P).to(dev)
+    out, mask = X.warp_f32_fwd(img, par)
+    g = synth.rng(gseed).standard_normal(crops.shape).astype(np.float32)
+    gimg, gpar = X.warp_f32_bwd(img, torch.from_numpy(g).to(dev), par)
+    torch.cuda.synchronize()
+    out, mask, gimg, gpar = out.cpu().numpy(), mask.cpu().numpy(), gimg.cpu().numpy(), gpar.cpu().numpy()
+    worst_v = worst_gi = worst_gp = 0.0
+    for k in range(n):
+        V, M = OD.warp_forward(crops[k], P[k])
+        edge = _edge(P[k], w, h)
+        assert np.all((mask[k].astype(bool) == M) | edge), (label, k)
+        both = M & mask[k].astype(bool)
+        worst_v = max(worst_v, float(np.abs(out[k][both] - V[both]).max()) if both.any() else 0.0)
+        assert np.all(out[k][~mask[k].astype(bool)] == 0)
+        gm = np.where(M & ~edge, g[k], 0.0)
+        if edge.any():      # a pixel on the domain edge may be valid on one side only
+            continue
+        ri, rp = OD.warp_adjoint(crops[k], gm, P[k])
+        scale_i = max(np.abs(ri).max(), 1e-12)
+        worst_gi = max(worst_gi, float(np.abs(gimg[k] - ri).max() / scale_i))
+        floor = 1e-3 * np.abs(rp).max()
+        rel = np.abs(gpar[k] - rp) / np.maximum(np.abs(rp), max(floor, 1e-300))
+        worst_gp = max(worst_gp, float(rel.max()))
+    say(f"[{label}] fwd max|err| {worst_v:.2e}; grad img max err / max {worst_gi:.2e}; grad params max rel {worst_gp:.2e}")
+    assert worst_v <= 1e-4
+    assert worst_gi <= 1e-3
+    assert worst_gp <= 1e-3
+
+
+def test_identity_and_shift(dev):
+    say("case: identity and integer shift reproduce the crop")
+    crops = synth.make_crops(2, 64, 5100)
+    P = np.array([(1, 0, 0, 1, 0, 0), (1, 0, 0, 1, 3, -2)], np.float64)
+    out, mask = X.warp_f32_fwd(torch.from_numpy(crops).to(dev), torch.from_numpy(P).to(dev))
+    out = out.cpu().numpy()
+    assert np.max(np.abs(out[0] - crops[0])) <= 1e-6
+    assert np.max(np.abs(out[1][:-2, 3:] - crops[1][2:, :-3])) <= 1e-6
+
+
+def test_parity_random_params(dev):
+    say("case: 6 crops of 96x80 with parameters drawn over t in [1, 6], s in [0.5, 1]")
+    crops = synth.make_crops(6, 96, 5000)[:, :, :80].copy()
+    P = synth.crop_params(6, 5000, max_shift=8.0)
+    _check(crops, P, dev, "random 96x80")
+
+
+def test_parity_ragged_and_degenerate(dev):
+    say("case: ragged sizes (37x53), one-pixel-wide crop, a view with no valid pixel")
+    crops = synth.make_crops(3, 53, 5200)[:, :37, :].copy()
+    P = np.array([(5.5, 2.9, -2.0, 0.51, 2.5, -1.5), (1.0, 0.0, 0.3, 1.0, 0.0, 0.0), (1.0, 0, 0, 1.0, 400.0, 0)])
+    _check(crops, P, dev, "ragged 53x37")
+    one = synth.make_crops(1, 16, 5300)[:, :, :1].copy()
+    _check(one, np.array([(1.3, 0.2, 0.1, 0.9, 0.0, 0.3)]), dev, "16x1")
+
+
+def test_full_size_batch_sampled(dev):
+    """The timed configuration: 256 crops of 512 x 512; crops 0, 97 and 255 against the oracle."""
+    say("case: 256 crops of 512x512 (16 distinct scenes); sampled crops vs the oracle")
+    crops = synth.make_crops(256, 512, 5000, distinct=16)
+    P = synth.crop_params(256, 5000)
+    img = torch.from_numpy(crops).to(dev)
+    par = torch.from_numpy(P).to(dev)
+    out, mask = X.warp_f32_fwd(img, par)
+    g = torch.zeros_like(img)
+    picks = [0, 97, 255]
+    rg = synth.rng(12)
+    gs = {k: rg.standard_normal((512, 512)).astype(np.float32) for k in picks}
+    for k in picks:
+        g[k] = torch.from_numpy(gs[k]).to(dev)
+    gimg, gpar = X.warp_f32_bwd(img, g, par)
+    torch.cuda.synchronize()
+    for k in picks:
+        V, M = OD.warp_forward(crops[k], P[k])
+        o, m = out[k].cpu().numpy(), mask[k].cpu().numpy().astype(bool)
+        assert np.all((m == M) | _edge(P[k], 512, 512))
+        both = m & M
+        assert np.abs(o[both] - V[both]).max() <= 1e-4, k
+        ri, rp = OD.warp_adjoint(crops[k], np.where(M, gs[k], 0.0), P[k])
+        gi, gp = gimg[k].cpu().numpy(), gpar[k].cpu().numpy()
+        assert np.abs(gi - ri).max() <= 1e-3 * np.abs(ri).max(), k
+        rel = np.abs(gp - rp) / np.maximum(np.abs(rp), 1e-3 * np.abs(rp).max())
+        assert rel.max() <= 1e-3, (k, gp, rp)
+        say(f"[512 crop {k}] fwd and adjoint within bounds, grad params rel err {rel.max():.2e}")
+    # crops that got no output gradient have zero gradients
+    assert float(gpar[1].abs().max()) == 0.0 and float(gimg[1].abs().max()) == 0.0
+
+
+def test_finite_differences_on_gpu_forward(dev):
+    say("case: central differences (h = 1e-3) of a loss on the GPU forward vs the GPU adjoint")
+    crop = synth.make_crops(1, 64, 5400)[0].astype(np.float64)
+    k = np.array([1, 4, 6, 4, 1], np.float64) / 16
+    for _ in range(12):
+        for ax in (0, 1):
+            crop = np.apply_along_axis(lambda r: np.convolve(r, k, mode="same"), ax, crop)
+    crops = crop[None].astype(np.float32)
+    target = np.roll(crops, 2, axis=2)
+    base = np.array([2.3, 0.7, 0.4, 0.8, 1.5, -0.5])
+    img = torch.from_numpy(crops).to(dev)
+    h = 1e-3
+    probes = [base.copy()]
+    for j in range(6):
+        for sg in (-1, 1):
+            p = base.copy()
+            p[j] += sg * h
+            probes.append(p)
+    outs, masks = X.warp_f32_fwd(img.expand(len(probes), -1, -1).contiguous(),
+                                 torch.from_numpy(np.array(probes)).to(dev))
+    outs = outs.cpu().numpy().astype(np.float64)
+    keep = np.logical_and.reduce(masks.cpu().numpy().astype(bool), axis=0)
+    r = np.where(keep, outs[0] - target[0], 0.0)
+    _, gp = X.warp_f32_bwd(img, torch.from_numpy(r[None].astype(np.float32)).to(dev),
+                           torch.from_numpy(base[None]).to(dev), need_img=False)
+    gp = gp.cpu().numpy()[0]
+    loss = [0.5 * np.sum(np.where(keep, o - target[0], 0.0) ** 2) for o in outs]
+    fd = np.array([(loss[2 + 2 * j] - loss[1 + 2 * j]) / (2 * h) for j in range(6)])
+    # the same differences on the oracle's fp64 forward
+    def fd_oracle(hh):
+        lo = []
+        for j in range(6):
+            for sg in (-1, 1):
+                p = base.copy()
+                p[j] += sg * hh
+                V, _ = OD.warp_forward(crop, p)
+                lo.append(0.5 * np.sum(np.where(keep, V - target[0], 0.0) ** 2))
+        return np.array([(lo[2 * j + 1] - lo[2 * j]) / (2 * hh) for j in range(6)])
+
+    fd64 = fd_oracle(h)
+    fd64_fine = fd_oracle(1e-5)
+    # at h = 1e-3 the O(h^2) truncation error is a few 1e-3 in absolute terms, which is large
+    # for components hundreds of times smaller than the largest: compare as vectors there,
+    # and component by component against the converged differences at h = 1e-5
+    relv32 = np.abs(gp - fd).max() / np.abs(fd).max()
+    relv64 = np.abs(gp - fd64).max() / np.abs(fd64).max()
+    relc = np.abs(gp - fd64_fine) / np.maximum(np.abs(fd64_fine), 1e-3 * np.abs(fd64_fine).max())
+    say(f"[fd] adjoint {np.round(gp, 4).tolist()} fd(h=1e-5, fp64) {np.round(fd64_fine, 4).tolist()}")
+    say(f"[fd] h=1e-3 vector rel err: fp32 forward {relv32:.2e}, fp64 forward {relv64:.2e}; "
+        f"h=1e-5 component-wise rel err {relc.max():.2e}")
+    assert relv32 <= 1e-3 and relv64 <= 1e-3
+    assert relc.max() <= 1e-4
+
+
+def test_autograd_function_and_refinement(dev):
+    """The autograd path equals the direct adjoint; grid search + 20 Adam steps on (t, phi)
+    lower the photometric loss and move the estimate toward the true parameters."""
+    say("case: torch.autograd.Function and the (t, phi) refinement")
+    crops = synth.make_crops(4, 128, 5500)
+    truth = np.array([(2.2, 0.45, 0.2, 0.9, 1.0, -1.0), (1.7, 2.1, -0.5, 0.8, -2.0, 0.5),
+                      (3.1, 1.0, 1.2, 0.95, 0.0, 0.0), (1.4, 0.2, 0.0, 1.0, 0.5, 0.5)])
+    ref = [OD.warp_forward(crops[k], truth[k]) for k in range(4)]
+    targets = np.stack([r[0] for r in ref]).astype(np.float32)
+    tmasks = np.stack([r[1] for r in ref]).astype(np.uint8)
+    img = torch.from_numpy(crops).to(dev).requires_grad_(True)
+    par = torch.from_numpy(truth + np.array([0.1, 0.05, 0, 0, 0, 0])).to(dev).requires_grad_(True)
+    tgt = torch.from_numpy(targets).to(dev)
+    out, mask = X.warp_f32(img, par)
+    loss = (((out - tgt) * mask) ** 2).sum() * 0.5
+    loss.backward()
+    gi, gp = X.warp_f32_bwd(img.detach(), ((out - tgt) * mask).detach(), par.detach())
+    torch.cuda.synchronize()
+    assert torch.allclose(par.grad, gp, rtol=1e-6, atol=1e-9)
+    assert torch.allclose(img.grad, gi, rtol=1e-4, atol=1e-6)
+    grid = [(float(t), float(f)) for t, f in OP.sampling_grid(4)]
+    start = torch.from_numpy(truth.copy()).to(dev)
+    start[:, 0] = 1.0
+    start[:, 1] = 0.0
+    refined, grid_loss, ref_loss = X.refine_tilt(img.detach(), tgt, start, grid,
+                                                 torch.from_numpy(tmasks).to(dev), steps=20)
+    torch.cuda.synchronize()
+    refined = refined.cpu().numpy()
+    gl, rl = grid_loss.cpu().numpy(), ref_loss.cpu().numpy()
+    say(f"[refine] grid loss {np.round(gl, 6).tolist()} refined {np.round(rl, 6).tolist()}")
+    say(f"[refine] (t, phi) refined {np.round(refined[:, :2], 3).tolist()} truth {truth[:, :2].tolist()}")
+    # every crop improves on its grid point, and the refined tilt is closer to the truth
+    # than the grid's tilts on either side of it
+    assert np.all(rl < 0.5 * gl)
+    assert np.all(np.abs(refined[:, 0] - truth[:, 0]) < 0.1 * truth[:, 0])
+    assert np.all(np.abs(refined[:, 1] - truth[:, 1]) < 0.1)
