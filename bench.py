@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=4, help="views per image in the CPU-baseline sample")
     ap.add_argument("--cpu-pairs", type=int, default=64, help="view pairs in the CPU-baseline sample")
+    ap.add_argument("--batch-pairs", type=int, default=64, help="image pairs in the batched leg (0 = skip)")
+    ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--crops", type=int, default=256, help="crops in the differentiable-warp leg (0 = skip)")
     return ap.parse_args()
 
 
@@ -95,6 +98,149 @@ def cpu_baseline(case, grid, wl, n_views: int, n_pairs: int):
     }
 
 
+def _make_batch_pair(k):
+    import synth
+    p = synth.batch_pairs(1, seed=3000 + k)[0]
+    return p.A, p.B, p.meta
+
+
+def batched_leg(args, dev, pattern, raw, gen_s):
+    """Many pairs of uneven sizes (sides 480..2048, aspect 0.6..1.6, absolute tilt 0..80 deg),
+    45-view grid at scales 1 and 1/2, 8 levels, 500 keypoints: all pairs in one graph replay
+    (views in memory-bounded chunks, one matching launch) against the same pairs run one
+    after another through the same entry point, one synchronisation per pair."""
+    import numpy as np
+    import torch
+
+    from paper_2503_03479_amd import xaffine as X
+
+    K = len(raw)
+    pairs = [(A, np.ascontiguousarray(B)) for A, B, _ in raw]
+    grid = [(float(r["t"]), float(r["phi"])) for r in X.sampling_grid(5)]
+    kw = dict(n_levels=8, n_features=500, fast_threshold=20, device=dev)
+    stream = torch.cuda.current_stream()
+
+    # plain: one runner per pair (same entry point, one pair per call), one shared workspace
+    single = [X.BatchRunner([pr], grid, (1.0, 0.5), allocate_ws=False, **kw) for pr in pairs]
+    shared = X._empty(max(r.ws_bytes for r in single), dev)
+    for r in single:
+        r.set_workspace(shared)
+    for r in single[:2]:
+        r.run(pattern)
+    torch.cuda.synchronize()
+    steps = max(1, args.batch_steps)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for r in single:
+            r.run(pattern)
+            torch.cuda.synchronize()
+    plain_s = (time.perf_counter() - t0) / steps
+    del shared
+
+    batch = X.BatchRunner(pairs, grid, (1.0, 0.5), **kw)
+    batch.capture(pattern)
+    batch.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        batch.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    batch_s = (time.perf_counter() - t0) / steps
+    batch_ev_s = e0.elapsed_time(e1) / 1e3 / steps
+    batch.close()
+
+    # the batch reproduces the per-pair results exactly
+    same = True
+    for k, r in enumerate(single):
+        a0, na, b0, nb = batch.pair_views[k]
+        base = int(batch.mplan.groups[k]["pair_base"])
+        same &= bool(torch.equal(batch.best[k], r.best[0]))
+        same &= bool(torch.equal(batch.pair_count[base:base + na * nb], r.pair_count))
+        same &= bool(torch.equal(batch.desc[a0:a0 + na], r.desc[:na]))
+    sides = [(A.shape[1], A.shape[0], B.shape[1], B.shape[0]) for A, B in pairs]
+    comparisons = 0
+    counts = batch.count.cpu().numpy().astype(np.int64)
+    for (a0, na, b0, nb) in batch.pair_views:
+        comparisons += int(counts[a0:a0 + na].sum() * counts[b0:b0 + nb].sum())
+    return {
+        "workload": f"{K} pairs, sides 480..2048 (aspect 0.6..1.6), absolute tilt 0..80 deg, 45-view grid at "
+                    f"scales 1 and 1/2 (90 views per image), 8 levels, 500 keypoints, ratio 4/5",
+        "pairs_per_s_batched": K / batch_s,
+        "pairs_per_s_plain": K / plain_s,
+        "batched_over_plain": plain_s / batch_s,
+        "ms_per_batch": batch_s * 1e3,
+        "event_ms_per_batch": batch_ev_s * 1e3,
+        "ms_per_pair_plain": plain_s * 1e3 / K,
+        "plain": "the same entry point with one pair per call and a host synchronisation after each pair",
+        "batched": "one HIP graph replay: scale stage, then simulate + ORB in memory-bounded view chunks, then "
+                   "one matching launch over all pairs' view pairs",
+        "views": batch.n_views,
+        "chunks": len(batch.chunks),
+        "workspace_GiB": batch.ws.numel() / 2 ** 30,
+        "comparisons": comparisons,
+        "identical_to_plain": same,
+        "mean_side_px": float(np.mean([math.sqrt(a * b) for a, b, _, _ in sides])),
+        "generate_s": gen_s,
+    }
+
+
+def diffwarp_leg(args, dev):
+    """Differentiable warp on n fp32 crops of 512 x 512 (parameters drawn per crop):
+    forward and adjoint (image + six parameters) timed with HIP events."""
+    import torch
+
+    import synth
+    from paper_2503_03479_amd import xaffine as X
+
+    n = args.crops
+    crops = torch.from_numpy(synth.make_crops(n, 512, 5000, distinct=16)).to(dev)
+    par = torch.from_numpy(synth.crop_params(n, 5000)).to(dev)
+    g = torch.randn(crops.shape, generator=torch.Generator(device=dev).manual_seed(5), device=dev)
+    stream = torch.cuda.current_stream()
+    L = X.lib()
+    out = torch.empty_like(crops)
+    mask = torch.empty(crops.shape, dtype=torch.uint8, device=dev)
+    gimg = torch.empty_like(crops)
+    gpar = torch.empty((n, 6), dtype=torch.float64, device=dev)
+    ws = X._empty(L.xa_warp_f32_bwd_workspace_size(n, 512, 512), dev)
+
+    def fwd():
+        X._check(L.xa_warp_f32_fwd(X._ptr(crops), n, 512, 512, X._ptr(par), X._ptr(out), X._ptr(mask), X._stream()))
+
+    def bwd():
+        X._check(L.xa_warp_f32_bwd(X._ptr(crops), X._ptr(g), X._ptr(par), n, 512, 512, X._ptr(gimg), X._ptr(gpar),
+                                   X._ptr(ws), ws.numel(), X._stream()))
+
+    res = {}
+    for name, f in (("fwd", fwd), ("bwd", bwd)):
+        f()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record(stream)
+        for _ in range(reps):
+            f()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res[name] = e0.elapsed_time(e1) / reps
+    px = n * 512 * 512
+    valid = int(mask.sum())
+    return {
+        "workload": f"{n} fp32 crops of 512x512, t in [1, 6], phi in [0, pi), psi in [-pi, pi), s in [0.5, 1], "
+                    f"shifts in [-16, 16]",
+        "fwd_ms": res["fwd"], "bwd_ms": res["bwd"],
+        "crops_per_s_fwd": n / (res["fwd"] / 1e3),
+        # algorithmic bytes: crop read once, output (fp32) + mask (u8) written
+        "fwd_GBps": px * 9 / (res["fwd"] / 1e3) / 1e9,
+        # crop + output gradient read, image gradient written (its zero fill included)
+        "bwd_GBps": px * 16 / (res["bwd"] / 1e3) / 1e9,
+        "valid_fraction": valid / px,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -103,6 +249,16 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
+
+    # the batched leg's pairs are rendered by worker processes before this process touches the GPU
+    raw, gen_s = [], 0.0
+    if args.batch_pairs > 0:
+        import multiprocessing as mp
+        t0 = time.perf_counter()
+        with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
+            raw = pool.map(_make_batch_pair, range(args.batch_pairs))
+        gen_s = time.perf_counter() - t0
+
     import torch
 
     import synth
@@ -226,6 +382,11 @@ def main():
         "host_cpu": platform.processor() or platform.machine(),
         "host_cores": os.cpu_count(),
     }
+    del st, run
+    if args.batch_pairs > 0:
+        out["batched"] = batched_leg(args, dev, pattern, raw, gen_s)
+    if args.crops > 0:
+        out["diffwarp"] = diffwarp_leg(args, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, grid, wl, args.cpu_views, args.cpu_pairs)
     print(json.dumps(out), flush=True)

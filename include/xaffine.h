@@ -303,29 +303,37 @@ xa_status xa_match_pair(const void* plan_a_host, const void* plan_a_dev, const u
                         const xa_pair_buffers* out, void* d_ws, size_t ws_bytes, hipStream_t stream);
 
 /* Many image pairs at once: the scale stage (optional: splan may be NULL), the
- * simulation and ORB of every view of every image (one view plan over all
- * sources), and the group matching of every image pair (one match plan), as
- * one sequence of batched launches on `stream` (each stage is a single launch
- * over all images; blocks find their work through the plans' prefix tables).
- * Outputs: kp/desc/count for the view plan's views ([n_views][n_features]...),
- * matches/pair_count for the match plan's view pairs, best [n_groups][4].
- * xa_match_batch_capture records the same sequence into a HIP graph (on a
- * private stream, nothing is executed) that xa_graph_launch replays on any
- * stream; the graph keeps every pointer it was captured with.
- * Workspace: xa_match_batch_workspace_size(splan_host, vplan_host). */
+ * simulation and ORB of every view of every image, and the group matching of
+ * every image pair (one match plan), as one sequence of launches on `stream`.
+ * The views come as n_chunks view plans over one sources buffer (the scale
+ * stage writes its outputs into it first); chunk c is simulated and extracted
+ * with one launch per stage over all of its views, then the next chunk reuses
+ * the same scratch, so the workspace holds the largest chunk, not the batch.
+ * Views are numbered across the chunks in order (chunk 0's views first); the
+ * outputs kp/desc/count hold all of them ([total views][n_features]...), the
+ * match plan's groups use that numbering, matches/pair_count hold its view
+ * pairs and best [n_groups][4] its groups' best pairs.  Every view plan and the
+ * match plan must agree on n_features.  xa_match_batch_capture records the same
+ * sequence into a HIP graph (on a private stream; nothing is executed) that
+ * xa_graph_launch replays on any stream; the graph keeps every pointer it was
+ * captured with, and the host plan blobs need not outlive the capture.
+ * Workspace: xa_match_batch_workspace_size(splan_host, n_chunks, vplan_hosts)
+ * (0 for invalid plans). */
 typedef struct {
     xa_keypoint* kp; uint8_t* desc; int32_t* count;
     xa_match* matches; int32_t* pair_count; int32_t* best;
 } xa_batch_buffers;
 typedef struct xa_graph xa_graph;
-size_t xa_match_batch_workspace_size(const void* splan_host, const void* vplan_host);
-xa_status xa_match_batch(const void* splan_host, const void* splan_dev, const void* vplan_host, const void* vplan_dev,
-                         const void* mplan_host, const void* mplan_dev, uint8_t* d_sources, const int8_t* d_pattern,
-                         int32_t ratio_num, int32_t ratio_den, const xa_batch_buffers* out, void* d_ws,
-                         size_t ws_bytes, hipStream_t stream);
-xa_status xa_match_batch_capture(const void* splan_host, const void* splan_dev, const void* vplan_host,
-                                 const void* vplan_dev, const void* mplan_host, const void* mplan_dev,
-                                 uint8_t* d_sources, const int8_t* d_pattern, int32_t ratio_num, int32_t ratio_den,
+size_t xa_match_batch_workspace_size(const void* splan_host, int32_t n_chunks, const void* const* vplan_hosts);
+xa_status xa_match_batch(const void* splan_host, const void* splan_dev, int32_t n_chunks,
+                         const void* const* vplan_hosts, const void* const* vplan_devs, const void* mplan_host,
+                         const void* mplan_dev, uint8_t* d_sources, const int8_t* d_pattern, int32_t ratio_num,
+                         int32_t ratio_den, const xa_batch_buffers* out, void* d_ws, size_t ws_bytes,
+                         hipStream_t stream);
+xa_status xa_match_batch_capture(const void* splan_host, const void* splan_dev, int32_t n_chunks,
+                                 const void* const* vplan_hosts, const void* const* vplan_devs,
+                                 const void* mplan_host, const void* mplan_dev, uint8_t* d_sources,
+                                 const int8_t* d_pattern, int32_t ratio_num, int32_t ratio_den,
                                  const xa_batch_buffers* out, void* d_ws, size_t ws_bytes, xa_graph** graph);
 xa_status xa_graph_launch(xa_graph* graph, hipStream_t stream);
 xa_status xa_graph_destroy(xa_graph* graph);

@@ -3,7 +3,9 @@
 // the best one, as one asynchronous sequence of launches on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <new>
+#include <vector>
 
 #include "internal.h"
 
@@ -87,20 +89,32 @@ struct BatchWs {
     size_t scale, arena, mask, sim, ext, total;
 };
 
-BatchWs batch_layout(const void* splan_host, const xa_plan_header* h) {
+// Scale-stage scratch, then one region per chunk buffer, each sized for the largest chunk:
+// the chunks run one after another and reuse it.
+BatchWs batch_layout(const void* splan_host, const PlanView* ph, int n_chunks) {
+    size_t arena = 0, sim = 0, ext = 0;
+    for (int c = 0; c < n_chunks; ++c) {
+        arena = std::max(arena, size_t(ph[c].h->arena_bytes));
+        sim = std::max(sim, simulate_ws_bytes(ph[c].h));
+        ext = std::max(ext, extract_ws_layout(ph[c].h).total);
+    }
     BatchWs w{};
     size_t o = 0;
     w.scale = o; o = align_up(o + (splan_host ? xa_scale_workspace_size(splan_host) : 0));
-    w.arena = o; o = align_up(o + size_t(h->arena_bytes));
-    w.mask = o;  o = align_up(o + size_t(h->arena_bytes));
-    w.sim = o;   o = align_up(o + simulate_ws_bytes(h));
-    w.ext = o;   o = align_up(o + extract_ws_layout(h).total);
+    w.arena = o; o = align_up(o + arena);
+    w.mask = o;  o = align_up(o + arena);
+    w.sim = o;   o = align_up(o + sim);
+    w.ext = o;   o = align_up(o + ext);
     w.total = o;
     return w;
 }
 
 struct BatchArgs {
-    const void *splan_host, *splan_dev, *vplan_host, *vplan_dev, *mplan_host, *mplan_dev;
+    const void *splan_host, *splan_dev;
+    int n_chunks;
+    const void* const* vplan_hosts;
+    const void* const* vplan_devs;
+    const void *mplan_host, *mplan_dev;
     uint8_t* sources;
     const int8_t* pattern;
     int32_t num, den;
@@ -109,39 +123,64 @@ struct BatchArgs {
     size_t ws_bytes;
 };
 
-xa_status batch_check(const BatchArgs& a, PlanView* ph, BatchWs* w) {
+xa_status chunk_views(int n_chunks, const void* const* hosts, std::vector<PlanView>* ph) {
+    if (n_chunks < 1 || n_chunks > (1 << 20) || !hosts) return fail(XA_EINVAL, "need at least one view plan");
+    ph->resize(n_chunks);
+    for (int c = 0; c < n_chunks; ++c) {
+        const xa_status s = plan_host_view(hosts[c], &(*ph)[c]);
+        if (s != XA_OK) return s;
+        if ((*ph)[c].h->n_features != (*ph)[0].h->n_features)
+            return fail(XA_EINVAL, "view plans %d and 0 disagree on n_features", c);
+    }
+    return XA_OK;
+}
+
+xa_status batch_check(const BatchArgs& a, std::vector<PlanView>* ph, BatchWs* w) {
     if (a.splan_host && !is_scale_plan(a.splan_host)) return fail(XA_EINVAL, "not a scale plan");
     if (a.splan_host && !a.splan_dev) return fail(XA_EINVAL, "scale plan without a device copy");
-    xa_status s = plan_host_view(a.vplan_host, ph);
+    xa_status s = chunk_views(a.n_chunks, a.vplan_hosts, ph);
     if (s != XA_OK) return s;
+    if (!a.vplan_devs) return fail(XA_EINVAL, "NULL device plan array");
+    long long views = 0;
+    for (int c = 0; c < a.n_chunks; ++c) {
+        if (!a.vplan_devs[c]) return fail(XA_EINVAL, "view plan %d has no device copy", c);
+        views += (*ph)[c].h->n_views;
+    }
+    if (views > INT32_MAX) return fail(XA_EUNSUPPORTED, "too many views");
     MatchPlanView mv;
     s = match_plan_view(a.mplan_host, &mv);
     if (s != XA_OK) return s;
-    if (mv.h->n_features != ph->h->n_features) return fail(XA_EINVAL, "view and match plans disagree on n_features");
-    if (mv.h->views_needed > ph->h->n_views)
-        return fail(XA_EINVAL, "match plan reads %d views, view plan has %d", mv.h->views_needed, ph->h->n_views);
-    if (!a.vplan_dev || !a.mplan_dev || !a.sources || !a.pattern) return fail(XA_EINVAL, "NULL pointer");
+    if (mv.h->n_features != (*ph)[0].h->n_features)
+        return fail(XA_EINVAL, "view and match plans disagree on n_features");
+    if (mv.h->views_needed > views)
+        return fail(XA_EINVAL, "match plan reads %d views, the view plans hold %lld", mv.h->views_needed, views);
+    if (!a.mplan_dev || !a.sources || !a.pattern) return fail(XA_EINVAL, "NULL pointer");
     const xa_batch_buffers& o = a.out;
     if (!o.kp || !o.desc || !o.count || !o.matches || !o.pair_count || !o.best)
         return fail(XA_EINVAL, "NULL output buffer");
     if (a.num < 0 || a.den < 1 || a.num > (1 << 20) || a.den > (1 << 20)) return fail(XA_EINVAL, "bad ratio");
-    *w = batch_layout(a.splan_host, ph->h);
+    *w = batch_layout(a.splan_host, ph->data(), a.n_chunks);
     if (a.ws_bytes < w->total) return fail(XA_ECAPACITY, "batch workspace needs %zu bytes, got %zu", w->total, a.ws_bytes);
     if (!a.ws || reinterpret_cast<uintptr_t>(a.ws) % kAlign) return fail(XA_EINVAL, "workspace must be 256-byte aligned");
     return XA_OK;
 }
 
-xa_status batch_launch(const BatchArgs& a, const PlanView& ph, const BatchWs& w, hipStream_t st) {
+xa_status batch_launch(const BatchArgs& a, const std::vector<PlanView>& ph, const BatchWs& w, hipStream_t st) {
     xa_status s = XA_OK;
     if (a.splan_host) s = launch_scale(a.splan_host, a.splan_dev, a.sources, nullptr, a.ws + w.scale, st);
     if (s != XA_OK) return s;
-    const PlanView pd = plan_dev_view(a.vplan_host, a.vplan_dev);
-    s = launch_simulate(ph, pd, a.sources, a.ws + w.arena, a.ws + w.mask, nullptr,
-                        reinterpret_cast<float*>(a.ws + w.sim), st);
-    if (s != XA_OK) return s;
-    s = launch_extract(ph, pd, a.ws + w.arena, a.ws + w.mask, a.pattern, a.out.kp, a.out.desc, a.out.count,
-                       a.ws + w.ext, st);
-    if (s != XA_OK) return s;
+    const size_t N = size_t(ph[0].h->n_features);
+    size_t v0 = 0;
+    for (int c = 0; c < a.n_chunks; ++c) {
+        const PlanView pd = plan_dev_view(a.vplan_hosts[c], a.vplan_devs[c]);
+        s = launch_simulate(ph[c], pd, a.sources, a.ws + w.arena, a.ws + w.mask, nullptr,
+                            reinterpret_cast<float*>(a.ws + w.sim), st);
+        if (s != XA_OK) return s;
+        s = launch_extract(ph[c], pd, a.ws + w.arena, a.ws + w.mask, a.pattern, a.out.kp + v0 * N,
+                           a.out.desc + v0 * N * 32, a.out.count + v0, a.ws + w.ext, st);
+        if (s != XA_OK) return s;
+        v0 += size_t(ph[c].h->n_views);
+    }
     return launch_match_plan(a.mplan_host, a.mplan_dev, a.out.desc, a.out.count, a.num, a.den, a.out.matches,
                              a.out.pair_count, a.out.best, st);
 }
@@ -154,21 +193,23 @@ struct xa_graph {
     hipGraphExec_t exec = nullptr;
 };
 
-extern "C" size_t xa_match_batch_workspace_size(const void* splan_host, const void* vplan_host) {
-    PlanView ph;
-    if (plan_host_view(vplan_host, &ph) != XA_OK) return 0;
+extern "C" size_t xa_match_batch_workspace_size(const void* splan_host, int32_t n_chunks,
+                                                const void* const* vplan_hosts) {
+    std::vector<PlanView> ph;
+    if (chunk_views(n_chunks, vplan_hosts, &ph) != XA_OK) return 0;
     if (splan_host && !is_scale_plan(splan_host)) return 0;
-    return batch_layout(splan_host, ph.h).total;
+    return batch_layout(splan_host, ph.data(), n_chunks).total;
 }
 
-extern "C" xa_status xa_match_batch(const void* splan_host, const void* splan_dev, const void* vplan_host,
-                                    const void* vplan_dev, const void* mplan_host, const void* mplan_dev,
-                                    uint8_t* d_sources, const int8_t* d_pattern, int32_t ratio_num, int32_t ratio_den,
+extern "C" xa_status xa_match_batch(const void* splan_host, const void* splan_dev, int32_t n_chunks,
+                                    const void* const* vplan_hosts, const void* const* vplan_devs,
+                                    const void* mplan_host, const void* mplan_dev, uint8_t* d_sources,
+                                    const int8_t* d_pattern, int32_t ratio_num, int32_t ratio_den,
                                     const xa_batch_buffers* out, void* d_ws, size_t ws_bytes, hipStream_t stream) {
     if (!out) return fail(XA_EINVAL, "NULL output buffers");
-    const BatchArgs a{splan_host, splan_dev, vplan_host, vplan_dev, mplan_host, mplan_dev, d_sources, d_pattern,
-                      ratio_num, ratio_den, *out, static_cast<uint8_t*>(d_ws), ws_bytes};
-    PlanView ph;
+    const BatchArgs a{splan_host, splan_dev, n_chunks, vplan_hosts, vplan_devs, mplan_host, mplan_dev, d_sources,
+                      d_pattern, ratio_num, ratio_den, *out, static_cast<uint8_t*>(d_ws), ws_bytes};
+    std::vector<PlanView> ph;
     BatchWs w;
     xa_status s = batch_check(a, &ph, &w);
     if (s != XA_OK) return s;
@@ -176,16 +217,17 @@ extern "C" xa_status xa_match_batch(const void* splan_host, const void* splan_de
     return s == XA_OK ? ok() : s;
 }
 
-extern "C" xa_status xa_match_batch_capture(const void* splan_host, const void* splan_dev, const void* vplan_host,
-                                            const void* vplan_dev, const void* mplan_host, const void* mplan_dev,
-                                            uint8_t* d_sources, const int8_t* d_pattern, int32_t ratio_num,
-                                            int32_t ratio_den, const xa_batch_buffers* out, void* d_ws,
-                                            size_t ws_bytes, xa_graph** graph) {
+extern "C" xa_status xa_match_batch_capture(const void* splan_host, const void* splan_dev, int32_t n_chunks,
+                                            const void* const* vplan_hosts, const void* const* vplan_devs,
+                                            const void* mplan_host, const void* mplan_dev, uint8_t* d_sources,
+                                            const int8_t* d_pattern, int32_t ratio_num, int32_t ratio_den,
+                                            const xa_batch_buffers* out, void* d_ws, size_t ws_bytes,
+                                            xa_graph** graph) {
     if (!out || !graph) return fail(XA_EINVAL, "NULL pointer");
     *graph = nullptr;
-    const BatchArgs a{splan_host, splan_dev, vplan_host, vplan_dev, mplan_host, mplan_dev, d_sources, d_pattern,
-                      ratio_num, ratio_den, *out, static_cast<uint8_t*>(d_ws), ws_bytes};
-    PlanView ph;
+    const BatchArgs a{splan_host, splan_dev, n_chunks, vplan_hosts, vplan_devs, mplan_host, mplan_dev, d_sources,
+                      d_pattern, ratio_num, ratio_den, *out, static_cast<uint8_t*>(d_ws), ws_bytes};
+    std::vector<PlanView> ph;
     BatchWs w;
     xa_status s = batch_check(a, &ph, &w);
     if (s != XA_OK) return s;

@@ -97,11 +97,14 @@ _SIGS = {
                                    _c.POINTER(_c.c_size_t)]),
     "xa_match_groups": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_int32,
                                    _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p]),
-    "xa_match_batch_workspace_size": (_c.c_size_t, [_c.c_void_p, _c.c_void_p]),
-    "xa_match_batch": (_c.c_int, [_c.c_void_p] * 8 + [_c.c_int32, _c.c_int32, _c.c_void_p, _c.c_void_p,
-                                                      _c.c_size_t, _c.c_void_p]),
-    "xa_match_batch_capture": (_c.c_int, [_c.c_void_p] * 8 + [_c.c_int32, _c.c_int32, _c.c_void_p, _c.c_void_p,
-                                                              _c.c_size_t, _c.POINTER(_c.c_void_p)]),
+    "xa_match_batch_workspace_size": (_c.c_size_t, [_c.c_void_p, _c.c_int32, _c.c_void_p]),
+    "xa_match_batch": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                  _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_int32, _c.c_void_p,
+                                  _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "xa_match_batch_capture": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p,
+                                          _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32,
+                                          _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_size_t,
+                                          _c.POINTER(_c.c_void_p)]),
     "xa_graph_launch": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
     "xa_graph_destroy": (_c.c_int, [_c.c_void_p]),
     "xa_warp_f32_fwd": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_void_p, _c.c_void_p,
@@ -539,72 +542,125 @@ def match_groups(mplan: MatchPlan, desc, count, ratio_num: int = 4, ratio_den: i
 
 
 class BatchRunner:
-    """Many image pairs through the batched path: one sources buffer (originals + scale-stage
-    outputs), one view plan over all images, one match plan with a group per image pair."""
+    """Many image pairs through the batched path.
+
+    One sources buffer holds the originals and the scale-stage outputs; the views of
+    consecutive image pairs are grouped into chunks (one view plan each) whose
+    simulation and ORB workspace stays under `chunk_bytes`; one match plan has a group
+    per image pair.  `pair_views[k]` = (first view of A, n views of A, first view of B,
+    n views of B) in the global view numbering.  `ws` may bring a workspace (a uint8
+    device tensor of at least `ws_bytes`, 256-byte aligned) shared with other runners
+    that are not in flight at the same time, or be set later (allocate_ws=False, then
+    set_workspace)."""
 
     def __init__(self, pairs, grid, scales=(1.0,), n_levels: int = 8, n_features: int = 500,
-                 fast_threshold: int = 20, device="cuda", queries_per_lane: int = 0):
+                 fast_threshold: int = 20, device="cuda", queries_per_lane: int = 0,
+                 chunk_bytes: int = 24 << 30, ws=None, allocate_ws: bool = True):
         import torch
         self.device = torch.device(device)
+        L = lib()
         arena = SourceArena()
-        jobs, vsrc, params, groups = [], [], [], []
-        rows = [(float(r["t"]), float(r["phi"])) for r in grid] if isinstance(grid, np.ndarray) else list(grid)
-        self.image_index = []        # (pair, side) -> original source index
-        images = {}
-        view_base = 0
-        for pi, (A, B) in enumerate(pairs):
-            ranges = []
+        jobs, images = [], {}
+        rows = [(float(t), float(f)) for t, f in grid]
+        pair_views = []          # per pair: list over sides of [(source index, scale)]
+        for (A, B) in pairs:
+            sides = []
             for img in (A, B):
                 si = arena.add(img.shape[1], img.shape[0])
                 images[si] = img
                 srcs = []
-                for s in scales:
-                    if s == 1.0:
+                for sc in scales:
+                    if sc == 1.0:
                         srcs.append(si)
                     else:
-                        w, h = scaled_size(img.shape[1], img.shape[0], s)
-                        di = arena.add(w, h, s)
-                        jobs.append((arena.descs[si], arena.descs[di], s))
+                        w, h = scaled_size(img.shape[1], img.shape[0], sc)
+                        di = arena.add(w, h, sc)
+                        jobs.append((arena.descs[si], arena.descs[di], sc))
                         srcs.append(di)
-                start = view_base
-                for src in srcs:
-                    for (t, phi) in rows:
-                        vsrc.append(src)
-                        params.append((t, phi, 0.0, 1.0, 0.0, 0.0))
-                        view_base += 1
-                ranges.append((start, view_base - start))
-            (a0, na), (b0, nb) = ranges
-            groups.append((a0, na, b0, nb, 0))
-        base = 0
-        for i, g in enumerate(groups):
-            groups[i] = g[:4] + (base,)
-            base += g[1] * g[3]
+                sides.append(srcs)
+            pair_views.append(sides)
+        table = arena.table()
+
+        def pair_plan(ps):
+            vsrc, params = [], []
+            for sides in ps:
+                for srcs in sides:
+                    for src in srcs:
+                        for (t, phi) in rows:
+                            vsrc.append(src)
+                            params.append((t, phi, 0.0, 1.0, 0.0, 0.0))
+            return plan_views(table, vsrc, np.array(params, PARAMS_DTYPE), n_levels, 1.2, n_features,
+                              fast_threshold), vsrc
+
+        def chunk_ws(plan):
+            ptrs = (ctypes.c_void_p * 1)(plan.host_ptr())
+            return L.xa_match_batch_workspace_size(None, 1, ptrs)
+
+        # greedy chunks of whole pairs under the workspace budget (a chunk's scratch is the
+        # sum of its pairs' scratch: arena, blur and candidate space add up view by view)
+        per_pair = [chunk_ws(pair_plan([pv])[0]) for pv in pair_views]
+        self.chunks, vsrc_all, cur, cur_bytes = [], [], [], 0
+        for k, pv in enumerate(pair_views):
+            if cur and cur_bytes + per_pair[k] > chunk_bytes:
+                plan0, vs0 = pair_plan(cur)
+                self.chunks.append(plan0)
+                vsrc_all += vs0
+                cur, cur_bytes = [], 0
+            cur.append(pv)
+            cur_bytes += per_pair[k]
+        if cur:
+            plan0, vs0 = pair_plan(cur)
+            self.chunks.append(plan0)
+            vsrc_all += vs0
+        nvs = len(rows) * len(scales)
+        groups, self.pair_views, base, v = [], [], 0, 0
+        for _ in pairs:
+            a0, b0 = v, v + nvs
+            groups.append((a0, nvs, b0, nvs, base))
+            self.pair_views.append((a0, nvs, b0, nvs))
+            base += nvs * nvs
+            v += 2 * nvs
         self.arena = arena
         self.splan = plan_scales(np.array(jobs, SCALE_JOB_DTYPE)) if jobs else None
-        self.vplan = plan_views(arena.table(), vsrc, np.array(params, PARAMS_DTYPE), n_levels, 1.2, n_features,
-                                fast_threshold)
         self.mplan = plan_matches(np.array(groups, GROUP_DTYPE), n_features, queries_per_lane)
-        self.view_scale = np.array([arena.descs[s][5] for s in vsrc])
+        self.view_scale = np.array([arena.descs[s][5] for s in vsrc_all])
+        self.n_views = len(vsrc_all)
         dev = self.device
         self.sources = torch.from_numpy(arena.pack(images)).to(dev)
-        nv, N = self.vplan.n_views, n_features
+        nv, N = self.n_views, n_features
         z = lambda *sh, dt=torch.uint8: torch.zeros(sh, dtype=dt, device=dev)  # noqa: E731
         self.kp, self.desc, self.count = z(nv, N, 40), z(nv, N, 32), z(nv, dt=torch.int32)
         P = self.mplan.total_pairs
         self.matches, self.pair_count = z(P, N, 8), z(P, dt=torch.int32)
         self.best = z(len(groups), 4, dt=torch.int32)
+        nc = len(self.chunks)
+        self._hosts = (ctypes.c_void_p * nc)(*[c.host_ptr() for c in self.chunks])
+        self._devs = (ctypes.c_void_p * nc)(*[_ptr(c.device(dev)) for c in self.chunks])
         sp = self.splan.host_ptr() if self.splan else None
-        need = lib().xa_match_batch_workspace_size(sp, self.vplan.host_ptr())
-        self.ws = _empty(need, dev)
+        need = L.xa_match_batch_workspace_size(sp, nc, self._hosts)
+        if need == 0:
+            raise XAError(-1, "invalid batch plans")
+        self.ws_bytes = need
+        if ws is not None and ws.numel() < need:
+            raise XAError(-2, f"batch workspace needs {need} bytes, got {ws.numel()}")
+        self.ws = ws if ws is not None else (_empty(need, dev) if allocate_ws else None)
         self.bufs = _BatchBuffers(*[_ptr(t) for t in (self.kp, self.desc, self.count, self.matches,
                                                       self.pair_count, self.best)])
-        self._args = None
         self.graph = None
 
+    def set_workspace(self, ws):
+        """Use `ws` (uint8 device tensor of at least ws_bytes) from now on."""
+        if ws.numel() < self.ws_bytes:
+            raise XAError(-2, f"batch workspace needs {self.ws_bytes} bytes, got {ws.numel()}")
+        self.close()
+        self.ws = ws
+
     def _call_args(self):
+        if self.ws is None:
+            raise XAError(-1, "no workspace: pass ws or call set_workspace")
         sp = self.splan.host_ptr() if self.splan else None
         sd = _ptr(self.splan.device(self.device)) if self.splan else None
-        return (sp, sd, self.vplan.host_ptr(), _ptr(self.vplan.device(self.device)), self.mplan.host_ptr(),
+        return (sp, sd, len(self.chunks), self._hosts, self._devs, self.mplan.host_ptr(),
                 _ptr(self.mplan.device(self.device)), _ptr(self.sources))
 
     def run(self, pattern, ratio_num: int = 4, ratio_den: int = 5):
@@ -612,6 +668,7 @@ class BatchRunner:
                                     _ptr(self.ws), self.ws.numel(), _stream()))
 
     def capture(self, pattern, ratio_num: int = 4, ratio_den: int = 5):
+        self.close()
         g = ctypes.c_void_p(0)
         _check(lib().xa_match_batch_capture(*self._call_args(), _ptr(pattern), ratio_num, ratio_den,
                                             ctypes.byref(self.bufs), _ptr(self.ws), self.ws.numel(), ctypes.byref(g)))
@@ -619,6 +676,8 @@ class BatchRunner:
         self._pattern = pattern       # the graph reads this buffer on every replay
 
     def replay(self):
+        if not self.graph:
+            raise XAError(-1, "no captured graph")
         _check(lib().xa_graph_launch(self.graph, _stream()))
 
     def close(self):

@@ -152,13 +152,34 @@ def test_batch_equals_stages_with_scales(dev, pairs):
     buf = src0.clone()
     X.scale_sources(br.splan, buf)
     assert torch.equal(buf, br.sources)
-    arena, mask = X.simulate_views(br.vplan, buf)
-    kp, desc, count = X.extract_orb(br.vplan, arena, mask, pat)
+    assert len(br.chunks) == 1
+    arena, mask = X.simulate_views(br.chunks[0], buf)
+    kp, desc, count = X.extract_orb(br.chunks[0], arena, mask, pat)
     m, pc, best = X.match_groups(br.mplan, desc, count)
     torch.cuda.synchronize()
     assert torch.equal(kp, br.kp) and torch.equal(desc, br.desc) and torch.equal(count, br.count)
     assert torch.equal(m, br.matches) and torch.equal(pc, br.pair_count) and torch.equal(best, br.best)
     say(f"[batch/scales] stage-by-stage identical; best per pair {best.tolist()}")
+
+
+def test_batch_chunks_give_the_same_result(dev, pairs):
+    """The same batch run as one chunk and as one chunk per pair (a tiny workspace budget):
+    identical outputs, and the chunked workspace is the largest pair's, not the sum."""
+    say("case: batch of 3 pairs (scales 1 and 0.5) as 1 chunk vs 3 chunks")
+    grid = _grid(2)
+    pat = torch.from_numpy(synth.brief_pattern()).to(dev)
+    imgs = [(p.A, np.ascontiguousarray(p.B)) for p in pairs]
+    one = X.BatchRunner(imgs, grid, (1.0, 0.5), n_levels=3, n_features=300, device=dev)
+    many = X.BatchRunner(imgs, grid, (1.0, 0.5), n_levels=3, n_features=300, device=dev, chunk_bytes=1)
+    assert len(one.chunks) == 1 and len(many.chunks) == 3
+    assert many.ws.numel() < one.ws.numel()
+    one.run(pat)
+    many.run(pat)
+    torch.cuda.synchronize()
+    for a, b in zip((one.kp, one.desc, one.count, one.matches, one.pair_count, one.best),
+                    (many.kp, many.desc, many.count, many.matches, many.pair_count, many.best)):
+        assert torch.equal(a, b)
+    say(f"[chunks] identical; workspace {one.ws.numel() >> 20} MiB as one chunk, {many.ws.numel() >> 20} MiB in 3")
 
 
 def test_batch_scaled_pair_vs_oracle(dev, pairs):
@@ -200,7 +221,8 @@ def test_batch_graph_replays(dev, pairs):
     grid = _grid(1)
     pat = torch.from_numpy(synth.brief_pattern()).to(dev)
     imgs = [(p.A, np.ascontiguousarray(p.B)) for p in pairs]
-    br = X.BatchRunner(imgs, grid, (1.0, 0.5), n_levels=3, n_features=200, device=dev)
+    br = X.BatchRunner(imgs, grid, (1.0, 0.5), n_levels=3, n_features=200, device=dev, chunk_bytes=1)
+    assert len(br.chunks) == 3
     br.run(pat)
     torch.cuda.synchronize()
     ref = [t.clone() for t in (br.kp, br.desc, br.count, br.matches, br.pair_count, br.best)]

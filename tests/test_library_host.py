@@ -161,3 +161,29 @@ def test_match_groups_rejects_views_outside_the_set():
     fake = ctypes.c_void_p(256)               # never dereferenced: the check comes first
     st = X.lib().xa_match_groups(mp.host_ptr(), fake, fake, fake, 6, 4, 5, fake, fake, fake, None)
     assert st == -1 and b"views" in X.lib().xa_last_error()
+
+
+def test_batch_chunking_on_host():
+    """BatchRunner's planning (no device work): views are numbered pair by pair, each
+    pair is one match group, and a small budget splits the views into one chunk per pair
+    whose workspace is the largest pair's."""
+    import synth
+    torch = pytest.importorskip("torch")
+    pairs = [synth.make_pair(w, h, 10, 8, seed, 1.5, 0.0, 0.3, supersample=1)
+             for (w, h, seed) in ((96, 80, 1), (120, 64, 2), (64, 64, 3))]
+    imgs = [(p.A, np.ascontiguousarray(p.B)) for p in pairs]
+    grid = [(t, f) for t, f in OP.sampling_grid(1)]
+    one = X.BatchRunner(imgs, grid, (1.0, 0.5), n_levels=2, n_features=64, device="cpu")
+    many = X.BatchRunner(imgs, grid, (1.0, 0.5), n_levels=2, n_features=64, device="cpu", chunk_bytes=1)
+    nvs = 2 * len(grid)
+    assert len(one.chunks) == 1 and len(many.chunks) == 3
+    assert one.n_views == many.n_views == 3 * 2 * nvs
+    assert sum(c.n_views for c in many.chunks) == many.n_views
+    assert [tuple(g)[:4] for g in many.mplan.groups] == [(2 * k * nvs, nvs, (2 * k + 1) * nvs, nvs) for k in range(3)]
+    assert many.mplan.total_pairs == 3 * nvs * nvs
+    per = [X.lib().xa_match_batch_workspace_size(None, 1, (ctypes.c_void_p * 1)(c.host_ptr())) for c in many.chunks]
+    assert many.ws.numel() <= max(per) + X.lib().xa_scale_workspace_size(many.splan.host_ptr()) + 4096
+    assert many.ws.numel() < one.ws.numel()
+    # scale-0.5 views come from the scale stage's outputs
+    assert np.array_equal(np.unique(many.view_scale), [0.5, 1.0])
+    del torch
