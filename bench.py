@@ -30,6 +30,25 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 HBM_PEAK_BPS = 8.0e12
 HAMMING_OPS_PER_CMP = 16          # 8 x v_xor_b32 + 8 x v_bcnt_u32_b32 per 256-bit comparison
 
+# HBM traffic of k_match on the full-size pair, from two rocprofv3 --pmc passes (FETCH_SIZE, then
+# WRITE_SIZE; KiB per dispatch), scaled by what the same counters read for a plain 1 GiB
+# device-to-device copy (FETCH_SIZE reads 0.5 GiB there, WRITE_SIZE 1 GiB).  Valid only for the
+# matcher source it was measured on: any change to that file reports null.
+K_MATCH_TRAFFIC = {
+    "source": "paper_2503_03479_amd/csrc/match.hip",
+    "sha256": "51c06c6e1ec8b0637e1c13e74da0b668b5f0b19e2c0122ae815110de1a15370b",
+    "fetch_kib": 10801.8, "write_kib": 15555.9, "fetch_scale": 2.0, "write_scale": 1.0,
+}
+
+
+def k_match_traffic():
+    import hashlib
+    with open(os.path.join(ROOT, K_MATCH_TRAFFIC["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != K_MATCH_TRAFFIC["sha256"]:
+            return None
+    t = K_MATCH_TRAFFIC
+    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -43,6 +62,9 @@ def parse():
     ap.add_argument("--batch-pairs", type=int, default=64, help="image pairs in the batched leg (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--crops", type=int, default=256, help="crops in the differentiable-warp leg (0 = skip)")
+    ap.add_argument("--only", choices=["batched", "diffwarp", "copy"], default=None,
+                    help="run one leg alone and print its JSON (for profiler runs); 'copy' is a plain 1 GiB "
+                         "device-to-device copy whose counter readings calibrate the HBM traffic counters")
     return ap.parse_args()
 
 
@@ -252,7 +274,7 @@ def main():
 
     # the batched leg's pairs are rendered by worker processes before this process touches the GPU
     raw, gen_s = [], 0.0
-    if args.batch_pairs > 0:
+    if args.batch_pairs > 0 and args.only in (None, "batched"):
         import multiprocessing as mp
         t0 = time.perf_counter()
         with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
@@ -268,6 +290,21 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.only is not None:
+        pattern = torch.from_numpy(synth.brief_pattern()).to(dev)
+        if args.only == "batched":
+            print(json.dumps(batched_leg(args, dev, pattern, raw, gen_s)), flush=True)
+        elif args.only == "diffwarp":
+            print(json.dumps(diffwarp_leg(args, dev)), flush=True)
+        else:
+            a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+            b = torch.empty_like(a)
+            for _ in range(3):
+                b.copy_(a)
+            torch.cuda.synchronize()
+            print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4,
+                              "dispatches": 3}), flush=True)
+        return
     wl = WORKLOADS[args.workload]
     cfg = synth.PAIR_CONFIGS[args.workload]
     case = synth.make_pair(**cfg)
@@ -325,6 +362,9 @@ def main():
 
     # dominant kernel: k_match (xa_match_views = a counter fill, k_match, a one-block argmax)
     match_s = stage_ms["match"] / 1e3
+    # descriptor sets read once + the match records and counts written
+    n_pairs = pa.n_views * pb.n_views
+    algo_bytes = (pa.n_views + pb.n_views) * wl["n_features"] * 32 + n_pairs * wl["n_features"] * 8 + n_pairs * 4
     achieved_ops = comparisons * HAMMING_OPS_PER_CMP / match_s
     roofline = {
         "kernel": "k_match (xa_match_views)",
@@ -333,7 +373,9 @@ def main():
         "peak": VALU_PEAK_OPS / 1e12,
         "unit": "Tops/s",
         "frac": achieved_ops / VALU_PEAK_OPS,
-        "traffic": None,
+        "traffic": k_match_traffic(),
+        "traffic_unit": "bytes per launch (HBM, counter-measured)",
+        "algorithmic_bytes_per_launch": algo_bytes,
         "algorithmic_ops_per_launch": comparisons * HAMMING_OPS_PER_CMP,
         "comparisons_per_launch": comparisons,
         "comparisons_per_s": comparisons / match_s,
