@@ -98,7 +98,8 @@ typedef struct {
     double sigma;
     double ux, uy;
     int64_t offset;             /* byte offset of level 0 in the pyramid arena */
-    int64_t blur_offset;        /* float offset of the blurred source in the simulate workspace, -1 if none */
+    int64_t blur_offset;        /* float offset of the blurred source in the simulate workspace, -1 if none;
+                                   its rows are (src_w + 3) / 4 * 4 floats apart */
     int32_t blur_major;         /* 0: taps step along x, 1: along y */
     int32_t blur_tap0;          /* first entry in the tap table */
     int32_t blur_ntaps;         /* 2K + 1, 0 if no blur */

@@ -42,6 +42,8 @@ static_assert(sizeof(xa_match) == 8, "match layout");
 
 inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
 inline int32_t level_pitch(int32_t w) { return (w + 15) / 16 * 16; }
+// Row pitch (floats) of a blurred source: rows start 16-byte aligned so the warp stages them in float4s.
+__host__ __device__ inline int32_t blur_pitch(int32_t w) { return (w + 3) & ~3; }
 
 // Candidate record written by the FAST kernel: raster position y * W + x and Harris response.
 struct Cand {

@@ -266,7 +266,7 @@ extern "C" xa_status xa_plan_views(const xa_source_desc* sources, int32_t n_sour
         xa_view_desc& v = pv[i].v;
         if (v.sigma > 0.0) {
             v.blur_offset = blur_floats;
-            blur_floats += int64_t(v.src_w) * v.src_h;
+            blur_floats += int64_t(blur_pitch(v.src_w)) * v.src_h;
             v.blur_tap0 = int32_t(taps.size());
             taps.insert(taps.end(), pv[i].taps.begin(), pv[i].taps.end());
             blur_views.push_back(i);

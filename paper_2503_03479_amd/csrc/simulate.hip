@@ -123,7 +123,7 @@ __global__ void __launch_bounds__(256) k_blur(const uint8_t* __restrict__ source
                     }
                 }
             }
-            o[size_t(y) * W + x] = acc;
+            o[size_t(y) * blur_pitch(W) + x] = acc;
         }
         return;
     }
@@ -151,7 +151,7 @@ __global__ void __launch_bounds__(256) k_blur(const uint8_t* __restrict__ source
                 acc += t.wa * a + t.wb * b;
             }
         }
-        o[size_t(y) * W + x] = acc;
+        o[size_t(y) * blur_pitch(W) + x] = acc;
     }
 }
 
@@ -228,43 +228,119 @@ __global__ void __launch_bounds__(kWarpThreads) k_warp(const uint8_t* __restrict
     const int x0 = (local % tiles_x) * tw, y0 = (local / tiles_x) * th;
     const int qx = x0 + int(threadIdx.x) % tw, qy = y0 + int(threadIdx.x) / tw;
     // bounding box of the footprint (the tile's pixel centres through inv, grown by the
-    // 8-tap window, clamped to the source); every thread derives the same box
-    double pxl = 1e300, pxh = -1e300, pyl = 1e300, pyh = -1e300;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const double cx = double(x0 + ((c & 1) ? tw - 1 : 0)), cy = double(y0 + ((c & 2) ? th - 1 : 0));
-        const double px = affine_x(v.inv, cx, cy), py = affine_x(v.inv + 3, cx, cy);
-        pxl = fmin(pxl, px); pxh = fmax(pxh, px);
-        pyl = fmin(pyl, py); pyh = fmax(pyh, py);
-    }
+    // 8-tap window, clamped to the source): the corner (x0, y0) plus the extreme offsets of
+    // the other corners; rounding here is ~1e-12 px, far inside the 1e-6 margin
+    const double ox = v.inv[0] * double(tw - 1), oy = v.inv[1] * double(th - 1);
+    const double o2x = v.inv[3] * double(tw - 1), o2y = v.inv[4] * double(th - 1);
+    const double cx0 = affine_x(v.inv, double(x0), double(y0)), cy0 = affine_x(v.inv + 3, double(x0), double(y0));
+    const double pxl = cx0 + fmin(ox, 0.0) + fmin(oy, 0.0), pxh = cx0 + fmax(ox, 0.0) + fmax(oy, 0.0);
+    const double pyl = cy0 + fmin(o2x, 0.0) + fmin(o2y, 0.0), pyh = cy0 + fmax(o2x, 0.0) + fmax(o2y, 0.0);
     const int bx0 = max(int(fmax(floor(pxl - 1e-6), -1e9)) - 3, 0);
     const int bx1 = min(int(fmin(floor(pxh + 1e-6), 1e9)) + 4, W - 1);
     const int by0 = max(int(fmax(floor(pyl - 1e-6), -1e9)) - 3, 0);
     const int by1 = min(int(fmin(floor(pyh + 1e-6), 1e9)) + 4, H - 1);
-    const int bw = bx1 - bx0 + 1, bh = by1 - by0 + 1;
-    const int ls = bw | 1;                  // odd LDS row stride: vertically adjacent taps fall in different banks
-    const bool use_lds = bw > 0 && bh > 0 && (long long)ls * bh <= kWarpLds;
+    const int bh = by1 - by0 + 1;
     const bool blur = v.blur_offset >= 0;
     const float* bsrc = blurred + (blur ? v.blur_offset : 0);
+    const int bp = blur_pitch(W);
+    // staged columns start at a multiple of 4 so that rows load in 16-byte (blurred) or
+    // 4-byte (u8) chunks; u8 sources whose rows are not 4-byte aligned load byte by byte
+    const bool vec = blur || (((reinterpret_cast<uintptr_t>(src)) | uintptr_t(pitch)) & 3) == 0;
+    const int ax0 = vec ? (bx0 & ~3) : bx0;
+    const int nc = vec ? ((bx1 - ax0) >> 2) + 1 : bx1 - bx0 + 1;      // chunks per row
+    const int cw = vec ? 4 : 1;                                         // columns per chunk
+    const int ls = (nc * cw) | 1;            // odd LDS row stride: vertically adjacent taps fall in different banks
+    const bool use_lds = bx1 >= bx0 && bh > 0 && (long long)ls * bh <= kWarpLds;
     if (use_lds) {
-        // flattened staging; r = e / bw through a float reciprocal is exact here because
-        // (e + 1/2) / bw stays at least 1/(2 bw) away from an integer and e < 2^13
-        // loads are issued 8 per thread before any is stored, so their latencies overlap
-        const float rbw = 1.0f / float(bw);
-        const int n = bw * bh;
-        for (int e0 = 0; e0 < n; e0 += 8 * kWarpThreads) {
-            float val[8];
+        // chunk e = r * nc + c; each thread starts at e = tid and steps by 256 = q * nc + rem
+        // chunks, so its (r, c) and both offsets advance by constants (no division per chunk);
+        // up to 4 loads are in flight before their LDS stores
+        const int n = nc * bh;
+        const int q = kWarpThreads / nc, rem = kWarpThreads - q * nc;
+        int e = int(threadIdx.x);
+        int r = e / nc, c = e - r * nc;
+        if (blur) {
+            const float* g = bsrc + size_t(by0 + r) * bp + ax0 + 4 * c;
+            int lo = r * ls + 4 * c;
+            while (e < n) {
+                float4 val[4];
+                int los[4];
+                int k = 0;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + u * kWarpThreads + int(threadIdx.x);
-                const int r = int((float(e) + 0.5f) * rbw), c = e - r * bw;
-                if (e < n) val[u] = blur ? bsrc[size_t(by0 + r) * W + bx0 + c] : float(src[size_t(by0 + r) * pitch + bx0 + c]);
+                for (int u = 0; u < 4; ++u) {
+                    if (e < n) {
+                        val[u] = *reinterpret_cast<const float4*>(g);
+                        los[u] = lo;
+                        ++k;
+                        e += kWarpThreads;
+                        c += rem;
+                        g += size_t(q) * bp + 4 * rem;
+                        lo += q * ls + 4 * rem;
+                        if (c >= nc) {
+                            c -= nc;
+                            g += bp - 4 * nc;
+                            lo += ls - 4 * nc;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (u < k) {
+                        tile[los[u]] = val[u].x;
+                        tile[los[u] + 1] = val[u].y;
+                        tile[los[u] + 2] = val[u].z;
+                        tile[los[u] + 3] = val[u].w;
+                    }
+                }
             }
+        } else if (vec) {
+            const uint8_t* g = src + size_t(by0 + r) * pitch + ax0 + 4 * c;
+            int lo = r * ls + 4 * c;
+            while (e < n) {
+                uint32_t val[4];
+                int los[4];
+                int k = 0;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + u * kWarpThreads + int(threadIdx.x);
-                const int r = int((float(e) + 0.5f) * rbw), c = e - r * bw;
-                if (e < n) tile[r * ls + c] = val[u];
+                for (int u = 0; u < 4; ++u) {
+                    if (e < n) {
+                        val[u] = *reinterpret_cast<const uint32_t*>(g);
+                        los[u] = lo;
+                        ++k;
+                        e += kWarpThreads;
+                        c += rem;
+                        g += size_t(q) * pitch + 4 * rem;
+                        lo += q * ls + 4 * rem;
+                        if (c >= nc) {
+                            c -= nc;
+                            g += pitch - 4 * nc;
+                            lo += ls - 4 * nc;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (u < k) {
+                        tile[los[u]] = float(val[u] & 0xFF);
+                        tile[los[u] + 1] = float((val[u] >> 8) & 0xFF);
+                        tile[los[u] + 2] = float((val[u] >> 16) & 0xFF);
+                        tile[los[u] + 3] = float(val[u] >> 24);
+                    }
+                }
+            }
+        } else {
+            const uint8_t* g = src + size_t(by0 + r) * pitch + ax0 + c;
+            int lo = r * ls + c;
+            while (e < n) {
+                tile[lo] = float(*g);
+                e += kWarpThreads;
+                c += rem;
+                g += size_t(q) * pitch + rem;
+                lo += q * ls + rem;
+                if (c >= nc) {
+                    c -= nc;
+                    g += pitch - nc;
+                    lo += ls - nc;
+                }
             }
         }
     }
@@ -289,7 +365,7 @@ __global__ void __launch_bounds__(kWarpThreads) k_warp(const uint8_t* __restrict
     float val;
     if (use_lds && ix >= 3 && ix + 4 <= W - 1 && iy >= 3 && iy + 4 <= H - 1) {
         // interior: the 8 x 8 window needs no clamping; rows are read at immediate offsets
-        const float* base = tile + (iy - 3 - by0) * ls + (ix - 3 - bx0);
+        const float* base = tile + (iy - 3 - by0) * ls + (ix - 3 - ax0);
         val = 0.0f;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -301,14 +377,13 @@ __global__ void __launch_bounds__(kWarpThreads) k_warp(const uint8_t* __restrict
         }
     } else if (use_lds) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) cols[i] = clampi(clampi(ix - 3 + i, 0, W - 1) - bx0, 0, bw - 1);
-        val = lanczos_sum([&](int j) { return tile + clampi(clampi(iy - 3 + j, 0, H - 1) - by0, 0, bh - 1) * ls; },
-                          cols, wx, wy);
+        for (int i = 0; i < 8; ++i) cols[i] = clampi(ix - 3 + i, bx0, bx1) - ax0;
+        val = lanczos_sum([&](int j) { return tile + (clampi(iy - 3 + j, by0, by1) - by0) * ls; }, cols, wx, wy);
     } else {
 #pragma unroll
         for (int i = 0; i < 8; ++i) cols[i] = clampi(ix - 3 + i, 0, W - 1);
         if (blur)
-            val = lanczos_sum([&](int j) { return bsrc + size_t(clampi(iy - 3 + j, 0, H - 1)) * W; }, cols, wx, wy);
+            val = lanczos_sum([&](int j) { return bsrc + size_t(clampi(iy - 3 + j, 0, H - 1)) * bp; }, cols, wx, wy);
         else
             val = lanczos_sum([&](int j) { return src + size_t(clampi(iy - 3 + j, 0, H - 1)) * pitch; }, cols, wx,
                               wy);
