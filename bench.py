@@ -1,11 +1,11 @@
 """Benchmark: image pairs per second through the whole parameter-search path on one MI355X.
 
-A step is one call of xa_match_pair on the full-size synthetic pair: both
-1024x768 / 725x725 images are simulated over the 45-view grid (tilts
-sqrt(2)^0..5, longitude step 72/t), ORB (8 levels at 1.2, 1000 keypoints per
-view, FAST threshold 20) runs on all 90 views, all 45 x 45 view pairs are
-matched with a 0.8 ratio test and the best pair is selected.  Inputs are
-resident in device memory before timing starts.
+A step is one call of the batched entry point (xa_match_batch) on the full-size
+synthetic pair: both 1024x768 / 725x725 images are simulated over the 45-view
+grid (tilts sqrt(2)^0..5, longitude step 72/t) as one view plan, ORB (8 levels
+at 1.2, 1000 keypoints per view, FAST threshold 20) runs on all 90 views, all
+45 x 45 view pairs are matched with a 0.8 ratio test and the best pair is
+selected.  Inputs are resident in device memory before timing starts.
 
 Prints one JSON line.  Besides the headline it reports, for the dominant
 kernel (the all-pairs Hamming matcher), achieved integer lane-ops/s against
@@ -315,18 +315,19 @@ def main():
     A = torch.from_numpy(np.ascontiguousarray(case.A)).to(dev)
     B = torch.from_numpy(np.ascontiguousarray(case.B)).to(dev)
     pattern = torch.from_numpy(synth.brief_pattern()).to(dev)
-    run = X.PairRunner(pa, pb, dev)
+    run = X.BatchRunner([(case.A, np.ascontiguousarray(case.B))], grid, (1.0,), n_levels=wl["n_levels"],
+                        n_features=wl["n_features"], fast_threshold=wl["fast"], device=dev)
     stream = torch.cuda.current_stream()
 
     for _ in range(args.warmup):
-        run.run(A, B, pattern)
+        run.run(pattern)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(stream)
     for _ in range(args.steps):
-        run.run(A, B, pattern)
+        run.run(pattern)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -334,10 +335,11 @@ def main():
     ev_ms = ev0.elapsed_time(ev1) / args.steps
 
     # quality of the result (outside the timed region)
-    pr = run.precision(case.H, 2.0).cpu().numpy()
-    best = run.best.cpu().numpy().tolist()
-    count_a = run.count_a.cpu().numpy().astype(np.int64)
-    count_b = run.count_b.cpu().numpy().astype(np.int64)
+    pr = run.precision(0, case.H, 2.0).cpu().numpy()
+    best = run.best[0].cpu().numpy().tolist()
+    nv = len(grid)
+    count_a = run.count[:nv].cpu().numpy().astype(np.int64)
+    count_b = run.count[nv:2 * nv].cpu().numpy().astype(np.int64)
     comparisons = int(count_a.sum() * count_b.sum())
 
     # stage breakdown and the dominant kernel, each timed with HIP events on the launch stream
@@ -358,7 +360,7 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         stage_ms[name] = e0.elapsed_time(e1) / reps
-    assert torch.equal(st.pair_count, run.pair_count), "stage-by-stage run disagrees with xa_match_pair"
+    assert torch.equal(st.pair_count, run.pair_count), "stage-by-stage run disagrees with the batched entry"
 
     # dominant kernel: k_match (xa_match_views = a counter fill, k_match, a one-block argmax)
     match_s = stage_ms["match"] / 1e3

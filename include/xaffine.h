@@ -92,7 +92,7 @@ typedef struct {
     double src_scale;           /* source -> original coordinates, see xa_source_desc */
     int32_t width, height;      /* canvas W' x H' */
     int32_t pitch;              /* row pitch of level 0 in the arena (bytes) */
-    int32_t warp_tile_w;        /* width of the warp's output tiles (tiles hold 256 pixels) */
+    int32_t warp_tile_w;        /* width of the warp's output tiles (tiles hold 512 pixels) */
     double fwd[6];
     double inv[6];
     double sigma;

@@ -10,7 +10,8 @@
 namespace xa {
 
 // Tile shapes of the launch geometry (the plan's prefix tables are counted in these tiles).
-constexpr int kWarpThreads = 256;           // warp: one thread per view pixel, tiles of 256 pixels
+constexpr int kWarpThreads = 256;           // warp: 256 threads per output tile
+constexpr int kWarpRows = 2;                // view pixels per warp thread (tiles hold kWarpRows * 256 pixels)
 constexpr int kWarpLds = 8192;              // floats of source footprint a warp tile can stage in LDS
 constexpr int kPyrTX = 256, kPyrTY = 4;     // pyramid down-sampling (4 output pixels per thread)
 constexpr int kFastTX = 64, kFastTY = 32;   // FAST / NMS / smoothing / Harris tiles (256 threads, 8 rows each)
@@ -18,8 +19,8 @@ constexpr int kBlurTX = 64, kBlurTY = 16;   // directional blur over the source 
 constexpr int kBlurStride = 128;            // LDS row stride (floats) of a major-x blur tile
 constexpr int kBlurLdsMax = 16384;          // floats of source a blur tile may stage in LDS (64 KiB)
 
-// Warp tile width for a view: the output tile is w x (256 / w), narrow along the compressed
-// axis so that its source footprint stays compact (about 16 t x 16 for a 16 x 16 tile).
+// Warp tile width for a view: the output tile is w x (512 / w), narrow along the compressed
+// axis so that its source footprint stays compact.
 inline int warp_tile_w(double t, double s) {
     const double c = t / s;
     return c < 2.0 ? 16 : (c < 8.0 ? 8 : 4);

@@ -275,7 +275,7 @@ extern "C" xa_status xa_plan_views(const xa_source_desc* sources, int32_t n_sour
         }
         warp_prefix[i] = int32_t(warp_tiles);
         v.warp_tile_w = warp_tile_w(v.p.t, v.p.s);
-        const int th = kWarpThreads / v.warp_tile_w;
+        const int th = kWarpRows * kWarpThreads / v.warp_tile_w;
         warp_tiles += int64_t((v.width + v.warp_tile_w - 1) / v.warp_tile_w) * ((v.height + th - 1) / th);
         int32_t kp_base = 0;
         for (int l = 0; l < n_levels; ++l) {

@@ -207,8 +207,10 @@ __device__ __forceinline__ float lanczos_sum(Row row, const int cols[8], const f
     return acc;
 }
 
-// One thread per view pixel, one block per 256-pixel output tile (w x 256/w, w per view);
-// all views of the plan in one launch (block -> view by prefix search).  The tile's source
+// One block per 512-pixel output tile (w x 512/w, w per view), two pixels per thread, so
+// that the block's serial chain (prefix search, view descriptor, footprint staging, barrier)
+// is paid once per 512 pixels; all views of the plan in one launch (block -> view by prefix
+// search).  The tile's source
 // footprint (bounding box of its pixel centres mapped through inv, grown by the 8-tap
 // window) is staged in LDS as fp32 when it fits; otherwise taps are read from global memory.
 __global__ void __launch_bounds__(kWarpThreads) k_warp(const uint8_t* __restrict__ sources,
@@ -223,10 +225,9 @@ __global__ void __launch_bounds__(kWarpThreads) k_warp(const uint8_t* __restrict
     const int W = v.src_w, H = v.src_h, pitch = v.src_pitch;
     const uint8_t* src = sources + v.src_offset;
     const int local = b - prefix[vi];
-    const int tw = v.warp_tile_w, th = kWarpThreads / tw;
+    const int tw = v.warp_tile_w, th = kWarpRows * kWarpThreads / tw;
     const int tiles_x = (v.width + tw - 1) / tw;
     const int x0 = (local % tiles_x) * tw, y0 = (local / tiles_x) * th;
-    const int qx = x0 + int(threadIdx.x) % tw, qy = y0 + int(threadIdx.x) / tw;
     // bounding box of the footprint (the tile's pixel centres through inv, grown by the
     // 8-tap window, clamped to the source): the corner (x0, y0) plus the extreme offsets of
     // the other corners; rounding here is ~1e-12 px, far inside the 1e-6 margin
@@ -345,54 +346,60 @@ __global__ void __launch_bounds__(kWarpThreads) k_warp(const uint8_t* __restrict
         }
     }
     __syncthreads();
-    if (qx >= v.width || qy >= v.height) return;
-    const size_t o = size_t(v.offset) + size_t(qy) * v.pitch + qx;
-    const double px = affine_x(v.inv, double(qx), double(qy));
-    const double py = affine_x(v.inv + 3, double(qx), double(qy));
-    const bool inside = px >= -0.5 && px <= W - 0.5 && py >= -0.5 && py <= H - 0.5;
-    if (!inside) {
-        arena[o] = 0;
-        mask[o] = 0;
-        if (values) values[o] = 0.0f;
-        return;
-    }
-    const double fxd = floor(px), fyd = floor(py);
-    const int ix = int(fxd), iy = int(fyd);
-    float wx[8], wy[8];
-    const float sx = lanczos4_weights(float(px - fxd), wx);
-    const float sy = lanczos4_weights(float(py - fyd), wy);
-    int cols[8];
-    float val;
-    if (use_lds && ix >= 3 && ix + 4 <= W - 1 && iy >= 3 && iy + 4 <= H - 1) {
-        // interior: the 8 x 8 window needs no clamping; rows are read at immediate offsets
-        const float* base = tile + (iy - 3 - by0) * ls + (ix - 3 - ax0);
-        val = 0.0f;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const float* r = base + j * ls;
-            float sacc = 0.0f;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) sacc += wx[i] * r[i];
-            val += wy[j] * sacc;
+    // each thread resamples kWarpRows pixels of its tile column, kWarpThreads / tw rows apart
+    const int qx = x0 + int(threadIdx.x) % tw;
+    for (int k = 0; k < kWarpRows; ++k) {
+        const int qy = y0 + int(threadIdx.x) / tw + k * (kWarpThreads / tw);
+        if (qx >= v.width || qy >= v.height) break;
+        const size_t o = size_t(v.offset) + size_t(qy) * v.pitch + qx;
+        const double px = affine_x(v.inv, double(qx), double(qy));
+        const double py = affine_x(v.inv + 3, double(qx), double(qy));
+        const bool inside = px >= -0.5 && px <= W - 0.5 && py >= -0.5 && py <= H - 0.5;
+        if (!inside) {
+            arena[o] = 0;
+            mask[o] = 0;
+            if (values) values[o] = 0.0f;
+            continue;
         }
-    } else if (use_lds) {
+        const double fxd = floor(px), fyd = floor(py);
+        const int ix = int(fxd), iy = int(fyd);
+        float wx[8], wy[8];
+        const float sx = lanczos4_weights(float(px - fxd), wx);
+        const float sy = lanczos4_weights(float(py - fyd), wy);
+        int cols[8];
+        float val;
+        if (use_lds && ix >= 3 && ix + 4 <= W - 1 && iy >= 3 && iy + 4 <= H - 1) {
+            // interior: the 8 x 8 window needs no clamping; rows are read at immediate offsets
+            const float* base = tile + (iy - 3 - by0) * ls + (ix - 3 - ax0);
+            val = 0.0f;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) cols[i] = clampi(ix - 3 + i, bx0, bx1) - ax0;
-        val = lanczos_sum([&](int j) { return tile + (clampi(iy - 3 + j, by0, by1) - by0) * ls; }, cols, wx, wy);
-    } else {
+            for (int j = 0; j < 8; ++j) {
+                const float* r = base + j * ls;
+                float sacc = 0.0f;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) cols[i] = clampi(ix - 3 + i, 0, W - 1);
-        if (blur)
-            val = lanczos_sum([&](int j) { return bsrc + size_t(clampi(iy - 3 + j, 0, H - 1)) * bp; }, cols, wx, wy);
-        else
-            val = lanczos_sum([&](int j) { return src + size_t(clampi(iy - 3 + j, 0, H - 1)) * pitch; }, cols, wx,
-                              wy);
+                for (int i = 0; i < 8; ++i) sacc += wx[i] * r[i];
+                val += wy[j] * sacc;
+            }
+        } else if (use_lds) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) cols[i] = clampi(ix - 3 + i, bx0, bx1) - ax0;
+            val = lanczos_sum([&](int j) { return tile + (clampi(iy - 3 + j, by0, by1) - by0) * ls; }, cols, wx, wy);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) cols[i] = clampi(ix - 3 + i, 0, W - 1);
+            if (blur)
+                val = lanczos_sum([&](int j) { return bsrc + size_t(clampi(iy - 3 + j, 0, H - 1)) * bp; }, cols, wx,
+                                  wy);
+            else
+                val = lanczos_sum([&](int j) { return src + size_t(clampi(iy - 3 + j, 0, H - 1)) * pitch; }, cols,
+                                  wx, wy);
+        }
+        val *= __builtin_amdgcn_rcpf(sx * sy);    // eq. (3) divided by the sum of the weights
+        const float q = rintf(val);
+        arena[o] = uint8_t(q < 0.0f ? 0.0f : (q > 255.0f ? 255.0f : q));
+        mask[o] = 1;
+        if (values) values[o] = val;
     }
-    val *= __builtin_amdgcn_rcpf(sx * sy);    // eq. (3) divided by the sum of the weights
-    const float q = rintf(val);
-    arena[o] = uint8_t(q < 0.0f ? 0.0f : (q > 255.0f ? 255.0f : q));
-    mask[o] = 1;
-    if (values) values[o] = val;
 }
 
 }  // namespace

@@ -648,6 +648,19 @@ class BatchRunner:
                                                       self.pair_count, self.best)])
         self.graph = None
 
+    def precision(self, k: int, H, th: float = 2.0, ratio_num: int = 4, ratio_den: int = 5):
+        """Eqs. (5)-(6) on pair k's best view pair: device int32 [correct, accepted]."""
+        import torch
+        a0, na, b0, nb = self.pair_views[k]
+        base = int(self.mplan.groups[k]["pair_base"])
+        N = self.mplan.n_features
+        out = torch.zeros(2, dtype=torch.int32, device=self.device)
+        Hc = np.ascontiguousarray(H, np.float64).reshape(9)
+        _check(lib().xa_pair_precision(_ptr(self.kp[a0]), _ptr(self.kp[b0]), _ptr(self.matches[base]),
+                                       _ptr(self.count[a0:]), _ptr(self.count[b0:]), nb, N, ratio_num, ratio_den,
+                                       _ptr(self.best[k]), Hc.ctypes.data, th, _ptr(out), _stream()))
+        return out
+
     def set_workspace(self, ws):
         """Use `ws` (uint8 device tensor of at least ws_bytes) from now on."""
         if ws.numel() < self.ws_bytes:

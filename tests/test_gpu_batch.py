@@ -135,6 +135,7 @@ def test_batch_equals_single_pair_calls(dev, pairs):
         assert torch.equal(br.matches[base:base + nv * nv], run.matches), pi
         assert torch.equal(br.pair_count[base:base + nv * nv], run.pair_count), pi
         assert torch.equal(br.best[pi], run.best), pi
+        assert torch.equal(br.precision(pi, p.H), run.precision(p.H)), pi
         say(f"[batch] pair {pi} ({p.A.shape[1]}x{p.A.shape[0]}): identical, best {run.best.tolist()}")
 
 
