@@ -51,7 +51,7 @@ typedef enum {
 } xa_status;
 
 #define XA_PLAN_MAGIC 0x58414650u   /* "XAFP" */
-#define XA_PLAN_VERSION 3u
+#define XA_PLAN_VERSION 4u
 #define XA_MAX_LEVELS 12
 #define XA_MAX_QUOTA 2048           /* keypoints per pyramid level */
 #define XA_MAX_FEATURES 4096        /* keypoints per view */
@@ -147,6 +147,8 @@ typedef struct {
     int64_t off_sources;        /* xa_source_desc[n_sources] */
     int32_t n_sources;
     int32_t pad;
+    int64_t off_fast_flags;     /* uint8[vl_prefix[n_views * n_levels]]: per FAST tile, bit 0 = some pixel can
+                                   be valid, bit 1 = some pixel can pass the content filter */
 } xa_plan_header;
 
 /* A keypoint in canonical order within its view: level ascending, then Harris

@@ -1,6 +1,7 @@
 // Internal declarations shared by the library's translation units.
 #pragma once
 
+#include <cmath>
 #include <cstddef>
 #include <cstdint>
 #include <string>
@@ -28,6 +29,81 @@ inline int warp_tile_w(double t, double s) {
 constexpr int kBorder = 22;                 // detection border (rotated BRIEF tests reach 21 px)
 constexpr size_t kAlign = 256;
 
+// True if no point of the level-pixel rectangle [rx0, rx1] x [ry0, ry1], taken to view level-0
+// coordinates (x0 = (x + 1/2) W0 / Wl - 1/2 per axis) and grown there by m pixels per axis,
+// maps through inv into the source rectangle [-1/2, W - 1/2] x [-1/2, H - 1/2].  The image
+// of the grown rectangle is a parallelogram; a separating axis among the source's two axes
+// and the parallelogram's two edge normals decides, in fp64 with a 1e-6 px margin.
+inline __host__ __device__ bool rect_misses_source(const xa_view_desc& v, double sx, double sy, double rx0, double rx1, double ry0,
+                                   double ry1, double m) {
+    const double ax = (rx0 + 0.5) * sx - 0.5 - m, bx = (rx1 + 0.5) * sx - 0.5 + m;
+    const double ay = (ry0 + 0.5) * sy - 0.5 - m, by = (ry1 + 0.5) * sy - 0.5 + m;
+    const double* G = v.inv;
+    const double qx[4] = {G[0] * ax + G[1] * ay + G[2], G[0] * bx + G[1] * ay + G[2], G[0] * bx + G[1] * by + G[2],
+                          G[0] * ax + G[1] * by + G[2]};
+    const double qy[4] = {G[3] * ax + G[4] * ay + G[5], G[3] * bx + G[4] * ay + G[5], G[3] * bx + G[4] * by + G[5],
+                          G[3] * ax + G[4] * by + G[5]};
+    const double eps = 1e-6;
+    const double lo_x = -0.5, hi_x = double(v.src_w) - 0.5, lo_y = -0.5, hi_y = double(v.src_h) - 0.5;
+    double mnx = qx[0], mxx = qx[0], mny = qy[0], mxy = qy[0];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+        mnx = fmin(mnx, qx[k]); mxx = fmax(mxx, qx[k]);
+        mny = fmin(mny, qy[k]); mxy = fmax(mxy, qy[k]);
+    }
+    if (mxx < lo_x - eps || mnx > hi_x + eps || mxy < lo_y - eps || mny > hi_y + eps) return true;
+    const double rx[4] = {lo_x, hi_x, hi_x, lo_x}, ry[4] = {lo_y, lo_y, hi_y, hi_y};
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        // normal of the edge q0 -> q1 (e = 0) or q0 -> q3 (e = 1)
+        const int k = e == 0 ? 1 : 3;
+        const double nx = -(qy[k] - qy[0]), ny = qx[k] - qx[0];
+        const double nn = sqrt(nx * nx + ny * ny);
+        if (!(nn > 0.0)) continue;
+        double qmn = 1e300, qmx = -1e300, rmn = 1e300, rmx = -1e300;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double pq = nx * qx[j] + ny * qy[j], pr = nx * rx[j] + ny * ry[j];
+            qmn = fmin(qmn, pq); qmx = fmax(qmx, pq);
+            rmn = fmin(rmn, pr); rmx = fmax(rmx, pr);
+        }
+        if (rmx < qmn - eps * nn || rmn > qmx + eps * nn) return true;
+    }
+    return false;
+}
+
+// Distance bound (view level-0 pixels per axis) between a level-l pixel whose pyramid mask is
+// set and a valid level-0 pixel: each level's mask is the AND of a 2 x 2 footprint within one
+// pixel of the same point one level down, and level k pixels span at most 1.25^k level-0
+// pixels, so the bound is 1 + sum_{k<l} 1.25^k.
+inline __host__ __device__ double mask_reach(int l) {
+    double r = 1.0, f = 1.0;
+    for (int k = 0; k < l; ++k) {
+        r += f;
+        f *= 1.25;
+    }
+    return r;
+}
+
+// Flags of one FAST tile (64 x 32 pixels at (x0, y0) of a level of size W x H of view v at
+// level l): bit 0 = some pixel of the tile can be valid (its smoothing can be read),
+// bit 1 = some pixel can pass the content filter (all four corners of its +-B box inside the
+// source).  Both bits are conservative: a pyramid-mask pixel is set only within mask_reach(l)
+// view pixels of a valid level-0 pixel, and the valid region is convex.
+inline __host__ __device__ uint8_t fast_tile_flags(const xa_view_desc& v, int W, int H, int l, int x0, int y0,
+                                                    int tile_w, int tile_h, int border) {
+    const double sxl = double(v.width) / double(W), syl = double(v.height) / double(H);
+    const double reach = mask_reach(l);
+    const double x1 = double((x0 + tile_w < W ? x0 + tile_w : W) - 1), y1 = double((y0 + tile_h < H ? y0 + tile_h : H) - 1);
+    const bool smooth = !rect_misses_source(v, sxl, syl, x0, x1, y0, y1, reach);
+    bool detect = true;
+    for (int c = 0; c < 4; ++c) {
+        const double ox = (c & 1) ? double(border) : -double(border), oy = (c & 2) ? double(border) : -double(border);
+        detect = detect && !rect_misses_source(v, sxl, syl, x0 + ox, x1 + ox, y0 + oy, y1 + oy, reach);
+    }
+    return uint8_t((smooth ? 1 : 0) | (detect ? 2 : 0));
+}
+
 struct BlurTap {
     float wa;       // w (1 - f): weight of the sample at the whole-pixel minor offset
     float wb;       // w f: weight of the next row / column (f = k m - floor(k m))
@@ -38,6 +114,7 @@ static_assert(sizeof(BlurTap) == 16, "tap layout");
 static_assert(sizeof(xa_view_desc) == 248, "view desc layout");
 static_assert(sizeof(xa_source_desc) == 32, "source desc layout");
 static_assert(sizeof(xa_level_desc) == 56, "level desc layout");
+static_assert(sizeof(xa_plan_header) == 168, "plan header layout");
 static_assert(sizeof(xa_keypoint) == 40, "keypoint layout");
 static_assert(sizeof(xa_match) == 8, "match layout");
 
@@ -71,6 +148,7 @@ struct PlanView {
     const int32_t* vl_prefix = nullptr;
     const int32_t* blur_prefix = nullptr;
     const xa_source_desc* sources = nullptr;
+    const uint8_t* fast_flags = nullptr;
 };
 xa_status plan_host_view(const void* blob, PlanView* out);
 PlanView plan_dev_view(const void* blob_host, const void* blob_dev);

@@ -238,7 +238,11 @@ __device__ __forceinline__ long long harris_lds(const uint8_t* p, int s) {
 //  4. 3x3 non-maximum suppression (ties go to the earlier raster position), the content
 //     filter on the corners of the +-B box, the Harris response of each survivor from the
 //     LDS tile, and one atomic reservation per block in the candidate arena.
-__global__ void __launch_bounds__(256) k_fast(const xa_level_desc* __restrict__ levels, const int32_t* __restrict__ prefix,
+// Tiles of a tilted view's empty corners skip work that cannot matter (flags from the
+// planner): smoothing when no pixel of the tile can be valid, detection when no pixel can
+// pass the content filter.
+__global__ void __launch_bounds__(256) k_fast(const uint8_t* __restrict__ fast_flags,
+                                              const xa_level_desc* __restrict__ levels, const int32_t* __restrict__ prefix,
                                               int nvl, int T, const uint8_t* __restrict__ arena,
                                               const uint8_t* __restrict__ mask, Cand* __restrict__ cand,
                                               int32_t* __restrict__ cand_count, uint8_t* __restrict__ smooth) {
@@ -258,6 +262,10 @@ __global__ void __launch_bounds__(256) k_fast(const xa_level_desc* __restrict__ 
     const int x0 = (local % tiles_x) * kFastTX, y0 = (local / tiles_x) * kFastTY;
     const uint8_t* P = arena + d.offset;
     const int t = threadIdx.x;
+    // which parts of the tile can matter (decided by the planner, see fast_tile_flags)
+    const uint8_t flags = fast_flags[b];
+    const bool need_smooth = (flags & 1) != 0, may_detect = (flags & 2) != 0;
+    if (!need_smooth && !may_detect) return;
     for (int e = t; e < kFLH * kFChunks; e += 256) {
         const int r = e / kFChunks, k = e - (e / kFChunks) * kFChunks;
         const int gy = clampi(y0 - kFH + r, 0, H - 1);
@@ -283,7 +291,7 @@ __global__ void __launch_bounds__(256) k_fast(const xa_level_desc* __restrict__ 
     __syncthreads();
 
     // ---- smoothing: thread = column c, rows 8g .. 8g + 7 of the tile
-    {
+    if (need_smooth) {
         const int c = t & 63, g = t >> 6;
         const int lx = c + 16 - 3;                 // first byte of the 7-tap window
         const int a = lx & ~3, o = lx & 3;
@@ -306,8 +314,8 @@ __global__ void __launch_bounds__(256) k_fast(const xa_level_desc* __restrict__ 
         }
     }
     // ---- FAST pre-test over the tile and its ring
-    const bool detect = !(x0 + kFastTX <= kBorder - 1 || x0 - 1 >= W - kBorder || y0 + kFastTY <= kBorder - 1 ||
-                          y0 - 1 >= H - kBorder);
+    const bool detect = may_detect && !(x0 + kFastTX <= kBorder - 1 || x0 - 1 >= W - kBorder ||
+                                        y0 + kFastTY <= kBorder - 1 || y0 - 1 >= H - kBorder);
     if (detect) {
         for (int e = t; e < kSH * kSW; e += 256) {
             const int sy = e / kSW, sx = e - (e / kSW) * kSW;
@@ -325,7 +333,7 @@ __global__ void __launch_bounds__(256) k_fast(const xa_level_desc* __restrict__ 
     }
     __syncthreads();
     // ---- smoothed tile out, 16 bytes per store (rows are padded to 16 bytes)
-    for (int e = t; e < kFastTY * (kFastTX / 16); e += 256) {
+    for (int e = t; need_smooth && e < kFastTY * (kFastTX / 16); e += 256) {
         const int r = e >> 2, k = e & 3;
         const int y = y0 + r, x = x0 + 16 * k;
         if (y < H && x < W)
@@ -637,8 +645,8 @@ xa_status launch_extract(const PlanView& ph, const PlanView& pd, uint8_t* arena,
     }
     const int vt = ph.vl_prefix[nvl];
     if (vt > 0)
-        hipLaunchKernelGGL(k_fast, dim3(vt), dim3(256), 0, st, pd.levels, pd.vl_prefix, nvl, h->fast_threshold,
-                           arena, mask, cand, cand_count, smooth);
+        hipLaunchKernelGGL(k_fast, dim3(vt), dim3(256), 0, st, pd.fast_flags, pd.levels, pd.vl_prefix, nvl,
+                           h->fast_threshold, arena, mask, cand, cand_count, smooth);
     hipLaunchKernelGGL(k_select, dim3(nvl), dim3(kSelThreads), 0, st, pd.levels, N, cand, cand_count, stage,
                        stage_count);
     hipLaunchKernelGGL(k_orient_brief, dim3((N + 3) / 4, nv), dim3(256), 0, st, pd.views, pd.levels, L, N, arena,

@@ -43,6 +43,7 @@ xa_status plan_host_view(const void* blob, PlanView* out) {
     out->vl_prefix = reinterpret_cast<const int32_t*>(b + h->off_vl_prefix);
     out->blur_prefix = reinterpret_cast<const int32_t*>(b + h->off_blur_prefix);
     out->sources = reinterpret_cast<const xa_source_desc*>(b + h->off_sources);
+    out->fast_flags = reinterpret_cast<const uint8_t*>(b + h->off_fast_flags);
     return XA_OK;
 }
 
@@ -60,6 +61,7 @@ PlanView plan_dev_view(const void* blob_host, const void* blob_dev) {
     p.vl_prefix = reinterpret_cast<const int32_t*>(b + h->off_vl_prefix);
     p.blur_prefix = reinterpret_cast<const int32_t*>(b + h->off_blur_prefix);
     p.sources = reinterpret_cast<const xa_source_desc*>(b + h->off_sources);
+    p.fast_flags = reinterpret_cast<const uint8_t*>(b + h->off_fast_flags);
     return p;
 }
 
@@ -259,6 +261,7 @@ extern "C" xa_status xa_plan_views(const xa_source_desc* sources, int32_t n_sour
     std::vector<int32_t> warp_prefix(n_views + 1, 0);
     std::vector<int32_t> level_prefix(size_t(n_levels) * (n_views + 1), 0);
     std::vector<int32_t> vl_prefix(nvl + 1, 0);
+    std::vector<uint8_t> fast_flags;
     int64_t arena = 0, cand = 0, blur_floats = 0;
     int64_t warp_tiles = 0, vl_tiles = 0, blur_tiles = 0;
     std::vector<int64_t> lvl_tiles(n_levels, 0);
@@ -299,7 +302,12 @@ extern "C" xa_status xa_plan_views(const xa_source_desc* sources, int32_t n_sour
             level_prefix[size_t(l) * (n_views + 1) + i] = int32_t(lvl_tiles[l]);
             lvl_tiles[l] += int64_t((d.width + kPyrTX - 1) / kPyrTX) * ((d.height + kPyrTY - 1) / kPyrTY);
             vl_prefix[size_t(i) * n_levels + l] = int32_t(vl_tiles);
-            vl_tiles += int64_t((d.width + kFastTX - 1) / kFastTX) * ((d.height + kFastTY - 1) / kFastTY);
+            const int ftx = (d.width + kFastTX - 1) / kFastTX, fty = (d.height + kFastTY - 1) / kFastTY;
+            vl_tiles += int64_t(ftx) * fty;
+            for (int ty = 0; ty < fty; ++ty)
+                for (int tx = 0; tx < ftx; ++tx)
+                    fast_flags.push_back(fast_tile_flags(v, d.width, d.height, l, tx * kFastTX, ty * kFastTY, kFastTX,
+                                                         kFastTY, kBorder));
         }
     }
     warp_prefix[n_views] = int32_t(warp_tiles);
@@ -335,6 +343,7 @@ extern "C" xa_status xa_plan_views(const xa_source_desc* sources, int32_t n_sour
     h.off_vl_prefix = int64_t(o);    o = align_up(o + 4 * vl_prefix.size(), 64);
     h.off_blur_prefix = int64_t(o);  o = align_up(o + 4 * blur_prefix.size(), 64);
     h.off_sources = int64_t(o);      o = align_up(o + sizeof(xa_source_desc) * n_sources, 64);
+    h.off_fast_flags = int64_t(o);   o = align_up(o + fast_flags.size(), 64);
     h.total_bytes = int64_t(o);
     *blob_bytes = o;
     if (!blob) return ok();
@@ -352,6 +361,7 @@ extern "C" xa_status xa_plan_views(const xa_source_desc* sources, int32_t n_sour
     std::memcpy(b + h.off_vl_prefix, vl_prefix.data(), 4 * vl_prefix.size());
     std::memcpy(b + h.off_blur_prefix, blur_prefix.data(), 4 * blur_prefix.size());
     std::memcpy(b + h.off_sources, sources, sizeof(xa_source_desc) * n_sources);
+    if (!fast_flags.empty()) std::memcpy(b + h.off_fast_flags, fast_flags.data(), fast_flags.size());
     return ok();
 }
 

@@ -39,13 +39,13 @@ HEADER_DTYPE = np.dtype([("magic", "u4"), ("version", "u4"), ("src_w", "i4"), ("
                          ("n_blur", "i4"), ("n_taps_total", "i4"), ("off_views", "i8"), ("off_levels", "i8"),
                          ("off_taps", "i8"), ("off_blur_views", "i8"), ("off_warp_prefix", "i8"),
                          ("off_level_prefix", "i8"), ("off_vl_prefix", "i8"), ("off_blur_prefix", "i8"),
-                         ("off_sources", "i8"), ("n_sources", "i4"), ("pad", "i4")])
+                         ("off_sources", "i8"), ("n_sources", "i4"), ("pad", "i4"), ("off_fast_flags", "i8")])
 TAP_DTYPE = np.dtype([("wa", "f4"), ("wb", "f4"), ("dmaj", "i4"), ("dmin", "i4")])
 KEYPOINT_DTYPE = np.dtype([("x", "i4"), ("y", "i4"), ("level", "i4"), ("bin", "i4"), ("harris", "i8"),
                            ("xs", "f8"), ("ys", "f8")])
 MATCH_DTYPE = np.dtype([("t", "i4"), ("d1", "u2"), ("d2", "u2")])
 assert VIEW_DTYPE.itemsize == 248 and LEVEL_DTYPE.itemsize == 56 and KEYPOINT_DTYPE.itemsize == 40
-assert MATCH_DTYPE.itemsize == 8 and HEADER_DTYPE.itemsize == 160 and SOURCE_DTYPE.itemsize == 32
+assert MATCH_DTYPE.itemsize == 8 and HEADER_DTYPE.itemsize == 168 and SOURCE_DTYPE.itemsize == 32
 
 
 class XAError(RuntimeError):

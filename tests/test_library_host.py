@@ -188,3 +188,40 @@ def test_batch_chunking_on_host():
     # scale-0.5 views come from the scale stage's outputs
     assert np.array_equal(np.unique(many.view_scale), [0.5, 1.0])
     del torch
+
+
+def test_fast_tile_flags_are_conservative():
+    """The planner's per-tile flags never skip work that matters: every corner that passes the
+    content filter (oracle, on oracle views) lies in a tile marked for detection, and every
+    pixel within 21 px of such a corner (the BRIEF reach) or with mask 1 lies in a tile marked
+    for smoothing; on tilted views a sizable share of tiles skips detection."""
+    import synth
+    from oracle import orb as OO
+    case = synth.make_pair(**synth.PAIR_CONFIGS["tiny"])
+    img = case.A
+    rows = [(1.0, 0.0), (2.0, 0.3), (2.0, 1.9), (2.0 * math.sqrt(2), 0.7), (4.0, 1.2), (4.0, 2.8)]
+    L = 4
+    plan = X.plan_image(img.shape[1], img.shape[0], X.make_params(rows), L, 1.2, 300, 20)
+    h = plan.header
+    vl = np.frombuffer(plan.blob, np.int32, plan.n_views * L + 1, int(h["off_vl_prefix"]))
+    flags = np.frombuffer(plan.blob, np.uint8, int(vl[-1]), int(h["off_fast_flags"]))
+    skipped = 0
+    for i, (t, phi) in enumerate(rows):
+        v = OP.plan_view(img.shape[1], img.shape[0], t, phi)
+        _, M, U = OS.simulate_view(img, v)
+        dims = OP.level_dims(v.width, v.height, L)
+        for l, (P, Mk) in enumerate(OO.build_pyramid(U, M, dims)):
+            W, H = dims[l]
+            tx_n = (W + 63) // 64
+            f = flags[vl[i * L + l]:vl[i * L + l + 1]].reshape(-1, tx_n)
+            skipped += int(((f & 2) == 0).sum())
+            ys, xs = np.nonzero(Mk)
+            assert np.all(f[ys // 32, xs // 64] & 1), (i, l)
+            cx, cy = OO.fast_candidates(P, Mk, 20)
+            assert np.all(f[cy // 32, cx // 64] & 2), (i, l)
+            for x, y in zip(cx, cy):
+                for yy in (max(0, y - 21), min(H - 1, y + 21)):
+                    for xx in (max(0, x - 21), min(W - 1, x + 21)):
+                        assert f[yy // 32, xx // 64] & 1, (i, l, x, y)
+    print("tiles without detection", skipped, "of", len(flags))
+    assert skipped > 0.2 * len(flags)
