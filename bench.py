@@ -37,12 +37,14 @@ HAMMING_OPS_PER_CMP = 16          # 8 x v_xor_b32 + 8 x v_bcnt_u32_b32 per 256-b
 K_MATCH_TRAFFIC = {
     "source": "paper_2503_03479_amd/csrc/match.hip",
     "sha256": "51c06c6e1ec8b0637e1c13e74da0b668b5f0b19e2c0122ae815110de1a15370b",
-    "fetch_kib": 10801.8, "write_kib": 15555.9, "fetch_scale": 2.0, "write_scale": 1.0,
+    "queries_per_lane": 4, "fetch_kib": 10801.8, "write_kib": 15555.9, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 
-def k_match_traffic():
+def k_match_traffic(queries_per_lane: int):
     import hashlib
+    if queries_per_lane != K_MATCH_TRAFFIC["queries_per_lane"]:
+        return None
     with open(os.path.join(ROOT, K_MATCH_TRAFFIC["source"]), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != K_MATCH_TRAFFIC["sha256"]:
             return None
@@ -139,18 +141,25 @@ def batched_leg(args, dev, pattern, raw, gen_s):
     K = len(raw)
     pairs = [(A, np.ascontiguousarray(B)) for A, B, _ in raw]
     grid = [(float(r["t"]), float(r["phi"])) for r in X.sampling_grid(5)]
-    kw = dict(n_levels=8, n_features=500, fast_threshold=20, device=dev)
+    kw = dict(n_levels=8, n_features=500, fast_threshold=20, device=dev, queries_per_lane="auto")
     stream = torch.cuda.current_stream()
 
-    # plain: one runner per pair (same entry point, one pair per call), one shared workspace
-    single = [X.BatchRunner([pr], grid, (1.0, 0.5), allocate_ws=False, **kw) for pr in pairs]
+    # the batch first: its first run tunes the matcher on its own descriptors
+    batch = X.BatchRunner(pairs, grid, (1.0, 0.5), **kw)
+    batch.run(pattern)
+    torch.cuda.synchronize()
+    steps = max(1, args.batch_steps)
+
+    # plain: one runner per pair (same entry point and matcher variant, one pair per call), one
+    # shared workspace
+    kw1 = dict(kw, queries_per_lane=batch.mplan_q)
+    single = [X.BatchRunner([pr], grid, (1.0, 0.5), allocate_ws=False, **kw1) for pr in pairs]
     shared = X._empty(max(r.ws_bytes for r in single), dev)
     for r in single:
         r.set_workspace(shared)
     for r in single[:2]:
         r.run(pattern)
     torch.cuda.synchronize()
-    steps = max(1, args.batch_steps)
     t0 = time.perf_counter()
     for _ in range(steps):
         for r in single:
@@ -159,7 +168,6 @@ def batched_leg(args, dev, pattern, raw, gen_s):
     plain_s = (time.perf_counter() - t0) / steps
     del shared
 
-    batch = X.BatchRunner(pairs, grid, (1.0, 0.5), **kw)
     batch.capture(pattern)
     batch.replay()
     torch.cuda.synchronize()
@@ -204,6 +212,7 @@ def batched_leg(args, dev, pattern, raw, gen_s):
         "workspace_GiB": batch.ws.numel() / 2 ** 30,
         "comparisons": comparisons,
         "identical_to_plain": same,
+        "matcher_autotune": batch.autotune,
         "mean_side_px": float(np.mean([math.sqrt(a * b) for a, b, _, _ in sides])),
         "generate_s": gen_s,
     }
@@ -316,7 +325,7 @@ def main():
     B = torch.from_numpy(np.ascontiguousarray(case.B)).to(dev)
     pattern = torch.from_numpy(synth.brief_pattern()).to(dev)
     run = X.BatchRunner([(case.A, np.ascontiguousarray(case.B))], grid, (1.0,), n_levels=wl["n_levels"],
-                        n_features=wl["n_features"], fast_threshold=wl["fast"], device=dev)
+                        n_features=wl["n_features"], fast_threshold=wl["fast"], device=dev, queries_per_lane="auto")
     stream = torch.cuda.current_stream()
 
     for _ in range(args.warmup):
@@ -344,9 +353,17 @@ def main():
 
     # stage breakdown and the dominant kernel, each timed with HIP events on the launch stream
     st = X.StageRunner(pa, pb, dev)
+    L = X.lib()
+
+    def match_stage():
+        # the matcher exactly as the timed step runs it: the batch's match plan on its descriptors
+        X._check(L.xa_match_groups(run.mplan.host_ptr(), X._ptr(run.mplan.device(dev)), X._ptr(run.desc),
+                                   X._ptr(run.count), run.n_views, 4, 5, X._ptr(run.matches), X._ptr(run.pair_count),
+                                   X._ptr(run.best), X._stream()))
+
     stages = {"simulate": lambda: (st.simulate("a", A), st.simulate("b", B)),
               "extract": lambda: (st.extract("a", pattern), st.extract("b", pattern)),
-              "match": lambda: st.match(4, 5)}
+              "match": match_stage}
     for f in stages.values():
         f()
     torch.cuda.synchronize()
@@ -360,22 +377,24 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         stage_ms[name] = e0.elapsed_time(e1) / reps
+    st.match(4, 5)
+    torch.cuda.synchronize()
     assert torch.equal(st.pair_count, run.pair_count), "stage-by-stage run disagrees with the batched entry"
 
-    # dominant kernel: k_match (xa_match_views = a counter fill, k_match, a one-block argmax)
+    # dominant kernel: k_match (xa_match_groups = a counter fill, k_match<Q>, a one-block argmax per group)
     match_s = stage_ms["match"] / 1e3
     # descriptor sets read once + the match records and counts written
     n_pairs = pa.n_views * pb.n_views
     algo_bytes = (pa.n_views + pb.n_views) * wl["n_features"] * 32 + n_pairs * wl["n_features"] * 8 + n_pairs * 4
     achieved_ops = comparisons * HAMMING_OPS_PER_CMP / match_s
     roofline = {
-        "kernel": "k_match (xa_match_views)",
+        "kernel": f"k_match<{run.mplan_q}> (xa_match_groups, {run.mplan_q} queries per lane)",
         "bound": "alu",
         "achieved": achieved_ops / 1e12,
         "peak": VALU_PEAK_OPS / 1e12,
         "unit": "Tops/s",
         "frac": achieved_ops / VALU_PEAK_OPS,
-        "traffic": k_match_traffic(),
+        "traffic": k_match_traffic(run.mplan_q),
         "traffic_unit": "bytes per launch (HBM, counter-measured)",
         "algorithmic_bytes_per_launch": algo_bytes,
         "algorithmic_ops_per_launch": comparisons * HAMMING_OPS_PER_CMP,
@@ -422,6 +441,7 @@ def main():
         "best_pair": best,
         "precision_best_pair": {"correct": int(pr[0]), "matches": int(pr[1]), "th_px": 2.0},
         "keypoints": {"a": int(count_a.sum()), "b": int(count_b.sum())},
+        "matcher_autotune": run.autotune,
         "device": torch.cuda.get_device_name(0),
         "host_cpu": platform.processor() or platform.machine(),
         "host_cores": os.cpu_count(),

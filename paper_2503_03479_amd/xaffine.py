@@ -528,6 +528,66 @@ def plan_matches(groups, n_features: int, queries_per_lane: int = 0) -> MatchPla
     return MatchPlan(blob, groups, n_features)
 
 
+AUTOTUNE_CACHE = os.environ.get("XAFFINE_AUTOTUNE_CACHE",
+                                os.path.join(os.path.expanduser("~"), ".cache", "xaffine", "autotune.json"))
+
+
+def autotune_queries_per_lane(groups, n_features: int, device="cuda", desc=None, count=None, reps: int = 5,
+                              use_cache: bool = True):
+    """The matcher variant (queries per lane 1, 2 or 4) that runs `groups` fastest on this GPU.
+
+    Every variant is timed with HIP events on the current stream, over the given descriptor
+    set (desc [views][n_features][32], count [views]) or, without one, over random descriptors
+    with every view full.  The matcher's work does not depend on the descriptor bits but does
+    depend on the counts: uneven counts favour more, smaller blocks.  The winner is cached per
+    device, n_features, group shape and total count in AUTOTUNE_CACHE (a JSON file).
+    Returns (queries_per_lane, {variant: ms})."""
+    import json
+    import torch
+    groups = np.ascontiguousarray(groups, GROUP_DTYPE)
+    dev = torch.device(device)
+    total = int((groups["pair_base"] + groups["na"].astype(np.int64) * groups["nb"]).max())
+    n_views = int(max((groups["a0"] + groups["na"]).max(), (groups["b0"] + groups["nb"]).max()))
+    if desc is None:
+        gen = torch.Generator(device=dev).manual_seed(1)
+        desc = torch.randint(0, 256, (n_views, n_features, 32), dtype=torch.uint8, device=dev, generator=gen)
+        count = torch.full((n_views,), n_features, dtype=torch.int32, device=dev)
+    total_count = int(count.sum())
+    key = (f"{torch.cuda.get_device_name(dev)}|N={n_features}|groups={len(groups)}|pairs={total}"
+           f"|count={total_count}")
+    cache = {}
+    if use_cache and os.path.exists(AUTOTUNE_CACHE):
+        try:
+            with open(AUTOTUNE_CACHE) as f:
+                cache = json.load(f)
+        except (OSError, ValueError):
+            cache = {}
+        if key in cache:
+            return int(cache[key]["queries_per_lane"]), {int(k): v for k, v in cache[key]["ms"].items()}
+    stream = torch.cuda.current_stream(dev)
+    times = {}
+    for q in (1, 2, 4):
+        mp = plan_matches(groups, n_features, q)
+        match_groups(mp, desc, count)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            match_groups(mp, desc, count)
+        e1.record(stream)
+        torch.cuda.synchronize(dev)
+        times[q] = e0.elapsed_time(e1) / reps
+    best = min(times, key=times.get)
+    if use_cache:
+        cache[key] = {"queries_per_lane": best, "ms": times}
+        try:
+            os.makedirs(os.path.dirname(AUTOTUNE_CACHE), exist_ok=True)
+            with open(AUTOTUNE_CACHE, "w") as f:
+                json.dump(cache, f, indent=1)
+        except OSError:
+            pass
+    return best, times
+
+
 def match_groups(mplan: MatchPlan, desc, count, ratio_num: int = 4, ratio_den: int = 5):
     """Group matching over one descriptor set.  Returns (matches u8[P, N, 8], pair_count i32[P], best i32[G, 4])."""
     import torch
@@ -551,7 +611,8 @@ class BatchRunner:
     n views of B) in the global view numbering.  `ws` may bring a workspace (a uint8
     device tensor of at least `ws_bytes`, 256-byte aligned) shared with other runners
     that are not in flight at the same time, or be set later (allocate_ws=False, then
-    set_workspace)."""
+    set_workspace).  queries_per_lane = "auto" picks the matcher variant with
+    autotune_queries_per_lane on the descriptors of the first run or capture."""
 
     def __init__(self, pairs, grid, scales=(1.0,), n_levels: int = 8, n_features: int = 500,
                  fast_threshold: int = 20, device="cuda", queries_per_lane: int = 0,
@@ -622,7 +683,10 @@ class BatchRunner:
             v += 2 * nvs
         self.arena = arena
         self.splan = plan_scales(np.array(jobs, SCALE_JOB_DTYPE)) if jobs else None
-        self.mplan = plan_matches(np.array(groups, GROUP_DTYPE), n_features, queries_per_lane)
+        self.autotune = None
+        self._tune = queries_per_lane == "auto"
+        self.mplan = plan_matches(np.array(groups, GROUP_DTYPE), n_features, 0 if self._tune else queries_per_lane)
+        self.mplan_q = int(np.frombuffer(self.mplan.blob, np.int32, 4)[3])
         self.view_scale = np.array([arena.descs[s][5] for s in vsrc_all])
         self.n_views = len(vsrc_all)
         dev = self.device
@@ -676,11 +740,27 @@ class BatchRunner:
         return (sp, sd, len(self.chunks), self._hosts, self._devs, self.mplan.host_ptr(),
                 _ptr(self.mplan.device(self.device)), _ptr(self.sources))
 
+    def _tune_matcher(self, pattern, ratio_num, ratio_den):
+        """First run with queries_per_lane = "auto": run once, time the matcher variants on the
+        descriptor sets this batch produced, and re-plan the matcher with the fastest."""
+        self._tune = False
+        self.run(pattern, ratio_num, ratio_den)
+        q, ms = autotune_queries_per_lane(self.mplan.groups, self.mplan.n_features, self.device, self.desc, self.count)
+        self.autotune = {"queries_per_lane": q, "ms": ms}
+        if q != self.mplan_q:
+            self.close()
+            self.mplan = plan_matches(self.mplan.groups, self.mplan.n_features, q)
+            self.mplan_q = q
+
     def run(self, pattern, ratio_num: int = 4, ratio_den: int = 5):
+        if self._tune:
+            self._tune_matcher(pattern, ratio_num, ratio_den)
         _check(lib().xa_match_batch(*self._call_args(), _ptr(pattern), ratio_num, ratio_den, ctypes.byref(self.bufs),
                                     _ptr(self.ws), self.ws.numel(), _stream()))
 
     def capture(self, pattern, ratio_num: int = 4, ratio_den: int = 5):
+        if self._tune:
+            self._tune_matcher(pattern, ratio_num, ratio_den)
         self.close()
         g = ctypes.c_void_p(0)
         _check(lib().xa_match_batch_capture(*self._call_args(), _ptr(pattern), ratio_num, ratio_den,

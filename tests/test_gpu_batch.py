@@ -242,3 +242,29 @@ def test_batch_graph_replays(dev, pairs):
             say(f"[graph] replay {r} identical (junk {float(junk):.1f})")
     finally:
         br.close()
+
+
+def test_autotuner_picks_a_variant_and_caches_it(dev, pairs, tmp_path, monkeypatch):
+    """The matcher autotuner times the three variants, caches the winner, and a batch built with
+    it gives the same bytes as batches with each fixed variant."""
+    say("case: matcher autotuner (queries per lane 1 / 2 / 4) and its cache")
+    monkeypatch.setattr(X, "AUTOTUNE_CACHE", str(tmp_path / "autotune.json"))
+    grid = _grid(1)
+    pat = torch.from_numpy(synth.brief_pattern()).to(dev)
+    imgs = [(p.A, np.ascontiguousarray(p.B)) for p in pairs[:2]]
+    auto = X.BatchRunner(imgs, grid, (1.0,), n_levels=3, n_features=700, device=dev, queries_per_lane="auto")
+    auto.run(pat)                                          # tunes on its own descriptors, then runs
+    torch.cuda.synchronize()
+    q, ms = auto.autotune["queries_per_lane"], auto.autotune["ms"]
+    assert q in (1, 2, 4) and set(ms) == {1, 2, 4} and all(v > 0 for v in ms.values()) and ms[q] == min(ms.values())
+    assert auto.mplan_q == q and (tmp_path / "autotune.json").exists()
+    q2, ms2 = X.autotune_queries_per_lane(auto.mplan.groups, 700, dev, auto.desc, auto.count)
+    assert q2 == q and ms2 == ms                          # served from the cache
+    qr, msr = X.autotune_queries_per_lane(auto.mplan.groups, 700, dev)   # random full descriptors
+    assert qr in (1, 2, 4) and set(msr) == {1, 2, 4}
+    for fixed in (1, 2, 4):
+        r = X.BatchRunner(imgs, grid, (1.0,), n_levels=3, n_features=700, device=dev, queries_per_lane=fixed)
+        r.run(pat)
+        torch.cuda.synchronize()
+        assert torch.equal(r.matches, auto.matches) and torch.equal(r.best, auto.best)
+    say(f"[autotune] picked {q} queries per lane; ms {ms}")
