@@ -30,12 +30,13 @@ class OrbOptions:
 
 
 def plan_image(w: int, h: int, grid, psi: float = 0.0, s: float = 1.0):
-    return [P.plan_view(w, h, t, phi, psi, s) for (t, phi) in grid]
+    """Views for grid entries (t, phi) or (t, phi, s) (the latter override s)."""
+    return [P.plan_view(w, h, g[0], g[1], psi, g[2] if len(g) > 2 else s) for g in grid]
 
 
-def simulate_image(src_u8, views):
+def simulate_image(src_u8, views, interp: str = "lanczos4"):
     """Per view (V fp64, mask, u8)."""
-    return [S.simulate_view(src_u8, v) for v in views]
+    return [S.simulate_view(src_u8, v, interp) for v in views]
 
 
 def extract_image(sims, views, opts: OrbOptions, pattern):

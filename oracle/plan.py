@@ -40,6 +40,19 @@ def sampling_grid(n_tilt: int, b_deg: float = LONGITUDE_STEP_DEG):
     return out
 
 
+def sampling_grid_scaled(n_tilt: int, delta_s: float, b_deg: float = LONGITUDE_STEP_DEG):
+    """The search schedule of Sec. III.B with the scale tied to the tilt index:
+    (t_i, phi, s_i) with s_i = 1 + i * delta_s (a magnification; eq. (11) charges the views
+    of tilt index i the area factor (1 + i delta_s)^2)."""
+    out = []
+    for i in range(n_tilt + 1):
+        t = tilt(i)
+        for (tt, phi) in sampling_grid(i, b_deg):
+            if tt == t:
+                out.append((t, phi, 1.0 + i * delta_s))
+    return out
+
+
 def rot(a: float) -> np.ndarray:
     c, s = math.cos(a), math.sin(a)
     return np.array([[c, -s], [s, c]], np.float64)

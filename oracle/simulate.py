@@ -2,7 +2,9 @@
 
 Test infrastructure only (see the package docstring).
 
-Parity status: pinned.  Blur: axis-aligned cases equal scipy.ndimage.convolve1d
+Parity status: pinned.  Nearest-neighbour sampling: the identity view and integer
+translations reproduce the input, half-pixel positions round up, quarter turns equal
+np.rot90.  Blur: axis-aligned cases equal scipy.ndimage.convolve1d
 (mode 'nearest'), constants and ramps are preserved, and the impulse response
 has its variance along the tilt direction.  Warp: closed forms of the kernel
 of eq. (4), identity view reproduces the input, quarter turns equal np.rot90,
@@ -136,17 +138,37 @@ def warp_lanczos4(S, view: View, chunk: int = 1 << 16):
     return V, mask
 
 
+def nearest_sample(S, px, py):
+    """Nearest-neighbour resampling (the paper's search-time interpolation, Sec. III): the
+    source pixel floor(p + 1/2) on each axis (halves go up), clamped to the image."""
+    S = np.asarray(S, np.float64)
+    H, W = S.shape
+    ix = np.clip(np.floor(px + 0.5).astype(np.int64), 0, W - 1)
+    iy = np.clip(np.floor(py + 0.5).astype(np.int64), 0, H - 1)
+    return S[iy, ix]
+
+
+def warp_nearest(S, view: View):
+    """Like warp_lanczos4 with nearest-neighbour sampling."""
+    px, py = view_coords(view)
+    mask = valid_mask(view, px, py)
+    V = np.zeros((view.height, view.width), np.float64)
+    V[mask] = nearest_sample(S, px[mask], py[mask])
+    return V, mask
+
+
 def quantize(V):
     """u8 = clamp(round-half-to-even(V), 0, 255)."""
     return np.clip(np.rint(V), 0, 255).astype(np.uint8)
 
 
-def simulate_view(src_u8, view: View):
-    """One simulated view: blur along the tilt direction (t > 1), then Lanczos-4 resampling.
+def simulate_view(src_u8, view: View, interp: str = "lanczos4"):
+    """One simulated view: blur along the tilt direction (t > 1), then Lanczos-4 resampling
+    (interp = "lanczos4") or nearest-neighbour sampling (interp = "nearest").
 
     Returns (V fp64, mask bool, u8)."""
     S = directional_blur(src_u8, view.sigma, view.u) if view.sigma > 0 else np.asarray(src_u8, np.float64)
-    V, mask = warp_lanczos4(S, view)
+    V, mask = warp_nearest(S, view) if interp == "nearest" else warp_lanczos4(S, view)
     U = quantize(V)
     U[~mask] = 0
     return V, mask, U

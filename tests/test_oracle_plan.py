@@ -99,3 +99,14 @@ def test_level_dims_and_quotas():
         assert all(a >= b for a, b in zip(q, q[1:]))
         # proportional to level area: consecutive ratios near 1.44
         assert q[1] / q[2] == pytest.approx(1.44, rel=0.05)
+
+
+def test_coupled_scale_schedule_matches_eq11():
+    """s_i = 1 + i delta_s on tilt index i; view counts per tilt stay 3, 4, 5, 8, 10, 15 and the
+    area factors are (1 + i delta_s)^2 as in eq. (11)."""
+    g = P.sampling_grid_scaled(5, 0.5)
+    assert len(g) == 45
+    for i, n in enumerate((3, 4, 5, 8, 10, 15)):
+        rows = [r for r in g if abs(r[0] - P.tilt(i)) < 1e-12]
+        assert len(rows) == n and all(abs(r[2] - (1 + 0.5 * i)) < 1e-15 for r in rows)
+    assert [r[:2] for r in P.sampling_grid_scaled(5, 0.0)] == P.sampling_grid(5)

@@ -216,3 +216,42 @@ def test_sigma_follows_net_compression():
     assert v.sigma == pytest.approx(0.8 * math.sqrt(3.0))
     assert P.plan_view(64, 64, 2.0, 0.3, s=2.0).sigma == 0.0
     assert P.plan_view(64, 64, 1.0, 0.0, s=3.0).sigma == 0.0
+
+
+def test_nearest_identity_shift_and_ties():
+    img = np.random.default_rng(4).integers(0, 256, (30, 41)).astype(np.uint8)
+    v = P.plan_view(41, 30, 1.0, 0.0)
+    V, M, U = S.simulate_view(img, v, "nearest")
+    assert M.all() and np.array_equal(U, img)
+    # half-pixel positions take the pixel above/right (floor(p + 1/2))
+    px = np.array([0.5, 1.5, 2.49999, 2.5, -0.5, 40.5])
+    py = np.array([0.5, 0.0, 0.0, 0.0, -0.5, 29.5])
+    got = S.nearest_sample(img, px, py)
+    assert np.array_equal(got, [img[1, 1], img[0, 2], img[0, 2], img[0, 3], img[0, 0], img[29, 40]])
+
+
+def test_nearest_quarter_turn_is_rot90():
+    img = np.random.default_rng(5).integers(0, 256, (24, 24)).astype(np.uint8)
+    for k, phi in ((1, math.pi / 2), (2, math.pi), (3, 3 * math.pi / 2)):
+        v = P.plan_view(24, 24, 1.0, phi)
+        _, M, U = S.simulate_view(img, v, "nearest")
+        assert M.all()
+        assert any(np.array_equal(U, np.rot90(img, kk)) for kk in (k, -k))
+
+
+def test_nearest_brute_force_on_a_tilted_view():
+    img = np.random.default_rng(6).integers(0, 256, (20, 26)).astype(np.uint8)
+    v = P.plan_view(26, 20, 2.0, 0.4, 0.3, 1.3)
+    B = S.directional_blur(img, v.sigma, v.u)
+    V, M = S.warp_nearest(B, v)
+    G = v.inv
+    for qy in range(v.height):
+        for qx in range(v.width):
+            px = G[0, 0] * qx + G[0, 1] * qy + G[0, 2]
+            py = G[1, 0] * qx + G[1, 1] * qy + G[1, 2]
+            inside = -0.5 <= px <= 25.5 and -0.5 <= py <= 19.5
+            assert M[qy, qx] == inside
+            if inside:
+                ix = min(max(int(math.floor(px + 0.5)), 0), 25)
+                iy = min(max(int(math.floor(py + 0.5)), 0), 19)
+                assert V[qy, qx] == B[iy, ix]
