@@ -103,8 +103,11 @@ typedef struct {
     int32_t blur_major;         /* 0: taps step along x, 1: along y */
     int32_t blur_tap0;          /* first entry in the tap table */
     int32_t blur_ntaps;         /* 2K + 1, 0 if no blur */
-    int32_t pad;
+    int32_t interp;             /* XA_INTERP_LANCZOS4 (eqs. (3)-(4)) or XA_INTERP_NEAREST */
 } xa_view_desc;
+
+#define XA_INTERP_LANCZOS4 0
+#define XA_INTERP_NEAREST 1
 
 /* One pyramid level of one view.  Level sizes are round(W' / scale^l);
  * quota is the number of keypoints the level may contribute.  Pixel (x, y)
@@ -192,6 +195,12 @@ const char* xa_version(void);
  * full count (XA_ECAPACITY if it exceeds cap).  Host only. */
 xa_status xa_sampling_grid(int32_t n_tilt, double b_deg, xa_affine_params* out, int32_t cap, int32_t* n_out);
 
+/* The same grid with the scale tied to the tilt index (Sec. III.B): the views of tilt
+ * t_i = sqrt(2)^i get s = 1 + i * delta_s, a magnification (eq. (11) charges them the area
+ * factor (1 + i delta_s)^2).  delta_s = 0 gives xa_sampling_grid.  delta_s must be >= 0. */
+xa_status xa_sampling_grid_scaled(int32_t n_tilt, double b_deg, double delta_s, xa_affine_params* out, int32_t cap,
+                                  int32_t* n_out);
+
 /* Plan simulated views of one or more source images (Sec. III.B, eq. (2)):
  * canvases, maps, blur taps, pyramid levels (n_levels at factor level_scale),
  * per-level quotas of n_features keypoints (proportional to level area) and
@@ -203,6 +212,13 @@ xa_status xa_sampling_grid(int32_t n_tilt, double b_deg, xa_affine_params* out, 
 xa_status xa_plan_views(const xa_source_desc* sources, int32_t n_sources, const int32_t* view_source,
                         const xa_affine_params* params, int32_t n_views, int32_t n_levels, double level_scale,
                         int32_t n_features, int32_t fast_threshold, void* blob, size_t blob_cap, size_t* blob_bytes);
+
+/* Resampling of every view of a host plan blob: XA_INTERP_LANCZOS4 (the default of
+ * xa_plan_views; eqs. (3)-(4)) or XA_INTERP_NEAREST (the search-time interpolation of
+ * Sec. III: the source pixel floor(p + 1/2) per axis, clamped).  Blur, canvas and validity
+ * are unchanged.  Call it before copying the blob to the device.  XA_EINVAL for another
+ * value or a blob that is not a view plan. */
+xa_status xa_plan_set_interp(void* plan_host, int32_t interp);
 
 /* xa_plan_views for one src_w x src_h image at offset 0 of its buffer. */
 xa_status xa_plan_image(int32_t src_w, int32_t src_h, int32_t src_pitch, const xa_affine_params* params,

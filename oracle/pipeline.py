@@ -61,14 +61,15 @@ def keypoints_to_source(feat, view, opts: OrbOptions, src_scale: float = 1.0):
     return xs, ys
 
 
-def simulate_and_extract(img, grid, opts: OrbOptions, pattern, scales=(1.0,)):
+def simulate_and_extract(img, grid, opts: OrbOptions, pattern, scales=(1.0,), interp: str = "lanczos4"):
     """Views of an image over the grid at every scale of the sampling group (Sec. III.B):
-    scale s != 1 goes through the scale stage first and its views use s = 1 in their map."""
+    scale s != 1 goes through the scale stage first and its views use s = 1 in their map
+    (grid entries (t, phi, s) carry their own s into the view map instead)."""
     views, sims, feats, vscale = [], [], [], []
     for s in scales:
         src = img if s == 1.0 else S.scale_image(img, s)[1]
         vs = plan_image(src.shape[1], src.shape[0], grid)
-        sm = simulate_image(src, vs)
+        sm = simulate_image(src, vs, interp)
         views += vs
         sims += sm
         feats += extract_image(sm, vs, opts, pattern)
@@ -76,11 +77,12 @@ def simulate_and_extract(img, grid, opts: OrbOptions, pattern, scales=(1.0,)):
     return views, sims, feats, vscale
 
 
-def match_pair(A, B, grid_a, grid_b, opts: OrbOptions, pattern, scales_a=(1.0,), scales_b=(1.0,)):
+def match_pair(A, B, grid_a, grid_b, opts: OrbOptions, pattern, scales_a=(1.0,), scales_b=(1.0,),
+               interp: str = "lanczos4"):
     """Full path for one image pair.  Returns a dict with per-view features, the
     pair counts, the best pair and its accepted matches in original-image coordinates."""
-    va, sa, fa, ka = simulate_and_extract(A, grid_a, opts, pattern, scales_a)
-    vb, sb, fb, kb = simulate_and_extract(B, grid_b, opts, pattern, scales_b)
+    va, sa, fa, ka = simulate_and_extract(A, grid_a, opts, pattern, scales_a, interp)
+    vb, sb, fb, kb = simulate_and_extract(B, grid_b, opts, pattern, scales_b, interp)
     results, counts, best = M.match_views([f["desc"] for f in fa], [f["desc"] for f in fb],
                                           opts.ratio_num, opts.ratio_den)
     k, i, j, c = best

@@ -96,7 +96,13 @@ static double tilt_of(int i) {
 
 extern "C" xa_status xa_sampling_grid(int32_t n_tilt, double b_deg, xa_affine_params* out, int32_t cap,
                                       int32_t* n_out) {
+    return xa_sampling_grid_scaled(n_tilt, b_deg, 0.0, out, cap, n_out);
+}
+
+extern "C" xa_status xa_sampling_grid_scaled(int32_t n_tilt, double b_deg, double delta_s, xa_affine_params* out,
+                                             int32_t cap, int32_t* n_out) {
     if (n_tilt < 0 || n_tilt > 20) return fail(XA_EINVAL, "n_tilt %d out of range [0, 20]", n_tilt);
+    if (!(delta_s >= 0.0) || !std::isfinite(delta_s)) return fail(XA_EINVAL, "delta_s must be >= 0");
     if (!(b_deg > 0.0) || !std::isfinite(b_deg)) return fail(XA_EINVAL, "longitude step must be > 0");
     if (!n_out || cap < 0 || (cap > 0 && !out)) return fail(XA_EINVAL, "bad output arguments");
     int32_t n = 0;
@@ -105,7 +111,7 @@ extern "C" xa_status xa_sampling_grid(int32_t n_tilt, double b_deg, xa_affine_pa
         for (int k = 0; double(k) * b_deg < 180.0 * t; ++k) {
             if (n < cap) {
                 const double deg = double(k) * b_deg / t;
-                out[n] = xa_affine_params{t, deg * (M_PI / 180.0), 0.0, 1.0, 0.0, 0.0};
+                out[n] = xa_affine_params{t, deg * (M_PI / 180.0), 0.0, 1.0 + double(i) * delta_s, 0.0, 0.0};
             }
             ++n;
         }
@@ -362,6 +368,16 @@ extern "C" xa_status xa_plan_views(const xa_source_desc* sources, int32_t n_sour
     std::memcpy(b + h.off_blur_prefix, blur_prefix.data(), 4 * blur_prefix.size());
     std::memcpy(b + h.off_sources, sources, sizeof(xa_source_desc) * n_sources);
     if (!fast_flags.empty()) std::memcpy(b + h.off_fast_flags, fast_flags.data(), fast_flags.size());
+    return ok();
+}
+
+extern "C" xa_status xa_plan_set_interp(void* plan_host, int32_t interp) {
+    if (interp != XA_INTERP_LANCZOS4 && interp != XA_INTERP_NEAREST) return fail(XA_EINVAL, "unknown interpolation %d", interp);
+    PlanView p;
+    const xa_status s = plan_host_view(plan_host, &p);
+    if (s != XA_OK) return s;
+    auto* views = reinterpret_cast<xa_view_desc*>(static_cast<char*>(plan_host) + p.h->off_views);
+    for (int i = 0; i < p.h->n_views; ++i) views[i].interp = interp;
     return ok();
 }
 

@@ -228,6 +228,33 @@ __global__ void __launch_bounds__(kWarpThreads) k_warp(const uint8_t* __restrict
     const int tw = v.warp_tile_w, th = kWarpRows * kWarpThreads / tw;
     const int tiles_x = (v.width + tw - 1) / tw;
     const int x0 = (local % tiles_x) * tw, y0 = (local / tiles_x) * th;
+    if (v.interp == XA_INTERP_NEAREST) {
+        // nearest neighbour (the search-time interpolation of Sec. III): one read per pixel,
+        // the source pixel floor(p + 1/2) per axis, clamped; nothing is staged
+        const float* nsrc = blurred + (v.blur_offset >= 0 ? v.blur_offset : 0);
+        const int qx = x0 + int(threadIdx.x) % tw;
+        for (int k = 0; k < kWarpRows; ++k) {
+            const int qy = y0 + int(threadIdx.x) / tw + k * (kWarpThreads / tw);
+            if (qx >= v.width || qy >= v.height) break;
+            const size_t o = size_t(v.offset) + size_t(qy) * v.pitch + qx;
+            const double px = affine_x(v.inv, double(qx), double(qy));
+            const double py = affine_x(v.inv + 3, double(qx), double(qy));
+            if (!(px >= -0.5 && px <= W - 0.5 && py >= -0.5 && py <= H - 0.5)) {
+                arena[o] = 0;
+                mask[o] = 0;
+                if (values) values[o] = 0.0f;
+                continue;
+            }
+            const int ix = clampi(int(floor(px + 0.5)), 0, W - 1), iy = clampi(int(floor(py + 0.5)), 0, H - 1);
+            const float val = v.blur_offset >= 0 ? nsrc[size_t(iy) * blur_pitch(W) + ix]
+                                                 : float(src[size_t(iy) * pitch + ix]);
+            const float q = rintf(val);
+            arena[o] = uint8_t(q < 0.0f ? 0.0f : (q > 255.0f ? 255.0f : q));
+            mask[o] = 1;
+            if (values) values[o] = val;
+        }
+        return;
+    }
     // bounding box of the footprint (the tile's pixel centres through inv, grown by the
     // 8-tap window, clamped to the source): the corner (x0, y0) plus the extreme offsets of
     // the other corners; rounding here is ~1e-12 px, far inside the 1e-6 margin

@@ -29,7 +29,7 @@ VIEW_DTYPE = np.dtype([("p", PARAMS_DTYPE), ("source", "i4"), ("src_w", "i4"), (
                        ("src_offset", "i8"), ("src_scale", "f8"), ("width", "i4"), ("height", "i4"), ("pitch", "i4"),
                        ("warp_tile_w", "i4"), ("fwd", "f8", 6), ("inv", "f8", 6), ("sigma", "f8"), ("ux", "f8"),
                        ("uy", "f8"), ("offset", "i8"), ("blur_offset", "i8"), ("blur_major", "i4"), ("blur_tap0", "i4"),
-                       ("blur_ntaps", "i4"), ("pad", "i4")])
+                       ("blur_ntaps", "i4"), ("interp", "i4")])
 LEVEL_DTYPE = np.dtype([("width", "i4"), ("height", "i4"), ("pitch", "i4"), ("quota", "i4"), ("offset", "i8"),
                         ("kp_base", "i4"), ("view", "i4"), ("level", "i4"), ("pad", "i4"), ("cand_offset", "i8"),
                         ("cand_cap", "i8")])
@@ -112,6 +112,9 @@ _SIGS = {
     "xa_warp_f32_bwd_workspace_size": (_c.c_size_t, [_c.c_int32, _c.c_int32, _c.c_int32]),
     "xa_warp_f32_bwd": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_int32, _c.c_int32,
                                    _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "xa_sampling_grid_scaled": (_c.c_int, [_c.c_int32, _c.c_double, _c.c_double, _c.c_void_p, _c.c_int32,
+                                           _c.POINTER(_c.c_int32)]),
+    "xa_plan_set_interp": (_c.c_int, [_c.c_void_p, _c.c_int32]),
     "xa_match_pair_workspace_size": (_c.c_size_t, [_c.c_void_p, _c.c_void_p]),
     "xa_match_pair": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                  _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_int32,
@@ -151,14 +154,26 @@ def version() -> str:
 
 # ---------------------------------------------------------------- planning (host only)
 
-def sampling_grid(n_tilt: int, b_deg: float = 72.0) -> np.ndarray:
+def sampling_grid(n_tilt: int, b_deg: float = 72.0, delta_s: float = 0.0) -> np.ndarray:
+    """The (t, phi) grid of Sec. III.B; delta_s > 0 ties the scale to the tilt index, s = 1 + i delta_s."""
     n = ctypes.c_int32(0)
-    st = lib().xa_sampling_grid(n_tilt, b_deg, None, 0, ctypes.byref(n))
+    st = lib().xa_sampling_grid_scaled(n_tilt, b_deg, delta_s, None, 0, ctypes.byref(n))
     if st not in (XA_OK, XA_ECAPACITY):
         _check(st)
     out = np.zeros(n.value, PARAMS_DTYPE)
-    _check(lib().xa_sampling_grid(n_tilt, b_deg, out.ctypes.data, n.value, ctypes.byref(n)))
+    _check(lib().xa_sampling_grid_scaled(n_tilt, b_deg, delta_s, out.ctypes.data, n.value, ctypes.byref(n)))
     return out
+
+
+INTERP = {"lanczos4": 0, "nearest": 1}
+
+
+def _set_interp(plan: "Plan", interp: str) -> "Plan":
+    if interp not in INTERP:
+        raise XAError(-1, f"interp must be one of {sorted(INTERP)}")
+    if INTERP[interp] != 0:
+        _check(lib().xa_plan_set_interp(plan.blob.ctypes.data, INTERP[interp]))
+    return _wrap_plan(plan.blob)
 
 
 def make_params(rows) -> np.ndarray:
@@ -227,7 +242,7 @@ def _wrap_plan(blob: np.ndarray) -> Plan:
 
 
 def plan_views(sources: np.ndarray, view_source, params: np.ndarray, n_levels: int = 8, level_scale: float = 1.2,
-               n_features: int = 1000, fast_threshold: int = 20) -> Plan:
+               n_features: int = 1000, fast_threshold: int = 20, interp: str = "lanczos4") -> Plan:
     """Plan views of several sources (SOURCE_DTYPE array); view i simulates sources[view_source[i]]."""
     sources = np.ascontiguousarray(sources, SOURCE_DTYPE)
     vs = np.ascontiguousarray(view_source, np.int32)
@@ -239,11 +254,12 @@ def plan_views(sources: np.ndarray, view_source, params: np.ndarray, n_levels: i
     _check(lib().xa_plan_views(*args, None, 0, ctypes.byref(n)))
     blob = np.zeros(n.value, np.uint8)
     _check(lib().xa_plan_views(*args, blob.ctypes.data, blob.size, ctypes.byref(n)))
-    return _wrap_plan(blob)
+    return _set_interp(_wrap_plan(blob), interp)
 
 
 def plan_image(src_w: int, src_h: int, params: np.ndarray, n_levels: int = 8, level_scale: float = 1.2,
-               n_features: int = 1000, fast_threshold: int = 20, src_pitch: int | None = None) -> Plan:
+               n_features: int = 1000, fast_threshold: int = 20, src_pitch: int | None = None,
+               interp: str = "lanczos4") -> Plan:
     """Plan views of one image stored at offset 0 of its buffer with the given row pitch."""
     params = np.ascontiguousarray(params, PARAMS_DTYPE)
     pitch = src_w if src_pitch is None else src_pitch
@@ -252,7 +268,7 @@ def plan_image(src_w: int, src_h: int, params: np.ndarray, n_levels: int = 8, le
     _check(lib().xa_plan_image(*args, None, 0, ctypes.byref(n)))
     blob = np.zeros(n.value, np.uint8)
     _check(lib().xa_plan_image(*args, blob.ctypes.data, blob.size, ctypes.byref(n)))
-    return _wrap_plan(blob)
+    return _set_interp(_wrap_plan(blob), interp)
 
 
 SCALE_JOB_DTYPE = np.dtype([("src", SOURCE_DTYPE), ("dst", SOURCE_DTYPE), ("s", "f8")])
@@ -616,13 +632,17 @@ class BatchRunner:
 
     def __init__(self, pairs, grid, scales=(1.0,), n_levels: int = 8, n_features: int = 500,
                  fast_threshold: int = 20, device="cuda", queries_per_lane: int = 0,
-                 chunk_bytes: int = 24 << 30, ws=None, allocate_ws: bool = True):
+                 chunk_bytes: int = 24 << 30, ws=None, allocate_ws: bool = True, interp: str = "lanczos4"):
         import torch
         self.device = torch.device(device)
         L = lib()
         arena = SourceArena()
         jobs, images = [], {}
-        rows = [(float(t), float(f)) for t, f in grid]
+        # grid rows (t, phi) or (t, phi, s); a structured PARAMS_DTYPE array gives all six parameters
+        if isinstance(grid, np.ndarray) and grid.dtype.names:
+            rows = [tuple(float(r[k]) for k in ("t", "phi", "psi", "s", "tx", "ty")) for r in grid]
+        else:
+            rows = [(float(g[0]), float(g[1]), 0.0, float(g[2]) if len(g) > 2 else 1.0, 0.0, 0.0) for g in grid]
         pair_views = []          # per pair: list over sides of [(source index, scale)]
         for (A, B) in pairs:
             sides = []
@@ -647,11 +667,11 @@ class BatchRunner:
             for sides in ps:
                 for srcs in sides:
                     for src in srcs:
-                        for (t, phi) in rows:
+                        for row in rows:
                             vsrc.append(src)
-                            params.append((t, phi, 0.0, 1.0, 0.0, 0.0))
+                            params.append(row)
             return plan_views(table, vsrc, np.array(params, PARAMS_DTYPE), n_levels, 1.2, n_features,
-                              fast_threshold), vsrc
+                              fast_threshold, interp), vsrc
 
         def chunk_ws(plan):
             ptrs = (ctypes.c_void_p * 1)(plan.host_ptr())

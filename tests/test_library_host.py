@@ -225,3 +225,19 @@ def test_fast_tile_flags_are_conservative():
                         assert f[yy // 32, xx // 64] & 1, (i, l, x, y)
     print("tiles without detection", skipped, "of", len(flags))
     assert skipped > 0.2 * len(flags)
+
+
+def test_scaled_grid_matches_oracle_and_interp_switch():
+    g = X.sampling_grid(5, 72.0, 0.5)
+    ref = OP.sampling_grid_scaled(5, 0.5)
+    assert len(g) == len(ref) == 45
+    for r, (t, phi, s) in zip(g, ref):
+        assert r["t"] == t and abs(r["phi"] - phi) < 1e-15 and r["s"] == s
+    assert np.array_equal(X.sampling_grid(5, 72.0, 0.0), X.sampling_grid(5))
+    with pytest.raises(X.XAError):
+        X.sampling_grid(5, 72.0, -0.5)
+    p = X.plan_image(64, 48, X.make_params([(1.0, 0.0), (2.0, 0.5)]), 2, 1.2, 50, 20, interp="nearest")
+    assert np.all(p.views["interp"] == 1)
+    assert np.all(X.plan_image(64, 48, X.make_params([(2.0, 0.5)]), 2, 1.2, 50, 20).views["interp"] == 0)
+    with pytest.raises(X.XAError):
+        X._check(X.lib().xa_plan_set_interp(p.blob.ctypes.data, 7))
