@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--batch-pairs", type=int, default=64, help="image pairs in the batched leg (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--crops", type=int, default=256, help="crops in the differentiable-warp leg (0 = skip)")
-    ap.add_argument("--only", choices=["batched", "diffwarp", "copy"], default=None,
+    ap.add_argument("--only", choices=["batched", "diffwarp", "copy", "sweep"], default=None,
                     help="run one leg alone and print its JSON (for profiler runs); 'copy' is a plain 1 GiB "
                          "device-to-device copy whose counter readings calibrate the HBM traffic counters")
     return ap.parse_args()
@@ -218,6 +218,47 @@ def batched_leg(args, dev, pattern, raw, gen_s):
     }
 
 
+def sweep_leg(args, dev, pattern):
+    """The parameter studies of Sec. IV.D as timings on the full-size pair, in the paper's search
+    mode (nearest-neighbour views of A over the grid with s_i = 1 + i ds, matched against B's
+    identity view): ORB point count N in {500, 800, 1000, 1200, 1500} at ds = 0.5, and
+    ds in {0, 0.2, ..., 1.0} at N = 1000.  Per setting: ms per pair (HIP events, 10 calls),
+    views and their pixels, best-pair matches and precision at 2 px."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2503_03479_amd import xaffine as X
+
+    case = synth.make_pair(**synth.PAIR_CONFIGS["full"])
+    A = torch.from_numpy(np.ascontiguousarray(case.A)).to(dev)
+    Bn = np.ascontiguousarray(case.B)
+    B = torch.from_numpy(Bn).to(dev)
+    stream = torch.cuda.current_stream()
+    out = []
+    settings = [(n, 0.5) for n in (500, 800, 1000, 1200, 1500)] + [(1000, ds) for ds in (0.0, 0.2, 0.4, 0.6, 0.8, 1.0)]
+    for n, ds in settings:
+        grid = X.sampling_grid(5, 72.0, ds)
+        pa = X.plan_image(1024, 768, grid, 8, 1.2, n, 20, interp="nearest")
+        pb = X.plan_image(Bn.shape[1], Bn.shape[0], X.make_params([(1.0, 0.0)]), 8, 1.2, n, 20, interp="nearest")
+        run = X.PairRunner(pa, pb, dev)
+        run.run(A, B, pattern)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(10):
+            run.run(A, B, pattern)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pr = run.precision(case.H, 2.0).cpu().numpy()
+        out.append({"n_features": n, "delta_s": ds, "ms_per_pair": e0.elapsed_time(e1) / 10,
+                    "views": pa.n_views, "view_mpx": float((pa.views["width"] * pa.views["height"]).sum()) / 1e6,
+                    "best_pair": run.best.cpu().numpy().tolist(), "correct": int(pr[0]), "matches": int(pr[1])})
+        del run
+    return {"workload": "full-size pair, search mode: nearest-neighbour views of A over the 45-view grid with "
+                        "s_i = 1 + i ds, single-image matching against B, 8 levels", "settings": out}
+
+
 def diffwarp_leg(args, dev):
     """Differentiable warp on n fp32 crops of 512 x 512 (parameters drawn per crop):
     forward and adjoint (image + six parameters) timed with HIP events."""
@@ -305,6 +346,8 @@ def main():
             print(json.dumps(batched_leg(args, dev, pattern, raw, gen_s)), flush=True)
         elif args.only == "diffwarp":
             print(json.dumps(diffwarp_leg(args, dev)), flush=True)
+        elif args.only == "sweep":
+            print(json.dumps(sweep_leg(args, dev, pattern)), flush=True)
         else:
             a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
             b = torch.empty_like(a)
