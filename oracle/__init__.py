@@ -18,5 +18,7 @@ Modules
   pipeline  -- the composition: simulate both images, extract, match all view pairs
   diffwarp  -- the Lanczos-4 warp of an fp image as a function of the six camera
                parameters, and its adjoint (image and parameter gradients)
+  geometry  -- homography RANSAC over matched points (Sec. III.C) and the inlier
+               ratio of eq. (7)
 """
-from . import plan, simulate, orb, match, pipeline, diffwarp  # noqa: F401
+from . import plan, simulate, orb, match, pipeline, diffwarp, geometry  # noqa: F401

@@ -1,0 +1,94 @@
+"""Homography RANSAC over matched points and the inlier ratio of eq. (7).
+
+Test infrastructure only (see the package docstring).
+
+Sec. III.C screens the final matches with RANSAC on a homography; eq. (7) scores a
+method by the share of matched points that RANSAC keeps as inliers.  Here the random
+draws are an input (K samples of 4 match indices), so the result is a plain function
+of the points, the samples and the threshold:
+
+* a sample is degenerate iff some 3 of its 4 points, in image A or in image B, span a
+  doubled triangle area |cross| < 1 px^2 (then it scores -1);
+* otherwise H (3x3, h33 = 1) is the solution of the 8x8 linear system that maps the 4
+  points of A onto those of B (numpy.linalg.solve);
+* its score is the number of matches with |H(p_a) - p_b| <= th, H(p) the projective
+  image (u/w, v/w); a match with w <= 0 is an outlier;
+* the best sample has the highest score, the lowest index on ties (none if every
+  sample is degenerate).
+
+Parity status: pinned.  The solved H maps its 4 points exactly onto their targets and
+recovers a known homography from any 4 of its correspondences; degenerate samples
+score -1; on data with a known homography and gross outliers the best score equals
+the number of true inliers; the inlier ratio is the plain quotient of eq. (7).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+DEGENERATE_AREA = 1.0          # doubled triangle area (px^2) below which 3 points count as collinear
+
+
+def degenerate(p4) -> bool:
+    """Some 3 of the 4 points (4 x 2) span |cross| < DEGENERATE_AREA."""
+    p = np.asarray(p4, np.float64)
+    for a, b, c in ((0, 1, 2), (0, 1, 3), (0, 2, 3), (1, 2, 3)):
+        cross = (p[b, 0] - p[a, 0]) * (p[c, 1] - p[a, 1]) - (p[b, 1] - p[a, 1]) * (p[c, 0] - p[a, 0])
+        if abs(cross) < DEGENERATE_AREA:
+            return True
+    return False
+
+
+def homography_from_4(src4, dst4):
+    """H with h33 = 1 mapping the 4 src points onto the 4 dst points, or None if degenerate."""
+    s = np.asarray(src4, np.float64)
+    d = np.asarray(dst4, np.float64)
+    if degenerate(s) or degenerate(d):
+        return None
+    A = np.zeros((8, 8))
+    b = np.zeros(8)
+    for i in range(4):
+        x, y = s[i]
+        u, v = d[i]
+        A[2 * i] = [x, y, 1.0, 0.0, 0.0, 0.0, -u * x, -u * y]
+        A[2 * i + 1] = [0.0, 0.0, 0.0, x, y, 1.0, -v * x, -v * y]
+        b[2 * i], b[2 * i + 1] = u, v
+    h = np.linalg.solve(A, b)
+    return np.append(h, 1.0).reshape(3, 3)
+
+
+def residuals(H, pa, pb):
+    """|H(p_a) - p_b| per match; inf where w <= 0."""
+    pa = np.asarray(pa, np.float64)
+    pb = np.asarray(pb, np.float64)
+    w = H[2, 0] * pa[:, 0] + H[2, 1] * pa[:, 1] + H[2, 2]
+    u = H[0, 0] * pa[:, 0] + H[0, 1] * pa[:, 1] + H[0, 2]
+    v = H[1, 0] * pa[:, 0] + H[1, 1] * pa[:, 1] + H[1, 2]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ex, ey = u / w - pb[:, 0], v / w - pb[:, 1]
+        r = np.sqrt(ex * ex + ey * ey)
+    return np.where(w > 0, r, np.inf)
+
+
+def ransac(pa, pb, samples, th: float):
+    """Score every sample; returns (scores [K], best index or -1, H of the best or None,
+    inlier mask of the best [n] bool)."""
+    pa = np.asarray(pa, np.float64)
+    pb = np.asarray(pb, np.float64)
+    scores = np.full(len(samples), -1, np.int64)
+    Hs = [None] * len(samples)
+    for k, idx in enumerate(np.asarray(samples, np.int64)):
+        H = homography_from_4(pa[idx], pb[idx])
+        if H is None:
+            continue
+        Hs[k] = H
+        scores[k] = int(np.sum(residuals(H, pa, pb) <= th))
+    if len(samples) == 0 or scores.max() < 0:
+        return scores, -1, None, np.zeros(len(pa), bool)
+    best = int(np.argmax(scores))                # first maximum: lowest index on ties
+    H = Hs[best]
+    return scores, best, H, residuals(H, pa, pb) <= th
+
+
+def inlier_ratio(n_inliers: int, n_points: int) -> float:
+    """Eq. (7): In_Num / Pt_Num (as a fraction; 0 for no points)."""
+    return n_inliers / n_points if n_points > 0 else 0.0
