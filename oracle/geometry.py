@@ -14,12 +14,14 @@ of the points, the samples and the threshold:
 * its score is the number of matches with |H(p_a) - p_b| <= th, H(p) the projective
   image (u/w, v/w); a match with w <= 0 is an outlier;
 * the best sample has the highest score, the lowest index on ties (none if every
-  sample is degenerate).
+  sample is degenerate); its inliers are refitted by least squares in Hartley-normalised
+  coordinates.
 
 Parity status: pinned.  The solved H maps its 4 points exactly onto their targets and
 recovers a known homography from any 4 of its correspondences; degenerate samples
 score -1; on data with a known homography and gross outliers the best score equals
-the number of true inliers; the inlier ratio is the plain quotient of eq. (7).
+the number of true inliers and the refit recovers the homography; the refit of exact
+correspondences is exact; the inlier ratio is the plain quotient of eq. (7).
 """
 from __future__ import annotations
 
@@ -69,9 +71,49 @@ def residuals(H, pa, pb):
     return np.where(w > 0, r, np.inf)
 
 
+def normalizing_transform(p):
+    """Hartley's normalisation: translate the centroid to 0 and scale the mean distance to
+    sqrt(2); None if the points coincide."""
+    p = np.asarray(p, np.float64)
+    c = p.mean(axis=0)
+    d = np.sqrt(((p - c) ** 2).sum(axis=1)).mean()
+    if not d > 0:
+        return None
+    s = np.sqrt(2.0) / d
+    return np.array([[s, 0.0, -s * c[0]], [0.0, s, -s * c[1]], [0.0, 0.0, 1.0]])
+
+
+def refit_homography(pa, pb):
+    """Least-squares homography (h33 = 1) over >= 4 correspondences in Hartley-normalised
+    coordinates (numpy.linalg.lstsq), mapped back; None with fewer than 4 points or
+    coincident points."""
+    pa = np.asarray(pa, np.float64)
+    pb = np.asarray(pb, np.float64)
+    if len(pa) < 4:
+        return None
+    Ta, Tb = normalizing_transform(pa), normalizing_transform(pb)
+    if Ta is None or Tb is None:
+        return None
+    a = pa @ Ta[:2, :2].T + Ta[:2, 2]
+    b = pb @ Tb[:2, :2].T + Tb[:2, 2]
+    m = len(a)
+    A = np.zeros((2 * m, 8))
+    r = np.zeros(2 * m)
+    A[0::2, 0], A[0::2, 1], A[0::2, 2] = a[:, 0], a[:, 1], 1.0
+    A[0::2, 6], A[0::2, 7] = -b[:, 0] * a[:, 0], -b[:, 0] * a[:, 1]
+    A[1::2, 3], A[1::2, 4], A[1::2, 5] = a[:, 0], a[:, 1], 1.0
+    A[1::2, 6], A[1::2, 7] = -b[:, 1] * a[:, 0], -b[:, 1] * a[:, 1]
+    r[0::2], r[1::2] = b[:, 0], b[:, 1]
+    h = np.linalg.lstsq(A, r, rcond=None)[0]
+    H = np.linalg.inv(Tb) @ np.append(h, 1.0).reshape(3, 3) @ Ta
+    return H / H[2, 2]
+
+
 def ransac(pa, pb, samples, th: float):
     """Score every sample; returns (scores [K], best index or -1, H of the best or None,
-    inlier mask of the best [n] bool)."""
+    inlier mask of the best [n] bool).  H is the least-squares refit over the best
+    sample's inliers (refit_homography), or the sample's own H if that has no solution;
+    the inlier mask is the best sample's."""
     pa = np.asarray(pa, np.float64)
     pb = np.asarray(pb, np.float64)
     scores = np.full(len(samples), -1, np.int64)
@@ -85,8 +127,9 @@ def ransac(pa, pb, samples, th: float):
     if len(samples) == 0 or scores.max() < 0:
         return scores, -1, None, np.zeros(len(pa), bool)
     best = int(np.argmax(scores))                # first maximum: lowest index on ties
-    H = Hs[best]
-    return scores, best, H, residuals(H, pa, pb) <= th
+    inl = residuals(Hs[best], pa, pb) <= th
+    H = refit_homography(pa[inl], pb[inl])
+    return scores, best, (Hs[best] if H is None else H), inl
 
 
 def inlier_ratio(n_inliers: int, n_points: int) -> float:

@@ -68,3 +68,17 @@ def test_points_behind_the_camera_are_outliers():
 
 def test_eq7_quotient():
     assert G.inlier_ratio(45, 60) == 0.75 and G.inlier_ratio(0, 0) == 0.0
+
+
+def test_refit_is_exact_on_exact_data_and_beats_the_sample():
+    g = synth.rng(5)
+    pa = g.uniform(0, 800, (60, 2))
+    assert np.abs(G.refit_homography(pa, _apply(_H(), pa)) - _H()).max() < 1e-9
+    assert G.refit_homography(pa[:3], pa[:3]) is None
+    pb = _apply(_H(), pa) + g.normal(0, 0.5, (60, 2))
+    H4 = G.homography_from_4(pa[:4], pb[:4])
+    Hr = G.refit_homography(pa, pb)
+    probe = g.uniform(0, 800, (200, 2))
+    e4 = np.abs(_apply(H4, probe) - _apply(_H(), probe)).max()
+    er = np.abs(_apply(Hr, probe) - _apply(_H(), probe)).max()
+    assert er < e4 and er < 0.5
