@@ -368,6 +368,33 @@ xa_status xa_pair_precision(const xa_keypoint* d_kp_a, const xa_keypoint* d_kp_b
                             const int32_t* d_best, const double* H, double th, int32_t* d_out,
                             hipStream_t stream);
 
+/* Accepted matches of a best view pair (d_best = (pair, i, j, count) as written by
+ * xa_match_views / xa_match_pair / xa_match_groups for one group) as points in original
+ * image coordinates, in query order: d_pa [N][2], d_pb [N][2] fp64 (N = n_features, the
+ * capacity), *d_n = how many were written (device).  n_b = views of B in the pair layout
+ * (pair = i * n_b + j).  The same acceptance rule as the pair counts (eqs. (5)-(6) use these
+ * points). */
+xa_status xa_best_pair_points(const xa_keypoint* d_kp_a, const xa_keypoint* d_kp_b, const xa_match* d_matches,
+                              const int32_t* d_count_a, const int32_t* d_count_b, int32_t n_b, int32_t n_features,
+                              int32_t ratio_num, int32_t ratio_den, const int32_t* d_best, double* d_pa, double* d_pb,
+                              int32_t* d_n, hipStream_t stream);
+
+/* Homography RANSAC over n matched points (Sec. III.C; eq. (7) is the inlier share):
+ * d_pa, d_pb [n][2] fp64; d_samples [k][4] int32 match indices (the random draws, made by
+ * the caller); th the inlier distance in pixels.  A sample whose indices leave [0, n) or
+ * some 3 of whose 4 points (in A or in B) span a doubled triangle area below 1 px^2 scores
+ * -1; otherwise H (h33 = 1) solves the 8 x 8 system that maps its 4 points of A onto those
+ * of B (partial pivoting, fp64) and scores the number of matches with |H(p_a) - p_b| <= th
+ * (projective image; w <= 0 counts as an outlier).  Outputs: d_scores [k]; d_best [2] =
+ * (index, score) of the best sample, the lowest index on ties, (-1, -1) if none is valid;
+ * d_H [9] the homography row-major: the least-squares refit (h33 = 1, Hartley-normalised
+ * coordinates) over the best sample's inliers, or the sample's own H when that has no
+ * solution (zeros if there is no valid sample); d_inliers [n] u8 the best sample's inlier
+ * mask (nullable).  No workspace. */
+xa_status xa_ransac_homography(const double* d_pa, const double* d_pb, int32_t n, const int32_t* d_samples, int32_t k,
+                               double th, int32_t* d_scores, int32_t* d_best, double* d_H, uint8_t* d_inliers,
+                               hipStream_t stream);
+
 /* The Lanczos-4 warp of eqs. (3)-(4) as a differentiable map of fp32 crops and of
  * the camera parameters of eq. (2), for photometric refinement of the grid
  * search's (t, phi).  n crops of h x w fp32 values (d_img [n][h][w], row-major,

@@ -115,6 +115,9 @@ _SIGS = {
     "xa_sampling_grid_scaled": (_c.c_int, [_c.c_int32, _c.c_double, _c.c_double, _c.c_void_p, _c.c_int32,
                                            _c.POINTER(_c.c_int32)]),
     "xa_plan_set_interp": (_c.c_int, [_c.c_void_p, _c.c_int32]),
+    "xa_best_pair_points": (_c.c_int, [_c.c_void_p] * 5 + [_c.c_int32] * 4 + [_c.c_void_p] * 5),
+    "xa_ransac_homography": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_int32, _c.c_double,
+                                        _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p]),
     "xa_match_pair_workspace_size": (_c.c_size_t, [_c.c_void_p, _c.c_void_p]),
     "xa_match_pair": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                  _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_int32,
@@ -949,3 +952,69 @@ def refine_tilt(img, target, params, grid, target_mask=None, steps: int = 20, lr
         keep = refined < best
         out = torch.where(keep[:, None], p, best_p)
     return out, best, refined
+
+
+# ---------------------------------------------------------------- precise stage
+
+def ransac_homography(pa, pb, samples, th: float = 3.0):
+    """Homography RANSAC (device tensors pa, pb [n, 2] fp64, samples [k, 4] int32).
+    Returns (scores [k] i32, best [2] i32, H [3, 3] f64, inliers [n] u8), all on the device."""
+    import torch
+    dev = pa.device
+    n, k = int(pa.shape[0]), int(samples.shape[0])
+    scores = torch.empty(max(k, 1), dtype=torch.int32, device=dev)
+    best = torch.empty(2, dtype=torch.int32, device=dev)
+    H = torch.empty(9, dtype=torch.float64, device=dev)
+    inl = torch.empty(max(n, 1), dtype=torch.uint8, device=dev)
+    _check(lib().xa_ransac_homography(_ptr(pa.contiguous()), _ptr(pb.contiguous()), n, _ptr(samples.contiguous()), k,
+                                      th, _ptr(scores), _ptr(best), _ptr(H), _ptr(inl), _stream()))
+    return scores[:k], best, H.view(3, 3), inl[:n]
+
+
+def best_pair_points(kp_a, kp_b, matches, count_a, count_b, best, n_b: int, n_features: int,
+                     ratio_num: int = 4, ratio_den: int = 5):
+    """Accepted matches of the best view pair as original-image points: (pa, pb, n) on the device,
+    pa/pb of capacity n_features."""
+    import torch
+    dev = kp_a.device
+    pa = torch.empty((n_features, 2), dtype=torch.float64, device=dev)
+    pb = torch.empty((n_features, 2), dtype=torch.float64, device=dev)
+    n = torch.empty(1, dtype=torch.int32, device=dev)
+    _check(lib().xa_best_pair_points(_ptr(kp_a), _ptr(kp_b), _ptr(matches), _ptr(count_a), _ptr(count_b), n_b,
+                                     n_features, ratio_num, ratio_den, _ptr(best), _ptr(pa), _ptr(pb), _ptr(n),
+                                     _stream()))
+    return pa, pb, n
+
+
+def draw_samples(n: int, k: int, seed: int = 0) -> np.ndarray:
+    """k RANSAC samples of 4 distinct match indices out of n (host numpy, seeded PCG64)."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    if n < 4:
+        return np.zeros((0, 4), np.int32)
+    return np.stack([g.choice(n, 4, replace=False) for _ in range(k)]).astype(np.int32)
+
+
+def precise_stage(A, B, params_a, params_b, pattern, n_levels: int = 8, n_features: int = 1000,
+                  fast_threshold: int = 20, ransac_k: int = 2000, th: float = 3.0, seed: int = 0,
+                  ratio_num: int = 4, ratio_den: int = 5):
+    """The stage after the search (Sec. III.C), for one pair of views: A and B (device u8
+    images) are re-simulated with Lanczos-4 at the best parameters (xa_affine_params rows),
+    ORB runs on both views and their matches are screened by homography RANSAC; eq. (7)
+    gives the inlier share.  Returns a dict with H (3x3 numpy, A original -> B original),
+    the number of matches, of inliers and their ratio, and the device point/inlier arrays."""
+    import torch
+    pa_plan = plan_image(A.shape[1], A.shape[0], make_params([tuple(params_a)]), n_levels, 1.2, n_features,
+                         fast_threshold)
+    pb_plan = plan_image(B.shape[1], B.shape[0], make_params([tuple(params_b)]), n_levels, 1.2, n_features,
+                         fast_threshold)
+    run = PairRunner(pa_plan, pb_plan, A.device)
+    run.run(A, B, pattern, ratio_num, ratio_den)
+    pa, pb, n_dev = best_pair_points(run.kp_a, run.kp_b, run.matches, run.count_a, run.count_b, run.best, 1,
+                                     n_features, ratio_num, ratio_den)
+    n = int(n_dev.item())
+    samples = torch.from_numpy(draw_samples(n, ransac_k, seed)).to(A.device)
+    scores, best, H, inl = ransac_homography(pa[:n], pb[:n], samples, th)
+    n_in = int(best[1].item())
+    return {"H": H.cpu().numpy(), "matches": n, "inliers": max(n_in, 0),
+            "inlier_ratio": max(n_in, 0) / n if n > 0 else 0.0, "pa": pa[:n], "pb": pb[:n], "inlier_mask": inl,
+            "samples": samples, "scores": scores}
