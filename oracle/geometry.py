@@ -1,4 +1,5 @@
-"""Homography RANSAC over matched points and the inlier ratio of eq. (7).
+"""Homography RANSAC over matched points, the inlier ratio of eq. (7), and the scaling
+coefficient of eq. (1) that picks the base image.
 
 Test infrastructure only (see the package docstring).
 
@@ -135,3 +136,20 @@ def ransac(pa, pb, samples, th: float):
 def inlier_ratio(n_inliers: int, n_points: int) -> float:
     """Eq. (7): In_Num / Pt_Num (as a fraction; 0 for no points)."""
     return n_inliers / n_points if n_points > 0 else 0.0
+
+
+def scaling_coefficient(pa, pb, des):
+    """Eq. (1): f = sum_i (|a_i a_{i+1}| - |b_i b_{i+1}|) (1 - (Des(i) + Des(i+1)) / 1000) over
+    consecutive matches i = 0 .. m-2 (in the order given), |.| the Euclidean segment length in
+    pixels and Des the matches' descriptor distances.  f > 0: the segments are longer in image
+    A, which is then the better base for simulation (Sec. III.A).  The printed summation bound
+    is garbled; every consecutive pair is read as one segment."""
+    pa = np.asarray(pa, np.float64)
+    pb = np.asarray(pb, np.float64)
+    d = np.asarray(des, np.float64)
+    if len(pa) < 2:
+        return 0.0
+    la = np.sqrt(((pa[1:] - pa[:-1]) ** 2).sum(axis=1))
+    lb = np.sqrt(((pb[1:] - pb[:-1]) ** 2).sum(axis=1))
+    w = 1.0 - (d[:-1] + d[1:]) / 1000.0
+    return float(np.sum((la - lb) * w))

@@ -82,3 +82,19 @@ def test_refit_is_exact_on_exact_data_and_beats_the_sample():
     e4 = np.abs(_apply(H4, probe) - _apply(_H(), probe)).max()
     er = np.abs(_apply(Hr, probe) - _apply(_H(), probe)).max()
     assert er < e4 and er < 0.5
+
+
+def test_scaling_coefficient_closed_forms():
+    g = synth.rng(9)
+    pa = g.uniform(0, 500, (50, 2))
+    des = g.integers(0, 100, 50)
+    # image B = image A scaled by 1/2 about the origin: every segment halves
+    pb = pa / 2
+    la = np.sqrt(((pa[1:] - pa[:-1]) ** 2).sum(axis=1))
+    w = 1 - (des[:-1] + des[1:]) / 1000
+    assert abs(G.scaling_coefficient(pa, pb, des) - np.sum(la / 2 * w)) < 1e-9
+    assert G.scaling_coefficient(pa, pb, des) > 0 > G.scaling_coefficient(pb, pa, des)
+    # a rigid motion keeps every length: f = 0
+    R = np.array([[0.6, -0.8], [0.8, 0.6]])
+    assert abs(G.scaling_coefficient(pa, pa @ R.T + 7.0, des)) < 1e-9
+    assert G.scaling_coefficient(pa[:1], pb[:1], des[:1]) == 0.0
