@@ -371,13 +371,21 @@ xa_status xa_pair_precision(const xa_keypoint* d_kp_a, const xa_keypoint* d_kp_b
 /* Accepted matches of a best view pair (d_best = (pair, i, j, count) as written by
  * xa_match_views / xa_match_pair / xa_match_groups for one group) as points in original
  * image coordinates, in query order: d_pa [N][2], d_pb [N][2] fp64 (N = n_features, the
- * capacity), *d_n = how many were written (device).  n_b = views of B in the pair layout
- * (pair = i * n_b + j).  The same acceptance rule as the pair counts (eqs. (5)-(6) use these
- * points). */
+ * capacity), d_dist [N] the matches' Hamming distances (nullable), *d_n = how many were
+ * written (device).  n_b = views of B in the pair layout (pair = i * n_b + j).  The same
+ * acceptance rule as the pair counts (eqs. (5)-(6) use these points). */
 xa_status xa_best_pair_points(const xa_keypoint* d_kp_a, const xa_keypoint* d_kp_b, const xa_match* d_matches,
                               const int32_t* d_count_a, const int32_t* d_count_b, int32_t n_b, int32_t n_features,
                               int32_t ratio_num, int32_t ratio_den, const int32_t* d_best, double* d_pa, double* d_pb,
-                              int32_t* d_n, hipStream_t stream);
+                              int32_t* d_dist, int32_t* d_n, hipStream_t stream);
+
+/* The scaling coefficient of eq. (1) (Sec. III.A, base-image selection) over the first
+ * min(*d_n, cap) matches (d_pa, d_pb [.][2] fp64 points, d_des [.] descriptor distances,
+ * as written by xa_best_pair_points): the sum over consecutive matches of
+ * (|a_i a_{i+1}| - |b_i b_{i+1}|) (1 - (Des(i) + Des(i+1)) / 1000), in a fixed order, into
+ * *d_f (device fp64).  f > 0 means segments are longer in image A. */
+xa_status xa_scaling_coefficient(const double* d_pa, const double* d_pb, const int32_t* d_des, const int32_t* d_n,
+                                 int32_t cap, double* d_f, hipStream_t stream);
 
 /* Homography RANSAC over n matched points (Sec. III.C; eq. (7) is the inlier share):
  * d_pa, d_pb [n][2] fp64; d_samples [k][4] int32 match indices (the random draws, made by

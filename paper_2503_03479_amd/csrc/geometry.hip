@@ -292,7 +292,7 @@ __global__ void __launch_bounds__(1024) k_pair_points(const xa_keypoint* __restr
                                                       const int32_t* __restrict__ count_b, int n_b, int N, int num,
                                                       int den, const int32_t* __restrict__ best,
                                                       double* __restrict__ pa, double* __restrict__ pb,
-                                                      int32_t* __restrict__ n_out) {
+                                                      int32_t* __restrict__ dist, int32_t* __restrict__ n_out) {
     __shared__ int wsum[16];
     __shared__ int base;
     const int pair = best[0], i = best[1], j = best[2];
@@ -322,6 +322,7 @@ __global__ void __launch_bounds__(1024) k_pair_points(const xa_keypoint* __restr
             const xa_keypoint bk = kp_b[size_t(j) * N + m.t];
             pa[2 * o] = a.xs; pa[2 * o + 1] = a.ys;
             pb[2 * o] = bk.xs; pb[2 * o + 1] = bk.ys;
+            if (dist) dist[o] = int32_t(m.d1);
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -334,10 +335,37 @@ __global__ void __launch_bounds__(1024) k_pair_points(const xa_keypoint* __restr
     if (threadIdx.x == 0) *n_out = base;
 }
 
+// Eq. (1) over the first min(*n, cap) matches: sum over consecutive pairs of the difference of
+// segment lengths weighted by 1 - (Des(i) + Des(i + 1)) / 1000, in a fixed summation order.
+__global__ void __launch_bounds__(256) k_scaling(const double* __restrict__ pa, const double* __restrict__ pb,
+                                                 const int32_t* __restrict__ des, const int32_t* __restrict__ n_dev,
+                                                 int cap, double* __restrict__ f) {
+    __shared__ double red[4];
+    const int n = min(max(*n_dev, 0), cap);
+    double acc = 0.0;
+    for (int i = threadIdx.x; i + 1 < n; i += blockDim.x) {
+        const double ax = pa[2 * i + 2] - pa[2 * i], ay = pa[2 * i + 3] - pa[2 * i + 1];
+        const double bx = pb[2 * i + 2] - pb[2 * i], by = pb[2 * i + 3] - pb[2 * i + 1];
+        const double w = 1.0 - double(des[i] + des[i + 1]) / 1000.0;
+        acc += (sqrt(ax * ax + ay * ay) - sqrt(bx * bx + by * by)) * w;
+    }
+    const double t = block_sum(acc, red);
+    if (threadIdx.x == 0) *f = t;
+}
+
 }  // namespace
 }  // namespace xa
 
 using namespace xa;
+
+extern "C" xa_status xa_scaling_coefficient(const double* d_pa, const double* d_pb, const int32_t* d_des,
+                                            const int32_t* d_n, int32_t cap, double* d_f, hipStream_t stream) {
+    if (!d_pa || !d_pb || !d_des || !d_n || !d_f) return fail(XA_EINVAL, "NULL pointer");
+    if (cap < 0) return fail(XA_EINVAL, "negative capacity");
+    hipLaunchKernelGGL(k_scaling, dim3(1), dim3(256), 0, stream, d_pa, d_pb, d_des, d_n, cap, d_f);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? ok() : hip_fail(e, "scaling coefficient launch");
+}
 
 extern "C" xa_status xa_ransac_homography(const double* d_pa, const double* d_pb, int32_t n, const int32_t* d_samples,
                                           int32_t k, double th, int32_t* d_scores, int32_t* d_best, double* d_H,
@@ -363,15 +391,15 @@ extern "C" xa_status xa_ransac_homography(const double* d_pa, const double* d_pb
 extern "C" xa_status xa_best_pair_points(const xa_keypoint* d_kp_a, const xa_keypoint* d_kp_b, const xa_match* d_matches,
                                          const int32_t* d_count_a, const int32_t* d_count_b, int32_t n_b,
                                          int32_t n_features, int32_t ratio_num, int32_t ratio_den,
-                                         const int32_t* d_best, double* d_pa, double* d_pb, int32_t* d_n,
-                                         hipStream_t stream) {
+                                         const int32_t* d_best, double* d_pa, double* d_pb, int32_t* d_dist,
+                                         int32_t* d_n, hipStream_t stream) {
     if (!d_kp_a || !d_kp_b || !d_matches || !d_count_a || !d_count_b || !d_best || !d_pa || !d_pb || !d_n)
         return fail(XA_EINVAL, "NULL pointer");
     if (n_b < 1 || n_features < 1 || n_features > XA_MAX_FEATURES) return fail(XA_EINVAL, "bad sizes");
     if (ratio_num < 0 || ratio_den < 1 || ratio_num > (1 << 20) || ratio_den > (1 << 20))
         return fail(XA_EINVAL, "bad ratio");
     hipLaunchKernelGGL(k_pair_points, dim3(1), dim3(1024), 0, stream, d_kp_a, d_kp_b, d_matches, d_count_a, d_count_b,
-                       n_b, n_features, ratio_num, ratio_den, d_best, d_pa, d_pb, d_n);
+                       n_b, n_features, ratio_num, ratio_den, d_best, d_pa, d_pb, d_dist, d_n);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? ok() : hip_fail(e, "pair points launch");
 }

@@ -115,7 +115,8 @@ _SIGS = {
     "xa_sampling_grid_scaled": (_c.c_int, [_c.c_int32, _c.c_double, _c.c_double, _c.c_void_p, _c.c_int32,
                                            _c.POINTER(_c.c_int32)]),
     "xa_plan_set_interp": (_c.c_int, [_c.c_void_p, _c.c_int32]),
-    "xa_best_pair_points": (_c.c_int, [_c.c_void_p] * 5 + [_c.c_int32] * 4 + [_c.c_void_p] * 5),
+    "xa_best_pair_points": (_c.c_int, [_c.c_void_p] * 5 + [_c.c_int32] * 4 + [_c.c_void_p] * 6),
+    "xa_scaling_coefficient": (_c.c_int, [_c.c_void_p] * 4 + [_c.c_int32, _c.c_void_p, _c.c_void_p]),
     "xa_ransac_homography": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_int32, _c.c_double,
                                         _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p]),
     "xa_match_pair_workspace_size": (_c.c_size_t, [_c.c_void_p, _c.c_void_p]),
@@ -973,17 +974,18 @@ def ransac_homography(pa, pb, samples, th: float = 3.0):
 
 def best_pair_points(kp_a, kp_b, matches, count_a, count_b, best, n_b: int, n_features: int,
                      ratio_num: int = 4, ratio_den: int = 5):
-    """Accepted matches of the best view pair as original-image points: (pa, pb, n) on the device,
-    pa/pb of capacity n_features."""
+    """Accepted matches of the best view pair as original-image points: (pa, pb, dist, n) on the
+    device, pa/pb/dist of capacity n_features (dist = Hamming distances)."""
     import torch
     dev = kp_a.device
     pa = torch.empty((n_features, 2), dtype=torch.float64, device=dev)
     pb = torch.empty((n_features, 2), dtype=torch.float64, device=dev)
+    dist = torch.empty(n_features, dtype=torch.int32, device=dev)
     n = torch.empty(1, dtype=torch.int32, device=dev)
     _check(lib().xa_best_pair_points(_ptr(kp_a), _ptr(kp_b), _ptr(matches), _ptr(count_a), _ptr(count_b), n_b,
-                                     n_features, ratio_num, ratio_den, _ptr(best), _ptr(pa), _ptr(pb), _ptr(n),
-                                     _stream()))
-    return pa, pb, n
+                                     n_features, ratio_num, ratio_den, _ptr(best), _ptr(pa), _ptr(pb), _ptr(dist),
+                                     _ptr(n), _stream()))
+    return pa, pb, dist, n
 
 
 def draw_samples(n: int, k: int, seed: int = 0) -> np.ndarray:
@@ -1009,8 +1011,8 @@ def precise_stage(A, B, params_a, params_b, pattern, n_levels: int = 8, n_featur
                          fast_threshold)
     run = PairRunner(pa_plan, pb_plan, A.device)
     run.run(A, B, pattern, ratio_num, ratio_den)
-    pa, pb, n_dev = best_pair_points(run.kp_a, run.kp_b, run.matches, run.count_a, run.count_b, run.best, 1,
-                                     n_features, ratio_num, ratio_den)
+    pa, pb, _, n_dev = best_pair_points(run.kp_a, run.kp_b, run.matches, run.count_a, run.count_b, run.best, 1,
+                                        n_features, ratio_num, ratio_den)
     n = int(n_dev.item())
     samples = torch.from_numpy(draw_samples(n, ransac_k, seed)).to(A.device)
     scores, best, H, inl = ransac_homography(pa[:n], pb[:n], samples, th)
@@ -1018,3 +1020,30 @@ def precise_stage(A, B, params_a, params_b, pattern, n_levels: int = 8, n_featur
     return {"H": H.cpu().numpy(), "matches": n, "inliers": max(n_in, 0),
             "inlier_ratio": max(n_in, 0) / n if n > 0 else 0.0, "pa": pa[:n], "pb": pb[:n], "inlier_mask": inl,
             "samples": samples, "scores": scores}
+
+
+def scaling_coefficient(pa, pb, dist, n):
+    """Eq. (1) on device points/distances (as from best_pair_points); returns a device fp64 [1]."""
+    import torch
+    f = torch.empty(1, dtype=torch.float64, device=pa.device)
+    _check(lib().xa_scaling_coefficient(_ptr(pa), _ptr(pb), _ptr(dist), _ptr(n), int(pa.shape[0]), _ptr(f),
+                                        _stream()))
+    return f
+
+
+def select_base_image(A, B, pattern, n_levels: int = 8, n_features: int = 1000, fast_threshold: int = 20,
+                      ratio_num: int = 4, ratio_den: int = 5):
+    """Base-image selection of Sec. III.A on the unsimulated images: ORB on A and B, matching
+    A -> B gives f1 and B -> A gives f2 by eq. (1) (the matches' Hamming distances stand in for
+    the SIFT distances); A is the base when f1 > f2.  Returns ("A" | "B", f1, f2)."""
+    ident = make_params([(1.0, 0.0)])
+    pa_plan = plan_image(A.shape[1], A.shape[0], ident, n_levels, 1.2, n_features, fast_threshold)
+    pb_plan = plan_image(B.shape[1], B.shape[0], ident, n_levels, 1.2, n_features, fast_threshold)
+    f = []
+    for q_plan, t_plan, Q, T in ((pa_plan, pb_plan, A, B), (pb_plan, pa_plan, B, A)):
+        run = PairRunner(q_plan, t_plan, Q.device)
+        run.run(Q, T, pattern, ratio_num, ratio_den)
+        p1, p2, dist, n = best_pair_points(run.kp_a, run.kp_b, run.matches, run.count_a, run.count_b, run.best, 1,
+                                           n_features, ratio_num, ratio_den)
+        f.append(float(scaling_coefficient(p1, p2, dist, n).item()))
+    return ("A" if f[0] > f[1] else "B"), f[0], f[1]

@@ -108,14 +108,21 @@ def test_best_pair_points_equal_the_oracle(dev):
                                    torch.from_numpy(pat).to(dev)))
     (kpa, da, ca), (kpb, db, cb) = feats
     m, pc, best = X.match_views(da, ca, db, cb)
-    pa, pb, n = X.best_pair_points(kpa, kpb, m, ca, cb, best, len(grid), 300)
+    pa, pb, dist, n = X.best_pair_points(kpa, kpb, m, ca, cb, best, len(grid), 300)
     torch.cuda.synchronize()
     n = int(n.item())
     assert tuple(best.cpu().tolist()) == tuple(ref["best"])
     assert n == len(ref["pa"]) == int(ref["best"][3])
     assert np.allclose(pa[:n].cpu().numpy(), ref["pa"], atol=1e-9, rtol=0)
     assert np.allclose(pb[:n].cpu().numpy(), ref["pb"], atol=1e-9, rtol=0)
-    say(f"[pair points] {n} accepted matches equal the oracle's")
+    k, i, j, c = ref["best"]
+    idx, d1, d2, acc = ref["results"][k]
+    assert np.array_equal(dist[:n].cpu().numpy(), d1[acc])
+    # eq. (1) on these matches equals the oracle's
+    f = float(X.scaling_coefficient(pa, pb, dist, torch.tensor([n], dtype=torch.int32, device=dev)).item())
+    rf = OG.scaling_coefficient(ref["pa"], ref["pb"], d1[acc])
+    assert abs(f - rf) <= 1e-9 * max(1.0, abs(rf))
+    say(f"[pair points] {n} accepted matches equal the oracle's; eq. (1) f = {f:.4f}")
 
 
 def test_precise_stage_recovers_the_ground_truth(dev):
@@ -139,3 +146,17 @@ def test_precise_stage_recovers_the_ground_truth(dev):
     rs, rb, rH, rinl = OG.ransac(pa, pb, out["samples"].cpu().numpy(), 3.0)
     assert rs[rb] == out["inliers"]
     assert np.abs(out["H"] - rH).max() <= 1e-7 * np.abs(rH).max()
+
+
+def test_base_image_selection_prefers_the_closer_view(dev):
+    """Eq. (1) both ways on a pair where B is A's scene seen from twice the distance (every
+    length halves): A is the base (f1 > 0 > f2)."""
+    say("case: base-image selection (eq. (1)) on a pair with a 2x scale change")
+    sc = synth.make_scene(512, 512, 160, 120, 77)
+    A = synth.render(sc, np.eye(2), np.zeros(2), 512, 512, noise_seed=1)
+    B = synth.render(sc, 0.5 * np.eye(2), np.zeros(2), 256, 256, noise_seed=2)
+    pat = torch.from_numpy(synth.brief_pattern()).to(dev)
+    base, f1, f2 = X.select_base_image(torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev), pat, n_levels=8,
+                                       n_features=500)
+    say(f"[base image] {base}: f1 = {f1:.1f}, f2 = {f2:.1f}")
+    assert base == "A" and f1 > 0 > f2
