@@ -9,7 +9,7 @@
 //
 // Coordinates are fp64; weights and sums fp32; per-pixel parameter gradients fp64.
 // Kernel weights use sin(pi (i - f)) = -(-1)^i sin(pi f) and the angle-difference
-// formula for sin(pi (i - f) / 4), so each axis needs sincospi of f and of f / 4 only;
+// formula for sin(pi (i - f) / 4), so each axis needs the sine and cosine of pi f and pi f / 4 only;
 // within 0.05 of a zero of the argument the weight and its derivative switch to the
 // Taylor series of sinc(x) sinc(x / 4), where the closed forms cancel.
 #include <hip/hip_runtime.h>
@@ -22,7 +22,8 @@
 namespace xa {
 namespace {
 
-constexpr int kDwTX = 64, kDwTY = 4;   // 256 threads, one view pixel each
+constexpr int kDwTX = 16, kDwTY = 16;  // 256 threads, one view pixel each
+constexpr int kDwLds = 8192;           // floats of source footprint a tile stages (forward) or accumulates (adjoint)
 
 struct CropMap {
     double m[4];      // L^-1, row-major
@@ -77,9 +78,10 @@ constexpr float kPi = 3.14159265358979323846f;
 // Weights w_i = L(i - f) and (if D) dw_i/dp = -L'(i - f) for i = -3..4; returns the sums.
 template <bool D>
 __device__ inline void axis_weights(float f, float* w, float* dw, float* sw, float* sdw) {
-    float s1, c1, s4, c4;
-    sincospif(f, &s1, &c1);
-    sincospif(0.25f * f, &s4, &c4);
+    // hardware sine / cosine take revolutions: sin(pi f) = sin(2 pi (f / 2)); absolute error ~1e-6,
+    // and the closed forms below are only used at least 0.05 away from a zero of the argument
+    const float s1 = __builtin_amdgcn_sinf(0.5f * f), c1 = __builtin_amdgcn_cosf(0.5f * f);
+    const float s4 = __builtin_amdgcn_sinf(0.125f * f), c4 = __builtin_amdgcn_cosf(0.125f * f);
     // sin(pi i / 4), cos(pi i / 4) for i = -3..4
     constexpr float kH = 0.70710678118654752f;
     const float si[8] = {-kH, -1.0f, -kH, 0.0f, kH, 1.0f, kH, 0.0f};
@@ -136,15 +138,66 @@ __global__ void __launch_bounds__(256) k_dw_fill(float* __restrict__ p, size_t n
         p[i] = 0.0f;
 }
 
+// Source box of a 16 x 16 tile: the bounding box of its pixel centres mapped through the
+// crop map, grown by the 8-tap window and clamped to the crop.  Every tap of a valid pixel of
+// the tile, once clamped to the crop, lies in it.
+struct Box {
+    int x0, x1, y0, y1;
+};
+__device__ Box tile_box(const CropMap& C, int tx0, int ty0, int w, int h) {
+    double pxl = 1e300, pxh = -1e300, pyl = 1e300, pyh = -1e300;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const Sample S = sample_point(C, tx0 + ((c & 1) ? kDwTX - 1 : 0), ty0 + ((c & 2) ? kDwTY - 1 : 0), w, h);
+        pxl = fmin(pxl, S.px); pxh = fmax(pxh, S.px);
+        pyl = fmin(pyl, S.py); pyh = fmax(pyh, S.py);
+    }
+    Box b;
+    b.x0 = max(int(fmax(floor(pxl - 1e-6), -1e9)) - 3, 0);
+    b.x1 = min(int(fmin(floor(pxh + 1e-6), 1e9)) + 4, w - 1);
+    b.y0 = max(int(fmax(floor(pyl - 1e-6), -1e9)) - 3, 0);
+    b.y1 = min(int(fmin(floor(pyh + 1e-6), 1e9)) + 4, h - 1);
+    return b;
+}
+
+// One 16 x 16 tile per block; its source box is staged in LDS when it fits (taps then read
+// from LDS), else taps are read from global memory.
 __global__ void __launch_bounds__(256) k_dw_fwd(const float* __restrict__ img, const xa_affine_params* __restrict__ params,
                                                 int w, int h, int tiles_x, int tiles, float* __restrict__ out,
                                                 uint8_t* __restrict__ mask) {
     __shared__ CropMap sC;
-    const int crop = blockIdx.x / tiles, tile = blockIdx.x - crop * tiles;
+    __shared__ float tile[kDwLds];
+    const int crop = blockIdx.x / tiles, tl = blockIdx.x - crop * tiles;
     if (threadIdx.x == 0) crop_map(params[crop], false, &sC, w, h);
     __syncthreads();
-    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
-    const int x = tx * kDwTX + int(threadIdx.x % kDwTX), y = ty * kDwTY + int(threadIdx.x / kDwTX);
+    const int tyi = tl / tiles_x, txi = tl - tyi * tiles_x;
+    const int tx0 = txi * kDwTX, ty0 = tyi * kDwTY;
+    const Box bx = tile_box(sC, tx0, ty0, w, h);
+    const int bw = bx.x1 - bx.x0 + 1, bh = bx.y1 - bx.y0 + 1;
+    const int ls = bw | 1;
+    const bool use_lds = bw > 0 && bh > 0 && ls * bh <= kDwLds;
+    const float* base = img + size_t(crop) * h * w;
+    if (use_lds) {
+        // element e = r * bw + c, each thread stepping by 256 = q * bw + rem (no division per element)
+        const int n = bw * bh, q = 256 / bw, rem = 256 - q * bw;
+        int e = threadIdx.x, r = e / bw, c = e - r * bw;
+        const float* g = base + size_t(bx.y0 + r) * w + bx.x0 + c;
+        int lo = r * ls + c;
+        while (e < n) {
+            tile[lo] = *g;
+            e += 256;
+            c += rem;
+            g += size_t(q) * w + rem;
+            lo += q * ls + rem;
+            if (c >= bw) {
+                c -= bw;
+                g += w - bw;
+                lo += ls - bw;
+            }
+        }
+    }
+    __syncthreads();
+    const int x = tx0 + int(threadIdx.x % kDwTX), y = ty0 + int(threadIdx.x / kDwTX);
     if (x >= w || y >= h) return;
     const size_t o = (size_t(crop) * h + y) * w + x;
     const Sample S = sample_point(sC, x, y, w, h);
@@ -155,18 +208,31 @@ __global__ void __launch_bounds__(256) k_dw_fwd(const float* __restrict__ img, c
         float wx[8], wy[8], sx, sy;
         axis_weights<false>(float(S.px - fx0), wx, nullptr, &sx, nullptr);
         axis_weights<false>(float(S.py - fy0), wy, nullptr, &sy, nullptr);
-        int cols[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) cols[i] = min(max(ix - 3 + i, 0), w - 1);
-        const float* base = img + size_t(crop) * h * w;
         float acc = 0.0f;
+        if (use_lds) {
+            int cols[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const float* row = base + size_t(min(max(iy - 3 + j, 0), h - 1)) * w;
-            float r = 0.0f;
+            for (int i = 0; i < 8; ++i) cols[i] = min(max(ix - 3 + i, bx.x0), bx.x1) - bx.x0;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) r = fmaf(wx[i], row[cols[i]], r);
-            acc = fmaf(wy[j], r, acc);
+            for (int j = 0; j < 8; ++j) {
+                const float* row = tile + (min(max(iy - 3 + j, bx.y0), bx.y1) - bx.y0) * ls;
+                float r = 0.0f;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) r = fmaf(wx[i], row[cols[i]], r);
+                acc = fmaf(wy[j], r, acc);
+            }
+        } else {
+            int cols[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) cols[i] = min(max(ix - 3 + i, 0), w - 1);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const float* row = base + size_t(min(max(iy - 3 + j, 0), h - 1)) * w;
+                float r = 0.0f;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) r = fmaf(wx[i], row[cols[i]], r);
+                acc = fmaf(wy[j], r, acc);
+            }
         }
         v = acc / (sx * sy);
     }
@@ -174,6 +240,10 @@ __global__ void __launch_bounds__(256) k_dw_fwd(const float* __restrict__ img, c
     if (mask) mask[o] = S.valid ? 1 : 0;
 }
 
+// Adjoint, one 16 x 16 tile per block.  The image gradient is accumulated in LDS over the
+// tile's source box with LDS atomics when the box fits, then added to the crop's gradient with
+// one global atomic per box pixel (a global atomic per tap otherwise); the parameter gradient
+// is summed per block in a fixed order.
 template <bool GIMG, bool GPAR>
 __global__ void __launch_bounds__(256) k_dw_bwd(const float* __restrict__ img, const float* __restrict__ gout,
                                                 const xa_affine_params* __restrict__ params, int w, int h,
@@ -181,15 +251,24 @@ __global__ void __launch_bounds__(256) k_dw_bwd(const float* __restrict__ img, c
                                                 double* __restrict__ partial) {
     __shared__ CropMap sC;
     __shared__ double sRed[4][6];
-    const int crop = blockIdx.x / tiles, tile = blockIdx.x - crop * tiles;
+    __shared__ float accum[GIMG ? kDwLds : 1];
+    const int crop = blockIdx.x / tiles, tl = blockIdx.x - crop * tiles;
     if (threadIdx.x == 0) crop_map(params[crop], GPAR, &sC, w, h);
     __syncthreads();
-    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
-    const int x = tx * kDwTX + int(threadIdx.x % kDwTX), y = ty * kDwTY + int(threadIdx.x / kDwTX);
+    const int tyi = tl / tiles_x, txi = tl - tyi * tiles_x;
+    const int tx0 = txi * kDwTX, ty0 = tyi * kDwTY;
+    const Box bx = tile_box(sC, tx0, ty0, w, h);
+    const int bw = bx.x1 - bx.x0 + 1, bh = bx.y1 - bx.y0 + 1;
+    const bool use_acc = GIMG && bw > 0 && bh > 0 && bw * bh <= kDwLds;
+    if (use_acc)
+        for (int e = threadIdx.x; e < bw * bh; e += 256) accum[e] = 0.0f;
+    __syncthreads();
+    const size_t cbase = size_t(crop) * h * w;
+    const int x = tx0 + int(threadIdx.x % kDwTX), y = ty0 + int(threadIdx.x / kDwTX);
     double gp[6] = {0, 0, 0, 0, 0, 0};
     if (x < w && y < h) {
         const Sample S = sample_point(sC, x, y, w, h);
-        const float g = gout[(size_t(crop) * h + y) * w + x];
+        const float g = gout[cbase + size_t(y) * w + x];
         if (S.valid && g != 0.0f) {
             const double fx0 = floor(S.px), fy0 = floor(S.py);
             const int ix = int(fx0), iy = int(fy0);
@@ -200,18 +279,17 @@ __global__ void __launch_bounds__(256) k_dw_bwd(const float* __restrict__ img, c
             int cols[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) cols[i] = min(max(ix - 3 + i, 0), w - 1);
-            const size_t cbase = size_t(crop) * h * w;
             float v = 0.0f, vx = 0.0f, vy = 0.0f;
             const float gn = g * inv;
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-                const size_t roff = cbase + size_t(min(max(iy - 3 + j, 0), h - 1)) * w;
+                const int row = min(max(iy - 3 + j, 0), h - 1);
                 if (GPAR) {
-                    const float* row = img + roff;
+                    const float* rp = img + cbase + size_t(row) * w;
                     float r = 0.0f, rd = 0.0f;
 #pragma unroll
                     for (int i = 0; i < 8; ++i) {
-                        const float a = row[cols[i]];
+                        const float a = rp[cols[i]];
                         r = fmaf(wx[i], a, r);
                         rd = fmaf(dwx[i], a, rd);
                     }
@@ -221,8 +299,14 @@ __global__ void __launch_bounds__(256) k_dw_bwd(const float* __restrict__ img, c
                 }
                 if (GIMG) {
                     const float gj = gn * wy[j];
+                    if (use_acc) {
+                        float* ar = accum + (row - bx.y0) * bw - bx.x0;
 #pragma unroll
-                    for (int i = 0; i < 8; ++i) unsafeAtomicAdd(gimg + roff + cols[i], gj * wx[i]);
+                        for (int i = 0; i < 8; ++i) atomicAdd(ar + cols[i], gj * wx[i]);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) unsafeAtomicAdd(gimg + cbase + size_t(row) * w + cols[i], gj * wx[i]);
+                    }
                 }
             }
             if (GPAR) {
@@ -239,6 +323,24 @@ __global__ void __launch_bounds__(256) k_dw_bwd(const float* __restrict__ img, c
                 // d(q - c - T)/dtx = (-1, 0), d/dty = (0, -1)
                 gp[4] = -gd * (dVx * sC.m[0] + dVy * sC.m[2]);
                 gp[5] = -gd * (dVx * sC.m[1] + dVy * sC.m[3]);
+            }
+        }
+    }
+    if (GIMG && use_acc) {
+        __syncthreads();
+        // one global atomic per box pixel that received a contribution
+        const int n = bw * bh, q = 256 / bw, rem = 256 - q * bw;
+        int e = threadIdx.x, r = e / bw, c = e - r * bw;
+        float* gptr = gimg + cbase + size_t(bx.y0 + r) * w + bx.x0 + c;
+        while (e < n) {
+            const float a = accum[e];
+            if (a != 0.0f) unsafeAtomicAdd(gptr, a);
+            e += 256;
+            c += rem;
+            gptr += size_t(q) * w + rem;
+            if (c >= bw) {
+                c -= bw;
+                gptr += w - bw;
             }
         }
     }
