@@ -14,7 +14,7 @@ namespace xa {
 constexpr int kWarpThreads = 256;           // warp: 256 threads per output tile
 constexpr int kWarpRows = 2;                // view pixels per warp thread (tiles hold kWarpRows * 256 pixels)
 constexpr int kWarpLds = 8192;              // floats of source footprint a warp tile can stage in LDS
-constexpr int kPyrTX = 256, kPyrTY = 4;     // pyramid down-sampling (4 output pixels per thread)
+constexpr int kPyrTX = 256, kPyrTY = 16;    // pyramid down-sampling (4 x 4 output pixels per thread)
 constexpr int kFastTX = 64, kFastTY = 32;   // FAST / NMS / smoothing / Harris tiles (256 threads, 8 rows each)
 constexpr int kBlurTX = 64, kBlurTY = 16;   // directional blur over the source (4 rows per thread)
 constexpr int kBlurStride = 128;            // LDS row stride (floats) of a major-x blur tile

@@ -69,12 +69,13 @@ __device__ __forceinline__ int resample_index(int d, int n_dst, int n_src) {
 }
 
 constexpr int kPyrLW = 640;        // LDS row stride of the staged source rows (bytes)
-constexpr int kPyrLH = 16;         // staged source rows
+constexpr int kPyrLH = 24;         // staged source rows (16 output rows span at most 15 * 1.25 + 2)
 
 // Level l of every view from level l-1: (sum_{2x2} wy wx pix + 2^21) >> 22; the content
-// mask of a level pixel is the AND over its 2x2 footprint.  One block per 256 x 4 output
-// tile, four output pixels (one 32-bit store) per thread; the source rows the tile reads
-// are staged in LDS in 16-byte chunks.
+// mask of a level pixel is the AND over its 2x2 footprint.  One block per 256 x 16 output
+// tile, so that its set-up (prefix search, resampling positions, staging) serves 4096 pixels;
+// each thread writes four 32-bit words (4 pixels each) on rows ty, ty + 4, ty + 8, ty + 12;
+// the source rows the tile reads are staged in LDS in 16-byte chunks.
 __global__ void __launch_bounds__(256) k_pyr(const xa_level_desc* __restrict__ levels, int n_levels, int l,
                                              const int32_t* __restrict__ prefix, int n_views,
                                              uint8_t* __restrict__ arena, uint8_t* __restrict__ mask) {
@@ -109,44 +110,47 @@ __global__ void __launch_bounds__(256) k_pyr(const xa_level_desc* __restrict__ l
     }
     __syncthreads();
     const int tx = t & 63, ty = t >> 6;
-    const int y = Y0 + ty;
-    if (y >= d.height) return;
     const int xb = X0 + 4 * tx;
     if (xb >= d.width) return;
-    const int rv = srow[ty];
-    const int y0 = rv >> 11, wy1 = rv & 2047, wy0 = 2048 - wy1, y1 = min(y0 + 1, p.height - 1);
-    uint32_t pix = 0, msk = 0;
+    for (int rr = 0; rr < kPyrTY / 4; ++rr) {
+        const int yr = ty + 4 * rr;
+        const int y = Y0 + yr;
+        if (y >= d.height) break;
+        const int rv = srow[yr];
+        const int y0 = rv >> 11, wy1 = rv & 2047, wy0 = 2048 - wy1, y1 = min(y0 + 1, p.height - 1);
+        uint32_t pix = 0, msk = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        if (xb + k >= d.width) break;
-        const int cv = scol[4 * tx + k];
-        const int x0 = cv >> 11, wx1 = cv & 2047, wx0 = 2048 - wx1, x1 = min(x0 + 1, p.width - 1);
-        int p00, p01, p10, p11, m;
-        if (staged) {
-            const uint8_t* r0 = simg + (y0 - r_lo) * kPyrLW - cb;
-            const uint8_t* r1 = simg + (y1 - r_lo) * kPyrLW - cb;
-            const uint8_t* q0 = smsk + (y0 - r_lo) * kPyrLW - cb;
-            const uint8_t* q1 = smsk + (y1 - r_lo) * kPyrLW - cb;
-            p00 = r0[x0]; p01 = r0[x1]; p10 = r1[x0]; p11 = r1[x1];
-            m = q0[x0] & q0[x1] & q1[x0] & q1[x1];
-        } else {
-            const uint8_t* r0 = P + size_t(y0) * p.pitch;
-            const uint8_t* r1 = P + size_t(y1) * p.pitch;
-            const uint8_t* q0 = M + size_t(y0) * p.pitch;
-            const uint8_t* q1 = M + size_t(y1) * p.pitch;
-            p00 = r0[x0]; p01 = r0[x1]; p10 = r1[x0]; p11 = r1[x1];
-            m = q0[x0] & q0[x1] & q1[x0] & q1[x1];
+        for (int k = 0; k < 4; ++k) {
+            if (xb + k >= d.width) break;
+            const int cv = scol[4 * tx + k];
+            const int x0 = cv >> 11, wx1 = cv & 2047, wx0 = 2048 - wx1, x1 = min(x0 + 1, p.width - 1);
+            int p00, p01, p10, p11, m;
+            if (staged) {
+                const uint8_t* r0 = simg + (y0 - r_lo) * kPyrLW - cb;
+                const uint8_t* r1 = simg + (y1 - r_lo) * kPyrLW - cb;
+                const uint8_t* q0 = smsk + (y0 - r_lo) * kPyrLW - cb;
+                const uint8_t* q1 = smsk + (y1 - r_lo) * kPyrLW - cb;
+                p00 = r0[x0]; p01 = r0[x1]; p10 = r1[x0]; p11 = r1[x1];
+                m = q0[x0] & q0[x1] & q1[x0] & q1[x1];
+            } else {
+                const uint8_t* r0 = P + size_t(y0) * p.pitch;
+                const uint8_t* r1 = P + size_t(y1) * p.pitch;
+                const uint8_t* q0 = M + size_t(y0) * p.pitch;
+                const uint8_t* q1 = M + size_t(y1) * p.pitch;
+                p00 = r0[x0]; p01 = r0[x1]; p10 = r1[x0]; p11 = r1[x1];
+                m = q0[x0] & q0[x1] & q1[x0] & q1[x1];
+            }
+            const int top = wx0 * p00 + wx1 * p01;
+            const int bot = wx0 * p10 + wx1 * p11;
+            const int out = (wy0 * top + wy1 * bot + (1 << 21)) >> 22;
+            pix |= uint32_t(out) << (8 * k);
+            msk |= uint32_t(m & 1) << (8 * k);
         }
-        const int top = wx0 * p00 + wx1 * p01;
-        const int bot = wx0 * p10 + wx1 * p11;
-        const int out = (wy0 * top + wy1 * bot + (1 << 21)) >> 22;
-        pix |= uint32_t(out) << (8 * k);
-        msk |= uint32_t(m & 1) << (8 * k);
+        // xb is a multiple of 4 below the width, so the word lies inside the 16-byte padded row
+        const size_t o = size_t(d.offset) + size_t(y) * d.pitch + xb;
+        *reinterpret_cast<uint32_t*>(arena + o) = pix;
+        *reinterpret_cast<uint32_t*>(mask + o) = msk;
     }
-    // xb is a multiple of 4 below the width, so the word lies inside the 16-byte padded row
-    const size_t o = size_t(d.offset) + size_t(y) * d.pitch + xb;
-    *reinterpret_cast<uint32_t*>(arena + o) = pix;
-    *reinterpret_cast<uint32_t*>(mask + o) = msk;
 }
 
 // ------------------------------------------------------------------ FAST-9 + NMS + Harris + smoothing
