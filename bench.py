@@ -31,25 +31,28 @@ HBM_PEAK_BPS = 8.0e12
 HAMMING_OPS_PER_CMP = 16          # 8 x v_xor_b32 + 8 x v_bcnt_u32_b32 per 256-bit comparison
 
 # HBM traffic of k_match on the full-size pair, from two rocprofv3 --pmc passes (FETCH_SIZE, then
-# WRITE_SIZE; KiB per dispatch), scaled by what the same counters read for a plain 1 GiB
-# device-to-device copy (FETCH_SIZE reads 0.5 GiB there, WRITE_SIZE 1 GiB).  Valid only for the
-# matcher source it was measured on: any change to that file reports null.
+# WRITE_SIZE; KiB per dispatch) per matcher variant (queries per lane), scaled by what the same
+# counters read for a plain 1 GiB device-to-device copy (FETCH_SIZE reads 0.5 GiB there,
+# WRITE_SIZE 1 GiB).  Valid only for the matcher source it was measured on: any change to that
+# file reports null.
 K_MATCH_TRAFFIC = {
     "source": "paper_2503_03479_amd/csrc/match.hip",
     "sha256": "51c06c6e1ec8b0637e1c13e74da0b668b5f0b19e2c0122ae815110de1a15370b",
-    "queries_per_lane": 4, "fetch_kib": 10801.8, "write_kib": 15555.9, "fetch_scale": 2.0, "write_scale": 1.0,
+    "fetch_scale": 2.0, "write_scale": 1.0,
+    "kib": {1: (6660.6, 15745.8), 2: (8032.8, 15619.2), 4: (10801.8, 15555.9)},   # (fetch, write) per variant
 }
 
 
 def k_match_traffic(queries_per_lane: int):
     import hashlib
-    if queries_per_lane != K_MATCH_TRAFFIC["queries_per_lane"]:
-        return None
-    with open(os.path.join(ROOT, K_MATCH_TRAFFIC["source"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != K_MATCH_TRAFFIC["sha256"]:
-            return None
     t = K_MATCH_TRAFFIC
-    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
+    if queries_per_lane not in t["kib"]:
+        return None
+    with open(os.path.join(ROOT, t["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
+            return None
+    fetch, write = t["kib"][queries_per_lane]
+    return (fetch * t["fetch_scale"] + write * t["write_scale"]) * 1024.0
 
 
 def parse():
@@ -64,6 +67,8 @@ def parse():
     ap.add_argument("--batch-pairs", type=int, default=64, help="image pairs in the batched leg (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--crops", type=int, default=256, help="crops in the differentiable-warp leg (0 = skip)")
+    ap.add_argument("--matcher-q", type=int, default=0, choices=[0, 1, 2, 4],
+                    help="matcher queries per lane for the full-pair leg (0 = autotune)")
     ap.add_argument("--only", choices=["batched", "diffwarp", "copy", "sweep"], default=None,
                     help="run one leg alone and print its JSON (for profiler runs); 'copy' is a plain 1 GiB "
                          "device-to-device copy whose counter readings calibrate the HBM traffic counters")
@@ -368,7 +373,8 @@ def main():
     B = torch.from_numpy(np.ascontiguousarray(case.B)).to(dev)
     pattern = torch.from_numpy(synth.brief_pattern()).to(dev)
     run = X.BatchRunner([(case.A, np.ascontiguousarray(case.B))], grid, (1.0,), n_levels=wl["n_levels"],
-                        n_features=wl["n_features"], fast_threshold=wl["fast"], device=dev, queries_per_lane="auto")
+                        n_features=wl["n_features"], fast_threshold=wl["fast"], device=dev,
+                        queries_per_lane=args.matcher_q or "auto")
     stream = torch.cuda.current_stream()
 
     for _ in range(args.warmup):
