@@ -46,7 +46,7 @@ __host__ __device__ inline BlurRegion blur_region(const xa_view_desc& v, const B
     } else {
         r.rx0 = x0 + dlo; r.rw = kBlurTX + dhi - dlo;
         r.ry0 = y0 - K; r.rh = kBlurTY + 2 * K;
-        r.stride = r.rw;                  // the partner is the next column
+        r.stride = r.rw | 1;              // the partner is the next column; odd stride spreads rows over banks
     }
     r.floats = (v.blur_major == 0 && r.rw > kBlurStride) ? (1 << 30) : r.stride * r.rh;
     return r;
@@ -97,33 +97,63 @@ __global__ void __launch_bounds__(256) k_blur(const uint8_t* __restrict__ source
             }
         }
         __syncthreads();
-        for (int j = 0; j < kBlurTY / 4; ++j) {
-            const int x = x0 + tx, y = y0 + ty0 + 4 * j;
-            if (x >= W || y >= H) continue;
-            const float* base = btile + (y - g.ry0) * g.stride + (x - g.rx0);
-            float acc = 0.0f;
-            // the tap table is padded with zero taps to a multiple of 4, so taps load 4 at a time
-            const int n4 = (n + 3) & ~3;
-            if (v.blur_major == 0) {
+        // each thread makes 4 outputs adjacent across the minor axis (rows for major x, columns
+        // for major y): tap k of the 4 reads 5 consecutive minor samples instead of 8, and each
+        // output keeps the same sum order as a one-output evaluation
+        const int n4 = (n + 3) & ~3;           // the tap table is padded with zero taps to a multiple of 4
+        const int bp = blur_pitch(W);
+        if (v.blur_major == 0) {
+            const int c = threadIdx.x & 63, gq = threadIdx.x >> 6;        // column, group of 4 rows
+            const int x = x0 + c, y = y0 + 4 * gq;
+            if (x < W && y < H) {
+                const int S = kBlurStride;
+                const float* base = btile + (y - g.ry0) * S + (x - g.rx0);
+                float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
                 for (int k = 0; k < n4; k += 4) {
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         const BlurTap t = tp[k + u];
-                        const float* q = base + t.dmin * kBlurStride + t.dmaj;
-                        acc = fmaf(t.wb, q[kBlurStride], fmaf(t.wa, q[0], acc));
+                        const float* q = base + t.dmin * S + t.dmaj;
+                        const float r0 = q[0], r1 = q[S], r2 = q[2 * S], r3 = q[3 * S], r4 = q[4 * S];
+                        a0 = fmaf(t.wb, r1, fmaf(t.wa, r0, a0));
+                        a1 = fmaf(t.wb, r2, fmaf(t.wa, r1, a1));
+                        a2 = fmaf(t.wb, r3, fmaf(t.wa, r2, a2));
+                        a3 = fmaf(t.wb, r4, fmaf(t.wa, r3, a3));
                     }
                 }
-            } else {
+                float* op = o + size_t(y) * bp + x;
+                op[0] = a0;
+                if (y + 1 < H) op[bp] = a1;
+                if (y + 2 < H) op[2 * bp] = a2;
+                if (y + 3 < H) op[3 * bp] = a3;
+            }
+        } else {
+            const int r = threadIdx.x & 15, cg = threadIdx.x >> 4;         // row, group of 4 columns
+            const int x = x0 + 4 * cg, y = y0 + r;
+            if (x < W && y < H) {
+                const float* base = btile + (y - g.ry0) * g.stride + (x - g.rx0);
+                float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
                 for (int k = 0; k < n4; k += 4) {
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         const BlurTap t = tp[k + u];
                         const float* q = base + t.dmaj * g.stride + t.dmin;
-                        acc = fmaf(t.wb, q[1], fmaf(t.wa, q[0], acc));
+                        const float r0 = q[0], r1 = q[1], r2 = q[2], r3 = q[3], r4 = q[4];
+                        a0 = fmaf(t.wb, r1, fmaf(t.wa, r0, a0));
+                        a1 = fmaf(t.wb, r2, fmaf(t.wa, r1, a1));
+                        a2 = fmaf(t.wb, r3, fmaf(t.wa, r2, a2));
+                        a3 = fmaf(t.wb, r4, fmaf(t.wa, r3, a3));
                     }
                 }
+                float* op = o + size_t(y) * bp + x;
+                if (x + 3 < W) {
+                    *reinterpret_cast<float4*>(op) = make_float4(a0, a1, a2, a3);   // x and bp are multiples of 4
+                } else {
+                    op[0] = a0;
+                    if (x + 1 < W) op[1] = a1;
+                    if (x + 2 < W) op[2] = a2;
+                }
             }
-            o[size_t(y) * blur_pitch(W) + x] = acc;
         }
         return;
     }
