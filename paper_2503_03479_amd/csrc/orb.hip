@@ -553,12 +553,20 @@ __global__ void __launch_bounds__(256) k_orient_brief(const xa_view_desc* __rest
     const int v = blockIdx.y;
     const int lane = threadIdx.x & 63;
     const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
-    int pre = 0, lev = -1, rank = 0;
-    for (int l = 0; l < n_levels; ++l) {
-        const int c = stage_count[v * n_levels + l];
-        if (lev < 0 && k < pre + c) { lev = l; rank = k - pre; }
-        pre += c;
+    // the level of keypoint k: lane l < n_levels holds level l's count; an inclusive wave scan
+    // gives each level's end, and the first level whose end exceeds k holds it
+    const int cnt = lane < n_levels ? stage_count[v * n_levels + lane] : 0;
+    int incl = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(incl, off);
+        if (lane >= off) incl += o;
     }
+    const int pre = __shfl(incl, 63);
+    const unsigned long long past = __ballot(lane < n_levels && incl > k);
+    const int lev = past ? int(__ffsll((long long)past)) - 1 : -1;
+    const int start = lev >= 0 ? __shfl(incl - cnt, lev) : 0;
+    const int rank = k - start;
     if (k == 0 && lane == 0) count[v] = pre;
     if (lev < 0) return;
     const xa_level_desc d = levels[v * n_levels + lev];
@@ -569,14 +577,24 @@ __global__ void __launch_bounds__(256) k_orient_brief(const xa_view_desc* __rest
     const uint8_t* P = arena + d.offset;
     int m10 = 0, m01 = 0;
     {
+        // all 16 rows' loads are issued before any is used: every lane loads (keypoints lie
+        // kBorder > 16 pixels inside the level, so offsets up to 16 stay in bounds) and the
+        // disk x^2 + y^2 <= 225 is applied afterwards
         const int dx = (lane & 31) - 15;
+        const uint8_t* row = P + size_t(y - 15 + (lane >> 5)) * pitch + x + dx;
+        int I[16];
+#pragma unroll
+        for (int it = 0; it < 16; ++it) I[it] = row[size_t(2 * it) * pitch];
+#pragma unroll
         for (int it = 0; it < 16; ++it) {
             const int dy = -15 + 2 * it + (lane >> 5);
-            if (dy <= 15 && dx * dx + dy * dy <= 225) {
-                const int I = P[size_t(y + dy) * pitch + x + dx];
-                m10 += dx * I;
-                m01 += dy * I;
-            }
+            if (!(dy <= 15 && dx * dx + dy * dy <= 225)) I[it] = 0;
+        }
+#pragma unroll
+        for (int it = 0; it < 16; ++it) {
+            const int dy = -15 + 2 * it + (lane >> 5);
+            m10 += dx * I[it];
+            m01 += dy * I[it];
         }
     }
 #pragma unroll
