@@ -404,132 +404,222 @@ __device__ __forceinline__ unsigned long long okey(long long r) { return (unsign
 
 // Digit (0..255) holding the k-th item, counting from the top bin when descending and from
 // the bottom bin otherwise, of a 256-bin histogram; every thread of a 256-thread block takes
-// part.  *s_k receives the rank of the item inside that bin.
-__device__ int pick_digit(const int* hist, int* scan, bool descending, int k, int* s_digit, int* s_k) {
-    const int t = threadIdx.x;
+// part.  *s_k receives the rank of the item inside that bin, *s_bin the bin's size.
+__device__ int pick_digit(const int* hist, int* wsum, bool descending, int k, int* s_digit, int* s_k, int* s_bin) {
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int g = descending ? 255 - t : t;
-    scan[t] = hist[g];
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        const int v = t >= off ? scan[t - off] : 0;
-        __syncthreads();
-        scan[t] += v;
-        __syncthreads();
+    const int h = hist[g];
+    int incl = h;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(incl, off);
+        if (lane >= off) incl += o;
     }
-    const int before = t > 0 ? scan[t - 1] : 0;
-    if (before < k && k <= scan[t]) { *s_digit = g; *s_k = k - before; }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    for (int w = 0; w < wv; ++w) incl += wsum[w];
+    const int before = incl - h;
+    if (before < k && k <= incl) { *s_digit = g; *s_k = k - before; *s_bin = h; }
     __syncthreads();
     return *s_digit;
 }
 
-// k-th value in the order given by `descending` among items i < C with pred(i), by 8-bit
-// digits from bit top_bit down; *k_rem receives how many items equal to it complete k.
-template <typename Get, typename Pred>
-__device__ unsigned long long radix_select(int C, int k, int top_bit, bool descending, Get get, Pred pred, int* hist,
-                                           int* scan, int* k_rem, int* s_digit, int* s_k) {
+// The candidates of one (view, level) block: the first kSelRegs * kSelThreads live in
+// registers (item i = threadIdx.x + r kSelThreads in slot r), the rest are read from memory.
+constexpr int kSelRegs = 8;
+
+struct SelItems {
+    unsigned long long key[kSelRegs];   // okey(Harris response)
+    uint32_t ras[kSelRegs];             // raster position
+};
+
+// Calls f(key, raster) for every candidate this thread owns.
+template <typename F>
+__device__ __forceinline__ void for_items(const SelItems& it, const Cand* cd, int C, F f) {
+#pragma unroll
+    for (int r = 0; r < kSelRegs; ++r)
+        if (int(threadIdx.x) + r * kSelThreads < C) f(it.key[r], it.ras[r]);
+    for (int i = threadIdx.x + kSelRegs * kSelThreads; i < C; i += kSelThreads) {
+        const Cand c = cd[i];
+        f(okey(c.harris), c.raster);
+    }
+}
+
+// k-th value, in the order given by `descending`, among this block's candidates with
+// pred(key, raster), of the field val(key, raster), by 8-bit digits of its bits
+// 8 n_digits - 1 .. 0 (higher bits are taken to be shared by every such candidate and come
+// back as zero).  *k_rem receives how many candidates equal to it complete k, *n_eq how many
+// equal it (n_items when n_digits is 0).
+template <typename Val, typename Pred>
+__device__ unsigned long long radix_select(const SelItems& it, const Cand* cd, int C, int n_items, int k, int n_digits,
+                                           bool descending, Val val, Pred pred, int* hist, int* wsum, int* k_rem,
+                                           int* n_eq, int* s_digit, int* s_k, int* s_bin) {
     unsigned long long prefix = 0, pmask = 0;
-    for (int shift = top_bit - 7; shift >= 0; shift -= 8) {
+    int eq = n_items;
+    for (int shift = 8 * (n_digits - 1); shift >= 0; shift -= 8) {
         hist[threadIdx.x] = 0;
         __syncthreads();
-        for (int i = threadIdx.x; i < C; i += blockDim.x) {
-            if (!pred(i)) continue;
-            const unsigned long long u = get(i);
-            if ((u & pmask) != prefix) continue;
-            atomicAdd(&hist[(u >> shift) & 0xFF], 1);
-        }
+        for_items(it, cd, C, [&](unsigned long long key, uint32_t ras) {
+            const unsigned long long u = val(key, ras);
+            if (pred(key, ras) && (u & pmask) == prefix) atomicAdd(&hist[(u >> shift) & 0xFF], 1);
+        });
         __syncthreads();
-        const int dgt = pick_digit(hist, scan, descending, k, s_digit, s_k);
+        const int dgt = pick_digit(hist, wsum, descending, k, s_digit, s_k, s_bin);
         prefix |= (unsigned long long)dgt << shift;
         pmask |= 0xFFull << shift;
         k = *s_k;
+        eq = *s_bin;
         __syncthreads();
     }
     *k_rem = k;
+    *n_eq = eq;
     return prefix;
 }
 
+// 8-bit digits that cover bits 0 .. the highest set bit of x (0 for x = 0)
+__device__ __forceinline__ int digits_for(unsigned long long x) { return x ? (64 - __clzll((long long)x) + 7) >> 3 : 0; }
+
+__device__ __forceinline__ unsigned long long wave_or(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v |= __shfl_xor(v, off);
+    return v;
+}
+__device__ __forceinline__ unsigned long long wave_and(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v &= __shfl_xor(v, off);
+    return v;
+}
+
 // One block per (view, level): the top `quota` candidates by (Harris response descending,
-// raster ascending), sorted in that order, into the staging slots.  Up to kSelMax
-// candidates are sorted directly in LDS; more are first cut down to the quota by radix
-// selection of the response (and, among equal responses, of the raster position).
+// raster ascending), in that order, into the staging slots.  The response threshold is found
+// by radix selection (over the positive responses alone when there are at least `quota` of
+// them, which leaves fewer distinct high bytes), ties at the threshold by a second selection
+// of the raster position; the kept candidates are compacted into LDS and each is written at
+// its rank, counted against the others.
 __global__ void __launch_bounds__(kSelThreads) k_select(const xa_level_desc* __restrict__ levels, int n_features,
                                                         const Cand* __restrict__ cand,
                                                         const int32_t* __restrict__ cand_count,
                                                         int4* __restrict__ stage, int32_t* __restrict__ stage_count) {
-    __shared__ unsigned long long s_key[kSelMax];
-    __shared__ uint32_t s_ras[kSelMax];
-    __shared__ int hist[256], scan[256];
-    __shared__ int s_digit, s_k, s_n;
-    const int vl = blockIdx.x;
+    // kept entries, padded with (0, 0xFFFFFFFF) to a multiple of 8: such an entry never
+    // precedes another
+    __shared__ __align__(16) unsigned long long s_key[kSelMax + 8];
+    __shared__ __align__(16) uint32_t s_ras[kSelMax + 8];
+    __shared__ int hist[256], wsum[kSelThreads / 64];
+    __shared__ unsigned long long s_red[4][kSelThreads / 64];
+    __shared__ int s_digit, s_k, s_bin, s_n, s_pos;
+    const int vl = blockIdx.x, t = threadIdx.x;
     const xa_level_desc d = levels[vl];
     const int C = int(min((long long)cand_count[vl], (long long)d.cand_cap));
     const int quota = d.quota;
     const Cand* cd = cand + d.cand_offset;
     const int n = min(C, quota);
-    if (threadIdx.x == 0) s_n = 0;
+    if (n <= 0) {                   // nothing to keep (no candidates, or a zero quota)
+        if (t == 0) stage_count[vl] = 0;
+        return;
+    }
+    SelItems it;
+#pragma unroll
+    for (int r = 0; r < kSelRegs; ++r) {
+        const int i = t + r * kSelThreads;
+        Cand c{};
+        if (i < C) c = cd[i];
+        it.key[r] = okey(c.harris);
+        it.ras[r] = c.raster;
+    }
+    if (t == 0) { s_n = 0; s_pos = 0; }
     __syncthreads();
-    if (C <= kSelMax) {
-        for (int i = threadIdx.x; i < C; i += blockDim.x) {
-            const Cand c = cd[i];
-            s_key[i] = okey(c.harris);
-            s_ras[i] = c.raster;
+    unsigned long long K = 0;       // kept: key > K, or key == K and raster <= Rthr
+    uint32_t Rthr = 0xFFFFFFFFu;
+    if (C > n) {
+        constexpr unsigned long long kPos = 0x8000000000000000ull;    // okey of a zero response
+        unsigned long long o = 0, a = ~0ull, op = 0, ap = ~0ull;
+        int npos = 0;
+        for_items(it, cd, C, [&](unsigned long long key, uint32_t) {
+            o |= key; a &= key;
+            if (key > kPos) { op |= key; ap &= key; ++npos; }
+        });
+        o = wave_or(o); a = wave_and(a); op = wave_or(op); ap = wave_and(ap);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) npos += __shfl_xor(npos, off);
+        if ((t & 63) == 0) {
+            s_red[0][t >> 6] = o; s_red[1][t >> 6] = a; s_red[2][t >> 6] = op; s_red[3][t >> 6] = ap;
+            atomicAdd(&s_pos, npos);
         }
-        if (threadIdx.x == 0) s_n = C;
-    } else if (n > 0) {
-        int k_eq;
-        const unsigned long long K = radix_select(
-            C, n, 63, true, [&](int i) { return okey(cd[i].harris); }, [](int) { return true; }, hist, scan, &k_eq,
-            &s_digit, &s_k);
-        int k_r;
-        const unsigned long long Rthr = radix_select(
-            C, k_eq, 31, false, [&](int i) { return (unsigned long long)cd[i].raster; },
-            [&](int i) { return okey(cd[i].harris) == K; }, hist, scan, &k_r, &s_digit, &s_k);
-        for (int i = threadIdx.x; i < C; i += blockDim.x) {
-            const Cand c = cd[i];
-            const unsigned long long u = okey(c.harris);
-            if (u > K || (u == K && c.raster <= Rthr)) {
-                const int slot = atomicAdd(&s_n, 1);
-                s_key[slot] = u;
-                s_ras[slot] = c.raster;
-            }
+        __syncthreads();
+        o = 0; a = ~0ull; op = 0; ap = ~0ull;
+        for (int w = 0; w < kSelThreads / 64; ++w) {
+            o |= s_red[0][w]; a &= s_red[1][w]; op |= s_red[2][w]; ap &= s_red[3][w];
+        }
+        const bool pos_only = s_pos >= n;
+        if (pos_only) { o = op; a = ap; }
+        const int nd = digits_for(o ^ a);
+        const unsigned long long high = nd == 8 ? 0ull : a & ~((1ull << (8 * nd)) - 1);
+        const int n_items = pos_only ? s_pos : C;
+        int k_eq, n_eq;
+        K = high | radix_select(
+            it, cd, C, n_items, n, nd, true, [](unsigned long long key, uint32_t) { return key; },
+            [&](unsigned long long key, uint32_t) { return !pos_only || key > kPos; }, hist, wsum, &k_eq, &n_eq,
+            &s_digit, &s_k, &s_bin);
+        // among responses equal to K the first k_eq raster positions are kept: all of them when
+        // k_eq covers every such candidate
+        if (k_eq < n_eq) {
+            int k_r, n_r;
+            const uint32_t npix = uint32_t(d.width) * uint32_t(d.height);
+            Rthr = uint32_t(radix_select(
+                it, cd, C, n_eq, k_eq, digits_for(npix - 1), false,
+                [](unsigned long long, uint32_t ras) { return (unsigned long long)ras; },
+                [&](unsigned long long key, uint32_t) { return key == K; }, hist, wsum, &k_r, &n_r, &s_digit,
+                &s_k, &s_bin));
         }
     }
+    // compact the n kept candidates (all of them when C <= quota)
+    for_items(it, cd, C, [&](unsigned long long key, uint32_t ras) {
+        if (key > K || (key == K && ras <= Rthr)) {
+            const int slot = atomicAdd(&s_n, 1);
+            s_key[slot] = key;
+            s_ras[slot] = ras;
+        }
+    });
+    if (t < 8) { s_key[n + t] = 0ull; s_ras[n + t] = 0xFFFFFFFFu; }
     __syncthreads();
-    const int m = s_n;              // entries to sort (all candidates, or exactly the quota)
-    int M = 1;
-    while (M < m) M <<= 1;
-    for (int i = m + threadIdx.x; i < M; i += blockDim.x) {
-        s_key[i] = 0ull;
-        s_ras[i] = 0xFFFFFFFFu;
+    // rank of kept entry i = entries before it in (key descending, raster ascending) order;
+    // rasters are distinct, so the ranks are a permutation of 0 .. n-1.  Each thread ranks
+    // entries t, t + kSelThreads, ... against 8 entries per step of 128-bit LDS reads.
+    const int per = (n + kSelThreads - 1) / kSelThreads;
+    unsigned long long ki[kSelRegs];
+    uint32_t ri[kSelRegs];
+    int rank[kSelRegs];
+#pragma unroll
+    for (int r = 0; r < kSelRegs; ++r) {
+        const int i = t + r * kSelThreads;
+        ki[r] = i < n ? s_key[i] : 0ull;
+        ri[r] = i < n ? s_ras[i] : 0xFFFFFFFFu;
+        rank[r] = 0;
     }
-    __syncthreads();
-    // bitonic sort: key descending, raster ascending
-    for (int k = 2; k <= M; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < M; i += blockDim.x) {
-                const int ixj = i ^ j;
-                if (ixj > i) {
-                    const unsigned long long ka = s_key[i], kb = s_key[ixj];
-                    const uint32_t ra = s_ras[i], rb = s_ras[ixj];
-                    const bool a_first = ka > kb || (ka == kb && ra < rb);
-                    const bool up = (i & k) == 0;
-                    if (up != a_first) {
-                        s_key[i] = kb; s_key[ixj] = ka;
-                        s_ras[i] = rb; s_ras[ixj] = ra;
-                    }
-                }
-            }
-            __syncthreads();
+    const ulonglong2* k2 = reinterpret_cast<const ulonglong2*>(s_key);
+    const uint4* r4 = reinterpret_cast<const uint4*>(s_ras);
+    for (int j = 0; j < n; j += 8) {
+        const ulonglong2 a0 = k2[j / 2], a1 = k2[j / 2 + 1], a2 = k2[j / 2 + 2], a3 = k2[j / 2 + 3];
+        const uint4 b0 = r4[j / 4], b1 = r4[j / 4 + 1];
+        const unsigned long long kj[8] = {a0.x, a0.y, a1.x, a1.y, a2.x, a2.y, a3.x, a3.y};
+        const uint32_t rj[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+#pragma unroll
+        for (int r = 0; r < kSelRegs; ++r) {
+            if (r >= per) break;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) rank[r] += (kj[e] > ki[r] || (kj[e] == ki[r] && rj[e] < ri[r])) ? 1 : 0;
         }
     }
     int4* st = stage + size_t(d.view) * n_features + d.kp_base;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const uint32_t r = s_ras[i];
-        const long long R = (long long)(s_key[i] ^ 0x8000000000000000ull);
-        st[i] = make_int4(int(r % uint32_t(d.width)), int(r / uint32_t(d.width)), int(uint32_t(R & 0xFFFFFFFFll)),
-                          int(R >> 32));
+#pragma unroll
+    for (int r = 0; r < kSelRegs; ++r) {
+        if (t + r * kSelThreads < n) {
+            const long long R = (long long)(ki[r] ^ 0x8000000000000000ull);
+            st[rank[r]] = make_int4(int(ri[r] % uint32_t(d.width)), int(ri[r] / uint32_t(d.width)),
+                                    int(uint32_t(R & 0xFFFFFFFFll)), int(R >> 32));
+        }
     }
-    if (threadIdx.x == 0) stage_count[vl] = n;
+    if (t == 0) stage_count[vl] = n;
 }
 
 // ------------------------------------------------------------------ orientation + rBRIEF
