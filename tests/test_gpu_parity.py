@@ -187,6 +187,39 @@ def test_extract_too_small_for_detection(dev):
     assert _check_extract(img, rows, 2, 50, dev, "small") == 0
 
 
+def _level0_responses(img, T):
+    xs, ys = OO.fast_candidates(img, np.ones(img.shape, bool), T)
+    return OO.harris_response(img, xs, ys)
+
+
+def test_extract_more_candidates_than_registers(dev):
+    say("case: extract on 600x600 noise, T=10: >2048 candidates per level (memory-read selection)")
+    img = np.random.default_rng(11).integers(0, 256, (600, 600)).astype(np.uint8)
+    R = _level0_responses(img, 10)
+    assert len(R) > 4 * 2048
+    # quotas 1771 and 1229: each thread of the selection ranks up to 7 kept entries
+    assert _check_extract(img, [(1.0, 0.0, 0.0, 1.0)], 2, 3000, dev, "noise 600 / N=3000", T=10) == 3000
+
+
+@pytest.mark.parametrize("tiles,N", [(20, 100), (6, 30)])
+def test_extract_ties_at_the_quota_cut(dev, tiles, N):
+    say(f"case: extract on a periodic image ({tiles}x{tiles} copies of one 24x24 block), N={N}: "
+        "the quota cuts through a group of equal responses")
+    blk = np.random.default_rng(11).integers(0, 256, (24, 24)).astype(np.uint8)
+    img = np.tile(blk, (tiles, tiles))
+    R = np.sort(_level0_responses(img, 20))[::-1]
+    assert len(R) > N and R[N - 1] == R[N]                # the cut splits a tie group
+    assert (len(R) > 2048) == (tiles == 20)
+    assert _check_extract(img, [(1.0, 0.0, 0.0, 1.0)], 1, N, dev, f"periodic {tiles} / N={N}") == N
+
+
+def test_extract_quota_beyond_the_positive_responses(dev, tiny):
+    say("case: extract tiny B at T=5 with a quota above its count of positive Harris responses")
+    R = _level0_responses(tiny.B, 5)
+    assert (R > 0).sum() < 400 < len(R)
+    assert _check_extract(tiny.B, [(1.0, 0.0, 0.0, 1.0)], 1, 400, dev, "tiny B / N=400, T=5", T=5) == 400
+
+
 def _pad_desc(feats, N):
     D = np.zeros((len(feats), N, 32), np.uint8)
     C = np.zeros(len(feats), np.int32)
