@@ -15,11 +15,13 @@ FLAGS = ["-std=c++17", "-O3", "--offload-arch=gfx950", "-fPIC",
          # keep the compiler from forming packed fp32 instructions
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(PKG, "csrc")]
+# per-source additions: the matcher's MFMA accumulators stay in VGPRs (no AGPR copies)
+EXTRA = {"match.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _compile(src: str, out_dir: str) -> str:
     obj = os.path.join(out_dir, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(PKG, "csrc", src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(PKG, "csrc", src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

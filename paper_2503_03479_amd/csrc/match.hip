@@ -1,8 +1,9 @@
 // All-view-pair brute-force Hamming matching on gfx950 (Sec. III.B) with the
 // nearest / second-nearest ratio test (Sec. IV.C), the best view pair, and the
-// precision of eqs. (5)-(6).  Matching is integer XOR + popcount on the vector
-// ALU: queries live in registers, train descriptors stream through LDS and are
-// read as wave-uniform broadcasts.
+// precision of eqs. (5)-(6).  Two families of kernels compute the same result:
+// integer XOR + popcount on the vector ALU (queries in registers, train
+// descriptors streamed through LDS and read as wave-uniform broadcasts), and an
+// exact fp4 matrix-core contraction of the descriptors read as +-1 vectors.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -145,6 +146,175 @@ k_match(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ count_q
     if (threadIdx.x == 0 && s_acc) atomicAdd(&pair_count[pair], s_acc);
 }
 
+// ------------------------------------------------------------------ matrix-core variant
+//
+// With descriptor bits read as +1 / -1, the dot product of two 256-bit descriptors is
+// 256 - 2 x their Hamming distance, so one view pair's distance table is the product of
+// two +-1 matrices: an fp4 (e2m1) MFMA contraction whose every input and partial sum is a
+// small integer, hence exact in fp32.  Train descriptors are the A rows and queries the B
+// columns of v_mfma_scale_f32_32x32x64_f8f6f4 (unit scales), so each lane holds one query
+// column and 16 train rows of a 32 x 32 tile.  The accumulator starts at
+// 512 + (16383 - j) / 2^14 for train row j, so the result dot + 512 + that fraction lies in
+// (255, 769) and is exact in fp32 (10 + 14 significant bits): the largest has the smallest
+// distance and, among equal distances, the smallest index.  Rows past the train count have
+// zero operands and start at 1, below every real row.  Positive floats order as their bit
+// patterns, so the two largest per query are kept with integer v_max / v_med3.
+
+constexpr int kMxThreads = 256;      // four waves
+constexpr int kMxQT = 4;             // 32-query tiles per wave: a block owns 512 queries of one view pair
+constexpr int kMxChunk = 256;        // train descriptors expanded into LDS per step (32 KiB)
+constexpr int kMxBlockQ = (kMxThreads / 64) * 32 * kMxQT;
+
+typedef int v8i_t __attribute__((ext_vector_type(8)));
+typedef float v16f_t __attribute__((ext_vector_type(16)));
+
+// byte -> 8 fp4 values, bit i -> nibble i: +1.0 (0x2) for a set bit, -1.0 (0xA) for a clear one
+__device__ __forceinline__ uint32_t byte_pm1(uint32_t b) {
+    uint32_t s = (b | (b << 12)) & 0x000F000Fu;
+    s = (s | (s << 6)) & 0x03030303u;
+    s = (s | (s << 3)) & 0x11111111u;
+    return 0xAAAAAAAAu ^ (s << 3);
+}
+
+// one 32-bit descriptor word -> the 32 fp4 values of one lane's MFMA operand
+__device__ __forceinline__ uint4 word_pm1(uint32_t w) {
+    return make_uint4(byte_pm1(w & 0xFFu), byte_pm1((w >> 8) & 0xFFu), byte_pm1((w >> 16) & 0xFFu), byte_pm1(w >> 24));
+}
+
+__device__ __forceinline__ v8i_t operand(uint4 u) {
+    v8i_t v = {int(u.x), int(u.y), int(u.z), int(u.w), 0, 0, 0, 0};
+    return v;
+}
+
+// Same block -> (group, view pair, query block) mapping and outputs as k_match.  The K
+// dimension is split alike for both operands: slice s of lane l is word 2 s + l / 32 of
+// descriptor (tile row or column) l % 32, so the contraction pairs equal bits whatever
+// order the hardware gives the 64 values of a slice.
+__global__ void __launch_bounds__(kMxThreads)
+k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ count_q, const uint32_t* __restrict__ desc_t,
+           const int32_t* __restrict__ count_t, const xa_match_group* __restrict__ groups,
+           const int32_t* __restrict__ block_prefix, int n_groups, xa_match_group one, int qblocks, int N, int num,
+           int den, xa_match* __restrict__ matches, int32_t* __restrict__ pair_count) {
+    // [tile of 32][slice][lane] operands of one chunk of train descriptors
+    __shared__ uint4 tr[(kMxChunk / 32) * 4 * 64];
+    __shared__ int s_acc;
+    xa_match_group G = one;
+    int local = blockIdx.x;
+    if (groups) {
+        const int gi = find_segment_wave(block_prefix, n_groups, blockIdx.x);
+        G = groups[gi];
+        local = blockIdx.x - block_prefix[gi];
+    }
+    const int qb = local % qblocks, pr = local / qblocks;
+    const int i = pr / G.nb, j = pr - (pr / G.nb) * G.nb;
+    const long long pair = G.pair_base + pr;
+    const int va = G.a0 + i, vb = G.b0 + j;
+    const int nq = min(max(count_q[va], 0), N), nt = min(max(count_t[vb], 0), N);
+    const int q0 = qb * kMxBlockQ;
+    if (q0 >= nq) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, h = lane >> 5, m = lane & 31;
+    const int qw0 = q0 + wv * 32 * kMxQT;                     // this wave's first query
+    const int nqt = min(max((nq - qw0 + 31) >> 5, 0), kMxQT);  // its 32-query tiles holding queries
+    uint4 B[kMxQT][4];
+#pragma unroll
+    for (int qt = 0; qt < kMxQT; ++qt) {
+        const int qi = qw0 + qt * 32 + m;
+        const uint32_t* p = desc_q + (size_t(va) * N + qi) * 8;
+#pragma unroll
+        for (int sl = 0; sl < 4; ++sl) B[qt][sl] = word_pm1(qi < nq ? p[2 * sl + h] : 0u);
+    }
+    uint32_t m1[kMxQT], m2[kMxQT];
+#pragma unroll
+    for (int qt = 0; qt < kMxQT; ++qt) { m1[qt] = 0u; m2[qt] = 0u; }
+    // start value of element r (tile row 8 (r / 4) + 4 h + r % 4) of a tile at base 0
+    float f0[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) f0[r] = 512.0f + float(16383 - (8 * (r >> 2) + 4 * h + (r & 3))) * (1.0f / 16384.0f);
+    const uint4* tb = reinterpret_cast<const uint4*>(desc_t + size_t(vb) * N * 8);
+    uint4 n0 = make_uint4(0, 0, 0, 0), n1 = n0;                // next chunk's descriptor of this thread
+    if (int(threadIdx.x) < nt) { n0 = tb[2 * threadIdx.x]; n1 = tb[2 * threadIdx.x + 1]; }
+    for (int c0 = 0; c0 < nt; c0 += kMxChunk) {
+        const int cn = min(kMxChunk, nt - c0);
+        __syncthreads();
+        {   // expand this thread's descriptor (chunk row t) into its 8 operand slots; rows
+            // past the train count get zero operands
+            const int t = threadIdx.x, tt = t >> 5, tm = t & 31;
+            const bool live = t < cn;
+            const uint32_t w[8] = {n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, n1.z, n1.w};
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                tr[(tt * 4 + (k >> 1)) * 64 + (k & 1) * 32 + tm] = live ? word_pm1(w[k]) : make_uint4(0, 0, 0, 0);
+        }
+        __syncthreads();
+        {
+            const int nx = c0 + kMxChunk + int(threadIdx.x);
+            if (nx < nt) { n0 = tb[2 * size_t(nx)]; n1 = tb[2 * size_t(nx) + 1]; }
+        }
+        if (nqt == 0) continue;
+        const int ntile = (cn + 31) >> 5;
+        for (int tt = 0; tt < ntile; ++tt) {
+            const int base = c0 + tt * 32;
+            const float fb = float(base) * (1.0f / 16384.0f);
+            v16f_t ci;
+            if (base + 32 <= nt) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) ci[r] = f0[r] - fb;
+            } else {
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    ci[r] = base + 8 * (r >> 2) + 4 * h + (r & 3) < nt ? f0[r] - fb : 1.0f;
+            }
+            const uint4* a = tr + tt * 4 * 64 + lane;
+            const v8i_t A0 = operand(a[0]), A1 = operand(a[64]), A2 = operand(a[128]), A3 = operand(a[192]);
+#pragma unroll
+            for (int qt = 0; qt < kMxQT; ++qt) {     // tiles past nq compute unused columns
+                v16f_t acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A0, operand(B[qt][0]), ci, 4, 4, 0, 127, 0, 127);
+                acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A1, operand(B[qt][1]), acc, 4, 4, 0, 127, 0, 127);
+                acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A2, operand(B[qt][2]), acc, 4, 4, 0, 127, 0, 127);
+                acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A3, operand(B[qt][3]), acc, 4, 4, 0, 127, 0, 127);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    // plain min / max (the compiler forms v_med3_u32 and, unlike for inline asm,
+                    // inserts the wait states an MFMA result needs before a VALU read)
+                    const uint32_t key = __float_as_uint(acc[r]);
+                    m2[qt] = max(m2[qt], min(m1[qt], key));
+                    m1[qt] = max(m1[qt], key);
+                }
+            }
+        }
+    }
+    if (threadIdx.x == 0) s_acc = 0;
+    __syncthreads();
+    int cnt = 0;
+#pragma unroll
+    for (int qt = 0; qt < kMxQT; ++qt) {
+        // lanes l and l + 32 saw disjoint rows of the same query column
+        const uint32_t o1 = __shfl_xor(m1[qt], 32), o2 = __shfl_xor(m2[qt], 32);
+        const float b1 = __uint_as_float(max(m1[qt], o1));
+        const float b2 = __uint_as_float(max(min(m1[qt], o1), max(m2[qt], o2)));
+        const int qi = qw0 + qt * 32 + m;
+        if (h != 0 || qi >= nq) continue;
+        xa_match r;
+        int d1 = 65535, d2 = 65535;
+        r.t = -1;
+        if (nt > 0) {   // b1 = (256 - 2 d1) + 512 + (16383 - t) / 2^14
+            const float it = floorf(b1);
+            r.t = 16383 - int((b1 - it) * 16384.0f);
+            d1 = (768 - int(it)) >> 1;
+        }
+        if (nt > 1) d2 = (768 - int(floorf(b2))) >> 1;
+        r.d1 = uint16_t(d1);
+        r.d2 = uint16_t(d2);
+        matches[size_t(pair) * N + qi] = r;
+        cnt += (nt >= 2 && den * d1 < num * d2) ? 1 : 0;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if (lane == 0 && cnt) atomicAdd(&s_acc, cnt);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_acc) atomicAdd(&pair_count[pair], s_acc);
+}
+
 // Per group: argmax of the pair counts, lowest pair index on ties, as the max over
 // (count << 32 | ~local pair); best[4 g ..] = local pair, i, j, count.
 __global__ void __launch_bounds__(1024) k_best(const int32_t* __restrict__ pair_count,
@@ -223,6 +393,9 @@ __global__ void __launch_bounds__(256) k_precision(const xa_keypoint* __restrict
 
 static int pick_q(int N) { return N > 2 * kMatchThreads ? 4 : (N > kMatchThreads ? 2 : 1); }
 
+// queries one block of matcher variant Q owns (Q = XA_MATCH_MATRIX: the matrix-core kernel)
+static int block_queries(int Q) { return Q == XA_MATCH_MATRIX ? kMxBlockQ : kMatchThreads * Q; }
+
 xa_status launch_match_any(const uint8_t* desc_q, const int32_t* count_q, const uint8_t* desc_t,
                            const int32_t* count_t, const xa_match_group* groups_dev, const int32_t* prefix_dev,
                            int n_groups, const xa_match_group& one, long long total_pairs, long long total_blocks,
@@ -234,9 +407,12 @@ xa_status launch_match_any(const uint8_t* desc_q, const int32_t* count_q, const 
                            int(total_pairs), 0);
     const uint32_t* dq = reinterpret_cast<const uint32_t*>(desc_q);
     const uint32_t* dt = reinterpret_cast<const uint32_t*>(desc_t);
-    const int qblocks = (N + kMatchThreads * Q - 1) / (kMatchThreads * Q);
+    const int qblocks = (N + block_queries(Q) - 1) / block_queries(Q);
     if (total_blocks > 0) {
-        if (Q == 4)
+        if (Q == XA_MATCH_MATRIX)
+            hipLaunchKernelGGL(k_match_mx, dim3(unsigned(total_blocks)), dim3(kMxThreads), 0, st, dq, count_q, dt,
+                               count_t, groups_dev, prefix_dev, n_groups, one, qblocks, N, num, den, matches, pair_count);
+        else if (Q == 4)
             hipLaunchKernelGGL(k_match<4>, dim3(unsigned(total_blocks)), dim3(kMatchThreads), 0, st, dq, count_q, dt,
                                count_t, groups_dev, prefix_dev, n_groups, one, qblocks, N, num, den, matches, pair_count);
         else if (Q == 2)
@@ -256,7 +432,7 @@ xa_status launch_match(const uint8_t* desc_a, const int32_t* count_a, int32_t n_
                        const int32_t* count_b, int32_t n_b, int32_t N, int32_t num, int32_t den, xa_match* matches,
                        int32_t* pair_count, int32_t* best, hipStream_t st) {
     const int Q = pick_q(N);
-    const int qblocks = (N + kMatchThreads * Q - 1) / (kMatchThreads * Q);
+    const int qblocks = (N + block_queries(Q) - 1) / block_queries(Q);
     const xa_match_group one{0, n_a, 0, n_b, 0};
     return launch_match_any(desc_a, count_a, desc_b, count_b, nullptr, nullptr, 1, one, (long long)n_a * n_b,
                             (long long)n_a * n_b * qblocks, N, Q, num, den, matches, pair_count, best, st);
@@ -326,8 +502,9 @@ extern "C" xa_status xa_plan_matches(const xa_match_group* groups, int32_t n_gro
     if (!blob_bytes || !groups || n_groups < 1) return fail(XA_EINVAL, "need at least one group");
     if (n_features < 1 || n_features > XA_MAX_FEATURES) return fail(XA_EUNSUPPORTED, "n_features out of range");
     const int Q = queries_per_lane == 0 ? pick_q(n_features) : queries_per_lane;
-    if (Q != 1 && Q != 2 && Q != 4) return fail(XA_EINVAL, "queries_per_lane must be 0 (auto), 1, 2 or 4");
-    const int qblocks = (n_features + kMatchThreads * Q - 1) / (kMatchThreads * Q);
+    if (Q != 1 && Q != 2 && Q != 4 && Q != XA_MATCH_MATRIX)
+        return fail(XA_EINVAL, "queries_per_lane must be 0 (auto), 1, 2, 4 or XA_MATCH_MATRIX");
+    const int qblocks = (n_features + block_queries(Q) - 1) / block_queries(Q);
     std::vector<int32_t> prefix(n_groups + 1, 0);
     long long blocks = 0, pairs = 0, views = 0;
     for (int g = 0; g < n_groups; ++g) {

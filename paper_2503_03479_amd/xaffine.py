@@ -548,13 +548,18 @@ def plan_matches(groups, n_features: int, queries_per_lane: int = 0) -> MatchPla
     return MatchPlan(blob, groups, n_features)
 
 
+MATCH_MATRIX = -1          # queries_per_lane code of the matrix-core (MFMA) matcher
+MATCH_VARIANTS = (1, 2, 4, MATCH_MATRIX)
+
+
 AUTOTUNE_CACHE = os.environ.get("XAFFINE_AUTOTUNE_CACHE",
                                 os.path.join(os.path.expanduser("~"), ".cache", "xaffine", "autotune.json"))
 
 
 def autotune_queries_per_lane(groups, n_features: int, device="cuda", desc=None, count=None, reps: int = 5,
                               use_cache: bool = True):
-    """The matcher variant (queries per lane 1, 2 or 4) that runs `groups` fastest on this GPU.
+    """The matcher variant (the popcount kernel with 1, 2 or 4 queries per lane, or the
+    matrix-core kernel, MATCH_MATRIX) that runs `groups` fastest on this GPU.
 
     Every variant is timed with HIP events on the current stream, over the given descriptor
     set (desc [views][n_features][32], count [views]) or, without one, over random descriptors
@@ -586,7 +591,7 @@ def autotune_queries_per_lane(groups, n_features: int, device="cuda", desc=None,
             return int(cache[key]["queries_per_lane"]), {int(k): v for k, v in cache[key]["ms"].items()}
     stream = torch.cuda.current_stream(dev)
     times = {}
-    for q in (1, 2, 4):
+    for q in MATCH_VARIANTS:
         mp = plan_matches(groups, n_features, q)
         match_groups(mp, desc, count)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

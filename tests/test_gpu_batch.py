@@ -44,8 +44,9 @@ def pairs():
     return out
 
 
-def test_match_groups_exact_random(dev):
-    say("case: group matching of random descriptors, 4 groups with ragged sizes and an empty one")
+@pytest.mark.parametrize("q", [0, X.MATCH_MATRIX])
+def test_match_groups_exact_random(dev, q):
+    say(f"case: group matching of random descriptors, 4 groups with ragged sizes and an empty one (variant {q})")
     g = np.random.default_rng(31)
     N = 600
     sizes = [300, 17, 0, 600, 1, 256, 599, 64, 2, 450]
@@ -59,7 +60,7 @@ def test_match_groups_exact_random(dev):
     descs[3][:200] = descs[0][:200] ^ np.uint8(4)
     D[3, :200] = descs[3][:200]
     groups = [(0, 3, 3, 4, 0), (5, 2, 0, 5, 12), (9, 0, 1, 3, 22), (2, 4, 6, 4, 22)]
-    mp = X.plan_matches(np.array(groups, X.GROUP_DTYPE), N)
+    mp = X.plan_matches(np.array(groups, X.GROUP_DTYPE), N, q)
     t = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
     m, pc, best = X.match_groups(mp, t(D), t(C))
     torch.cuda.synchronize()
@@ -75,9 +76,10 @@ def test_match_groups_exact_random(dev):
     say(f"[groups] exact on 4 groups, best {best.tolist()}")
 
 
-@pytest.mark.parametrize("q", [1, 2, 4])
+@pytest.mark.parametrize("q", X.MATCH_VARIANTS)
 def test_match_groups_variants_agree(dev, q):
-    say(f"case: group matching, queries_per_lane={q} equals the oracle at N=1100")
+    say(f"case: group matching, queries_per_lane={q} equals the oracle at N=1100 (duplicate train rows: "
+        "equal distances go to the lowest index)")
     g = np.random.default_rng(32 + q)
     N = 1100
     sizes = [1100, 1099, 513, 0, 1024]
@@ -89,6 +91,11 @@ def test_match_groups_variants_agree(dev, q):
         descs.append(d)
     descs[4][:300] = descs[0][:300] ^ np.uint8(16)
     D[4, :300] = descs[4][:300]
+    for v in (0, 2):                                  # exact duplicates among train rows
+        descs[v][400:480] = descs[v][:80]
+        D[v, 400:480] = descs[v][400:480]
+    descs[1][:80] = descs[0][:80]                     # queries equal to duplicated train rows
+    D[1, :80] = descs[1][:80]
     groups = [(0, 2, 2, 3, 0), (4, 1, 0, 2, 6)]
     mp = X.plan_matches(np.array(groups, X.GROUP_DTYPE), N, q)
     t = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
@@ -245,9 +252,9 @@ def test_batch_graph_replays(dev, pairs):
 
 
 def test_autotuner_picks_a_variant_and_caches_it(dev, pairs, tmp_path, monkeypatch):
-    """The matcher autotuner times the three variants, caches the winner, and a batch built with
-    it gives the same bytes as batches with each fixed variant."""
-    say("case: matcher autotuner (queries per lane 1 / 2 / 4) and its cache")
+    """The matcher autotuner times every variant, caches the winner, and a batch built with it
+    gives the same bytes as batches with each fixed variant."""
+    say("case: matcher autotuner (popcount kernel with 1 / 2 / 4 queries per lane, matrix-core kernel) and its cache")
     monkeypatch.setattr(X, "AUTOTUNE_CACHE", str(tmp_path / "autotune.json"))
     grid = _grid(1)
     pat = torch.from_numpy(synth.brief_pattern()).to(dev)
@@ -256,13 +263,14 @@ def test_autotuner_picks_a_variant_and_caches_it(dev, pairs, tmp_path, monkeypat
     auto.run(pat)                                          # tunes on its own descriptors, then runs
     torch.cuda.synchronize()
     q, ms = auto.autotune["queries_per_lane"], auto.autotune["ms"]
-    assert q in (1, 2, 4) and set(ms) == {1, 2, 4} and all(v > 0 for v in ms.values()) and ms[q] == min(ms.values())
+    V = set(X.MATCH_VARIANTS)
+    assert q in V and set(ms) == V and all(v > 0 for v in ms.values()) and ms[q] == min(ms.values())
     assert auto.mplan_q == q and (tmp_path / "autotune.json").exists()
     q2, ms2 = X.autotune_queries_per_lane(auto.mplan.groups, 700, dev, auto.desc, auto.count)
     assert q2 == q and ms2 == ms                          # served from the cache
     qr, msr = X.autotune_queries_per_lane(auto.mplan.groups, 700, dev)   # random full descriptors
-    assert qr in (1, 2, 4) and set(msr) == {1, 2, 4}
-    for fixed in (1, 2, 4):
+    assert qr in V and set(msr) == V
+    for fixed in X.MATCH_VARIANTS:
         r = X.BatchRunner(imgs, grid, (1.0,), n_levels=3, n_features=700, device=dev, queries_per_lane=fixed)
         r.run(pat)
         torch.cuda.synchronize()
