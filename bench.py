@@ -7,10 +7,13 @@ at 1.2, 1000 keypoints per view, FAST threshold 20) runs on all 90 views, all
 45 x 45 view pairs are matched with a 0.8 ratio test and the best pair is
 selected.  Inputs are resident in device memory before timing starts.
 
-Prints one JSON line.  Besides the headline it reports, for the dominant
-kernel (the all-pairs Hamming matcher), achieved integer lane-ops/s against
-the vector-ALU peak of the chip, timed with HIP events on the launch stream,
-and the CPU oracle timed on a bounded sample of the same workload.
+Prints one JSON line.  Besides the headline it reports, for the all-pairs
+Hamming matcher (the variant the autotuner picks: the fp4 matrix-core kernel,
+priced as a +-1 contraction of 256 multiply-adds per descriptor comparison
+against the dense fp4 MFMA peak, or a popcount kernel, priced in integer
+lane-ops against the vector-ALU peak), its achieved rate timed with HIP events
+on the launch stream, and the CPU oracle timed on a bounded sample of the same
+workload.
 """
 from __future__ import annotations
 
@@ -29,17 +32,22 @@ sys.path.insert(0, ROOT)
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
 HBM_PEAK_BPS = 8.0e12
 HAMMING_OPS_PER_CMP = 16          # 8 x v_xor_b32 + 8 x v_bcnt_u32_b32 per 256-bit comparison
+# dense fp4 MFMA peak of the MI355X (no sparsity): 10.1 PFLOP/s
+FP4_PEAK_FLOPS = 10.1e15
+MX_FLOPS_PER_CMP = 2 * 256        # a +-1 dot product of two 256-bit descriptors: 256 multiply-adds
+MATCH_MATRIX = -1                 # matcher variant code of the matrix-core kernel
 
-# HBM traffic of k_match on the full-size pair, from two rocprofv3 --pmc passes (FETCH_SIZE, then
-# WRITE_SIZE; KiB per dispatch) per matcher variant (queries per lane), scaled by what the same
+# HBM traffic of the matching kernel on the full-size pair, from two rocprofv3 --pmc passes
+# (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) per matcher variant (-1 = the matrix-core
+# kernel, else the popcount kernel's queries per lane), scaled by what the same
 # counters read for a plain 1 GiB device-to-device copy (FETCH_SIZE reads 0.5 GiB there,
 # WRITE_SIZE 1 GiB).  Valid only for the matcher source it was measured on: any change to that
 # file reports null.
 K_MATCH_TRAFFIC = {
     "source": "paper_2503_03479_amd/csrc/match.hip",
-    "sha256": "51c06c6e1ec8b0637e1c13e74da0b668b5f0b19e2c0122ae815110de1a15370b",
+    "sha256": "0637d015ae5ed3e16ef4e52ed86efccc6675aaf67e1fbaf16f40af5c13583037",
     "fetch_scale": 2.0, "write_scale": 1.0,
-    "kib": {1: (6660.6, 15745.8), 2: (8032.8, 15619.2), 4: (10801.8, 15555.9)},   # (fetch, write) per variant
+    "kib": {-1: (8095.6, 15619.2), 1: (6660.8, 15745.8), 2: (8041.2, 15619.2), 4: (10802.5, 15555.9)},  # (fetch, write)
 }
 
 
@@ -67,8 +75,9 @@ def parse():
     ap.add_argument("--batch-pairs", type=int, default=64, help="image pairs in the batched leg (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--crops", type=int, default=256, help="crops in the differentiable-warp leg (0 = skip)")
-    ap.add_argument("--matcher-q", type=int, default=0, choices=[0, 1, 2, 4],
-                    help="matcher queries per lane for the full-pair leg (0 = autotune)")
+    ap.add_argument("--matcher-q", type=int, default=0, choices=[0, 1, 2, 4, MATCH_MATRIX],
+                    help="matcher variant for the full-pair leg: 0 = autotune, 1 / 2 / 4 = popcount kernel "
+                         "with that many queries per lane, -1 = matrix-core kernel")
     ap.add_argument("--only", choices=["batched", "diffwarp", "copy", "sweep"], default=None,
                     help="run one leg alone and print its JSON (for profiler runs); 'copy' is a plain 1 GiB "
                          "device-to-device copy whose counter readings calibrate the HBM traffic counters")
@@ -430,26 +439,29 @@ def main():
     torch.cuda.synchronize()
     assert torch.equal(st.pair_count, run.pair_count), "stage-by-stage run disagrees with the batched entry"
 
-    # dominant kernel: k_match (xa_match_groups = a counter fill, k_match<Q>, a one-block argmax per group)
+    # the matcher (xa_match_groups = a counter fill, the matching kernel, a one-block argmax per group)
     match_s = stage_ms["match"] / 1e3
     # descriptor sets read once + the match records and counts written
     n_pairs = pa.n_views * pb.n_views
     algo_bytes = (pa.n_views + pb.n_views) * wl["n_features"] * 32 + n_pairs * wl["n_features"] * 8 + n_pairs * 4
-    achieved_ops = comparisons * HAMMING_OPS_PER_CMP / match_s
-    roofline = {
-        "kernel": f"k_match<{run.mplan_q}> (xa_match_groups, {run.mplan_q} queries per lane)",
-        "bound": "alu",
-        "achieved": achieved_ops / 1e12,
-        "peak": VALU_PEAK_OPS / 1e12,
-        "unit": "Tops/s",
-        "frac": achieved_ops / VALU_PEAK_OPS,
-        "traffic": k_match_traffic(run.mplan_q),
+    q = run.mplan_q
+    if q == MATCH_MATRIX:
+        achieved = comparisons * MX_FLOPS_PER_CMP / match_s
+        head = {"kernel": "k_match_mx (xa_match_groups, fp4 matrix-core contraction of +-1 descriptors)",
+                "bound": "mfma", "achieved": achieved / 1e12, "peak": FP4_PEAK_FLOPS / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / FP4_PEAK_FLOPS, "algorithmic_flops_per_launch": comparisons * MX_FLOPS_PER_CMP}
+    else:
+        achieved = comparisons * HAMMING_OPS_PER_CMP / match_s
+        head = {"kernel": f"k_match<{q}> (xa_match_groups, popcount, {q} queries per lane)",
+                "bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
+                "frac": achieved / VALU_PEAK_OPS, "algorithmic_ops_per_launch": comparisons * HAMMING_OPS_PER_CMP}
+    roofline = dict(head, **{
+        "traffic": k_match_traffic(q),
         "traffic_unit": "bytes per launch (HBM, counter-measured)",
         "algorithmic_bytes_per_launch": algo_bytes,
-        "algorithmic_ops_per_launch": comparisons * HAMMING_OPS_PER_CMP,
         "comparisons_per_launch": comparisons,
         "comparisons_per_s": comparisons / match_s,
-    }
+    })
 
     # warp: algorithmic bytes of the simulate stage (source read once per view, canvas + mask written)
     sim_bytes = 0

@@ -298,8 +298,8 @@ xa_status xa_match_views(const uint8_t* d_desc_a, const int32_t* d_count_a, int3
  * descriptor set (n_views): xa_plan_matches and xa_match_groups reject plans
  * that break either rule with XA_EINVAL, and xa_match_batch checks the views
  * against its view plan.  queries_per_lane selects the matcher variant (the
- * autotuner times them; all give identical results): 0 = choose from
- * n_features, 1, 2 or 4 = the vector-ALU popcount kernel with that many queries
+ * autotuner times them; all give identical results): 0 = the default (the
+ * matrix-core kernel), 1, 2 or 4 = the vector-ALU popcount kernel with that many queries
  * per lane, XA_MATCH_MATRIX = the matrix-core kernel (the +-1 dot product of two
  * descriptors is 256 - 2 x their Hamming distance, contracted exactly in fp4 on
  * MFMA).  Match plans are blobs like view plans (host and device copies). */
