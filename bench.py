@@ -63,6 +63,82 @@ def k_match_traffic(queries_per_lane: int):
     return (fetch * t["fetch_scale"] + write * t["write_scale"]) * 1024.0
 
 
+# HBM traffic of k_warp on one launch over both images' 90 views of the full-size pair (the launch
+# the timed step makes), from the same two --pmc passes and copy calibration as the matcher's.  Valid
+# only for the simulate source it was measured on.
+K_WARP_TRAFFIC = {
+    "sources": ["paper_2503_03479_amd/csrc/simulate.hip", "paper_2503_03479_amd/csrc/internal.h"],
+    "sha256": "c469f8153c22f765b056d1f854f72286720afeb0d6cf3e16064efe5288e07cb6",   # of the sources, concatenated
+    "fetch_scale": 2.0, "write_scale": 1.0,
+    "kib": (109277.0, 67589.0),   # (fetch, write) per launch
+}
+WARP_OPS_PER_PX = 72 + 16         # 64 + 8 multiply-adds of the 8 x 8 sum and the 16 kernel weights per view pixel
+
+
+def k_warp_traffic():
+    import hashlib
+    t = K_WARP_TRAFFIC
+    h = hashlib.sha256()
+    for src in t["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != t["sha256"]:
+        return None
+    fetch, write = t["kib"]
+    return (fetch * t["fetch_scale"] + write * t["write_scale"]) * 1024.0
+
+
+def warp_roofline(case, grid_np, wl, dev, stream, pattern, match_stage, reps: int = 20, warmup: int = 5):
+    """The dominant kernel, k_warp, on exactly the launch of the timed step: one xa_warp_views call over
+    both images' views (one view plan over one sources buffer), its blurred planes made once by
+    xa_blur_views, timed with HIP events on the launch stream around each warp launch inside a
+    step-like sequence of launches.  Algorithmic work per view pixel:
+    the 8 x 8 weighted sum and its 8 row sums (72 multiply-adds) and the 16 kernel weights; algorithmic
+    bytes: each source read once per view (fp32 when blurred, else u8) and the canvas and mask written."""
+    import numpy as np
+    import torch
+    from paper_2503_03479_amd import xaffine as X
+    arena_src = X.SourceArena()
+    ia = arena_src.add(case.A.shape[1], case.A.shape[0])
+    ib = arena_src.add(case.B.shape[1], case.B.shape[0])
+    buf = torch.from_numpy(arena_src.pack({ia: case.A, ib: np.ascontiguousarray(case.B)})).to(dev)
+    params = np.concatenate([grid_np, grid_np])
+    plan = X.plan_views(arena_src.table(), [ia] * len(grid_np) + [ib] * len(grid_np), params, wl["n_levels"], 1.2,
+                        wl["n_features"], wl["fast"])
+    arena = torch.zeros(plan.arena_bytes, dtype=torch.uint8, device=dev)
+    mask = torch.zeros(plan.arena_bytes, dtype=torch.uint8, device=dev)
+    ws = X._empty(X.lib().xa_simulate_workspace_size(plan.host_ptr()), dev)
+    X.blur_views(plan, buf, ws)
+    X.warp_views(plan, buf, arena, mask, ws)
+    torch.cuda.synchronize()
+    ext_ws = X._empty(X.lib().xa_extract_workspace_size(plan.host_ptr()), dev)
+    # each timed warp launch sits in a whole step's sequence of launches (blur, warp, ORB, matching),
+    # as in the timed region: warps launched back to back alone run hotter and slower.  Only the
+    # warp launches sit between the events.
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps + warmup)]
+    for e0, e1 in ev:
+        X.blur_views(plan, buf, ws)
+        e0.record(stream)
+        X.warp_views(plan, buf, arena, mask, ws)
+        e1.record(stream)
+        X.extract_orb(plan, arena, mask, pattern, ws=ext_ws)
+        match_stage()
+    torch.cuda.synchronize()
+    t = sum(e0.elapsed_time(e1) for e0, e1 in ev[warmup:]) / reps / 1e3      # the first `warmup` untimed
+    v = plan.views
+    px = int((v["width"].astype(np.int64) * v["height"]).sum())
+    src_px = np.array([int(d["width"]) * int(d["height"]) for d in arena_src.table()])[v["source"]]
+    algo_bytes = int(np.where(v["sigma"] > 0, 4 * src_px, src_px).sum()) + 2 * px
+    ops = WARP_OPS_PER_PX * px
+    return {"kernel": "k_warp (xa_warp_views over both images' 90 views, one launch as in the timed step)",
+            "bound": "alu", "achieved": ops / t / 1e12, "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
+            "frac": ops / t / VALU_PEAK_OPS, "traffic": k_warp_traffic(),
+            "traffic_unit": "bytes per launch (HBM, counter-measured)",
+            "algorithmic_ops_per_launch": ops, "algorithmic_bytes_per_launch": algo_bytes,
+            "view_px_per_launch": px, "ms_per_launch": t * 1e3,
+            "hbm_GBps": algo_bytes / t / 1e9, "hbm_frac": algo_bytes / t / HBM_PEAK_BPS}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -455,7 +531,7 @@ def main():
         head = {"kernel": f"k_match<{q}> (xa_match_groups, popcount, {q} queries per lane)",
                 "bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
                 "frac": achieved / VALU_PEAK_OPS, "algorithmic_ops_per_launch": comparisons * HAMMING_OPS_PER_CMP}
-    roofline = dict(head, **{
+    matcher = dict(head, **{
         "traffic": k_match_traffic(q),
         "traffic_unit": "bytes per launch (HBM, counter-measured)",
         "algorithmic_bytes_per_launch": algo_bytes,
@@ -471,6 +547,8 @@ def main():
         for v in p.views:
             sim_bytes += (4 * src if v["sigma"] > 0 else src) + 2 * int(v["width"]) * int(v["height"])
     n_views = pa.n_views + pb.n_views
+    roofline = warp_roofline(case, grid_np, wl, dev, stream, pattern, match_stage)
+    del st
     value = 1e3 / ms_per_step
     out = {
         "metric": "image pairs/s, full parameter-search path (simulate 45 views per image, ORB, 45x45 "
@@ -497,6 +575,7 @@ def main():
         "views_per_s": n_views * value,
         "stage_ms": stage_ms,
         "roofline": roofline,
+        "matcher": matcher,
         "simulate_GBps": sim_bytes / (stage_ms["simulate"] / 1e3) / 1e9,
         "simulate_frac_hbm": sim_bytes / (stage_ms["simulate"] / 1e3) / HBM_PEAK_BPS,
         "best_pair": best,
@@ -507,7 +586,7 @@ def main():
         "host_cpu": platform.processor() or platform.machine(),
         "host_cores": os.cpu_count(),
     }
-    del st, run
+    del run
     if args.batch_pairs > 0:
         out["batched"] = batched_leg(args, dev, pattern, raw, gen_s)
     if args.crops > 0:

@@ -239,6 +239,20 @@ xa_status xa_simulate_views(const void* plan_host, const void* plan_dev, const u
                             uint8_t* d_arena, uint8_t* d_mask, float* d_values,
                             void* d_ws, size_t ws_bytes, hipStream_t stream);
 
+/* The two stages of xa_simulate_views, callable one at a time (to time or to
+ * repeat one of them).  xa_blur_views writes the blurred fp32 planes of the
+ * plan's blurred views into the workspace; xa_warp_views resamples every view
+ * from those planes (unblurred views read d_sources directly) and writes what
+ * xa_simulate_views writes.  xa_warp_views requires a workspace that
+ * xa_blur_views filled for the same plan and sources, untouched since; the
+ * workspace, arguments and errors are those of xa_simulate_views
+ * (xa_blur_views takes no arena or mask). */
+xa_status xa_blur_views(const void* plan_host, const void* plan_dev, const uint8_t* d_sources, void* d_ws,
+                        size_t ws_bytes, hipStream_t stream);
+xa_status xa_warp_views(const void* plan_host, const void* plan_dev, const uint8_t* d_sources,
+                        uint8_t* d_arena, uint8_t* d_mask, float* d_values,
+                        void* d_ws, size_t ws_bytes, hipStream_t stream);
+
 /* Scale stage for the scale parameter of the sampling group (Sec. III.B).  A
  * job resamples src into dst at factor s: for s < 1 an isotropic anti-alias
  * Gaussian of standard deviation 0.8 sqrt(1/s^2 - 1) first, then Lanczos-4

@@ -26,6 +26,16 @@ inline int warp_tile_w(double t, double s) {
     const double c = t / s;
     return c < 2.0 ? 16 : (c < 8.0 ? 8 : 4);
 }
+// The hardware deals consecutive blocks of a launch round-robin to the 8 XCDs, each with its
+// own L2.  For kernels whose neighbouring tiles share cache lines (narrow warp tiles), this
+// remap gives each XCD one contiguous run of tiles instead: block b, the i-th on XCD b % 8,
+// takes tile start(b % 8) + i, where XCD x owns the run of n / 8 (+1 for x < n % 8) tiles
+// starting at start(x).  A bijection on [0, n).
+constexpr int kXcds = 8;
+__host__ __device__ inline int xcd_contiguous(int b, int n) {
+    const int x = b % kXcds, i = b / kXcds, q = n / kXcds, r = n % kXcds;
+    return x * q + (x < r ? x : r) + i;
+}
 constexpr int kBorder = 22;                 // detection border (rotated BRIEF tests reach 21 px)
 constexpr size_t kAlign = 256;
 
@@ -161,8 +171,10 @@ ExtractWs extract_ws_layout(const xa_plan_header* h);
 size_t simulate_ws_bytes(const xa_plan_header* h);
 
 // Stage launchers (device work only, arguments already validated).
+constexpr int kStageBlur = 1, kStageWarp = 2;   // launch_simulate stage mask
 xa_status launch_simulate(const PlanView& ph, const PlanView& pd, const uint8_t* sources,
-                          uint8_t* arena, uint8_t* mask, float* values, float* blurred, hipStream_t st);
+                          uint8_t* arena, uint8_t* mask, float* values, float* blurred, hipStream_t st,
+                          int stages = kStageBlur | kStageWarp);
 xa_status launch_extract(const PlanView& ph, const PlanView& pd, uint8_t* arena, uint8_t* mask,
                          const int8_t* pattern, xa_keypoint* kp, uint8_t* desc, int32_t* count,
                          uint8_t* ws, hipStream_t st);

@@ -249,7 +249,7 @@ __global__ void __launch_bounds__(kWarpThreads) k_warp(const uint8_t* __restrict
                                                        const int32_t* __restrict__ prefix, uint8_t* __restrict__ arena,
                                                        uint8_t* __restrict__ mask, float* __restrict__ values) {
     __shared__ float tile[kWarpLds];
-    const int b = blockIdx.x;
+    const int b = xcd_contiguous(blockIdx.x, gridDim.x);
     const int vi = find_segment_wave(prefix, n_views, b);
     const xa_view_desc& v = views[vi];
     const int W = v.src_w, H = v.src_h, pitch = v.src_pitch;
@@ -466,9 +466,9 @@ xa_status hip_fail(int err, const char* what) {
 }
 
 xa_status launch_simulate(const PlanView& ph, const PlanView& pd, const uint8_t* sources,
-                          uint8_t* arena, uint8_t* mask, float* values, float* blurred, hipStream_t st) {
+                          uint8_t* arena, uint8_t* mask, float* values, float* blurred, hipStream_t st, int stages) {
     const xa_plan_header* h = ph.h;
-    if (h->n_blur > 0) {
+    if ((stages & kStageBlur) && h->n_blur > 0) {
         const int tiles = ph.blur_prefix[h->n_blur];
         // LDS sized for the largest footprint among the blurred views (tiles away from the border
         // have the same footprint size as the first); larger ones fall back to global reads
@@ -484,7 +484,7 @@ xa_status launch_simulate(const PlanView& ph, const PlanView& pd, const uint8_t*
         if (e != hipSuccess) return hip_fail(e, "blur launch");
     }
     const int tiles = ph.warp_prefix[h->n_views];
-    if (tiles > 0) {
+    if ((stages & kStageWarp) && tiles > 0) {
         hipLaunchKernelGGL(k_warp, dim3(tiles), dim3(kWarpThreads), 0, st, sources, blurred, pd.views, h->n_views,
                            pd.warp_prefix, arena, mask, values);
         hipError_t e = hipGetLastError();
@@ -503,20 +503,43 @@ extern "C" size_t xa_simulate_workspace_size(const void* plan_host) {
     return simulate_ws_bytes(p.h);
 }
 
-extern "C" xa_status xa_simulate_views(const void* plan_host, const void* plan_dev, const uint8_t* d_sources,
-                                       uint8_t* d_arena, uint8_t* d_mask, float* d_values, void* d_ws,
-                                       size_t ws_bytes, hipStream_t stream) {
+static xa_status simulate_entry(const void* plan_host, const void* plan_dev, const uint8_t* d_sources,
+                                uint8_t* d_arena, uint8_t* d_mask, float* d_values, void* d_ws, size_t ws_bytes,
+                                hipStream_t stream, int stages) {
     PlanView ph;
     xa_status s = plan_host_view(plan_host, &ph);
     if (s != XA_OK) return s;
-    if (!plan_dev || !d_sources || !d_arena || !d_mask) return fail(XA_EINVAL, "NULL device pointer");
-    if ((reinterpret_cast<uintptr_t>(d_arena) | reinterpret_cast<uintptr_t>(d_mask)) % 128)
-        return fail(XA_EINVAL, "arena and mask must be 128-byte aligned");
+    if (!plan_dev || !d_sources) return fail(XA_EINVAL, "NULL device pointer");
+    if (stages & kStageWarp) {
+        if (!d_arena || !d_mask) return fail(XA_EINVAL, "NULL device pointer");
+        if ((reinterpret_cast<uintptr_t>(d_arena) | reinterpret_cast<uintptr_t>(d_mask)) % 128)
+            return fail(XA_EINVAL, "arena and mask must be 128-byte aligned");
+    }
     const size_t need = simulate_ws_bytes(ph.h);
     if (ws_bytes < need) return fail(XA_ECAPACITY, "simulate workspace needs %zu bytes, got %zu", need, ws_bytes);
     if (need > 0 && (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) % kAlign)))
         return fail(XA_EINVAL, "workspace must be non-NULL and 256-byte aligned");
     const PlanView pd = plan_dev_view(plan_host, plan_dev);
-    s = launch_simulate(ph, pd, d_sources, d_arena, d_mask, d_values, static_cast<float*>(d_ws), stream);
+    s = launch_simulate(ph, pd, d_sources, d_arena, d_mask, d_values, static_cast<float*>(d_ws), stream, stages);
     return s == XA_OK ? ok() : s;
+}
+
+extern "C" xa_status xa_simulate_views(const void* plan_host, const void* plan_dev, const uint8_t* d_sources,
+                                       uint8_t* d_arena, uint8_t* d_mask, float* d_values, void* d_ws,
+                                       size_t ws_bytes, hipStream_t stream) {
+    return simulate_entry(plan_host, plan_dev, d_sources, d_arena, d_mask, d_values, d_ws, ws_bytes, stream,
+                          kStageBlur | kStageWarp);
+}
+
+extern "C" xa_status xa_blur_views(const void* plan_host, const void* plan_dev, const uint8_t* d_sources, void* d_ws,
+                                   size_t ws_bytes, hipStream_t stream) {
+    return simulate_entry(plan_host, plan_dev, d_sources, nullptr, nullptr, nullptr, d_ws, ws_bytes, stream,
+                          kStageBlur);
+}
+
+extern "C" xa_status xa_warp_views(const void* plan_host, const void* plan_dev, const uint8_t* d_sources,
+                                   uint8_t* d_arena, uint8_t* d_mask, float* d_values, void* d_ws, size_t ws_bytes,
+                                   hipStream_t stream) {
+    return simulate_entry(plan_host, plan_dev, d_sources, d_arena, d_mask, d_values, d_ws, ws_bytes, stream,
+                          kStageWarp);
 }

@@ -87,6 +87,9 @@ _SIGS = {
     "xa_simulate_workspace_size": (_c.c_size_t, [_c.c_void_p]),
     "xa_simulate_views": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                      _c.c_void_p, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "xa_blur_views": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "xa_warp_views": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                 _c.c_void_p, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
     "xa_extract_workspace_size": (_c.c_size_t, [_c.c_void_p]),
     "xa_extract_orb": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                   _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
@@ -384,6 +387,19 @@ def simulate_views(plan: Plan, src, values: bool = False, ws=None):
     _check(lib().xa_simulate_views(plan.host_ptr(), _ptr(plan.device(dev)), _ptr(src), _ptr(arena),
                                    _ptr(mask), _ptr(vals), _ptr(ws), ws.numel(), _stream()))
     return (arena, mask, vals) if values else (arena, mask)
+
+
+def blur_views(plan: Plan, src, ws):
+    """First stage of simulate_views: the blurred fp32 planes of the plan's blurred views, into ws
+    (xa_simulate_workspace_size bytes)."""
+    _check(lib().xa_blur_views(plan.host_ptr(), _ptr(plan.device(src.device)), _ptr(src), _ptr(ws), ws.numel(),
+                               _stream()))
+
+
+def warp_views(plan: Plan, src, arena, mask, ws, values=None):
+    """Second stage of simulate_views: every view resampled from the planes blur_views left in ws."""
+    _check(lib().xa_warp_views(plan.host_ptr(), _ptr(plan.device(src.device)), _ptr(src), _ptr(arena), _ptr(mask),
+                               _ptr(values), _ptr(ws), ws.numel(), _stream()))
 
 
 def extract_orb(plan: Plan, arena, mask, pattern, ws=None):

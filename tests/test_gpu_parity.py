@@ -115,6 +115,23 @@ def test_identity_view_is_exact(dev):
     assert plan.level_image(mask.cpu().numpy(), 0, 0).all()
 
 
+def test_blur_then_warp_equals_simulate(dev, tiny):
+    say("case: xa_blur_views then xa_warp_views (twice) equal xa_simulate_views byte for byte")
+    rows, params = _params(2, [(2.2, 1.0, 0.5, 1.1)])
+    plan = X.plan_image(tiny.A.shape[1], tiny.A.shape[0], params, 3, 1.2, 300, 20)
+    src = torch.from_numpy(np.ascontiguousarray(tiny.A)).to(dev)
+    arena, mask, vals = X.simulate_views(plan, src, values=True)
+    ws = X._empty(X.lib().xa_simulate_workspace_size(plan.host_ptr()), dev)
+    a2 = torch.zeros_like(arena)
+    m2 = torch.zeros_like(mask)
+    v2 = torch.zeros_like(vals)
+    X.blur_views(plan, src, ws)
+    for _ in range(2):                       # the planes stay valid: the warp can be repeated
+        X.warp_views(plan, src, a2, m2, ws, v2)
+        torch.cuda.synchronize()
+        assert torch.equal(a2, arena) and torch.equal(m2, mask) and torch.equal(v2, vals)
+
+
 def _gpu_extract_from_views(plan, views_u8, masks, pattern, dev):
     arena = np.zeros(plan.arena_bytes, np.uint8)
     mask = np.zeros(plan.arena_bytes, np.uint8)

@@ -138,6 +138,13 @@ def test_device_calls_validate_before_launch(L):
     assert st == X.XA_ECAPACITY
     assert L.xa_match_views(256, 256, 0, 256, 256, 1, 100, 4, 5, 256, 256, 256, None) == X.XA_EINVAL
     assert L.xa_match_views(256, 256, 1, 256, 256, 1, 100, 4, 0, 256, 256, 256, None) == X.XA_EINVAL
+    # the two simulate stages: NULL pointers, a short workspace, a blob that is not a plan
+    assert L.xa_blur_views(hp, hp, None, 256, 1 << 30, None) == X.XA_EINVAL
+    assert L.xa_blur_views(hp, hp, 256, 256, 0, None) == X.XA_ECAPACITY
+    assert L.xa_warp_views(hp, hp, 256, None, 256, None, 256, 1 << 30, None) == X.XA_EINVAL
+    assert L.xa_warp_views(hp, hp, 256, 256, 256, None, 256, 0, None) == X.XA_ECAPACITY
+    junk = np.zeros(256, np.uint8)
+    assert L.xa_warp_views(junk.ctypes.data, hp, 256, 256, 256, None, 256, 1 << 30, None) == X.XA_EINVAL
 
 
 def test_match_plan_rules():
