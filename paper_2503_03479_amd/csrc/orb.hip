@@ -68,7 +68,8 @@ __device__ __forceinline__ int resample_index(int d, int n_dst, int n_src) {
     return (a << 11) | w;
 }
 
-constexpr int kPyrLW = 640;        // LDS row stride of the staged source rows (bytes)
+constexpr int kPyrLW = 352;        // LDS row stride of the staged source rows (bytes): 256 output columns at
+                                   // scale <= 1.25 span <= 322 source columns, plus 15 of 16-byte alignment
 constexpr int kPyrLH = 24;         // staged source rows (16 output rows span at most 15 * 1.25 + 2)
 
 // Level l of every view from level l-1: (sum_{2x2} wy wx pix + 2^21) >> 22; the content
