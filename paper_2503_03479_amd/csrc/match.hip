@@ -266,35 +266,24 @@ k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ coun
             }
             const uint4* a = tr + tt * 4 * 64 + lane;
             const v8i_t A0 = operand(a[0]), A1 = operand(a[64]), A2 = operand(a[128]), A3 = operand(a[192]);
-            // all chains first (tiles past nq compute unused columns), then the updates; the
-            // scheduling groups below interleave each update with the MFMAs of later chains
-            v16f_t acc[kMxQT];
+            // each chain, then its updates (tiles past nq compute unused columns)
 #pragma unroll
             for (int qt = 0; qt < kMxQT; ++qt) {
-                acc[qt] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A0, operand(B[qt][0]), ci, 4, 4, 0, 127, 0, 127);
-                acc[qt] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A1, operand(B[qt][1]), acc[qt], 4, 4, 0, 127, 0, 127);
-                acc[qt] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A2, operand(B[qt][2]), acc[qt], 4, 4, 0, 127, 0, 127);
-                acc[qt] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A3, operand(B[qt][3]), acc[qt], 4, 4, 0, 127, 0, 127);
-            }
-#pragma unroll
-            for (int qt = 0; qt < kMxQT; ++qt) {
+                v16f_t acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A0, operand(B[qt][0]), ci, 4, 4, 0, 127, 0, 127);
+                acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A1, operand(B[qt][1]), acc, 4, 4, 0, 127, 0, 127);
+                acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A2, operand(B[qt][2]), acc, 4, 4, 0, 127, 0, 127);
+                acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A3, operand(B[qt][3]), acc, 4, 4, 0, 127, 0, 127);
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     // keys are positive floats, whose order is their bit patterns' order: the
                     // float median of three (a builtin, so the compiler inserts the wait states
                     // an MFMA result needs before a VALU read) updates the second largest and an
                     // integer max the largest
-                    const uint32_t key = __float_as_uint(acc[qt][r]);
-                    m2[qt] = __float_as_uint(__builtin_amdgcn_fmed3f(__uint_as_float(m1[qt]), acc[qt][r],
+                    const uint32_t key = __float_as_uint(acc[r]);
+                    m2[qt] = __float_as_uint(__builtin_amdgcn_fmed3f(__uint_as_float(m1[qt]), acc[r],
                                                                      __uint_as_float(m2[qt])));
                     m1[qt] = max(m1[qt], key);
                 }
-            }
-            __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);        // chains 0 and 1
-#pragma unroll
-            for (int g = 0; g < 8; ++g) {
-                __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);    // updates ...
-                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);    // ... beside chains 2 and 3
             }
         }
     }
