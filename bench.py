@@ -45,9 +45,9 @@ MATCH_MATRIX = -1                 # matcher variant code of the matrix-core kern
 # file reports null.
 K_MATCH_TRAFFIC = {
     "source": "paper_2503_03479_amd/csrc/match.hip",
-    "sha256": "0637d015ae5ed3e16ef4e52ed86efccc6675aaf67e1fbaf16f40af5c13583037",
+    "sha256": "ce036939fa848ac7494d1f4773f492a5e1412a42958b5b2f9449ef3547c9ad05",
     "fetch_scale": 2.0, "write_scale": 1.0,
-    "kib": {-1: (8095.6, 15619.2), 1: (6660.8, 15745.8), 2: (8041.2, 15619.2), 4: (10802.5, 15555.9)},  # (fetch, write)
+    "kib": {-1: (8095.8, 15619.2)},  # variant -> (fetch, write), variants measured on this source only
 }
 
 
