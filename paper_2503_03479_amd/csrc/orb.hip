@@ -354,13 +354,16 @@ __global__ void __launch_bounds__(256) k_fast(const uint8_t* __restrict__ fast_f
         score[e] = int16_t(fast_score_lds(img + (sy - 1 + kFH) * kFLW + sx - 1 + 16, kFLW, T));
     }
     __syncthreads();
-    // ---- NMS + content filter -> block candidate list
+    // ---- NMS + content filter -> block candidate list.  Only queued pixels can score above T
+    // (every other pixel keeps kNegV), so the queue, compacted, is walked instead of the tile.
     const uint8_t* Mk = mask + d.offset;
-    for (int e = t; e < kFastTX * kFastTY; e += 256) {
-        const int ty = e >> 6, tx = e & 63;
+    for (int q = t; q < nq; q += 256) {
+        const int e = queue[q];
+        const int ty = e / kSW - 1, tx = e - (e / kSW) * kSW - 1;       // tile coordinates
+        if (tx < 0 || tx >= kFastTX || ty < 0 || ty >= kFastTY) continue;   // ring pixel
         const int x = x0 + tx, y = y0 + ty;
         if (x < kBorder || x >= W - kBorder || y < kBorder || y >= H - kBorder) continue;
-        const int vp = score[(ty + 1) * kSW + tx + 1];
+        const int vp = score[e];
         if (vp <= T) continue;
         bool keep = true;
 #pragma unroll
@@ -368,7 +371,7 @@ __global__ void __launch_bounds__(256) k_fast(const uint8_t* __restrict__ fast_f
 #pragma unroll
             for (int dx = -1; dx <= 1; ++dx) {
                 if (dx == 0 && dy == 0) continue;
-                const int vq = score[(ty + 1 + dy) * kSW + tx + 1 + dx];
+                const int vq = score[e + dy * kSW + dx];
                 const bool q_after = dy > 0 || (dy == 0 && dx > 0);
                 keep = keep && (vp > vq || (vp == vq && q_after));
             }
