@@ -113,6 +113,17 @@ __global__ void __launch_bounds__(256) k_pyr(const xa_level_desc* __restrict__ l
     const int tx = t & 63, ty = t >> 6;
     const int xb = X0 + 4 * tx;
     if (xb >= d.width) return;
+    // the thread's 4 source columns and weights, the same for all of its rows
+    const int nk = min(4, d.width - xb);
+    int cx0[4], cx1[4], cw0[4], cw1[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int cv = k < nk ? scol[4 * tx + k] : 0;
+        cx0[k] = cv >> 11;
+        cw1[k] = cv & 2047;
+        cw0[k] = 2048 - cw1[k];
+        cx1[k] = min(cx0[k] + 1, p.width - 1);
+    }
     for (int rr = 0; rr < kPyrTY / 4; ++rr) {
         const int yr = ty + 4 * rr;
         const int y = Y0 + yr;
@@ -122,9 +133,8 @@ __global__ void __launch_bounds__(256) k_pyr(const xa_level_desc* __restrict__ l
         uint32_t pix = 0, msk = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            if (xb + k >= d.width) break;
-            const int cv = scol[4 * tx + k];
-            const int x0 = cv >> 11, wx1 = cv & 2047, wx0 = 2048 - wx1, x1 = min(x0 + 1, p.width - 1);
+            if (k >= nk) break;
+            const int x0 = cx0[k], wx1 = cw1[k], wx0 = cw0[k], x1 = cx1[k];
             int p00, p01, p10, p11, m;
             if (staged) {
                 const uint8_t* r0 = simg + (y0 - r_lo) * kPyrLW - cb;
