@@ -288,6 +288,19 @@ def test_match_exact_large_blocks(dev):
     _check_match(da, db, 2000, dev, "random N=2000")
 
 
+def test_match_exact_at_the_largest_n(dev):
+    say("case: match at N=4096 (the largest): a best match at train index 4095, a train view of 4096 "
+        "equal rows (every distance tied: index 0 wins), distances 0 and 256")
+    g = np.random.default_rng(23)
+    N = 4096
+    da = [g.integers(0, 256, (N, 32)).astype(np.uint8), g.integers(0, 256, (33, 32)).astype(np.uint8)]
+    db = [g.integers(0, 256, (N, 32)).astype(np.uint8), np.repeat(g.integers(0, 256, (1, 32)), N, 0).astype(np.uint8)]
+    db[0][N - 1] = da[0][0]                          # distance 0 at the last index
+    da[0][1] = db[1][0]                              # equal to every row of train view 1
+    da[1][0] = ~db[1][0]                             # distance 256 to every row of train view 1
+    _check_match(da, db, N, dev, "random N=4096")
+
+
 def test_match_exact_on_oracle_features(dev, tiny):
     say("case: match oracle ORB descriptors of the tiny pair (all 144 view pairs)")
     rows, _ = _params(2)
