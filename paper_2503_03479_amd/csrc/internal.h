@@ -165,8 +165,10 @@ PlanView plan_dev_view(const void* blob_host, const void* blob_dev);
 
 // Workspace layouts.
 struct ExtractWs {
-    size_t smooth, cand, cand_count, harris, stage, stage_count, total;
+    size_t smooth, cand, cand_count, harris, stage, stage_count, steer, total;
 };
+constexpr int kOrientBins = 30;             // orientation bins of the steered BRIEF pattern
+constexpr int kBriefTests = 256;            // binary tests per descriptor
 ExtractWs extract_ws_layout(const xa_plan_header* h);
 size_t simulate_ws_bytes(const xa_plan_header* h);
 

@@ -644,6 +644,21 @@ __device__ __forceinline__ int rnd20(int v) {
     return v < 0 ? -r : r;
 }
 
+// The rotated test offsets of the BRIEF pattern for every orientation bin: entry (b, i) packs
+// (ax, ay, bx, by) of test i steered by bin b as four int8 (each within +-21: the pattern's
+// coordinates are clamped to [-15, 15]).  One block per bin, one thread per test.
+__global__ void __launch_bounds__(kBriefTests) k_steer(const int8_t* __restrict__ pattern, uint32_t* __restrict__ steer) {
+    const int b = blockIdx.x, i = threadIdx.x;
+    const int Cb = c_cos[b], Sb = c_sin[b];
+    const int x1 = clampi(pattern[4 * i], -15, 15), y1 = clampi(pattern[4 * i + 1], -15, 15);
+    const int x2 = clampi(pattern[4 * i + 2], -15, 15), y2 = clampi(pattern[4 * i + 3], -15, 15);
+    const int ax = rnd20(x1 * Cb - y1 * Sb), ay = rnd20(x1 * Sb + y1 * Cb);
+    const int bx = rnd20(x2 * Cb - y2 * Sb), by = rnd20(x2 * Sb + y2 * Cb);
+    steer[b * kBriefTests + i] = uint32_t(uint8_t(ax)) | (uint32_t(uint8_t(ay)) << 8) | (uint32_t(uint8_t(bx)) << 16) |
+                                 (uint32_t(uint8_t(by)) << 24);
+}
+
+
 // One wave per keypoint: intensity-centroid moments over the radius-15 disk, integer
 // argmax over the 30 bins, then 256 steered binary tests on the smoothed level,
 // packed four 64-bit ballots at a time.  Keypoints are written in canonical order.
@@ -652,7 +667,7 @@ __global__ void __launch_bounds__(256) k_orient_brief(const xa_view_desc* __rest
                                                       int n_features, const uint8_t* __restrict__ arena,
                                                       const uint8_t* __restrict__ smooth, const int4* __restrict__ stage,
                                                       const int32_t* __restrict__ stage_count,
-                                                      const int8_t* __restrict__ pattern, xa_keypoint* __restrict__ kp,
+                                                      const uint32_t* __restrict__ steer, xa_keypoint* __restrict__ kp,
                                                       uint8_t* __restrict__ desc, int32_t* __restrict__ count) {
     const int v = blockIdx.y;
     const int lane = threadIdx.x & 63;
@@ -715,17 +730,15 @@ __global__ void __launch_bounds__(256) k_orient_brief(const xa_view_desc* __rest
         if (os > sc || (os == sc && ob < bk)) { sc = os; bk = ob; }
     }
     const int bin = bk;
-    const int Cb = c_cos[bin], Sb = c_sin[bin];
     const uint8_t* Sm = smooth + d.offset;
+    const uint32_t* st = steer + bin * kBriefTests;
     unsigned long long words[4];
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-        const int i = g * 64 + lane;
-        // pattern coordinates are clamped to the documented [-15, 15], so every test stays inside the border
-        const int x1 = clampi(pattern[4 * i], -15, 15), y1 = clampi(pattern[4 * i + 1], -15, 15);
-        const int x2 = clampi(pattern[4 * i + 2], -15, 15), y2 = clampi(pattern[4 * i + 3], -15, 15);
-        const int ax = rnd20(x1 * Cb - y1 * Sb), ay = rnd20(x1 * Sb + y1 * Cb);
-        const int bx = rnd20(x2 * Cb - y2 * Sb), by = rnd20(x2 * Sb + y2 * Cb);
+        // test g * 64 + lane steered by the bin (k_steer; offsets within +-21, inside the border)
+        const uint32_t pk = st[g * 64 + lane];
+        const int ax = int(int8_t(pk & 0xFF)), ay = int(int8_t((pk >> 8) & 0xFF));
+        const int bx = int(int8_t((pk >> 16) & 0xFF)), by = int(int8_t(pk >> 24));
         const bool bit = Sm[size_t(y + ay) * pitch + x + ax] < Sm[size_t(y + by) * pitch + x + bx];
         words[g] = __ballot(bit);
     }
@@ -775,8 +788,10 @@ xa_status launch_extract(const PlanView& ph, const PlanView& pd, uint8_t* arena,
                            h->fast_threshold, arena, mask, cand, cand_count, smooth);
     hipLaunchKernelGGL(k_select, dim3(nvl), dim3(kSelThreads), 0, st, pd.levels, N, cand, cand_count, stage,
                        stage_count);
+    uint32_t* steer = reinterpret_cast<uint32_t*>(ws + w.steer);
+    hipLaunchKernelGGL(k_steer, dim3(kOrientBins), dim3(kBriefTests), 0, st, pattern, steer);
     hipLaunchKernelGGL(k_orient_brief, dim3((N + 3) / 4, nv), dim3(256), 0, st, pd.views, pd.levels, L, N, arena,
-                       smooth, stage, stage_count, pattern, kp, desc, count);
+                       smooth, stage, stage_count, steer, kp, desc, count);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "extract launch");
     return XA_OK;

@@ -75,6 +75,7 @@ ExtractWs extract_ws_layout(const xa_plan_header* h) {
     w.harris = o;
     w.stage = o;       o = align_up(o + size_t(h->n_views) * h->n_features * 16);
     w.stage_count = o; o = align_up(o + nvl * 4);
+    w.steer = o;       o = align_up(o + size_t(kOrientBins) * kBriefTests * 4);
     w.total = o;
     return w;
 }
