@@ -927,8 +927,8 @@ def refine_tilt(img, target, params, grid, target_mask=None, steps: int = 20, lr
     steps on (log t, phi) start from it, coarse to fine (crop and target smoothed by a
     Gaussian of sigma 4 px for the first half of the steps and 1 px for the rest,
     unless `sigmas` gives one sigma per step), with the other four parameters held.
-    The grid point is the judge: a crop keeps its refined (t, phi) only if the refined
-    loss on the unsmoothed crops is lower.
+    The grid point decides: a crop keeps its refined (t, phi) only if the refined loss on
+    the unsmoothed crops is lower.
     Returns (params [n, 6], grid_loss [n], refined_loss [n])."""
     import torch
     n = img.shape[0]
