@@ -6,6 +6,12 @@ Sec. III.B: simulate views of the images over the (t, phi) grid, run ORB on
 every view, match views with a brute-force Hamming matcher and keep the view
 pair with the most matches; the matched points of that pair are mapped back
 to the original images (Sec. IV.B evaluates them with eqs. (5)-(6)).
+
+Parity status: pinned.  The composed stages are pinned in their own modules; the back-map is
+pinned by closed forms (the identity view maps level-0 keypoints to themselves, a level's pixel
+centres span the view symmetrically, the scale-stage factor maps u to 2u + 1/2 at s = 1/2) and
+by the view map (a back-mapped point maps forward onto its keypoint); end to end, the tiny pair's
+matches agree with the known homography.
 """
 from __future__ import annotations
 
