@@ -251,24 +251,43 @@ __global__ void __launch_bounds__(256) k_dw_bwd(const float* __restrict__ img, c
                                                 double* __restrict__ partial) {
     __shared__ CropMap sC;
     __shared__ double sRed[4][6];
-    __shared__ float accum[GIMG ? kDwLds : 1];
+    __shared__ float sMax[4];
+    // the tile's image-gradient box, accumulated in LDS as fixed point (see below)
+    __shared__ int accum[GIMG ? kDwLds : 1];
     const int crop = blockIdx.x / tiles, tl = blockIdx.x - crop * tiles;
     if (threadIdx.x == 0) crop_map(params[crop], GPAR, &sC, w, h);
-    __syncthreads();
     const int tyi = tl / tiles_x, txi = tl - tyi * tiles_x;
     const int tx0 = txi * kDwTX, ty0 = tyi * kDwTY;
-    const Box bx = tile_box(sC, tx0, ty0, w, h);
-    const int bw = bx.x1 - bx.x0 + 1, bh = bx.y1 - bx.y0 + 1;
-    const bool use_acc = GIMG && bw > 0 && bh > 0 && bw * bh <= kDwLds;
-    if (use_acc)
-        for (int e = threadIdx.x; e < bw * bh; e += 256) accum[e] = 0.0f;
-    __syncthreads();
     const size_t cbase = size_t(crop) * h * w;
     const int x = tx0 + int(threadIdx.x % kDwTX), y = ty0 + int(threadIdx.x / kDwTX);
+    const float g = (x < w && y < h) ? gout[cbase + size_t(y) * w + x] : 0.0f;
+    if (GIMG) {     // m = max |g| over the tile (infinite if some g is NaN)
+        float a = g != g ? INFINITY : fabsf(g);
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) a = fmaxf(a, __shfl_xor(a, off));
+        if ((threadIdx.x & 63) == 0) sMax[threadIdx.x >> 6] = a;
+    }
+    __syncthreads();
+    const Box bx = tile_box(sC, tx0, ty0, w, h);
+    const int bw = bx.x1 - bx.x0 + 1, bh = bx.y1 - bx.y0 + 1;
+    // Integer LDS atomics run several times faster than float ones, so the box sums are kept
+    // in int32 units of 1/S, S = 2^(29 - k) with 2^k <= 1024 m < 2^(k+1): one output pixel adds
+    // at most |g| (sum |wx| / |sum wx|) (sum |wy| / |sum wy|) < 4 |g| to a box pixel (clamped
+    // taps included) and at most 256 output pixels reach it, so every sum stays below 2^30.
+    // Rounding each contribution to 1/S costs at most 2^-20 m.  A tile whose m is not finite
+    // keeps float atomics (the box is then reused as float); a tile whose m is tiny keeps S at
+    // 2^125.
+    const float m = GIMG ? fmaxf(fmaxf(sMax[0], sMax[1]), fmaxf(sMax[2], sMax[3])) : 0.0f;
+    const bool fixed = GIMG && isfinite(1024.0f * m);
+    // k is held at -96 or above so that S stays a finite float for tiny gradients
+    const float scale = fixed && m > 0.0f ? ldexpf(1.0f, 29 - max(ilogbf(1024.0f * m), -96)) : 1.0f;
+    const bool use_acc = GIMG && bw > 0 && bh > 0 && bw * bh <= kDwLds;
+    if (use_acc)
+        for (int e = threadIdx.x; e < bw * bh; e += 256) accum[e] = 0;
+    __syncthreads();
     double gp[6] = {0, 0, 0, 0, 0, 0};
     if (x < w && y < h) {
         const Sample S = sample_point(sC, x, y, w, h);
-        const float g = gout[cbase + size_t(y) * w + x];
         if (S.valid && g != 0.0f) {
             const double fx0 = floor(S.px), fy0 = floor(S.py);
             const int ix = int(fx0), iy = int(fy0);
@@ -299,8 +318,13 @@ __global__ void __launch_bounds__(256) k_dw_bwd(const float* __restrict__ img, c
                 }
                 if (GIMG) {
                     const float gj = gn * wy[j];
-                    if (use_acc) {
-                        float* ar = accum + (row - bx.y0) * bw - bx.x0;
+                    if (use_acc && fixed) {
+                        int* ar = accum + (row - bx.y0) * bw - bx.x0;
+                        const float gs = gj * scale;
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) atomicAdd(ar + cols[i], int(rintf(gs * wx[i])));
+                    } else if (use_acc) {
+                        float* ar = reinterpret_cast<float*>(accum) + (row - bx.y0) * bw - bx.x0;
 #pragma unroll
                         for (int i = 0; i < 8; ++i) atomicAdd(ar + cols[i], gj * wx[i]);
                     } else {
@@ -332,8 +356,9 @@ __global__ void __launch_bounds__(256) k_dw_bwd(const float* __restrict__ img, c
         const int n = bw * bh, q = 256 / bw, rem = 256 - q * bw;
         int e = threadIdx.x, r = e / bw, c = e - r * bw;
         float* gptr = gimg + cbase + size_t(bx.y0 + r) * w + bx.x0 + c;
+        const float inv_scale = 1.0f / scale;
         while (e < n) {
-            const float a = accum[e];
+            const float a = fixed ? float(accum[e]) * inv_scale : __int_as_float(accum[e]);
             if (a != 0.0f) unsafeAtomicAdd(gptr, a);
             e += 256;
             c += rem;

@@ -101,6 +101,26 @@ def test_parity_ragged_and_degenerate(dev):
     _check(one, np.array([(1.3, 0.2, 0.1, 0.9, 0.0, 0.3)]), dev, "16x1")
 
 
+def test_image_gradient_scale_range_and_nan(dev):
+    say("case: image gradient of c gout equals c times that of gout for c = 1e30 and 1e-30 "
+        "(fixed-point tile sums at both ends of the float range); a NaN in gout propagates")
+    crops = synth.make_crops(2, 96, 5400)
+    P = synth.crop_params(2, 5400, max_shift=8.0)
+    img = torch.from_numpy(crops).to(dev)
+    par = torch.from_numpy(P).to(dev)
+    g = torch.from_numpy(synth.rng(12).standard_normal(crops.shape).astype(np.float32)).to(dev)
+    ref, _ = X.warp_f32_bwd(img, g, par, need_params=False)
+    for c in (1e30, 1e-30):
+        got, _ = X.warp_f32_bwd(img, g * c, par, need_params=False)
+        err = float((got.double() / c - ref.double()).abs().max() / ref.double().abs().max())
+        assert err <= 1e-4, (c, err)
+    gn = g.clone()
+    gn[0, 40, 40] = float("nan")
+    got, _ = X.warp_f32_bwd(img, gn, par, need_params=False)
+    torch.cuda.synchronize()
+    assert torch.isnan(got[0]).any() and not torch.isnan(got[1]).any()
+
+
 def test_full_size_batch_sampled(dev):
     """The timed configuration: 256 crops of 512 x 512; crops 0, 97 and 255 against the oracle."""
     say("case: 256 crops of 512x512 (16 distinct scenes); sampled crops vs the oracle")
