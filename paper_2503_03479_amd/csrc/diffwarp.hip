@@ -254,6 +254,11 @@ __global__ void __launch_bounds__(256) k_dw_bwd(const float* __restrict__ img, c
     __shared__ float sMax[4];
     // the tile's image-gradient box, accumulated in LDS as fixed point (see below)
     __shared__ int accum[GIMG ? kDwLds : 1];
+    // the tile's source box, staged for the parameter gradient's tap reads (as in the forward)
+    // when the image gradient is not wanted: with both, the two 32 KiB arrays would leave room
+    // for two blocks per CU, which costs more than the staging saves
+    constexpr bool kStage = GPAR && !GIMG;
+    __shared__ float stile[kStage ? kDwLds : 1];
     const int crop = blockIdx.x / tiles, tl = blockIdx.x - crop * tiles;
     if (threadIdx.x == 0) crop_map(params[crop], GPAR, &sC, w, h);
     const int tyi = tl / tiles_x, txi = tl - tyi * tiles_x;
@@ -284,6 +289,27 @@ __global__ void __launch_bounds__(256) k_dw_bwd(const float* __restrict__ img, c
     const bool use_acc = GIMG && bw > 0 && bh > 0 && bw * bh <= kDwLds;
     if (use_acc)
         for (int e = threadIdx.x; e < bw * bh; e += 256) accum[e] = 0;
+    const int ls = bw | 1;
+    const bool use_tile = kStage && bw > 0 && bh > 0 && ls * bh <= kDwLds;
+    if (use_tile) {
+        // element e = r * bw + c, each thread stepping by 256 = q * bw + rem (no division per element)
+        const int n = bw * bh, q = 256 / bw, rem = 256 - q * bw;
+        int e = threadIdx.x, r = e / bw, c = e - r * bw;
+        const float* gsrc = img + cbase + size_t(bx.y0 + r) * w + bx.x0 + c;
+        int lo = r * ls + c;
+        while (e < n) {
+            stile[lo] = *gsrc;
+            e += 256;
+            c += rem;
+            gsrc += size_t(q) * w + rem;
+            lo += q * ls + rem;
+            if (c >= bw) {
+                c -= bw;
+                gsrc += w - bw;
+                lo += ls - bw;
+            }
+        }
+    }
     __syncthreads();
     double gp[6] = {0, 0, 0, 0, 0, 0};
     if (x < w && y < h) {
@@ -304,13 +330,27 @@ __global__ void __launch_bounds__(256) k_dw_bwd(const float* __restrict__ img, c
             for (int j = 0; j < 8; ++j) {
                 const int row = min(max(iy - 3 + j, 0), h - 1);
                 if (GPAR) {
-                    const float* rp = img + cbase + size_t(row) * w;
+                    // taps of a valid pixel lie inside the tile's box (the image-gradient box relies
+                    // on the same), so the staged copy serves them, at box-relative (non-negative)
+                    // offsets; the LDS and global reads stay separate loops (the choice is uniform
+                    // per block)
                     float r = 0.0f, rd = 0.0f;
+                    if (use_tile) {
+                        const float* tr = stile + (row - bx.y0) * ls;
 #pragma unroll
-                    for (int i = 0; i < 8; ++i) {
-                        const float a = rp[cols[i]];
-                        r = fmaf(wx[i], a, r);
-                        rd = fmaf(dwx[i], a, rd);
+                        for (int i = 0; i < 8; ++i) {
+                            const float a = tr[cols[i] - bx.x0];
+                            r = fmaf(wx[i], a, r);
+                            rd = fmaf(dwx[i], a, rd);
+                        }
+                    } else {
+                        const float* rp = img + cbase + size_t(row) * w;
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) {
+                            const float a = rp[cols[i]];
+                            r = fmaf(wx[i], a, r);
+                            rd = fmaf(dwx[i], a, rd);
+                        }
                     }
                     v = fmaf(wy[j], r, v);
                     vx = fmaf(wy[j], rd, vx);
@@ -318,15 +358,15 @@ __global__ void __launch_bounds__(256) k_dw_bwd(const float* __restrict__ img, c
                 }
                 if (GIMG) {
                     const float gj = gn * wy[j];
-                    if (use_acc && fixed) {
-                        int* ar = accum + (row - bx.y0) * bw - bx.x0;
+                    if (use_acc && fixed) {     // box-relative, non-negative offsets
+                        int* ar = accum + (row - bx.y0) * bw;
                         const float gs = gj * scale;
 #pragma unroll
-                        for (int i = 0; i < 8; ++i) atomicAdd(ar + cols[i], int(rintf(gs * wx[i])));
+                        for (int i = 0; i < 8; ++i) atomicAdd(ar + (cols[i] - bx.x0), int(rintf(gs * wx[i])));
                     } else if (use_acc) {
-                        float* ar = reinterpret_cast<float*>(accum) + (row - bx.y0) * bw - bx.x0;
+                        float* ar = reinterpret_cast<float*>(accum) + (row - bx.y0) * bw;
 #pragma unroll
-                        for (int i = 0; i < 8; ++i) atomicAdd(ar + cols[i], gj * wx[i]);
+                        for (int i = 0; i < 8; ++i) atomicAdd(ar + (cols[i] - bx.x0), gj * wx[i]);
                     } else {
 #pragma unroll
                         for (int i = 0; i < 8; ++i) unsafeAtomicAdd(gimg + cbase + size_t(row) * w + cols[i], gj * wx[i]);
