@@ -21,9 +21,9 @@ __device__ bool degenerate4(const double* x, const double* y) {
     const int tri[4][3] = {{0, 1, 2}, {0, 1, 3}, {0, 2, 3}, {1, 2, 3}};
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
+#pragma clang fp contract(off)
         const int a = tri[t][0], b = tri[t][1], c = tri[t][2];
-        const double cross = __dsub_rn(__dmul_rn(__dsub_rn(x[b], x[a]), __dsub_rn(y[c], y[a])),
-                                       __dmul_rn(__dsub_rn(y[b], y[a]), __dsub_rn(x[c], x[a])));
+        const double cross = (x[b] - x[a]) * (y[c] - y[a]) - (y[b] - y[a]) * (x[c] - x[a]);
         if (fabs(cross) < kDegenerateArea) return true;
     }
     return false;
@@ -78,14 +78,16 @@ __device__ bool sample_homography(const double* __restrict__ pa, const double* _
     return true;
 }
 
-// |H(p_a) - p_b| <= th, evaluated term by term without contraction
+// |H(p_a) - p_b| <= th, evaluated term by term without contraction (the pragma: device code
+// is otherwise built with multiply-adds fused)
 __device__ __forceinline__ bool is_inlier(const double* H, double x, double y, double bx, double by, double th) {
-    const double w = __dadd_rn(__dadd_rn(__dmul_rn(H[6], x), __dmul_rn(H[7], y)), H[8]);
+#pragma clang fp contract(off)
+    const double w = H[6] * x + H[7] * y + H[8];
     if (!(w > 0.0)) return false;
-    const double u = __dadd_rn(__dadd_rn(__dmul_rn(H[0], x), __dmul_rn(H[1], y)), H[2]);
-    const double v = __dadd_rn(__dadd_rn(__dmul_rn(H[3], x), __dmul_rn(H[4], y)), H[5]);
-    const double ex = __dsub_rn(__ddiv_rn(u, w), bx), ey = __dsub_rn(__ddiv_rn(v, w), by);
-    return __dsqrt_rn(__dadd_rn(__dmul_rn(ex, ex), __dmul_rn(ey, ey))) <= th;
+    const double u = H[0] * x + H[1] * y + H[2];
+    const double v = H[3] * x + H[4] * y + H[5];
+    const double ex = u / w - bx, ey = v / w - by;
+    return sqrt(ex * ex + ey * ey) <= th;
 }
 
 // One 64-lane block per sample: lane 0 solves, every lane counts inliers.

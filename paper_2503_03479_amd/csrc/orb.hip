@@ -745,17 +745,18 @@ __global__ void __launch_bounds__(256) k_orient_brief(const xa_view_desc* __rest
     const size_t slot = size_t(v) * n_features + k;
     if (lane < 4) reinterpret_cast<unsigned long long*>(desc + slot * XA_DESC_BYTES)[lane] = words[lane];
     if (lane == 0) {
+#pragma clang fp contract(off)     // the back-map rounds term by term, as a plain fp64 evaluation
         const xa_view_desc& vd = views[v];
         const xa_level_desc& l0 = levels[v * n_levels];
-        const double x0 = __dadd_rn(__dmul_rn(__dadd_rn(double(x), 0.5), double(l0.width) / double(d.width)), -0.5);
-        const double y0 = __dadd_rn(__dmul_rn(__dadd_rn(double(y), 0.5), double(l0.height) / double(d.height)), -0.5);
+        const double x0 = (double(x) + 0.5) * (double(l0.width) / double(d.width)) - 0.5;
+        const double y0 = (double(y) + 0.5) * (double(l0.height) / double(d.height)) - 0.5;
         xa_keypoint o;
         o.x = x; o.y = y; o.level = lev; o.bin = bin; o.harris = R;
-        o.xs = __dadd_rn(__dadd_rn(__dmul_rn(vd.inv[0], x0), __dmul_rn(vd.inv[1], y0)), vd.inv[2]);
-        o.ys = __dadd_rn(__dadd_rn(__dmul_rn(vd.inv[3], x0), __dmul_rn(vd.inv[4], y0)), vd.inv[5]);
+        o.xs = vd.inv[0] * x0 + vd.inv[1] * y0 + vd.inv[2];
+        o.ys = vd.inv[3] * x0 + vd.inv[4] * y0 + vd.inv[5];
         if (vd.src_scale != 1.0) {     // scale-stage source: back to the original image
-            o.xs = __dadd_rn(__dadd_rn(o.xs, 0.5) / vd.src_scale, -0.5);
-            o.ys = __dadd_rn(__dadd_rn(o.ys, 0.5) / vd.src_scale, -0.5);
+            o.xs = (o.xs + 0.5) / vd.src_scale - 0.5;
+            o.ys = (o.ys + 0.5) / vd.src_scale - 0.5;
         }
         kp[slot] = o;
     }

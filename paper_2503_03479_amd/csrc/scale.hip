@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "lanczos.h"
 
 namespace xa {
 namespace {
@@ -93,30 +94,6 @@ __global__ void __launch_bounds__(256) k_sblur(const ScaleJob* __restrict__ jobs
         for (int k = 0; k <= 2 * K; ++k) acc = fmaf(g[k], hx[(r + k) * kSTX + c], acc);
         o[size_t(y) * W + x] = acc;
     }
-}
-
-// Normalised Lanczos-4 weights of eq. (4) at fractional offset f (f == 0: one-hot).
-__device__ __forceinline__ float lanczos4_weights(float f, float w[8]) {
-    if (f == 0.0f) {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) w[i] = (i == 3) ? 1.0f : 0.0f;
-        return 1.0f;
-    }
-    const float sp = __builtin_amdgcn_sinf(0.5f * f);
-    const float u = sp * __builtin_amdgcn_cosf(0.125f * f);
-    const float v = sp * __builtin_amdgcn_sinf(0.125f * f);
-    constexpr float k = 0.40528473456935108578f;
-    constexpr float h = 0.70710678118654752440f;
-    const float A[8] = {-k * h, k, -k * h, 0.0f, k * h, -k, k * h, 0.0f};
-    const float B[8] = {k * h, 0.0f, -k * h, k, -k * h, 0.0f, k * h, -k};
-    float sum = 0.0f;
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const float x = float(t - 3) - f;
-        w[t] = (A[t] * u + B[t] * v) * __builtin_amdgcn_rcpf(x * x);
-        sum += w[t];
-    }
-    return sum;
 }
 
 // Lanczos-4 resampling of one job onto its output grid: p = (q + 1/2)/s - 1/2 per axis,

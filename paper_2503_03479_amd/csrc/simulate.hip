@@ -6,6 +6,7 @@
 #include <cmath>
 
 #include "internal.h"
+#include "lanczos.h"
 
 namespace xa {
 namespace {
@@ -185,40 +186,12 @@ __global__ void __launch_bounds__(256) k_blur(const uint8_t* __restrict__ source
     }
 }
 
-// Weights L4(i - f), i = -3..4, of eq. (4) (a = 4), unnormalised; returns their sum.
-// sin(pi (i - f)) = (-1)^(i+1) sin(pi f) and sin(pi (i - f)/4) expands with the
-// angle-difference formula, so three transcendental evaluations serve all 8 taps:
-// L4(i - f) = (A_i sin(pi f) cos(pi f/4) + B_i sin(pi f) sin(pi f/4)) / (i - f)^2 with
-// A_i = (4/pi^2) (-1)^(i+1) sin(pi i/4), B_i = -(4/pi^2) (-1)^(i+1) cos(pi i/4).  The hardware
-// sine / cosine (argument in revolutions, absolute error ~1e-6, far below what moves an
-// 8-bit intensity) and reciprocal are used.  f == 0 gives the exact one-hot weights.
-__device__ __forceinline__ float lanczos4_weights(float f, float w[8]) {
-    if (f == 0.0f) {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) w[i] = (i == 3) ? 1.0f : 0.0f;
-        return 1.0f;
-    }
-    const float sp = __builtin_amdgcn_sinf(0.5f * f);            // sin(pi f)
-    const float u = sp * __builtin_amdgcn_cosf(0.125f * f);      // sin(pi f) cos(pi f / 4)
-    const float v = sp * __builtin_amdgcn_sinf(0.125f * f);      // sin(pi f) sin(pi f / 4)
-    constexpr float k = 0.40528473456935108578f;                 // 4 / pi^2
-    constexpr float h = 0.70710678118654752440f;
-    const float A[8] = {-k * h, k, -k * h, 0.0f, k * h, -k, k * h, 0.0f};
-    const float B[8] = {k * h, 0.0f, -k * h, k, -k * h, 0.0f, k * h, -k};
-    float sum = 0.0f;
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const float x = float(t - 3) - f;
-        w[t] = (A[t] * u + B[t] * v) * __builtin_amdgcn_rcpf(x * x);
-        sum += w[t];
-    }
-    return sum;
-}
-
 // Source coordinate of a view pixel, evaluated term by term in fp64 without contraction
-// (the same rounding as a plain left-to-right evaluation of inv * q).
+// (the same rounding as a plain left-to-right evaluation of inv * q; device code is otherwise
+// built with multiply-adds fused, so the operators stand under a pragma that keeps them apart).
 __device__ __forceinline__ double affine_x(const double* m, double qx, double qy) {
-    return __dadd_rn(__dadd_rn(__dmul_rn(m[0], qx), __dmul_rn(m[1], qy)), m[2]);
+#pragma clang fp contract(off)
+    return m[0] * qx + m[1] * qy + m[2];
 }
 
 // 8 x 8 Lanczos sum of eq. (3) with normalised weights; row(j) returns a pointer such

@@ -115,6 +115,30 @@ def test_identity_view_is_exact(dev):
     assert plan.level_image(mask.cpu().numpy(), 0, 0).all()
 
 
+def test_coordinates_just_below_integers(dev, tiny):
+    """Quarter and half turns (cos 90 deg is 6e-17, not 0), a 1e-12 rad rotation and s = 1 + 1e-11
+    put source coordinates within 1e-11 below an integer: their fp64 fraction rounds to 1.0 in
+    fp32, the limit where the weight of the tap one to the right tends to 1.  The turns are exact
+    permutations of the image, and the other two views equal it."""
+    say("case: views whose source coordinates sit just below integers (turns, tiny rotation, s = 1 + 1e-11)")
+    rows = [(1.0, np.pi / 2, 0.0, 1.0), (1.0, np.pi, 0.0, 1.0), (1.0, -np.pi / 2, 0.0, 1.0),
+            (1.0, 0.0, 1e-12, 1.0), (1.0, 0.0, 0.0, 1.0 + 1e-11)]
+    img = tiny.A
+    plan = X.plan_image(img.shape[1], img.shape[0], X.make_params(rows), 3, 1.2, 300, 20)
+    _check_simulate(img, rows, plan, dev, "near-integer coordinates")
+    arena, _ = X.simulate_views(plan, torch.from_numpy(np.ascontiguousarray(img)).to(dev))
+    torch.cuda.synchronize()
+    arena = arena.cpu().numpy()
+    for i, want in enumerate([np.rot90(img, -1), np.rot90(img, 2), np.rot90(img, 1), img]):
+        assert np.array_equal(plan.level_image(arena, i, 0), want), rows[i]
+    assert np.array_equal(plan.level_image(arena, 4, 0)[:-1, :-1], img)
+
+
+def test_scale_stage_near_unit_scales(dev, tiny):
+    say("case: scale stage at s = 1 +- 1e-11 (fractions just below 1 and just above 0)")
+    _scale_case(tiny.A, [1.0 + 1e-11, 1.0 - 1e-11], dev, "scale near 1")
+
+
 def test_blur_then_warp_equals_simulate(dev, tiny):
     say("case: xa_blur_views then xa_warp_views (twice) equal xa_simulate_views byte for byte")
     rows, params = _params(2, [(2.2, 1.0, 0.5, 1.1)])
