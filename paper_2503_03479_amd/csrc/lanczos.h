@@ -6,62 +6,45 @@
 
 namespace xa {
 
-// Weights proportional to L4(i - f), i = -3..4, for the fractional offset f in [0, 1]; returns
-// their sum, by which the caller divides (the proportionality factor is the same for all 8 and
-// positive).
-//
-// Only ratios matter, so two factors common to all taps drop out:
-//  - sin(pi (i - f)) = (-1)^(i+1) sin(pi f), and 4 / pi^2, leaving
-//    L4(i - f) ~ (-1)^(i+1) sin(pi (i - f) / 4) / (i - f)^2;
-//  - multiplying all 8 by D = prod_j (j - f)^2 turns the 8 reciprocals into products:
-//    w_i = (-1)^(i+1) sin(pi (i - f) / 4) prod_{j != i} (j - f)^2, formed from prefix and
-//    suffix products of the squared distances (26 multiplies instead of 8 quarter-rate
-//    reciprocals).
-// The numerators come from C = cos(pi f / 4) and S = sin(pi f / 4) by the angle-difference
-// formula, except at i = 1, whose factor sin(pi (1 - f) / 4) is evaluated directly: it vanishes as
-// f -> 1, where the difference h (C - S) would cancel to noise, and near there its tap must
-// dominate.  Both poles (i = 0 at f -> 0, i = 1 at f -> 1) then have accurate numerators.  The
-// magnitudes stay in range: every squared distance is at most 16, so no product exceeds 16^7.
-// f at most 2^-40 (the neighbouring weights are below 1e-11) and f == 1 (an fp64 fraction within
-// 2^-25 of 1, rounded to fp32) give the one-hot limits at i = 0 and i = 1.
-//
-// The hardware sine and cosine take revolutions (sin(pi x / 4) = sin(2 pi (x / 8))); their
-// absolute error, ~1e-6, moves an 8-bit intensity by far less than its rounding step.
+// With g = f - 1/2, taps p and 7 - p (p = 0..3) of the window weigh L4(p - 7/2 -+ g), whose even
+// and odd parts in g are E_p(h) = sum_k kLanczosEven[p][k] h^k and O_p = g sum_k kLanczosOdd[p][k]
+// h^k, h = g^2.  L4 is entire, so these degree-4 least-squares fits hold to 1.4e-7 in fp32 over
+// the whole of 0 <= f <= 1 (fp32 rounding of weights near 1), one-hot limits at f = 0 and 1
+// included; gen_lanczos_poly.py prints this table.
+constexpr float kLanczosEven[4][5] = {
+    {-1.266088057e-02f, 4.956583306e-02f, 1.182281319e-02f, -3.285482526e-02f, 1.122928970e-02f},
+    {5.990948528e-02f, -2.697711289e-01f, 1.186428145e-01f, 9.818997234e-03f, -9.039720520e-03f},
+    {-1.664152294e-01f, 7.228511572e-01f, -2.318021953e-01f, 1.084158383e-02f, 5.296494346e-03f},
+    {6.203830242e-01f, -5.134930015e-01f, 1.300900429e-01f, -8.574611507e-03f, -1.643885276e-03f},
+};
+constexpr float kLanczosOdd[4][5] = {
+    {3.124131449e-02f, -1.518085748e-01f, 1.153091788e-01f, -3.287798539e-02f, 4.537742585e-03f},
+    {-6.741748750e-02f, 3.247852325e-01f, -2.359036207e-01f, 6.402381510e-02f, -9.015359916e-03f},
+    {1.677483320e-01f, -7.656255960e-01f, 4.019368887e-01f, -9.694371372e-02f, 1.325049903e-02f},
+    {-1.305212140e+00f, 1.348976851e+00f, -5.413594842e-01f, 1.193514392e-01f, -1.587783545e-02f},
+};
+
+// Weights L4(i - f), i = -3..4, for the fractional offset f in [0, 1] (w[i + 3]); returns their
+// sum, by which the caller divides.  Per tap pair: two degree-4 Horner chains in h, one multiply
+// by g, a sum and a difference; the sum of all 8 is twice the sum of the even parts.  No
+// transcendental, reciprocal or branch.
 __device__ __forceinline__ float lanczos4_weights(float f, float w[8]) {
-    if (f <= 0x1p-40f || f >= 1.0f) {
-        const int hot = f >= 1.0f ? 4 : 3;
+    const float g = f - 0.5f, h = g * g;
+    float s = 0.0f;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) w[i] = (i == hot) ? 1.0f : 0.0f;
-        return 1.0f;
+    for (int p = 0; p < 4; ++p) {
+        float e = kLanczosEven[p][4], o = kLanczosOdd[p][4];
+#pragma unroll
+        for (int k = 3; k >= 0; --k) {
+            e = fmaf(e, h, kLanczosEven[p][k]);
+            o = fmaf(o, h, kLanczosOdd[p][k]);
+        }
+        o *= g;
+        w[p] = e + o;
+        w[7 - p] = e - o;
+        s += e;
     }
-    constexpr float h = 0.70710678118654752440f;                  // sin(pi / 4) = cos(pi / 4)
-    const float S = __builtin_amdgcn_sinf(0.125f * f);
-    const float C = __builtin_amdgcn_cosf(0.125f * f);
-    const float S1 = __builtin_amdgcn_sinf(0.125f - 0.125f * f); // sin(pi (1 - f) / 4)
-    const float hs = h * S, hc = h * C;
-    // (-1)^(i+1) sin(pi (i - f) / 4) for i = -3..4
-    const float g[8] = {hs - hc, C, -(hc + hs), S, S1, -C, hc + hs, -S};
-    float d[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const float x = float(t - 3) - f;
-        d[t] = x * x;
-    }
-    float pre[8], suf[8];                    // pre[t] = prod_{j < t} d_j, suf[t] = prod_{j > t} d_j
-    pre[1] = d[0];
-    suf[6] = d[7];
-#pragma unroll
-    for (int t = 2; t < 8; ++t) pre[t] = pre[t - 1] * d[t - 1];
-#pragma unroll
-    for (int t = 5; t >= 0; --t) suf[t] = suf[t + 1] * d[t + 1];
-    float sum = 0.0f;
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const float q = t == 0 ? suf[0] : (t == 7 ? pre[7] : pre[t] * suf[t]);
-        w[t] = g[t] * q;
-        sum += w[t];
-    }
-    return sum;
+    return 2.0f * s;
 }
 
 }  // namespace xa
