@@ -47,7 +47,7 @@ K_MATCH_TRAFFIC = {
     "source": "paper_2503_03479_amd/csrc/match.hip",
     "sha256": "ce036939fa848ac7494d1f4773f492a5e1412a42958b5b2f9449ef3547c9ad05",
     "fetch_scale": 2.0, "write_scale": 1.0,
-    "kib": {-1: (8095.8, 15619.2)},  # variant -> (fetch, write), variants measured on this source only
+    "kib": {-1: (8149.2, 15619.2)},  # variant -> (fetch, write), variants measured on this source only
 }
 
 
@@ -67,10 +67,11 @@ def k_match_traffic(queries_per_lane: int):
 # the timed step makes), from the same two --pmc passes and copy calibration as the matcher's.  Valid
 # only for the simulate source it was measured on.
 K_WARP_TRAFFIC = {
-    "sources": ["paper_2503_03479_amd/csrc/simulate.hip", "paper_2503_03479_amd/csrc/internal.h"],
-    "sha256": "6449ab3e391b2f317dc0a72351c63f588ae71614dd7cb06fae71bf9eaea124a3",   # of the sources, concatenated
+    "sources": ["paper_2503_03479_amd/csrc/simulate.hip", "paper_2503_03479_amd/csrc/internal.h",
+                "paper_2503_03479_amd/csrc/lanczos.h"],
+    "sha256": "6c5275a3c3cf7bfd80380901d4a83e0f34202cd8e71b5a3a6ac46653ae1672ae",   # of the sources, concatenated
     "fetch_scale": 2.0, "write_scale": 1.0,
-    "kib": (109277.0, 67586.9),   # (fetch, write) per launch
+    "kib": (109302.7, 67587.4),   # (fetch, write) per launch
 }
 WARP_OPS_PER_PX = 72 + 16         # 64 + 8 multiply-adds of the 8 x 8 sum and the 16 kernel weights per view pixel
 
@@ -139,6 +140,10 @@ def warp_roofline(case, grid_np, wl, dev, stream, pattern, match_stage, reps: in
             "hbm_GBps": algo_bytes / t / 1e9, "hbm_frac": algo_bytes / t / HBM_PEAK_BPS}
 
 
+def progress(msg: str):
+    print(msg, file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,6 +155,10 @@ def parse():
     ap.add_argument("--cpu-pairs", type=int, default=64, help="view pairs in the CPU-baseline sample")
     ap.add_argument("--batch-pairs", type=int, default=64, help="image pairs in the batched leg (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--gen-workers", type=int, default=16,
+                    help="processes rendering the batched leg's pairs (0 = in this process, one progress "
+                         "line per pair; for profiler runs, which would otherwise load the profiler into "
+                         "every worker)")
     ap.add_argument("--crops", type=int, default=256, help="crops in the differentiable-warp leg (0 = skip)")
     ap.add_argument("--matcher-q", type=int, default=0, choices=[0, 1, 2, 4, MATCH_MATRIX],
                     help="matcher variant for the full-pair leg: 0 = autotune, 1 / 2 / 4 = popcount kernel "
@@ -238,6 +247,7 @@ def batched_leg(args, dev, pattern, raw, gen_s):
     batch = X.BatchRunner(pairs, grid, (1.0, 0.5), **kw)
     batch.run(pattern)
     torch.cuda.synchronize()
+    progress("batched leg: first batch run (matcher tuned) done")
     steps = max(1, args.batch_steps)
 
     # plain: one runner per pair (same entry point and matcher variant, one pair per call), one
@@ -257,6 +267,7 @@ def batched_leg(args, dev, pattern, raw, gen_s):
             torch.cuda.synchronize()
     plain_s = (time.perf_counter() - t0) / steps
     del shared
+    progress("batched leg: per-pair runs timed")
 
     batch.capture(pattern)
     batch.replay()
@@ -271,6 +282,7 @@ def batched_leg(args, dev, pattern, raw, gen_s):
     batch_s = (time.perf_counter() - t0) / steps
     batch_ev_s = e0.elapsed_time(e1) / 1e3 / steps
     batch.close()
+    progress("batched leg: graph replays timed")
 
     # the batch reproduces the per-pair results exactly
     same = True
@@ -415,10 +427,15 @@ def main():
     # the batched leg's pairs are rendered by worker processes before this process touches the GPU
     raw, gen_s = [], 0.0
     if args.batch_pairs > 0 and args.only in (None, "batched"):
-        import multiprocessing as mp
         t0 = time.perf_counter()
-        with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
-            raw = pool.map(_make_batch_pair, range(args.batch_pairs))
+        if args.gen_workers > 0:
+            import multiprocessing as mp
+            with mp.get_context("spawn").Pool(min(args.gen_workers, os.cpu_count() or 1)) as pool:
+                raw = pool.map(_make_batch_pair, range(args.batch_pairs))
+        else:
+            for k in range(args.batch_pairs):
+                raw.append(_make_batch_pair(k))
+                progress(f"batched leg: pair {k + 1}/{args.batch_pairs} rendered")
         gen_s = time.perf_counter() - t0
 
     import torch
