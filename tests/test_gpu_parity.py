@@ -134,6 +134,17 @@ def test_coordinates_just_below_integers(dev, tiny):
     assert np.array_equal(plan.level_image(arena, 4, 0)[:-1, :-1], img)
 
 
+def test_simulate_steep_tilts(dev, tiny):
+    """Compressions t/s >= 8 take the 4-pixel-wide warp tiles and blurs of 45-73 taps (sigma up to 9);
+    on the rotated ones some tiles' source footprints exceed the LDS stage (up to 65 792 floats
+    against 8192), so their taps are read from global memory."""
+    say("case: steep tilts t = 8, 8 sqrt 2, 9 (s = 1.05, psi = 0.4), 11 on tiny A (LDS and global tap paths)")
+    rows = [(8.0, 0.3, 0.0, 1.0), (8.0 * np.sqrt(2.0), 1.1, 0.0, 1.0), (9.0, 2.5, 0.4, 1.05), (11.0, 0.0, 0.0, 1.0)]
+    plan = X.plan_image(256, 256, X.make_params(rows), 3, 1.2, 300, 20)
+    assert all(int(v["warp_tile_w"]) == 4 for v in plan.views)
+    _check_simulate(tiny.A, rows, plan, dev, "steep tilts")
+
+
 def test_scale_stage_near_unit_scales(dev, tiny):
     say("case: scale stage at s = 1 +- 1e-11 (fractions just below 1 and just above 0)")
     _scale_case(tiny.A, [1.0 + 1e-11, 1.0 - 1e-11], dev, "scale near 1")
