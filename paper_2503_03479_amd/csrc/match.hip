@@ -274,15 +274,15 @@ k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ coun
                 acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A2, operand(B[qt][2]), acc, 4, 4, 0, 127, 0, 127);
                 acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A3, operand(B[qt][3]), acc, 4, 4, 0, 127, 0, 127);
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    // keys are positive floats, whose order is their bit patterns' order: the
-                    // float median of three (a builtin, so the compiler inserts the wait states
-                    // an MFMA result needs before a VALU read) updates the second largest and an
-                    // integer max the largest
-                    const uint32_t key = __float_as_uint(acc[r]);
-                    m2[qt] = __float_as_uint(__builtin_amdgcn_fmed3f(__uint_as_float(m1[qt]), acc[r],
-                                                                     __uint_as_float(m2[qt])));
-                    m1[qt] = max(m1[qt], key);
+                for (int r = 0; r < 16; r += 2) {
+                    // keys are positive floats, whose order is their bit patterns' order.  Two
+                    // keys x, y at a time: the second largest of {m1, m2, x, y} (m1 >= m2) is
+                    // max(m2, med3(m1, x, y)) and the largest max3(m1, x, y), three instructions
+                    // for two keys.  The float median is a builtin, so the compiler inserts the
+                    // wait states an MFMA result needs before a VALU read.
+                    const float mid = __builtin_amdgcn_fmed3f(__uint_as_float(m1[qt]), acc[r], acc[r + 1]);
+                    m2[qt] = max(m2[qt], __float_as_uint(mid));
+                    m1[qt] = max(max(m1[qt], __float_as_uint(acc[r])), __float_as_uint(acc[r + 1]));
                 }
             }
         }
