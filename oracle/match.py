@@ -9,7 +9,9 @@ eqs. (5)-(6): a match is correct when the ground-truth map sends the first
 point within Th pixels of its match.
 
 Parity status: pinned (a pure-Python popcount brute force, d(x, x) = 0,
-symmetry, duplicated train descriptors force d2 = d1 and reject).
+symmetry, duplicated train descriptors force d2 = d1 and reject; for the L2 matcher of SIFT
+descriptors a pure-Python brute force of the squared distances, scipy's squared-Euclidean
+distance, the exact ratio boundary and the missing-neighbour cases).
 """
 from __future__ import annotations
 
@@ -50,6 +52,52 @@ def ratio_accept(d1, d2, n_train: int, num: int = 4, den: int = 5):
     if n_train < 2:
         return np.zeros(d1.shape, bool)
     return den * d1 < num * d2
+
+
+# ------------------------------------------------------------------ L2 matching of SIFT descriptors
+# Sec. III.A and III.C match SIFT descriptors (128-D) by descriptor distance with the same
+# nearest / second-nearest screening (threshold 0.75, Sec. IV.C).  Reading: the descriptor is
+# in its usual 8-bit quantised form (components 0..255) and the distance is Euclidean; ranking
+# by the squared distance is the same, and the ratio test d1 < (num/den) d2 on distances is
+# den^2 d1^2 < num^2 d2^2 on squared ones, exact in integers.
+
+L2_MISSING = (1 << 32) - 1          # squared distance reported where a neighbour does not exist
+
+
+def l2sq_matrix(Dq, Dt):
+    """d[q, r] = sum_k (Dq[q, k] - Dt[r, k])^2 (int64, exact)."""
+    a = np.asarray(Dq, np.int64)
+    b = np.asarray(Dt, np.int64)
+    return (a * a).sum(axis=1)[:, None] + (b * b).sum(axis=1)[None, :] - 2 * (a @ b.T)
+
+
+def nearest_two_l2(Dq, Dt):
+    """For each query: idx1 = smallest train index attaining the minimum squared distance d1;
+    d2 = minimum over the other train descriptors (may equal d1).  Missing values are
+    -1 / L2_MISSING."""
+    nq, nt = len(Dq), len(Dt)
+    idx = np.full(nq, -1, np.int64)
+    d1 = np.full(nq, L2_MISSING, np.int64)
+    d2 = np.full(nq, L2_MISSING, np.int64)
+    if nq == 0 or nt == 0:
+        return idx, d1, d2
+    d = l2sq_matrix(Dq, Dt)
+    idx = np.argmin(d, axis=1)                      # first minimum = smallest index
+    d1 = d[np.arange(nq), idx]
+    if nt >= 2:
+        d[np.arange(nq), idx] = np.iinfo(np.int64).max
+        d2 = d.min(axis=1)
+    return idx.astype(np.int64), d1, d2
+
+
+def ratio_accept_l2(d1sq, d2sq, n_train: int, num: int = 3, den: int = 4):
+    """Accept iff there are at least two train descriptors and d1 < (num/den) d2 on distances,
+    evaluated exactly on squared distances as den^2 d1^2 < num^2 d2^2."""
+    d1sq = np.asarray(d1sq, np.int64)
+    d2sq = np.asarray(d2sq, np.int64)
+    if n_train < 2:
+        return np.zeros(d1sq.shape, bool)
+    return den * den * d1sq < num * num * d2sq
 
 
 def match_views(descs_a, descs_b, num: int = 4, den: int = 5, pairs=None):

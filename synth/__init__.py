@@ -262,3 +262,31 @@ def batch_pairs(n: int, seed: int = 3000, side_min: int = 480, side_max: int = 2
         out.append(make_pair(w, h, max(8, int(round(400 * area))), max(6, int(round(300 * area))), seed + k,
                              1.0 / math.cos(theta), phi, psi, supersample=supersample, name=f"batch{k}"))
     return out
+
+
+def sift_like_descriptors(n: int, seed: int) -> np.ndarray:
+    """n x 128 u8 descriptors distributed like 8-bit SIFT descriptors: 128 gamma(0.6) magnitudes
+    normalised to unit length, clipped at 0.2, renormalised, scaled by 512, rounded and clipped to
+    0..255 (the usual quantisation of the SIFT descriptor)."""
+    g = rng(seed)
+    v = g.gamma(0.6, 1.0, (n, 128))
+    v /= np.maximum(np.linalg.norm(v, axis=1, keepdims=True), 1e-12)
+    v = np.minimum(v, 0.2)
+    v /= np.maximum(np.linalg.norm(v, axis=1, keepdims=True), 1e-12)
+    return np.clip(np.rint(v * 512.0), 0, 255).astype(np.uint8)
+
+
+def sift_like_sets(n_q: int, n_t: int, seed: int, shared: float = 0.5, noise: float = 6.0):
+    """Query and train sets of SIFT-like descriptors where a fraction `shared` of the queries are
+    noisy copies (Gaussian noise of the given std, rounded, clipped) of random train descriptors,
+    the rest independent, so that nearest-neighbour matching finds true pairs among distractors.
+    Returns (queries, train, source) with source[q] = the train index copied, or -1."""
+    g = rng(seed + 1)
+    T = sift_like_descriptors(n_t, seed)
+    Q = sift_like_descriptors(n_q, seed + 2)
+    src = np.full(n_q, -1, np.int64)
+    if n_t > 0:
+        k = g.random(n_q) < shared
+        src[k] = g.integers(0, n_t, int(k.sum()))
+        Q[k] = np.clip(np.rint(T[src[k]].astype(np.float64) + g.normal(0.0, noise, (int(k.sum()), 128))), 0, 255)
+    return np.ascontiguousarray(Q, np.uint8), np.ascontiguousarray(T, np.uint8), src

@@ -88,3 +88,51 @@ def test_tiny_pair_recovers_ground_truth():
     assert frac >= 0.8
     # the view pair that wins simulates (part of) the true tilt on the A side
     assert grid[i][0] > 1.0
+
+
+# ------------------------------------------------------------------ L2 matching of SIFT descriptors
+
+def test_l2sq_matrix_brute_force_and_scipy():
+    from scipy.spatial.distance import cdist
+    g = np.random.default_rng(41)
+    Dq = g.integers(0, 256, (7, 128)).astype(np.uint8)
+    Dt = g.integers(0, 256, (9, 128)).astype(np.uint8)
+    d = M.l2sq_matrix(Dq, Dt)
+    for i in range(7):
+        for j in range(9):
+            assert d[i, j] == sum((int(a) - int(b)) ** 2 for a, b in zip(Dq[i], Dt[j]))
+    # squared Euclidean distances of 8-bit vectors stay far below 2^53: exact in fp64
+    assert np.array_equal(d, cdist(Dq.astype(np.float64), Dt.astype(np.float64), "sqeuclidean").astype(np.int64))
+    assert M.l2sq_matrix(np.full((1, 128), 255, np.uint8), np.zeros((1, 128), np.uint8))[0, 0] == 128 * 255 * 255
+
+
+def test_nearest_two_l2_brute_force_ties_and_self():
+    g = np.random.default_rng(42)
+    Dt = g.integers(0, 40, (12, 128)).astype(np.uint8)
+    Dt[7] = Dt[3]                                   # duplicate: equal distances go to the lower index
+    Dq = np.concatenate([Dt[[3, 5]], g.integers(0, 40, (6, 128)).astype(np.uint8)])
+    idx, d1, d2 = M.nearest_two_l2(Dq, Dt)
+    for q in range(len(Dq)):
+        ds = [sum((int(a) - int(b)) ** 2 for a, b in zip(Dq[q], Dt[r])) for r in range(len(Dt))]
+        best = min(range(len(ds)), key=lambda r: (ds[r], r))
+        assert idx[q] == best and d1[q] == ds[best]
+        assert d2[q] == min(ds[r] for r in range(len(ds)) if r != best)
+    assert idx[0] == 3 and d1[0] == 0 and d2[0] == 0 and not M.ratio_accept_l2(d1, d2, 12)[0]
+    assert idx[1] == 5 and d1[1] == 0
+
+
+def test_ratio_test_l2_is_exact_on_squared_distances():
+    # d1 / d2 = 3 / 4 exactly (squared 9 : 16) is rejected; just below is accepted
+    d1 = np.array([9, 9 * 10000 - 1, 0, 5])
+    d2 = np.array([16, 16 * 10000, 0, M.L2_MISSING])
+    acc = M.ratio_accept_l2(d1, d2, 2, 3, 4)
+    assert acc.tolist() == [False, True, False, True]
+    assert not M.ratio_accept_l2(d1, d2, 1, 3, 4).any()
+
+
+def test_l2_missing_neighbours():
+    D = np.zeros((3, 128), np.uint8)
+    idx, d1, d2 = M.nearest_two_l2(D, D[:0])
+    assert (idx == -1).all() and (d1 == M.L2_MISSING).all() and (d2 == M.L2_MISSING).all()
+    idx, d1, d2 = M.nearest_two_l2(D, D[:1])
+    assert (idx == 0).all() and (d1 == 0).all() and (d2 == M.L2_MISSING).all()
