@@ -329,6 +329,31 @@ xa_status xa_match_groups(const void* mplan_host, const void* mplan_dev, const u
                           int32_t n_views, int32_t ratio_num, int32_t ratio_den, xa_match* d_matches,
                           int32_t* d_pair_count, int32_t* d_best, hipStream_t stream);
 
+/* Exact L2 nearest-two matching of SIFT descriptors (the SIFT feature matching of Sec. III.A and
+ * III.C, screened by the nearest / second-nearest distance ratio of Sec. IV.C), for descriptors in
+ * their usual 8-bit form: 128 components 0..255 per descriptor, row-major, d_q [n_q][128] and
+ * d_t [n_t][128], both 16-byte aligned device arrays (NULL allowed where the count is 0).
+ * d_out [n_q] (device): t = the train index of the smallest squared Euclidean distance d1 (the
+ * lowest index on ties; -1 if n_t = 0), d2 = the smallest squared distance to any other train
+ * descriptor (may equal d1); a missing distance reads 0xFFFFFFFF.  *d_count (device) = the queries
+ * that pass the ratio test on distances, d1 < (ratio_num / ratio_den) d2, evaluated exactly on the
+ * squared values as ratio_den^2 d1 < ratio_num^2 d2, with at least two train descriptors (the
+ * paper's threshold is 3 / 4).  Squared distances are exact: the dot products are contracted on
+ * the int8 matrix cores.  d_ws: caller-owned device workspace of
+ * xa_match_l2_workspace_size(n_q, n_t) bytes, 16-byte aligned (none is needed when n_q = 0).
+ * Asynchronous on stream; the library allocates nothing.  XA_EINVAL for counts outside
+ * 0..XA_L2_MAX_DESCRIPTORS, a ratio outside 0 <= num, 1 <= den <= 2^16, a NULL or misaligned
+ * array, or a short workspace; XA_EHIP if a launch fails. */
+#define XA_L2_MAX_DESCRIPTORS (1 << 20)
+typedef struct {
+    int32_t t;
+    uint32_t d1, d2;
+} xa_l2_match;
+size_t xa_match_l2_workspace_size(int32_t n_q, int32_t n_t);
+xa_status xa_match_l2(const uint8_t* d_q, int32_t n_q, const uint8_t* d_t, int32_t n_t, int32_t ratio_num,
+                      int32_t ratio_den, xa_l2_match* d_out, int32_t* d_count, void* d_ws, size_t ws_bytes,
+                      hipStream_t stream);
+
 /* The whole parameter-search path for one image pair: simulate both images,
  * extract ORB on every view, match all view pairs, pick the best pair.
  * Both plans must use the same n_features.  Workspace:

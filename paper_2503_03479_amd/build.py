@@ -8,15 +8,16 @@ from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SOURCES = ["plan.cpp", "simulate.hip", "scale.hip", "orb.hip", "match.hip", "pipeline.hip", "diffwarp.hip", "geometry.hip"]
+SOURCES = ["plan.cpp", "simulate.hip", "scale.hip", "orb.hip", "match.hip", "match_l2.hip", "pipeline.hip",
+           "diffwarp.hip", "geometry.hip"]
 LIB = os.path.join(PKG, "libxaffine.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-std=c++17", "-O3", "--offload-arch=gfx950", "-fPIC",
          # keep the compiler from forming packed fp32 instructions
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(PKG, "csrc")]
-# per-source additions: the matcher's MFMA accumulators stay in VGPRs (no AGPR copies)
-EXTRA = {"match.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+# per-source additions: the matchers' MFMA accumulators stay in VGPRs (no AGPR copies)
+EXTRA = {"match.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"], "match_l2.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _compile(src: str, out_dir: str) -> str:

@@ -100,6 +100,9 @@ _SIGS = {
                                    _c.POINTER(_c.c_size_t)]),
     "xa_match_groups": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_int32,
                                    _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p]),
+    "xa_match_l2_workspace_size": (_c.c_size_t, [_c.c_int32, _c.c_int32]),
+    "xa_match_l2": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_void_p,
+                               _c.c_void_p, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
     "xa_match_batch_workspace_size": (_c.c_size_t, [_c.c_void_p, _c.c_int32, _c.c_void_p]),
     "xa_match_batch": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                   _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_int32, _c.c_void_p,
@@ -473,6 +476,35 @@ def keypoints_np(kp_tensor) -> np.ndarray:
     """Device keypoint buffer -> numpy structured array (n_views, N)."""
     a = kp_tensor.cpu().numpy()
     return a.reshape(a.shape[0], a.shape[1] * a.shape[2]).view(KEYPOINT_DTYPE)
+
+
+L2_MATCH_DTYPE = np.dtype([("t", "i4"), ("d1", "u4"), ("d2", "u4")])
+L2_MISSING = 0xFFFFFFFF
+
+
+def match_l2(dq, dt, ratio_num: int = 3, ratio_den: int = 4, ws=None):
+    """Exact L2 nearest-two matching of 8-bit SIFT descriptors (xa_match_l2): dq [n_q, 128] and
+    dt [n_t, 128] uint8 device tensors.  Returns (out int32 [n_q, 3] = (t, d1, d2) with d1, d2 the
+    squared distances as uint32 bits, count int32 [1] of ratio-test passes); decode with
+    l2_matches_np."""
+    import torch
+    for name, d in (("dq", dq), ("dt", dt)):
+        if d.dtype != torch.uint8 or d.dim() != 2 or d.shape[1] != 128 or not d.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous uint8 tensor of shape [n, 128]")
+    dev = dq.device
+    nq, nt = int(dq.shape[0]), int(dt.shape[0])
+    need = lib().xa_match_l2_workspace_size(nq, nt)
+    if ws is None:
+        ws = _empty(need, dev)
+    out = torch.empty((max(nq, 1), 3), dtype=torch.int32, device=dev)
+    count = torch.empty(1, dtype=torch.int32, device=dev)
+    _check(lib().xa_match_l2(_ptr(dq) if nq else None, nq, _ptr(dt) if nt else None, nt, ratio_num, ratio_den,
+                             _ptr(out), _ptr(count), _ptr(ws), ws.numel(), _stream()))
+    return out[:nq], count
+
+
+def l2_matches_np(out) -> np.ndarray:
+    return np.ascontiguousarray(out.cpu().numpy()).view(L2_MATCH_DTYPE).reshape(-1)
 
 
 def matches_np(m_tensor) -> np.ndarray:

@@ -145,6 +145,16 @@ def test_device_calls_validate_before_launch(L):
     assert L.xa_warp_views(hp, hp, 256, 256, 256, None, 256, 0, None) == X.XA_ECAPACITY
     junk = np.zeros(256, np.uint8)
     assert L.xa_warp_views(junk.ctypes.data, hp, 256, 256, 256, None, 256, 1 << 30, None) == X.XA_EINVAL
+    # the L2 matcher: counts, ratio, NULL, misaligned and short-workspace arguments
+    need = L.xa_match_l2_workspace_size(1000, 700)
+    assert need > 0 and L.xa_match_l2_workspace_size(0, 700) == 0 and L.xa_match_l2_workspace_size(-1, 5) == 0
+    assert L.xa_match_l2(256, -1, 256, 5, 3, 4, 256, 256, 256, need, None) == X.XA_EINVAL
+    assert L.xa_match_l2(256, 5, 256, (1 << 20) + 1, 3, 4, 256, 256, 256, need, None) == X.XA_EINVAL
+    assert L.xa_match_l2(256, 1000, 256, 700, 3, 0, 256, 256, 256, need, None) == X.XA_EINVAL
+    assert L.xa_match_l2(None, 1000, 256, 700, 3, 4, 256, 256, 256, need, None) == X.XA_EINVAL
+    assert L.xa_match_l2(256, 1000, 256, 700, 3, 4, 256, None, 256, need, None) == X.XA_EINVAL
+    assert L.xa_match_l2(264, 1000, 256, 700, 3, 4, 256, 256, 256, need, None) == X.XA_EINVAL
+    assert L.xa_match_l2(256, 1000, 256, 700, 3, 4, 256, 256, 256, need - 16, None) == X.XA_EINVAL
 
 
 def test_match_plan_rules():
