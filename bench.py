@@ -163,7 +163,8 @@ def parse():
     ap.add_argument("--matcher-q", type=int, default=0, choices=[0, 1, 2, 4, MATCH_MATRIX],
                     help="matcher variant for the full-pair leg: 0 = autotune, 1 / 2 / 4 = popcount kernel "
                          "with that many queries per lane, -1 = matrix-core kernel")
-    ap.add_argument("--only", choices=["batched", "diffwarp", "copy", "sweep"], default=None,
+    ap.add_argument("--l2-n", type=int, default=32768, help="descriptors per set in the L2 matcher leg (0 = skip)")
+    ap.add_argument("--only", choices=["batched", "diffwarp", "copy", "sweep", "l2"], default=None,
                     help="run one leg alone and print its JSON (for profiler runs); 'copy' is a plain 1 GiB "
                          "device-to-device copy whose counter readings calibrate the HBM traffic counters")
     return ap.parse_args()
@@ -361,6 +362,60 @@ def sweep_leg(args, dev, pattern):
                         "s_i = 1 + i ds, single-image matching against B, 8 levels", "settings": out}
 
 
+INT8_PEAK_OPS = 5.0e15            # MI355X dense int8 matrix-core peak, ops/s
+L2_OPS_PER_CMP = 2 * 128          # multiply-adds of one 128-D dot product
+
+
+def l2_leg(args, dev):
+    """L2 nearest-two matching of 8-bit SIFT descriptors (xa_match_l2) on seeded SIFT-like sets:
+    the throughput size (n x n) and the paper's size (1000 features per image), HIP events over
+    10 calls after one untimed call."""
+    import torch
+
+    import synth
+    from paper_2503_03479_amd import xaffine as X
+
+    L = X.lib()
+    res = {}
+    for tag, n in (("large", args.l2_n), ("paper", 1000)):
+        Q, T, _ = synth.sift_like_sets(n, n, 21)
+        q = torch.from_numpy(Q).to(dev)
+        t = torch.from_numpy(T).to(dev)
+        out = torch.empty((n, 3), dtype=torch.int32, device=dev)
+        count = torch.empty(1, dtype=torch.int32, device=dev)
+        ws = X._empty(L.xa_match_l2_workspace_size(n, n), dev)
+        stream = torch.cuda.current_stream()
+
+        def call():
+            X._check(L.xa_match_l2(X._ptr(q), n, X._ptr(t), n, 3, 4, X._ptr(out), X._ptr(count), X._ptr(ws),
+                                   ws.numel(), X._stream()))
+
+        call()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record(stream)
+        for _ in range(reps):
+            call()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        cmp = n * n
+        res[tag] = {"n_query": n, "n_train": n, "ms_per_call": ms, "comparisons_per_s": cmp / (ms / 1e3),
+                    "accepted": int(count.cpu()[0])}
+    big = res["large"]
+    achieved = big["comparisons_per_s"] * L2_OPS_PER_CMP
+    return {
+        "workload": f"SIFT-like 8-bit descriptors (gamma magnitudes, unit length, clipped at 0.2, x512), "
+                    f"half of the queries noisy copies of train rows; {args.l2_n} x {args.l2_n} and 1000 x 1000, "
+                    f"ratio 3/4",
+        "kernel": "k_match_l2 + k_match_l2_final (xa_match_l2, int8 matrix-core contraction)",
+        "bound": "mfma", "achieved": achieved / 1e12, "peak": INT8_PEAK_OPS / 1e12, "unit": "TOP/s",
+        "frac": achieved / INT8_PEAK_OPS, "ops_per_comparison": L2_OPS_PER_CMP,
+        "large": big, "paper_size": res["paper"],
+    }
+
+
 def diffwarp_leg(args, dev):
     """Differentiable warp on n fp32 crops of 512 x 512 (parameters drawn per crop):
     forward and adjoint (image + six parameters) timed with HIP events."""
@@ -451,6 +506,8 @@ def main():
         pattern = torch.from_numpy(synth.brief_pattern()).to(dev)
         if args.only == "batched":
             print(json.dumps(batched_leg(args, dev, pattern, raw, gen_s)), flush=True)
+        elif args.only == "l2":
+            print(json.dumps(l2_leg(args, dev)), flush=True)
         elif args.only == "diffwarp":
             print(json.dumps(diffwarp_leg(args, dev)), flush=True)
         elif args.only == "sweep":
@@ -608,6 +665,8 @@ def main():
         out["batched"] = batched_leg(args, dev, pattern, raw, gen_s)
     if args.crops > 0:
         out["diffwarp"] = diffwarp_leg(args, dev)
+    if args.l2_n > 0:
+        out["l2_matcher"] = l2_leg(args, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, grid, wl, args.cpu_views, args.cpu_pairs)
     print(json.dumps(out), flush=True)

@@ -20,8 +20,9 @@
 namespace xa {
 namespace {
 
-constexpr int kL2Threads = 256;            // four waves, one 32-query tile each
-constexpr int kL2BlockQ = 128;             // queries per block
+constexpr int kL2Threads = 256;            // four waves
+constexpr int kL2QT = 2;                   // 32-query tiles per wave (each train operand feeds both)
+constexpr int kL2BlockQ = (kL2Threads / 64) * 32 * kL2QT;   // queries per block
 constexpr int kL2Chunk = 128;              // train rows staged in LDS per step (16 KiB of operands)
 constexpr int kL2TargetBlocks = 2048;      // train slices are added until a launch has about this many blocks
 constexpr int kL2Sentinel = 0x7F000000;    // key base of a row past the train range: above every real key
@@ -56,7 +57,7 @@ __device__ __forceinline__ uint32_t udot4(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_udot4(a, b, c, false);
 }
 
-// Block (query block qb, train slice blockIdx.y): 128 queries against the slice's train rows,
+// Block (query block qb, train slice blockIdx.y): 256 queries against the slice's train rows,
 // chunk by chunk; the two best (value, index) per query of the slice go to part[slice][query].
 // Operand layout: slice s of lane (h = lane / 32, m = lane % 32) is bytes 32 s + 16 h .. + 15 of
 // descriptor m of the tile, for both operands, so the contraction pairs equal components
@@ -68,26 +69,37 @@ k_match_l2(const uint4* __restrict__ q, int nq, const uint4* __restrict__ t, int
     __shared__ uint4 tr[(kL2Chunk / 32) * 4 * 64];      // [tile][slice][lane]
     __shared__ __align__(16) int t7[kL2Chunk];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, h = lane >> 5, m = lane & 31;
-    const int qw = blockIdx.x * kL2BlockQ + wv * 32;      // this wave's first query
-    const int qi = qw + m;
-    v4i_t B[4];
+    const int qw = blockIdx.x * kL2BlockQ + wv * 32 * kL2QT;   // this wave's first query
+    v4i_t B[kL2QT][4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
-        B[s] = qi < nq ? as_v4i(q[size_t(qi) * kL2DescWords + 2 * s + h], 0x80808080u) : v4i_t{0, 0, 0, 0};
-    long long K1 = kNone, K2 = kNone;
+    for (int qt = 0; qt < kL2QT; ++qt) {
+        const int qi = qw + qt * 32 + m;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            B[qt][s] = qi < nq ? as_v4i(q[size_t(qi) * kL2DescWords + 2 * s + h], 0x80808080u) : v4i_t{0, 0, 0, 0};
+    }
+    long long K1[kL2QT], K2[kL2QT];
+#pragma unroll
+    for (int qt = 0; qt < kL2QT; ++qt) { K1[qt] = kNone; K2[qt] = kNone; }
     const int c_begin = blockIdx.y * chunks_per_slice * kL2Chunk;
     const int c_end = min(nt, c_begin + chunks_per_slice * kL2Chunk);
+    // staging: thread -> chunk row r = tid / 2, its 16-byte pieces 4 (tid % 2) .. + 3; each
+    // chunk's pieces are loaded one chunk ahead, so the loads overlap the previous chunk's tiles
+    const int r = threadIdx.x >> 1, hf = threadIdx.x & 1;
+    uint4 nx[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        nx[k] = c_begin + r < c_end ? t[size_t(c_begin + r) * kL2DescWords + hf * 4 + k] : make_uint4(0, 0, 0, 0);
     for (int c0 = c_begin; c0 < c_end; c0 += kL2Chunk) {
         __syncthreads();                                  // the previous chunk's readers are done
-        {   // stage: thread -> row r = tid / 2, 16-byte pieces 4 (tid % 2) .. + 3, with P_t
-            const int r = threadIdx.x >> 1, hf = threadIdx.x & 1;
+        {   // stage this chunk's operands and T7 (with P_t)
             const int row = c0 + r;
             const bool live = row < c_end;
             uint32_t sq = 0, s1 = 0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const int c = hf * 4 + k;                 // piece c: slice c / 2, half c % 2
-                const uint4 w = live ? t[size_t(row) * kL2DescWords + c] : make_uint4(0, 0, 0, 0);
+                const uint4 w = live ? nx[k] : make_uint4(0, 0, 0, 0);
                 sq = udot4(w.x, w.x, udot4(w.y, w.y, udot4(w.z, w.z, udot4(w.w, w.w, sq))));
                 s1 = udot4(w.x, 0x01010101u, udot4(w.y, 0x01010101u, udot4(w.z, 0x01010101u, udot4(w.w, 0x01010101u, s1))));
                 tr[((r >> 5) * 4 + (c >> 1)) * 64 + (c & 1) * 32 + (r & 31)] =
@@ -99,44 +111,64 @@ k_match_l2(const uint4* __restrict__ q, int nq, const uint4* __restrict__ t, int
             if (hf == 0) t7[r] = live ? (int(sq) - 256 * int(s1)) * 128 + r : kL2Sentinel + r;
         }
         __syncthreads();
-        if (qw >= nq) continue;                           // wave-uniform: no query in this tile
-        int m1 = INT_MAX, m2 = INT_MAX;
+        {
+            const int row = c0 + kL2Chunk + r;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (row < c_end) nx[k] = t[size_t(row) * kL2DescWords + hf * 4 + k];
+        }
+        if (qw >= nq) continue;                           // wave-uniform: no query in this wave
+        int m1[kL2QT], m2[kL2QT];
+#pragma unroll
+        for (int qt = 0; qt < kL2QT; ++qt) { m1[qt] = INT_MAX; m2[qt] = INT_MAX; }
         const int ntile = (min(kL2Chunk, c_end - c0) + 31) >> 5;
         for (int tt = 0; tt < ntile; ++tt) {
             const uint4* a = tr + tt * 4 * 64 + lane;
-            v16i_t acc = {};
-            acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(as_v4i(a[0], 0u), B[0], acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(as_v4i(a[64], 0u), B[1], acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(as_v4i(a[128], 0u), B[2], acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(as_v4i(a[192], 0u), B[3], acc, 0, 0, 0);
+            const v4i_t A0 = as_v4i(a[0], 0u), A1 = as_v4i(a[64], 0u), A2 = as_v4i(a[128], 0u), A3 = as_v4i(a[192], 0u);
             const int4* tp = reinterpret_cast<const int4*>(t7 + tt * 32 + 4 * h);
             const int4 g[4] = {tp[0], tp[2], tp[4], tp[6]};   // rows 8 j + 4 h + 0..3
-            int key[16];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                key[4 * j + 0] = g[j].x + acc[4 * j + 0] * 256;
-                key[4 * j + 1] = g[j].y + acc[4 * j + 1] * 256;
-                key[4 * j + 2] = g[j].z + acc[4 * j + 2] * 256;
-                key[4 * j + 3] = g[j].w + acc[4 * j + 3] * 256;
-            }
+            for (int qt = 0; qt < kL2QT; ++qt) {
+                v16i_t acc = {};
+                acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(A0, B[qt][0], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1, B[qt][1], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(A2, B[qt][2], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(A3, B[qt][3], acc, 0, 0, 0);
+                int key[16];
 #pragma unroll
-            for (int r = 0; r < 16; r += 2) {             // the two smallest of {m1, m2, x, y}
-                m2 = min(m2, med3_i32(m1, key[r], key[r + 1]));
-                m1 = min(min(m1, key[r]), key[r + 1]);
+                for (int j = 0; j < 4; ++j) {
+                    key[4 * j + 0] = g[j].x + acc[4 * j + 0] * 256;
+                    key[4 * j + 1] = g[j].y + acc[4 * j + 1] * 256;
+                    key[4 * j + 2] = g[j].z + acc[4 * j + 2] * 256;
+                    key[4 * j + 3] = g[j].w + acc[4 * j + 3] * 256;
+                }
+#pragma unroll
+                for (int r = 0; r < 16; r += 2) {         // the two smallest of {m1, m2, x, y}
+                    m2[qt] = min(m2[qt], med3_i32(m1[qt], key[r], key[r + 1]));
+                    m1[qt] = min(min(m1[qt], key[r]), key[r + 1]);
+                }
             }
         }
         // the chunk's two smallest keys, decoded to (value, train index); missing rows decode
         // to values of 2^23 and above
-        const int v1 = m1 >> 7, v2 = m2 >> 7;
-        const long long b1 = v1 < (1 << 23) ? lex(v1, c0 + (m1 & 127)) : kNone;
-        const long long b2 = v2 < (1 << 23) ? lex(v2, c0 + (m2 & 127)) : kNone;
-        merge2(K1, K2, b1, b2);
+#pragma unroll
+        for (int qt = 0; qt < kL2QT; ++qt) {
+            const int v1 = m1[qt] >> 7, v2 = m2[qt] >> 7;
+            const long long b1 = v1 < (1 << 23) ? lex(v1, c0 + (m1[qt] & 127)) : kNone;
+            const long long b2 = v2 < (1 << 23) ? lex(v2, c0 + (m2[qt] & 127)) : kNone;
+            merge2(K1[qt], K2[qt], b1, b2);
+        }
     }
-    // lanes h = 0 and 1 saw disjoint rows of the same query column
-    const long long o1 = __shfl_xor(K1, 32), o2 = __shfl_xor(K2, 32);
-    merge2(K1, K2, o1, o2);
-    if (h == 0 && qi < nq)
-        part[size_t(blockIdx.y) * nq + qi] = make_int4(int(K1 >> 32), int(uint32_t(K1)), int(K2 >> 32), int(uint32_t(K2)));
+#pragma unroll
+    for (int qt = 0; qt < kL2QT; ++qt) {
+        // lanes h = 0 and 1 saw disjoint rows of the same query column
+        const long long o1 = __shfl_xor(K1[qt], 32), o2 = __shfl_xor(K2[qt], 32);
+        merge2(K1[qt], K2[qt], o1, o2);
+        const int qi = qw + qt * 32 + m;
+        if (h == 0 && qi < nq)
+            part[size_t(blockIdx.y) * nq + qi] =
+                make_int4(int(K1[qt] >> 32), int(uint32_t(K1[qt])), int(K2[qt] >> 32), int(uint32_t(K2[qt])));
+    }
 }
 
 // Per query: the slices' best pairs merged in slice order, the squared distances restored
