@@ -78,23 +78,64 @@ __global__ void __launch_bounds__(256) k_blur(const uint8_t* __restrict__ source
     const BlurRegion g = blur_region(v, tp, x0, y0);
     float* o = out + v.blur_offset;
     if (g.floats <= lds_floats) {
-        // loads are issued 8 per thread before any is stored, so their latencies overlap;
-        // r = e / rw through a float reciprocal is exact for e < 2^14 (see the warp's staging)
-        const int n_el = g.rw * g.rh;
-        const float rrw = 1.0f / float(g.rw);
-        for (int e0 = 0; e0 < n_el; e0 += 8 * 256) {
-            float val[8];
+        if (((reinterpret_cast<uintptr_t>(src) | uintptr_t(pitch)) & 3) == 0) {
+            // 4-byte-aligned sources: the footprint's rows are read as aligned words (columns
+            // ax0 + 4 j .. + 3), 4 per thread before any is stored; words that leave the image are
+            // assembled byte by byte with the border replicated, and columns outside the footprint
+            // are dropped.  r = e / nw through a float reciprocal is exact for e < 2^14.
+            const int ax0 = g.rx0 & ~3;
+            const int nw = ((g.rx0 + g.rw - 1 - ax0) >> 2) + 1;
+            const int n_w = nw * g.rh;
+            const float rnw = 1.0f / float(nw);
+            for (int e0 = 0; e0 < n_w; e0 += 4 * 256) {
+                uint32_t wv[4];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + u * 256 + int(threadIdx.x);
-                const int r = int((float(e) + 0.5f) * rrw), c = e - r * g.rw;
-                if (e < n_el) val[u] = float(src[size_t(clampi(g.ry0 + r, 0, H - 1)) * pitch + clampi(g.rx0 + c, 0, W - 1)]);
+                for (int u = 0; u < 4; ++u) {
+                    const int e = e0 + u * 256 + int(threadIdx.x);
+                    const int r = int((float(e) + 0.5f) * rnw), j = e - r * nw;
+                    const int gx = ax0 + 4 * j;
+                    const uint8_t* row = src + size_t(clampi(g.ry0 + r, 0, H - 1)) * pitch;
+                    if (e < n_w) {
+                        if (gx >= 0 && gx + 3 < W) {
+                            wv[u] = *reinterpret_cast<const uint32_t*>(row + gx);
+                        } else {
+                            wv[u] = 0;
+#pragma unroll
+                            for (int b = 0; b < 4; ++b) wv[u] |= uint32_t(row[clampi(gx + b, 0, W - 1)]) << (8 * b);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int e = e0 + u * 256 + int(threadIdx.x);
+                    const int r = int((float(e) + 0.5f) * rnw), j = e - r * nw;
+                    const int c0 = ax0 + 4 * j - g.rx0;
+                    if (e < n_w) {
+#pragma unroll
+                        for (int b = 0; b < 4; ++b)
+                            if (c0 + b >= 0 && c0 + b < g.rw) btile[r * g.stride + c0 + b] = float((wv[u] >> (8 * b)) & 0xFFu);
+                    }
+                }
             }
+        } else {
+            // loads are issued 8 per thread before any is stored, so their latencies overlap;
+            // r = e / rw through a float reciprocal is exact for e < 2^14 (see the warp's staging)
+            const int n_el = g.rw * g.rh;
+            const float rrw = 1.0f / float(g.rw);
+            for (int e0 = 0; e0 < n_el; e0 += 8 * 256) {
+                float val[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + u * 256 + int(threadIdx.x);
-                const int r = int((float(e) + 0.5f) * rrw), c = e - r * g.rw;
-                if (e < n_el) btile[r * g.stride + c] = val[u];
+                for (int u = 0; u < 8; ++u) {
+                    const int e = e0 + u * 256 + int(threadIdx.x);
+                    const int r = int((float(e) + 0.5f) * rrw), c = e - r * g.rw;
+                    if (e < n_el) val[u] = float(src[size_t(clampi(g.ry0 + r, 0, H - 1)) * pitch + clampi(g.rx0 + c, 0, W - 1)]);
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int e = e0 + u * 256 + int(threadIdx.x);
+                    const int r = int((float(e) + 0.5f) * rrw), c = e - r * g.rw;
+                    if (e < n_el) btile[r * g.stride + c] = val[u];
+                }
             }
         }
         __syncthreads();
