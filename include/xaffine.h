@@ -51,7 +51,7 @@ typedef enum {
 } xa_status;
 
 #define XA_PLAN_MAGIC 0x58414650u   /* "XAFP" */
-#define XA_PLAN_VERSION 4u
+#define XA_PLAN_VERSION 5u
 #define XA_MAX_LEVELS 12
 #define XA_MAX_QUOTA 2048           /* keypoints per pyramid level */
 #define XA_MAX_FEATURES 4096        /* keypoints per view */
@@ -104,6 +104,9 @@ typedef struct {
     int32_t blur_tap0;          /* first entry in the tap table */
     int32_t blur_ntaps;         /* 2K + 1, 0 if no blur */
     int32_t interp;             /* XA_INTERP_LANCZOS4 (eqs. (3)-(4)) or XA_INTERP_NEAREST */
+    int32_t warp_ls_mod;        /* residue mod 64 of the row stride (floats) of the warp's LDS source tile,
+                                   chosen by the planner to spread the 8 x 8 sums' reads over the LDS banks */
+    int32_t reserved;
 } xa_view_desc;
 
 #define XA_INTERP_LANCZOS4 0

@@ -121,7 +121,7 @@ struct BlurTap {
     int32_t dmin;   // floor(k m): whole-pixel step along the minor axis
 };
 static_assert(sizeof(BlurTap) == 16, "tap layout");
-static_assert(sizeof(xa_view_desc) == 248, "view desc layout");
+static_assert(sizeof(xa_view_desc) == 256, "view desc layout");
 static_assert(sizeof(xa_source_desc) == 32, "source desc layout");
 static_assert(sizeof(xa_level_desc) == 56, "level desc layout");
 static_assert(sizeof(xa_plan_header) == 168, "plan header layout");

@@ -1,9 +1,12 @@
 // Host-side planning: the sampling grid of Sec. III.B, the view maps of eq. (2),
 // anti-alias taps, pyramid levels, keypoint quotas and the arena / tile layout.
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <vector>
 
 #include "internal.h"
@@ -140,6 +143,95 @@ struct Planned {
     std::vector<BlurTap> taps;
 };
 
+// Residue mod 64 of the row stride (floats) of the warp's LDS source tile for a view.  A wave
+// reads tap (j, i) of its 64 pixels at base_l + j ls + i, two dwords per lane (i, i + 1); every
+// tap's pattern over the banks is the same up to a shift, so one read of the wave's base
+// addresses stands for all of them.  Its cost is the most distinct dwords one of the 64 banks
+// (4 bytes each) serves, at least 2 for 128 dwords; the residue with the least cost summed over
+// the waves and pixel rows of two interior sample tiles wins, the smallest on ties.  The tile
+// footprint and the stride follow the kernel: ls = w + ((mod - w) & 63) for the footprint width
+// w (16-byte chunks), or w | 1 where that would not fit the LDS stage.
+int warp_ls_mod(const xa_view_desc& v) {
+    if (v.interp != XA_INTERP_LANCZOS4) return 1;
+    const int tw = v.warp_tile_w, th = kWarpRows * kWarpThreads / tw;
+    const int W = v.src_w, H = v.src_h;
+    const int tiles_x = (v.width + tw - 1) / tw, tiles_y = (v.height + th - 1) / th;
+    struct Sample {
+        int width, bh;
+        std::vector<int> rr, cc;   // per wave-row group of 64 lanes: row and column offsets, -1 = unused lane
+    };
+    std::vector<Sample> samples;
+    const int picks[2][2] = {{tiles_x / 3, tiles_y / 3}, {(2 * tiles_x) / 3, (2 * tiles_y) / 3}};
+    for (const auto& pk : picks) {
+        const int x0 = pk[0] * tw, y0 = pk[1] * th;
+        const double* m = v.inv;
+        const double ox = m[0] * (tw - 1), oy = m[1] * (th - 1), o2x = m[3] * (tw - 1), o2y = m[4] * (th - 1);
+        const double cx0 = m[0] * x0 + m[1] * y0 + m[2], cy0 = m[3] * x0 + m[4] * y0 + m[5];
+        const double pxl = cx0 + std::min(ox, 0.0) + std::min(oy, 0.0), pxh = cx0 + std::max(ox, 0.0) + std::max(oy, 0.0);
+        const double pyl = cy0 + std::min(o2x, 0.0) + std::min(o2y, 0.0), pyh = cy0 + std::max(o2x, 0.0) + std::max(o2y, 0.0);
+        const int bx0 = std::max(int(std::fmax(std::floor(pxl - 1e-6), -1e9)) - 3, 0);
+        const int bx1 = std::min(int(std::fmin(std::floor(pxh + 1e-6), 1e9)) + 4, W - 1);
+        const int by0 = std::max(int(std::fmax(std::floor(pyl - 1e-6), -1e9)) - 3, 0);
+        const int by1 = std::min(int(std::fmin(std::floor(pyh + 1e-6), 1e9)) + 4, H - 1);
+        if (bx1 < bx0 || by1 < by0) continue;
+        const int ax0 = bx0 & ~3;
+        Sample sm;
+        sm.width = (((bx1 - ax0) >> 2) + 1) * 4;
+        sm.bh = by1 - by0 + 1;
+        for (int t = 0; t < kWarpThreads; ++t)
+            for (int k = 0; k < kWarpRows; ++k) {
+                const int qx = x0 + t % tw, qy = y0 + t / tw + k * (kWarpThreads / tw);
+                const double px = m[0] * qx + m[1] * qy + m[2], py = m[3] * qx + m[4] * qy + m[5];
+                const bool ok = qx < v.width && qy < v.height && px >= -0.5 && px <= W - 0.5 && py >= -0.5 &&
+                                py <= H - 0.5;
+                sm.rr.push_back(ok ? int(std::floor(py)) - 3 - by0 : -1);
+                sm.cc.push_back(ok ? int(std::floor(px)) - 3 - ax0 : 0);
+            }
+        samples.push_back(std::move(sm));
+    }
+    if (samples.empty()) return 1;
+    int best_mod = 1;
+    long best = -1;
+    // dwords already counted in the current read: a flag per footprint float (reads of border
+    // pixels start up to 3 rows and columns before the staged box: offset into range)
+    std::vector<uint8_t> seen(size_t(kWarpLds) * 2 + 4096, 0);
+    std::vector<int> touched;
+    touched.reserve(128);
+    for (int mod = 0; mod < 64; ++mod) {
+        long cost = 0;
+        for (const Sample& sm : samples) {
+            int ls = sm.width + ((mod - sm.width) & 63);
+            if (int64_t(ls) * sm.bh > kWarpLds) ls = sm.width | 1;
+            // lanes of one wave and pixel row: entries (wave * 64 + lane) * kWarpRows + k
+            for (int wv = 0; wv < kWarpThreads / 64; ++wv)
+                for (int k = 0; k < kWarpRows; ++k) {
+                    int count[64] = {0};
+                    int worst = 2;
+                    for (int lane = 0; lane < 64; ++lane) {
+                        const size_t e = size_t(wv * 64 + lane) * kWarpRows + k;
+                        if (sm.rr[e] < 0) continue;
+                        const int a = sm.rr[e] * ls + sm.cc[e];
+                        for (int d = 0; d < 2; ++d) {
+                            const long slot = long(a + d) + 2048;
+                            if (slot < 0 || slot >= long(seen.size()) || seen[size_t(slot)]) continue;
+                            seen[size_t(slot)] = 1;
+                            touched.push_back(int(slot));
+                            worst = std::max(worst, ++count[(a + d) & 63]);
+                        }
+                    }
+                    for (int sl : touched) seen[size_t(sl)] = 0;
+                    touched.clear();
+                    cost += worst;
+                }
+        }
+        if (best < 0 || cost < best) {
+            best = cost;
+            best_mod = mod;
+        }
+    }
+    return best_mod;
+}
+
 Planned plan_one(const xa_source_desc& src, int32_t source, const xa_affine_params& p) {
     Planned out{};
     xa_view_desc& v = out.v;
@@ -272,6 +364,7 @@ extern "C" xa_status xa_plan_views(const xa_source_desc* sources, int32_t n_sour
     int64_t arena = 0, cand = 0, blur_floats = 0;
     int64_t warp_tiles = 0, vl_tiles = 0, blur_tiles = 0;
     std::vector<int64_t> lvl_tiles(n_levels, 0);
+    std::map<std::array<double, 5>, int> ls_cache;
     for (int i = 0; i < n_views; ++i) {
         xa_view_desc& v = pv[i].v;
         if (v.sigma > 0.0) {
@@ -285,6 +378,14 @@ extern "C" xa_status xa_plan_views(const xa_source_desc* sources, int32_t n_sour
         }
         warp_prefix[i] = int32_t(warp_tiles);
         v.warp_tile_w = warp_tile_w(v.p.t, v.p.s);
+        {   // the residue depends on the view's linear map and tile width (the sources' sizes only
+            // move the sample tiles): views that share them, as the grid's views of many pairs
+            // do, share one search
+            const std::array<double, 5> key = {v.inv[0], v.inv[1], v.inv[3], v.inv[4], double(v.warp_tile_w)};
+            auto it = ls_cache.find(key);
+            if (it == ls_cache.end()) it = ls_cache.emplace(key, warp_ls_mod(v)).first;
+            v.warp_ls_mod = it->second;
+        }
         const int th = kWarpRows * kWarpThreads / v.warp_tile_w;
         warp_tiles += int64_t((v.width + v.warp_tile_w - 1) / v.warp_tile_w) * ((v.height + th - 1) / th);
         int32_t kp_base = 0;

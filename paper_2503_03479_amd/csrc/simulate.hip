@@ -321,7 +321,11 @@ __global__ void __launch_bounds__(kWarpThreads) k_warp(const uint8_t* __restrict
     const int ax0 = vec ? (bx0 & ~3) : bx0;
     const int nc = vec ? ((bx1 - ax0) >> 2) + 1 : bx1 - bx0 + 1;      // chunks per row
     const int cw = vec ? 4 : 1;                                         // columns per chunk
-    const int ls = (nc * cw) | 1;            // odd LDS row stride: vertically adjacent taps fall in different banks
+    // LDS row stride: the planner's residue mod 64 (spreads the 8 x 8 sums' reads over the banks),
+    // or the odd width where that would not fit
+    const int wmin = nc * cw;
+    int ls = wmin + ((v.warp_ls_mod - wmin) & 63);
+    if ((long long)ls * bh > kWarpLds) ls = wmin | 1;
     const bool use_lds = bx1 >= bx0 && bh > 0 && (long long)ls * bh <= kWarpLds;
     if (use_lds) {
         // chunk e = r * nc + c; each thread starts at e = tid and steps by 256 = q * nc + rem

@@ -29,7 +29,7 @@ VIEW_DTYPE = np.dtype([("p", PARAMS_DTYPE), ("source", "i4"), ("src_w", "i4"), (
                        ("src_offset", "i8"), ("src_scale", "f8"), ("width", "i4"), ("height", "i4"), ("pitch", "i4"),
                        ("warp_tile_w", "i4"), ("fwd", "f8", 6), ("inv", "f8", 6), ("sigma", "f8"), ("ux", "f8"),
                        ("uy", "f8"), ("offset", "i8"), ("blur_offset", "i8"), ("blur_major", "i4"), ("blur_tap0", "i4"),
-                       ("blur_ntaps", "i4"), ("interp", "i4")])
+                       ("blur_ntaps", "i4"), ("interp", "i4"), ("warp_ls_mod", "i4"), ("reserved", "i4")])
 LEVEL_DTYPE = np.dtype([("width", "i4"), ("height", "i4"), ("pitch", "i4"), ("quota", "i4"), ("offset", "i8"),
                         ("kp_base", "i4"), ("view", "i4"), ("level", "i4"), ("pad", "i4"), ("cand_offset", "i8"),
                         ("cand_cap", "i8")])
@@ -44,7 +44,7 @@ TAP_DTYPE = np.dtype([("wa", "f4"), ("wb", "f4"), ("dmaj", "i4"), ("dmin", "i4")
 KEYPOINT_DTYPE = np.dtype([("x", "i4"), ("y", "i4"), ("level", "i4"), ("bin", "i4"), ("harris", "i8"),
                            ("xs", "f8"), ("ys", "f8")])
 MATCH_DTYPE = np.dtype([("t", "i4"), ("d1", "u2"), ("d2", "u2")])
-assert VIEW_DTYPE.itemsize == 248 and LEVEL_DTYPE.itemsize == 56 and KEYPOINT_DTYPE.itemsize == 40
+assert VIEW_DTYPE.itemsize == 256 and LEVEL_DTYPE.itemsize == 56 and KEYPOINT_DTYPE.itemsize == 40
 assert MATCH_DTYPE.itemsize == 8 and HEADER_DTYPE.itemsize == 168 and SOURCE_DTYPE.itemsize == 32
 
 
