@@ -16,9 +16,14 @@ constexpr int kWarpRows = 2;                // view pixels per warp thread (tile
 constexpr int kWarpLds = 8192;              // floats of source footprint a warp tile can stage in LDS
 constexpr int kPyrTX = 256, kPyrTY = 16;    // pyramid down-sampling (4 x 4 output pixels per thread)
 constexpr int kFastTX = 64, kFastTY = 32;   // FAST / NMS / smoothing / Harris tiles (256 threads, 8 rows each)
-constexpr int kBlurTX = 64, kBlurTY = 16;   // directional blur over the source (4 rows per thread)
+constexpr int kBlurTX = 64, kBlurTY = 16;   // directional blur over the source, taps along x (4 rows per thread)
 constexpr int kBlurStride = 128;            // LDS row stride (floats) of a major-x blur tile
 constexpr int kBlurLdsMax = 16384;          // floats of source a blur tile may stage in LDS (64 KiB)
+// Blur tiles: 64 x 16 when the taps step along x (a wave's lanes take 64 columns of one row
+// group), 16 x 64 when they step along y (a wave's lanes take 64 rows of one 4-column group, so
+// each tap read hits 64 rows, one per LDS bank at the odd row stride).
+__host__ __device__ inline int blur_tile_w(int major) { return major == 0 ? kBlurTX : kBlurTY; }
+__host__ __device__ inline int blur_tile_h(int major) { return major == 0 ? kBlurTY : kBlurTX; }
 
 // Warp tile width for a view: the output tile is w x (512 / w), narrow along the compressed
 // axis so that its source footprint stays compact.

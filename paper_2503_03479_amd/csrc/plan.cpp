@@ -374,7 +374,8 @@ extern "C" xa_status xa_plan_views(const xa_source_desc* sources, int32_t n_sour
             taps.insert(taps.end(), pv[i].taps.begin(), pv[i].taps.end());
             blur_views.push_back(i);
             blur_prefix.push_back(int32_t(blur_tiles));
-            blur_tiles += int64_t((v.src_w + kBlurTX - 1) / kBlurTX) * ((v.src_h + kBlurTY - 1) / kBlurTY);
+            const int btw = blur_tile_w(v.blur_major), bth = blur_tile_h(v.blur_major);
+            blur_tiles += int64_t((v.src_w + btw - 1) / btw) * ((v.src_h + bth - 1) / bth);
         }
         warp_prefix[i] = int32_t(warp_tiles);
         v.warp_tile_w = warp_tile_w(v.p.t, v.p.s);

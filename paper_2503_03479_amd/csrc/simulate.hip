@@ -39,21 +39,23 @@ struct BlurRegion {
 __host__ __device__ inline BlurRegion blur_region(const xa_view_desc& v, const BlurTap* tp, int x0, int y0) {
     const int n = v.blur_ntaps, K = (n - 1) / 2;
     const int dlo = min(tp[0].dmin, tp[n - 1].dmin), dhi = max(tp[0].dmin, tp[n - 1].dmin) + 1;
+    const int tw = blur_tile_w(v.blur_major), th = blur_tile_h(v.blur_major);
     BlurRegion r;
     if (v.blur_major == 0) {
-        r.rx0 = x0 - K; r.rw = kBlurTX + 2 * K;
-        r.ry0 = y0 + dlo; r.rh = kBlurTY + dhi - dlo;
+        r.rx0 = x0 - K; r.rw = tw + 2 * K;
+        r.ry0 = y0 + dlo; r.rh = th + dhi - dlo;
         r.stride = kBlurStride;           // the interpolation partner is one row down: a fixed offset
     } else {
-        r.rx0 = x0 + dlo; r.rw = kBlurTX + dhi - dlo;
-        r.ry0 = y0 - K; r.rh = kBlurTY + 2 * K;
+        r.rx0 = x0 + dlo; r.rw = tw + dhi - dlo;
+        r.ry0 = y0 - K; r.rh = th + 2 * K;
         r.stride = r.rw | 1;              // the partner is the next column; odd stride spreads rows over banks
     }
     r.floats = (v.blur_major == 0 && r.rw > kBlurStride) ? (1 << 30) : r.stride * r.rh;
     return r;
 }
 
-// Directional Gaussian over the source, one block per 64 x 16 tile of one blurred view.
+// Directional Gaussian over the source, one block per 64 x 16 tile of one blurred view (16 x 64
+// when the taps step along y).
 // out(p) = sum_k w_k lerp(I, p + k v), v = (1, m) (major x) or (m, 1) (major y), written as
 // sum_k wa_k I(p + k v_whole) + wb_k I(p + k v_whole + e_minor).  The tile's source footprint
 // is staged in LDS as fp32 with the border replicated at load time (the same as clamping
@@ -70,9 +72,10 @@ __global__ void __launch_bounds__(256) k_blur(const uint8_t* __restrict__ source
     const int W = v.src_w, H = v.src_h, pitch = v.src_pitch;
     const uint8_t* src = sources + v.src_offset;
     const int local = blockIdx.x - blur_prefix[bi];
-    const int tiles_x = (W + kBlurTX - 1) / kBlurTX;
-    const int x0 = (local % tiles_x) * kBlurTX, y0 = (local / tiles_x) * kBlurTY;
-    const int tx = threadIdx.x % kBlurTX, ty0 = threadIdx.x / kBlurTX;
+    const int btw = blur_tile_w(v.blur_major), bth = blur_tile_h(v.blur_major);
+    const int tiles_x = (W + btw - 1) / btw;
+    const int x0 = (local % tiles_x) * btw, y0 = (local / tiles_x) * bth;
+    const int tx = threadIdx.x % btw, ty0 = threadIdx.x / btw;
     const BlurTap* tp = taps + v.blur_tap0;
     const int n = v.blur_ntaps;
     const BlurRegion g = blur_region(v, tp, x0, y0);
@@ -170,7 +173,7 @@ __global__ void __launch_bounds__(256) k_blur(const uint8_t* __restrict__ source
                 if (y + 3 < H) op[3 * bp] = a3;
             }
         } else {
-            const int r = threadIdx.x & 15, cg = threadIdx.x >> 4;         // row, group of 4 columns
+            const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;         // row, group of 4 columns
             const int x = x0 + 4 * cg, y = y0 + r;
             if (x < W && y < H) {
                 const float* base = btile + (y - g.ry0) * g.stride + (x - g.rx0);
@@ -200,8 +203,8 @@ __global__ void __launch_bounds__(256) k_blur(const uint8_t* __restrict__ source
         return;
     }
     // footprint larger than the LDS tile (very large sigma): read the taps from global memory
-    for (int j = 0; j < kBlurTY / 4; ++j) {
-        const int x = x0 + tx, y = y0 + ty0 + 4 * j;
+    for (int j = 0; j < (btw * bth) / 256; ++j) {
+        const int x = x0 + tx, y = y0 + ty0 + (256 / btw) * j;
         if (x >= W || y >= H) continue;
         float acc = 0.0f;
         if (v.blur_major == 0) {
