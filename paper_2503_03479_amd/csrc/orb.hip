@@ -75,8 +75,9 @@ constexpr int kPyrLH = 24;         // staged source rows (16 output rows span at
 // Level l of every view from level l-1: (sum_{2x2} wy wx pix + 2^21) >> 22; the content
 // mask of a level pixel is the AND over its 2x2 footprint.  One block per 256 x 16 output
 // tile, so that its set-up (prefix search, resampling positions, staging) serves 4096 pixels;
-// each thread writes four 32-bit words (4 pixels each) on rows ty, ty + 4, ty + 8, ty + 12;
-// the source rows the tile reads are staged in LDS in 16-byte chunks.
+// each thread writes columns tx + 64 k (k = 0..3) on rows ty, ty + 4, ty + 8, ty + 12, so that
+// a wave's lanes read neighbouring source bytes (one pass over the LDS banks) and store 64
+// consecutive bytes; the source rows the tile reads are staged in LDS in 16-byte chunks.
 __global__ void __launch_bounds__(256) k_pyr(const xa_level_desc* __restrict__ levels, int n_levels, int l,
                                              const int32_t* __restrict__ prefix, int n_views,
                                              uint8_t* __restrict__ arena, uint8_t* __restrict__ mask) {
@@ -111,14 +112,14 @@ __global__ void __launch_bounds__(256) k_pyr(const xa_level_desc* __restrict__ l
     }
     __syncthreads();
     const int tx = t & 63, ty = t >> 6;
-    const int xb = X0 + 4 * tx;
-    if (xb >= d.width) return;
-    // the thread's 4 source columns and weights, the same for all of its rows
-    const int nk = min(4, d.width - xb);
+    if (X0 + tx >= d.width) return;
+    // the thread's columns tx + 64 k: a wave's lanes read neighbouring source bytes
     int cx0[4], cx1[4], cw0[4], cw1[4];
+    bool cv_ok[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const int cv = k < nk ? scol[4 * tx + k] : 0;
+        cv_ok[k] = X0 + tx + 64 * k < d.width;
+        const int cv = cv_ok[k] ? scol[tx + 64 * k] : 0;
         cx0[k] = cv >> 11;
         cw1[k] = cv & 2047;
         cw0[k] = 2048 - cw1[k];
@@ -130,10 +131,10 @@ __global__ void __launch_bounds__(256) k_pyr(const xa_level_desc* __restrict__ l
         if (y >= d.height) break;
         const int rv = srow[yr];
         const int y0 = rv >> 11, wy1 = rv & 2047, wy0 = 2048 - wy1, y1 = min(y0 + 1, p.height - 1);
-        uint32_t pix = 0, msk = 0;
+        const size_t o = size_t(d.offset) + size_t(y) * d.pitch + X0 + tx;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            if (k >= nk) break;
+            if (!cv_ok[k]) break;
             const int x0 = cx0[k], wx1 = cw1[k], wx0 = cw0[k], x1 = cx1[k];
             int p00, p01, p10, p11, m;
             if (staged) {
@@ -153,14 +154,9 @@ __global__ void __launch_bounds__(256) k_pyr(const xa_level_desc* __restrict__ l
             }
             const int top = wx0 * p00 + wx1 * p01;
             const int bot = wx0 * p10 + wx1 * p11;
-            const int out = (wy0 * top + wy1 * bot + (1 << 21)) >> 22;
-            pix |= uint32_t(out) << (8 * k);
-            msk |= uint32_t(m & 1) << (8 * k);
+            arena[o + 64 * k] = uint8_t((wy0 * top + wy1 * bot + (1 << 21)) >> 22);
+            mask[o + 64 * k] = uint8_t(m & 1);
         }
-        // xb is a multiple of 4 below the width, so the word lies inside the 16-byte padded row
-        const size_t o = size_t(d.offset) + size_t(y) * d.pitch + xb;
-        *reinterpret_cast<uint32_t*>(arena + o) = pix;
-        *reinterpret_cast<uint32_t*>(mask + o) = msk;
     }
 }
 
