@@ -258,3 +258,22 @@ def test_scaled_grid_matches_oracle_and_interp_switch():
     assert np.all(X.plan_image(64, 48, X.make_params([(2.0, 0.5)]), 2, 1.2, 50, 20).views["interp"] == 0)
     with pytest.raises(X.XAError):
         X._check(X.lib().xa_plan_set_interp(p.blob.ctypes.data, 7))
+
+
+def test_warp_stride_residues(L):
+    """The planner's LDS row-stride residue of each view: in 0..63, the same for views that share
+    a linear map and tile width (one search per map), and deterministic."""
+    g = X.sampling_grid(5)
+    p1 = X.plan_image(1024, 768, g, 8, 1.2, 1000, 20)
+    p2 = X.plan_image(1024, 768, g, 8, 1.2, 1000, 20)
+    p3 = X.plan_image(900, 700, g, 8, 1.2, 1000, 20)
+    m1 = p1.views["warp_ls_mod"]
+    assert ((m1 >= 0) & (m1 < 64)).all()
+    assert np.array_equal(m1, p2.views["warp_ls_mod"])
+    assert (p1.views["reserved"] == 0).all()
+    # a second image size gives the same linear maps: each residue lies in 0..63 there too
+    assert ((p3.views["warp_ls_mod"] >= 0) & (p3.views["warp_ls_mod"] < 64)).all()
+    # duplicated grid views share the residue
+    rows = [(2.0, 0.5), (2.0, 0.5), (1.0, 0.0)]
+    p4 = X.plan_image(300, 200, X.make_params(rows), 3, 1.2, 100, 20)
+    assert p4.views["warp_ls_mod"][0] == p4.views["warp_ls_mod"][1]
