@@ -59,14 +59,14 @@ __device__ __forceinline__ uint32_t udot4(uint32_t a, uint32_t b, uint32_t c) {
 
 // Block (query block qb, train slice blockIdx.y): 256 queries against the slice's train rows,
 // chunk by chunk; the two best (value, index) per query of the slice go to part[slice][query].
-// Operand layout: slice s of lane (h = lane / 32, m = lane % 32) is bytes 32 s + 16 h .. + 15 of
+// Operand layout: K-step s of lane (h = lane / 32, m = lane % 32) is bytes 32 s + 16 h .. + 15 of
 // descriptor m of the tile, for both operands, so the contraction pairs equal components
 // whatever order the hardware gives the 16 bytes.  Result r of the lane is tile row
 // 8 (r / 4) + 4 h + r % 4 of query column m.
 __global__ void __launch_bounds__(kL2Threads)
 k_match_l2(const uint4* __restrict__ q, int nq, const uint4* __restrict__ t, int nt, int chunks_per_slice,
            int4* __restrict__ part) {
-    __shared__ uint4 tr[(kL2Chunk / 32) * 4 * 64];      // [tile][slice][lane]
+    __shared__ uint4 tr[(kL2Chunk / 32) * 4 * 64];      // [tile][K-step][lane]
     __shared__ __align__(16) int t7[kL2Chunk];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, h = lane >> 5, m = lane & 31;
     const int qw = blockIdx.x * kL2BlockQ + wv * 32 * kL2QT;   // this wave's first query
@@ -98,7 +98,7 @@ k_match_l2(const uint4* __restrict__ q, int nq, const uint4* __restrict__ t, int
             uint32_t sq = 0, s1 = 0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const int c = hf * 4 + k;                 // piece c: slice c / 2, half c % 2
+                const int c = hf * 4 + k;                 // piece c: K-step c / 2, half c % 2
                 const uint4 w = live ? nx[k] : make_uint4(0, 0, 0, 0);
                 sq = udot4(w.x, w.x, udot4(w.y, w.y, udot4(w.z, w.z, udot4(w.w, w.w, sq))));
                 s1 = udot4(w.x, 0x01010101u, udot4(w.y, 0x01010101u, udot4(w.z, 0x01010101u, udot4(w.w, 0x01010101u, s1))));
