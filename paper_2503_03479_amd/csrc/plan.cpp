@@ -146,9 +146,11 @@ struct Planned {
 // Residue mod 64 of the row stride (floats) of the warp's LDS source tile for a view.  A wave
 // reads tap (j, i) of its 64 pixels at base_l + j ls + i, two dwords per lane (i, i + 1); every
 // tap's pattern over the banks is the same up to a shift, so one read of the wave's base
-// addresses stands for all of them.  Its cost is the most distinct dwords one of the 64 banks
-// (4 bytes each) serves, at least 2 for 128 dwords; the residue with the least cost summed over
-// the waves and pixel rows of two interior sample tiles wins, the smallest on ties.  The tile
+// addresses stands for all of them.  The LDS serves a wave in two halves of 32 lanes over 32
+// banks of 4 bytes, so a read costs, per half, the most distinct dwords one bank serves (at
+// least 2 for 64 dwords); the residue with the least cost summed over the halves, waves and
+// pixel rows of two interior sample tiles wins, the smallest on ties.  (This model matched the
+// measured change of the LDS cycles, where one pass over 64 banks underestimated them.)  The tile
 // footprint and the stride follow the kernel: ls = w + ((mod - w) & 63) for the footprint width
 // w (16-byte chunks), or w | 1 where that would not fit the LDS stage.
 int warp_ls_mod(const xa_view_desc& v) {
@@ -204,25 +206,26 @@ int warp_ls_mod(const xa_view_desc& v) {
             if (int64_t(ls) * sm.bh > kWarpLds) ls = sm.width | 1;
             // lanes of one wave and pixel row: entries (wave * 64 + lane) * kWarpRows + k
             for (int wv = 0; wv < kWarpThreads / 64; ++wv)
-                for (int k = 0; k < kWarpRows; ++k) {
-                    int count[64] = {0};
-                    int worst = 2;
-                    for (int lane = 0; lane < 64; ++lane) {
-                        const size_t e = size_t(wv * 64 + lane) * kWarpRows + k;
-                        if (sm.rr[e] < 0) continue;
-                        const int a = sm.rr[e] * ls + sm.cc[e];
-                        for (int d = 0; d < 2; ++d) {
-                            const long slot = long(a + d) + 2048;
-                            if (slot < 0 || slot >= long(seen.size()) || seen[size_t(slot)]) continue;
-                            seen[size_t(slot)] = 1;
-                            touched.push_back(int(slot));
-                            worst = std::max(worst, ++count[(a + d) & 63]);
+                for (int k = 0; k < kWarpRows; ++k)
+                    for (int half = 0; half < 2; ++half) {
+                        int count[32] = {0};
+                        int worst = 2;
+                        for (int lane = 32 * half; lane < 32 * half + 32; ++lane) {
+                            const size_t e = size_t(wv * 64 + lane) * kWarpRows + k;
+                            if (sm.rr[e] < 0) continue;
+                            const int a = sm.rr[e] * ls + sm.cc[e];
+                            for (int d = 0; d < 2; ++d) {
+                                const long slot = long(a + d) + 2048;
+                                if (slot < 0 || slot >= long(seen.size()) || seen[size_t(slot)]) continue;
+                                seen[size_t(slot)] = 1;
+                                touched.push_back(int(slot));
+                                worst = std::max(worst, ++count[(a + d) & 31]);
+                            }
                         }
+                        for (int sl : touched) seen[size_t(sl)] = 0;
+                        touched.clear();
+                        cost += worst;
                     }
-                    for (int sl : touched) seen[size_t(sl)] = 0;
-                    touched.clear();
-                    cost += worst;
-                }
         }
         if (best < 0 || cost < best) {
             best = cost;
