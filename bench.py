@@ -71,7 +71,7 @@ K_WARP_TRAFFIC = {
                 "paper_2503_03479_amd/csrc/lanczos.h"],
     "sha256": "6b1a7454f695fd702a7325303ef8da02a9e78dd1565c9bf834e20b66cf9f9c27",   # of the sources, concatenated
     "fetch_scale": 2.0, "write_scale": 1.0,
-    "kib": (109316.9, 67576.7),   # (fetch, write) per launch
+    "kib": (109318.1, 67583.2),   # (fetch, write) per launch
 }
 WARP_OPS_PER_PX = 72 + 16         # 64 + 8 multiply-adds of the 8 x 8 sum and the 16 kernel weights per view pixel
 
