@@ -188,17 +188,28 @@ class PairCase:
 
 
 def make_pair(width: int, height: int, n_blobs: int, n_rects: int, seed: int,
-              t: float, phi: float, psi: float, supersample: int = 4, name: str = "pair") -> PairCase:
-    """A = the scene seen head-on; B = the scene after a tilt t along longitude phi and a rotation psi."""
+              t: float, phi: float, psi: float, supersample: int = 4, name: str = "pair",
+              t_a: float = 1.0, phi_a: float = 0.0) -> PairCase:
+    """A = the scene seen head-on, or after a tilt t_a along longitude phi_a when t_a > 1;
+    B = the scene after a tilt t along longitude phi and a rotation psi.  Each image covers the
+    bounding box of the transformed scene."""
     sc = make_scene(width, height, n_blobs, n_rects, seed)
-    A = render(sc, np.eye(2), np.zeros(2), width, height, noise_seed=seed * 7919 + 1, supersample=supersample)
+    if t_a == 1.0:
+        MA, offa = np.eye(2), np.zeros(2)
+        A = render(sc, MA, offa, width, height, noise_seed=seed * 7919 + 1, supersample=supersample)
+    else:
+        MA = tilt_rotation(t_a, phi_a, 0.0)
+        aw, ah, offa = affine_canvas(MA, width, height)
+        A = render(sc, MA, offa, aw, ah, noise_seed=seed * 7919 + 1, supersample=supersample)
     M = tilt_rotation(t, phi, psi)
     bw, bh, off = affine_canvas(M, width, height)
     B = render(sc, M, off, bw, bh, noise_seed=seed * 7919 + 2, supersample=supersample)
+    # pB = M pS + off and pA = MA pS + offa  =>  pB = M MA^-1 (pA - offa) + off
+    L = M @ np.linalg.inv(MA)
     H = np.eye(3)
-    H[:2, :2] = M
-    H[:2, 2] = off
-    return PairCase(name, A, B, H, dict(t=t, phi=phi, psi=psi, seed=seed))
+    H[:2, :2] = L
+    H[:2, 2] = off - L @ offa
+    return PairCase(name, A, B, H, dict(t=t, phi=phi, psi=psi, seed=seed, t_a=t_a, phi_a=phi_a))
 
 
 # Workload definitions (image sizes, scene density, ground-truth camera change).
@@ -207,6 +218,12 @@ PAIR_CONFIGS = {
     "tiny": dict(width=256, height=256, n_blobs=40, n_rects=30, seed=1, t=2.0, phi=0.0, psi=math.radians(30.0)),
     # 1024x768, 400 blobs, 300 rectangles; B: absolute tilt 4 (~75.5 deg), rotation 45 deg.
     "full": dict(width=1024, height=768, n_blobs=400, n_rects=300, seed=2, t=4.0, phi=0.0, psi=math.radians(45.0)),
+    # 4096x3072, 4000 blobs, 3000 rectangles; A and B: absolute tilt 80 deg (t = 1 / cos 80 deg =
+    # 5.76), A compressed along x, B along y (tilt along longitude 90 deg, turned back by -90 deg),
+    # so the transition tilt from A to B is t^2 = 33.2 (88.3 deg).
+    "stress": dict(width=4096, height=3072, n_blobs=4000, n_rects=3000, seed=4,
+                   t_a=1.0 / math.cos(math.radians(80.0)), phi_a=0.0,
+                   t=1.0 / math.cos(math.radians(80.0)), phi=math.radians(90.0), psi=math.radians(-90.0)),
 }
 
 

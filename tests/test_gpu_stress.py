@@ -1,0 +1,206 @@
+"""GPU: the large-view stress pair, checked against the oracle on samples it computes in seconds.
+
+Workload: a 4096 x 3072 scene (4000 blobs, 3000 rectangles) seen under absolute tilt 80 deg
+(t = 5.76) along x in A (712 x 3072) and along y in B (4096 x 534), a transition tilt of 33.2
+(88.3 deg); the 94-view grid of tilts up to 8 sqrt(2) at longitude step 72 deg / t, on sources
+at scales {1, 0.5, 0.25}: 282 views per image, 79524 view pairs, 2000 keypoints per view,
+8 levels at 1.2, FAST threshold 20, ratio 4/5, run by the batched entry point with the
+matrix-core matcher.
+
+- The batched run equals the stand-alone stages (scale, simulate, extract) on its own plan.
+- Scaled sources: the four scaled images against the oracle's scale stage.
+- Views: five views (tilts 1 to 8 sqrt(2), all three scales, both images) against the oracle's
+  simulation of the oracle's source at that scale, to the tolerance of the small-size tests.
+- ORB: bit-exact on the GPU's own level-0 views of two views.
+- Matching: bit-exact on six sampled view pairs, including the best.
+- The best pair is the argmax of all 79524 pair counts, lowest index on ties."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import match as OM
+from oracle import orb as OO
+from oracle import plan as OP
+from oracle import simulate as OS
+
+torch = pytest.importorskip("torch")
+X = pytest.importorskip("paper_2503_03479_amd.xaffine")
+
+pytestmark = pytest.mark.gpu
+
+N, LEVELS, FAST_T, N_TILT = 2000, 8, 20, 7
+SCALES = (1.0, 0.5, 0.25)
+WARP_TOL = 1e-4 * 255.0
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    X.lib()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def stress(dev):
+    t0 = time.time()
+    say("case: stress pair 4096x3072 scene, tilts 80 deg along x and y, grid of 7 tilts, scales 1/0.5/0.25")
+    case = synth.make_pair(**synth.PAIR_CONFIGS["stress"])
+    A, B = np.ascontiguousarray(case.A), np.ascontiguousarray(case.B)
+    say(f"[stress] generated A {A.shape} B {B.shape} in {time.time() - t0:.1f} s")
+    grid_np = X.sampling_grid(N_TILT)
+    grid = [(float(r["t"]), float(r["phi"])) for r in grid_np]
+    pattern_np = synth.brief_pattern()
+    pattern = torch.from_numpy(pattern_np).to(dev)
+    run = X.BatchRunner([(A, B)], grid, SCALES, n_levels=LEVELS, n_features=N, fast_threshold=FAST_T,
+                        device=dev, queries_per_lane=X.MATCH_MATRIX)
+    assert len(run.chunks) == 1
+    src0 = run.sources.clone()
+    say(f"[stress] batch of {run.n_views} views, {run.mplan.total_pairs} view pairs, "
+        f"workspace {run.ws_bytes / 2**30:.2f} GiB; running")
+    run.run(pattern)
+    torch.cuda.synchronize()
+    say("[stress] batch done; running the stages one by one")
+    buf = src0
+    X.scale_sources(run.splan, buf)
+    arena, mask = X.simulate_views(run.chunks[0], buf)
+    kp, desc, count = X.extract_orb(run.chunks[0], arena, mask, pattern)
+    torch.cuda.synchronize()
+    say(f"[stress] stages done after {time.time() - t0:.1f} s")
+    return dict(A=A, B=B, grid=grid, pattern=pattern_np, run=run, buf=buf.cpu().numpy(),
+                arena=arena.cpu().numpy(), mask=mask.cpu().numpy(), kp=kp, desc=desc, count=count)
+
+
+def _view_index(side, k, i, n_grid):
+    """Batch order: A's views then B's; per image the sources by scale, per source the grid."""
+    return (0 if side == "a" else len(SCALES) * n_grid) + k * n_grid + i
+
+
+def _source_index(side, k):
+    """Source arena order: A, A at 0.5, A at 0.25, B, B at 0.5, B at 0.25."""
+    return (0 if side == "a" else len(SCALES)) + k
+
+
+def test_stress_batch_equals_stages(stress):
+    run = stress["run"]
+    assert torch.equal(run.count, stress["count"])
+    assert torch.equal(run.kp, stress["kp"]) and torch.equal(run.desc, stress["desc"])
+    c = run.count.cpu().numpy()
+    say(f"[stress] batch == stages; keypoints {int(c.sum())} (min {c.min()}, max {c.max()} per view)")
+    # views that tilt a side further along its own compression are a few pixels across: the
+    # counts run from the full quota down to zero
+    assert c.max() == N and c.min() == 0
+
+
+@pytest.mark.parametrize("side", ["a", "b"])
+def test_stress_scaled_sources(stress, side):
+    img = stress["A"] if side == "a" else stress["B"]
+    arena = stress["run"].arena
+    for k, s in enumerate(SCALES):
+        if s == 1.0:
+            continue
+        _, U = OS.scale_image(img, s)
+        g = arena.view(stress["buf"], _source_index(side, k))
+        assert g.shape == U.shape
+        du = np.abs(g.astype(np.int64) - U.astype(np.int64))
+        assert du.max() <= 1, (side, s)
+        n_bad = int((du > 0).sum())
+        assert n_bad <= max(1, 1e-4 * du.size), (side, s)
+        say(f"[stress scale {side} {s}] {U.shape[1]}x{U.shape[0]}: u8 mismatches {n_bad}/{du.size}")
+
+
+def _pick(grid, t, j):
+    """Index of the j-th grid view with tilt t."""
+    return [i for i, (ti, _) in enumerate(grid) if abs(ti - t) < 1e-9][j]
+
+
+# (image, scale index, tilt, j-th longitude at that tilt)
+VIEW_CASES = [("a", 0, 8 * 2 ** 0.5, 5), ("a", 2, 1.0, 0), ("a", 1, 2.0, 2), ("b", 1, 4 * 2 ** 0.5, 3),
+              ("b", 2, 8 * 2 ** 0.5, 11)]
+
+
+@pytest.mark.parametrize("side,k,t,j", VIEW_CASES)
+def test_stress_views_against_the_oracle(stress, side, k, t, j):
+    grid = stress["grid"]
+    i = _pick(grid, t, j)
+    img = stress["A"] if side == "a" else stress["B"]
+    src = img if SCALES[k] == 1.0 else OS.scale_image(img, SCALES[k])[1]
+    ti, phi = grid[i]
+    v = OP.plan_view(src.shape[1], src.shape[0], ti, phi, 0.0, 1.0)
+    say(f"case: stress view {side} s={SCALES[k]} t={ti:.3f} phi={np.degrees(phi):.1f} ({v.width}x{v.height})")
+    V, M, U = OS.simulate_view(src, v)
+    plan = stress["run"].chunks[0]
+    vi = _view_index(side, k, i, len(grid))
+    gu = plan.level_image(stress["arena"], vi, 0)
+    gm = plan.level_image(stress["mask"], vi, 0).astype(bool)
+    assert gu.shape == U.shape
+    px, py = OS.view_coords(v)
+    edge = (np.minimum(np.abs(px + 0.5), np.abs(px - (v.src_w - 0.5))) < 1e-9) | \
+           (np.minimum(np.abs(py + 0.5), np.abs(py - (v.src_h - 0.5))) < 1e-9)
+    assert np.all((gm == M) | edge)
+    both = gm & M
+    du = np.abs(gu[both].astype(np.int64) - U[both].astype(np.int64))
+    assert du.max(initial=0) <= 1
+    n_bad, n_px = int((du > 0).sum()), int(both.sum())
+    assert n_bad <= max(1, 1e-4 * n_px)
+    assert np.all(gu[~gm] == 0)
+    say(f"[stress view {side}{vi}] u8 mismatches {n_bad}/{n_px}")
+
+
+@pytest.mark.parametrize("side,k,t,j", [("a", 1, 2 * 2 ** 0.5, 4), ("b", 2, 1.0, 0)])
+def test_stress_orb_on_the_gpu_views(stress, side, k, t, j):
+    grid = stress["grid"]
+    i = _pick(grid, t, j)
+    plan = stress["run"].chunks[0]
+    vi = _view_index(side, k, i, len(grid))
+    U = plan.level_image(stress["arena"], vi, 0).copy()
+    M = plan.level_image(stress["mask"], vi, 0).astype(bool)
+    vd = plan.views[vi]
+    say(f"case: stress ORB on view {side}{vi} ({int(vd['width'])}x{int(vd['height'])})")
+    dims = OP.level_dims(int(vd["width"]), int(vd["height"]), LEVELS)
+    f = OO.extract_view(U, M, dims, OP.level_quotas(N, LEVELS), FAST_T, stress["pattern"])
+    n = len(f["x"])
+    g = X.keypoints_np(stress["run"].kp)[vi][:n]
+    assert int(stress["run"].count[vi]) == n
+    for key in ("x", "y", "level", "harris", "bin"):
+        assert np.array_equal(g[key], f[key]), key
+    assert np.array_equal(stress["run"].desc[vi].cpu().numpy()[:n], f["desc"])
+    say(f"[stress ORB {side}{vi}] {n} keypoints exact")
+
+
+def test_stress_matching_on_sampled_pairs(stress):
+    run = stress["run"]
+    a0, na, b0, nb = run.pair_views[0]
+    pc = run.pair_count.cpu().numpy()
+    k = int(np.argmax(pc))
+    rng = np.random.default_rng(17)
+    pairs = {(k // nb, k % nb)} | {(int(a), int(b)) for a, b in rng.integers(0, [na, nb], (5, 2))}
+    c = run.count.cpu().numpy()
+    d = run.desc.cpu().numpy()
+    for a, b in sorted(pairs):
+        res, counts, _ = OM.match_views([d[a0 + a][:c[a0 + a]]], [d[b0 + b][:c[b0 + b]]], 4, 5)
+        idx, d1, d2, _ = res[0]
+        kk = a * nb + b
+        nq = int(c[a0 + a])
+        m = X.matches_np(run.matches[kk:kk + 1])[0]
+        assert np.array_equal(m[:nq]["t"], idx) and np.array_equal(m[:nq]["d1"], d1), (a, b)
+        assert np.array_equal(m[:nq]["d2"], d2), (a, b)
+        assert pc[kk] == counts[0], (a, b)
+    say(f"[stress matching] exact on view pairs {sorted(pairs)}")
+
+
+def test_stress_best_pair_is_the_argmax(stress):
+    run = stress["run"]
+    pc = run.pair_count.cpu().numpy()
+    nb = run.pair_views[0][3]
+    k = int(np.argmax(pc))
+    assert run.best[0].tolist() == [k, k // nb, k % nb, int(pc[k])]
+    say(f"[stress best] pair {k} = views ({k // nb}, {k % nb}) with {int(pc[k])} matches")
