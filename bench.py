@@ -144,6 +144,16 @@ def progress(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
 
+def profiler_preloaded() -> bool:
+    """True when a profiler's tool library is preloaded into this process (rocprofv3 and its kin
+    set LD_PRELOAD and ROCPROF_* / ROCP_* variables).  Such a tool initialises the GPU before the
+    program starts, so this process must not start worker processes: each would be a fork and exec
+    of a process that has already touched the GPU."""
+    if "rocprof" in os.environ.get("LD_PRELOAD", ""):
+        return True
+    return any(k.startswith(("ROCPROF_", "ROCP_")) for k in os.environ)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -479,7 +489,11 @@ def main():
         sys.exit(2)
     import numpy as np
 
-    # the batched leg's pairs are rendered by worker processes before this process touches the GPU
+    # the batched leg's pairs are rendered by worker processes before this process touches the GPU,
+    # unless a profiler is preloaded (then everything runs in this process)
+    if profiler_preloaded() and args.gen_workers > 0:
+        progress("bench.py: profiler preloaded; rendering in this process (--gen-workers 0)")
+        args.gen_workers = 0
     raw, gen_s = [], 0.0
     if args.batch_pairs > 0 and args.only in (None, "batched"):
         t0 = time.perf_counter()
@@ -636,7 +650,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u8/fp32 warp, int32/int64 ORB and matching",
+        "dtype": ("u8 images, fp32 blur and warp, int32/int64 ORB, Hamming matching as an exact fp4 (+-1) "
+                  "MFMA contraction with fp32 accumulation" if q == MATCH_MATRIX else
+                  "u8 images, fp32 blur and warp, int32/int64 ORB, int32 popcount Hamming matching"),
         "data": "synthetic (seeded scene renderer; ground-truth affine pair)",
         "config": {
             "workload": f"{args.workload}: one {case.A.shape[1]}x{case.A.shape[0]} / {case.B.shape[1]}x{case.B.shape[0]} "

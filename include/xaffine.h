@@ -192,6 +192,14 @@ typedef struct {
 const char* xa_last_error(void);
 const char* xa_version(void);
 
+/* Surfaces an asynchronous failure of work enqueued earlier: XA_EHIP (with the HIP runtime's
+ * message in xa_last_error) if the runtime holds an error left by a failed launch or kernel
+ * (the error is cleared by reporting it) or if `stream` itself is in an error state; XA_OK
+ * otherwise, also while work is still running on `stream` (the call never waits: synchronise
+ * the stream first to check completed work).  Argument errors of other calls are reported by
+ * those calls on the host and leave nothing for xa_check.  stream = NULL is the null stream. */
+xa_status xa_check(hipStream_t stream);
+
 /* Sampling rule of Sec. III.B: for i = 0..n_tilt, t = sqrt(2)^i and
  * phi = k b / t for k = 0, 1, ... while k b / t < 180 deg (b in degrees);
  * psi = tx = ty = 0, s = 1.  Writes at most cap entries; *n_out receives the
@@ -278,7 +286,9 @@ size_t xa_scale_workspace_size(const void* splan_host);
 xa_status xa_scale_sources(const void* splan_host, const void* splan_dev, uint8_t* d_sources, float* d_values,
                            void* d_ws, size_t ws_bytes, hipStream_t stream);
 
-/* ORB on every planned view (levels 1.. of the pyramid are written into
+/* ORB feature extraction on every simulated view of the search (Sec. III.B: ORB runs on each image
+ * of the simulated group; Sec. IV.C: 1000 feature points per image in the measured setting).
+ * ORB on every planned view (levels 1.. of the pyramid are written into
  * d_arena and d_mask, whose level 0 must hold the simulated views): FAST-9
  * at the plan's threshold with 3x3 non-maximum suppression and a content
  * filter, integer Harris top-N per level, 30-bin intensity-centroid
@@ -304,7 +314,8 @@ xa_status xa_match_views(const uint8_t* d_desc_a, const int32_t* d_count_a, int3
                          xa_match* d_matches, int32_t* d_pair_count, int32_t* d_best,
                          hipStream_t stream);
 
-/* Matching over groups of view pairs, for many image pairs in one launch: group
+/* The brute-force Hamming matching of Sec. III.B with the ratio test of Sec. IV.C (as in
+ * xa_match_views), over groups of view pairs, for many image pairs in one launch: group
  * g matches query views [a0, a0 + na) against train views [b0, b0 + nb) of one
  * descriptor set (d_desc [n_views][n_features][32], d_count [n_views]) and
  * writes its na * nb view pairs from index pair_base on (pair pair_base + i * nb
@@ -357,8 +368,11 @@ xa_status xa_match_l2(const uint8_t* d_q, int32_t n_q, const uint8_t* d_t, int32
                       int32_t ratio_den, xa_l2_match* d_out, int32_t* d_count, void* d_ws, size_t ws_bytes,
                       hipStream_t stream);
 
-/* The whole parameter-search path for one image pair: simulate both images,
- * extract ORB on every view, match all view pairs, pick the best pair.
+/* The whole parameter-search path for one image pair (Sec. III.B: simulate the image group over
+ * the (t, phi, s) grid, extract ORB on every image of it, match with the brute-force Hamming
+ * matcher and keep the parameters of the view pair with the most matches; ratio test of
+ * Sec. IV.C): simulate both images, extract ORB on every view, match all view pairs, pick the
+ * best pair (the paper's single-target search is the case of plan B holding one identity view).
  * Both plans must use the same n_features.  Workspace:
  * xa_match_pair_workspace_size(plan_a_host, plan_b_host). */
 size_t xa_match_pair_workspace_size(const void* plan_a_host, const void* plan_b_host);
@@ -367,7 +381,10 @@ xa_status xa_match_pair(const void* plan_a_host, const void* plan_a_dev, const u
                         const int8_t* d_pattern, int32_t ratio_num, int32_t ratio_den,
                         const xa_pair_buffers* out, void* d_ws, size_t ws_bytes, hipStream_t stream);
 
-/* Many image pairs at once: the scale stage (optional: splan may be NULL), the
+/* The search of Sec. III.B (with the scale parameter of the sampling group, Sec. III.B and
+ * Sec. IV.D, as the scale stage) for many image pairs in one sequence of launches: each pair's
+ * outputs are those xa_match_pair computes for it; the batching itself is not in the paper.
+ * Many image pairs at once: the scale stage (optional: splan may be NULL), the
  * simulation and ORB of every view of every image, and the group matching of
  * every image pair (one match plan), as one sequence of launches on `stream`.
  * The views come as n_chunks view plans over one sources buffer (the scale

@@ -361,6 +361,17 @@ struct H9 {
     double h[9];
 };
 
+// |H (x, y) - (bx, by)| <= th of eqs. (5)-(6), evaluated term by term without contraction, so
+// that it rounds as the plain evaluation (device code is otherwise built with multiply-adds fused)
+__device__ __forceinline__ bool within_th(const H9& H, double x, double y, double bx, double by, double th) {
+#pragma clang fp contract(off)
+    const double w = H.h[6] * x + H.h[7] * y + H.h[8];
+    const double px = (H.h[0] * x + H.h[1] * y + H.h[2]) / w;
+    const double py = (H.h[3] * x + H.h[4] * y + H.h[5]) / w;
+    const double ex = px - bx, ey = py - by;
+    return sqrt(ex * ex + ey * ey) <= th;
+}
+
 // Eqs. (5)-(6) on the best pair: correct iff |H p_a - p_b| <= th.
 __global__ void __launch_bounds__(256) k_precision(const xa_keypoint* __restrict__ kp_a, const xa_keypoint* __restrict__ kp_b,
                                                    const xa_match* __restrict__ matches, const int32_t* __restrict__ count_a,
@@ -380,12 +391,8 @@ __global__ void __launch_bounds__(256) k_precision(const xa_keypoint* __restrict
         if (!(nt >= 2 && den * int(m.d1) < num * int(m.d2)) || m.t < 0 || m.t >= nt) continue;
         const xa_keypoint a = kp_a[size_t(i) * N + q];
         const xa_keypoint b = kp_b[size_t(j) * N + m.t];
-        const double w = H.h[6] * a.xs + H.h[7] * a.ys + H.h[8];
-        const double px = (H.h[0] * a.xs + H.h[1] * a.ys + H.h[2]) / w;
-        const double py = (H.h[3] * a.xs + H.h[4] * a.ys + H.h[5]) / w;
-        const double ex = px - b.xs, ey = py - b.ys;
         n += 1;
-        ok += (sqrt(ex * ex + ey * ey) <= th) ? 1 : 0;
+        ok += within_th(H, a.xs, a.ys, b.xs, b.ys, th) ? 1 : 0;
     }
     atomicAdd(&s_ok, ok);
     atomicAdd(&s_n, n);

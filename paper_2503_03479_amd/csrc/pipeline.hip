@@ -278,3 +278,13 @@ extern "C" xa_status xa_graph_destroy(xa_graph* graph) {
     delete graph;
     return ok();
 }
+
+extern "C" xa_status xa_check(hipStream_t stream) {
+    // a sticky error left by an earlier asynchronous failure (cleared once reported)
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "pending HIP error");
+    // the stream's own state: finished, still running, or failed
+    e = hipStreamQuery(stream);
+    if (e != hipSuccess && e != hipErrorNotReady) return hip_fail(e, "stream");
+    return ok();
+}

@@ -129,6 +129,7 @@ _SIGS = {
     "xa_match_pair": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                  _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_int32,
                                  _c.POINTER(_PairBuffers), _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "xa_check": (_c.c_int, [_c.c_void_p]),
     "xa_pair_precision": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32,
                                      _c.c_int32, _c.c_int32, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_double,
                                      _c.c_void_p, _c.c_void_p]),

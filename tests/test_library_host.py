@@ -277,3 +277,18 @@ def test_warp_stride_residues(L):
     rows = [(2.0, 0.5), (2.0, 0.5), (1.0, 0.0)]
     p4 = X.plan_image(300, 200, X.make_params(rows), 3, 1.2, 100, 20)
     assert p4.views["warp_ls_mod"][0] == p4.views["warp_ls_mod"][1]
+
+
+def test_check_reports_runtime_state(L):
+    """xa_check returns a status and a message and never crashes: XA_OK on a healthy runtime, and
+    XA_EHIP naming the runtime's error where no GPU is present (as in this CPU-only container)."""
+    import torch
+    st = L.xa_check(None)
+    msg = L.xa_last_error().decode()
+    if torch.cuda.is_available():
+        assert st == X.XA_OK and msg == ""
+    else:
+        assert st == X.XA_EHIP and "device" in msg
+    # a host-rejected argument error leaves nothing pending for xa_check
+    assert L.xa_match_views(256, 256, 0, 256, 256, 1, 100, 4, 5, 256, 256, 256, None) == X.XA_EINVAL
+    assert L.xa_check(None) == st

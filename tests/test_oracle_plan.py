@@ -99,6 +99,17 @@ def test_level_dims_and_quotas():
         assert all(a >= b for a, b in zip(q, q[1:]))
         # proportional to level area: consecutive ratios near 1.44
         assert q[1] / q[2] == pytest.approx(1.44, rel=0.05)
+        # exact: level l >= 1 gets floor(N r^l / sum_m r^m) with r = 1.2^-2 = 25/36, evaluated in
+        # rational arithmetic; level 0 takes the rest
+        from fractions import Fraction
+        r = Fraction(25, 36)
+        tot = sum(r ** m for m in range(L))
+        upper = [int(n * r ** l // tot) for l in range(1, L)]
+        assert q == [n - sum(upper)] + upper
+    # the values worked out by hand for the tiny and full-size workloads (300 points over 3 levels,
+    # 1000 over 8): flooring, not rounding, on the upper levels
+    assert P.level_quotas(300, 3) == [139, 95, 66]
+    assert P.level_quotas(1000, 8) == [325, 224, 155, 108, 75, 52, 36, 25]
 
 
 def test_coupled_scale_schedule_matches_eq11():
