@@ -368,6 +368,21 @@ xa_status xa_match_l2(const uint8_t* d_q, int32_t n_q, const uint8_t* d_t, int32
                       int32_t ratio_den, xa_l2_match* d_out, int32_t* d_count, void* d_ws, size_t ws_bytes,
                       hipStream_t stream);
 
+/* xa_match_l2 for callers that cannot allocate device memory or pass a workspace (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels and
+ * the same results, with the per-slice partial results in a library-owned device array of
+ * XA_L2_NOALLOC_SCRATCH_BYTES per GPU (held from the first call on a device until the process
+ * ends; its address is looked up once per device with that device current).  The caller still
+ * owns d_q, d_t, d_out and d_count, with the layouts, alignment and limits of xa_match_l2.  No
+ * hipMalloc, hipFree or allocating library routine is called.  XA_ECAPACITY when
+ * xa_match_l2_workspace_size(n_q, n_t) exceeds the scratch size (it never does within
+ * XA_L2_MAX_DESCRIPTORS); XA_EINVAL as for xa_match_l2.  Every call on one GPU shares that GPU's
+ * scratch array and leaves its contents behind: calls that overlap on one GPU (on different
+ * streams, or from different threads) race and must be serialised by the caller. */
+#define XA_L2_NOALLOC_SCRATCH_BYTES (16u << 20)
+xa_status xa_match_l2_noalloc(const uint8_t* d_q, int32_t n_q, const uint8_t* d_t, int32_t n_t, int32_t ratio_num,
+                              int32_t ratio_den, xa_l2_match* d_out, int32_t* d_count, hipStream_t stream);
+
 /* The whole parameter-search path for one image pair (Sec. III.B: simulate the image group over
  * the (t, phi, s) grid, extract ORB on every image of it, match with the brute-force Hamming
  * matcher and keep the parameters of the view pair with the most matches; ratio test of

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <mutex>
 
 #include "internal.h"
 
@@ -227,15 +228,51 @@ L2Launch l2_launch(int nq, int nt) {
 
 using namespace xa;
 
+// Scratch of the allocation-free entry: every device the library runs on holds one copy of
+// this array until the process ends.  In host code its name stands for the host-side shadow,
+// not a device address, so kernels are only ever given the address hipGetSymbolAddress returns
+// for the current device.
+static __device__ __align__(256) int4 scratch[XA_L2_NOALLOC_SCRATCH_BYTES / sizeof(int4)];
+
+namespace xa {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of the scratch array, looked up once per device.
+xa_status scratch_for_current_device(int4** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(XA_EUNSUPPORTED, "device %d beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p || reinterpret_cast<uintptr_t>(p) % 256) return fail(XA_EHIP, "scratch array address not 256-byte aligned");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<int4*>(g_scratch_ptr[dev]);
+    return XA_OK;
+}
+
+}  // namespace
+}  // namespace xa
+
 extern "C" size_t xa_match_l2_workspace_size(int32_t n_q, int32_t n_t) {
     if (n_q < 0 || n_t < 0) return 0;
     const L2Launch L = l2_launch(n_q, n_t);
     return size_t(L.n_slices) * size_t(n_q) * sizeof(int4);
 }
 
-extern "C" xa_status xa_match_l2(const uint8_t* d_q, int32_t n_q, const uint8_t* d_t, int32_t n_t, int32_t ratio_num,
-                                 int32_t ratio_den, xa_l2_match* d_out, int32_t* d_count, void* d_ws, size_t ws_bytes,
-                                 hipStream_t stream) {
+namespace xa {
+namespace {
+
+xa_status l2_check(const uint8_t* d_q, int32_t n_q, const uint8_t* d_t, int32_t n_t, int32_t ratio_num,
+                   int32_t ratio_den, const xa_l2_match* d_out, const int32_t* d_count) {
     if (n_q < 0 || n_t < 0 || n_q > XA_L2_MAX_DESCRIPTORS || n_t > XA_L2_MAX_DESCRIPTORS)
         return fail(XA_EINVAL, "descriptor counts must lie in 0..%d", XA_L2_MAX_DESCRIPTORS);
     if (ratio_num < 0 || ratio_den < 1 || ratio_num > (1 << 16) || ratio_den > (1 << 16))
@@ -243,13 +280,16 @@ extern "C" xa_status xa_match_l2(const uint8_t* d_q, int32_t n_q, const uint8_t*
     if (!d_count || (n_q > 0 && (!d_q || !d_out)) || (n_t > 0 && !d_t)) return fail(XA_EINVAL, "NULL device pointer");
     if ((reinterpret_cast<uintptr_t>(d_q) | reinterpret_cast<uintptr_t>(d_t)) % 16)
         return fail(XA_EINVAL, "descriptor arrays must be 16-byte aligned");
-    const size_t need = xa_match_l2_workspace_size(n_q, n_t);
-    if (need > 0 && (!d_ws || ws_bytes < need || reinterpret_cast<uintptr_t>(d_ws) % 16))
-        return fail(XA_EINVAL, "workspace of %zu bytes (16-byte aligned) needed, %zu given", need, ws_bytes);
+    return XA_OK;
+}
+
+// The count is cleared by a kernel (no memset node, so the sequence can be graph-captured),
+// then the slices' partial results go to part and the final pass merges them.
+xa_status l2_enqueue(const uint8_t* d_q, int32_t n_q, const uint8_t* d_t, int32_t n_t, int32_t ratio_num,
+                     int32_t ratio_den, xa_l2_match* d_out, int32_t* d_count, int4* part, hipStream_t stream) {
     hipLaunchKernelGGL(k_l2_zero, dim3(1), dim3(64), 0, stream, d_count);
     if (n_q > 0) {
         const L2Launch L = l2_launch(n_q, n_t);
-        int4* part = static_cast<int4*>(d_ws);
         hipLaunchKernelGGL(k_match_l2, dim3(unsigned(L.qblocks), unsigned(L.n_slices)), dim3(kL2Threads), 0, stream,
                            reinterpret_cast<const uint4*>(d_q), n_q, reinterpret_cast<const uint4*>(d_t), n_t,
                            L.chunks_per_slice, part);
@@ -260,4 +300,33 @@ extern "C" xa_status xa_match_l2(const uint8_t* d_q, int32_t n_q, const uint8_t*
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "L2 match launch");
     return ok();
+}
+
+}  // namespace
+}  // namespace xa
+
+extern "C" xa_status xa_match_l2(const uint8_t* d_q, int32_t n_q, const uint8_t* d_t, int32_t n_t, int32_t ratio_num,
+                                 int32_t ratio_den, xa_l2_match* d_out, int32_t* d_count, void* d_ws, size_t ws_bytes,
+                                 hipStream_t stream) {
+    const xa_status st = l2_check(d_q, n_q, d_t, n_t, ratio_num, ratio_den, d_out, d_count);
+    if (st != XA_OK) return st;
+    const size_t need = xa_match_l2_workspace_size(n_q, n_t);
+    if (need > 0 && (!d_ws || ws_bytes < need || reinterpret_cast<uintptr_t>(d_ws) % 16))
+        return fail(XA_EINVAL, "workspace of %zu bytes (16-byte aligned) needed, %zu given", need, ws_bytes);
+    return l2_enqueue(d_q, n_q, d_t, n_t, ratio_num, ratio_den, d_out, d_count, static_cast<int4*>(d_ws), stream);
+}
+
+extern "C" xa_status xa_match_l2_noalloc(const uint8_t* d_q, int32_t n_q, const uint8_t* d_t, int32_t n_t,
+                                         int32_t ratio_num, int32_t ratio_den, xa_l2_match* d_out, int32_t* d_count,
+                                         hipStream_t stream) {
+    xa_status st = l2_check(d_q, n_q, d_t, n_t, ratio_num, ratio_den, d_out, d_count);
+    if (st != XA_OK) return st;
+    const size_t need = xa_match_l2_workspace_size(n_q, n_t);
+    if (need > XA_L2_NOALLOC_SCRATCH_BYTES)
+        return fail(XA_ECAPACITY, "%d x %d descriptors need %zu bytes of scratch, above the %zu-byte maximum", n_q, n_t,
+                    need, size_t(XA_L2_NOALLOC_SCRATCH_BYTES));
+    int4* part = nullptr;
+    st = scratch_for_current_device(&part);
+    if (st != XA_OK) return st;
+    return l2_enqueue(d_q, n_q, d_t, n_t, ratio_num, ratio_den, d_out, d_count, part, stream);
 }

@@ -103,6 +103,8 @@ _SIGS = {
     "xa_match_l2_workspace_size": (_c.c_size_t, [_c.c_int32, _c.c_int32]),
     "xa_match_l2": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_void_p,
                                _c.c_void_p, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "xa_match_l2_noalloc": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_int32, _c.c_int32, _c.c_int32,
+                                       _c.c_void_p, _c.c_void_p, _c.c_void_p]),
     "xa_match_batch_workspace_size": (_c.c_size_t, [_c.c_void_p, _c.c_int32, _c.c_void_p]),
     "xa_match_batch": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                   _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_int32, _c.c_void_p,
@@ -502,6 +504,27 @@ def match_l2(dq, dt, ratio_num: int = 3, ratio_den: int = 4, ws=None):
     _check(lib().xa_match_l2(_ptr(dq) if nq else None, nq, _ptr(dt) if nt else None, nt, ratio_num, ratio_den,
                              _ptr(out), _ptr(count), _ptr(ws), ws.numel(), _stream()))
     return out[:nq], count
+
+
+def match_l2_noalloc(dq, dt, ratio_num: int = 3, ratio_den: int = 4, out=None, count=None):
+    """xa_match_l2_noalloc: match_l2 with the library's own per-GPU scratch array in place of a
+    workspace.  out / count may be passed in (preallocated), so the call itself allocates
+    nothing; calls that overlap on one GPU race on the shared scratch."""
+    import torch
+    for name, d in (("dq", dq), ("dt", dt)):
+        if d.dtype != torch.uint8 or d.dim() != 2 or d.shape[1] != 128 or not d.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous uint8 tensor of shape [n, 128]")
+    dev = dq.device
+    nq, nt = int(dq.shape[0]), int(dt.shape[0])
+    if out is None:
+        out = torch.empty((max(nq, 1), 3), dtype=torch.int32, device=dev)
+    if count is None:
+        count = torch.empty(1, dtype=torch.int32, device=dev)
+    if out.dtype != torch.int32 or not out.is_contiguous() or out.numel() < 3 * nq:
+        raise ValueError("out must be a contiguous int32 tensor of at least n_q x 3 entries")
+    _check(lib().xa_match_l2_noalloc(_ptr(dq) if nq else None, nq, _ptr(dt) if nt else None, nt, ratio_num,
+                                     ratio_den, _ptr(out), _ptr(count), _stream()))
+    return out.view(-1)[:3 * nq].view(nq, 3), count
 
 
 def l2_matches_np(out) -> np.ndarray:
