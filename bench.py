@@ -445,9 +445,11 @@ def diffwarp_leg(args, dev):
     gimg = torch.empty_like(crops)
     gpar = torch.empty((n, 6), dtype=torch.float64, device=dev)
     ws = X._empty(L.xa_warp_f32_bwd_workspace_size(n, 512, 512), dev)
+    wsf = X._empty(L.xa_warp_f32_fwd_workspace_size(n, 512, 512), dev)
 
     def fwd():
-        X._check(L.xa_warp_f32_fwd(X._ptr(crops), n, 512, 512, X._ptr(par), X._ptr(out), X._ptr(mask), X._stream()))
+        X._check(L.xa_warp_f32_fwd(X._ptr(crops), n, 512, 512, X._ptr(par), X._ptr(out), X._ptr(mask), X._ptr(wsf),
+                                   wsf.numel(), X._stream()))
 
     def bwd():
         X._check(L.xa_warp_f32_bwd(X._ptr(crops), X._ptr(g), X._ptr(par), n, 512, 512, X._ptr(gimg), X._ptr(gpar),

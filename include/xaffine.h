@@ -496,11 +496,16 @@ xa_status xa_ransac_homography(const double* d_pa, const double* d_pb, int32_t n
  * xa_warp_f32_bwd: given dLoss/dout (d_gout [n][h][w]), writes dLoss/dimg to
  * d_gimg [n][h][w] (overwritten; nullable) and dLoss/d(t, phi, psi, s, tx, ty)
  * to d_gparams [n][6] fp64 (nullable).  The parameter gradient is summed over
- * each crop in a fixed order (deterministic); the image gradient is scattered
- * with fp32 atomics, so its last bits depend on the order of arrival.
- * Workspace (needed when d_gparams is given): xa_warp_f32_bwd_workspace_size. */
+ * each crop in a fixed order (deterministic); the image gradient is summed per
+ * tile in fixed point and added to d_gimg with fp32 atomics, so its last bits
+ * depend on the order of arrival.
+ * Workspaces (16-byte aligned; each call first writes the crops' maps and tile
+ * shapes there): xa_warp_f32_fwd_workspace_size and xa_warp_f32_bwd_workspace_size.
+ * XA_EINVAL for sizes below 1, NULL or misaligned buffers; XA_ECAPACITY for a short
+ * workspace; XA_EUNSUPPORTED above 2^28 pixels per crop or 2^38 in all. */
+size_t xa_warp_f32_fwd_workspace_size(int32_t n, int32_t h, int32_t w);
 xa_status xa_warp_f32_fwd(const float* d_img, int32_t n, int32_t h, int32_t w, const xa_affine_params* d_params,
-                          float* d_out, uint8_t* d_mask, hipStream_t stream);
+                          float* d_out, uint8_t* d_mask, void* d_ws, size_t ws_bytes, hipStream_t stream);
 size_t xa_warp_f32_bwd_workspace_size(int32_t n, int32_t h, int32_t w);
 xa_status xa_warp_f32_bwd(const float* d_img, const float* d_gout, const xa_affine_params* d_params, int32_t n,
                           int32_t h, int32_t w, float* d_gimg, double* d_gparams, void* d_ws, size_t ws_bytes,

@@ -8,7 +8,12 @@ fits converge fast: E_p(g) = sum_k e_pk h^k and O_p(g) = g sum_k o_pk h^k in h =
 each, fitted by least squares on a dense grid.  Evaluated in fp32 by Horner's rule they stay
 within 1.4e-7 of L4, the rounding level of fp32 weights near 1.
 
-Run as a script to print the table that lanczos.h holds."""
+The adjoint of the warp also needs the weights' derivatives in f (= d/dg).  For the tap pair the
+derivative splits the same way: dw_p/dg = A_p(g) + B_p(g) and dw_{7-p}/dg = A_p(g) - B_p(g), with
+A_p = g sum_k a_pk h^k odd and B_p = sum_k b_pk h^k even, fitted by least squares to the exact
+derivative -L4'(p - 7/2 -+ g); degree 4 keeps them within 1e-7 of it.
+
+Run as a script to print the tables that lanczos.h holds."""
 import numpy as np
 
 DEGREE = 4
@@ -17,6 +22,20 @@ DEGREE = 4
 def lanczos4(x):
     x = np.asarray(x, np.float64)
     return np.where(np.abs(x) < 4.0, np.sinc(x) * np.sinc(x / 4.0), 0.0)
+
+
+def sinc_deriv(x):
+    """d/dx sin(pi x) / (pi x) = (cos(pi x) - sinc(x)) / x, and its series -pi^2 x / 3 near 0."""
+    x = np.asarray(x, np.float64)
+    small = np.abs(x) < 1e-4
+    xs = np.where(small, 1.0, x)
+    return np.where(small, -(np.pi ** 2 / 3.0) * x, (np.cos(np.pi * xs) - np.sinc(xs)) / xs)
+
+
+def lanczos4_deriv(x):
+    x = np.asarray(x, np.float64)
+    d = sinc_deriv(x) * np.sinc(x / 4.0) + np.sinc(x) * sinc_deriv(x / 4.0) / 4.0
+    return np.where(np.abs(x) < 4.0, d, 0.0)
 
 
 def coefficients(degree=DEGREE, n=40001):
@@ -32,10 +51,25 @@ def coefficients(degree=DEGREE, n=40001):
     return np.array(E, np.float32), np.array(O, np.float32)
 
 
+def derivative_coefficients(degree=DEGREE, n=40001):
+    """(A, B): dw_p/dg = g A_p(h) + B_p(h) and dw_{7-p}/dg = g A_p(h) - B_p(h), p = 0..3."""
+    g = np.linspace(0.0, 0.5, n)
+    h = g * g
+    even = np.vander(h, degree + 1, increasing=True)
+    odd = g[:, None] * even
+    A, B = [], []
+    for p in range(4):
+        d, dm = -lanczos4_deriv(p - 3.5 - g), -lanczos4_deriv(3.5 - p - g)
+        A.append(np.linalg.lstsq(odd, 0.5 * (d + dm), rcond=None)[0])
+        B.append(np.linalg.lstsq(even, 0.5 * (d - dm), rcond=None)[0])
+    return np.array(A, np.float32), np.array(B, np.float32)
+
+
 def table():
     E, O = coefficients()
+    A, B = derivative_coefficients()
     rows = []
-    for name, M in (("kLanczosEven", E), ("kLanczosOdd", O)):
+    for name, M in (("kLanczosEven", E), ("kLanczosOdd", O), ("kLanczosDerivOdd", A), ("kLanczosDerivEven", B)):
         rows.append(f"constexpr float {name}[4][{M.shape[1]}] = {{")
         for r in M:
             rows.append("    {" + ", ".join(f"{float(c):.9e}f" for c in r) + "},")

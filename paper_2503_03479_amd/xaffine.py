@@ -115,8 +115,9 @@ _SIGS = {
                                           _c.POINTER(_c.c_void_p)]),
     "xa_graph_launch": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
     "xa_graph_destroy": (_c.c_int, [_c.c_void_p]),
+    "xa_warp_f32_fwd_workspace_size": (_c.c_size_t, [_c.c_int32, _c.c_int32, _c.c_int32]),
     "xa_warp_f32_fwd": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_void_p, _c.c_void_p,
-                                   _c.c_void_p, _c.c_void_p]),
+                                   _c.c_void_p, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
     "xa_warp_f32_bwd_workspace_size": (_c.c_size_t, [_c.c_int32, _c.c_int32, _c.c_int32]),
     "xa_warp_f32_bwd": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_int32, _c.c_int32,
                                    _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
@@ -905,7 +906,9 @@ def warp_f32_fwd(img, params):
     n, h, w = img.shape
     out = torch.empty_like(img)
     mask = torch.empty((n, h, w), dtype=torch.uint8, device=img.device)
-    _check(lib().xa_warp_f32_fwd(_ptr(img), n, h, w, _ptr(params), _ptr(out), _ptr(mask), _stream()))
+    ws = _empty(lib().xa_warp_f32_fwd_workspace_size(n, h, w), img.device)
+    _check(lib().xa_warp_f32_fwd(_ptr(img), n, h, w, _ptr(params), _ptr(out), _ptr(mask), _ptr(ws), ws.numel(),
+                                 _stream()))
     return out, mask
 
 
@@ -919,9 +922,9 @@ def warp_f32_bwd(img, gout, params, need_img: bool = True, need_params: bool = T
     n, h, w = img.shape
     gimg = torch.empty_like(img) if need_img else None
     gpar = torch.empty((n, 6), dtype=torch.float64, device=img.device) if need_params else None
-    ws = _empty(lib().xa_warp_f32_bwd_workspace_size(n, h, w), img.device) if need_params else None
+    ws = _empty(lib().xa_warp_f32_bwd_workspace_size(n, h, w), img.device)
     _check(lib().xa_warp_f32_bwd(_ptr(img), _ptr(gout), _ptr(params), n, h, w, _ptr(gimg), _ptr(gpar), _ptr(ws),
-                                 0 if ws is None else ws.numel(), _stream()))
+                                 ws.numel(), _stream()))
     return gimg, gpar
 
 
