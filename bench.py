@@ -18,6 +18,7 @@ workload.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import math
 import os
@@ -174,7 +175,8 @@ def parse():
                     help="matcher variant for the full-pair leg: 0 = autotune, 1 / 2 / 4 = popcount kernel "
                          "with that many queries per lane, -1 = matrix-core kernel")
     ap.add_argument("--l2-n", type=int, default=32768, help="descriptors per set in the L2 matcher leg (0 = skip)")
-    ap.add_argument("--only", choices=["batched", "diffwarp", "copy", "sweep", "l2"], default=None,
+    ap.add_argument("--no-sift", action="store_true", help="skip the SIFT leg")
+    ap.add_argument("--only", choices=["batched", "diffwarp", "copy", "sweep", "l2", "sift"], default=None,
                     help="run one leg alone and print its JSON (for profiler runs); 'copy' is a plain 1 GiB "
                          "device-to-device copy whose counter readings calibrate the HBM traffic counters")
     return ap.parse_args()
@@ -426,6 +428,70 @@ def l2_leg(args, dev):
     }
 
 
+def sift_leg(args, dev):
+    """SIFT extraction (xa_extract_sift) on the full-size pair's two images, HIP events over 10
+    calls after one untimed call; then the base-image selection of Sec. III.A end to end (SIFT on
+    both, L2 matching both ways, eq. (1)), wall-clock with its host synchronisations; and the
+    oracle's SIFT on image A, one core, for context."""
+    import numpy as np
+    import torch
+
+    import synth
+    from oracle import sift as OS
+    from paper_2503_03479_amd import xaffine as X
+
+    L = X.lib()
+    case = synth.make_pair(**synth.PAIR_CONFIGS["full"])
+    res = {}
+    stream = torch.cuda.current_stream()
+    for tag, img in (("A", case.A), ("B", np.ascontiguousarray(case.B))):
+        t = torch.from_numpy(np.ascontiguousarray(img)).to(dev)
+        opts = X.sift_opts()
+        h, w = img.shape
+        ws = X._empty(L.xa_sift_workspace_size(w, h, ctypes.byref(opts)), dev)
+        kp = torch.empty((opts.max_keypoints, 8), dtype=torch.int32, device=dev)
+        desc = torch.empty((opts.max_keypoints, 128), dtype=torch.uint8, device=dev)
+        count = torch.empty(2, dtype=torch.int32, device=dev)
+
+        def call():
+            X._check(L.xa_extract_sift(X._ptr(t), w, h, w, ctypes.byref(opts), X._ptr(kp), X._ptr(desc), X._ptr(count),
+                                       X._ptr(ws), ws.numel(), X._stream()))
+
+        call()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record(stream)
+        for _ in range(reps):
+            call()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[tag] = {"width": w, "height": h, "ms_per_image": ms, "keypoints": int(count.cpu()[0]),
+                    "mpx_per_s": w * h / (ms / 1e3) / 1e6}
+    A = torch.from_numpy(case.A).to(dev)
+    B = torch.from_numpy(np.ascontiguousarray(case.B)).to(dev)
+    X.select_base_image(A, B)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 5
+    for _ in range(reps):
+        base, f1, f2 = X.select_base_image(A, B)
+    torch.cuda.synchronize()
+    sel_ms = (time.perf_counter() - t0) / reps * 1e3
+    t0 = time.perf_counter()
+    kpo, _, _ = OS.extract(case.A)
+    oracle_s = time.perf_counter() - t0
+    return {
+        "workload": "SIFT (3 layers per octave, sigma 1.6, no doubling, contrast 0.04, edge 10, 4096 keypoints at "
+                    "most) on the full-size pair's images",
+        "kernels": "k_sift_hblur, k_sift_vblur, k_sift_down, k_sift_dog, k_sift_rows<0/1>, k_sift_scan, "
+                   "k_sift_orient, k_sift_scan_peaks, k_sift_desc (xa_extract_sift)",
+        "images": res, "base_selection_ms": sel_ms, "base": base, "f1": f1, "f2": f2,
+        "oracle_s_image_a": oracle_s, "oracle_keypoints_a": int(len(kpo)), "oracle_cores": 1,
+    }
+
+
 def diffwarp_leg(args, dev):
     """Differentiable warp on n fp32 crops of 512 x 512 (parameters drawn per crop):
     forward and adjoint (image + six parameters) timed with HIP events."""
@@ -526,6 +592,8 @@ def main():
             print(json.dumps(l2_leg(args, dev)), flush=True)
         elif args.only == "diffwarp":
             print(json.dumps(diffwarp_leg(args, dev)), flush=True)
+        elif args.only == "sift":
+            print(json.dumps(sift_leg(args, dev)), flush=True)
         elif args.only == "sweep":
             print(json.dumps(sweep_leg(args, dev, pattern)), flush=True)
         else:
@@ -685,6 +753,8 @@ def main():
         out["diffwarp"] = diffwarp_leg(args, dev)
     if args.l2_n > 0:
         out["l2_matcher"] = l2_leg(args, dev)
+    if not args.no_sift:
+        out["sift"] = sift_leg(args, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, grid, wl, args.cpu_views, args.cpu_pairs)
     print(json.dumps(out), flush=True)

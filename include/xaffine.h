@@ -383,6 +383,64 @@ xa_status xa_match_l2(const uint8_t* d_q, int32_t n_q, const uint8_t* d_t, int32
 xa_status xa_match_l2_noalloc(const uint8_t* d_q, int32_t n_q, const uint8_t* d_t, int32_t n_t, int32_t ratio_num,
                               int32_t ratio_den, xa_l2_match* d_out, int32_t* d_count, hipStream_t stream);
 
+/* SIFT keypoints and descriptors of one 8-bit image (Lowe's detector and descriptor, which the
+ * method uses to choose the base image, Sec. III.A, and to match the re-simulated reference
+ * against the target, Sec. III.C).  Scale space: s layers per octave (s + 3 Gaussian images,
+ * s + 2 DoG images), input blur sigma_in, base blur sigma0, no initial doubling,
+ * floor(log2 min(W, H)) - 3 octaves unless n_octaves is given, each octave from every second
+ * pixel of the previous octave's G_s; separable fp32 blurs summed from tap -r to tap r with
+ * every product and sum rounded.  Keypoints: strict 26-neighbour DoG extrema, at least 5 pixels
+ * from the border, refined by the quadratic fit (decisions taken on cofactors, no division),
+ * rejected below |D| = 255 contrast / s or at principal-curvature ratio >= edge; one keypoint
+ * per orientation peak (36 bins, >= 0.8 of the highest).  Descriptors: 4 x 4 x 8 trilinear
+ * histograms, unit norm, clipped at 0.2, renormalised, min(255, floor(512 v + 1/2)).
+ *
+ * Order: keypoints come in the order of their DoG candidates (octave, candidate layer, row,
+ * column), one candidate's orientations in bin order; the first max_keypoints are written.
+ * d_img: W x H u8 at row pitch `pitch` bytes (device).  d_kp [max_keypoints], d_desc
+ * [max_keypoints][128] u8, d_count [2] = {keypoints written, keypoints found}: device, caller-
+ * owned.  Fitted keypoints beyond raw_capacity (default 2 max_keypoints + 1024) are dropped
+ * before orientation assignment, in order, so "found" then counts only the kept ones.  The
+ * outputs do not depend on thread scheduling (histograms are summed in fixed point).
+ * Workspace: xa_sift_workspace_size(w, h, opts) bytes, 256-byte aligned; opts NULL = defaults.
+ * XA_EINVAL for sizes, options or pointers out of range; XA_EUNSUPPORTED above 2^28 pixels. */
+#define XA_SIFT_MAX_KEYPOINTS 65536
+typedef struct {
+    int32_t n_octaves;          /* 0: floor(log2 min(W, H)) - 3, at least 1 */
+    int32_t n_layers;           /* s, 1..5 (3) */
+    int32_t max_keypoints;      /* capacity of d_kp / d_desc, 1..XA_SIFT_MAX_KEYPOINTS (4096) */
+    int32_t raw_capacity;       /* fitted keypoints kept for orientation; 0 = 2 max_keypoints + 1024 */
+    double sigma0;              /* 1.6 */
+    double sigma_in;            /* 0.5 */
+    double contrast;            /* 0.04, on intensities scaled to [0, 1] */
+    double edge;                /* 10 */
+} xa_sift_opts;
+typedef struct {
+    float x, y;                 /* original-image pixel coordinates */
+    float size;                 /* blur of the keypoint's scale in original pixels */
+    float angle;                /* radians in [0, 2 pi), atan2 convention in image axes (y down) */
+    float response;             /* |D| at the fitted extremum */
+    int32_t xi, yi;             /* sample position in the octave */
+    int8_t octave, layer, peak, pad;
+} xa_sift_keypoint;
+size_t xa_sift_workspace_size(int32_t w, int32_t h, const xa_sift_opts* opts);
+xa_status xa_extract_sift(const uint8_t* d_img, int32_t w, int32_t h, int32_t pitch, const xa_sift_opts* opts,
+                          xa_sift_keypoint* d_kp, uint8_t* d_desc, int32_t* d_count, void* d_ws, size_t ws_bytes,
+                          hipStream_t stream);
+
+/* The SIFT matches kept for eq. (1) (Sec. III.A) and for RANSAC (Sec. III.C): of the n_q
+ * queries matched by xa_match_l2 (d_matches), those passing its ratio test (at least two train
+ * rows, den^2 d1^2 < num^2 d2^2), in query order.  For the o-th kept match, d_pq[2 o..] and
+ * d_pt[2 o..] are the query and train keypoints' (x, y) taken through the 2 x 3 row-major maps
+ * map_q and map_t (host memory, NULL = identity; e.g. a simulated view's inverse map back to its
+ * source), and d_des[o] = sqrt(d1^2), the descriptor distance.  *d_n = kept matches.  Outputs
+ * hold n_q entries at most (device, caller-owned).  XA_EINVAL for counts or ratios out of range
+ * or NULL pointers. */
+xa_status xa_sift_match_points(const xa_sift_keypoint* d_kp_q, const xa_sift_keypoint* d_kp_t,
+                               const xa_l2_match* d_matches, int32_t n_q, int32_t n_t, int32_t ratio_num,
+                               int32_t ratio_den, const double* map_q, const double* map_t, double* d_pq,
+                               double* d_pt, double* d_des, int32_t* d_n, hipStream_t stream);
+
 /* The whole parameter-search path for one image pair (Sec. III.B: simulate the image group over
  * the (t, phi, s) grid, extract ORB on every image of it, match with the brute-force Hamming
  * matcher and keep the parameters of the view pair with the most matches; ratio test of
@@ -464,6 +522,9 @@ xa_status xa_best_pair_points(const xa_keypoint* d_kp_a, const xa_keypoint* d_kp
  * *d_f (device fp64).  f > 0 means segments are longer in image A. */
 xa_status xa_scaling_coefficient(const double* d_pa, const double* d_pb, const int32_t* d_des, const int32_t* d_n,
                                  int32_t cap, double* d_f, hipStream_t stream);
+/* The same with fp64 descriptor distances (the SIFT distances of xa_sift_match_points). */
+xa_status xa_scaling_coefficient_f64(const double* d_pa, const double* d_pb, const double* d_des, const int32_t* d_n,
+                                     int32_t cap, double* d_f, hipStream_t stream);
 
 /* Homography RANSAC over n matched points (Sec. III.C; eq. (7) is the inlier share):
  * d_pa, d_pb [n][2] fp64; d_samples [k][4] int32 match indices (the random draws, made by

@@ -41,8 +41,9 @@ readings a plain definition needs written out:
     (2 cells) and spread over the 8 neighbouring bins by trilinear interpolation; the 128 values
     are normalised to unit length, clipped at 0.2, renormalised, and stored as 8 bits:
     min(255, floor(512 v + 1/2));
-  * order: keypoints sorted by (octave, layer, row, column, peak bin); the first max_keypoints
-    are kept.
+  * order: keypoints in the order of their candidates (octave, candidate layer, row, column,
+    before any move of the fit), the peaks of one candidate in bin order; the first
+    max_keypoints are kept.
 
 Parity status: pinned.  The tap table against the closed form of a sampled Gaussian; a blur of
 a constant stays constant and a blurred impulse has the taps as its row and column profile;
@@ -343,10 +344,6 @@ def descriptor(G, x: int, y: int, angle: float, sigma_oct: float) -> np.ndarray:
     return np.minimum(np.floor(desc * scale + 0.5), 255.0).astype(np.uint8)
 
 
-def sort_key(kp) -> tuple:
-    return (kp["octave"], kp["layer"], kp["yi"], kp["xi"], kp["peak"])
-
-
 def extract(img_u8, max_keypoints: int = 4096, n_octaves: int = 0, n_layers: int = N_LAYERS,
             sigma0: float = SIGMA0, sigma_in: float = SIGMA_IN, contrast: float = CONTRAST, edge: float = EDGE):
     """(keypoints [KEYPOINT_DTYPE], descriptors u8 [n, 128], total found) of an 8-bit image."""
@@ -364,7 +361,6 @@ def extract(img_u8, max_keypoints: int = 4096, n_octaves: int = 0, n_layers: int
             kp["peak"] = peak
             kp["angle"] = ang
             kps.append(kp)
-    kps.sort(key=sort_key)
     total = len(kps)
     kps = kps[:max_keypoints]
     out = np.zeros(len(kps), KEYPOINT_DTYPE)

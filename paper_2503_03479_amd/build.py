@@ -9,7 +9,7 @@ from concurrent.futures import ThreadPoolExecutor
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SOURCES = ["plan.cpp", "simulate.hip", "scale.hip", "orb.hip", "match.hip", "match_l2.hip", "pipeline.hip",
-           "diffwarp.hip", "geometry.hip"]
+           "diffwarp.hip", "geometry.hip", "sift.hip"]
 LIB = os.path.join(PKG, "libxaffine.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-std=c++17", "-O3", "--offload-arch=gfx950", "-fPIC",

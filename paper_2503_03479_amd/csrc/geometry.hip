@@ -339,8 +339,9 @@ __global__ void __launch_bounds__(1024) k_pair_points(const xa_keypoint* __restr
 
 // Eq. (1) over the first min(*n, cap) matches: sum over consecutive pairs of the difference of
 // segment lengths weighted by 1 - (Des(i) + Des(i + 1)) / 1000, in a fixed summation order.
+template <typename D>
 __global__ void __launch_bounds__(256) k_scaling(const double* __restrict__ pa, const double* __restrict__ pb,
-                                                 const int32_t* __restrict__ des, const int32_t* __restrict__ n_dev,
+                                                 const D* __restrict__ des, const int32_t* __restrict__ n_dev,
                                                  int cap, double* __restrict__ f) {
     __shared__ double red[4];
     const int n = min(max(*n_dev, 0), cap);
@@ -348,7 +349,7 @@ __global__ void __launch_bounds__(256) k_scaling(const double* __restrict__ pa, 
     for (int i = threadIdx.x; i + 1 < n; i += blockDim.x) {
         const double ax = pa[2 * i + 2] - pa[2 * i], ay = pa[2 * i + 3] - pa[2 * i + 1];
         const double bx = pb[2 * i + 2] - pb[2 * i], by = pb[2 * i + 3] - pb[2 * i + 1];
-        const double w = 1.0 - double(des[i] + des[i + 1]) / 1000.0;
+        const double w = 1.0 - (double(des[i]) + double(des[i + 1])) / 1000.0;
         acc += (sqrt(ax * ax + ay * ay) - sqrt(bx * bx + by * by)) * w;
     }
     const double t = block_sum(acc, red);
@@ -364,7 +365,16 @@ extern "C" xa_status xa_scaling_coefficient(const double* d_pa, const double* d_
                                             const int32_t* d_n, int32_t cap, double* d_f, hipStream_t stream) {
     if (!d_pa || !d_pb || !d_des || !d_n || !d_f) return fail(XA_EINVAL, "NULL pointer");
     if (cap < 0) return fail(XA_EINVAL, "negative capacity");
-    hipLaunchKernelGGL(k_scaling, dim3(1), dim3(256), 0, stream, d_pa, d_pb, d_des, d_n, cap, d_f);
+    hipLaunchKernelGGL(k_scaling<int32_t>, dim3(1), dim3(256), 0, stream, d_pa, d_pb, d_des, d_n, cap, d_f);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? ok() : hip_fail(e, "scaling coefficient launch");
+}
+
+extern "C" xa_status xa_scaling_coefficient_f64(const double* d_pa, const double* d_pb, const double* d_des,
+                                                const int32_t* d_n, int32_t cap, double* d_f, hipStream_t stream) {
+    if (!d_pa || !d_pb || !d_des || !d_n || !d_f) return fail(XA_EINVAL, "NULL pointer");
+    if (cap < 0) return fail(XA_EINVAL, "negative capacity");
+    hipLaunchKernelGGL(k_scaling<double>, dim3(1), dim3(256), 0, stream, d_pa, d_pb, d_des, d_n, cap, d_f);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? ok() : hip_fail(e, "scaling coefficient launch");
 }

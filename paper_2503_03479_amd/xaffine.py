@@ -105,6 +105,14 @@ _SIGS = {
                                _c.c_void_p, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
     "xa_match_l2_noalloc": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_int32, _c.c_int32, _c.c_int32,
                                        _c.c_void_p, _c.c_void_p, _c.c_void_p]),
+    "xa_sift_workspace_size": (_c.c_size_t, [_c.c_int32, _c.c_int32, _c.c_void_p]),
+    "xa_extract_sift": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_void_p, _c.c_void_p,
+                                   _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "xa_sift_match_points": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_int32, _c.c_int32,
+                                        _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                        _c.c_void_p, _c.c_void_p, _c.c_void_p]),
+    "xa_scaling_coefficient_f64": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32,
+                                              _c.c_void_p, _c.c_void_p]),
     "xa_match_batch_workspace_size": (_c.c_size_t, [_c.c_void_p, _c.c_int32, _c.c_void_p]),
     "xa_match_batch": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                   _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_int32, _c.c_void_p,
@@ -526,6 +534,55 @@ def match_l2_noalloc(dq, dt, ratio_num: int = 3, ratio_den: int = 4, out=None, c
     _check(lib().xa_match_l2_noalloc(_ptr(dq) if nq else None, nq, _ptr(dt) if nt else None, nt, ratio_num,
                                      ratio_den, _ptr(out), _ptr(count), _stream()))
     return out.view(-1)[:3 * nq].view(nq, 3), count
+
+
+class SiftOpts(_c.Structure):
+    """xa_sift_opts (defaults: 3 layers, sigma0 1.6, input blur 0.5, contrast 0.04, edge 10)."""
+    _fields_ = [("n_octaves", _c.c_int32), ("n_layers", _c.c_int32), ("max_keypoints", _c.c_int32),
+                ("raw_capacity", _c.c_int32), ("sigma0", _c.c_double), ("sigma_in", _c.c_double),
+                ("contrast", _c.c_double), ("edge", _c.c_double)]
+
+
+def sift_opts(max_keypoints: int = 4096, n_octaves: int = 0, n_layers: int = 3, raw_capacity: int = 0,
+              sigma0: float = 1.6, sigma_in: float = 0.5, contrast: float = 0.04, edge: float = 10.0) -> SiftOpts:
+    return SiftOpts(n_octaves, n_layers, max_keypoints, raw_capacity, sigma0, sigma_in, contrast, edge)
+
+
+SIFT_KP_DTYPE = np.dtype([("x", "f4"), ("y", "f4"), ("size", "f4"), ("angle", "f4"), ("response", "f4"),
+                          ("xi", "i4"), ("yi", "i4"), ("octave", "i1"), ("layer", "i1"), ("peak", "i1"),
+                          ("pad", "i1")])
+
+
+def extract_sift(img, opts: SiftOpts = None, ws=None):
+    """SIFT on a u8 device image [H, W] (xa_extract_sift).  Returns (kp int32 [max, 8] holding
+    xa_sift_keypoint records, desc u8 [max, 128], count int32 [2] = written, found); decode the
+    keypoints with sift_keypoints_np."""
+    import torch
+    if img.dtype != torch.uint8 or img.dim() != 2:
+        raise ValueError("img must be a uint8 tensor [H, W]")
+    if opts is None:
+        opts = sift_opts()
+    h, w = int(img.shape[0]), int(img.shape[1])
+    pitch = int(img.stride(0))
+    if img.stride(1) != 1:
+        raise ValueError("img rows must be contiguous")
+    dev = img.device
+    need = lib().xa_sift_workspace_size(w, h, _c.byref(opts))
+    if need == 0:
+        raise XAError(-1, "invalid SIFT options or image size")
+    if ws is None:
+        ws = _empty(need, dev)
+    m = int(opts.max_keypoints)
+    kp = torch.empty((m, 8), dtype=torch.int32, device=dev)
+    desc = torch.empty((m, 128), dtype=torch.uint8, device=dev)
+    count = torch.empty(2, dtype=torch.int32, device=dev)
+    _check(lib().xa_extract_sift(_ptr(img), w, h, pitch, _c.byref(opts), _ptr(kp), _ptr(desc), _ptr(count),
+                                 _ptr(ws), ws.numel(), _stream()))
+    return kp, desc, count
+
+
+def sift_keypoints_np(kp, n: int) -> np.ndarray:
+    return np.ascontiguousarray(kp[:n].cpu().numpy()).view(SIFT_KP_DTYPE).reshape(-1)
 
 
 def l2_matches_np(out) -> np.ndarray:
@@ -1076,30 +1133,67 @@ def draw_samples(n: int, k: int, seed: int = 0) -> np.ndarray:
     return np.stack([g.choice(n, 4, replace=False) for _ in range(k)]).astype(np.int32)
 
 
-def precise_stage(A, B, params_a, params_b, pattern, n_levels: int = 8, n_features: int = 1000,
-                  fast_threshold: int = 20, ransac_k: int = 2000, th: float = 3.0, seed: int = 0,
-                  ratio_num: int = 4, ratio_den: int = 5):
-    """The stage after the search (Sec. III.C), for one pair of views: A and B (device u8
-    images) are re-simulated with Lanczos-4 at the best parameters (xa_affine_params rows),
-    ORB runs on both views and their matches are screened by homography RANSAC; eq. (7)
-    gives the inlier share.  Returns a dict with H (3x3 numpy, A original -> B original),
-    the number of matches, of inliers and their ratio, and the device point/inlier arrays."""
+def sift_features(img, opts: "SiftOpts" = None):
+    """SIFT keypoints and descriptors of a u8 device image: (kp, desc, n) with n the host count
+    (one synchronisation: the L2 matcher takes its sizes on the host)."""
+    kp, desc, count = extract_sift(img, opts)
+    n = int(count[0].item())
+    return kp, desc, n
+
+
+def sift_match_points(fq, ft, ratio_num: int = 3, ratio_den: int = 4, map_q=None, map_t=None):
+    """L2 matching of the query features fq against the train features ft (xa_match_l2) and the
+    kept matches' points and distances (xa_sift_match_points): (pq, pt, des, n) on the device,
+    points taken through the 2 x 3 maps map_q / map_t (None = identity)."""
     import torch
-    pa_plan = plan_image(A.shape[1], A.shape[0], make_params([tuple(params_a)]), n_levels, 1.2, n_features,
-                         fast_threshold)
-    pb_plan = plan_image(B.shape[1], B.shape[0], make_params([tuple(params_b)]), n_levels, 1.2, n_features,
-                         fast_threshold)
-    run = PairRunner(pa_plan, pb_plan, A.device)
-    run.run(A, B, pattern, ratio_num, ratio_den)
-    pa, pb, _, n_dev = best_pair_points(run.kp_a, run.kp_b, run.matches, run.count_a, run.count_b, run.best, 1,
-                                        n_features, ratio_num, ratio_den)
+    kq, dq, nq = fq
+    kt, dt, nt = ft
+    dev = kq.device
+    out, _ = match_l2(dq[:nq], dt[:nt], ratio_num, ratio_den)
+    pq = torch.empty((max(nq, 1), 2), dtype=torch.float64, device=dev)
+    pt = torch.empty((max(nq, 1), 2), dtype=torch.float64, device=dev)
+    des = torch.empty(max(nq, 1), dtype=torch.float64, device=dev)
+    n = torch.empty(1, dtype=torch.int32, device=dev)
+    mq = None if map_q is None else np.ascontiguousarray(map_q, np.float64).reshape(6)
+    mt = None if map_t is None else np.ascontiguousarray(map_t, np.float64).reshape(6)
+    _check(lib().xa_sift_match_points(_ptr(kq), _ptr(kt), _ptr(out), nq, nt, ratio_num, ratio_den,
+                                      None if mq is None else mq.ctypes.data, None if mt is None else mt.ctypes.data,
+                                      _ptr(pq), _ptr(pt), _ptr(des), _ptr(n), _stream()))
+    return pq, pt, des, n
+
+
+def simulated_view(img, params, interp: str = "lanczos4"):
+    """One simulated view of a u8 device image (the camera change of eq. (2), Lanczos-4 of
+    eqs. (3)-(4) after the anti-alias blur): (view u8 [H', W'] device tensor (a strided view
+    into the arena), inverse map view -> image as 6 floats)."""
+    plan = plan_image(int(img.shape[1]), int(img.shape[0]), make_params([tuple(params)]), 1, 1.2, 1, 20,
+                      interp=interp)
+    arena, _ = simulate_views(plan, img.contiguous())
+    v = plan.views[0]
+    o, w, h, p = int(v["offset"]), int(v["width"]), int(v["height"]), int(v["pitch"])
+    return arena[o:o + p * h].view(h, p)[:, :w], np.array(v["inv"], np.float64)
+
+
+def precise_stage(A, B, params_a, params_b, opts: "SiftOpts" = None, ransac_k: int = 2000, th: float = 3.0,
+                  seed: int = 0, ratio_num: int = 3, ratio_den: int = 4):
+    """The stage after the search (Sec. III.C): A and B (device u8 originals) are re-simulated
+    with Lanczos-4 at the best parameters (xa_affine_params rows), SIFT runs on both views, the
+    views' L2 matches (ratio num/den, Sec. IV.C) are taken back to the original images through the
+    views' inverse maps and screened by homography RANSAC; eq. (7) gives the inlier share.
+    Returns a dict with H (3x3 numpy, A original -> B original), the number of matches, of
+    inliers and their ratio, and the device point/inlier arrays."""
+    import torch
+    va, inv_a = simulated_view(A, params_a)
+    vb, inv_b = simulated_view(B, params_b)
+    fa, fb = sift_features(va, opts), sift_features(vb, opts)
+    pa, pb, _, n_dev = sift_match_points(fa, fb, ratio_num, ratio_den, inv_a, inv_b)
     n = int(n_dev.item())
     samples = torch.from_numpy(draw_samples(n, ransac_k, seed)).to(A.device)
     scores, best, H, inl = ransac_homography(pa[:n], pb[:n], samples, th)
     n_in = int(best[1].item())
     return {"H": H.cpu().numpy(), "matches": n, "inliers": max(n_in, 0),
             "inlier_ratio": max(n_in, 0) / n if n > 0 else 0.0, "pa": pa[:n], "pb": pb[:n], "inlier_mask": inl,
-            "samples": samples, "scores": scores}
+            "samples": samples, "scores": scores, "keypoints": (fa[2], fb[2])}
 
 
 def scaling_coefficient(pa, pb, dist, n):
@@ -1111,19 +1205,22 @@ def scaling_coefficient(pa, pb, dist, n):
     return f
 
 
-def select_base_image(A, B, pattern, n_levels: int = 8, n_features: int = 1000, fast_threshold: int = 20,
-                      ratio_num: int = 4, ratio_den: int = 5):
-    """Base-image selection of Sec. III.A on the unsimulated images: ORB on A and B, matching
-    A -> B gives f1 and B -> A gives f2 by eq. (1) (the matches' Hamming distances stand in for
-    the SIFT distances); A is the base when f1 > f2.  Returns ("A" | "B", f1, f2)."""
-    ident = make_params([(1.0, 0.0)])
-    pa_plan = plan_image(A.shape[1], A.shape[0], ident, n_levels, 1.2, n_features, fast_threshold)
-    pb_plan = plan_image(B.shape[1], B.shape[0], ident, n_levels, 1.2, n_features, fast_threshold)
+def scaling_coefficient_f64(pa, pb, des, n):
+    """Eq. (1) with fp64 descriptor distances (xa_scaling_coefficient_f64); a device fp64 [1]."""
+    import torch
+    f = torch.empty(1, dtype=torch.float64, device=pa.device)
+    _check(lib().xa_scaling_coefficient_f64(_ptr(pa), _ptr(pb), _ptr(des), _ptr(n), int(pa.shape[0]), _ptr(f),
+                                            _stream()))
+    return f
+
+
+def select_base_image(A, B, opts: "SiftOpts" = None, ratio_num: int = 3, ratio_den: int = 4):
+    """Base-image selection of Sec. III.A on the unsimulated images: SIFT on A and B, L2 matching
+    A -> B gives f1 and B -> A gives f2 by eq. (1) over the kept matches in query order, with
+    their SIFT descriptor distances; A is the base when f1 > f2.  Returns ("A" | "B", f1, f2)."""
+    fa, fb = sift_features(A, opts), sift_features(B, opts)
     f = []
-    for q_plan, t_plan, Q, T in ((pa_plan, pb_plan, A, B), (pb_plan, pa_plan, B, A)):
-        run = PairRunner(q_plan, t_plan, Q.device)
-        run.run(Q, T, pattern, ratio_num, ratio_den)
-        p1, p2, dist, n = best_pair_points(run.kp_a, run.kp_b, run.matches, run.count_a, run.count_b, run.best, 1,
-                                           n_features, ratio_num, ratio_den)
-        f.append(float(scaling_coefficient(p1, p2, dist, n).item()))
+    for fq, ft in ((fa, fb), (fb, fa)):
+        pq, pt, des, n = sift_match_points(fq, ft, ratio_num, ratio_den)
+        f.append(float(scaling_coefficient_f64(pq, pt, des, n).item()))
     return ("A" if f[0] > f[1] else "B"), f[0], f[1]

@@ -126,21 +126,20 @@ def test_best_pair_points_equal_the_oracle(dev):
 
 
 def test_precise_stage_recovers_the_ground_truth(dev):
-    """Re-simulation at the true view (tilt 2 along phi = 0 for A, identity for B), ORB, matching
-    and RANSAC on the tiny pair: H maps A's corners within 2 px of the ground truth and the
-    inlier share of eq. (7) is high."""
-    say("case: precise stage (Lanczos re-simulation, ORB, RANSAC) on the tiny pair")
+    """Re-simulation at the true view (tilt 2 along phi = 0 for A, identity for B), SIFT, L2
+    matching and RANSAC on the tiny pair: H maps A's corners within 2 px of the ground truth and
+    the inlier share of eq. (7) is high."""
+    say("case: precise stage (Lanczos re-simulation, SIFT, RANSAC) on the tiny pair")
     case = synth.make_pair(**synth.PAIR_CONFIGS["tiny"])
     A = torch.from_numpy(case.A).to(dev)
     B = torch.from_numpy(np.ascontiguousarray(case.B)).to(dev)
-    pat = torch.from_numpy(synth.brief_pattern()).to(dev)
-    out = X.precise_stage(A, B, (2.0, 0.0, 0.0, 1.0, 0.0, 0.0), (1.0, 0.0, 0.0, 1.0, 0.0, 0.0), pat, n_levels=3,
-                          n_features=500, ransac_k=1000, th=3.0)
+    out = X.precise_stage(A, B, (2.0, 0.0, 0.0, 1.0, 0.0, 0.0), (1.0, 0.0, 0.0, 1.0, 0.0, 0.0), ransac_k=1000,
+                          th=3.0)
     corners = np.array([[0.0, 0.0], [255.0, 0.0], [0.0, 255.0], [255.0, 255.0], [128.0, 128.0]])
     err = np.linalg.norm(_apply(out["H"], corners) - _apply(case.H, corners), axis=1)
     say(f"[precise] {out['matches']} matches, {out['inliers']} inliers (eq. 7: {out['inlier_ratio']:.3f}); "
         f"corner error {err.max():.2f} px")
-    assert out["matches"] > 40 and out["inlier_ratio"] >= 0.8 and err.max() <= 2.0
+    assert out["matches"] > 20 and out["inlier_ratio"] >= 0.8 and err.max() <= 2.0
     # the oracle's RANSAC on the same points and samples agrees
     pa, pb = out["pa"].cpu().numpy(), out["pb"].cpu().numpy()
     rs, rb, rH, rinl = OG.ransac(pa, pb, out["samples"].cpu().numpy(), 3.0)
@@ -149,14 +148,12 @@ def test_precise_stage_recovers_the_ground_truth(dev):
 
 
 def test_base_image_selection_prefers_the_closer_view(dev):
-    """Eq. (1) both ways on a pair where B is A's scene seen from twice the distance (every
-    length halves): A is the base (f1 > 0 > f2)."""
+    """Eq. (1) both ways on SIFT matches of a pair where B is A's scene seen from twice the
+    distance (every length halves): A is the base (f1 > 0 > f2)."""
     say("case: base-image selection (eq. (1)) on a pair with a 2x scale change")
     sc = synth.make_scene(512, 512, 160, 120, 77)
     A = synth.render(sc, np.eye(2), np.zeros(2), 512, 512, noise_seed=1)
     B = synth.render(sc, 0.5 * np.eye(2), np.zeros(2), 256, 256, noise_seed=2)
-    pat = torch.from_numpy(synth.brief_pattern()).to(dev)
-    base, f1, f2 = X.select_base_image(torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev), pat, n_levels=8,
-                                       n_features=500)
+    base, f1, f2 = X.select_base_image(torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev))
     say(f"[base image] {base}: f1 = {f1:.1f}, f2 = {f2:.1f}")
     assert base == "A" and f1 > 0 > f2

@@ -190,9 +190,11 @@ def test_descriptor_norm_and_clip():
     nrm = np.sqrt((v * v).sum(1))
     assert np.all(np.abs(nrm - 512) < 0.5 * math.sqrt(128) + 1)
     assert desc.max() <= 255
-    # the keypoints are sorted by (octave, layer, row, column, peak)
-    keys = list(zip(kp["octave"], kp["layer"], kp["yi"], kp["xi"], kp["peak"]))
-    assert keys == sorted(keys)
+    # keypoints come octave by octave; one candidate's peaks in bin order
+    assert np.all(np.diff(kp["octave"]) >= 0)
+    # keeping fewer keeps the first ones
+    kp2, desc2, total2 = S.extract(img, max_keypoints=7)
+    assert total2 == total and np.array_equal(kp2, kp[:7]) and np.array_equal(desc2, desc[:7])
 
 
 def test_rotation_by_90_degrees():
