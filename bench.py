@@ -162,8 +162,6 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["full", "tiny"], default="full")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-views", type=int, default=4, help="views per image in the CPU-baseline sample")
-    ap.add_argument("--cpu-pairs", type=int, default=64, help="view pairs in the CPU-baseline sample")
     ap.add_argument("--batch-pairs", type=int, default=64, help="image pairs in the batched leg (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--gen-workers", type=int, default=16,
@@ -176,6 +174,7 @@ def parse():
                          "with that many queries per lane, -1 = matrix-core kernel")
     ap.add_argument("--l2-n", type=int, default=32768, help="descriptors per set in the L2 matcher leg (0 = skip)")
     ap.add_argument("--no-sift", action="store_true", help="skip the SIFT leg")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the Sec. IV.D sweep leg")
     ap.add_argument("--only", choices=["batched", "diffwarp", "copy", "sweep", "l2", "sift"], default=None,
                     help="run one leg alone and print its JSON (for profiler runs); 'copy' is a plain 1 GiB "
                          "device-to-device copy whose counter readings calibrate the HBM traffic counters")
@@ -188,49 +187,169 @@ WORKLOADS = {
 }
 
 
-def cpu_baseline(case, grid, wl, n_views: int, n_pairs: int):
-    """Oracle (single process, numpy) on a sample: simulate + ORB on n_views evenly spaced views of
-    each image, Hamming matching on n_pairs of the view pairs they form; scaled to one full pair."""
-    import numpy as np
+# ---------------------------------------------------------------- oracle on all host cores
+# The whole oracle pipeline of one pair, split into independent tasks (simulate + ORB per view,
+# then one row of the view-pair matching table per task) over a pool of worker processes with
+# one BLAS / OpenMP thread each.  The pool is started before this process touches the GPU.
 
-    import synth
-    from oracle import match as OM
+_CPU_CTX = {}
+
+
+def _cpu_workers() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _cpu_init(ctx):
+    _CPU_CTX.clear()
+    _CPU_CTX.update(ctx)
+
+
+def _cpu_view_task(task):
+    """(key, i) -> (key, i, descriptors, seconds): oracle simulate + ORB of view i of image key."""
     from oracle import orb as OO
     from oracle import plan as OP
     from oracle import simulate as OS
-
-    pattern = synth.brief_pattern()
-    quotas = OP.level_quotas(wl["n_features"], wl["n_levels"])
-    nv = len(grid)
-    pick = sorted(set(int(round(x)) for x in np.linspace(0, nv - 1, n_views)))
-    t_view, feats = [], {"a": [], "b": []}
-    for key, img in (("a", case.A), ("b", case.B)):
-        for i in pick:
-            t, f = grid[i]
-            t0 = time.perf_counter()
-            v = OP.plan_view(img.shape[1], img.shape[0], t, f)
-            V, mask, U = OS.simulate_view(img, v)
-            dims = OP.level_dims(v.width, v.height, wl["n_levels"])
-            fe = OO.extract_view(U, mask, dims, quotas, wl["fast"], pattern)
-            t_view.append(time.perf_counter() - t0)
-            feats[key].append(fe["desc"])
-    pairs = [(i, j) for i in range(len(pick)) for j in range(len(pick))][:n_pairs]
-    reps = max(1, n_pairs // len(pairs))
+    key, i = task
+    c = _CPU_CTX
     t0 = time.perf_counter()
-    done = 0
-    for _ in range(reps):
-        for (i, j) in pairs:
-            OM.nearest_two(feats["a"][i], feats["b"][j])
-            done += 1
-    t_match = (time.perf_counter() - t0) / done
-    per_view = float(np.mean(t_view))
-    t_pair = per_view * 2 * nv + t_match * nv * nv
+    img = c[key]
+    t, f = c["grid"][i]
+    v = OP.plan_view(img.shape[1], img.shape[0], t, f)
+    V, mask, U = OS.simulate_view(img, v)
+    dims = OP.level_dims(v.width, v.height, c["n_levels"])
+    fe = OO.extract_view(U, mask, dims, c["quotas"], c["fast"], c["pattern"])
+    return key, i, fe["desc"], time.perf_counter() - t0
+
+
+def _cpu_match_task(task):
+    """(i, desc_a_i, descs_b) -> (i, counts over j, seconds): oracle matching of view i of A
+    against every view of B with the ratio test 4/5."""
+    from oracle import match as OM
+    i, da, dbs = task
+    t0 = time.perf_counter()
+    counts = []
+    for db in dbs:
+        idx, d1, d2 = OM.nearest_two(da, db)
+        counts.append(int(OM.ratio_accept(d1, d2, len(db), 4, 5).sum()))
+    return i, counts, time.perf_counter() - t0
+
+
+def _cpu_crop_task(task):
+    """(crop, params, gout) -> seconds: the oracle's fp64 forward and adjoint of one crop."""
+    from oracle import diffwarp as OD
+    crop, P, g = task
+    t0 = time.perf_counter()
+    OD.warp_forward(crop, P)
+    OD.warp_adjoint(crop, g, P)
+    return time.perf_counter() - t0
+
+
+def _cpu_context(name):
+    import numpy as np
+
+    import synth
+    from oracle import plan as OP
+    wl = WORKLOADS[name]
+    case = synth.make_pair(**synth.PAIR_CONFIGS[name])
+    grid = [(float(t), float(f)) for t, f in OP.sampling_grid(wl["n_tilt"])]
+    return {"a": case.A, "b": np.ascontiguousarray(case.B), "grid": grid, "n_levels": wl["n_levels"],
+            "quotas": OP.level_quotas(wl["n_features"], wl["n_levels"]), "fast": wl["fast"],
+            "pattern": synth.brief_pattern()}
+
+
+def _cpu_pair(pool, ctx, pick=None):
+    """The oracle's parameter search for one pair on the pool, whose workers hold ctx, over the
+    views `pick` of each image (all by default) and every view pair among them: (wall seconds,
+    seconds per view, seconds per view pair (summed over the workers' tasks), best pair)."""
+    n = len(ctx["grid"])
+    pick = list(range(n)) if pick is None else list(pick)
+    t0 = time.perf_counter()
+    views = pool.map(_cpu_view_task, [(k, i) for k in ("a", "b") for i in pick], chunksize=1)
+    feats = {"a": {}, "b": {}}
+    t_view = 0.0
+    for key, i, d, dt in views:
+        feats[key][i] = d
+        t_view += dt
+    rows = pool.map(_cpu_match_task, [(i, feats["a"][i], [feats["b"][j] for j in pick]) for i in pick],
+                    chunksize=1)
+    wall = time.perf_counter() - t0
+    best, t_match = (-1, -1, -1), 0.0
+    for i, counts, dt in sorted(rows):
+        t_match += dt
+        for jj, c in enumerate(counts):
+            if c > best[2]:
+                best = (i, pick[jj], c)
+    return wall, t_view / (2 * len(pick)), t_match / (len(pick) ** 2), best
+
+
+def cpu_baselines():
+    """The oracle timed on the host's cores (a spawn pool, one thread per worker).  Headline: the
+    full-size pair's search on a sample of 12 evenly spaced views of each image and the 144 view
+    pairs among them, scaled to the whole search (90 views, 2025 view pairs) by its measured
+    seconds per view and per view pair, at the sample's own parallel efficiency.  Also: the tiny
+    pair's whole search (median of 3) and 4 of the 256 differentiable-warp crops (fp64 forward +
+    adjoint)."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    import synth
+    workers = _cpu_workers()
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in saved:
+        os.environ[k] = "1"
+    try:
+        sp = mp.get_context("spawn")
+        progress(f"cpu baseline: oracle on {workers} worker processes")
+        ctx = _cpu_context("full")
+        nv = len(ctx["grid"])
+        pick = sorted(set(int(round(x)) for x in np.linspace(0, nv - 1, 12)))
+        with sp.Pool(workers, initializer=_cpu_init, initargs=(ctx,)) as pool:
+            wall_s, t_view, t_match, best = _cpu_pair(pool, ctx, pick)
+        work_s = t_view * 2 * len(pick) + t_match * len(pick) ** 2
+        work_full = t_view * 2 * nv + t_match * nv * nv
+        wall_full = wall_s * work_full / work_s
+        progress(f"cpu baseline: full-pair sample {wall_s:.1f} s wall, {work_s:.1f} s of work")
+        ctx = _cpu_context("tiny")
+        tiny = []
+        with sp.Pool(workers, initializer=_cpu_init, initargs=(ctx,)) as pool:
+            for _ in range(3):
+                w_, tv, tm, _ = _cpu_pair(pool, ctx)
+                m = len(ctx["grid"])
+                tiny.append((w_, tv * 2 * m + tm * m * m))
+        tiny = sorted(tiny)[1]
+        with sp.Pool(min(4, workers)) as pool:
+            crops = synth.make_crops(4, 512, 5000, distinct=4)
+            P = synth.crop_params(256, 5000)[:4]
+            g = synth.rng(5).standard_normal(crops.shape).astype(np.float32)
+            t0 = time.perf_counter()
+            per_crop = pool.map(_cpu_crop_task, [(crops[k], P[k], g[k]) for k in range(4)], chunksize=1)
+            dw_wall = time.perf_counter() - t0
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
     return {
-        "value": 1.0 / t_pair, "unit": "pairs/s", "cores": 1, "kind": "oracle",
-        "sample": f"simulate+ORB on {len(pick)} of {nv} views of each image ({per_view:.2f} s/view) and "
-                  f"{done} view-pair matchings ({t_match * 1e3:.1f} ms each); scaled to {2 * nv} views and "
-                  f"{nv * nv} view pairs per image pair",
-        "seconds_per_pair": t_pair,
+        "value": 1.0 / wall_full, "unit": "pairs/s", "cores": workers, "kind": "oracle",
+        "sample": f"the full-size pair: simulate + ORB of {len(pick)} evenly spaced views of each image "
+                  f"({t_view:.2f} s per view) and the {len(pick) ** 2} view-pair matchings among them "
+                  f"({t_match * 1e3:.1f} ms each) on {workers} worker processes with one thread each, "
+                  f"{wall_s:.1f} s wall for {work_s:.1f} s of work; scaled to {2 * nv} views and {nv * nv} view pairs",
+        "seconds_per_pair": wall_full, "single_core_seconds_per_pair": work_full,
+        "single_core_value": 1.0 / work_full, "sample_best_pair": list(best),
+        "configs": {
+            "tiny": {"pairs_per_s": 1.0 / tiny[0], "single_core_pairs_per_s": 1.0 / tiny[1], "cores": workers,
+                     "sample": "the tiny pair's whole search, median of 3"},
+            "diffwarp": {"crops_per_s": 4 / dw_wall, "single_core_crops_per_s": 4 / sum(per_crop), "cores": min(4, workers),
+                         "sample": "fp64 forward + adjoint of 4 of the 256 crops of 512x512, one per worker"},
+        },
+        "host_cpu": platform.processor() or platform.machine(), "host_cpu_count": os.cpu_count(),
     }
 
 
@@ -562,6 +681,12 @@ def main():
     if profiler_preloaded() and args.gen_workers > 0:
         progress("bench.py: profiler preloaded; rendering in this process (--gen-workers 0)")
         args.gen_workers = 0
+    cpu = None
+    if args.only is None and not args.no_cpu_baseline:
+        if profiler_preloaded():
+            progress("bench.py: profiler preloaded; no worker pool, so no oracle baseline")
+        else:
+            cpu = cpu_baselines()
     raw, gen_s = [], 0.0
     if args.batch_pairs > 0 and args.only in (None, "batched"):
         t0 = time.perf_counter()
@@ -755,8 +880,10 @@ def main():
         out["l2_matcher"] = l2_leg(args, dev)
     if not args.no_sift:
         out["sift"] = sift_leg(args, dev)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case, grid, wl, args.cpu_views, args.cpu_pairs)
+    if not args.no_sweep:
+        out["sweep"] = sweep_leg(args, dev, pattern)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -113,3 +113,65 @@ def test_paper_search_mode_end_to_end(dev, tiny):
     for i, f in enumerate(ref["feats_a"]):
         n = len(f["x"])
         assert count[i] == n and np.array_equal(desc[i][:n], f["desc"]), i
+
+
+def test_full_size_search_mode_ds_half_sampled(dev):
+    """The sweep's magnifications at full size: image A of the full-size pair over the coupled
+    grid with ds = 0.5 (s_i = 1 + 0.5 i up to 3.5, 45 views, 117 Mpx at level 0), nearest
+    sampling, matched against B's identity view.  Sampled views (s = 1, 2, 3, 3.5) equal the
+    oracle's; ORB on the GPU's own view 22 (t = 4, s = 3, 960 x 3670) is bit-exact; its
+    matching against B is bit-exact; the best pair is the argmax of the 45 pair counts."""
+    say("case: full-size A, coupled grid ds = 0.5 (s up to 3.5), nearest views, single-image matching")
+    case = synth.make_pair(**synth.PAIR_CONFIGS["full"])
+    A, B = case.A, np.ascontiguousarray(case.B)
+    grid = X.sampling_grid(5, 72.0, 0.5)
+    N, LV = 1000, 8
+    pa = X.plan_image(1024, 768, grid, LV, 1.2, N, 20, interp="nearest")
+    pb = X.plan_image(B.shape[1], B.shape[0], X.make_params([(1.0, 0.0)]), LV, 1.2, N, 20, interp="nearest")
+    pat_np = synth.brief_pattern()
+    pat = torch.from_numpy(pat_np).to(dev)
+    arena_a, mask_a = X.simulate_views(pa, torch.from_numpy(A).to(dev))
+    arena_b, mask_b = X.simulate_views(pb, torch.from_numpy(B).to(dev))
+    kpa, da, ca = X.extract_orb(pa, arena_a, mask_a, pat)
+    kpb, db, cb = X.extract_orb(pb, arena_b, mask_b, pat)
+    m, pc, best = X.match_views(da, ca, db, cb, 4, 5)
+    torch.cuda.synchronize()
+
+    def level0(plan, t, i):
+        L = plan.levels[i, 0]
+        o, w, h, p = int(L["offset"]), int(L["width"]), int(L["height"]), int(L["pitch"])
+        return t[o:o + p * h].reshape(h, p)[:, :w].cpu().numpy()
+
+    for i in (0, 10, 22, 35):
+        r = grid[i]
+        v = OP.plan_view(1024, 768, float(r["t"]), float(r["phi"]), 0.0, float(r["s"]))
+        V, M, U = OS.simulate_view(A, v, "nearest")
+        gu, gm = level0(pa, arena_a, i), level0(pa, mask_a, i).astype(bool)
+        assert gu.shape == U.shape and np.array_equal(gm, M), i
+        du = np.abs(gu.astype(int) - U.astype(int))
+        assert du.max() <= 1 and int((du > 0).sum()) <= max(1, 1e-4 * du.size), i
+        say(f"[search full view {i}] t {float(r['t']):.3f} s {float(r['s']):.1f}: {v.width}x{v.height}, "
+            f"u8 mismatches {int((du > 0).sum())}")
+    # ORB on the GPU's own view 22, bit-exact
+    i = 22
+    U, M = level0(pa, arena_a, i), level0(pa, mask_a, i).astype(bool)
+    v = pa.views[i]
+    f = OO.extract_view(U, M, OP.level_dims(int(v["width"]), int(v["height"]), LV), OP.level_quotas(N, LV), 20,
+                        pat_np)
+    n = len(f["x"])
+    g = X.keypoints_np(kpa)[i][:n]
+    assert int(ca[i]) == n
+    for k in ("x", "y", "level", "harris", "bin"):
+        assert np.array_equal(g[k], f[k]), k
+    assert np.array_equal(da[i].cpu().numpy()[:n], f["desc"])
+    # its matching against B's identity view, bit-exact on the GPU's descriptors
+    cbn = int(cb[0])
+    res, counts, _ = OM.match_views([da[i].cpu().numpy()[:n]], [db[0].cpu().numpy()[:cbn]], 4, 5)
+    idx, d1, d2, _ = res[0]
+    mm = X.matches_np(m)[i]
+    assert np.array_equal(mm[:n]["t"], idx) and np.array_equal(mm[:n]["d1"], d1) and np.array_equal(mm[:n]["d2"], d2)
+    pcn = pc.cpu().numpy()
+    assert pcn[i] == counts[0]
+    k = int(np.argmax(pcn))
+    assert best.cpu().tolist() == [k, k, 0, int(pcn[k])]
+    say(f"[search full] ORB of view 22 exact ({n} keypoints), its matches exact ({counts[0]}); best {best.tolist()}")
