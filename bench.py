@@ -401,6 +401,20 @@ def batched_leg(args, dev, pattern, raw, gen_s):
     del shared
     progress("batched leg: per-pair runs timed")
 
+    # the plain path fixed up front for this comparison: the same kernels, one launch per stage
+    # per view (the scale stage once per pair, simulate and ORB on one-view plans, matching one
+    # view of A against all of B's views per call), one host synchronisation per pair, no graph
+    pv = _plain_per_view_setup(X, batch, dev)
+    _plain_per_view_run(X, batch, pv, pattern, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for k in range(K):
+            _plain_per_view_run(X, batch, pv, pattern, k)
+            torch.cuda.synchronize()
+    per_view_s = (time.perf_counter() - t0) / steps
+    progress("batched leg: per-view plain path timed")
+
     batch.capture(pattern)
     batch.replay()
     torch.cuda.synchronize()
@@ -424,6 +438,8 @@ def batched_leg(args, dev, pattern, raw, gen_s):
         same &= bool(torch.equal(batch.best[k], r.best[0]))
         same &= bool(torch.equal(batch.pair_count[base:base + na * nb], r.pair_count))
         same &= bool(torch.equal(batch.desc[a0:a0 + na], r.desc[:na]))
+    same_pv = bool(torch.equal(batch.pair_count, pv["pair_count"])) and bool(torch.equal(batch.desc, pv["desc"])) \
+        and bool(torch.equal(batch.count, pv["count"]))
     sides = [(A.shape[1], A.shape[0], B.shape[1], B.shape[0]) for A, B in pairs]
     comparisons = 0
     counts = batch.count.cpu().numpy().astype(np.int64)
@@ -435,6 +451,13 @@ def batched_leg(args, dev, pattern, raw, gen_s):
         "pairs_per_s_batched": K / batch_s,
         "pairs_per_s_plain": K / plain_s,
         "batched_over_plain": plain_s / batch_s,
+        "pairs_per_s_plain_per_view": K / per_view_s,
+        "batched_over_plain_per_view": per_view_s / batch_s,
+        "plain_per_view": "the same kernels, one launch per stage per view: the scale stage once per pair, simulate "
+                          "and ORB on a one-view plan for each of the pair's 180 views, matching one view of A "
+                          "against B's 90 views per call; a host synchronisation after each pair, no graph",
+        "plain_per_view_launch_calls_per_pair": pv["calls_per_pair"],
+        "identical_to_plain_per_view": same_pv,
         "ms_per_batch": batch_s * 1e3,
         "event_ms_per_batch": batch_ev_s * 1e3,
         "ms_per_pair_plain": plain_s * 1e3 / K,
@@ -450,6 +473,64 @@ def batched_leg(args, dev, pattern, raw, gen_s):
         "mean_side_px": float(np.mean([math.sqrt(a * b) for a, b, _, _ in sides])),
         "generate_s": gen_s,
     }
+
+
+def _plain_per_view_setup(X, batch, dev):
+    """One-view plans for every view of the batch (in its numbering), per-pair scale plans, and
+    buffers of the batch's shapes for the plain per-view path."""
+    import numpy as np
+    import torch
+    L = X.lib()
+    table = batch.arena.table()
+    N = batch.mplan.n_features
+    plans = []
+    for v in range(batch.n_views):
+        p = X.plan_views(table, [batch.view_source[v]], np.array([batch.view_rows[v % len(batch.view_rows)]],
+                                                                   X.PARAMS_DTYPE), 8, 1.2, N, 20)
+        plans.append((p, X._ptr(p.device(dev))))
+    splans = []
+    for jobs in batch.pair_jobs:
+        sp = X.plan_scales(np.array(jobs, X.SCALE_JOB_DTYPE)) if jobs else None
+        splans.append((sp, X._ptr(sp.device(dev)) if sp else None))
+    arena_bytes = max(p.arena_bytes for p, _ in plans)
+    ws_bytes = max(max(L.xa_simulate_workspace_size(p.host_ptr()), L.xa_extract_workspace_size(p.host_ptr()))
+                   for p, _ in plans)
+    ws_bytes = max([ws_bytes] + [L.xa_scale_workspace_size(sp.host_ptr()) for sp, _ in splans if sp])
+    nv = batch.n_views
+    z = lambda *sh, dt=torch.uint8: torch.zeros(sh, dtype=dt, device=dev)  # noqa: E731
+    pv = {"plans": plans, "splans": splans, "arena": z(arena_bytes), "mask": z(arena_bytes), "ws": X._empty(ws_bytes, dev),
+          "sources": batch.sources.clone(), "kp": z(nv, N, 40), "desc": z(nv, N, 32), "count": z(nv, dt=torch.int32),
+          "matches": z(batch.mplan.total_pairs, N, 8), "pair_count": z(batch.mplan.total_pairs, dt=torch.int32),
+          "best": z(4, dt=torch.int32), "N": N}
+    a0, na, b0, nb = batch.pair_views[0]
+    pv["calls_per_pair"] = {"scale": 1 if splans[0][0] else 0, "simulate": na + nb, "extract": na + nb, "match": na}
+    return pv
+
+
+def _plain_per_view_run(X, batch, pv, pattern, k):
+    """Pair k through the plain per-view path (asynchronous; the caller synchronises)."""
+    L = X.lib()
+    st = X._stream()
+    N = pv["N"]
+    ws, wsb = X._ptr(pv["ws"]), pv["ws"].numel()
+    src = X._ptr(pv["sources"])
+    sp, spd = pv["splans"][k]
+    if sp:
+        X._check(L.xa_scale_sources(sp.host_ptr(), spd, src, None, ws, wsb, st))
+    a0, na, b0, nb = batch.pair_views[k]
+    arena, mask, pat = X._ptr(pv["arena"]), X._ptr(pv["mask"]), X._ptr(pattern)
+    kp, desc, count = pv["kp"], pv["desc"], pv["count"]
+    for v in list(range(a0, a0 + na)) + list(range(b0, b0 + nb)):
+        p, pd = pv["plans"][v]
+        X._check(L.xa_simulate_views(p.host_ptr(), pd, src, arena, mask, None, ws, wsb, st))
+        X._check(L.xa_extract_orb(p.host_ptr(), pd, arena, mask, pat, X._ptr(kp[v]), X._ptr(desc[v]),
+                                  X._ptr(count[v:v + 1]), ws, wsb, st))
+    base = int(batch.mplan.groups[k]["pair_base"])
+    for i in range(na):
+        q = base + i * nb
+        X._check(L.xa_match_views(X._ptr(desc[a0 + i]), X._ptr(count[a0 + i:a0 + i + 1]), 1, X._ptr(desc[b0]),
+                                  X._ptr(count[b0:b0 + nb]), nb, N, 4, 5, X._ptr(pv["matches"][q]),
+                                  X._ptr(pv["pair_count"][q:q + nb]), X._ptr(pv["best"]), st))
 
 
 def sweep_leg(args, dev, pattern):

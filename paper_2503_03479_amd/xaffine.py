@@ -783,8 +783,9 @@ class BatchRunner:
         else:
             rows = [(float(g[0]), float(g[1]), 0.0, float(g[2]) if len(g) > 2 else 1.0, 0.0, 0.0) for g in grid]
         pair_views = []          # per pair: list over sides of [(source index, scale)]
+        self.pair_jobs = []      # per pair: its scale-stage jobs
         for (A, B) in pairs:
-            sides = []
+            sides, pj = [], []
             for img in (A, B):
                 si = arena.add(img.shape[1], img.shape[0])
                 images[si] = img
@@ -796,9 +797,12 @@ class BatchRunner:
                         w, h = scaled_size(img.shape[1], img.shape[0], sc)
                         di = arena.add(w, h, sc)
                         jobs.append((arena.descs[si], arena.descs[di], sc))
+                        pj.append(jobs[-1])
                         srcs.append(di)
                 sides.append(srcs)
             pair_views.append(sides)
+            self.pair_jobs.append(pj)
+        self.view_rows = rows
         table = arena.table()
 
         def pair_plan(ps):
@@ -847,6 +851,7 @@ class BatchRunner:
         self.mplan = plan_matches(np.array(groups, GROUP_DTYPE), n_features, 0 if self._tune else queries_per_lane)
         self.mplan_q = int(np.frombuffer(self.mplan.blob, np.int32, 4)[3])
         self.view_scale = np.array([arena.descs[s][5] for s in vsrc_all])
+        self.view_source = list(vsrc_all)     # source index of each view (global numbering)
         self.n_views = len(vsrc_all)
         dev = self.device
         self.sources = torch.from_numpy(arena.pack(images)).to(dev)
