@@ -175,6 +175,7 @@ def parse():
     ap.add_argument("--l2-n", type=int, default=32768, help="descriptors per set in the L2 matcher leg (0 = skip)")
     ap.add_argument("--no-sift", action="store_true", help="skip the SIFT leg")
     ap.add_argument("--no-sweep", action="store_true", help="skip the Sec. IV.D sweep leg")
+    ap.add_argument("--no-tune-tiles", action="store_true", help="keep the built-in warp tile widths")
     ap.add_argument("--only", choices=["batched", "diffwarp", "copy", "sweep", "l2", "sift"], default=None,
                     help="run one leg alone and print its JSON (for profiler runs); 'copy' is a plain 1 GiB "
                          "device-to-device copy whose counter readings calibrate the HBM traffic counters")
@@ -790,6 +791,11 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    # warp tile widths per compression class, timed on this device before any plan is made
+    tile_widths, tile_ms = X.get_warp_tiles(), None
+    if not args.no_tune_tiles and args.only in (None, "batched", "sweep"):
+        tile_widths, tile_ms = X.tune_warp_tiles(dev)
+        progress(f"bench.py: warp tile widths {tile_widths.tolist()}")
     if args.only is not None:
         pattern = torch.from_numpy(synth.brief_pattern()).to(dev)
         if args.only == "batched":
@@ -948,6 +954,11 @@ def main():
         "precision_best_pair": {"correct": int(pr[0]), "matches": int(pr[1]), "th_px": 2.0},
         "keypoints": {"a": int(count_a.sum()), "b": int(count_b.sum())},
         "matcher_autotune": run.autotune,
+        "warp_tiles": {"widths_per_class": [int(w) for w in tile_widths],
+                       "rule": [16, 16, 8, 8, 8, 8, 4, 4],
+                       "ms_per_class_and_candidate": None if tile_ms is None else np.round(tile_ms, 4).tolist(),
+                       "candidates": list(X.WARP_CANDIDATES),
+                       "tuner": "xa_tune_warp_tiles on a 1024x768 test image, class k = tilt sqrt(2)^k"},
         "device": torch.cuda.get_device_name(0),
         "host_cpu": platform.processor() or platform.machine(),
         "host_cores": os.cpu_count(),

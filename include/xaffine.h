@@ -250,6 +250,31 @@ xa_status xa_simulate_views(const void* plan_host, const void* plan_dev, const u
                             uint8_t* d_arena, uint8_t* d_mask, float* d_values,
                             void* d_ws, size_t ws_bytes, hipStream_t stream);
 
+/* Warp tile widths (the output tiles of the view warp hold 512 pixels as w x 512 / w) per
+ * compression class: class k holds the views with sqrt(2)^k <= t / s < sqrt(2)^(k + 1), the
+ * last class open-ended.  Plans made after xa_set_warp_tiles use its widths (0 = the built-in
+ * rule: 16 below t / s = 2, 8 below 8, else 4); plans made before keep theirs.  The width
+ * changes only the speed: every view pixel is computed the same way.  widths: host arrays of
+ * XA_WARP_CLASSES entries in {0, 4, 8, 16, 32, 64} (NULL: the rule for every class);
+ * xa_get_warp_tiles returns the widths in effect.  XA_EINVAL for other widths. */
+#define XA_WARP_CLASSES 8
+#define XA_WARP_CANDIDATES 5
+xa_status xa_set_warp_tiles(const int32_t* widths);
+xa_status xa_get_warp_tiles(int32_t* widths);
+
+/* The autotuner of the warp tile widths: for each compression class k, the sampling grid's views
+ * of tilt sqrt(2)^k (scale 1) of a src_w x src_h test image are blurred once, then warped with
+ * each candidate width (4, 8, 16, 32, 64), 3 timed launches each after one untimed; widths[k]
+ * gets the fastest (ms[k][c], if not NULL, the mean times in milliseconds).  The result is not
+ * applied: pass it to xa_set_warp_tiles (and keep it per device).  Synchronises `stream` (it
+ * uploads a plan per candidate and reads events); not to be run concurrently with other work
+ * timed on the same device.  Workspace: xa_tune_warp_tiles_workspace_size(src_w, src_h) bytes,
+ * 256-byte aligned (0 for sizes outside 16..8192).  XA_EINVAL for sizes or pointers out of
+ * range; XA_EHIP for runtime errors. */
+size_t xa_tune_warp_tiles_workspace_size(int32_t src_w, int32_t src_h);
+xa_status xa_tune_warp_tiles(int32_t src_w, int32_t src_h, void* d_ws, size_t ws_bytes, hipStream_t stream,
+                             int32_t* widths, float* ms);
+
 /* The two stages of xa_simulate_views, callable one at a time (to time or to
  * repeat one of them).  xa_blur_views writes the blurred fp32 planes of the
  * plan's blurred views into the workspace; xa_warp_views resamples every view

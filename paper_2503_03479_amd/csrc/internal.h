@@ -31,6 +31,12 @@ inline int warp_tile_w(double t, double s) {
     const double c = t / s;
     return c < 2.0 ? 16 : (c < 8.0 ? 8 : 4);
 }
+// Warp tile width the planner uses for a view: the caller's table (xa_set_warp_tiles) or the
+// tuner's per-thread override for the view's compression class, else the rule above.
+int warp_class(double t, double s);
+int planned_warp_tile_w(double t, double s);
+void set_tile_override(const int32_t* widths);   // per thread; NULL ends the override
+bool valid_warp_tile_w(int32_t w);
 // The hardware deals consecutive blocks of a launch round-robin to the 8 XCDs, each with its
 // own L2.  For kernels whose neighbouring tiles share cache lines (narrow warp tiles), this
 // remap gives each XCD one contiguous run of tiles instead: block b, the i-th on XCD b % 8,

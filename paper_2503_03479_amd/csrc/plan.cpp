@@ -7,11 +7,35 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
 
 namespace xa {
+
+// Warp tile widths per compression class (set by the caller, e.g. from xa_tune_warp_tiles; 0 =
+// the built-in rule), and a per-thread override the tuner plans with.
+static std::mutex g_tiles_mu;
+static int32_t g_warp_tiles[XA_WARP_CLASSES] = {};
+static thread_local const int32_t* t_tile_override = nullptr;
+
+int warp_class(double t, double s) {
+    const double c = t / s;
+    const int k = int(std::floor(2.0 * std::log2(std::max(c, 1.0)) + 1e-9));
+    return std::min(std::max(k, 0), XA_WARP_CLASSES - 1);
+}
+
+int planned_warp_tile_w(double t, double s) {
+    const int k = warp_class(t, s);
+    if (t_tile_override && t_tile_override[k] > 0) return t_tile_override[k];
+    std::lock_guard<std::mutex> lock(g_tiles_mu);
+    return g_warp_tiles[k] > 0 ? g_warp_tiles[k] : warp_tile_w(t, s);
+}
+
+void set_tile_override(const int32_t* widths) { t_tile_override = widths; }
+
+bool valid_warp_tile_w(int32_t w) { return w == 4 || w == 8 || w == 16 || w == 32 || w == 64; }
 
 static thread_local std::string g_error;
 
@@ -381,7 +405,7 @@ extern "C" xa_status xa_plan_views(const xa_source_desc* sources, int32_t n_sour
             blur_tiles += int64_t((v.src_w + btw - 1) / btw) * ((v.src_h + bth - 1) / bth);
         }
         warp_prefix[i] = int32_t(warp_tiles);
-        v.warp_tile_w = warp_tile_w(v.p.t, v.p.s);
+        v.warp_tile_w = planned_warp_tile_w(v.p.t, v.p.s);
         {   // the residue depends on the view's linear map and tile width (the sources' sizes only
             // move the sample tiles): views that share them, as the grid's views of many pairs
             // do, share one search
@@ -494,4 +518,24 @@ extern "C" xa_status xa_plan_image(int32_t src_w, int32_t src_h, int32_t src_pit
     std::vector<int32_t> vs(n_views > 0 ? n_views : 0, 0);
     return xa_plan_views(&src, 1, vs.data(), params, n_views, n_levels, level_scale, n_features, fast_threshold, blob,
                          blob_cap, blob_bytes);
+}
+
+extern "C" xa_status xa_set_warp_tiles(const int32_t* widths) {
+    if (widths)
+        for (int k = 0; k < XA_WARP_CLASSES; ++k)
+            if (widths[k] != 0 && !valid_warp_tile_w(widths[k]))
+                return fail(XA_EINVAL, "warp tile width %d of class %d is not 0, 4, 8, 16, 32 or 64", widths[k], k);
+    std::lock_guard<std::mutex> lock(g_tiles_mu);
+    for (int k = 0; k < XA_WARP_CLASSES; ++k) g_warp_tiles[k] = widths ? widths[k] : 0;
+    return ok();
+}
+
+extern "C" xa_status xa_get_warp_tiles(int32_t* widths) {
+    if (!widths) return fail(XA_EINVAL, "NULL output");
+    std::lock_guard<std::mutex> lock(g_tiles_mu);
+    for (int k = 0; k < XA_WARP_CLASSES; ++k) {
+        const double c = std::pow(2.0, 0.5 * k + 0.25);     // a compression inside class k
+        widths[k] = g_warp_tiles[k] > 0 ? g_warp_tiles[k] : warp_tile_w(c, 1.0);
+    }
+    return ok();
 }

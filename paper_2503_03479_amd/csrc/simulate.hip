@@ -564,3 +564,152 @@ extern "C" xa_status xa_warp_views(const void* plan_host, const void* plan_dev, 
     return simulate_entry(plan_host, plan_dev, d_sources, d_arena, d_mask, d_values, d_ws, ws_bytes, stream,
                           kStageWarp);
 }
+
+// ------------------------------------------------------------------ warp tile tuning
+
+namespace xa {
+namespace {
+
+constexpr int kTuneCandidates[XA_WARP_CANDIDATES] = {4, 8, 16, 32, 64};
+
+__global__ void __launch_bounds__(256) k_tune_fill(uint8_t* __restrict__ p, int pitch, int w, int h) {
+    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+    if (x >= w) return;
+    uint32_t v = uint32_t(x) * 2654435761u ^ uint32_t(y) * 40503u;
+    v ^= v >> 15;
+    p[size_t(y) * pitch + x] = uint8_t(v);
+}
+
+// The views of compression class k: tilt sqrt(2)^k, longitudes 0, 72/t, 144/t, ... degrees below
+// 180 (the sampling grid's views of that tilt), scale 1.
+std::vector<xa_affine_params> class_views(int k) {
+    std::vector<xa_affine_params> v;
+    const double t = std::pow(2.0, 0.5 * k);
+    const double step = 72.0 / t;
+    for (int j = 0; k == 0 ? j < 1 : j * step < 180.0 - 1e-9; ++j) {
+        xa_affine_params p{t, j * step * 3.141592653589793 / 180.0, 0.0, 1.0, 0.0, 0.0};
+        v.push_back(p);
+    }
+    return v;
+}
+
+struct TunePlan {
+    std::vector<uint8_t> blob;
+};
+
+xa_status tune_plan(int w, int h, int pitch, int k, int width, TunePlan* out) {
+    const std::vector<xa_affine_params> views = class_views(k);
+    int32_t forced[XA_WARP_CLASSES];
+    for (int c = 0; c < XA_WARP_CLASSES; ++c) forced[c] = width;
+    set_tile_override(forced);
+    size_t bytes = 0;
+    xa_status s = xa_plan_image(w, h, pitch, views.data(), int32_t(views.size()), 1, 1.2, 1, 20, nullptr, 0, &bytes);
+    if (s == XA_OK) {
+        out->blob.assign(bytes, 0);
+        s = xa_plan_image(w, h, pitch, views.data(), int32_t(views.size()), 1, 1.2, 1, 20, out->blob.data(), bytes,
+                          &bytes);
+    }
+    set_tile_override(nullptr);
+    return s;
+}
+
+struct TuneLayout {
+    size_t src, blob, ws, arena, mask, total;
+    int pitch;
+};
+
+xa_status tune_layout(int w, int h, TuneLayout* L) {
+    L->pitch = (w + 15) / 16 * 16;
+    size_t blob = 0, ws = 0, arena = 0;
+    for (int k = 0; k < XA_WARP_CLASSES; ++k) {
+        TunePlan P;
+        const xa_status s = tune_plan(w, h, L->pitch, k, 8, &P);
+        if (s != XA_OK) return s;
+        PlanView pv;
+        plan_host_view(P.blob.data(), &pv);
+        blob = std::max(blob, P.blob.size());
+        ws = std::max(ws, simulate_ws_bytes(pv.h));
+        arena = std::max(arena, size_t(pv.h->arena_bytes));
+    }
+    size_t o = 0;
+    L->src = o;   o += align_up(size_t(L->pitch) * h);
+    L->blob = o;  o += align_up(blob);
+    L->ws = o;    o += align_up(ws);
+    L->arena = o; o += align_up(arena);
+    L->mask = o;  o += align_up(arena);
+    L->total = o;
+    return XA_OK;
+}
+
+}  // namespace
+}  // namespace xa
+
+extern "C" size_t xa_tune_warp_tiles_workspace_size(int32_t src_w, int32_t src_h) {
+    if (src_w < 16 || src_h < 16 || src_w > 8192 || src_h > 8192) return 0;
+    TuneLayout L;
+    return tune_layout(src_w, src_h, &L) == XA_OK ? L.total : 0;
+}
+
+extern "C" xa_status xa_tune_warp_tiles(int32_t src_w, int32_t src_h, void* d_ws, size_t ws_bytes, hipStream_t stream,
+                                        int32_t* widths, float* ms) {
+    if (src_w < 16 || src_h < 16 || src_w > 8192 || src_h > 8192)
+        return fail(XA_EINVAL, "tuning image must be 16..8192 pixels a side");
+    if (!widths) return fail(XA_EINVAL, "NULL output");
+    TuneLayout L;
+    xa_status s = tune_layout(src_w, src_h, &L);
+    if (s != XA_OK) return s;
+    if (!d_ws || ws_bytes < L.total || reinterpret_cast<uintptr_t>(d_ws) % kAlign)
+        return fail(XA_EINVAL, "workspace of %zu bytes (256-byte aligned) needed, %zu given", L.total, ws_bytes);
+    uint8_t* base = static_cast<uint8_t*>(d_ws);
+    uint8_t* src = base + L.src;
+    void* blob_dev = base + L.blob;
+    float* blurred = reinterpret_cast<float*>(base + L.ws);
+    uint8_t* arena = base + L.arena;
+    uint8_t* mask = base + L.mask;
+    hipLaunchKernelGGL(k_tune_fill, dim3(unsigned((src_w + 255) / 256), unsigned(src_h)), dim3(256), 0, stream, src,
+                       L.pitch, src_w, src_h);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) return hip_fail(e, "event create");
+    constexpr int kReps = 3;
+    for (int k = 0; k < XA_WARP_CLASSES && s == XA_OK; ++k) {
+        float best_ms = 0.0f;
+        int best_w = 0;
+        for (int c = 0; c < XA_WARP_CANDIDATES && s == XA_OK; ++c) {
+            TunePlan P;
+            s = tune_plan(src_w, src_h, L.pitch, k, kTuneCandidates[c], &P);
+            if (s != XA_OK) break;
+            if (P.blob.size() > L.ws - L.blob) {     // the plan's slot in the workspace
+                s = fail(XA_EUNSUPPORTED, "tuning plan larger than its workspace slot");
+                break;
+            }
+            e = hipMemcpyAsync(blob_dev, P.blob.data(), P.blob.size(), hipMemcpyHostToDevice, stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(stream);     // the host blob goes out of scope below
+            if (e != hipSuccess) { s = hip_fail(e, "plan upload"); break; }
+            PlanView ph;
+            plan_host_view(P.blob.data(), &ph);
+            const PlanView pd = plan_dev_view(P.blob.data(), blob_dev);
+            if (c == 0) s = launch_simulate(ph, pd, src, arena, mask, nullptr, blurred, stream, kStageBlur);
+            if (s == XA_OK) s = launch_simulate(ph, pd, src, arena, mask, nullptr, blurred, stream, kStageWarp);
+            e = hipEventRecord(e0, stream);
+            for (int r = 0; r < kReps && s == XA_OK; ++r)
+                s = launch_simulate(ph, pd, src, arena, mask, nullptr, blurred, stream, kStageWarp);
+            if (e == hipSuccess) e = hipEventRecord(e1, stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float t = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+            if (e != hipSuccess) { s = hip_fail(e, "tuning timing"); break; }
+            t /= kReps;
+            if (ms) ms[k * XA_WARP_CANDIDATES + c] = t;
+            if (best_w == 0 || t < best_ms) {
+                best_ms = t;
+                best_w = kTuneCandidates[c];
+            }
+        }
+        widths[k] = best_w;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return s == XA_OK ? ok() : s;
+}

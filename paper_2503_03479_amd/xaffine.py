@@ -113,6 +113,11 @@ _SIGS = {
                                         _c.c_void_p, _c.c_void_p, _c.c_void_p]),
     "xa_scaling_coefficient_f64": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32,
                                               _c.c_void_p, _c.c_void_p]),
+    "xa_set_warp_tiles": (_c.c_int, [_c.c_void_p]),
+    "xa_get_warp_tiles": (_c.c_int, [_c.c_void_p]),
+    "xa_tune_warp_tiles_workspace_size": (_c.c_size_t, [_c.c_int32, _c.c_int32]),
+    "xa_tune_warp_tiles": (_c.c_int, [_c.c_int32, _c.c_int32, _c.c_void_p, _c.c_size_t, _c.c_void_p, _c.c_void_p,
+                                      _c.c_void_p]),
     "xa_match_batch_workspace_size": (_c.c_size_t, [_c.c_void_p, _c.c_int32, _c.c_void_p]),
     "xa_match_batch": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                   _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_int32, _c.c_void_p,
@@ -188,6 +193,54 @@ def sampling_grid(n_tilt: int, b_deg: float = 72.0, delta_s: float = 0.0) -> np.
 
 
 INTERP = {"lanczos4": 0, "nearest": 1}
+
+
+WARP_CLASSES = 8
+WARP_CANDIDATES = (4, 8, 16, 32, 64)
+_TUNED_TILES = {}        # device name -> widths chosen by tune_warp_tiles in this process
+
+
+def set_warp_tiles(widths=None):
+    """Warp tile widths per compression class for plans made from now on (None: the built-in rule)."""
+    if widths is None:
+        _check(lib().xa_set_warp_tiles(None))
+        return
+    w = np.ascontiguousarray(widths, np.int32)
+    if w.shape != (WARP_CLASSES,):
+        raise XAError(-1, f"need {WARP_CLASSES} widths")
+    _check(lib().xa_set_warp_tiles(w.ctypes.data))
+
+
+def get_warp_tiles() -> np.ndarray:
+    w = np.zeros(WARP_CLASSES, np.int32)
+    _check(lib().xa_get_warp_tiles(w.ctypes.data))
+    return w
+
+
+def tune_warp_tiles(device="cuda", src_w: int = 1024, src_h: int = 768, apply: bool = True, cache: bool = True):
+    """Run the library's warp tile tuner (xa_tune_warp_tiles) on `device`; returns (widths int32
+    [classes], ms float32 [classes, candidates]).  With apply, the widths are set for the plans
+    made from then on; with cache, a device already tuned in this process is not timed again
+    (ms is then None)."""
+    import torch
+    dev = torch.device(device)
+    name = torch.cuda.get_device_name(dev)
+    if cache and name in _TUNED_TILES:
+        widths, ms = _TUNED_TILES[name], None
+    else:
+        need = lib().xa_tune_warp_tiles_workspace_size(src_w, src_h)
+        if need == 0:
+            raise XAError(-1, "tuning image size out of range")
+        ws = _empty(need, dev)
+        widths = np.zeros(WARP_CLASSES, np.int32)
+        ms = np.zeros((WARP_CLASSES, len(WARP_CANDIDATES)), np.float32)
+        with torch.cuda.device(dev):
+            _check(lib().xa_tune_warp_tiles(src_w, src_h, _ptr(ws), ws.numel(), _stream(), widths.ctypes.data,
+                                            ms.ctypes.data))
+        _TUNED_TILES[name] = widths.copy()
+    if apply:
+        set_warp_tiles(widths)
+    return widths, ms
 
 
 def _set_interp(plan: "Plan", interp: str) -> "Plan":

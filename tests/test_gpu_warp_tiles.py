@@ -1,0 +1,65 @@
+"""GPU: the warp tile tuner (xa_tune_warp_tiles) and tuned plans.  The tuner times every
+candidate width per compression class and returns valid widths; a plan made with tuned widths
+(or any other widths) simulates the same views byte for byte as the rule's plan, since the
+tile width changes only which threads compute a pixel, not how."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+X = pytest.importorskip("paper_2503_03479_amd.xaffine")
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    X.lib()
+    return torch.device("cuda:0")
+
+
+def test_tuner_returns_valid_widths(dev):
+    say("case: warp tile tuner on a 512 x 384 test image")
+    try:
+        widths, ms = X.tune_warp_tiles(dev, 512, 384, apply=False, cache=False)
+        torch.cuda.synchronize()
+        assert all(int(w) in X.WARP_CANDIDATES for w in widths)
+        assert np.all(ms > 0) and np.all(np.isfinite(ms))
+        # each class's width is its fastest candidate
+        for k in range(X.WARP_CLASSES):
+            assert ms[k, X.WARP_CANDIDATES.index(int(widths[k]))] == ms[k].min()
+        say(f"[tuner] widths {widths.tolist()}")
+    finally:
+        X.set_warp_tiles(None)
+
+
+def test_tuned_and_rule_plans_simulate_the_same_views(dev):
+    say("case: the full-size pair's image A: rule widths against widths 64 / 4 / 32 per class")
+    case = synth.make_pair(**synth.PAIR_CONFIGS["full"])
+    src = torch.from_numpy(np.ascontiguousarray(case.A)).to(dev)
+    grid = X.sampling_grid(5)
+    outs = []
+    try:
+        for widths in (None, [64, 4, 32, 4, 64, 16, 4, 4], [4, 64, 4, 32, 8, 64, 4, 4]):
+            X.set_warp_tiles(widths)
+            plan = X.plan_image(1024, 768, grid, 8, 1.2, 1000, 20)
+            arena, mask = X.simulate_views(plan, src)
+            torch.cuda.synchronize()
+            outs.append((plan.views["warp_tile_w"].copy(), arena.cpu().numpy(), mask.cpu().numpy()))
+    finally:
+        X.set_warp_tiles(None)
+    (w0, a0, m0) = outs[0]
+    for (w, a, m) in outs[1:]:
+        assert not np.array_equal(w, w0)
+        assert np.array_equal(a, a0) and np.array_equal(m, m0)
+    say("[tiles] views identical under three width tables")

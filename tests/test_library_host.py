@@ -292,3 +292,37 @@ def test_check_reports_runtime_state(L):
     # a host-rejected argument error leaves nothing pending for xa_check
     assert L.xa_match_views(256, 256, 0, 256, 256, 1, 100, 4, 5, 256, 256, 256, None) == X.XA_EINVAL
     assert L.xa_check(None) == st
+
+
+def test_warp_tile_table_drives_the_planner(L):
+    """xa_set_warp_tiles: widths per compression class, validated, used by plans made afterwards
+    only; NULL restores the built-in rule (16 below t/s = 2, 8 below 8, else 4)."""
+    rule = X.get_warp_tiles()
+    assert rule.tolist() == [16, 16, 8, 8, 8, 8, 4, 4]
+    grid = X.sampling_grid(5)
+    before = X.plan_image(640, 480, grid, 3, 1.2, 300, 20)
+    try:
+        X.set_warp_tiles([32, 16, 8, 8, 4, 4, 64, 4])
+        assert X.get_warp_tiles().tolist() == [32, 16, 8, 8, 4, 4, 64, 4]
+        p = X.plan_image(640, 480, grid, 3, 1.2, 300, 20)
+        want = {1.0: 32, 1.414: 16, 2.0: 8, 2.828: 8, 4.0: 4, 5.657: 4}
+        for v in p.views:
+            assert v["warp_tile_w"] == want[round(float(v["p"]["t"]), 3)]
+        # the class is that of the compression t / s: t = 8 is class 6, t = 4 magnified by s = 2 class 2
+        p2 = X.plan_image(640, 480, X.make_params([(8.0, 0.0, 0.0, 1.0), (4.0, 0.0, 0.0, 2.0)]), 3, 1.2, 300, 20)
+        assert p2.views["warp_tile_w"].tolist() == [64, 8]
+        # tiles of a view cover it: the warp prefix counts ceil(W / w) ceil(H / (512 / w)) per view
+        wp = np.frombuffer(p.blob, np.int32, p.n_views + 1, int(p.header["off_warp_prefix"]))
+        for i, v in enumerate(p.views):
+            w = int(v["warp_tile_w"])
+            assert wp[i + 1] - wp[i] == -(-int(v["width"]) // w) * -(-int(v["height"]) // (512 // w))
+        for bad in ([3] + [0] * 7, [0] * 7 + [128]):
+            with pytest.raises(X.XAError):
+                X.set_warp_tiles(bad)
+        # plans made before keep their widths
+        assert before.views["warp_tile_w"][0] == 16
+    finally:
+        X.set_warp_tiles(None)
+    assert X.get_warp_tiles().tolist() == rule.tolist()
+    assert X.lib().xa_tune_warp_tiles_workspace_size(8, 8) == 0
+    assert X.lib().xa_tune_warp_tiles_workspace_size(1024, 768) > 1024 * 768
