@@ -368,6 +368,25 @@ xa_status xa_match_groups(const void* mplan_host, const void* mplan_dev, const u
                           int32_t n_views, int32_t ratio_num, int32_t ratio_den, xa_match* d_matches,
                           int32_t* d_pair_count, int32_t* d_best, hipStream_t stream);
 
+/* The matcher's autotuner: every variant (1, 2, 4 queries per lane, XA_MATCH_MATRIX) runs the
+ * given groups on the given descriptor set (d_desc, d_count, n_views as for xa_match_groups),
+ * once untimed and `reps` times timed with HIP events; *best_variant gets the fastest (ms[4],
+ * if not NULL, the mean times in milliseconds, in the order above).  Every variant's results are
+ * the same; d_matches, d_pair_count and d_best receive them (sized as for xa_match_groups).  The
+ * workspace holds the plans' device copies: xa_tune_matcher_workspace_size(groups, n_groups,
+ * n_features) bytes, 256-byte aligned.  The library keeps each result per device, keyed by the
+ * group table, n_features and the per-view counts (read from d_count); with XA_TUNE_USE_CACHE in
+ * `flags` a known key returns its stored result and launches nothing (the outputs are then left
+ * as they are); without it the variants are timed again and the entry replaced.  Synchronises
+ * `stream`.  XA_EINVAL as for xa_plan_matches / xa_match_groups, for reps outside 1..1000 or for
+ * unknown flags. */
+#define XA_TUNE_USE_CACHE 1
+size_t xa_tune_matcher_workspace_size(const xa_match_group* groups, int32_t n_groups, int32_t n_features);
+xa_status xa_tune_matcher(const xa_match_group* groups, int32_t n_groups, int32_t n_features, const uint8_t* d_desc,
+                          const int32_t* d_count, int32_t n_views, int32_t reps, int32_t flags,
+                          xa_match* d_matches, int32_t* d_pair_count, int32_t* d_best, void* d_ws, size_t ws_bytes,
+                          hipStream_t stream, int32_t* best_variant, float* ms);
+
 /* Exact L2 nearest-two matching of SIFT descriptors (the SIFT feature matching of Sec. III.A and
  * III.C, screened by the nearest / second-nearest distance ratio of Sec. IV.C), for descriptors in
  * their usual 8-bit form: 128 components 0..255 per descriptor, row-major, d_q [n_q][128] and
@@ -589,6 +608,15 @@ xa_status xa_ransac_homography(const double* d_pa, const double* d_pb, int32_t n
  * shapes there): xa_warp_f32_fwd_workspace_size and xa_warp_f32_bwd_workspace_size.
  * XA_EINVAL for sizes below 1, NULL or misaligned buffers; XA_ECAPACITY for a short
  * workspace; XA_EUNSUPPORTED above 2^28 pixels per crop or 2^38 in all. */
+/* Separable Gaussian blur of n fp32 crops h x w (d_in, d_out [n][h][w], device; may not
+ * alias): taps exp(-k^2 / 2 sigma^2) for |k| <= max(1, ceil(3 sigma)), normalised, edge pixels
+ * replicated, rows then columns.  The coarse-to-fine smoothing of the photometric refinement of
+ * (t, phi) (crop and target smoothed alike).  Workspace: xa_blur_f32_workspace_size(n, h, w)
+ * bytes (the row pass).  XA_EINVAL for sizes beyond 65535 crops or rows, or sigma outside (0, 16]. */
+size_t xa_blur_f32_workspace_size(int32_t n, int32_t h, int32_t w);
+xa_status xa_blur_f32(const float* d_in, int32_t n, int32_t h, int32_t w, double sigma, float* d_out, void* d_ws,
+                      size_t ws_bytes, hipStream_t stream);
+
 size_t xa_warp_f32_fwd_workspace_size(int32_t n, int32_t h, int32_t w);
 xa_status xa_warp_f32_fwd(const float* d_img, int32_t n, int32_t h, int32_t w, const xa_affine_params* d_params,
                           float* d_out, uint8_t* d_mask, void* d_ws, size_t ws_bytes, hipStream_t stream);

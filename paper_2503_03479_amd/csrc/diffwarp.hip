@@ -634,6 +634,29 @@ int dw_slots(int w, int h) {
     return best;
 }
 
+// Separable Gaussian of fp32 crops (the coarse-to-fine smoothing of the photometric refinement):
+// taps exp(-k^2 / 2 sigma^2), |k| <= max(1, ceil(3 sigma)), normalised; edge pixels replicated.
+constexpr int kCropBlurMaxTaps = 97;     // sigma up to 16
+struct CropTaps {
+    float w[kCropBlurMaxTaps];
+    int r;
+};
+
+template <bool ROWS>
+__global__ void __launch_bounds__(256) k_crop_blur(const float* __restrict__ in, int h, int w, CropTaps t,
+                                                   float* __restrict__ out) {
+    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, c = blockIdx.z;
+    if (x >= w) return;
+    const float* base = in + size_t(c) * h * w;
+    float acc = 0.0f;
+    for (int k = -t.r; k <= t.r; ++k) {
+        const float v = ROWS ? base[size_t(y) * w + min(max(x + k, 0), w - 1)]
+                             : base[size_t(min(max(y + k, 0), h - 1)) * w + x];
+        acc = fmaf(t.w[k + t.r], v, acc);
+    }
+    out[(size_t(c) * h + y) * w + x] = acc;
+}
+
 struct DwGeom {
     int slots;
     long long slot_total;
@@ -764,4 +787,32 @@ extern "C" xa_status xa_warp_f32_bwd(const float* d_img, const float* d_gout, co
         hipLaunchKernelGGL(k_dw_reduce, dim3(unsigned(n)), dim3(256), 0, stream, W.partial, W.prefix, d_gparams);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? ok() : hip_fail(e, "warp backward launch");
+}
+
+extern "C" size_t xa_blur_f32_workspace_size(int32_t n, int32_t h, int32_t w) {
+    if (n < 1 || h < 1 || w < 1) return 0;
+    return align_up(size_t(n) * h * w * sizeof(float));
+}
+
+extern "C" xa_status xa_blur_f32(const float* d_in, int32_t n, int32_t h, int32_t w, double sigma, float* d_out,
+                                 void* d_ws, size_t ws_bytes, hipStream_t stream) {
+    if (n < 1 || h < 1 || w < 1 || n > 65535 || h > 65535 || (long long)n * h * w > (1LL << 34))
+        return fail(XA_EINVAL, "need 1 <= n, h <= 65535, w >= 1 and at most 2^34 values");
+    if (!(sigma > 0.0) || !(sigma <= 16.0)) return fail(XA_EINVAL, "sigma must lie in (0, 16]");
+    if (!d_in || !d_out) return fail(XA_EINVAL, "NULL pointer");
+    const size_t need = xa_blur_f32_workspace_size(n, h, w);
+    if (!d_ws || ws_bytes < need || reinterpret_cast<uintptr_t>(d_ws) % 4)
+        return fail(XA_EINVAL, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    CropTaps t;
+    t.r = std::max(1, int(std::ceil(3.0 * sigma)));
+    double sum = 0.0;
+    double raw[kCropBlurMaxTaps];
+    for (int k = -t.r; k <= t.r; ++k) sum += (raw[k + t.r] = std::exp(-double(k) * k / (2.0 * sigma * sigma)));
+    for (int k = 0; k <= 2 * t.r; ++k) t.w[k] = float(raw[k] / sum);
+    const dim3 grid(unsigned((w + 255) / 256), unsigned(h), unsigned(n));
+    float* tmp = static_cast<float*>(d_ws);
+    hipLaunchKernelGGL(k_crop_blur<true>, grid, dim3(256), 0, stream, d_in, h, w, t, tmp);
+    hipLaunchKernelGGL(k_crop_blur<false>, grid, dim3(256), 0, stream, tmp, h, w, t, d_out);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? ok() : hip_fail(e, "crop blur launch");
 }

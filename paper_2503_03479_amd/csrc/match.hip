@@ -8,6 +8,8 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -580,4 +582,113 @@ extern "C" xa_status xa_match_groups(const void* mplan_host, const void* mplan_d
     s = launch_match_plan(mplan_host, mplan_dev, d_desc, d_count, ratio_num, ratio_den, d_matches, d_pair_count,
                           d_best, stream);
     return s == XA_OK ? ok() : s;
+}
+
+extern "C" size_t xa_tune_matcher_workspace_size(const xa_match_group* groups, int32_t n_groups, int32_t n_features) {
+    size_t most = 0;
+    const int variants[4] = {1, 2, 4, XA_MATCH_MATRIX};
+    for (int v : variants) {
+        size_t bytes = 0;
+        if (xa_plan_matches(groups, n_groups, n_features, v, nullptr, 0, &bytes) != XA_OK) return 0;
+        most = std::max(most, bytes);
+    }
+    return align_up(most);
+}
+
+namespace {
+// The tuner's results, per device, keyed by everything the matcher's run time depends on: the
+// group table, n_features and the per-view counts (the descriptor bits do not matter).
+struct TuneEntry {
+    int32_t best;
+    float ms[4];
+};
+std::mutex g_tune_mu;
+std::map<std::pair<int, uint64_t>, TuneEntry> g_tune_cache;
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+    const uint8_t* b = static_cast<const uint8_t*>(p);
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+    return h;
+}
+}  // namespace
+
+extern "C" xa_status xa_tune_matcher(const xa_match_group* groups, int32_t n_groups, int32_t n_features,
+                                     const uint8_t* d_desc, const int32_t* d_count, int32_t n_views, int32_t reps,
+                                     int32_t flags, xa_match* d_matches, int32_t* d_pair_count, int32_t* d_best,
+                                     void* d_ws, size_t ws_bytes, hipStream_t stream, int32_t* best_variant,
+                                     float* ms) {
+    if (!best_variant) return fail(XA_EINVAL, "NULL output");
+    if (reps < 1 || reps > 1000) return fail(XA_EINVAL, "reps must lie in 1..1000");
+    if (flags & ~XA_TUNE_USE_CACHE) return fail(XA_EINVAL, "unknown flags 0x%x", unsigned(flags));
+    const size_t need = xa_tune_matcher_workspace_size(groups, n_groups, n_features);
+    if (need == 0) return fail(XA_EINVAL, "invalid match groups");
+    if (!d_ws || ws_bytes < need || reinterpret_cast<uintptr_t>(d_ws) % kAlign)
+        return fail(XA_EINVAL, "workspace of %zu bytes (256-byte aligned) needed, %zu given", need, ws_bytes);
+    if (!d_count || n_views < 1) return fail(XA_EINVAL, "need the per-view counts");
+    int device = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::vector<int32_t> counts(size_t(n_views), 0);
+    e = hipMemcpyAsync(counts.data(), d_count, counts.size() * sizeof(int32_t), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "count download");
+    uint64_t key = fnv1a(1469598103934665603ull, groups, size_t(n_groups) * sizeof(xa_match_group));
+    key = fnv1a(key, &n_features, sizeof n_features);
+    key = fnv1a(key, counts.data(), counts.size() * sizeof(int32_t));
+    if (flags & XA_TUNE_USE_CACHE) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        const auto it = g_tune_cache.find({device, key});
+        if (it != g_tune_cache.end()) {
+            *best_variant = it->second.best;
+            if (ms) std::copy(it->second.ms, it->second.ms + 4, ms);
+            return ok();
+        }
+    }
+    const int variants[4] = {1, 2, 4, XA_MATCH_MATRIX};
+    TuneEntry entry{};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) return hip_fail(e, "event create");
+    xa_status s = XA_OK;
+    float best = 0.0f;
+    int best_v = 0;
+    for (int i = 0; i < 4 && s == XA_OK; ++i) {
+        size_t bytes = 0;
+        s = xa_plan_matches(groups, n_groups, n_features, variants[i], nullptr, 0, &bytes);
+        if (s != XA_OK) break;
+        std::vector<uint8_t> blob(bytes);
+        s = xa_plan_matches(groups, n_groups, n_features, variants[i], blob.data(), bytes, &bytes);
+        if (s != XA_OK) break;
+        e = hipMemcpyAsync(d_ws, blob.data(), bytes, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);     // the host blob goes out of scope below
+        if (e != hipSuccess) { s = hip_fail(e, "plan upload"); break; }
+        s = xa_match_groups(blob.data(), d_ws, d_desc, d_count, n_views, 4, 5, d_matches, d_pair_count, d_best, stream);
+        e = hipEventRecord(e0, stream);
+        for (int r = 0; r < reps && s == XA_OK; ++r)
+            s = xa_match_groups(blob.data(), d_ws, d_desc, d_count, n_views, 4, 5, d_matches, d_pair_count, d_best,
+                                stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float t = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        if (e != hipSuccess) { s = hip_fail(e, "matcher timing"); break; }
+        t /= reps;
+        entry.ms[i] = t;
+        if (best_v == 0 || t < best) {
+            best = t;
+            best_v = variants[i];
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (s != XA_OK) return s;
+    entry.best = best_v;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[{device, key}] = entry;
+    }
+    *best_variant = best_v;
+    if (ms) std::copy(entry.ms, entry.ms + 4, ms);
+    return ok();
 }

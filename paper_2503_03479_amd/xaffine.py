@@ -118,6 +118,13 @@ _SIGS = {
     "xa_tune_warp_tiles_workspace_size": (_c.c_size_t, [_c.c_int32, _c.c_int32]),
     "xa_tune_warp_tiles": (_c.c_int, [_c.c_int32, _c.c_int32, _c.c_void_p, _c.c_size_t, _c.c_void_p, _c.c_void_p,
                                       _c.c_void_p]),
+    "xa_tune_matcher_workspace_size": (_c.c_size_t, [_c.c_void_p, _c.c_int32, _c.c_int32]),
+    "xa_tune_matcher": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_int32,
+                                   _c.c_int32, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_size_t,
+                                   _c.c_void_p, _c.c_void_p, _c.c_void_p]),
+    "xa_blur_f32_workspace_size": (_c.c_size_t, [_c.c_int32, _c.c_int32, _c.c_int32]),
+    "xa_blur_f32": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_double, _c.c_void_p,
+                               _c.c_void_p, _c.c_size_t, _c.c_void_p]),
     "xa_match_batch_workspace_size": (_c.c_size_t, [_c.c_void_p, _c.c_int32, _c.c_void_p]),
     "xa_match_batch": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                   _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_int32, _c.c_void_p,
@@ -735,22 +742,22 @@ MATCH_MATRIX = -1          # queries_per_lane code of the matrix-core (MFMA) mat
 MATCH_VARIANTS = (1, 2, 4, MATCH_MATRIX)
 
 
-AUTOTUNE_CACHE = os.environ.get("XAFFINE_AUTOTUNE_CACHE",
-                                os.path.join(os.path.expanduser("~"), ".cache", "xaffine", "autotune.json"))
+TUNE_USE_CACHE = 1
 
 
 def autotune_queries_per_lane(groups, n_features: int, device="cuda", desc=None, count=None, reps: int = 5,
-                              use_cache: bool = True):
+                              use_cache: bool = True, out=None):
     """The matcher variant (the popcount kernel with 1, 2 or 4 queries per lane, or the
     matrix-core kernel, MATCH_MATRIX) that runs `groups` fastest on this GPU.
 
-    Every variant is timed with HIP events on the current stream, over the given descriptor
-    set (desc [views][n_features][32], count [views]) or, without one, over random descriptors
-    with every view full.  The matcher's work does not depend on the descriptor bits but does
-    depend on the counts: uneven counts favour more, smaller blocks.  The winner is cached per
-    device, n_features, group shape and total count in AUTOTUNE_CACHE (a JSON file).
-    Returns (queries_per_lane, {variant: ms})."""
-    import json
+    The library's tuner (xa_tune_matcher) times every variant with HIP events on the current
+    stream, over the given descriptor set (desc [views][n_features][32], count [views]) or,
+    without one, over random descriptors with every view full.  The matcher's work does not
+    depend on the descriptor bits but does depend on the counts: uneven counts favour more,
+    smaller blocks.  out = (matches, pair_count, best) may bring the result buffers.  The
+    library keeps the winner per device, keyed by the group table, n_features and the counts;
+    use_cache serves a known key from there, use_cache=False times again.  Returns
+    (queries_per_lane, {variant: ms})."""
     import torch
     groups = np.ascontiguousarray(groups, GROUP_DTYPE)
     dev = torch.device(device)
@@ -760,41 +767,19 @@ def autotune_queries_per_lane(groups, n_features: int, device="cuda", desc=None,
         gen = torch.Generator(device=dev).manual_seed(1)
         desc = torch.randint(0, 256, (n_views, n_features, 32), dtype=torch.uint8, device=dev, generator=gen)
         count = torch.full((n_views,), n_features, dtype=torch.int32, device=dev)
-    total_count = int(count.sum())
-    key = (f"{torch.cuda.get_device_name(dev)}|N={n_features}|groups={len(groups)}|pairs={total}"
-           f"|count={total_count}")
-    cache = {}
-    if use_cache and os.path.exists(AUTOTUNE_CACHE):
-        try:
-            with open(AUTOTUNE_CACHE) as f:
-                cache = json.load(f)
-        except (OSError, ValueError):
-            cache = {}
-        if key in cache:
-            return int(cache[key]["queries_per_lane"]), {int(k): v for k, v in cache[key]["ms"].items()}
-    stream = torch.cuda.current_stream(dev)
-    times = {}
-    for q in MATCH_VARIANTS:
-        mp = plan_matches(groups, n_features, q)
-        match_groups(mp, desc, count)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
-            match_groups(mp, desc, count)
-        e1.record(stream)
-        torch.cuda.synchronize(dev)
-        times[q] = e0.elapsed_time(e1) / reps
-    best = min(times, key=times.get)
-    if use_cache:
-        cache[key] = {"queries_per_lane": best, "ms": times}
-        try:
-            os.makedirs(os.path.dirname(AUTOTUNE_CACHE), exist_ok=True)
-            with open(AUTOTUNE_CACHE, "w") as f:
-                json.dump(cache, f, indent=1)
-        except OSError:
-            pass
-    return best, times
-
+    if out is None:
+        out = (torch.empty((total, n_features, MATCH_DTYPE.itemsize), dtype=torch.uint8, device=dev),
+               torch.empty(total, dtype=torch.int32, device=dev),
+               torch.empty((len(groups), 4), dtype=torch.int32, device=dev))
+    matches, pair_count, best_buf = out
+    ws = _empty(lib().xa_tune_matcher_workspace_size(groups.ctypes.data, len(groups), n_features), dev)
+    best_q = ctypes.c_int32(0)
+    ms = np.zeros(4, np.float32)
+    _check(lib().xa_tune_matcher(groups.ctypes.data, len(groups), n_features, _ptr(desc), _ptr(count),
+                                 int(desc.shape[0]), reps, TUNE_USE_CACHE if use_cache else 0, _ptr(matches),
+                                 _ptr(pair_count), _ptr(best_buf), _ptr(ws), ws.numel(), _stream(),
+                                 ctypes.byref(best_q), ms.ctypes.data))
+    return int(best_q.value), {q: float(t) for q, t in zip(MATCH_VARIANTS, ms)}
 
 def match_groups(mplan: MatchPlan, desc, count, ratio_num: int = 4, ratio_den: int = 5):
     """Group matching over one descriptor set.  Returns (matches u8[P, N, 8], pair_count i32[P], best i32[G, 4])."""
@@ -962,7 +947,8 @@ class BatchRunner:
         descriptor sets this batch produced, and re-plan the matcher with the fastest."""
         self._tune = False
         self.run(pattern, ratio_num, ratio_den)
-        q, ms = autotune_queries_per_lane(self.mplan.groups, self.mplan.n_features, self.device, self.desc, self.count)
+        q, ms = autotune_queries_per_lane(self.mplan.groups, self.mplan.n_features, self.device, self.desc, self.count,
+                                          out=(self.matches, self.pair_count, self.best))
         self.autotune = {"queries_per_lane": q, "ms": ms}
         if q != self.mplan_q:
             self.close()
@@ -1077,19 +1063,20 @@ def warp_f32(img, params):
     return _WARP_FN.apply(img.contiguous(), params.contiguous())
 
 
-def _gauss_blur(x, sigma: float):
-    """Separable Gaussian (replicated border) of fp32 crops [n, h, w]; sigma 0 = none."""
+def blur_f32(x, sigma: float):
+    """Separable Gaussian (replicated border, |k| <= ceil(3 sigma)) of fp32 crops [n, h, w] by
+    xa_blur_f32; sigma 0 returns x."""
     import torch
-    import torch.nn.functional as F
     if sigma <= 0:
         return x
-    r = max(1, int(math.ceil(3 * sigma)))
-    k = torch.exp(-(torch.arange(-r, r + 1, dtype=torch.float64, device=x.device) ** 2) / (2 * sigma * sigma))
-    k = (k / k.sum()).to(x.dtype)
-    y = F.pad(x[:, None], (r, r, 0, 0), mode="replicate")
-    y = F.conv2d(y, k.view(1, 1, 1, -1))
-    y = F.pad(y, (0, 0, r, r), mode="replicate")
-    return F.conv2d(y, k.view(1, 1, -1, 1))[:, 0]
+    x = x.contiguous()
+    if x.dtype != torch.float32 or x.dim() != 3:
+        raise XAError(-1, "need float32 crops [n, h, w]")
+    n, h, w = x.shape
+    out = torch.empty_like(x)
+    ws = _empty(lib().xa_blur_f32_workspace_size(n, h, w), x.device)
+    _check(lib().xa_blur_f32(_ptr(x), n, h, w, float(sigma), _ptr(out), _ptr(ws), ws.numel(), _stream()))
+    return out
 
 
 def refine_tilt(img, target, params, grid, target_mask=None, steps: int = 20, lr: float = 0.03, sigmas=None):
@@ -1136,7 +1123,7 @@ def refine_tilt(img, target, params, grid, target_mask=None, steps: int = 20, lr
     smoothed = {}
     for sg in sigmas:
         if sg not in smoothed:
-            smoothed[sg] = (_gauss_blur(img, sg).contiguous(), _gauss_blur(target * tmask, sg))
+            smoothed[sg] = (blur_f32(img, sg), blur_f32((target * tmask).contiguous(), sg))
         im, tg = smoothed[sg]
         opt.zero_grad()
         p = torch.cat([logt.exp()[:, None], phi[:, None], best_p[:, 2:]], dim=1)

@@ -251,11 +251,10 @@ def test_batch_graph_replays(dev, pairs):
         br.close()
 
 
-def test_autotuner_picks_a_variant_and_caches_it(dev, pairs, tmp_path, monkeypatch):
-    """The matcher autotuner times every variant, caches the winner, and a batch built with it
-    gives the same bytes as batches with each fixed variant."""
+def test_autotuner_picks_a_variant_and_caches_it(dev, pairs):
+    """The library's matcher autotuner times every variant, keeps the winner per device and
+    key, and a batch built with it gives the same bytes as batches with each fixed variant."""
     say("case: matcher autotuner (popcount kernel with 1 / 2 / 4 queries per lane, matrix-core kernel) and its cache")
-    monkeypatch.setattr(X, "AUTOTUNE_CACHE", str(tmp_path / "autotune.json"))
     grid = _grid(1)
     pat = torch.from_numpy(synth.brief_pattern()).to(dev)
     imgs = [(p.A, np.ascontiguousarray(p.B)) for p in pairs[:2]]
@@ -265,9 +264,13 @@ def test_autotuner_picks_a_variant_and_caches_it(dev, pairs, tmp_path, monkeypat
     q, ms = auto.autotune["queries_per_lane"], auto.autotune["ms"]
     V = set(X.MATCH_VARIANTS)
     assert q in V and set(ms) == V and all(v > 0 for v in ms.values()) and ms[q] == min(ms.values())
-    assert auto.mplan_q == q and (tmp_path / "autotune.json").exists()
+    assert auto.mplan_q == q
     q2, ms2 = X.autotune_queries_per_lane(auto.mplan.groups, 700, dev, auto.desc, auto.count)
-    assert q2 == q and ms2 == ms                          # served from the cache
+    assert q2 == q and ms2 == ms                          # served from the library's cache
+    q3, ms3 = X.autotune_queries_per_lane(auto.mplan.groups, 700, dev, auto.desc, auto.count, use_cache=False)
+    assert q3 in V and set(ms3) == V and ms3 != ms        # timed again
+    q4, ms4 = X.autotune_queries_per_lane(auto.mplan.groups, 700, dev, auto.desc, auto.count)
+    assert (q4, ms4) == (q3, ms3)                         # the new timing replaced the entry
     qr, msr = X.autotune_queries_per_lane(auto.mplan.groups, 700, dev)   # random full descriptors
     assert qr in V and set(msr) == V
     for fixed in X.MATCH_VARIANTS:

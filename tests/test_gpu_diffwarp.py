@@ -284,3 +284,34 @@ def test_image_gradient_mixed_magnitudes_per_entry(dev):
         f"{float((err / bound).max()):.3f}; far entries worst relative error {far_rel:.2e}")
     assert (~near).sum() > 1000 and near.sum() > 1000
     assert np.all(err <= bound)
+
+
+def _blur_ref(x, sigma):
+    """Separable Gaussian in fp64, replicated border: the plain definition of xa_blur_f32."""
+    r = max(1, int(np.ceil(3 * sigma)))
+    k = np.arange(-r, r + 1, dtype=np.float64)
+    w = np.exp(-k * k / (2 * sigma * sigma))
+    w /= w.sum()
+    n, h, wd = x.shape
+    xp = np.pad(x.astype(np.float64), ((0, 0), (0, 0), (r, r)), mode="edge")
+    rows = sum(w[i] * xp[:, :, i:i + wd] for i in range(2 * r + 1))
+    rp = np.pad(rows, ((0, 0), (r, r), (0, 0)), mode="edge")
+    return sum(w[i] * rp[:, i:i + h, :] for i in range(2 * r + 1))
+
+
+def test_crop_blur_against_the_definition(dev):
+    """The refinement's coarse-to-fine smoothing (xa_blur_f32) on ragged crops, from a narrow
+    kernel to one four times wider than the crop is tall: within fp32 accumulation of the fp64
+    definition; sigma 0 is the identity, sigma beyond 16 is refused."""
+    say("case: crop blur, 3 crops of 37x300, sigma 0.5 / 1 / 2.5 / 16")
+    rng = np.random.default_rng(77)
+    x = (rng.random((3, 37, 300)) * 255).astype(np.float32)
+    t = torch.from_numpy(x).to(dev)
+    for sigma in (0.5, 1.0, 2.5, 16.0):
+        got = X.blur_f32(t, sigma).cpu().numpy()
+        ref = _blur_ref(x, sigma)
+        err = np.abs(got - ref).max()
+        assert err <= 255 * 2e-6, (sigma, err)
+    assert X.blur_f32(t, 0.0) is t
+    with pytest.raises(X.XAError):
+        X.blur_f32(t, 16.5)
