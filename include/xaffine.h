@@ -263,9 +263,11 @@ xa_status xa_set_warp_tiles(const int32_t* widths);
 xa_status xa_get_warp_tiles(int32_t* widths);
 
 /* The autotuner of the warp tile widths: for each compression class k, the sampling grid's views
- * of tilt sqrt(2)^k (scale 1) of a src_w x src_h test image are blurred once, then warped with
- * each candidate width (4, 8, 16, 32, 64), 3 timed launches each after one untimed; widths[k]
- * gets the fastest (ms[k][c], if not NULL, the mean times in milliseconds).  The result is not
+ * of tilt sqrt(2)^k (scale 1) of a src_w x src_h test image, repeated until they hold about 8 M
+ * view pixels (a launch that fills the chip), are blurred once, then warped with each candidate
+ * width (4, 8, 16, 32, 64), 3 timed launches each after one untimed (ms[k][c], if not NULL, the
+ * mean times in milliseconds).  widths[k] gets the fastest candidate if it beats the built-in
+ * rule's width by more than 3 %, else the rule's width.  The result is not
  * applied: pass it to xa_set_warp_tiles (and keep it per device).  Synchronises `stream` (it
  * uploads a plan per candidate and reads events); not to be run concurrently with other work
  * timed on the same device.  Workspace: xa_tune_warp_tiles_workspace_size(src_w, src_h) bytes,

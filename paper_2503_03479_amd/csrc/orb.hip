@@ -211,44 +211,32 @@ constexpr int kFChunks = kFLW / 16;
 constexpr int kSW = kFastTX + 2, kSH = kFastTY + 2; // FAST scores: the tile plus a one-pixel ring
 constexpr int kMaxBlockCand = kFastTX * kFastTY / 4;
 
-// Harris response at LDS pixel p (stride s): 3x3 Sobel, 7x7 structure tensor,
-// R = 25 (a b - c^2) - (a + b)^2 in int64.
-__device__ __forceinline__ long long harris_lds(const uint8_t* p, int s) {
-    int a = 0, b = 0, c = 0;
-    for (int dy = -3; dy <= 3; ++dy) {
-        const uint8_t* r0 = p + (dy - 1) * s;
-        const uint8_t* r1 = r0 + s;
-        const uint8_t* r2 = r1 + s;
-        int v0[9], v1[9], v2[9];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            v0[k] = r0[k - 4];
-            v1[k] = r1[k - 4];
-            v2[k] = r2[k - 4];
-        }
-#pragma unroll
-        for (int dx = 1; dx <= 7; ++dx) {
-            const int ix = (v0[dx + 1] + 2 * v1[dx + 1] + v2[dx + 1]) - (v0[dx - 1] + 2 * v1[dx - 1] + v2[dx - 1]);
-            const int iy = (v2[dx - 1] + 2 * v2[dx] + v2[dx + 1]) - (v0[dx - 1] + 2 * v0[dx] + v0[dx + 1]);
-            a += ix * ix;
-            b += iy * iy;
-            c += ix * iy;
-        }
-    }
-    const long long tr = (long long)(a + b);
-    return 25LL * ((long long)a * b - (long long)c * c) - tr * tr;
+// Exact pre-test of FAST-9 on the four compass pixels: any arc of 9 contiguous circle pixels
+// holds two of them, so a pixel can be a corner only if two are brighter than c + T or two
+// darker than c - T.  Two of the four exceed c + T iff the second largest does, and two fall
+// below c - T iff the second smallest does; with the pairs (n, s) and (e, w) ordered, the second
+// largest is max(min of the two maxima, both minima) and the second smallest min(max of the two
+// minima, both maxima).
+__device__ __forceinline__ bool fast_pretest(int c, int n, int e, int s, int w, int T) {
+    const int hi1 = max(n, s), lo1 = min(n, s), hi2 = max(e, w), lo2 = min(e, w);
+    const int second_hi = max(max(lo1, lo2), min(hi1, hi2));
+    const int second_lo = min(min(hi1, hi2), max(lo1, lo2));
+    return max(second_hi - c, c - second_lo) > T;
 }
 
 // One block per 64 x 32 tile of one (view, level) that can hold detections:
 //  1. the tile plus a 4-row / 16-column halo is staged in LDS in 16-byte chunks (border
 //     replicated, byte by byte, for chunks that leave the image);
-//  2. the 7-tap smoothing [18 34 49 54 49 34 18] / 256 of the tile is written out (exact
-//     horizontal sums by v_dot4 over byte windows, rounded vertical pass);
-//  3. FAST-9 scores on the tile plus a one-pixel ring: an exact pre-test on the four compass
-//     pixels (any 9-pixel arc contains two of them) queues the pixels that can be corners;
-//  4. 3x3 non-maximum suppression (ties go to the earlier raster position), the content
-//     filter on the corners of the +-B box, the Harris response of each survivor from the
-//     LDS tile, and one atomic reservation per block in the candidate arena.
+//  2. one pass over the tile, thread = column, 8 rows each: the 7-tap smoothing
+//     [18 34 49 54 49 34 18] / 256 (exact horizontal sums by v_dot4 over byte windows, rounded
+//     vertical pass) and, from the same row words, the FAST pre-test of the tile's pixels on
+//     their four compass pixels (any 9-pixel arc contains two of them); the one-pixel ring the
+//     suppression also needs is pre-tested separately.  Pixels that pass are queued;
+//  3. full FAST-9 scores of the queued pixels;
+//  4. 3x3 non-maximum suppression (ties go to the earlier raster position) and the content
+//     filter on the corners of the +-B box, then one atomic reservation per block in the
+//     candidate arena and the Harris response of each survivor, 16 lanes per candidate (each
+//     lane takes 3 or 4 of the 49 window positions; the integer sums are reduced across them).
 // Tiles of a tilted view's empty corners skip work that cannot matter (flags from the
 // planner): smoothing when no pixel of the tile can be valid, detection when no pixel can
 // pass the content filter.
@@ -257,9 +245,12 @@ __global__ void __launch_bounds__(256) k_fast(const uint8_t* __restrict__ fast_f
                                               int nvl, int T, const uint8_t* __restrict__ arena,
                                               const uint8_t* __restrict__ mask, Cand* __restrict__ cand,
                                               int32_t* __restrict__ cand_count, uint8_t* __restrict__ smooth) {
+    constexpr int kScoreWords = (kSH * kSW) / 4;    // 4 scores per 8-byte word
+    static_assert((kSH * kSW) % 4 == 0, "score grid in whole 8-byte words");
+    constexpr int kRing = 2 * kSW + 2 * kFastTY;    // ring pixels: top and bottom rows, left and right columns
     __shared__ __align__(16) uint8_t img[kFLH * kFLW];
     __shared__ __align__(16) uint8_t sm[kFastTY * kFastTX];
-    __shared__ int16_t score[kSH * kSW];
+    __shared__ __align__(8) int16_t score[kSH * kSW];
     __shared__ int16_t queue[kSH * kSW];
     __shared__ int16_t cxy[2 * kMaxBlockCand];
     __shared__ int qn, cn, cbase;
@@ -277,6 +268,8 @@ __global__ void __launch_bounds__(256) k_fast(const uint8_t* __restrict__ fast_f
     const uint8_t flags = fast_flags[b];
     const bool need_smooth = (flags & 1) != 0, may_detect = (flags & 2) != 0;
     if (!need_smooth && !may_detect) return;
+    const bool detect = may_detect && !(x0 + kFastTX <= kBorder - 1 || x0 - 1 >= W - kBorder ||
+                                        y0 + kFastTY <= kBorder - 1 || y0 - 1 >= H - kBorder);
     for (int e = t; e < kFLH * kFChunks; e += 256) {
         const int r = e / kFChunks, k = e - (e / kFChunks) * kFChunks;
         const int gy = clampi(y0 - kFH + r, 0, H - 1);
@@ -298,48 +291,70 @@ __global__ void __launch_bounds__(256) k_fast(const uint8_t* __restrict__ fast_f
         }
         *reinterpret_cast<uint4*>(img + r * kFLW + 16 * k) = v;
     }
+    if (detect)   // every score starts at kNegV (-1: all bits set)
+        for (int e = t; e < kScoreWords; e += 256) reinterpret_cast<unsigned long long*>(score)[e] = ~0ull;
     if (t == 0) { qn = 0; cn = 0; }
     __syncthreads();
 
-    // ---- smoothing: thread = column c, rows 8g .. 8g + 7 of the tile
-    if (need_smooth) {
-        const int c = t & 63, g = t >> 6;
+    // ---- smoothing and the tile's pre-test: thread = column c, tile rows 8g .. 8g + 7
+    {
+        const int c = t & 63, g = __builtin_amdgcn_readfirstlane(t >> 6);   // g: the wave's row group
         const int lx = c + 16 - 3;                 // first byte of the 7-tap window
         const int a = lx & ~3, o = lx & 3;
         const uint32_t w03 = 18u | (34u << 8) | (49u << 16) | (54u << 24);
         const uint32_t w46 = 49u | (34u << 8) | (18u << 16);
-        int h[14];
+        int h[14], ctr[14], wst[8], est[8];
 #pragma unroll
         for (int j = 0; j < 14; ++j) {
             const uint32_t* row = reinterpret_cast<const uint32_t*>(img + (kFH + 8 * g - 3 + j) * kFLW + a);
             const uint32_t d0 = row[0], d1 = row[1], d2 = row[2];
-            const uint32_t lo = __builtin_amdgcn_alignbyte(d1, d0, o);
-            const uint32_t hi = __builtin_amdgcn_alignbyte(d2, d1, o) & 0x00FFFFFFu;
+            const uint32_t lo = __builtin_amdgcn_alignbyte(d1, d0, o);                // bytes lx .. lx + 3
+            const uint32_t hi = __builtin_amdgcn_alignbyte(d2, d1, o) & 0x00FFFFFFu;  // bytes lx + 4 .. lx + 6
             h[j] = int(__builtin_amdgcn_udot4(lo, w03, __builtin_amdgcn_udot4(hi, w46, 0u, false), false));
+            ctr[j] = int(lo >> 24);                                                    // the column's own byte
+            if (j >= 3 && j < 11) {
+                wst[j - 3] = int(lo & 0xFFu);                                          // 3 columns left
+                est[j - 3] = int(hi >> 16);                                            // 3 columns right
+            }
         }
+        if (need_smooth) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int s = 18 * h[j] + 34 * h[j + 1] + 49 * h[j + 2] + 54 * h[j + 3] + 49 * h[j + 4] + 34 * h[j + 5] +
-                          18 * h[j + 6];
-            sm[(8 * g + j) * kFastTX + c] = uint8_t((s + (1 << 15)) >> 16);
+            for (int j = 0; j < 8; ++j) {
+                const int s = 18 * h[j] + 34 * h[j + 1] + 49 * h[j + 2] + 54 * h[j + 3] + 49 * h[j + 4] +
+                              34 * h[j + 5] + 18 * h[j + 6];
+                sm[(8 * g + j) * kFastTX + c] = uint8_t((s + (1 << 15)) >> 16);
+            }
+        }
+        if (detect) {
+            const int gx = x0 + c;
+            const bool col_ok = gx >= kBorder - 1 && gx <= W - kBorder;
+            uint32_t pass = 0;                     // bit j: tile row 8 g + j passes
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int gy = y0 + 8 * g + j;     // the same for the whole wave
+                const bool ok = col_ok && gy >= kBorder - 1 && gy <= H - kBorder &&
+                                fast_pretest(ctr[j + 3], ctr[j], est[j], ctr[j + 6], wst[j], T);
+                pass |= uint32_t(ok) << j;
+            }
+            while (pass) {
+                const int j = __builtin_ctz(pass);
+                pass &= pass - 1;
+                queue[atomicAdd(&qn, 1)] = int16_t((8 * g + j + 1) * kSW + c + 1);
+            }
         }
     }
-    // ---- FAST pre-test over the tile and its ring
-    const bool detect = may_detect && !(x0 + kFastTX <= kBorder - 1 || x0 - 1 >= W - kBorder ||
-                                        y0 + kFastTY <= kBorder - 1 || y0 - 1 >= H - kBorder);
+    // ---- the ring's pre-test (rows -1 and 32, columns -1 and 64 of the tile)
     if (detect) {
-        for (int e = t; e < kSH * kSW; e += 256) {
-            const int sy = e / kSW, sx = e - (e / kSW) * kSW;
+        for (int e = t; e < kRing; e += 256) {
+            int sx, sy;
+            if (e < 2 * kSW) { sy = e < kSW ? 0 : kSH - 1; sx = e < kSW ? e : e - kSW; }
+            else { const int r = e - 2 * kSW; sx = r < kFastTY ? 0 : kSW - 1; sy = 1 + (r < kFastTY ? r : r - kFastTY); }
             const int gx = x0 - 1 + sx, gy = y0 - 1 + sy;
             if (gx >= kBorder - 1 && gx <= W - kBorder && gy >= kBorder - 1 && gy <= H - kBorder) {
                 const uint8_t* p = img + (sy - 1 + kFH) * kFLW + sx - 1 + 16;
-                const int cc = p[0];
-                const int n = p[-3 * kFLW], e3 = p[3], s3 = p[3 * kFLW], w3 = p[-3];
-                const int nb = (n > cc + T) + (e3 > cc + T) + (s3 > cc + T) + (w3 > cc + T);
-                const int nd = (n < cc - T) + (e3 < cc - T) + (s3 < cc - T) + (w3 < cc - T);
-                if (nb >= 2 || nd >= 2) queue[atomicAdd(&qn, 1)] = int16_t(e);
+                if (fast_pretest(p[0], p[-3 * kFLW], p[3], p[3 * kFLW], p[-3], T))
+                    queue[atomicAdd(&qn, 1)] = int16_t(sy * kSW + sx);
             }
-            score[e] = kNegV;
         }
     }
     __syncthreads();
@@ -361,7 +376,7 @@ __global__ void __launch_bounds__(256) k_fast(const uint8_t* __restrict__ fast_f
     }
     __syncthreads();
     // ---- NMS + content filter -> block candidate list.  Only queued pixels can score above T
-    // (every other pixel keeps kNegV), so the queue, compacted, is walked instead of the tile.
+    // (every other pixel keeps kNegV), so the queue is walked instead of the tile.
     const uint8_t* Mk = mask + d.offset;
     for (int q = t; q < nq; q += 256) {
         const int e = queue[q];
@@ -394,14 +409,37 @@ __global__ void __launch_bounds__(256) k_fast(const uint8_t* __restrict__ fast_f
     if (t == 0) cbase = atomicAdd(&cand_count[vl], nc);
     __syncthreads();
     const int base = cbase;
-    for (int s = t; s < nc; s += 256) {
+    // Harris response: 3x3 Sobel gradients over the 7x7 window, structure tensor sums a, b, c,
+    // R = 25 (a b - c^2) - (a + b)^2 in int64.  16 lanes per candidate; the group's lanes are
+    // active together, so the xor shuffles below stay inside it.
+    const int grp = t >> 4, sub = t & 15;
+    for (int s = grp; s < nc; s += 256 / 16) {
         const int tx = cxy[2 * s], ty = cxy[2 * s + 1];
-        const long long R = harris_lds(img + (ty + kFH) * kFLW + tx + 16, kFLW);
-        if (base + s < d.cand_cap) {
+        int sa = 0, sb = 0, sc = 0;
+        for (int pw = sub; pw < 49; pw += 16) {
+            const int dy = pw / 7 - 3, dx = pw - (pw / 7) * 7 - 3;
+            const uint8_t* p = img + (ty + kFH + dy) * kFLW + tx + 16 + dx;
+            const int v00 = p[-kFLW - 1], v01 = p[-kFLW], v02 = p[-kFLW + 1];
+            const int v10 = p[-1], v12 = p[1];
+            const int v20 = p[kFLW - 1], v21 = p[kFLW], v22 = p[kFLW + 1];
+            const int ix = (v02 + 2 * v12 + v22) - (v00 + 2 * v10 + v20);
+            const int iy = (v20 + 2 * v21 + v22) - (v00 + 2 * v01 + v02);
+            sa += ix * ix;
+            sb += iy * iy;
+            sc += ix * iy;
+        }
+#pragma unroll
+        for (int off = 8; off >= 1; off >>= 1) {
+            sa += __shfl_xor(sa, off);
+            sb += __shfl_xor(sb, off);
+            sc += __shfl_xor(sc, off);
+        }
+        if (sub == 0 && base + s < d.cand_cap) {
+            const long long tr = (long long)(sa + sb);
             Cand cd;
             cd.raster = uint32_t(y0 + ty) * uint32_t(W) + uint32_t(x0 + tx);
             cd.pad = 0;
-            cd.harris = R;
+            cd.harris = 25LL * ((long long)sa * sb - (long long)sc * sc) - tr * tr;
             cand[d.cand_offset + base + s] = cd;
         }
     }

@@ -581,8 +581,12 @@ __global__ void __launch_bounds__(256) k_tune_fill(uint8_t* __restrict__ p, int 
 }
 
 // The views of compression class k: tilt sqrt(2)^k, longitudes 0, 72/t, 144/t, ... degrees below
-// 180 (the sampling grid's views of that tilt), scale 1.
-std::vector<xa_affine_params> class_views(int k) {
+// 180 (the sampling grid's views of that tilt), scale 1, repeated until they hold about
+// kTuneViewPixels view pixels, so that each timed launch fills the chip as a real plan's does
+// (one view of a small class would time launch latency, the same for every width).
+constexpr double kTuneViewPixels = 8.0e6;
+
+std::vector<xa_affine_params> class_views(int k, int w, int h) {
     std::vector<xa_affine_params> v;
     const double t = std::pow(2.0, 0.5 * k);
     const double step = 72.0 / t;
@@ -590,6 +594,11 @@ std::vector<xa_affine_params> class_views(int k) {
         xa_affine_params p{t, j * step * 3.141592653589793 / 180.0, 0.0, 1.0, 0.0, 0.0};
         v.push_back(p);
     }
+    const double px = double(v.size()) * double(w) * double(h) / t;
+    const int reps = std::max(1, int(std::ceil(kTuneViewPixels / px)));
+    const size_t n = v.size();
+    for (int r = 1; r < reps; ++r)
+        for (size_t i = 0; i < n; ++i) v.push_back(v[i]);
     return v;
 }
 
@@ -598,7 +607,7 @@ struct TunePlan {
 };
 
 xa_status tune_plan(int w, int h, int pitch, int k, int width, TunePlan* out) {
-    const std::vector<xa_affine_params> views = class_views(k);
+    const std::vector<xa_affine_params> views = class_views(k, w, h);
     int32_t forced[XA_WARP_CLASSES];
     for (int c = 0; c < XA_WARP_CLASSES; ++c) forced[c] = width;
     set_tile_override(forced);
@@ -673,9 +682,9 @@ extern "C" xa_status xa_tune_warp_tiles(int32_t src_w, int32_t src_h, void* d_ws
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e != hipSuccess) return hip_fail(e, "event create");
     constexpr int kReps = 3;
+    constexpr float kTuneMargin = 0.03f;
     for (int k = 0; k < XA_WARP_CLASSES && s == XA_OK; ++k) {
-        float best_ms = 0.0f;
-        int best_w = 0;
+        float times[XA_WARP_CANDIDATES] = {};
         for (int c = 0; c < XA_WARP_CANDIDATES && s == XA_OK; ++c) {
             TunePlan P;
             s = tune_plan(src_w, src_h, L.pitch, k, kTuneCandidates[c], &P);
@@ -702,12 +711,18 @@ extern "C" xa_status xa_tune_warp_tiles(int32_t src_w, int32_t src_h, void* d_ws
             if (e != hipSuccess) { s = hip_fail(e, "tuning timing"); break; }
             t /= kReps;
             if (ms) ms[k * XA_WARP_CANDIDATES + c] = t;
-            if (best_w == 0 || t < best_ms) {
-                best_ms = t;
-                best_w = kTuneCandidates[c];
-            }
+            times[c] = t;
         }
-        widths[k] = best_w;
+        if (s != XA_OK) break;
+        // the rule's width stays unless a candidate is faster by more than the timing noise
+        const int rule_w = warp_tile_w(std::pow(2.0, 0.5 * k), 1.0);
+        int best_c = 0;
+        for (int c = 1; c < XA_WARP_CANDIDATES; ++c)
+            if (times[c] < times[best_c]) best_c = c;
+        float rule_ms = times[best_c];
+        for (int c = 0; c < XA_WARP_CANDIDATES; ++c)
+            if (kTuneCandidates[c] == rule_w) rule_ms = times[c];
+        widths[k] = times[best_c] < (1.0f - kTuneMargin) * rule_ms ? kTuneCandidates[best_c] : rule_w;
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
