@@ -125,38 +125,40 @@ __global__ void __launch_bounds__(256) k_pyr(const xa_level_desc* __restrict__ l
         cw0[k] = 2048 - cw1[k];
         cx1[k] = min(cx0[k] + 1, p.width - 1);
     }
-    for (int rr = 0; rr < kPyrTY / 4; ++rr) {
-        const int yr = ty + 4 * rr;
-        const int y = Y0 + yr;
-        if (y >= d.height) break;
-        const int rv = srow[yr];
-        const int y0 = rv >> 11, wy1 = rv & 2047, wy0 = 2048 - wy1, y1 = min(y0 + 1, p.height - 1);
-        const size_t o = size_t(d.offset) + size_t(y) * d.pitch + X0 + tx;
+    // The staged and the direct path are separate loops, so that the staged one reads LDS with
+    // LDS instructions (one loop over a pointer that may be either compiles to flat loads).
+    auto rows = [&](auto fetch) {
+        for (int rr = 0; rr < kPyrTY / 4; ++rr) {
+            const int yr = ty + 4 * rr;
+            const int y = Y0 + yr;
+            if (y >= d.height) break;
+            const int rv = srow[yr];
+            const int y0 = rv >> 11, wy1 = rv & 2047, wy0 = 2048 - wy1, y1 = min(y0 + 1, p.height - 1);
+            const size_t o = size_t(d.offset) + size_t(y) * d.pitch + X0 + tx;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (!cv_ok[k]) break;
-            const int x0 = cx0[k], wx1 = cw1[k], wx0 = cw0[k], x1 = cx1[k];
-            int p00, p01, p10, p11, m;
-            if (staged) {
-                const uint8_t* r0 = simg + (y0 - r_lo) * kPyrLW - cb;
-                const uint8_t* r1 = simg + (y1 - r_lo) * kPyrLW - cb;
-                const uint8_t* q0 = smsk + (y0 - r_lo) * kPyrLW - cb;
-                const uint8_t* q1 = smsk + (y1 - r_lo) * kPyrLW - cb;
-                p00 = r0[x0]; p01 = r0[x1]; p10 = r1[x0]; p11 = r1[x1];
-                m = q0[x0] & q0[x1] & q1[x0] & q1[x1];
-            } else {
-                const uint8_t* r0 = P + size_t(y0) * p.pitch;
-                const uint8_t* r1 = P + size_t(y1) * p.pitch;
-                const uint8_t* q0 = M + size_t(y0) * p.pitch;
-                const uint8_t* q1 = M + size_t(y1) * p.pitch;
-                p00 = r0[x0]; p01 = r0[x1]; p10 = r1[x0]; p11 = r1[x1];
-                m = q0[x0] & q0[x1] & q1[x0] & q1[x1];
+            for (int k = 0; k < 4; ++k) {
+                if (!cv_ok[k]) break;
+                int p00, p01, p10, p11, m;
+                fetch(y0, y1, cx0[k], cx1[k], p00, p01, p10, p11, m);
+                const int top = cw0[k] * p00 + cw1[k] * p01;
+                const int bot = cw0[k] * p10 + cw1[k] * p11;
+                arena[o + 64 * k] = uint8_t((wy0 * top + wy1 * bot + (1 << 21)) >> 22);
+                mask[o + 64 * k] = uint8_t(m & 1);
             }
-            const int top = wx0 * p00 + wx1 * p01;
-            const int bot = wx0 * p10 + wx1 * p11;
-            arena[o + 64 * k] = uint8_t((wy0 * top + wy1 * bot + (1 << 21)) >> 22);
-            mask[o + 64 * k] = uint8_t(m & 1);
         }
+    };
+    if (staged) {
+        rows([&](int y0, int y1, int x0, int x1, int& p00, int& p01, int& p10, int& p11, int& m) {
+            const int a0 = (y0 - r_lo) * kPyrLW - cb, a1 = (y1 - r_lo) * kPyrLW - cb;
+            p00 = simg[a0 + x0]; p01 = simg[a0 + x1]; p10 = simg[a1 + x0]; p11 = simg[a1 + x1];
+            m = smsk[a0 + x0] & smsk[a0 + x1] & smsk[a1 + x0] & smsk[a1 + x1];
+        });
+    } else {
+        rows([&](int y0, int y1, int x0, int x1, int& p00, int& p01, int& p10, int& p11, int& m) {
+            const size_t a0 = size_t(y0) * p.pitch, a1 = size_t(y1) * p.pitch;
+            p00 = P[a0 + x0]; p01 = P[a0 + x1]; p10 = P[a1 + x0]; p11 = P[a1 + x1];
+            m = M[a0 + x0] & M[a0 + x1] & M[a1 + x0] & M[a1 + x1];
+        });
     }
 }
 
