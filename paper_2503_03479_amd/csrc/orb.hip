@@ -165,45 +165,34 @@ __global__ void __launch_bounds__(256) k_pyr(const xa_level_desc* __restrict__ l
 // ------------------------------------------------------------------ FAST-9 + NMS + Harris + smoothing
 
 // Bresenham circle of radius 3, clockwise from 12 o'clock (x right, y down).
-__constant__ int8_t c_circle_x[16] = {0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3, -3, -3, -2, -1};
-__constant__ int8_t c_circle_y[16] = {-3, -3, -2, -1, 0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3};
+constexpr int kCircleX[16] = {0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3, -3, -3, -2, -1};
+constexpr int kCircleY[16] = {-3, -3, -2, -1, 0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3};
 
-// True iff the 16-bit circular mask has a run of at least 9 set bits.
-__device__ __forceinline__ bool has_run9(uint32_t m) {
-    const uint32_t x = m | (m << 16);
-    uint32_t r = x & (x >> 1);
-    r &= r >> 2;
-    r &= r >> 4;
-    r &= x >> 8;
-    return (r & 0xFFFFu) != 0;
-}
-
-// FAST-9 score of an LDS pixel: V = max over the 16 arcs of 9 contiguous circle pixels and
-// both polarities of the arc minimum of the signed difference; kNegV unless V > T.  Both
-// polarities cannot have a 9-arc at once, so only the polarity that has one is scored.
-__device__ __forceinline__ int fast_score_lds(const uint8_t* p, int stride, int T) {
+// FAST-9 score of an LDS pixel (row stride S): with d_k the circle pixel minus the centre,
+// V = max over the 16 arcs of 9 contiguous circle pixels of the larger of the arc's min d and
+// its min -d; kNegV unless V > T.  A pixel with a bright 9-arc (all d > T) has no dark one, since
+// two 9-arcs of 16 share a pixel, so V is the score of the polarity that makes it a corner.
+// Arc minima from three-wide minima: min over k..k+8 = min(m3[k], m3[k+3], m3[k+6]).
+template <int S>
+__device__ __forceinline__ int fast_score_lds(const uint8_t* p, int T) {
     const int c = p[0];
     int d[16];
-    uint32_t bm = 0, dm = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) d[k] = int(p[kCircleY[k] * S + kCircleX[k]]) - c;
+    int lo3[16], hi3[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-        d[k] = int(p[c_circle_y[k] * stride + c_circle_x[k]]) - c;
-        bm |= uint32_t(d[k] > T) << k;
-        dm |= uint32_t(d[k] < -T) << k;
+        lo3[k] = min(min(d[k], d[(k + 1) & 15]), d[(k + 2) & 15]);
+        hi3[k] = max(max(d[k], d[(k + 1) & 15]), d[(k + 2) & 15]);
     }
-    const bool bright = has_run9(bm);
-    if (!bright && !has_run9(dm)) return kNegV;
-    if (!bright) {
+    int bright = INT_MIN, dark = INT_MAX;     // max over arcs of the arc min; min over arcs of the arc max
 #pragma unroll
-        for (int k = 0; k < 16; ++k) d[k] = -d[k];
+    for (int k = 0; k < 16; ++k) {
+        bright = max(bright, min(min(lo3[k], lo3[(k + 3) & 15]), lo3[(k + 6) & 15]));
+        dark = min(dark, max(max(hi3[k], hi3[(k + 3) & 15]), hi3[(k + 6) & 15]));
     }
-    int m3[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) m3[k] = min(min(d[k], d[(k + 1) & 15]), d[(k + 2) & 15]);
-    int best = INT_MIN;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) best = max(best, min(min(m3[k], m3[(k + 3) & 15]), m3[(k + 6) & 15]));
-    return best;
+    const int v = max(bright, -dark);
+    return v > T ? v : kNegV;
 }
 
 constexpr int kFH = 4;                              // halo rows above and below the tile
@@ -374,7 +363,7 @@ __global__ void __launch_bounds__(256) k_fast(const uint8_t* __restrict__ fast_f
     for (int q = t; q < nq; q += 256) {
         const int e = queue[q];
         const int sy = e / kSW, sx = e - (e / kSW) * kSW;
-        score[e] = int16_t(fast_score_lds(img + (sy - 1 + kFH) * kFLW + sx - 1 + 16, kFLW, T));
+        score[e] = int16_t(fast_score_lds<kFLW>(img + (sy - 1 + kFH) * kFLW + sx - 1 + 16, T));
     }
     __syncthreads();
     // ---- NMS + content filter -> block candidate list.  Only queued pixels can score above T
