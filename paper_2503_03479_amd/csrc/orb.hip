@@ -684,9 +684,13 @@ __global__ void __launch_bounds__(kBriefTests) k_steer(const int8_t* __restrict_
 }
 
 
-// One wave per keypoint: intensity-centroid moments over the radius-15 disk, integer
-// argmax over the 30 bins, then 256 steered binary tests on the smoothed level,
-// packed four 64-bit ballots at a time.  Keypoints are written in canonical order.
+// Two keypoints per wave: intensity-centroid moments over the radius-15 disk, integer argmax
+// over the 30 bins, then 256 steered binary tests on the smoothed level, packed four 64-bit
+// ballots at a time.  Keypoints are written in canonical order.  The kernel is bound by its
+// chain of dependent loads (counts, level, keypoint, disk, steered table, smoothed samples), so
+// each step is taken for both keypoints before the next: their loads overlap.
+constexpr int kKpPerWave = 2;
+
 __global__ void __launch_bounds__(256) k_orient_brief(const xa_view_desc* __restrict__ views,
                                                       const xa_level_desc* __restrict__ levels, int n_levels,
                                                       int n_features, const uint8_t* __restrict__ arena,
@@ -694,9 +698,10 @@ __global__ void __launch_bounds__(256) k_orient_brief(const xa_view_desc* __rest
                                                       const int32_t* __restrict__ stage_count,
                                                       const uint32_t* __restrict__ steer, xa_keypoint* __restrict__ kp,
                                                       uint8_t* __restrict__ desc, int32_t* __restrict__ count) {
+    constexpr int KW = kKpPerWave;
     const int v = blockIdx.y;
     const int lane = threadIdx.x & 63;
-    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int k0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * KW;
     // the level of keypoint k: lane l < n_levels holds level l's count; an inclusive wave scan
     // gives each level's end, and the first level whose end exceeds k holds it
     const int cnt = lane < n_levels ? stage_count[v * n_levels + lane] : 0;
@@ -707,83 +712,147 @@ __global__ void __launch_bounds__(256) k_orient_brief(const xa_view_desc* __rest
         if (lane >= off) incl += o;
     }
     const int pre = __shfl(incl, 63);
-    const unsigned long long past = __ballot(lane < n_levels && incl > k);
-    const int lev = past ? int(__ffsll((long long)past)) - 1 : -1;
-    const int start = lev >= 0 ? __shfl(incl - cnt, lev) : 0;
-    const int rank = k - start;
-    if (k == 0 && lane == 0) count[v] = pre;
-    if (lev < 0) return;
-    const xa_level_desc d = levels[v * n_levels + lev];
-    const int4 s = stage[size_t(v) * n_features + d.kp_base + rank];
-    const int x = s.x, y = s.y;
-    const long long R = (long long)(((unsigned long long)(uint32_t)s.w << 32) | (uint32_t)s.z);
-    const int pitch = d.pitch;
-    const uint8_t* P = arena + d.offset;
-    int m10 = 0, m01 = 0;
+    if (k0 == 0 && lane == 0) count[v] = pre;
+    int lev[KW], x[KW], y[KW];
+    long long R[KW];
+    xa_level_desc d[KW];
+#pragma unroll
+    for (int u = 0; u < KW; ++u) {
+        const int k = k0 + u;
+        const unsigned long long past = __ballot(lane < n_levels && incl > k);
+        lev[u] = (past && k < n_features) ? int(__ffsll((long long)past)) - 1 : -1;
+    }
+    if (lev[0] < 0) return;                   // keypoints of a wave are consecutive: none is kept
+#pragma unroll
+    for (int u = 0; u < KW; ++u) d[u] = levels[v * n_levels + (lev[u] >= 0 ? lev[u] : lev[0])];
+    int4 st4[KW];
+#pragma unroll
+    for (int u = 0; u < KW; ++u) {
+        const int l = lev[u] >= 0 ? lev[u] : lev[0];
+        const int start = __shfl(incl - cnt, l);
+        const int rank = lev[u] >= 0 ? k0 + u - start : 0;
+        st4[u] = stage[size_t(v) * n_features + d[u].kp_base + rank];
+    }
+#pragma unroll
+    for (int u = 0; u < KW; ++u) {
+        x[u] = st4[u].x;
+        y[u] = st4[u].y;
+        R[u] = (long long)(((unsigned long long)(uint32_t)st4[u].w << 32) | (uint32_t)st4[u].z);
+    }
+    // disk moments: all rows' loads of both keypoints are issued before any is used (keypoints
+    // lie kBorder > 16 pixels inside the level, so offsets up to 16 stay in bounds); the disk
+    // x^2 + y^2 <= 225 is applied afterwards
+    const int dx = (lane & 31) - 15;
+    int I[KW][16];
+#pragma unroll
+    for (int u = 0; u < KW; ++u) {
+        const uint8_t* row = arena + d[u].offset + size_t(y[u] - 15 + (lane >> 5)) * d[u].pitch + x[u] + dx;
+#pragma unroll
+        for (int it = 0; it < 16; ++it) I[u][it] = row[size_t(2 * it) * d[u].pitch];
+    }
+    int bin[KW];
+#pragma unroll
+    for (int u = 0; u < KW; ++u) {
+        int m10 = 0, m01 = 0;
+#pragma unroll
+        for (int it = 0; it < 16; ++it) {
+            const int dy = -15 + 2 * it + (lane >> 5);
+            const int val = (dy <= 15 && dx * dx + dy * dy <= 225) ? I[u][it] : 0;
+            m10 += dx * val;
+            m01 += dy * val;
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            m10 += __shfl_xor(m10, off);
+            m01 += __shfl_xor(m01, off);
+        }
+        long long sc = lane < 30 ? (long long)m10 * c_cos[lane] + (long long)m01 * c_sin[lane] : LLONG_MIN;
+        int bk = lane;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const long long os = __shfl_xor(sc, off);
+            const int ob = __shfl_xor(bk, off);
+            if (os > sc || (os == sc && ob < bk)) { sc = os; bk = ob; }
+        }
+        bin[u] = bk;
+    }
+    // The smoothed 43 x 43 patch the steered tests read (offsets within +-21) is staged in LDS by
+    // aligned 4-byte row loads: the tests' scattered byte reads would each touch a cache line of
+    // their own.  (Issued together with the disk's loads instead, the registers they hold cost
+    // more than the overlap gains.)
+    // Columns a .. a + 47 with a = (x - 21) & ~3 >= 0 (x >= kBorder); the row past x + 21 stays
+    // inside the level's padded row or runs into the next row (y + 21 < H - 1).
+    constexpr int kPR = 2 * 21 + 1, kPW = 12;          // patch rows, 4-byte words per row
+    __shared__ uint32_t patch[4][KW][kPR * kPW];
+    const int wv = threadIdx.x >> 6;
+    int a0[KW];
     {
-        // all 16 rows' loads are issued before any is used: every lane loads (keypoints lie
-        // kBorder > 16 pixels inside the level, so offsets up to 16 stay in bounds) and the
-        // disk x^2 + y^2 <= 225 is applied afterwards
-        const int dx = (lane & 31) - 15;
-        const uint8_t* row = P + size_t(y - 15 + (lane >> 5)) * pitch + x + dx;
-        int I[16];
+        uint32_t w[KW][(kPR * kPW + 63) / 64];
 #pragma unroll
-        for (int it = 0; it < 16; ++it) I[it] = row[size_t(2 * it) * pitch];
+        for (int u = 0; u < KW; ++u) {
+            a0[u] = (x[u] - 21) & ~3;
+            const uint8_t* base = smooth + d[u].offset + size_t(y[u] - 21) * d[u].pitch + a0[u];
 #pragma unroll
-        for (int it = 0; it < 16; ++it) {
-            const int dy = -15 + 2 * it + (lane >> 5);
-            if (!(dy <= 15 && dx * dx + dy * dy <= 225)) I[it] = 0;
+            for (int it = 0; it < (kPR * kPW + 63) / 64; ++it) {
+                const int e = it * 64 + lane, r = e / kPW, c = e - (e / kPW) * kPW;
+                w[u][it] = e < kPR * kPW ? *reinterpret_cast<const uint32_t*>(base + size_t(r) * d[u].pitch + 4 * c) : 0u;
+            }
         }
 #pragma unroll
-        for (int it = 0; it < 16; ++it) {
-            const int dy = -15 + 2 * it + (lane >> 5);
-            m10 += dx * I[it];
-            m01 += dy * I[it];
+        for (int u = 0; u < KW; ++u)
+#pragma unroll
+            for (int it = 0; it < (kPR * kPW + 63) / 64; ++it) {
+                const int e = it * 64 + lane;
+                if (e < kPR * kPW) patch[wv][u][e] = w[u][it];
+            }
+    }
+    // the patch is written and read by this wave alone: order its LDS writes before the reads
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // tests g * 64 + lane steered by the bin (k_steer)
+    uint32_t pk[KW][4];
+#pragma unroll
+    for (int u = 0; u < KW; ++u)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) pk[u][g] = steer[bin[u] * kBriefTests + g * 64 + lane];
+    bool bit[KW][4];
+#pragma unroll
+    for (int u = 0; u < KW; ++u) {
+        const uint8_t* P8 = reinterpret_cast<const uint8_t*>(patch[wv][u]);
+        const int cx = x[u] - a0[u];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const uint32_t q = pk[u][g];
+            const int ax = int(int8_t(q & 0xFF)), ay = int(int8_t((q >> 8) & 0xFF));
+            const int bx = int(int8_t((q >> 16) & 0xFF)), by = int(int8_t(q >> 24));
+            bit[u][g] = P8[(ay + 21) * (4 * kPW) + cx + ax] < P8[(by + 21) * (4 * kPW) + cx + bx];
         }
     }
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        m10 += __shfl_xor(m10, off);
-        m01 += __shfl_xor(m01, off);
-    }
-    long long sc = lane < 30 ? (long long)m10 * c_cos[lane] + (long long)m01 * c_sin[lane] : LLONG_MIN;
-    int bk = lane;
+    for (int u = 0; u < KW; ++u) {
+        unsigned long long words[4];
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const long long os = __shfl_xor(sc, off);
-        const int ob = __shfl_xor(bk, off);
-        if (os > sc || (os == sc && ob < bk)) { sc = os; bk = ob; }
-    }
-    const int bin = bk;
-    const uint8_t* Sm = smooth + d.offset;
-    const uint32_t* st = steer + bin * kBriefTests;
-    unsigned long long words[4];
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        // test g * 64 + lane steered by the bin (k_steer; offsets within +-21, inside the border)
-        const uint32_t pk = st[g * 64 + lane];
-        const int ax = int(int8_t(pk & 0xFF)), ay = int(int8_t((pk >> 8) & 0xFF));
-        const int bx = int(int8_t((pk >> 16) & 0xFF)), by = int(int8_t(pk >> 24));
-        const bool bit = Sm[size_t(y + ay) * pitch + x + ax] < Sm[size_t(y + by) * pitch + x + bx];
-        words[g] = __ballot(bit);
-    }
-    const size_t slot = size_t(v) * n_features + k;
-    if (lane < 4) reinterpret_cast<unsigned long long*>(desc + slot * XA_DESC_BYTES)[lane] = words[lane];
-    if (lane == 0) {
+        for (int g = 0; g < 4; ++g) words[g] = __ballot(bit[u][g]);
+        if (lev[u] < 0) continue;
+        const size_t slot = size_t(v) * n_features + k0 + u;
+        if (lane < 4) reinterpret_cast<unsigned long long*>(desc + slot * XA_DESC_BYTES)[lane] = words[lane];
+        if (lane == 0) {
 #pragma clang fp contract(off)     // the back-map rounds term by term, as a plain fp64 evaluation
-        const xa_view_desc& vd = views[v];
-        const xa_level_desc& l0 = levels[v * n_levels];
-        const double x0 = (double(x) + 0.5) * (double(l0.width) / double(d.width)) - 0.5;
-        const double y0 = (double(y) + 0.5) * (double(l0.height) / double(d.height)) - 0.5;
-        xa_keypoint o;
-        o.x = x; o.y = y; o.level = lev; o.bin = bin; o.harris = R;
-        o.xs = vd.inv[0] * x0 + vd.inv[1] * y0 + vd.inv[2];
-        o.ys = vd.inv[3] * x0 + vd.inv[4] * y0 + vd.inv[5];
-        if (vd.src_scale != 1.0) {     // scale-stage source: back to the original image
-            o.xs = (o.xs + 0.5) / vd.src_scale - 0.5;
-            o.ys = (o.ys + 0.5) / vd.src_scale - 0.5;
+            const xa_view_desc& vd = views[v];
+            const xa_level_desc& l0 = levels[v * n_levels];
+            const double x0 = (double(x[u]) + 0.5) * (double(l0.width) / double(d[u].width)) - 0.5;
+            const double y0 = (double(y[u]) + 0.5) * (double(l0.height) / double(d[u].height)) - 0.5;
+            xa_keypoint o;
+            o.x = x[u]; o.y = y[u]; o.level = lev[u]; o.bin = bin[u]; o.harris = R[u];
+            o.xs = vd.inv[0] * x0 + vd.inv[1] * y0 + vd.inv[2];
+            o.ys = vd.inv[3] * x0 + vd.inv[4] * y0 + vd.inv[5];
+            if (vd.src_scale != 1.0) {     // scale-stage source: back to the original image
+                o.xs = (o.xs + 0.5) / vd.src_scale - 0.5;
+                o.ys = (o.ys + 0.5) / vd.src_scale - 0.5;
+            }
+            kp[slot] = o;
         }
-        kp[slot] = o;
     }
 }
 
@@ -816,7 +885,7 @@ xa_status launch_extract(const PlanView& ph, const PlanView& pd, uint8_t* arena,
                        stage_count);
     uint32_t* steer = reinterpret_cast<uint32_t*>(ws + w.steer);
     hipLaunchKernelGGL(k_steer, dim3(kOrientBins), dim3(kBriefTests), 0, st, pattern, steer);
-    hipLaunchKernelGGL(k_orient_brief, dim3((N + 3) / 4, nv), dim3(256), 0, st, pd.views, pd.levels, L, N, arena,
+    hipLaunchKernelGGL(k_orient_brief, dim3((N + 4 * kKpPerWave - 1) / (4 * kKpPerWave), nv), dim3(256), 0, st, pd.views, pd.levels, L, N, arena,
                        smooth, stage, stage_count, steer, kp, desc, count);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "extract launch");
