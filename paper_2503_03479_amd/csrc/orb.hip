@@ -47,11 +47,6 @@ __device__ __forceinline__ int find_segment_wave(const int32_t* __restrict__ pre
     return lo;
 }
 
-__global__ void k_fill_i32(int32_t* p, int n, int32_t v) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-
 // ------------------------------------------------------------------ pyramid
 
 // Bilinear source position of destination index d for an n_src -> n_dst resize:
@@ -672,7 +667,15 @@ __device__ __forceinline__ int rnd20(int v) {
 // The rotated test offsets of the BRIEF pattern for every orientation bin: entry (b, i) packs
 // (ax, ay, bx, by) of test i steered by bin b as four int8 (each within +-21: the pattern's
 // coordinates are clamped to [-15, 15]).  One block per bin, one thread per test.
-__global__ void __launch_bounds__(kBriefTests) k_steer(const int8_t* __restrict__ pattern, uint32_t* __restrict__ steer) {
+// The extraction's set-up in one launch: blocks 0 .. kOrientBins - 1 steer the pattern (block b:
+// bin b), the rest zero the n candidate counters.
+__global__ void __launch_bounds__(kBriefTests) k_steer(const int8_t* __restrict__ pattern, uint32_t* __restrict__ steer,
+                                                       int32_t* __restrict__ zero, int n) {
+    if (int(blockIdx.x) >= kOrientBins) {
+        const int z = (blockIdx.x - kOrientBins) * kBriefTests + threadIdx.x;
+        if (z < n) zero[z] = 0;
+        return;
+    }
     const int b = blockIdx.x, i = threadIdx.x;
     const int Cb = c_cos[b], Sb = c_sin[b];
     const int x1 = clampi(pattern[4 * i], -15, 15), y1 = clampi(pattern[4 * i + 1], -15, 15);
@@ -869,7 +872,9 @@ xa_status launch_extract(const PlanView& ph, const PlanView& pd, uint8_t* arena,
     int32_t* cand_count = reinterpret_cast<int32_t*>(ws + w.cand_count);
     int4* stage = reinterpret_cast<int4*>(ws + w.stage);
     int32_t* stage_count = reinterpret_cast<int32_t*>(ws + w.stage_count);
-    hipLaunchKernelGGL(k_fill_i32, dim3((nvl + 255) / 256), dim3(256), 0, st, cand_count, nvl, 0);
+    uint32_t* steer = reinterpret_cast<uint32_t*>(ws + w.steer);
+    hipLaunchKernelGGL(k_steer, dim3(kOrientBins + (nvl + kBriefTests - 1) / kBriefTests), dim3(kBriefTests), 0, st,
+                       pattern, steer, cand_count, nvl);
     for (int l = 1; l < L; ++l) {
         const int32_t* pre_h = ph.level_prefix + size_t(l) * (nv + 1);
         const int tiles = pre_h[nv];
@@ -883,8 +888,6 @@ xa_status launch_extract(const PlanView& ph, const PlanView& pd, uint8_t* arena,
                            h->fast_threshold, arena, mask, cand, cand_count, smooth);
     hipLaunchKernelGGL(k_select, dim3(nvl), dim3(kSelThreads), 0, st, pd.levels, N, cand, cand_count, stage,
                        stage_count);
-    uint32_t* steer = reinterpret_cast<uint32_t*>(ws + w.steer);
-    hipLaunchKernelGGL(k_steer, dim3(kOrientBins), dim3(kBriefTests), 0, st, pattern, steer);
     hipLaunchKernelGGL(k_orient_brief, dim3((N + 4 * kKpPerWave - 1) / (4 * kKpPerWave), nv), dim3(256), 0, st, pd.views, pd.levels, L, N, arena,
                        smooth, stage, stage_count, steer, kp, desc, count);
     hipError_t e = hipGetLastError();
