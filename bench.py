@@ -46,7 +46,7 @@ MATCH_MATRIX = -1                 # matcher variant code of the matrix-core kern
 # file reports null.
 K_MATCH_TRAFFIC = {
     "source": "paper_2503_03479_amd/csrc/match.hip",
-    "sha256": "ea9a9be7510cbaa0056b87a579cec7c613ee3d54cbac3a8d7e415ec40b8d55ca",
+    "sha256": "9bc1c16fc117c1d8675b82d05ad713a54118d3d3c73f98b05784588b0970c3a1",
     "fetch_scale": 2.0, "write_scale": 1.0,
     "kib": {-1: (8148.2, 15619.2)},  # variant -> (fetch, write), variants measured on this source only
 }
@@ -65,21 +65,26 @@ def k_match_traffic(queries_per_lane: int):
 
 
 # HBM traffic of k_warp on one launch over both images' 90 views of the full-size pair (the launch
-# the timed step makes), from the same two --pmc passes and copy calibration as the matcher's.  Valid
-# only for the simulate source it was measured on.
+# the timed step makes), from the same two --pmc passes and copy calibration as the matcher's, with
+# the warp tile widths given here (the tuner's usual choice on MI355X).  Valid only for the simulate
+# sources it was measured on and for those widths.
 K_WARP_TRAFFIC = {
     "sources": ["paper_2503_03479_amd/csrc/simulate.hip", "paper_2503_03479_amd/csrc/internal.h",
                 "paper_2503_03479_amd/csrc/lanczos.h"],
-    "sha256": "6b1a7454f695fd702a7325303ef8da02a9e78dd1565c9bf834e20b66cf9f9c27",   # of the sources, concatenated
+    "sha256": "19b4ff5785662f3636669e234b28192dbecacbf455750ccb287009533fa026d8",   # of the sources, concatenated
+    "warp_tiles": [32, 16, 8, 8, 8, 8, 8, 8],
     "fetch_scale": 2.0, "write_scale": 1.0,
-    "kib": (109318.1, 67583.2),   # (fetch, write) per launch
+    "kib": (109311.4, 67582.3),   # (fetch, write) per launch
 }
 WARP_OPS_PER_PX = 72 + 16         # 64 + 8 multiply-adds of the 8 x 8 sum and the 16 kernel weights per view pixel
 
 
 def k_warp_traffic():
     import hashlib
+    from paper_2503_03479_amd import xaffine as X
     t = K_WARP_TRAFFIC
+    if [int(w) for w in X.get_warp_tiles()] != t["warp_tiles"]:
+        return None
     h = hashlib.sha256()
     for src in t["sources"]:
         with open(os.path.join(ROOT, src), "rb") as f:
@@ -176,6 +181,9 @@ def parse():
     ap.add_argument("--no-sift", action="store_true", help="skip the SIFT leg")
     ap.add_argument("--no-sweep", action="store_true", help="skip the Sec. IV.D sweep leg")
     ap.add_argument("--no-tune-tiles", action="store_true", help="keep the built-in warp tile widths")
+    ap.add_argument("--warp-tiles", default=None,
+                    help="fixed warp tile widths per compression class, 8 comma-separated values from 4 8 16 32 "
+                         "64 (instead of tuning them; for runs under a profiler, which distorts the tuner's timings)")
     ap.add_argument("--only", choices=["batched", "diffwarp", "copy", "sweep", "l2", "sift"], default=None,
                     help="run one leg alone and print its JSON (for profiler runs); 'copy' is a plain 1 GiB "
                          "device-to-device copy whose counter readings calibrate the HBM traffic counters")
@@ -793,7 +801,10 @@ def main():
     dev = torch.device("cuda:0")
     # warp tile widths per compression class, timed on this device before any plan is made
     tile_widths, tile_ms = X.get_warp_tiles(), None
-    if not args.no_tune_tiles and args.only in (None, "batched", "sweep"):
+    if args.warp_tiles is not None:
+        X.set_warp_tiles([int(w) for w in args.warp_tiles.split(",")])
+        tile_widths = X.get_warp_tiles()
+    elif not args.no_tune_tiles and args.only in (None, "batched", "sweep"):
         tile_widths, tile_ms = X.tune_warp_tiles(dev)
         progress(f"bench.py: warp tile widths {tile_widths.tolist()}")
     if args.only is not None:
@@ -958,7 +969,9 @@ def main():
                        "rule": [16, 16, 8, 8, 8, 8, 4, 4],
                        "ms_per_class_and_candidate": None if tile_ms is None else np.round(tile_ms, 4).tolist(),
                        "candidates": list(X.WARP_CANDIDATES),
-                       "tuner": "xa_tune_warp_tiles on a 1024x768 test image, class k = tilt sqrt(2)^k"},
+                       "tuner": ("fixed by --warp-tiles" if args.warp_tiles is not None else
+                                 "built-in rule (--no-tune-tiles)" if tile_ms is None else
+                                 "xa_tune_warp_tiles on a 1024x768 test image, class k = tilt sqrt(2)^k")},
         "device": torch.cuda.get_device_name(0),
         "host_cpu": platform.processor() or platform.machine(),
         "host_cores": os.cpu_count(),
