@@ -180,7 +180,11 @@ def parse():
     ap.add_argument("--l2-n", type=int, default=32768, help="descriptors per set in the L2 matcher leg (0 = skip)")
     ap.add_argument("--no-sift", action="store_true", help="skip the SIFT leg")
     ap.add_argument("--no-sweep", action="store_true", help="skip the Sec. IV.D sweep leg")
-    ap.add_argument("--no-tune-tiles", action="store_true", help="keep the built-in warp tile widths")
+    ap.add_argument("--no-tune-tiles", action="store_true",
+                    help="keep the built-in warp tile widths and blur outputs per thread")
+    ap.add_argument("--blur-rows", default=None,
+                    help="fixed blur outputs per thread per compression class, 8 comma-separated values from 4 8 "
+                         "(instead of tuning them)")
     ap.add_argument("--warp-tiles", default=None,
                     help="fixed warp tile widths per compression class, 8 comma-separated values from 4 8 16 32 "
                          "64 (instead of tuning them; for runs under a profiler, which distorts the tuner's timings)")
@@ -807,6 +811,13 @@ def main():
     elif not args.no_tune_tiles and args.only in (None, "batched", "sweep"):
         tile_widths, tile_ms = X.tune_warp_tiles(dev)
         progress(f"bench.py: warp tile widths {tile_widths.tolist()}")
+    blur_rows, blur_ms = X.get_blur_rows(), None
+    if args.blur_rows is not None:
+        X.set_blur_rows([int(r) for r in args.blur_rows.split(",")])
+        blur_rows = X.get_blur_rows()
+    elif not args.no_tune_tiles and args.only in (None, "batched", "sweep"):
+        blur_rows, blur_ms = X.tune_blur_rows(dev)
+        progress(f"bench.py: blur rows {blur_rows.tolist()}")
     if args.only is not None:
         pattern = torch.from_numpy(synth.brief_pattern()).to(dev)
         if args.only == "batched":
@@ -972,6 +983,11 @@ def main():
                        "tuner": ("fixed by --warp-tiles" if args.warp_tiles is not None else
                                  "built-in rule (--no-tune-tiles)" if tile_ms is None else
                                  "xa_tune_warp_tiles on a 1024x768 test image, class k = tilt sqrt(2)^k")},
+        "blur_rows": {"rows_per_class": [int(r) for r in blur_rows], "default": 8,
+                      "ms_per_class_4_8": None if blur_ms is None else np.round(blur_ms, 4).tolist(),
+                      "tuner": ("fixed by --blur-rows" if args.blur_rows is not None else
+                                "default (--no-tune-tiles)" if blur_ms is None else
+                                "xa_tune_blur_rows on a 1024x768 test image, class k = tilt sqrt(2)^k")},
         "device": torch.cuda.get_device_name(0),
         "host_cpu": platform.processor() or platform.machine(),
         "host_cores": os.cpu_count(),

@@ -51,7 +51,7 @@ typedef enum {
 } xa_status;
 
 #define XA_PLAN_MAGIC 0x58414650u   /* "XAFP" */
-#define XA_PLAN_VERSION 5u
+#define XA_PLAN_VERSION 6u
 #define XA_MAX_LEVELS 12
 #define XA_MAX_QUOTA 2048           /* keypoints per pyramid level */
 #define XA_MAX_FEATURES 4096        /* keypoints per view */
@@ -106,7 +106,8 @@ typedef struct {
     int32_t interp;             /* XA_INTERP_LANCZOS4 (eqs. (3)-(4)) or XA_INTERP_NEAREST */
     int32_t warp_ls_mod;        /* residue mod 64 of the row stride (floats) of the warp's LDS source tile,
                                    chosen by the planner to spread the 8 x 8 sums' reads over the LDS banks */
-    int32_t reserved;
+    int32_t blur_rows;          /* outputs per thread of the blur across the minor axis (4 or 8; 0 if no blur):
+                                   the blur's tiles are 64 x 4 blur_rows (taps along x) or 4 blur_rows x 64 */
 } xa_view_desc;
 
 #define XA_INTERP_LANCZOS4 0
@@ -273,6 +274,22 @@ xa_status xa_get_warp_tiles(int32_t* widths);
  * timed on the same device.  Workspace: xa_tune_warp_tiles_workspace_size(src_w, src_h) bytes,
  * 256-byte aligned (0 for sizes outside 16..8192).  XA_EINVAL for sizes or pointers out of
  * range; XA_EHIP for runtime errors. */
+/* The blur's outputs per thread across the minor axis (4 or 8), per compression class as for the
+ * warp tiles: xa_set_blur_rows(rows) sets the table the planner reads (rows: XA_WARP_CLASSES
+ * entries in {0, 4, 8}, 0 = the default 8; NULL: the default for every class); plans made before
+ * keep theirs.  Only the speed changes: each blurred sample is the same sum in the same order.
+ * xa_get_blur_rows returns the table in effect.  XA_EINVAL for other values.  The tuner blurs the
+ * sampling grid's views of each class k >= 1 of a src_w x src_h test image (repeated to about
+ * 8 M source pixels) with 4 and 8 rows, 3 timed launches each after one untimed (ms[k][2], if not
+ * NULL; class 0 has no blur and gets 0), and gives rows[k] = 4 if that beats 8 by more than 3 %,
+ * else 8.  Not applied; synchronises `stream`.  Workspace: xa_tune_blur_rows_workspace_size(src_w,
+ * src_h) bytes, 256-byte aligned; XA_EINVAL for sizes outside 16..8192 or bad pointers. */
+xa_status xa_set_blur_rows(const int32_t* rows);
+xa_status xa_get_blur_rows(int32_t* rows);
+size_t xa_tune_blur_rows_workspace_size(int32_t src_w, int32_t src_h);
+xa_status xa_tune_blur_rows(int32_t src_w, int32_t src_h, void* d_ws, size_t ws_bytes, hipStream_t stream,
+                            int32_t* rows, float* ms);
+
 size_t xa_tune_warp_tiles_workspace_size(int32_t src_w, int32_t src_h);
 xa_status xa_tune_warp_tiles(int32_t src_w, int32_t src_h, void* d_ws, size_t ws_bytes, hipStream_t stream,
                              int32_t* widths, float* ms);

@@ -16,14 +16,16 @@ constexpr int kWarpRows = 2;                // view pixels per warp thread (tile
 constexpr int kWarpLds = 8192;              // floats of source footprint a warp tile can stage in LDS
 constexpr int kPyrTX = 256, kPyrTY = 16;    // pyramid down-sampling (4 x 4 output pixels per thread)
 constexpr int kFastTX = 64, kFastTY = 32;   // FAST / NMS / smoothing / Harris tiles (256 threads, 8 rows each)
-constexpr int kBlurTX = 64, kBlurTY = 16;   // directional blur over the source, taps along x (4 rows per thread)
+constexpr int kBlurRowsDefault = 8;         // directional blur: outputs per thread across the minor axis
+constexpr int kBlurTX = 64;                  // blur tile side along the taps' major axis (one wave's lanes)
 constexpr int kBlurStride = 128;            // LDS row stride (floats) of a major-x blur tile
 constexpr int kBlurLdsMax = 16384;          // floats of source a blur tile may stage in LDS (64 KiB)
 // Blur tiles: 64 x 16 when the taps step along x (a wave's lanes take 64 columns of one row
 // group), 16 x 64 when they step along y (a wave's lanes take 64 rows of one 4-column group, so
 // each tap read hits 64 rows, one per LDS bank at the odd row stride).
-__host__ __device__ inline int blur_tile_w(int major) { return major == 0 ? kBlurTX : kBlurTY; }
-__host__ __device__ inline int blur_tile_h(int major) { return major == 0 ? kBlurTY : kBlurTX; }
+// Blur tile: kBlurTX along the major axis by 4 waves x `rows` outputs across it.
+__host__ __device__ inline int blur_tile_w(int major, int rows) { return major == 0 ? kBlurTX : 4 * rows; }
+__host__ __device__ inline int blur_tile_h(int major, int rows) { return major == 0 ? 4 * rows : kBlurTX; }
 
 // Warp tile width for a view: the output tile is w x (512 / w), narrow along the compressed
 // axis so that its source footprint stays compact.
@@ -37,6 +39,11 @@ int warp_class(double t, double s);
 int planned_warp_tile_w(double t, double s);
 void set_tile_override(const int32_t* widths);   // per thread; NULL ends the override
 bool valid_warp_tile_w(int32_t w);
+// Blur outputs per thread the planner uses for a view of compression class warp_class(t, s): the
+// caller's table (xa_set_blur_rows) or the tuner's per-thread override, else kBlurRowsDefault.
+int planned_blur_rows(double t, double s);
+void set_blur_rows_override(const int32_t* rows);   // per thread; NULL ends the override
+inline bool valid_blur_rows(int32_t r) { return r == 4 || r == 8; }
 // The hardware deals consecutive blocks of a launch round-robin to the 8 XCDs, each with its
 // own L2.  For kernels whose neighbouring tiles share cache lines (narrow warp tiles), this
 // remap gives each XCD one contiguous run of tiles instead: block b, the i-th on XCD b % 8,

@@ -35,6 +35,18 @@ int planned_warp_tile_w(double t, double s) {
 
 void set_tile_override(const int32_t* widths) { t_tile_override = widths; }
 
+static int32_t g_blur_rows[XA_WARP_CLASSES] = {};
+static thread_local const int32_t* t_rows_override = nullptr;
+
+int planned_blur_rows(double t, double s) {
+    const int k = warp_class(t, s);
+    if (t_rows_override && t_rows_override[k] > 0) return t_rows_override[k];
+    std::lock_guard<std::mutex> lock(g_tiles_mu);
+    return g_blur_rows[k] > 0 ? g_blur_rows[k] : kBlurRowsDefault;
+}
+
+void set_blur_rows_override(const int32_t* rows) { t_rows_override = rows; }
+
 bool valid_warp_tile_w(int32_t w) { return w == 4 || w == 8 || w == 16 || w == 32 || w == 64; }
 
 static thread_local std::string g_error;
@@ -401,7 +413,8 @@ extern "C" xa_status xa_plan_views(const xa_source_desc* sources, int32_t n_sour
             taps.insert(taps.end(), pv[i].taps.begin(), pv[i].taps.end());
             blur_views.push_back(i);
             blur_prefix.push_back(int32_t(blur_tiles));
-            const int btw = blur_tile_w(v.blur_major), bth = blur_tile_h(v.blur_major);
+            v.blur_rows = planned_blur_rows(v.p.t, v.p.s);
+            const int btw = blur_tile_w(v.blur_major, v.blur_rows), bth = blur_tile_h(v.blur_major, v.blur_rows);
             blur_tiles += int64_t((v.src_w + btw - 1) / btw) * ((v.src_h + bth - 1) / bth);
         }
         warp_prefix[i] = int32_t(warp_tiles);
@@ -537,5 +550,22 @@ extern "C" xa_status xa_get_warp_tiles(int32_t* widths) {
         const double c = std::pow(2.0, 0.5 * k + 0.25);     // a compression inside class k
         widths[k] = g_warp_tiles[k] > 0 ? g_warp_tiles[k] : warp_tile_w(c, 1.0);
     }
+    return ok();
+}
+
+extern "C" xa_status xa_set_blur_rows(const int32_t* rows) {
+    if (rows)
+        for (int k = 0; k < XA_WARP_CLASSES; ++k)
+            if (rows[k] != 0 && !valid_blur_rows(rows[k]))
+                return fail(XA_EINVAL, "blur rows %d of class %d are not 0, 4 or 8", rows[k], k);
+    std::lock_guard<std::mutex> lock(g_tiles_mu);
+    for (int k = 0; k < XA_WARP_CLASSES; ++k) g_blur_rows[k] = rows ? rows[k] : 0;
+    return ok();
+}
+
+extern "C" xa_status xa_get_blur_rows(int32_t* rows) {
+    if (!rows) return fail(XA_EINVAL, "NULL output");
+    std::lock_guard<std::mutex> lock(g_tiles_mu);
+    for (int k = 0; k < XA_WARP_CLASSES; ++k) rows[k] = g_blur_rows[k] > 0 ? g_blur_rows[k] : kBlurRowsDefault;
     return ok();
 }

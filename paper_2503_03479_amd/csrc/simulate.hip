@@ -39,7 +39,7 @@ struct BlurRegion {
 __host__ __device__ inline BlurRegion blur_region(const xa_view_desc& v, const BlurTap* tp, int x0, int y0) {
     const int n = v.blur_ntaps, K = (n - 1) / 2;
     const int dlo = min(tp[0].dmin, tp[n - 1].dmin), dhi = max(tp[0].dmin, tp[n - 1].dmin) + 1;
-    const int tw = blur_tile_w(v.blur_major), th = blur_tile_h(v.blur_major);
+    const int tw = blur_tile_w(v.blur_major, v.blur_rows), th = blur_tile_h(v.blur_major, v.blur_rows);
     BlurRegion r;
     if (v.blur_major == 0) {
         r.rx0 = x0 - K; r.rw = tw + 2 * K;
@@ -54,8 +54,76 @@ __host__ __device__ inline BlurRegion blur_region(const xa_view_desc& v, const B
     return r;
 }
 
-// Directional Gaussian over the source, one block per 64 x 16 tile of one blurred view (16 x 64
-// when the taps step along y).
+// The outputs of one blur tile from its staged footprint: each thread makes R outputs adjacent
+// across the minor axis (rows for taps along x, columns for taps along y); tap k of them reads
+// R + 1 consecutive minor samples, and each output keeps the same sum order as a one-output
+// evaluation.
+template <int R>
+__device__ __forceinline__ void blur_outputs(const float* __restrict__ btile, const BlurRegion& g, const xa_view_desc& v,
+                                             const BlurTap* __restrict__ tp, int n, int x0, int y0, int W, int H,
+                                             float* __restrict__ o) {
+    const int n4 = (n + 3) & ~3;           // the tap table is padded with zero taps to a multiple of 4
+    const int bp = blur_pitch(W);
+    float a[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) a[i] = 0.0f;
+    if (v.blur_major == 0) {
+        const int c = threadIdx.x & 63, gq = threadIdx.x >> 6;        // column, group of R rows
+        const int x = x0 + c, y = y0 + R * gq;
+        if (x < W && y < H) {
+            constexpr int S = kBlurStride;
+            const float* base = btile + (y - g.ry0) * S + (x - g.rx0);
+            for (int k = 0; k < n4; k += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const BlurTap t = tp[k + u];
+                    const float* q = base + t.dmin * S + t.dmaj;
+                    float r[R + 1];
+#pragma unroll
+                    for (int i = 0; i <= R; ++i) r[i] = q[i * S];
+#pragma unroll
+                    for (int i = 0; i < R; ++i) a[i] = fmaf(t.wb, r[i + 1], fmaf(t.wa, r[i], a[i]));
+                }
+            }
+            float* op = o + size_t(y) * bp + x;
+#pragma unroll
+            for (int i = 0; i < R; ++i)
+                if (y + i < H) op[size_t(i) * bp] = a[i];
+        }
+    } else {
+        const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;         // row, group of R columns
+        const int x = x0 + R * cg, y = y0 + r;
+        if (x < W && y < H) {
+            const float* base = btile + (y - g.ry0) * g.stride + (x - g.rx0);
+            for (int k = 0; k < n4; k += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const BlurTap t = tp[k + u];
+                    const float* q = base + t.dmaj * g.stride + t.dmin;
+                    float rr[R + 1];
+#pragma unroll
+                    for (int i = 0; i <= R; ++i) rr[i] = q[i];
+#pragma unroll
+                    for (int i = 0; i < R; ++i) a[i] = fmaf(t.wb, rr[i + 1], fmaf(t.wa, rr[i], a[i]));
+                }
+            }
+            float* op = o + size_t(y) * bp + x;
+#pragma unroll
+            for (int i = 0; i < R; i += 4) {
+                if (x + i + 3 < W) {
+                    *reinterpret_cast<float4*>(op + i) = make_float4(a[i], a[i + 1], a[i + 2], a[i + 3]);   // x + i and bp are multiples of 4
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (x + i + e < W) op[i + e] = a[i + e];
+                }
+            }
+        }
+    }
+}
+
+// Directional Gaussian over the source, one block per 64 x 4R tile of one blurred view (4R x 64
+// when the taps step along y; R = blur_rows, 4 or 8).
 // out(p) = sum_k w_k lerp(I, p + k v), v = (1, m) (major x) or (m, 1) (major y), written as
 // sum_k wa_k I(p + k v_whole) + wb_k I(p + k v_whole + e_minor).  The tile's source footprint
 // is staged in LDS as fp32 with the border replicated at load time (the same as clamping
@@ -72,7 +140,7 @@ __global__ void __launch_bounds__(256) k_blur(const uint8_t* __restrict__ source
     const int W = v.src_w, H = v.src_h, pitch = v.src_pitch;
     const uint8_t* src = sources + v.src_offset;
     const int local = blockIdx.x - blur_prefix[bi];
-    const int btw = blur_tile_w(v.blur_major), bth = blur_tile_h(v.blur_major);
+    const int btw = blur_tile_w(v.blur_major, v.blur_rows), bth = blur_tile_h(v.blur_major, v.blur_rows);
     const int tiles_x = (W + btw - 1) / btw;
     const int x0 = (local % tiles_x) * btw, y0 = (local / tiles_x) * bth;
     const int tx = threadIdx.x % btw, ty0 = threadIdx.x / btw;
@@ -142,64 +210,8 @@ __global__ void __launch_bounds__(256) k_blur(const uint8_t* __restrict__ source
             }
         }
         __syncthreads();
-        // each thread makes 4 outputs adjacent across the minor axis (rows for major x, columns
-        // for major y): tap k of the 4 reads 5 consecutive minor samples instead of 8, and each
-        // output keeps the same sum order as a one-output evaluation
-        const int n4 = (n + 3) & ~3;           // the tap table is padded with zero taps to a multiple of 4
-        const int bp = blur_pitch(W);
-        if (v.blur_major == 0) {
-            const int c = threadIdx.x & 63, gq = threadIdx.x >> 6;        // column, group of 4 rows
-            const int x = x0 + c, y = y0 + 4 * gq;
-            if (x < W && y < H) {
-                const int S = kBlurStride;
-                const float* base = btile + (y - g.ry0) * S + (x - g.rx0);
-                float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
-                for (int k = 0; k < n4; k += 4) {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const BlurTap t = tp[k + u];
-                        const float* q = base + t.dmin * S + t.dmaj;
-                        const float r0 = q[0], r1 = q[S], r2 = q[2 * S], r3 = q[3 * S], r4 = q[4 * S];
-                        a0 = fmaf(t.wb, r1, fmaf(t.wa, r0, a0));
-                        a1 = fmaf(t.wb, r2, fmaf(t.wa, r1, a1));
-                        a2 = fmaf(t.wb, r3, fmaf(t.wa, r2, a2));
-                        a3 = fmaf(t.wb, r4, fmaf(t.wa, r3, a3));
-                    }
-                }
-                float* op = o + size_t(y) * bp + x;
-                op[0] = a0;
-                if (y + 1 < H) op[bp] = a1;
-                if (y + 2 < H) op[2 * bp] = a2;
-                if (y + 3 < H) op[3 * bp] = a3;
-            }
-        } else {
-            const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;         // row, group of 4 columns
-            const int x = x0 + 4 * cg, y = y0 + r;
-            if (x < W && y < H) {
-                const float* base = btile + (y - g.ry0) * g.stride + (x - g.rx0);
-                float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
-                for (int k = 0; k < n4; k += 4) {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const BlurTap t = tp[k + u];
-                        const float* q = base + t.dmaj * g.stride + t.dmin;
-                        const float r0 = q[0], r1 = q[1], r2 = q[2], r3 = q[3], r4 = q[4];
-                        a0 = fmaf(t.wb, r1, fmaf(t.wa, r0, a0));
-                        a1 = fmaf(t.wb, r2, fmaf(t.wa, r1, a1));
-                        a2 = fmaf(t.wb, r3, fmaf(t.wa, r2, a2));
-                        a3 = fmaf(t.wb, r4, fmaf(t.wa, r3, a3));
-                    }
-                }
-                float* op = o + size_t(y) * bp + x;
-                if (x + 3 < W) {
-                    *reinterpret_cast<float4*>(op) = make_float4(a0, a1, a2, a3);   // x and bp are multiples of 4
-                } else {
-                    op[0] = a0;
-                    if (x + 1 < W) op[1] = a1;
-                    if (x + 2 < W) op[2] = a2;
-                }
-            }
-        }
+        if (v.blur_rows == 4) blur_outputs<4>(btile, g, v, tp, n, x0, y0, W, H, o);
+        else blur_outputs<8>(btile, g, v, tp, n, x0, y0, W, H, o);
         return;
     }
     // footprint larger than the LDS tile (very large sigma): read the taps from global memory
@@ -606,11 +618,15 @@ struct TunePlan {
     std::vector<uint8_t> blob;
 };
 
-xa_status tune_plan(int w, int h, int pitch, int k, int width, TunePlan* out) {
+xa_status tune_plan(int w, int h, int pitch, int k, int width, TunePlan* out, int rows = 0) {
     const std::vector<xa_affine_params> views = class_views(k, w, h);
-    int32_t forced[XA_WARP_CLASSES];
-    for (int c = 0; c < XA_WARP_CLASSES; ++c) forced[c] = width;
+    int32_t forced[XA_WARP_CLASSES], forced_rows[XA_WARP_CLASSES];
+    for (int c = 0; c < XA_WARP_CLASSES; ++c) {
+        forced[c] = width;
+        forced_rows[c] = rows;
+    }
     set_tile_override(forced);
+    set_blur_rows_override(rows > 0 ? forced_rows : nullptr);
     size_t bytes = 0;
     xa_status s = xa_plan_image(w, h, pitch, views.data(), int32_t(views.size()), 1, 1.2, 1, 20, nullptr, 0, &bytes);
     if (s == XA_OK) {
@@ -619,6 +635,7 @@ xa_status tune_plan(int w, int h, int pitch, int k, int width, TunePlan* out) {
                           &bytes);
     }
     set_tile_override(nullptr);
+    set_blur_rows_override(nullptr);
     return s;
 }
 
@@ -631,14 +648,16 @@ xa_status tune_layout(int w, int h, TuneLayout* L) {
     L->pitch = (w + 15) / 16 * 16;
     size_t blob = 0, ws = 0, arena = 0;
     for (int k = 0; k < XA_WARP_CLASSES; ++k) {
-        TunePlan P;
-        const xa_status s = tune_plan(w, h, L->pitch, k, 8, &P);
-        if (s != XA_OK) return s;
-        PlanView pv;
-        plan_host_view(P.blob.data(), &pv);
-        blob = std::max(blob, P.blob.size());
-        ws = std::max(ws, simulate_ws_bytes(pv.h));
-        arena = std::max(arena, size_t(pv.h->arena_bytes));
+        for (const int rows : {4, 8}) {
+            TunePlan P;
+            const xa_status s = tune_plan(w, h, L->pitch, k, 8, &P, rows);
+            if (s != XA_OK) return s;
+            PlanView pv;
+            plan_host_view(P.blob.data(), &pv);
+            blob = std::max(blob, P.blob.size());
+            ws = std::max(ws, simulate_ws_bytes(pv.h));
+            arena = std::max(arena, size_t(pv.h->arena_bytes));
+        }
     }
     size_t o = 0;
     L->src = o;   o += align_up(size_t(L->pitch) * h);
@@ -723,6 +742,73 @@ extern "C" xa_status xa_tune_warp_tiles(int32_t src_w, int32_t src_h, void* d_ws
         for (int c = 0; c < XA_WARP_CANDIDATES; ++c)
             if (kTuneCandidates[c] == rule_w) rule_ms = times[c];
         widths[k] = times[best_c] < (1.0f - kTuneMargin) * rule_ms ? kTuneCandidates[best_c] : rule_w;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return s == XA_OK ? ok() : s;
+}
+
+extern "C" size_t xa_tune_blur_rows_workspace_size(int32_t src_w, int32_t src_h) {
+    return xa_tune_warp_tiles_workspace_size(src_w, src_h);
+}
+
+extern "C" xa_status xa_tune_blur_rows(int32_t src_w, int32_t src_h, void* d_ws, size_t ws_bytes, hipStream_t stream,
+                                       int32_t* rows, float* ms) {
+    if (src_w < 16 || src_h < 16 || src_w > 8192 || src_h > 8192)
+        return fail(XA_EINVAL, "tuning image must be 16..8192 pixels a side");
+    if (!rows) return fail(XA_EINVAL, "NULL output");
+    TuneLayout L;
+    xa_status s = tune_layout(src_w, src_h, &L);
+    if (s != XA_OK) return s;
+    if (!d_ws || ws_bytes < L.total || reinterpret_cast<uintptr_t>(d_ws) % kAlign)
+        return fail(XA_EINVAL, "workspace of %zu bytes (256-byte aligned) needed, %zu given", L.total, ws_bytes);
+    uint8_t* base = static_cast<uint8_t*>(d_ws);
+    uint8_t* src = base + L.src;
+    void* blob_dev = base + L.blob;
+    float* blurred = reinterpret_cast<float*>(base + L.ws);
+    uint8_t* arena = base + L.arena;
+    uint8_t* mask = base + L.mask;
+    hipLaunchKernelGGL(k_tune_fill, dim3(unsigned((src_w + 255) / 256), unsigned(src_h)), dim3(256), 0, stream, src,
+                       L.pitch, src_w, src_h);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) return hip_fail(e, "event create");
+    constexpr int kReps = 3;
+    constexpr float kTuneMargin = 0.03f;
+    constexpr int kRows[2] = {4, 8};
+    rows[0] = kBlurRowsDefault;                  // class 0 (t/s < sqrt 2) has no blur on the grid
+    if (ms) ms[0] = ms[1] = 0.0f;
+    for (int k = 1; k < XA_WARP_CLASSES && s == XA_OK; ++k) {
+        float times[2] = {};
+        for (int c = 0; c < 2 && s == XA_OK; ++c) {
+            TunePlan P;
+            s = tune_plan(src_w, src_h, L.pitch, k, 8, &P, kRows[c]);
+            if (s != XA_OK) break;
+            if (P.blob.size() > L.ws - L.blob) {     // the plan's slot in the workspace
+                s = fail(XA_EUNSUPPORTED, "tuning plan larger than its workspace slot");
+                break;
+            }
+            e = hipMemcpyAsync(blob_dev, P.blob.data(), P.blob.size(), hipMemcpyHostToDevice, stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(stream);     // the host blob goes out of scope below
+            if (e != hipSuccess) { s = hip_fail(e, "plan upload"); break; }
+            PlanView ph;
+            plan_host_view(P.blob.data(), &ph);
+            const PlanView pd = plan_dev_view(P.blob.data(), blob_dev);
+            s = launch_simulate(ph, pd, src, arena, mask, nullptr, blurred, stream, kStageBlur);
+            e = hipEventRecord(e0, stream);
+            for (int r = 0; r < kReps && s == XA_OK; ++r)
+                s = launch_simulate(ph, pd, src, arena, mask, nullptr, blurred, stream, kStageBlur);
+            if (e == hipSuccess) e = hipEventRecord(e1, stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float t = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+            if (e != hipSuccess) { s = hip_fail(e, "tuning timing"); break; }
+            times[c] = t / kReps;
+            if (ms) ms[2 * k + c] = times[c];
+        }
+        if (s != XA_OK) break;
+        rows[k] = times[0] < (1.0f - kTuneMargin) * times[1] ? 4 : 8;
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);

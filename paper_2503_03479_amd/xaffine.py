@@ -29,7 +29,7 @@ VIEW_DTYPE = np.dtype([("p", PARAMS_DTYPE), ("source", "i4"), ("src_w", "i4"), (
                        ("src_offset", "i8"), ("src_scale", "f8"), ("width", "i4"), ("height", "i4"), ("pitch", "i4"),
                        ("warp_tile_w", "i4"), ("fwd", "f8", 6), ("inv", "f8", 6), ("sigma", "f8"), ("ux", "f8"),
                        ("uy", "f8"), ("offset", "i8"), ("blur_offset", "i8"), ("blur_major", "i4"), ("blur_tap0", "i4"),
-                       ("blur_ntaps", "i4"), ("interp", "i4"), ("warp_ls_mod", "i4"), ("reserved", "i4")])
+                       ("blur_ntaps", "i4"), ("interp", "i4"), ("warp_ls_mod", "i4"), ("blur_rows", "i4")])
 LEVEL_DTYPE = np.dtype([("width", "i4"), ("height", "i4"), ("pitch", "i4"), ("quota", "i4"), ("offset", "i8"),
                         ("kp_base", "i4"), ("view", "i4"), ("level", "i4"), ("pad", "i4"), ("cand_offset", "i8"),
                         ("cand_cap", "i8")])
@@ -118,6 +118,11 @@ _SIGS = {
     "xa_tune_warp_tiles_workspace_size": (_c.c_size_t, [_c.c_int32, _c.c_int32]),
     "xa_tune_warp_tiles": (_c.c_int, [_c.c_int32, _c.c_int32, _c.c_void_p, _c.c_size_t, _c.c_void_p, _c.c_void_p,
                                       _c.c_void_p]),
+    "xa_set_blur_rows": (_c.c_int, [_c.c_void_p]),
+    "xa_get_blur_rows": (_c.c_int, [_c.c_void_p]),
+    "xa_tune_blur_rows_workspace_size": (_c.c_size_t, [_c.c_int32, _c.c_int32]),
+    "xa_tune_blur_rows": (_c.c_int, [_c.c_int32, _c.c_int32, _c.c_void_p, _c.c_size_t, _c.c_void_p, _c.c_void_p,
+                                     _c.c_void_p]),
     "xa_tune_matcher_workspace_size": (_c.c_size_t, [_c.c_void_p, _c.c_int32, _c.c_int32]),
     "xa_tune_matcher": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_int32,
                                    _c.c_int32, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_size_t,
@@ -248,6 +253,51 @@ def tune_warp_tiles(device="cuda", src_w: int = 1024, src_h: int = 768, apply: b
     if apply:
         set_warp_tiles(widths)
     return widths, ms
+
+
+BLUR_ROWS = (4, 8)
+_TUNED_ROWS = {}         # device name -> blur rows chosen by tune_blur_rows in this process
+
+
+def set_blur_rows(rows=None):
+    """Blur outputs per thread (4 or 8) per compression class for plans made from now on (None: 8)."""
+    if rows is None:
+        _check(lib().xa_set_blur_rows(None))
+        return
+    r = np.ascontiguousarray(rows, np.int32)
+    if r.shape != (WARP_CLASSES,):
+        raise XAError(-1, f"need {WARP_CLASSES} values")
+    _check(lib().xa_set_blur_rows(r.ctypes.data))
+
+
+def get_blur_rows() -> np.ndarray:
+    r = np.zeros(WARP_CLASSES, np.int32)
+    _check(lib().xa_get_blur_rows(r.ctypes.data))
+    return r
+
+
+def tune_blur_rows(device="cuda", src_w: int = 1024, src_h: int = 768, apply: bool = True, cache: bool = True):
+    """Run the library's blur tuner (xa_tune_blur_rows) on `device`; returns (rows int32 [classes],
+    ms float32 [classes, 2] for 4 and 8 rows).  apply and cache as for tune_warp_tiles."""
+    import torch
+    dev = torch.device(device)
+    name = torch.cuda.get_device_name(dev)
+    if cache and name in _TUNED_ROWS:
+        rows, ms = _TUNED_ROWS[name], None
+    else:
+        need = lib().xa_tune_blur_rows_workspace_size(src_w, src_h)
+        if need == 0:
+            raise XAError(-1, "tuning image size out of range")
+        ws = _empty(need, dev)
+        rows = np.zeros(WARP_CLASSES, np.int32)
+        ms = np.zeros((WARP_CLASSES, len(BLUR_ROWS)), np.float32)
+        with torch.cuda.device(dev):
+            _check(lib().xa_tune_blur_rows(src_w, src_h, _ptr(ws), ws.numel(), _stream(), rows.ctypes.data,
+                                           ms.ctypes.data))
+        _TUNED_ROWS[name] = rows.copy()
+    if apply:
+        set_blur_rows(rows)
+    return rows, ms
 
 
 def _set_interp(plan: "Plan", interp: str) -> "Plan":

@@ -67,3 +67,36 @@ def test_tuned_and_rule_plans_simulate_the_same_views(dev):
         assert not np.array_equal(w, w0)
         assert np.array_equal(a, a0) and np.array_equal(m, m0)
     say("[tiles] views identical under three width tables")
+
+
+def test_blur_rows_tuner_and_identical_blurs(dev):
+    """The blur's outputs per thread (4 or 8) change only which thread makes a blurred sample: the
+    blurred planes (fp32 values of the views) are bit-identical under three tables, and the tuner
+    keeps 8 unless 4 is more than 3 % faster in a class."""
+    say("case: blur rows tuner on 512 x 384; the full-size pair's image A under rows 8 / 4 / mixed")
+    try:
+        rows, ms = X.tune_blur_rows(dev, 512, 384, apply=False, cache=False)
+        torch.cuda.synchronize()
+        assert rows[0] == 8 and np.all(ms[0] == 0)
+        for k in range(1, X.WARP_CLASSES):
+            assert np.all(ms[k] > 0) and np.all(np.isfinite(ms[k]))
+            want = 4 if ms[k, 0] < np.float32(0.97) * ms[k, 1] else 8
+            assert int(rows[k]) == want, (k, rows.tolist(), ms[k].tolist())
+        say(f"[blur rows] tuned {rows.tolist()}")
+        case = synth.make_pair(**synth.PAIR_CONFIGS["full"])
+        src = torch.from_numpy(np.ascontiguousarray(case.A)).to(dev)
+        grid = X.sampling_grid(5)
+        outs = []
+        for table in (None, [4] * 8, [8, 4, 8, 4, 4, 8, 4, 8]):
+            X.set_blur_rows(table)
+            plan = X.plan_image(1024, 768, grid, 8, 1.2, 1000, 20)
+            arena, mask, vals = X.simulate_views(plan, src, values=True)
+            torch.cuda.synchronize()
+            outs.append((plan.views["blur_rows"].copy(), vals.cpu().numpy(), arena.cpu().numpy()))
+    finally:
+        X.set_blur_rows(None)
+    (r0, v0, a0) = outs[0]
+    for (r, v, a) in outs[1:]:
+        assert not np.array_equal(r, r0)
+        assert np.array_equal(v, v0) and np.array_equal(a, a0)
+    say("[blur rows] view values identical under three tables")

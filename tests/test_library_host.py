@@ -270,7 +270,8 @@ def test_warp_stride_residues(L):
     m1 = p1.views["warp_ls_mod"]
     assert ((m1 >= 0) & (m1 < 64)).all()
     assert np.array_equal(m1, p2.views["warp_ls_mod"])
-    assert (p1.views["reserved"] == 0).all()
+    # blurred views carry the blur's outputs per thread (the default 8), unblurred ones 0
+    assert (p1.views["blur_rows"] == np.where(p1.views["sigma"] > 0, 8, 0)).all()
     # a second image size gives the same linear maps: each residue lies in 0..63 there too
     assert ((p3.views["warp_ls_mod"] >= 0) & (p3.views["warp_ls_mod"] < 64)).all()
     # duplicated grid views share the residue
@@ -326,3 +327,36 @@ def test_warp_tile_table_drives_the_planner(L):
     assert X.get_warp_tiles().tolist() == rule.tolist()
     assert X.lib().xa_tune_warp_tiles_workspace_size(8, 8) == 0
     assert X.lib().xa_tune_warp_tiles_workspace_size(1024, 768) > 1024 * 768
+
+
+def test_blur_rows_table_drives_the_planner(L):
+    """xa_set_blur_rows: the blur's outputs per thread (4 or 8) per compression class, validated,
+    used by plans made afterwards only, with blur tiles of 64 x 4r (taps along x) or 4r x 64 counted
+    in the plan's blur prefix; NULL restores 8 everywhere."""
+    assert X.get_blur_rows().tolist() == [8] * 8
+    grid = X.sampling_grid(5)
+    before = X.plan_image(640, 480, grid, 3, 1.2, 300, 20)
+    try:
+        X.set_blur_rows([0, 4, 8, 4, 8, 4, 8, 8])
+        assert X.get_blur_rows().tolist() == [8, 4, 8, 4, 8, 4, 8, 8]
+        p = X.plan_image(640, 480, grid, 3, 1.2, 300, 20)
+        want = {1.414: 4, 2.0: 8, 2.828: 4, 4.0: 8, 5.657: 4}
+        v = p.views
+        blurred = np.nonzero(v["sigma"] > 0)[0]
+        for i in blurred:
+            assert v["blur_rows"][i] == want[round(float(v["p"]["t"][i]), 3)]
+        assert (v["blur_rows"][v["sigma"] == 0] == 0).all()
+        bp = np.frombuffer(p.blob, np.int32, len(blurred) + 1, int(p.header["off_blur_prefix"]))
+        for j, i in enumerate(blurred):
+            r = int(v["blur_rows"][i])
+            tw, th = (64, 4 * r) if v["blur_major"][i] == 0 else (4 * r, 64)
+            assert bp[j + 1] - bp[j] == -(-int(v["src_w"][i]) // tw) * -(-int(v["src_h"][i]) // th)
+        for bad in ([2] + [0] * 7, [0] * 7 + [16]):
+            with pytest.raises(X.XAError):
+                X.set_blur_rows(bad)
+        assert (before.views["blur_rows"][before.views["sigma"] > 0] == 8).all()
+    finally:
+        X.set_blur_rows(None)
+    assert X.get_blur_rows().tolist() == [8] * 8
+    assert X.lib().xa_tune_blur_rows_workspace_size(8, 8) == 0
+    assert X.lib().xa_tune_blur_rows_workspace_size(1024, 768) > 1024 * 768
