@@ -543,7 +543,7 @@ def _plain_per_view_run(X, batch, pv, pattern, k):
         q = base + i * nb
         X._check(L.xa_match_views(X._ptr(desc[a0 + i]), X._ptr(count[a0 + i:a0 + i + 1]), 1, X._ptr(desc[b0]),
                                   X._ptr(count[b0:b0 + nb]), nb, N, 4, 5, X._ptr(pv["matches"][q]),
-                                  X._ptr(pv["pair_count"][q:q + nb]), X._ptr(pv["best"]), None, 0, st))
+                                  X._ptr(pv["pair_count"][q:q + nb]), X._ptr(pv["best"]), st))
 
 
 def sweep_leg(args, dev, pattern):
@@ -881,14 +881,11 @@ def main():
     st = X.StageRunner(pa, pb, dev)
     L = X.lib()
 
-    ops_ws = X._empty(X.match_operands_size(run.n_views, run.mplan.n_features), dev)
-
     def match_stage():
-        # the matcher exactly as the timed step runs it: the batch's match plan on its descriptors,
-        # every view's operands expanded once
+        # the matcher exactly as the timed step runs it: the batch's match plan on its descriptors
         X._check(L.xa_match_groups(run.mplan.host_ptr(), X._ptr(run.mplan.device(dev)), X._ptr(run.desc),
                                    X._ptr(run.count), run.n_views, 4, 5, X._ptr(run.matches), X._ptr(run.pair_count),
-                                   X._ptr(run.best), X._ptr(ops_ws), ops_ws.numel(), X._stream()))
+                                   X._ptr(run.best), X._stream()))
 
     stages = {"simulate": lambda: (st.simulate("a", A), st.simulate("b", B)),
               "extract": lambda: (st.extract("a", pattern), st.extract("b", pattern)),
@@ -910,8 +907,7 @@ def main():
     torch.cuda.synchronize()
     assert torch.equal(st.pair_count, run.pair_count), "stage-by-stage run disagrees with the batched entry"
 
-    # the matcher (xa_match_groups = a counter fill, the operand expansion, the matching kernel, a
-    # one-block argmax per group)
+    # the matcher (xa_match_groups = a counter fill, the matching kernel, a one-block argmax per group)
     match_s = stage_ms["match"] / 1e3
     # descriptor sets read once + the match records and counts written
     n_pairs = pa.n_views * pb.n_views

@@ -351,19 +351,12 @@ xa_status xa_extract_orb(const void* plan_host, const void* plan_dev,
  * of B (train), Sec. III.B, with the ratio test of Sec. IV.C evaluated exactly
  * as ratio_den * d1 < ratio_num * d2 (and at least two train descriptors).
  * d_matches: [n_a * n_b][n_features]; d_pair_count: [n_a * n_b]; d_best: [4]
- * (see xa_pair_buffers).
- * Operand workspace (optional; the results are the same either way): d_ws = NULL makes
- * every block of the matrix-core matcher turn its train view's packed descriptors into
- * +-1 fp4 operands itself; a 256-byte aligned d_ws of xa_match_operands_size(n_a + n_b,
- * n_features) bytes (XA_ECAPACITY if smaller) lets one extra launch expand every view
- * once (4 KiB per 32 descriptors, 4x the descriptors' bytes) and the matcher stream them
- * into LDS.  Its contents are scratch, rewritten by each call. */
-size_t xa_match_operands_size(int32_t n_views, int32_t n_features);
+ * (see xa_pair_buffers).  No workspace. */
 xa_status xa_match_views(const uint8_t* d_desc_a, const int32_t* d_count_a, int32_t n_a,
                          const uint8_t* d_desc_b, const int32_t* d_count_b, int32_t n_b,
                          int32_t n_features, int32_t ratio_num, int32_t ratio_den,
                          xa_match* d_matches, int32_t* d_pair_count, int32_t* d_best,
-                         void* d_ws, size_t ws_bytes, hipStream_t stream);
+                         hipStream_t stream);
 
 /* The brute-force Hamming matching of Sec. III.B with the ratio test of Sec. IV.C (as in
  * xa_match_views), over groups of view pairs, for many image pairs in one launch: group
@@ -381,10 +374,7 @@ xa_status xa_match_views(const uint8_t* d_desc_a, const int32_t* d_count_a, int3
  * matrix-core kernel), 1, 2 or 4 = the vector-ALU popcount kernel with that many queries
  * per lane, XA_MATCH_MATRIX = the matrix-core kernel (the +-1 dot product of two
  * descriptors is 256 - 2 x their Hamming distance, contracted exactly in fp4 on
- * MFMA).  Match plans are blobs like view plans (host and device copies).  d_ws / ws_bytes:
- * the optional operand workspace of xa_match_views, here xa_match_operands_size(n_views,
- * n_features) bytes (the plan's largest view index bounds what is used); the popcount
- * variants ignore it. */
+ * MFMA).  Match plans are blobs like view plans (host and device copies). */
 #define XA_MATCH_MATRIX (-1)
 typedef struct {
     int32_t a0, na;
@@ -395,14 +385,13 @@ xa_status xa_plan_matches(const xa_match_group* groups, int32_t n_groups, int32_
                           void* blob, size_t blob_cap, size_t* blob_bytes);
 xa_status xa_match_groups(const void* mplan_host, const void* mplan_dev, const uint8_t* d_desc, const int32_t* d_count,
                           int32_t n_views, int32_t ratio_num, int32_t ratio_den, xa_match* d_matches,
-                          int32_t* d_pair_count, int32_t* d_best, void* d_ws, size_t ws_bytes, hipStream_t stream);
+                          int32_t* d_pair_count, int32_t* d_best, hipStream_t stream);
 
 /* The matcher's autotuner: every variant (1, 2, 4 queries per lane, XA_MATCH_MATRIX) runs the
  * given groups on the given descriptor set (d_desc, d_count, n_views as for xa_match_groups),
  * once untimed and `reps` times timed with HIP events; *best_variant gets the fastest (ms[4],
  * if not NULL, the mean times in milliseconds, in the order above).  Every variant's results are
- * the same; d_matches, d_pair_count and d_best receive them (sized as for xa_match_groups; the
- * matrix-core variant runs without an operand workspace).  The
+ * the same; d_matches, d_pair_count and d_best receive them (sized as for xa_match_groups).  The
  * workspace holds the plans' device copies: xa_tune_matcher_workspace_size(groups, n_groups,
  * n_features) bytes, 256-byte aligned.  The library keeps each result per device, keyed by the
  * group table, n_features and the per-view counts (read from d_count); with XA_TUNE_USE_CACHE in
@@ -521,8 +510,7 @@ xa_status xa_sift_match_points(const xa_sift_keypoint* d_kp_q, const xa_sift_key
  * Sec. IV.C): simulate both images, extract ORB on every view, match all view pairs, pick the
  * best pair (the paper's single-target search is the case of plan B holding one identity view).
  * Both plans must use the same n_features.  Workspace:
- * xa_match_pair_workspace_size(plan_a_host, plan_b_host) (it includes the matcher's operand
- * workspace for both images' views). */
+ * xa_match_pair_workspace_size(plan_a_host, plan_b_host). */
 size_t xa_match_pair_workspace_size(const void* plan_a_host, const void* plan_b_host);
 xa_status xa_match_pair(const void* plan_a_host, const void* plan_a_dev, const uint8_t* d_a,
                         const void* plan_b_host, const void* plan_b_dev, const uint8_t* d_b,
@@ -548,8 +536,7 @@ xa_status xa_match_pair(const void* plan_a_host, const void* plan_a_dev, const u
  * xa_graph_launch replays on any stream; the graph keeps every pointer it was
  * captured with, and the host plan blobs need not outlive the capture.
  * Workspace: xa_match_batch_workspace_size(splan_host, n_chunks, vplan_hosts)
- * (0 for invalid plans); beside the largest chunk's scratch it holds the matcher's operand
- * workspace for every view of the batch. */
+ * (0 for invalid plans). */
 typedef struct {
     xa_keypoint* kp; uint8_t* desc; int32_t* count;
     xa_match* matches; int32_t* pair_count; int32_t* best;

@@ -213,17 +213,12 @@ struct MatchPlanView {
     const MatchPlanHeader* h = nullptr;
 };
 xa_status match_plan_view(const void* blob, MatchPlanView* out);
-// Bytes of matrix-core operands for n_views descriptor sets of N each (4 KiB per 32 descriptors).
-size_t expanded_bytes(long long n_views, int N);
-// ex (nullable): expanded_bytes(views_needed, n_features) of scratch; with it a matrix-core
-// plan expands every view's operands once instead of once per block.
 xa_status launch_match_plan(const void* mplan_host, const void* mplan_dev, const uint8_t* desc, const int32_t* count,
                             int32_t num, int32_t den, xa_match* matches, int32_t* pair_count, int32_t* best,
-                            uint8_t* ex, hipStream_t st);
-// ex_a / ex_b (both or neither): expanded_bytes(n_a, N) and expanded_bytes(n_b, N) of scratch.
+                            hipStream_t st);
 xa_status launch_match(const uint8_t* desc_a, const int32_t* count_a, int32_t n_a,
                        const uint8_t* desc_b, const int32_t* count_b, int32_t n_b, int32_t n_features,
                        int32_t num, int32_t den, xa_match* matches, int32_t* pair_count, int32_t* best,
-                       uint8_t* ex_a, uint8_t* ex_b, hipStream_t st);
+                       hipStream_t st);
 
 }  // namespace xa

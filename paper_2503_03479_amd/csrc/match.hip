@@ -188,60 +188,39 @@ __device__ __forceinline__ v8i_t operand(uint4 u) {
     return v;
 }
 
-// Operands of every view, expanded once: view v, tile t of 32 descriptors, slice s and lane l
-// hold word_pm1 of word 2 s + l / 32 of descriptor 32 t + l % 32 at uint4 index
-// ((v T + t) 4 + s) 64 + l, T = ceil(N / 32): a tile is 4 KiB laid out exactly as the
-// matcher's LDS and its query registers want it.  Descriptors at or past the view's count
-// get zero operands.  Block = one tile of one view.
-__global__ void __launch_bounds__(256) k_expand_operands(const uint32_t* __restrict__ desc,
-                                                          const int32_t* __restrict__ count, int N, int T,
-                                                          uint4* __restrict__ ex) {
-    const int v = blockIdx.x / T, tile = blockIdx.x - (blockIdx.x / T) * T;
-    const int lane = threadIdx.x & 63, sl = threadIdx.x >> 6;
-    const int row = tile * 32 + (lane & 31), k = 2 * sl + (lane >> 5);
-    const int n = min(max(count[v], 0), N);
-    ex[size_t(blockIdx.x) * 256 + threadIdx.x] =
-        row < n ? word_pm1(desc[(size_t(v) * N + row) * 8 + k]) : make_uint4(0, 0, 0, 0);
+// The hardware deals a grid's blocks to the 8 XCDs round robin (block b runs on XCD b % 8).
+// XCD x takes the contiguous logical range that starts at x (B / 8) + min(x, B % 8), so the
+// blocks that share an L2 are neighbours in the logical order (a bijection of [0, B)).
+__device__ __forceinline__ int xcd_block(int b, int B) {
+    const int q = B >> 3, r = B & 7, x = b & 7;
+    return x * q + min(x, r) + (b >> 3);
 }
 
-// Copy ntile expanded tiles from global memory into LDS with direct-to-LDS loads (no
-// registers in between): wave w moves bytes [1 KiB w, 1 KiB (w + 1)) of every 4 KiB tile,
-// 16 bytes a lane.  The copy is complete once the issuing wave has waited for its vector
-// memory counter.
-__device__ __forceinline__ void stage_tiles(const uint4* src, uint4* dst, int ntile, int wv, int lane) {
-    for (int tt = 0; tt < ntile; ++tt)
-        __builtin_amdgcn_global_load_lds(src + tt * 256 + wv * 64 + lane, dst + tt * 256 + wv * 64, 16, 0, 0);
-}
-
-// Same block -> (group, view pair, query block) mapping and outputs as k_match.  The K
-// dimension is split alike for both operands: slice s of lane l is word 2 s + l / 32 of
-// descriptor (tile row or column) l % 32, so the contraction pairs equal bits whatever
-// order the hardware gives the 64 values of a slice.  PRE = false expands the packed
-// descriptors itself (each block re-expands its train view); PRE = true reads operands
-// that k_expand_operands laid out (xq, xt, T tiles a view, counts equal to the ones the
-// expansion saw) and double-buffers the train chunks through LDS.
-template <bool PRE>
+// Same (group, view pair, query block) blocks and outputs as k_match, visited in another
+// order: blocks run through the XCD mapping above, and within a group the view pairs run
+// train-view-major, so an XCD works on a few train views at a time (its L2 then holds
+// them).  The K dimension is split alike for both operands: slice s of lane l is word
+// 2 s + l / 32 of descriptor (tile row or column) l % 32, so the contraction pairs equal
+// bits whatever order the hardware gives the 64 values of a slice.
 __global__ void __launch_bounds__(kMxThreads) __attribute__((amdgpu_waves_per_eu(3)))
 k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ count_q, const uint32_t* __restrict__ desc_t,
-           const int32_t* __restrict__ count_t, const uint4* __restrict__ xq, const uint4* __restrict__ xt, int T,
-           const xa_match_group* __restrict__ groups, const int32_t* __restrict__ block_prefix, int n_groups,
-           xa_match_group one, int qblocks, int N, int num, int den, xa_match* __restrict__ matches,
-           int32_t* __restrict__ pair_count) {
-    // [buffer][tile of 32][slice][lane] operands of one chunk of train descriptors
-    constexpr int kChunk = PRE ? kMxChunk / 2 : kMxChunk;   // two buffers of half the size (PRE)
-    constexpr int kBuf = (kChunk / 32) * 4 * 64;
-    __shared__ uint4 tr[(PRE ? 2 : 1) * kBuf];
+           const int32_t* __restrict__ count_t, const xa_match_group* __restrict__ groups,
+           const int32_t* __restrict__ block_prefix, int n_groups, xa_match_group one, int qblocks, int N, int num,
+           int den, xa_match* __restrict__ matches, int32_t* __restrict__ pair_count) {
+    // [tile of 32][slice][lane] operands of one chunk of train descriptors
+    __shared__ uint4 tr[(kMxChunk / 32) * 4 * 64];
     __shared__ int s_acc;
+    const int L = xcd_block(blockIdx.x, gridDim.x);
     xa_match_group G = one;
-    int local = blockIdx.x;
+    int local = L;
     if (groups) {
-        const int gi = find_segment_wave(block_prefix, n_groups, blockIdx.x);
+        const int gi = find_segment_wave(block_prefix, n_groups, L);
         G = groups[gi];
-        local = blockIdx.x - block_prefix[gi];
+        local = L - block_prefix[gi];
     }
     const int qb = local % qblocks, pr = local / qblocks;
-    const int i = pr / G.nb, j = pr - (pr / G.nb) * G.nb;
-    const long long pair = G.pair_base + pr;
+    const int j = pr / G.na, i = pr - (pr / G.na) * G.na;
+    const long long pair = G.pair_base + (long long)i * G.nb + j;
     const int va = G.a0 + i, vb = G.b0 + j;
     const int nq = min(max(count_q[va], 0), N), nt = min(max(count_t[vb], 0), N);
     const int q0 = qb * kMxBlockQ;
@@ -249,21 +228,13 @@ k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ coun
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, h = lane >> 5, m = lane & 31;
     const int qw0 = q0 + wv * 32 * kMxQT;                     // this wave's first query
     const int nqt = min(max((nq - qw0 + 31) >> 5, 0), kMxQT);  // its 32-query tiles holding queries
-    const uint4* xtv = xt + size_t(vb) * T * 256;                  // this pair's train view (PRE)
-    if (PRE && nt > 0) stage_tiles(xtv, tr, (min(kChunk, nt) + 31) >> 5, wv, lane);
     uint4 B[kMxQT][4];
 #pragma unroll
     for (int qt = 0; qt < kMxQT; ++qt) {
-        if (PRE) {
-            const uint4* p = xq + (size_t(va) * T + (qw0 >> 5) + qt) * 256 + lane;
+        const int qi = qw0 + qt * 32 + m;
+        const uint32_t* p = desc_q + (size_t(va) * N + qi) * 8;
 #pragma unroll
-            for (int sl = 0; sl < 4; ++sl) B[qt][sl] = qt < nqt ? p[sl * 64] : make_uint4(0, 0, 0, 0);
-        } else {
-            const int qi = qw0 + qt * 32 + m;
-            const uint32_t* p = desc_q + (size_t(va) * N + qi) * 8;
-#pragma unroll
-            for (int sl = 0; sl < 4; ++sl) B[qt][sl] = word_pm1(qi < nq ? p[2 * sl + h] : 0u);
-        }
+        for (int sl = 0; sl < 4; ++sl) B[qt][sl] = word_pm1(qi < nq ? p[2 * sl + h] : 0u);
     }
     uint32_t m1[kMxQT], m2[kMxQT];
 #pragma unroll
@@ -274,34 +245,23 @@ k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ coun
     for (int r = 0; r < 16; ++r) f0[r] = 512.0f + float(16383 - (8 * (r >> 2) + 4 * h + (r & 3))) * (1.0f / 16384.0f);
     const uint4* tb = reinterpret_cast<const uint4*>(desc_t + size_t(vb) * N * 8);
     uint4 n0 = make_uint4(0, 0, 0, 0), n1 = n0;                // next chunk's descriptor of this thread
-    if (!PRE && int(threadIdx.x) < nt) { n0 = tb[2 * threadIdx.x]; n1 = tb[2 * threadIdx.x + 1]; }
-    for (int c0 = 0, buf = 0; c0 < nt; c0 += kChunk, buf ^= 1) {
-        const int cn = min(kChunk, nt - c0);
-        const uint4* trb = tr + (PRE ? buf * kBuf : 0);
-        if (PRE) {
-            // chunk c0 has landed in buffer buf once every wave has waited for its own
-            // copies; past the barrier every wave has also left buffer buf ^ 1, which
-            // then takes the next chunk while this one is contracted
-            __builtin_amdgcn_s_waitcnt(0);
-            __syncthreads();
-            const int nx = c0 + kChunk;
-            if (nx < nt) stage_tiles(xtv + (nx >> 5) * 256, tr + (buf ^ 1) * kBuf, (min(kChunk, nt - nx) + 31) >> 5, wv, lane);
-        } else {
-            __syncthreads();
-            {   // expand this thread's descriptor (chunk row t) into its 8 operand slots; rows
-                // past the train count get zero operands
-                const int t = threadIdx.x, tt = t >> 5, tm = t & 31;
-                const bool live = t < cn;
-                const uint32_t w[8] = {n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, n1.z, n1.w};
+    if (int(threadIdx.x) < nt) { n0 = tb[2 * threadIdx.x]; n1 = tb[2 * threadIdx.x + 1]; }
+    for (int c0 = 0; c0 < nt; c0 += kMxChunk) {
+        const int cn = min(kMxChunk, nt - c0);
+        __syncthreads();
+        {   // expand this thread's descriptor (chunk row t) into its 8 operand slots; rows
+            // past the train count get zero operands
+            const int t = threadIdx.x, tt = t >> 5, tm = t & 31;
+            const bool live = t < cn;
+            const uint32_t w[8] = {n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, n1.z, n1.w};
 #pragma unroll
-                for (int k = 0; k < 8; ++k)
-                    tr[(tt * 4 + (k >> 1)) * 64 + (k & 1) * 32 + tm] = live ? word_pm1(w[k]) : make_uint4(0, 0, 0, 0);
-            }
-            __syncthreads();
-            {
-                const int nx = c0 + kMxChunk + int(threadIdx.x);
-                if (nx < nt) { n0 = tb[2 * size_t(nx)]; n1 = tb[2 * size_t(nx) + 1]; }
-            }
+            for (int k = 0; k < 8; ++k)
+                tr[(tt * 4 + (k >> 1)) * 64 + (k & 1) * 32 + tm] = live ? word_pm1(w[k]) : make_uint4(0, 0, 0, 0);
+        }
+        __syncthreads();
+        {
+            const int nx = c0 + kMxChunk + int(threadIdx.x);
+            if (nx < nt) { n0 = tb[2 * size_t(nx)]; n1 = tb[2 * size_t(nx) + 1]; }
         }
         if (nqt == 0) continue;
         // keys are positive floats, whose order is their bit patterns' order.  Per pair
@@ -323,7 +283,7 @@ k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ coun
         // one tile of 32 train descriptors against the wave's query tiles (tiles past nq
         // compute unused columns)
         auto contract = [&](int tt, const v16f_t& ci) {
-            const uint4* a = trb + tt * 4 * 64 + lane;
+            const uint4* a = tr + tt * 4 * 64 + lane;
             const v8i_t A0 = operand(a[0]), A1 = operand(a[64]), A2 = operand(a[128]), A3 = operand(a[192]);
             // each chain, then its updates
 #pragma unroll
@@ -476,23 +436,8 @@ static int pick_q(int) { return XA_MATCH_MATRIX; }
 // queries one block of matcher variant Q owns (Q = XA_MATCH_MATRIX: the matrix-core kernel)
 static int block_queries(int Q) { return Q == XA_MATCH_MATRIX ? kMxBlockQ : kMatchThreads * Q; }
 
-size_t expanded_bytes(long long n_views, int N) { return size_t(n_views) * size_t((N + 31) / 32) * 4096; }
-
-xa_status launch_expand(const uint8_t* desc, const int32_t* count, int n_views, int N, uint8_t* ex, hipStream_t st) {
-    const long long blocks = (long long)n_views * ((N + 31) / 32);
-    if (blocks > INT32_MAX) return fail(XA_EUNSUPPORTED, "too many views to expand");
-    if (blocks > 0)
-        hipLaunchKernelGGL(k_expand_operands, dim3(unsigned(blocks)), dim3(256), 0, st,
-                           reinterpret_cast<const uint32_t*>(desc), count, N, (N + 31) / 32, reinterpret_cast<uint4*>(ex));
-    const hipError_t e = hipGetLastError();
-    return e == hipSuccess ? XA_OK : hip_fail(e, "expand launch");
-}
-
-// ex_q / ex_t: operands launch_expand wrote for the query and train descriptor sets (both
-// or neither); with them the matrix-core variant reads those instead of expanding.
 xa_status launch_match_any(const uint8_t* desc_q, const int32_t* count_q, const uint8_t* desc_t,
-                           const int32_t* count_t, const uint8_t* ex_q, const uint8_t* ex_t,
-                           const xa_match_group* groups_dev, const int32_t* prefix_dev,
+                           const int32_t* count_t, const xa_match_group* groups_dev, const int32_t* prefix_dev,
                            int n_groups, const xa_match_group& one, long long total_pairs, long long total_blocks,
                            int N, int Q, int num, int den, xa_match* matches, int32_t* pair_count, int32_t* best,
                            hipStream_t st) {
@@ -504,17 +449,9 @@ xa_status launch_match_any(const uint8_t* desc_q, const int32_t* count_q, const 
     const uint32_t* dt = reinterpret_cast<const uint32_t*>(desc_t);
     const int qblocks = (N + block_queries(Q) - 1) / block_queries(Q);
     if (total_blocks > 0) {
-        const uint4* xq = reinterpret_cast<const uint4*>(ex_q);
-        const uint4* xt = reinterpret_cast<const uint4*>(ex_t);
-        const int T = (N + 31) / 32;
-        if (Q == XA_MATCH_MATRIX && xq && xt)
-            hipLaunchKernelGGL(k_match_mx<true>, dim3(unsigned(total_blocks)), dim3(kMxThreads), 0, st, dq, count_q,
-                               dt, count_t, xq, xt, T, groups_dev, prefix_dev, n_groups, one, qblocks, N, num, den,
-                               matches, pair_count);
-        else if (Q == XA_MATCH_MATRIX)
-            hipLaunchKernelGGL(k_match_mx<false>, dim3(unsigned(total_blocks)), dim3(kMxThreads), 0, st, dq, count_q,
-                               dt, count_t, xq, xt, T, groups_dev, prefix_dev, n_groups, one, qblocks, N, num, den,
-                               matches, pair_count);
+        if (Q == XA_MATCH_MATRIX)
+            hipLaunchKernelGGL(k_match_mx, dim3(unsigned(total_blocks)), dim3(kMxThreads), 0, st, dq, count_q, dt,
+                               count_t, groups_dev, prefix_dev, n_groups, one, qblocks, N, num, den, matches, pair_count);
         else if (Q == 4)
             hipLaunchKernelGGL(k_match<4>, dim3(unsigned(total_blocks)), dim3(kMatchThreads), 0, st, dq, count_q, dt,
                                count_t, groups_dev, prefix_dev, n_groups, one, qblocks, N, num, den, matches, pair_count);
@@ -533,20 +470,12 @@ xa_status launch_match_any(const uint8_t* desc_q, const int32_t* count_q, const 
 
 xa_status launch_match(const uint8_t* desc_a, const int32_t* count_a, int32_t n_a, const uint8_t* desc_b,
                        const int32_t* count_b, int32_t n_b, int32_t N, int32_t num, int32_t den, xa_match* matches,
-                       int32_t* pair_count, int32_t* best, uint8_t* ex_a, uint8_t* ex_b, hipStream_t st) {
+                       int32_t* pair_count, int32_t* best, hipStream_t st) {
     const int Q = pick_q(N);
     const int qblocks = (N + block_queries(Q) - 1) / block_queries(Q);
     const xa_match_group one{0, n_a, 0, n_b, 0};
-    if (Q == XA_MATCH_MATRIX && ex_a && ex_b) {
-        xa_status s = launch_expand(desc_a, count_a, n_a, N, ex_a, st);
-        if (s == XA_OK) s = launch_expand(desc_b, count_b, n_b, N, ex_b, st);
-        if (s != XA_OK) return s;
-    } else {
-        ex_a = ex_b = nullptr;
-    }
-    return launch_match_any(desc_a, count_a, desc_b, count_b, ex_a, ex_b, nullptr, nullptr, 1, one,
-                            (long long)n_a * n_b, (long long)n_a * n_b * qblocks, N, Q, num, den, matches, pair_count,
-                            best, st);
+    return launch_match_any(desc_a, count_a, desc_b, count_b, nullptr, nullptr, 1, one, (long long)n_a * n_b,
+                            (long long)n_a * n_b * qblocks, N, Q, num, den, matches, pair_count, best, st);
 }
 
 // ------------------------------------------------------------------ match plans
@@ -561,17 +490,11 @@ xa_status match_plan_view(const void* blob, MatchPlanView* out) {
 
 xa_status launch_match_plan(const void* mplan_host, const void* mplan_dev, const uint8_t* desc, const int32_t* count,
                             int32_t num, int32_t den, xa_match* matches, int32_t* pair_count, int32_t* best,
-                            uint8_t* ex, hipStream_t st) {
+                            hipStream_t st) {
     const auto* h = static_cast<const MatchPlanHeader*>(mplan_host);
     const char* d = static_cast<const char*>(mplan_dev);
     const xa_match_group one{0, 0, 0, 0, 0};
-    if (h->q == XA_MATCH_MATRIX && ex) {
-        const xa_status s = launch_expand(desc, count, h->views_needed, h->n_features, ex, st);
-        if (s != XA_OK) return s;
-    } else {
-        ex = nullptr;
-    }
-    return launch_match_any(desc, count, desc, count, ex, ex, reinterpret_cast<const xa_match_group*>(d + h->off_groups),
+    return launch_match_any(desc, count, desc, count, reinterpret_cast<const xa_match_group*>(d + h->off_groups),
                             reinterpret_cast<const int32_t*>(d + h->off_prefix), h->n_groups, one, h->total_pairs,
                             h->total_blocks, h->n_features, h->q, num, den, matches, pair_count, best, st);
 }
@@ -580,24 +503,10 @@ xa_status launch_match_plan(const void* mplan_host, const void* mplan_dev, const
 
 using namespace xa;
 
-extern "C" size_t xa_match_operands_size(int32_t n_views, int32_t n_features) {
-    if (n_views < 1 || n_features < 1 || n_features > XA_MAX_FEATURES) return 0;
-    return expanded_bytes(n_views, n_features);
-}
-
-// optional operand workspace of a matcher entry: NULL, or at least `need` bytes, 256-byte aligned
-static xa_status check_operands(const void* d_ws, size_t ws_bytes, size_t need) {
-    if (!d_ws) return XA_OK;
-    if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return fail(XA_EINVAL, "operand workspace must be 256-byte aligned");
-    if (ws_bytes < need) return fail(XA_ECAPACITY, "operand workspace needs %zu bytes, got %zu", need, ws_bytes);
-    return XA_OK;
-}
-
 extern "C" xa_status xa_match_views(const uint8_t* d_desc_a, const int32_t* d_count_a, int32_t n_a,
                                     const uint8_t* d_desc_b, const int32_t* d_count_b, int32_t n_b,
                                     int32_t n_features, int32_t ratio_num, int32_t ratio_den, xa_match* d_matches,
-                                    int32_t* d_pair_count, int32_t* d_best, void* d_ws, size_t ws_bytes,
-                                    hipStream_t stream) {
+                                    int32_t* d_pair_count, int32_t* d_best, hipStream_t stream) {
     if (n_a < 1 || n_b < 1 || int64_t(n_a) * n_b > (int64_t(1) << 30)) return fail(XA_EINVAL, "bad view counts");
     if (n_features < 1 || n_features > XA_MAX_FEATURES) return fail(XA_EUNSUPPORTED, "n_features out of range");
     if (ratio_num < 0 || ratio_den < 1 || ratio_num > (1 << 20) || ratio_den > (1 << 20))
@@ -606,12 +515,8 @@ extern "C" xa_status xa_match_views(const uint8_t* d_desc_a, const int32_t* d_co
         return fail(XA_EINVAL, "NULL device pointer");
     if ((reinterpret_cast<uintptr_t>(d_desc_a) | reinterpret_cast<uintptr_t>(d_desc_b)) % 16)
         return fail(XA_EINVAL, "descriptor arrays must be 16-byte aligned");
-    xa_status s = check_operands(d_ws, ws_bytes, expanded_bytes((long long)n_a + n_b, n_features));
-    if (s != XA_OK) return s;
-    uint8_t* ex_a = static_cast<uint8_t*>(d_ws);
-    uint8_t* ex_b = ex_a ? ex_a + expanded_bytes(n_a, n_features) : nullptr;
-    s = launch_match(d_desc_a, d_count_a, n_a, d_desc_b, d_count_b, n_b, n_features, ratio_num, ratio_den, d_matches,
-                     d_pair_count, d_best, ex_a, ex_b, stream);
+    xa_status s = launch_match(d_desc_a, d_count_a, n_a, d_desc_b, d_count_b, n_b, n_features, ratio_num, ratio_den,
+                               d_matches, d_pair_count, d_best, stream);
     return s == XA_OK ? ok() : s;
 }
 
@@ -688,8 +593,7 @@ extern "C" xa_status xa_plan_matches(const xa_match_group* groups, int32_t n_gro
 
 extern "C" xa_status xa_match_groups(const void* mplan_host, const void* mplan_dev, const uint8_t* d_desc,
                                      const int32_t* d_count, int32_t n_views, int32_t ratio_num, int32_t ratio_den,
-                                     xa_match* d_matches, int32_t* d_pair_count, int32_t* d_best, void* d_ws,
-                                     size_t ws_bytes, hipStream_t stream) {
+                                     xa_match* d_matches, int32_t* d_pair_count, int32_t* d_best, hipStream_t stream) {
     MatchPlanView mv;
     xa_status s = match_plan_view(mplan_host, &mv);
     if (s != XA_OK) return s;
@@ -700,10 +604,8 @@ extern "C" xa_status xa_match_groups(const void* mplan_host, const void* mplan_d
     if (reinterpret_cast<uintptr_t>(d_desc) % 16) return fail(XA_EINVAL, "descriptors must be 16-byte aligned");
     if (ratio_num < 0 || ratio_den < 1 || ratio_num > (1 << 20) || ratio_den > (1 << 20))
         return fail(XA_EINVAL, "ratio must be num/den with 0 <= num, 1 <= den <= 2^20");
-    s = check_operands(d_ws, ws_bytes, expanded_bytes(mv.h->views_needed, mv.h->n_features));
-    if (s != XA_OK) return s;
     s = launch_match_plan(mplan_host, mplan_dev, d_desc, d_count, ratio_num, ratio_den, d_matches, d_pair_count,
-                          d_best, static_cast<uint8_t*>(d_ws), stream);
+                          d_best, stream);
     return s == XA_OK ? ok() : s;
 }
 
@@ -786,12 +688,11 @@ extern "C" xa_status xa_tune_matcher(const xa_match_group* groups, int32_t n_gro
         e = hipMemcpyAsync(d_ws, blob.data(), bytes, hipMemcpyHostToDevice, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);     // the host blob goes out of scope below
         if (e != hipSuccess) { s = hip_fail(e, "plan upload"); break; }
-        s = xa_match_groups(blob.data(), d_ws, d_desc, d_count, n_views, 4, 5, d_matches, d_pair_count, d_best,
-                            nullptr, 0, stream);
+        s = xa_match_groups(blob.data(), d_ws, d_desc, d_count, n_views, 4, 5, d_matches, d_pair_count, d_best, stream);
         e = hipEventRecord(e0, stream);
         for (int r = 0; r < reps && s == XA_OK; ++r)
             s = xa_match_groups(blob.data(), d_ws, d_desc, d_count, n_views, 4, 5, d_matches, d_pair_count, d_best,
-                                nullptr, 0, stream);
+                                stream);
         if (e == hipSuccess) e = hipEventRecord(e1, stream);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float t = 0.0f;

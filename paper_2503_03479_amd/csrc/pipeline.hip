@@ -13,7 +13,7 @@ namespace xa {
 namespace {
 
 struct PairWs {
-    size_t arena_a, mask_a, sim_a, ext_a, arena_b, mask_b, sim_b, ext_b, ops_a, ops_b, total;
+    size_t arena_a, mask_a, sim_a, ext_a, arena_b, mask_b, sim_b, ext_b, total;
 };
 
 PairWs pair_layout(const xa_plan_header* a, const xa_plan_header* b) {
@@ -27,8 +27,6 @@ PairWs pair_layout(const xa_plan_header* a, const xa_plan_header* b) {
     w.mask_b = o;  o = align_up(o + size_t(b->arena_bytes));
     w.sim_b = o;   o = align_up(o + simulate_ws_bytes(b));
     w.ext_b = o;   o = align_up(o + extract_ws_layout(b).total);
-    w.ops_a = o;   o = align_up(o + expanded_bytes(a->n_views, a->n_features));
-    w.ops_b = o;   o = align_up(o + expanded_bytes(b->n_views, b->n_features));
     w.total = o;
     return w;
 }
@@ -78,8 +76,7 @@ extern "C" xa_status xa_match_pair(const void* plan_a_host, const void* plan_a_d
                        ws + w.ext_b, stream);
     if (s != XA_OK) return s;
     s = launch_match(out->desc_a, out->count_a, ha.h->n_views, out->desc_b, out->count_b, hb.h->n_views,
-                     ha.h->n_features, ratio_num, ratio_den, out->matches, out->pair_count, out->best, ws + w.ops_a,
-                     ws + w.ops_b, stream);
+                     ha.h->n_features, ratio_num, ratio_den, out->matches, out->pair_count, out->best, stream);
     return s == XA_OK ? ok() : s;
 }
 
@@ -89,19 +86,17 @@ namespace xa {
 namespace {
 
 struct BatchWs {
-    size_t scale, arena, mask, sim, ext, ops, total;
+    size_t scale, arena, mask, sim, ext, total;
 };
 
 // Scale-stage scratch, then one region per chunk buffer, each sized for the largest chunk:
 // the chunks run one after another and reuse it.
 BatchWs batch_layout(const void* splan_host, const PlanView* ph, int n_chunks) {
     size_t arena = 0, sim = 0, ext = 0;
-    long long views = 0;
     for (int c = 0; c < n_chunks; ++c) {
         arena = std::max(arena, size_t(ph[c].h->arena_bytes));
         sim = std::max(sim, simulate_ws_bytes(ph[c].h));
         ext = std::max(ext, extract_ws_layout(ph[c].h).total);
-        views += ph[c].h->n_views;
     }
     BatchWs w{};
     size_t o = 0;
@@ -110,7 +105,6 @@ BatchWs batch_layout(const void* splan_host, const PlanView* ph, int n_chunks) {
     w.mask = o;  o = align_up(o + arena);
     w.sim = o;   o = align_up(o + sim);
     w.ext = o;   o = align_up(o + ext);
-    w.ops = o;   o = align_up(o + expanded_bytes(views, ph[0].h->n_features));   // every view's matcher operands
     w.total = o;
     return w;
 }
@@ -188,7 +182,7 @@ xa_status batch_launch(const BatchArgs& a, const std::vector<PlanView>& ph, cons
         v0 += size_t(ph[c].h->n_views);
     }
     return launch_match_plan(a.mplan_host, a.mplan_dev, a.out.desc, a.out.count, a.num, a.den, a.out.matches,
-                             a.out.pair_count, a.out.best, a.ws + w.ops, st);
+                             a.out.pair_count, a.out.best, st);
 }
 
 }  // namespace

@@ -93,15 +93,13 @@ _SIGS = {
     "xa_extract_workspace_size": (_c.c_size_t, [_c.c_void_p]),
     "xa_extract_orb": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                   _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
-    "xa_match_operands_size": (_c.c_size_t, [_c.c_int32, _c.c_int32]),
     "xa_match_views": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_int32,
                                   _c.c_int32, _c.c_int32, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p,
-                                  _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+                                  _c.c_void_p]),
     "xa_plan_matches": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_void_p, _c.c_size_t,
                                    _c.POINTER(_c.c_size_t)]),
     "xa_match_groups": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_int32,
-                                   _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_size_t,
-                                   _c.c_void_p]),
+                                   _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p]),
     "xa_match_l2_workspace_size": (_c.c_size_t, [_c.c_int32, _c.c_int32]),
     "xa_match_l2": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_void_p,
                                _c.c_void_p, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
@@ -545,14 +543,8 @@ def extract_orb(plan: Plan, arena, mask, pattern, ws=None):
     return kp, desc, count
 
 
-def match_operands_size(n_views: int, n_features: int) -> int:
-    """Bytes of the matcher's optional operand workspace for n_views views (0 for bad sizes)."""
-    return int(lib().xa_match_operands_size(n_views, n_features))
-
-
-def match_views(desc_a, count_a, desc_b, count_b, ratio_num: int = 4, ratio_den: int = 5, expand: bool = False):
-    """All-pairs matching.  Returns (matches u8[n_a*n_b, N, 8], pair_count i32[n_a*n_b], best i32[4]).
-    expand=True passes an operand workspace (every view's operands expanded once)."""
+def match_views(desc_a, count_a, desc_b, count_b, ratio_num: int = 4, ratio_den: int = 5):
+    """All-pairs matching.  Returns (matches u8[n_a*n_b, N, 8], pair_count i32[n_a*n_b], best i32[4])."""
     import torch
     dev = desc_a.device
     n_a, N = desc_a.shape[0], desc_a.shape[1]
@@ -560,11 +552,8 @@ def match_views(desc_a, count_a, desc_b, count_b, ratio_num: int = 4, ratio_den:
     matches = torch.zeros((n_a * n_b, N, MATCH_DTYPE.itemsize), dtype=torch.uint8, device=dev)
     pair_count = torch.zeros(n_a * n_b, dtype=torch.int32, device=dev)
     best = torch.zeros(4, dtype=torch.int32, device=dev)
-    ws = _empty(match_operands_size(n_a + n_b, N), dev) if expand else None
     _check(lib().xa_match_views(_ptr(desc_a), _ptr(count_a), n_a, _ptr(desc_b), _ptr(count_b), n_b, N, ratio_num,
-                                ratio_den, _ptr(matches), _ptr(pair_count), _ptr(best),
-                                _ptr(ws) if ws is not None else None, ws.numel() if ws is not None else 0,
-                                _stream()))
+                                ratio_den, _ptr(matches), _ptr(pair_count), _ptr(best), _stream()))
     return matches, pair_count, best
 
 
@@ -737,7 +726,6 @@ class StageRunner:
                 count=torch.zeros(p.n_views, dtype=torch.int32, device=self.device))
         n_pairs = plan_a.n_views * plan_b.n_views
         self.matches = torch.zeros((n_pairs, plan_a.n_features, 8), dtype=torch.uint8, device=self.device)
-        self.ops_ws = _empty(match_operands_size(plan_a.n_views + plan_b.n_views, plan_a.n_features), self.device)
         self.pair_count = torch.zeros(n_pairs, dtype=torch.int32, device=self.device)
         self.best = torch.zeros(4, dtype=torch.int32, device=self.device)
 
@@ -759,7 +747,7 @@ class StageRunner:
         _check(lib().xa_match_views(_ptr(a["desc"]), _ptr(a["count"]), self.plan_a.n_views, _ptr(b["desc"]),
                                     _ptr(b["count"]), self.plan_b.n_views, self.plan_a.n_features, ratio_num,
                                     ratio_den, _ptr(self.matches), _ptr(self.pair_count), _ptr(self.best),
-                                    _ptr(self.ops_ws), self.ops_ws.numel(), _stream()))
+                                    _stream()))
 
 
 # ---------------------------------------------------------------- match plans and batches
@@ -843,20 +831,16 @@ def autotune_queries_per_lane(groups, n_features: int, device="cuda", desc=None,
                                  ctypes.byref(best_q), ms.ctypes.data))
     return int(best_q.value), {q: float(t) for q, t in zip(MATCH_VARIANTS, ms)}
 
-def match_groups(mplan: MatchPlan, desc, count, ratio_num: int = 4, ratio_den: int = 5, expand: bool = False):
-    """Group matching over one descriptor set.  Returns (matches u8[P, N, 8], pair_count i32[P], best i32[G, 4]).
-    expand=True passes an operand workspace (every view's operands expanded once)."""
+def match_groups(mplan: MatchPlan, desc, count, ratio_num: int = 4, ratio_den: int = 5):
+    """Group matching over one descriptor set.  Returns (matches u8[P, N, 8], pair_count i32[P], best i32[G, 4])."""
     import torch
     dev = desc.device
     P, N, G = mplan.total_pairs, mplan.n_features, len(mplan.groups)
     matches = torch.zeros((P, N, 8), dtype=torch.uint8, device=dev)
     pc = torch.zeros(P, dtype=torch.int32, device=dev)
     best = torch.zeros((G, 4), dtype=torch.int32, device=dev)
-    ws = _empty(match_operands_size(count.numel(), N), dev) if expand else None
     _check(lib().xa_match_groups(mplan.host_ptr(), _ptr(mplan.device(dev)), _ptr(desc), _ptr(count), count.numel(),
-                                 ratio_num, ratio_den, _ptr(matches), _ptr(pc), _ptr(best),
-                                 _ptr(ws) if ws is not None else None, ws.numel() if ws is not None else 0,
-                                 _stream()))
+                                 ratio_num, ratio_den, _ptr(matches), _ptr(pc), _ptr(best), _stream()))
     return matches, pc, best
 
 

@@ -44,11 +44,9 @@ def pairs():
     return out
 
 
-@pytest.mark.parametrize("expand", [False, True])
 @pytest.mark.parametrize("q", [0, X.MATCH_MATRIX])
-def test_match_groups_exact_random(dev, q, expand):
-    say(f"case: group matching of random descriptors, 4 groups with ragged sizes and an empty one (variant {q}, "
-        f"operand workspace {expand})")
+def test_match_groups_exact_random(dev, q):
+    say(f"case: group matching of random descriptors, 4 groups with ragged sizes and an empty one (variant {q})")
     g = np.random.default_rng(31)
     N = 600
     sizes = [300, 17, 0, 600, 1, 256, 599, 64, 2, 450]
@@ -64,7 +62,7 @@ def test_match_groups_exact_random(dev, q, expand):
     groups = [(0, 3, 3, 4, 0), (5, 2, 0, 5, 12), (9, 0, 1, 3, 22), (2, 4, 6, 4, 22)]
     mp = X.plan_matches(np.array(groups, X.GROUP_DTYPE), N, q)
     t = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
-    m, pc, best = X.match_groups(mp, t(D), t(C), expand=expand)
+    m, pc, best = X.match_groups(mp, t(D), t(C))
     torch.cuda.synchronize()
     m, pc, best = X.matches_np(m), pc.cpu().numpy(), best.cpu().numpy()
     for gi, (a0, na, b0, nb, base) in enumerate(groups):
@@ -78,11 +76,10 @@ def test_match_groups_exact_random(dev, q, expand):
     say(f"[groups] exact on 4 groups, best {best.tolist()}")
 
 
-@pytest.mark.parametrize("expand", [False, True])
 @pytest.mark.parametrize("q", X.MATCH_VARIANTS)
-def test_match_groups_variants_agree(dev, q, expand):
+def test_match_groups_variants_agree(dev, q):
     say(f"case: group matching, queries_per_lane={q} equals the oracle at N=1100 (duplicate train rows: "
-        f"equal distances go to the lowest index), operand workspace {expand}")
+        "equal distances go to the lowest index)")
     g = np.random.default_rng(32 + q)
     N = 1100
     sizes = [1100, 1099, 513, 0, 1024]
@@ -102,7 +99,7 @@ def test_match_groups_variants_agree(dev, q, expand):
     groups = [(0, 2, 2, 3, 0), (4, 1, 0, 2, 6)]
     mp = X.plan_matches(np.array(groups, X.GROUP_DTYPE), N, q)
     t = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
-    m, pc, best = X.match_groups(mp, t(D), t(np.array(sizes, np.int32)), expand=expand)
+    m, pc, best = X.match_groups(mp, t(D), t(np.array(sizes, np.int32)))
     torch.cuda.synchronize()
     m, pc, best = X.matches_np(m), pc.cpu().numpy(), best.cpu().numpy()
     for gi, (a0, na, b0, nb, base) in enumerate(groups):

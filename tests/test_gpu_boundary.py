@@ -37,6 +37,6 @@ def test_check_healthy_stream(dev):
     assert L.xa_check(X._stream()) == X.XA_OK
     torch.cuda.synchronize()
     assert L.xa_check(X._stream()) == X.XA_OK and L.xa_check(None) == X.XA_OK
-    assert L.xa_match_views(256, 256, 0, 256, 256, 1, 100, 4, 5, 256, 256, 256, None, 0, None) == X.XA_EINVAL
+    assert L.xa_match_views(256, 256, 0, 256, 256, 1, 100, 4, 5, 256, 256, 256, None) == X.XA_EINVAL
     assert L.xa_check(X._stream()) == X.XA_OK
     assert int(run.best[3].item()) > 0

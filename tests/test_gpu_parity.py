@@ -282,27 +282,23 @@ def _pad_desc(feats, N):
 
 
 def _check_match(da, db, N, dev, label, num=4, den=5):
-    """Both matcher forms (operands expanded per block, and expanded once into a workspace)
-    against the oracle."""
     Da, Ca = _pad_desc(da, N)
     Db, Cb = _pad_desc(db, N)
     t = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
+    m, pc, best = X.match_views(t(Da), t(Ca), t(Db), t(Cb), num, den)
+    torch.cuda.synchronize()
+    m = X.matches_np(m)
+    pc = pc.cpu().numpy()
+    best = best.cpu().numpy()
     res, counts, rbest = OM.match_views(da, db, num, den)
-    for expand in (False, True):
-        say(f"[{label}] matcher, operand workspace: {expand}")
-        m, pc, best = X.match_views(t(Da), t(Ca), t(Db), t(Cb), num, den, expand=expand)
-        torch.cuda.synchronize()
-        m = X.matches_np(m)
-        pc = pc.cpu().numpy()
-        best = best.cpu().numpy()
-        for k, (idx, d1, d2, acc) in enumerate(res):
-            i, j = divmod(k, len(db))
-            nq = len(da[i])
-            assert np.array_equal(m[k][:nq]["t"], idx), (label, expand, k)
-            assert np.array_equal(m[k][:nq]["d1"], d1), (label, expand, k)
-            assert np.array_equal(m[k][:nq]["d2"], d2), (label, expand, k)
-        assert np.array_equal(pc, counts), (label, expand)
-        assert tuple(best.tolist()) == tuple(rbest), (label, expand, best, rbest)
+    for k, (idx, d1, d2, acc) in enumerate(res):
+        i, j = divmod(k, len(db))
+        nq = len(da[i])
+        assert np.array_equal(m[k][:nq]["t"], idx), (label, k)
+        assert np.array_equal(m[k][:nq]["d1"], d1), (label, k)
+        assert np.array_equal(m[k][:nq]["d2"], d2), (label, k)
+    assert np.array_equal(pc, counts), label
+    assert tuple(best.tolist()) == tuple(rbest), (label, best, rbest)
     say(f"[{label}] matching exact on {len(res)} view pairs, best {tuple(best.tolist())}")
 
 

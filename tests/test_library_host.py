@@ -136,12 +136,8 @@ def test_device_calls_validate_before_launch(L):
     # too-small workspace (non-NULL dummy pointers are never dereferenced on the host)
     st = L.xa_extract_orb(hp, hp, 256, 256, 256, 256, 256, 256, 256, 0, None)
     assert st == X.XA_ECAPACITY
-    assert L.xa_match_views(256, 256, 0, 256, 256, 1, 100, 4, 5, 256, 256, 256, None, 0, None) == X.XA_EINVAL
-    assert L.xa_match_views(256, 256, 1, 256, 256, 1, 100, 4, 0, 256, 256, 256, None, 0, None) == X.XA_EINVAL
-    # the matcher's operand workspace: misaligned, then one byte short of 3 views x 4 tiles x 4 KiB
-    need = L.xa_match_operands_size(3, 100)
-    assert L.xa_match_views(256, 256, 2, 256, 256, 1, 100, 4, 5, 256, 256, 256, 264, need, None) == X.XA_EINVAL
-    assert L.xa_match_views(256, 256, 2, 256, 256, 1, 100, 4, 5, 256, 256, 256, 256, need - 1, None) == X.XA_ECAPACITY
+    assert L.xa_match_views(256, 256, 0, 256, 256, 1, 100, 4, 5, 256, 256, 256, None) == X.XA_EINVAL
+    assert L.xa_match_views(256, 256, 1, 256, 256, 1, 100, 4, 0, 256, 256, 256, None) == X.XA_EINVAL
     # the two simulate stages: NULL pointers, a short workspace, a blob that is not a plan
     assert L.xa_blur_views(hp, hp, None, 256, 1 << 30, None) == X.XA_EINVAL
     assert L.xa_blur_views(hp, hp, 256, 256, 0, None) == X.XA_ECAPACITY
@@ -177,32 +173,10 @@ def test_match_plan_rules():
     X.plan_matches(np.array([(0, 0, 3, 4, 0), (7, 2, 0, 2, 0)], G), 500)
 
 
-def test_match_operands_size(L):
-    """4 KiB of +-1 fp4 operands per 32 descriptors (a partial last tile counts whole), per view."""
-    assert L.xa_match_operands_size(1, 1) == 4096
-    assert L.xa_match_operands_size(1, 32) == 4096 and L.xa_match_operands_size(1, 33) == 2 * 4096
-    assert L.xa_match_operands_size(90, 1000) == 90 * 32 * 4096
-    assert L.xa_match_operands_size(7, 4096) == 7 * 128 * 4096 == 7 * 4096 * 128
-    assert L.xa_match_operands_size(0, 100) == 0 and L.xa_match_operands_size(3, 0) == 0
-    assert L.xa_match_operands_size(3, 4097) == 0
-
-
-def test_match_groups_operand_workspace_rules():
-    """The plan's largest view bounds the operand workspace; a short one fails before any launch."""
-    mp = X.plan_matches(np.array([(0, 3, 3, 4, 0)], X.GROUP_DTYPE), 64)   # views 0..6
-    fake = ctypes.c_void_p(256)
-    need = X.lib().xa_match_operands_size(7, 64)
-    st = X.lib().xa_match_groups(mp.host_ptr(), fake, fake, fake, 9, 4, 5, fake, fake, fake, fake, need - 1, None)
-    assert st == X.XA_ECAPACITY and b"operand" in X.lib().xa_last_error()
-    st = X.lib().xa_match_groups(mp.host_ptr(), fake, fake, fake, 9, 4, 5, fake, fake, fake,
-                                 ctypes.c_void_p(384), need, None)
-    assert st == X.XA_EINVAL and b"aligned" in X.lib().xa_last_error()
-
-
 def test_match_groups_rejects_views_outside_the_set():
     mp = X.plan_matches(np.array([(0, 3, 3, 4, 0)], X.GROUP_DTYPE), 64)
     fake = ctypes.c_void_p(256)               # never dereferenced: the check comes first
-    st = X.lib().xa_match_groups(mp.host_ptr(), fake, fake, fake, 6, 4, 5, fake, fake, fake, None, 0, None)
+    st = X.lib().xa_match_groups(mp.host_ptr(), fake, fake, fake, 6, 4, 5, fake, fake, fake, None)
     assert st == -1 and b"views" in X.lib().xa_last_error()
 
 
@@ -317,7 +291,7 @@ def test_check_reports_runtime_state(L):
     else:
         assert st == X.XA_EHIP and "device" in msg
     # a host-rejected argument error leaves nothing pending for xa_check
-    assert L.xa_match_views(256, 256, 0, 256, 256, 1, 100, 4, 5, 256, 256, 256, None, 0, None) == X.XA_EINVAL
+    assert L.xa_match_views(256, 256, 0, 256, 256, 1, 100, 4, 5, 256, 256, 256, None) == X.XA_EINVAL
     assert L.xa_check(None) == st
 
 
