@@ -188,20 +188,10 @@ __device__ __forceinline__ v8i_t operand(uint4 u) {
     return v;
 }
 
-// The hardware deals a grid's blocks to the 8 XCDs round robin (block b runs on XCD b % 8).
-// XCD x takes the contiguous logical range that starts at x (B / 8) + min(x, B % 8), so the
-// blocks that share an L2 are neighbours in the logical order (a bijection of [0, B)).
-__device__ __forceinline__ int xcd_block(int b, int B) {
-    const int q = B >> 3, r = B & 7, x = b & 7;
-    return x * q + min(x, r) + (b >> 3);
-}
-
-// Same (group, view pair, query block) blocks and outputs as k_match, visited in another
-// order: blocks run through the XCD mapping above, and within a group the view pairs run
-// train-view-major, so an XCD works on a few train views at a time (its L2 then holds
-// them).  The K dimension is split alike for both operands: slice s of lane l is word
-// 2 s + l / 32 of descriptor (tile row or column) l % 32, so the contraction pairs equal
-// bits whatever order the hardware gives the 64 values of a slice.
+// Same block -> (group, view pair, query block) mapping and outputs as k_match.  The K
+// dimension is split alike for both operands: slice s of lane l is word 2 s + l / 32 of
+// descriptor (tile row or column) l % 32, so the contraction pairs equal bits whatever
+// order the hardware gives the 64 values of a slice.
 __global__ void __launch_bounds__(kMxThreads) __attribute__((amdgpu_waves_per_eu(3)))
 k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ count_q, const uint32_t* __restrict__ desc_t,
            const int32_t* __restrict__ count_t, const xa_match_group* __restrict__ groups,
@@ -210,28 +200,31 @@ k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ coun
     // [tile of 32][slice][lane] operands of one chunk of train descriptors
     __shared__ uint4 tr[(kMxChunk / 32) * 4 * 64];
     __shared__ int s_acc;
-    const int L = xcd_block(blockIdx.x, gridDim.x);
     xa_match_group G = one;
-    int local = L;
+    int local = blockIdx.x;
     if (groups) {
-        const int gi = find_segment_wave(block_prefix, n_groups, L);
+        const int gi = find_segment_wave(block_prefix, n_groups, blockIdx.x);
         G = groups[gi];
-        local = L - block_prefix[gi];
+        local = blockIdx.x - block_prefix[gi];
     }
     const int qb = local % qblocks, pr = local / qblocks;
-    const int j = pr / G.na, i = pr - (pr / G.na) * G.na;
-    const long long pair = G.pair_base + (long long)i * G.nb + j;
+    const int i = pr / G.nb, j = pr - (pr / G.nb) * G.nb;
+    const long long pair = G.pair_base + pr;
     const int va = G.a0 + i, vb = G.b0 + j;
     const int nq = min(max(count_q[va], 0), N), nt = min(max(count_t[vb], 0), N);
     const int q0 = qb * kMxBlockQ;
     if (q0 >= nq) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, h = lane >> 5, m = lane & 31;
-    const int qw0 = q0 + wv * 32 * kMxQT;                     // this wave's first query
-    const int nqt = min(max((nq - qw0 + 31) >> 5, 0), kMxQT);  // its 32-query tiles holding queries
+    // the block's 32-query tiles are dealt to the waves in turn (tile wv + 4 qt of the block
+    // is slot qt of wave wv), so a block that is partly filled keeps every SIMD busy; nqt =
+    // the wave's slots holding queries (the first nqt), and empty slots are skipped
+    const int btiles = min((nq - q0 + 31) >> 5, kMxQT * 4);
+    const int nqt = __builtin_amdgcn_readfirstlane(min(max((btiles - wv + 3) >> 2, 0), kMxQT));
+    auto query_of = [&](int qt) { return q0 + (wv + 4 * qt) * 32 + m; };
     uint4 B[kMxQT][4];
 #pragma unroll
     for (int qt = 0; qt < kMxQT; ++qt) {
-        const int qi = qw0 + qt * 32 + m;
+        const int qi = query_of(qt);
         const uint32_t* p = desc_q + (size_t(va) * N + qi) * 8;
 #pragma unroll
         for (int sl = 0; sl < 4; ++sl) B[qt][sl] = word_pm1(qi < nq ? p[2 * sl + h] : 0u);
@@ -280,14 +273,15 @@ k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ coun
                 m2[qt] = max(max(m2[qt], __float_as_uint(mid0)), __float_as_uint(mid1));
             }
         };
-        // one tile of 32 train descriptors against the wave's query tiles (tiles past nq
-        // compute unused columns)
+        // one tile of 32 train descriptors against the wave's query tiles (a partly filled
+        // tile computes unused columns)
         auto contract = [&](int tt, const v16f_t& ci) {
             const uint4* a = tr + tt * 4 * 64 + lane;
             const v8i_t A0 = operand(a[0]), A1 = operand(a[64]), A2 = operand(a[128]), A3 = operand(a[192]);
-            // each chain, then its updates
+            // each chain, then its updates (a slot past nqt holds no query)
 #pragma unroll
             for (int qt = 0; qt < kMxQT; ++qt) {
+                if (qt >= nqt) break;
                 v16f_t acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A0, operand(B[qt][0]), ci, 4, 4, 0, 127, 0, 127);
                 acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A1, operand(B[qt][1]), acc, 4, 4, 0, 127, 0, 127);
                 acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A2, operand(B[qt][2]), acc, 4, 4, 0, 127, 0, 127);
@@ -323,7 +317,7 @@ k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ coun
         const uint32_t o1 = __shfl_xor(m1[qt], 32), o2 = __shfl_xor(m2[qt], 32);
         const float b1 = __uint_as_float(max(m1[qt], o1));
         const float b2 = __uint_as_float(max(min(m1[qt], o1), max(m2[qt], o2)));
-        const int qi = qw0 + qt * 32 + m;
+        const int qi = query_of(qt);
         if (h != 0 || qi >= nq) continue;
         xa_match r;
         int d1 = 65535, d2 = 65535;
