@@ -188,10 +188,17 @@ __device__ __forceinline__ v8i_t operand(uint4 u) {
     return v;
 }
 
-// Same block -> (group, view pair, query block) mapping and outputs as k_match.  The K
-// dimension is split alike for both operands: slice s of lane l is word 2 s + l / 32 of
-// descriptor (tile row or column) l % 32, so the contraction pairs equal bits whatever
-// order the hardware gives the 64 values of a slice.
+// Blocks of one train view take the group's query tiles packed: the 32-query tiles of all its
+// query views, concatenated in view order, sixteen to a block, so views with few keypoints share
+// a block instead of each filling a block of its own with padding.  A group of more query views
+// than kMxPackViews (the prefix over them lives in LDS) keeps one query view per block.
+constexpr int kMxPackViews = 1024;
+
+// Outputs as k_match's.  Block mapping per group: packed, block local = b nb + j takes packed
+// tiles [16 b, 16 b + 16) against train view j (blocks past the group's tiles exit); otherwise
+// as k_match (view pair, then query block of 512).  The K dimension is split alike for both
+// operands: slice s of lane l is word 2 s + l / 32 of descriptor (tile row or column) l % 32,
+// so the contraction pairs equal bits whatever order the hardware gives the 64 values of a slice.
 __global__ void __launch_bounds__(kMxThreads) __attribute__((amdgpu_waves_per_eu(3)))
 k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ count_q, const uint32_t* __restrict__ desc_t,
            const int32_t* __restrict__ count_t, const xa_match_group* __restrict__ groups,
@@ -199,7 +206,8 @@ k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ coun
            int den, xa_match* __restrict__ matches, int32_t* __restrict__ pair_count) {
     // [tile of 32][slice][lane] operands of one chunk of train descriptors
     __shared__ uint4 tr[(kMxChunk / 32) * 4 * 64];
-    __shared__ int s_acc;
+    __shared__ int s_pre[kMxPackViews + 1];    // exclusive prefix of the query views' tiles
+    __shared__ int s_wsum[kMxThreads / 64];
     xa_match_group G = one;
     int local = blockIdx.x;
     if (groups) {
@@ -207,27 +215,90 @@ k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ coun
         G = groups[gi];
         local = blockIdx.x - block_prefix[gi];
     }
-    const int qb = local % qblocks, pr = local / qblocks;
-    const int i = pr / G.nb, j = pr - (pr / G.nb) * G.nb;
-    const long long pair = G.pair_base + pr;
-    const int va = G.a0 + i, vb = G.b0 + j;
-    const int nq = min(max(count_q[va], 0), N), nt = min(max(count_t[vb], 0), N);
-    const int q0 = qb * kMxBlockQ;
-    if (q0 >= nq) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, h = lane >> 5, m = lane & 31;
-    // the block's 32-query tiles are dealt to the waves in turn (tile wv + 4 qt of the block
-    // is slot qt of wave wv), so a block that is partly filled keeps every SIMD busy; nqt =
-    // the wave's slots holding queries (the first nqt), and empty slots are skipped
-    const int btiles = min((nq - q0 + 31) >> 5, kMxQT * 4);
-    const int nqt = __builtin_amdgcn_readfirstlane(min(max((btiles - wv + 3) >> 2, 0), kMxQT));
-    auto query_of = [&](int qt) { return q0 + (wv + 4 * qt) * 32 + m; };
+    // The block's sixteen 32-query tiles are dealt to the waves in turn (tile wv + 4 qt of the
+    // block is slot qt of wave wv), so a partly filled block keeps every SIMD busy; nqt = the
+    // wave's slots holding queries (the first nqt; empty slots are skipped).  Slot qt holds rows
+    // [row0[qt], row0[qt] + 32) of query view sv[qt] (sn[qt] queries), of view pair sp[qt].
+    int sv[kMxQT], row0[kMxQT], sn[kMxQT];
+    long long sp[kMxQT];
+    int nqt, j;
+    if (G.na <= kMxPackViews) {
+        const int b = local / G.nb;
+        j = local - b * G.nb;
+        {   // s_pre[v] = tiles of query views [0, v); four views a thread, one block-wide scan
+            int c[4], tsum = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int v = 4 * int(threadIdx.x) + e;
+                c[e] = v < G.na ? (min(max(count_q[G.a0 + v], 0), N) + 31) >> 5 : 0;
+                tsum += c[e];
+            }
+            int x = tsum;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int y = __shfl_up(x, off);
+                if (lane >= off) x += y;
+            }
+            if (lane == 63) s_wsum[wv] = x;
+            __syncthreads();
+            int ex = x - tsum;
+            for (int w = 0; w < wv; ++w) ex += s_wsum[w];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int v = 4 * int(threadIdx.x) + e;
+                if (v <= G.na) s_pre[v] = ex;
+                ex += c[e];
+            }
+            if (int(threadIdx.x) == kMxThreads - 1 && G.na == kMxPackViews) s_pre[kMxPackViews] = ex;
+            __syncthreads();
+        }
+        const int T = s_pre[G.na];
+        if (16 * b >= T) return;
+        nqt = __builtin_amdgcn_readfirstlane(min(max((T - 16 * b - wv + 3) >> 2, 0), kMxQT));
+#pragma unroll
+        for (int qt = 0; qt < kMxQT; ++qt) {
+            sv[qt] = G.a0; row0[qt] = 0; sn[qt] = 0; sp[qt] = 0;
+            if (qt < nqt) {
+                const int u = 16 * b + wv + 4 * qt;      // packed tile index, below T
+                int lo = 0, hi = G.na;                   // the view i with s_pre[i] <= u < s_pre[i + 1]
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_pre[mid] <= u) lo = mid; else hi = mid;
+                }
+                const int i = __builtin_amdgcn_readfirstlane(lo);
+                sv[qt] = G.a0 + i;
+                row0[qt] = __builtin_amdgcn_readfirstlane((u - s_pre[i]) * 32);
+                sn[qt] = __builtin_amdgcn_readfirstlane(min(max(count_q[G.a0 + i], 0), N));
+                sp[qt] = G.pair_base + (long long)i * G.nb + j;
+            }
+        }
+    } else {
+        const int qb = local % qblocks, pr = local / qblocks;
+        const int i = pr / G.nb;
+        j = pr - i * G.nb;
+        const int nq = min(max(count_q[G.a0 + i], 0), N);
+        const int q0 = qb * kMxBlockQ;
+        if (q0 >= nq) return;
+        const int btiles = min((nq - q0 + 31) >> 5, kMxQT * 4);
+        nqt = __builtin_amdgcn_readfirstlane(min(max((btiles - wv + 3) >> 2, 0), kMxQT));
+#pragma unroll
+        for (int qt = 0; qt < kMxQT; ++qt) {
+            sv[qt] = G.a0 + i;
+            row0[qt] = q0 + (wv + 4 * qt) * 32;
+            sn[qt] = qt < nqt ? nq : 0;
+            sp[qt] = G.pair_base + pr;
+        }
+    }
+    const int vb = G.b0 + j;
+    const int nt = min(max(count_t[vb], 0), N);
     uint4 B[kMxQT][4];
 #pragma unroll
     for (int qt = 0; qt < kMxQT; ++qt) {
-        const int qi = query_of(qt);
-        const uint32_t* p = desc_q + (size_t(va) * N + qi) * 8;
+        const int qi = row0[qt] + m;
+        const uint32_t* p = desc_q + (size_t(sv[qt]) * N + qi) * 8;
 #pragma unroll
-        for (int sl = 0; sl < 4; ++sl) B[qt][sl] = word_pm1(qi < nq ? p[2 * sl + h] : 0u);
+        for (int sl = 0; sl < 4; ++sl) B[qt][sl] = word_pm1(qi < sn[qt] ? p[2 * sl + h] : 0u);
     }
     uint32_t m1[kMxQT], m2[kMxQT];
 #pragma unroll
@@ -308,36 +379,34 @@ k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ coun
             contract(nfull, ci);
         }
     }
-    if (threadIdx.x == 0) s_acc = 0;
-    __syncthreads();
-    int cnt = 0;
 #pragma unroll
     for (int qt = 0; qt < kMxQT; ++qt) {
+        if (qt >= nqt) break;
         // lanes l and l + 32 saw disjoint rows of the same query column
         const uint32_t o1 = __shfl_xor(m1[qt], 32), o2 = __shfl_xor(m2[qt], 32);
         const float b1 = __uint_as_float(max(m1[qt], o1));
         const float b2 = __uint_as_float(max(min(m1[qt], o1), max(m2[qt], o2)));
-        const int qi = query_of(qt);
-        if (h != 0 || qi >= nq) continue;
-        xa_match r;
-        int d1 = 65535, d2 = 65535;
-        r.t = -1;
-        if (nt > 0) {   // b1 = (256 - 2 d1) + 512 + (16383 - t) / 2^14
-            const float it = floorf(b1);
-            r.t = 16383 - int((b1 - it) * 16384.0f);
-            d1 = (768 - int(it)) >> 1;
+        const int qi = row0[qt] + m;
+        int cnt = 0;
+        if (h == 0 && qi < sn[qt]) {
+            xa_match r;
+            int d1 = 65535, d2 = 65535;
+            r.t = -1;
+            if (nt > 0) {   // b1 = (256 - 2 d1) + 512 + (16383 - t) / 2^14
+                const float it = floorf(b1);
+                r.t = 16383 - int((b1 - it) * 16384.0f);
+                d1 = (768 - int(it)) >> 1;
+            }
+            if (nt > 1) d2 = (768 - int(floorf(b2))) >> 1;
+            r.d1 = uint16_t(d1);
+            r.d2 = uint16_t(d2);
+            matches[size_t(sp[qt]) * N + qi] = r;
+            cnt = (nt >= 2 && den * d1 < num * d2) ? 1 : 0;
         }
-        if (nt > 1) d2 = (768 - int(floorf(b2))) >> 1;
-        r.d1 = uint16_t(d1);
-        r.d2 = uint16_t(d2);
-        matches[size_t(pair) * N + qi] = r;
-        cnt += (nt >= 2 && den * d1 < num * d2) ? 1 : 0;
-    }
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off);
-    if (lane == 0 && cnt) atomicAdd(&s_acc, cnt);
-    __syncthreads();
-    if (threadIdx.x == 0 && s_acc) atomicAdd(&pair_count[pair], s_acc);
+        for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off);
+        if (lane == 0 && cnt) atomicAdd(&pair_count[sp[qt]], cnt);
+    }
 }
 
 // Per group: argmax of the pair counts, lowest pair index on ties, as the max over

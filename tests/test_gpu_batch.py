@@ -111,6 +111,38 @@ def test_match_groups_variants_agree(dev, q):
         assert np.array_equal(pc[base:base + na * nb], counts) and tuple(best[gi].tolist()) == tuple(rb)
 
 
+def test_match_groups_many_query_views(dev):
+    say("case: matrix matcher, a group of 1100 query views (past the 1024 views whose query tiles a "
+        "block packs: one query view per block) and a packed group of exactly 1024, ragged counts, N = 64")
+    g = np.random.default_rng(35)
+    N = 64
+    sizes = g.integers(0, N + 1, 1103)
+    sizes[:6] = [0, 1, 64, 33, 32, 0]
+    sizes[1100:] = [64, 7, 0]
+    D = np.zeros((len(sizes), N, 32), np.uint8)
+    descs = []
+    for v, n in enumerate(sizes):
+        d = g.integers(0, 256, (int(n), 32)).astype(np.uint8)
+        D[v, :n] = d
+        descs.append(d)
+    descs[2][:20] = descs[1100][:20] ^ np.uint8(8)
+    D[2, :20] = descs[2][:20]
+    groups = [(0, 1100, 1100, 3, 0), (3, 1024, 1100, 2, 3300)]
+    mp = X.plan_matches(np.array(groups, X.GROUP_DTYPE), N, X.MATCH_MATRIX)
+    t = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
+    m, pc, best = X.match_groups(mp, t(D), t(sizes.astype(np.int32)))
+    torch.cuda.synchronize()
+    m, pc, best = X.matches_np(m), pc.cpu().numpy(), best.cpu().numpy()
+    for gi, (a0, na, b0, nb, base) in enumerate(groups):
+        res, counts, rb = OM.match_views(descs[a0:a0 + na], descs[b0:b0 + nb])
+        for k, (idx, d1, d2, acc) in enumerate(res):
+            nq = len(descs[a0 + k // nb])
+            assert np.array_equal(m[base + k][:nq]["t"], idx) and np.array_equal(m[base + k][:nq]["d1"], d1)
+            assert np.array_equal(m[base + k][:nq]["d2"], d2), (gi, k)
+        assert np.array_equal(pc[base:base + na * nb], counts) and tuple(best[gi].tolist()) == tuple(rb), gi
+    say(f"[many views] exact on {sum(na * nb for _, na, _, nb, _ in groups)} view pairs")
+
+
 def _grid(n_tilt):
     return [(t, f) for t, f in OP.sampling_grid(n_tilt)]
 
