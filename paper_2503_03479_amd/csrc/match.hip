@@ -207,6 +207,7 @@ k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ coun
     // [tile of 32][slice][lane] operands of one chunk of train descriptors
     __shared__ uint4 tr[(kMxChunk / 32) * 4 * 64];
     __shared__ int s_pre[kMxPackViews + 1];    // exclusive prefix of the query views' tiles
+    __shared__ int s_cnt[kMxPackViews];        // the query views' clamped counts
     __shared__ int s_wsum[kMxThreads / 64];
     xa_match_group G = one;
     int local = blockIdx.x;
@@ -222,61 +223,90 @@ k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ coun
     // [row0[qt], row0[qt] + 32) of query view sv[qt] (sn[qt] queries), of view pair sp[qt].
     int sv[kMxQT], row0[kMxQT], sn[kMxQT];
     long long sp[kMxQT];
-    int nqt, j;
-    if (G.na <= kMxPackViews) {
+    // the train view first: its count and its first chunk's rows load while the query side is
+    // worked out (rows past the count are loaded too, and masked when expanded)
+    const bool packed = G.na <= kMxPackViews;
+    int j;
+    if (packed) {
+        j = local % G.nb;
+    } else {
+        const int pr = local / qblocks;
+        j = pr % G.nb;
+    }
+    const int vb = G.b0 + j;
+    const int nt = min(max(count_t[vb], 0), N);
+    const uint4* tb = reinterpret_cast<const uint4*>(desc_t + size_t(vb) * N * 8);
+    uint4 n0 = make_uint4(0, 0, 0, 0), n1 = n0;                // next chunk's descriptor of this thread
+    if (int(threadIdx.x) < N) { n0 = tb[2 * threadIdx.x]; n1 = tb[2 * threadIdx.x + 1]; }
+    int nqt;
+    if (packed) {
         const int b = local / G.nb;
-        j = local - b * G.nb;
-        {   // s_pre[v] = tiles of query views [0, v); four views a thread, one block-wide scan
-            int c[4], tsum = 0;
+        {   // s_pre[v] = tiles of query views [0, v), s_cnt[v] = view v's clamped count, four views
+            // a thread: up to 256 views wave 0 scans them alone (one barrier); beyond that every
+            // wave scans its share and the waves' sums are combined (two barriers)
+            const bool one_wave = G.na <= 4 * 64;
+            const int nscan = one_wave ? 64 : kMxThreads;
+            int c[4], tsum = 0, x = 0;
+            if (!one_wave || wv == 0) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int v = 4 * int(threadIdx.x) + e;
-                c[e] = v < G.na ? (min(max(count_q[G.a0 + v], 0), N) + 31) >> 5 : 0;
-                tsum += c[e];
-            }
-            int x = tsum;
+                for (int e = 0; e < 4; ++e) {
+                    const int v = 4 * int(threadIdx.x) + e;
+                    const int n = v < G.na ? min(max(count_q[G.a0 + v], 0), N) : 0;
+                    if (v < G.na) s_cnt[v] = n;
+                    c[e] = (n + 31) >> 5;
+                    tsum += c[e];
+                }
+                x = tsum;
 #pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const int y = __shfl_up(x, off);
-                if (lane >= off) x += y;
+                for (int off = 1; off < 64; off <<= 1) {
+                    const int y = __shfl_up(x, off);
+                    if (lane >= off) x += y;
+                }
             }
-            if (lane == 63) s_wsum[wv] = x;
-            __syncthreads();
             int ex = x - tsum;
-            for (int w = 0; w < wv; ++w) ex += s_wsum[w];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int v = 4 * int(threadIdx.x) + e;
-                if (v <= G.na) s_pre[v] = ex;
-                ex += c[e];
+            if (!one_wave) {
+                if (lane == 63) s_wsum[wv] = x;
+                __syncthreads();
+                for (int w = 0; w < wv; ++w) ex += s_wsum[w];
             }
-            if (int(threadIdx.x) == kMxThreads - 1 && G.na == kMxPackViews) s_pre[kMxPackViews] = ex;
+            if (!one_wave || wv == 0) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int v = 4 * int(threadIdx.x) + e;
+                    if (v <= G.na) s_pre[v] = ex;
+                    ex += c[e];
+                }
+                if (int(threadIdx.x) == nscan - 1 && G.na == 4 * nscan) s_pre[G.na] = ex;
+            }
             __syncthreads();
         }
         const int T = s_pre[G.na];
         if (16 * b >= T) return;
         nqt = __builtin_amdgcn_readfirstlane(min(max((T - 16 * b - wv + 3) >> 2, 0), kMxQT));
+        // slot qt's view i (s_pre[i] <= u < s_pre[i + 1]) is the number of views v >= 1 with
+        // s_pre[v] <= u, counted by ballots over the prefix
+        int le[kMxQT] = {0, 0, 0, 0};
+        for (int v0 = 1; v0 < G.na; v0 += 64) {
+            const int v = v0 + lane;
+            const int pv = v < G.na ? s_pre[v] : INT32_MAX;
+#pragma unroll
+            for (int qt = 0; qt < kMxQT; ++qt) le[qt] += __popcll(__ballot(pv <= 16 * b + wv + 4 * qt));
+        }
 #pragma unroll
         for (int qt = 0; qt < kMxQT; ++qt) {
             sv[qt] = G.a0; row0[qt] = 0; sn[qt] = 0; sp[qt] = 0;
             if (qt < nqt) {
                 const int u = 16 * b + wv + 4 * qt;      // packed tile index, below T
-                int lo = 0, hi = G.na;                   // the view i with s_pre[i] <= u < s_pre[i + 1]
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (s_pre[mid] <= u) lo = mid; else hi = mid;
-                }
-                const int i = __builtin_amdgcn_readfirstlane(lo);
+                const int i = __builtin_amdgcn_readfirstlane(le[qt]);
                 sv[qt] = G.a0 + i;
                 row0[qt] = __builtin_amdgcn_readfirstlane((u - s_pre[i]) * 32);
-                sn[qt] = __builtin_amdgcn_readfirstlane(min(max(count_q[G.a0 + i], 0), N));
+                sn[qt] = __builtin_amdgcn_readfirstlane(s_cnt[i]);
                 sp[qt] = G.pair_base + (long long)i * G.nb + j;
             }
         }
     } else {
         const int qb = local % qblocks, pr = local / qblocks;
         const int i = pr / G.nb;
-        j = pr - i * G.nb;
         const int nq = min(max(count_q[G.a0 + i], 0), N);
         const int q0 = qb * kMxBlockQ;
         if (q0 >= nq) return;
@@ -290,8 +320,6 @@ k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ coun
             sp[qt] = G.pair_base + pr;
         }
     }
-    const int vb = G.b0 + j;
-    const int nt = min(max(count_t[vb], 0), N);
     uint4 B[kMxQT][4];
 #pragma unroll
     for (int qt = 0; qt < kMxQT; ++qt) {
@@ -307,9 +335,6 @@ k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ coun
     float f0[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) f0[r] = 512.0f + float(16383 - (8 * (r >> 2) + 4 * h + (r & 3))) * (1.0f / 16384.0f);
-    const uint4* tb = reinterpret_cast<const uint4*>(desc_t + size_t(vb) * N * 8);
-    uint4 n0 = make_uint4(0, 0, 0, 0), n1 = n0;                // next chunk's descriptor of this thread
-    if (int(threadIdx.x) < nt) { n0 = tb[2 * threadIdx.x]; n1 = tb[2 * threadIdx.x + 1]; }
     for (int c0 = 0; c0 < nt; c0 += kMxChunk) {
         const int cn = min(kMxChunk, nt - c0);
         __syncthreads();

@@ -113,7 +113,8 @@ def test_match_groups_variants_agree(dev, q):
 
 def test_match_groups_many_query_views(dev):
     say("case: matrix matcher, a group of 1100 query views (past the 1024 views whose query tiles a "
-        "block packs: one query view per block) and a packed group of exactly 1024, ragged counts, N = 64")
+        "block packs: one query view per block) and packed groups of 1024, 300 (block-wide count scans) "
+        "and 256 views (one wave's scan), ragged counts, N = 64")
     g = np.random.default_rng(35)
     N = 64
     sizes = g.integers(0, N + 1, 1103)
@@ -127,7 +128,7 @@ def test_match_groups_many_query_views(dev):
         descs.append(d)
     descs[2][:20] = descs[1100][:20] ^ np.uint8(8)
     D[2, :20] = descs[2][:20]
-    groups = [(0, 1100, 1100, 3, 0), (3, 1024, 1100, 2, 3300)]
+    groups = [(0, 1100, 1100, 3, 0), (3, 1024, 1100, 2, 3300), (5, 256, 1100, 1, 5348), (7, 300, 1101, 2, 5604)]
     mp = X.plan_matches(np.array(groups, X.GROUP_DTYPE), N, X.MATCH_MATRIX)
     t = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
     m, pc, best = X.match_groups(mp, t(D), t(sizes.astype(np.int32)))
