@@ -37,6 +37,7 @@ HAMMING_OPS_PER_CMP = 16          # 8 x v_xor_b32 + 8 x v_bcnt_u32_b32 per 256-b
 FP4_PEAK_FLOPS = 10.1e15
 MX_FLOPS_PER_CMP = 2 * 256        # a +-1 dot product of two 256-bit descriptors: 256 multiply-adds
 MATCH_MATRIX = -1                 # matcher variant code of the matrix-core kernel
+MATCH_MATRIX_PACKED = -2          # the same with query tiles packed across views
 
 # HBM traffic of the matching kernel on the full-size pair, from two rocprofv3 --pmc passes
 # (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) per matcher variant (-1 = the matrix-core
@@ -46,9 +47,9 @@ MATCH_MATRIX = -1                 # matcher variant code of the matrix-core kern
 # file reports null.
 K_MATCH_TRAFFIC = {
     "source": "paper_2503_03479_amd/csrc/match.hip",
-    "sha256": "9deb1def45ae0dbad8290111624deada6d57081c19d6f1736e8349c677325fdf",
+    "sha256": "01fdb3ef6e4f425a61a95810aa87a1e0ca723ed2b7fbec565b21bd5ee669c64a",
     "fetch_scale": 2.0, "write_scale": 1.0,
-    "kib": {-1: (8152.3, 15619.2)},  # variant -> (fetch, write), variants measured on this source only
+    "kib": {-1: (10937.1, 17123.9)},  # variant -> (fetch, write), variants measured on this source only
 }
 
 
@@ -174,7 +175,7 @@ def parse():
                          "line per pair; for profiler runs, which would otherwise load the profiler into "
                          "every worker)")
     ap.add_argument("--crops", type=int, default=256, help="crops in the differentiable-warp leg (0 = skip)")
-    ap.add_argument("--matcher-q", type=int, default=0, choices=[0, 1, 2, 4, MATCH_MATRIX],
+    ap.add_argument("--matcher-q", type=int, default=0, choices=[0, 1, 2, 4, MATCH_MATRIX, MATCH_MATRIX_PACKED],
                     help="matcher variant for the full-pair leg: 0 = autotune, 1 / 2 / 4 = popcount kernel "
                          "with that many queries per lane, -1 = matrix-core kernel")
     ap.add_argument("--l2-n", type=int, default=32768, help="descriptors per set in the L2 matcher leg (0 = skip)")
@@ -913,9 +914,10 @@ def main():
     n_pairs = pa.n_views * pb.n_views
     algo_bytes = (pa.n_views + pb.n_views) * wl["n_features"] * 32 + n_pairs * wl["n_features"] * 8 + n_pairs * 4
     q = run.mplan_q
-    if q == MATCH_MATRIX:
+    if q in (MATCH_MATRIX, MATCH_MATRIX_PACKED):
         achieved = comparisons * MX_FLOPS_PER_CMP / match_s
-        head = {"kernel": "k_match_mx (xa_match_groups, fp4 matrix-core contraction of +-1 descriptors)",
+        packed = ", query tiles packed across views" if q == MATCH_MATRIX_PACKED else ""
+        head = {"kernel": f"k_match_mx (xa_match_groups, fp4 matrix-core contraction of +-1 descriptors{packed})",
                 "bound": "mfma", "achieved": achieved / 1e12, "peak": FP4_PEAK_FLOPS / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / FP4_PEAK_FLOPS, "algorithmic_flops_per_launch": comparisons * MX_FLOPS_PER_CMP}
     else:
@@ -955,7 +957,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": ("u8 images, fp32 blur and warp, int32/int64 ORB, Hamming matching as an exact fp4 (+-1) "
-                  "MFMA contraction with fp32 accumulation" if q == MATCH_MATRIX else
+                  "MFMA contraction with fp32 accumulation" if q in (MATCH_MATRIX, MATCH_MATRIX_PACKED) else
                   "u8 images, fp32 blur and warp, int32/int64 ORB, int32 popcount Hamming matching"),
         "data": "synthetic (seeded scene renderer; ground-truth affine pair)",
         "config": {

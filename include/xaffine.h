@@ -374,8 +374,13 @@ xa_status xa_match_views(const uint8_t* d_desc_a, const int32_t* d_count_a, int3
  * matrix-core kernel), 1, 2 or 4 = the vector-ALU popcount kernel with that many queries
  * per lane, XA_MATCH_MATRIX = the matrix-core kernel (the +-1 dot product of two
  * descriptors is 256 - 2 x their Hamming distance, contracted exactly in fp4 on
- * MFMA).  Match plans are blobs like view plans (host and device copies). */
+ * MFMA), XA_MATCH_MATRIX_PACKED = the same kernel with each block's sixteen 32-query
+ * tiles packed across the group's query views from their device-side counts (views with
+ * few keypoints share blocks; each block first scans the group's counts, so it pays where
+ * many views hold far fewer keypoints than n_features; groups of more than 1024 query
+ * views keep one view per block).  Match plans are blobs like view plans (host and device copies). */
 #define XA_MATCH_MATRIX (-1)
+#define XA_MATCH_MATRIX_PACKED (-2)
 typedef struct {
     int32_t a0, na;
     int32_t b0, nb;
@@ -387,10 +392,11 @@ xa_status xa_match_groups(const void* mplan_host, const void* mplan_dev, const u
                           int32_t n_views, int32_t ratio_num, int32_t ratio_den, xa_match* d_matches,
                           int32_t* d_pair_count, int32_t* d_best, hipStream_t stream);
 
-/* The matcher's autotuner: every variant (1, 2, 4 queries per lane, XA_MATCH_MATRIX) runs the
- * given groups on the given descriptor set (d_desc, d_count, n_views as for xa_match_groups),
- * once untimed and `reps` times timed with HIP events; *best_variant gets the fastest (ms[4],
- * if not NULL, the mean times in milliseconds, in the order above).  Every variant's results are
+/* The matcher's autotuner: every variant (1, 2, 4 queries per lane, XA_MATCH_MATRIX,
+ * XA_MATCH_MATRIX_PACKED) runs the given groups on the given descriptor set (d_desc, d_count,
+ * n_views as for xa_match_groups), once untimed and `reps` times timed with HIP events;
+ * *best_variant gets the fastest (ms[5], if not NULL, the mean times in milliseconds, in the
+ * order above).  Every variant's results are
  * the same; d_matches, d_pair_count and d_best receive them (sized as for xa_match_groups).  The
  * workspace holds the plans' device copies: xa_tune_matcher_workspace_size(groups, n_groups,
  * n_features) bytes, 256-byte aligned.  The library keeps each result per device, keyed by the

@@ -188,17 +188,21 @@ __device__ __forceinline__ v8i_t operand(uint4 u) {
     return v;
 }
 
-// Blocks of one train view take the group's query tiles packed: the 32-query tiles of all its
-// query views, concatenated in view order, sixteen to a block, so views with few keypoints share
-// a block instead of each filling a block of its own with padding.  A group of more query views
+// PACK: blocks of one train view take the group's query tiles packed: the 32-query tiles of all
+// its query views, concatenated in view order, sixteen to a block, so views with few keypoints
+// share a block instead of each filling a block of its own with padding.  Finding its tiles
+// costs each block a scan of the group's counts before its first query load, which the plain
+// mapping does not pay, so the two are separate matcher variants.  A group of more query views
 // than kMxPackViews (the prefix over them lives in LDS) keeps one query view per block.
 constexpr int kMxPackViews = 1024;
 
-// Outputs as k_match's.  Block mapping per group: packed, block local = b nb + j takes packed
-// tiles [16 b, 16 b + 16) against train view j (blocks past the group's tiles exit); otherwise
-// as k_match (view pair, then query block of 512).  The K dimension is split alike for both
-// operands: slice s of lane l is word 2 s + l / 32 of descriptor (tile row or column) l % 32,
-// so the contraction pairs equal bits whatever order the hardware gives the 64 values of a slice.
+// Outputs as k_match's.  Block mapping per group: PACK (and at most kMxPackViews query views),
+// block local = b nb + j takes packed tiles [16 b, 16 b + 16) against train view j (blocks past
+// the group's tiles exit); otherwise as k_match (view pair, then query block of 512).  The K
+// dimension is split alike for both operands: slice s of lane l is word 2 s + l / 32 of
+// descriptor (tile row or column) l % 32, so the contraction pairs equal bits whatever order
+// the hardware gives the 64 values of a slice.
+template <bool PACK>
 __global__ void __launch_bounds__(kMxThreads) __attribute__((amdgpu_waves_per_eu(3)))
 k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ count_q, const uint32_t* __restrict__ desc_t,
            const int32_t* __restrict__ count_t, const xa_match_group* __restrict__ groups,
@@ -206,8 +210,8 @@ k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ coun
            int den, xa_match* __restrict__ matches, int32_t* __restrict__ pair_count) {
     // [tile of 32][slice][lane] operands of one chunk of train descriptors
     __shared__ uint4 tr[(kMxChunk / 32) * 4 * 64];
-    __shared__ int s_pre[kMxPackViews + 1];    // exclusive prefix of the query views' tiles
-    __shared__ int s_cnt[kMxPackViews];        // the query views' clamped counts
+    __shared__ int s_pre[PACK ? kMxPackViews + 1 : 1];    // exclusive prefix of the query views' tiles
+    __shared__ int s_cnt[PACK ? kMxPackViews : 1];        // the query views' clamped counts
     __shared__ int s_wsum[kMxThreads / 64];
     xa_match_group G = one;
     int local = blockIdx.x;
@@ -223,23 +227,18 @@ k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ coun
     // [row0[qt], row0[qt] + 32) of query view sv[qt] (sn[qt] queries), of view pair sp[qt].
     int sv[kMxQT], row0[kMxQT], sn[kMxQT];
     long long sp[kMxQT];
-    // the train view first: its count and its first chunk's rows load while the query side is
-    // worked out (rows past the count are loaded too, and masked when expanded)
-    const bool packed = G.na <= kMxPackViews;
-    int j;
-    if (packed) {
-        j = local % G.nb;
-    } else {
-        const int pr = local / qblocks;
-        j = pr % G.nb;
-    }
-    const int vb = G.b0 + j;
-    const int nt = min(max(count_t[vb], 0), N);
-    const uint4* tb = reinterpret_cast<const uint4*>(desc_t + size_t(vb) * N * 8);
+    const bool packed = PACK && G.na <= kMxPackViews;
+    int j = 0, vb = 0, nt = 0, nqt;
+    const uint4* tb = nullptr;
     uint4 n0 = make_uint4(0, 0, 0, 0), n1 = n0;                // next chunk's descriptor of this thread
-    if (int(threadIdx.x) < N) { n0 = tb[2 * threadIdx.x]; n1 = tb[2 * threadIdx.x + 1]; }
-    int nqt;
     if (packed) {
+        // the train view first: its count and its first chunk's rows load while the query side
+        // is worked out (rows past the count are loaded too, and masked when expanded)
+        j = local % G.nb;
+        vb = G.b0 + j;
+        nt = min(max(count_t[vb], 0), N);
+        tb = reinterpret_cast<const uint4*>(desc_t + size_t(vb) * N * 8);
+        if (int(threadIdx.x) < N) { n0 = tb[2 * threadIdx.x]; n1 = tb[2 * threadIdx.x + 1]; }
         const int b = local / G.nb;
         {   // s_pre[v] = tiles of query views [0, v), s_cnt[v] = view v's clamped count, four views
             // a thread: up to 256 views wave 0 scans them alone (one barrier); beyond that every
@@ -307,7 +306,10 @@ k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ coun
     } else {
         const int qb = local % qblocks, pr = local / qblocks;
         const int i = pr / G.nb;
+        j = pr - i * G.nb;
+        vb = G.b0 + j;
         const int nq = min(max(count_q[G.a0 + i], 0), N);
+        nt = min(max(count_t[vb], 0), N);
         const int q0 = qb * kMxBlockQ;
         if (q0 >= nq) return;
         const int btiles = min((nq - q0 + 31) >> 5, kMxQT * 4);
@@ -327,6 +329,10 @@ k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ coun
         const uint32_t* p = desc_q + (size_t(sv[qt]) * N + qi) * 8;
 #pragma unroll
         for (int sl = 0; sl < 4; ++sl) B[qt][sl] = word_pm1(qi < sn[qt] ? p[2 * sl + h] : 0u);
+    }
+    if (!packed) {   // one query view: its train view's first chunk loads after the queries
+        tb = reinterpret_cast<const uint4*>(desc_t + size_t(vb) * N * 8);
+        if (int(threadIdx.x) < nt) { n0 = tb[2 * threadIdx.x]; n1 = tb[2 * threadIdx.x + 1]; }
     }
     uint32_t m1[kMxQT], m2[kMxQT];
 #pragma unroll
@@ -404,6 +410,13 @@ k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ coun
             contract(nfull, ci);
         }
     }
+    // PACK: a block may span several view pairs, so each slot adds its accepted count; the
+    // plain variant's block is one view pair and adds its count once
+    if constexpr (!PACK) {
+        if (threadIdx.x == 0) s_wsum[0] = 0;
+        __syncthreads();
+    }
+    int cnt = 0;
 #pragma unroll
     for (int qt = 0; qt < kMxQT; ++qt) {
         if (qt >= nqt) break;
@@ -412,7 +425,7 @@ k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ coun
         const float b1 = __uint_as_float(max(m1[qt], o1));
         const float b2 = __uint_as_float(max(min(m1[qt], o1), max(m2[qt], o2)));
         const int qi = row0[qt] + m;
-        int cnt = 0;
+        int acc = 0;
         if (h == 0 && qi < sn[qt]) {
             xa_match r;
             int d1 = 65535, d2 = 65535;
@@ -426,11 +439,22 @@ k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ coun
             r.d1 = uint16_t(d1);
             r.d2 = uint16_t(d2);
             matches[size_t(sp[qt]) * N + qi] = r;
-            cnt = (nt >= 2 && den * d1 < num * d2) ? 1 : 0;
+            acc = (nt >= 2 && den * d1 < num * d2) ? 1 : 0;
         }
+        if constexpr (PACK) {
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+            if (lane == 0 && acc) atomicAdd(&pair_count[sp[qt]], acc);
+        } else {
+            cnt += acc;
+        }
+    }
+    if constexpr (!PACK) {
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off);
-        if (lane == 0 && cnt) atomicAdd(&pair_count[sp[qt]], cnt);
+        if (lane == 0 && cnt) atomicAdd(&s_wsum[0], cnt);
+        __syncthreads();
+        if (threadIdx.x == 0 && s_wsum[0]) atomicAdd(&pair_count[sp[0]], s_wsum[0]);
     }
 }
 
@@ -521,8 +545,11 @@ __global__ void __launch_bounds__(256) k_precision(const xa_keypoint* __restrict
 // kernels' rate at a thousand features per view)
 static int pick_q(int) { return XA_MATCH_MATRIX; }
 
-// queries one block of matcher variant Q owns (Q = XA_MATCH_MATRIX: the matrix-core kernel)
-static int block_queries(int Q) { return Q == XA_MATCH_MATRIX ? kMxBlockQ : kMatchThreads * Q; }
+// queries one block of matcher variant Q owns (Q = XA_MATCH_MATRIX[_PACKED]: the matrix-core
+// kernel; the packed form's grid keeps the bound of one 512-query block per view pair)
+static int block_queries(int Q) {
+    return Q == XA_MATCH_MATRIX || Q == XA_MATCH_MATRIX_PACKED ? kMxBlockQ : kMatchThreads * Q;
+}
 
 xa_status launch_match_any(const uint8_t* desc_q, const int32_t* count_q, const uint8_t* desc_t,
                            const int32_t* count_t, const xa_match_group* groups_dev, const int32_t* prefix_dev,
@@ -537,8 +564,11 @@ xa_status launch_match_any(const uint8_t* desc_q, const int32_t* count_q, const 
     const uint32_t* dt = reinterpret_cast<const uint32_t*>(desc_t);
     const int qblocks = (N + block_queries(Q) - 1) / block_queries(Q);
     if (total_blocks > 0) {
-        if (Q == XA_MATCH_MATRIX)
-            hipLaunchKernelGGL(k_match_mx, dim3(unsigned(total_blocks)), dim3(kMxThreads), 0, st, dq, count_q, dt,
+        if (Q == XA_MATCH_MATRIX_PACKED)
+            hipLaunchKernelGGL(k_match_mx<true>, dim3(unsigned(total_blocks)), dim3(kMxThreads), 0, st, dq, count_q, dt,
+                               count_t, groups_dev, prefix_dev, n_groups, one, qblocks, N, num, den, matches, pair_count);
+        else if (Q == XA_MATCH_MATRIX)
+            hipLaunchKernelGGL(k_match_mx<false>, dim3(unsigned(total_blocks)), dim3(kMxThreads), 0, st, dq, count_q, dt,
                                count_t, groups_dev, prefix_dev, n_groups, one, qblocks, N, num, den, matches, pair_count);
         else if (Q == 4)
             hipLaunchKernelGGL(k_match<4>, dim3(unsigned(total_blocks)), dim3(kMatchThreads), 0, st, dq, count_q, dt,
@@ -630,8 +660,8 @@ extern "C" xa_status xa_plan_matches(const xa_match_group* groups, int32_t n_gro
     if (!blob_bytes || !groups || n_groups < 1) return fail(XA_EINVAL, "need at least one group");
     if (n_features < 1 || n_features > XA_MAX_FEATURES) return fail(XA_EUNSUPPORTED, "n_features out of range");
     const int Q = queries_per_lane == 0 ? pick_q(n_features) : queries_per_lane;
-    if (Q != 1 && Q != 2 && Q != 4 && Q != XA_MATCH_MATRIX)
-        return fail(XA_EINVAL, "queries_per_lane must be 0 (auto), 1, 2, 4 or XA_MATCH_MATRIX");
+    if (Q != 1 && Q != 2 && Q != 4 && Q != XA_MATCH_MATRIX && Q != XA_MATCH_MATRIX_PACKED)
+        return fail(XA_EINVAL, "queries_per_lane must be 0 (auto), 1, 2, 4, XA_MATCH_MATRIX or XA_MATCH_MATRIX_PACKED");
     const int qblocks = (n_features + block_queries(Q) - 1) / block_queries(Q);
     std::vector<int32_t> prefix(n_groups + 1, 0);
     long long blocks = 0, pairs = 0, views = 0;
@@ -697,9 +727,12 @@ extern "C" xa_status xa_match_groups(const void* mplan_host, const void* mplan_d
     return s == XA_OK ? ok() : s;
 }
 
+// the variants the tuner times, in the order of its ms[] output
+static constexpr int kTuneVariants = 5;
+
 extern "C" size_t xa_tune_matcher_workspace_size(const xa_match_group* groups, int32_t n_groups, int32_t n_features) {
     size_t most = 0;
-    const int variants[4] = {1, 2, 4, XA_MATCH_MATRIX};
+    const int variants[kTuneVariants] = {1, 2, 4, XA_MATCH_MATRIX, XA_MATCH_MATRIX_PACKED};
     for (int v : variants) {
         size_t bytes = 0;
         if (xa_plan_matches(groups, n_groups, n_features, v, nullptr, 0, &bytes) != XA_OK) return 0;
@@ -713,7 +746,7 @@ namespace {
 // group table, n_features and the per-view counts (the descriptor bits do not matter).
 struct TuneEntry {
     int32_t best;
-    float ms[4];
+    float ms[kTuneVariants];
 };
 std::mutex g_tune_mu;
 std::map<std::pair<int, uint64_t>, TuneEntry> g_tune_cache;
@@ -753,11 +786,11 @@ extern "C" xa_status xa_tune_matcher(const xa_match_group* groups, int32_t n_gro
         const auto it = g_tune_cache.find({device, key});
         if (it != g_tune_cache.end()) {
             *best_variant = it->second.best;
-            if (ms) std::copy(it->second.ms, it->second.ms + 4, ms);
+            if (ms) std::copy(it->second.ms, it->second.ms + kTuneVariants, ms);
             return ok();
         }
     }
-    const int variants[4] = {1, 2, 4, XA_MATCH_MATRIX};
+    const int variants[kTuneVariants] = {1, 2, 4, XA_MATCH_MATRIX, XA_MATCH_MATRIX_PACKED};
     TuneEntry entry{};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     e = hipEventCreate(&e0);
@@ -766,7 +799,7 @@ extern "C" xa_status xa_tune_matcher(const xa_match_group* groups, int32_t n_gro
     xa_status s = XA_OK;
     float best = 0.0f;
     int best_v = 0;
-    for (int i = 0; i < 4 && s == XA_OK; ++i) {
+    for (int i = 0; i < kTuneVariants && s == XA_OK; ++i) {
         size_t bytes = 0;
         s = xa_plan_matches(groups, n_groups, n_features, variants[i], nullptr, 0, &bytes);
         if (s != XA_OK) break;
@@ -802,6 +835,6 @@ extern "C" xa_status xa_tune_matcher(const xa_match_group* groups, int32_t n_gro
         g_tune_cache[{device, key}] = entry;
     }
     *best_variant = best_v;
-    if (ms) std::copy(entry.ms, entry.ms + 4, ms);
+    if (ms) std::copy(entry.ms, entry.ms + kTuneVariants, ms);
     return ok();
 }

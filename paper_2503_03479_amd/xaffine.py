@@ -789,7 +789,8 @@ def plan_matches(groups, n_features: int, queries_per_lane: int = 0) -> MatchPla
 
 
 MATCH_MATRIX = -1          # queries_per_lane code of the matrix-core (MFMA) matcher
-MATCH_VARIANTS = (1, 2, 4, MATCH_MATRIX)
+MATCH_MATRIX_PACKED = -2   # the same with query tiles packed across views
+MATCH_VARIANTS = (1, 2, 4, MATCH_MATRIX, MATCH_MATRIX_PACKED)
 
 
 TUNE_USE_CACHE = 1
@@ -798,7 +799,8 @@ TUNE_USE_CACHE = 1
 def autotune_queries_per_lane(groups, n_features: int, device="cuda", desc=None, count=None, reps: int = 5,
                               use_cache: bool = True, out=None):
     """The matcher variant (the popcount kernel with 1, 2 or 4 queries per lane, or the
-    matrix-core kernel, MATCH_MATRIX) that runs `groups` fastest on this GPU.
+    matrix-core kernel, MATCH_MATRIX, plain or with query tiles packed across views,
+    MATCH_MATRIX_PACKED) that runs `groups` fastest on this GPU.
 
     The library's tuner (xa_tune_matcher) times every variant with HIP events on the current
     stream, over the given descriptor set (desc [views][n_features][32], count [views]) or,
@@ -824,7 +826,7 @@ def autotune_queries_per_lane(groups, n_features: int, device="cuda", desc=None,
     matches, pair_count, best_buf = out
     ws = _empty(lib().xa_tune_matcher_workspace_size(groups.ctypes.data, len(groups), n_features), dev)
     best_q = ctypes.c_int32(0)
-    ms = np.zeros(4, np.float32)
+    ms = np.zeros(len(MATCH_VARIANTS), np.float32)
     _check(lib().xa_tune_matcher(groups.ctypes.data, len(groups), n_features, _ptr(desc), _ptr(count),
                                  int(desc.shape[0]), reps, TUNE_USE_CACHE if use_cache else 0, _ptr(matches),
                                  _ptr(pair_count), _ptr(best_buf), _ptr(ws), ws.numel(), _stream(),

@@ -44,7 +44,7 @@ def pairs():
     return out
 
 
-@pytest.mark.parametrize("q", [0, X.MATCH_MATRIX])
+@pytest.mark.parametrize("q", [0, X.MATCH_MATRIX, X.MATCH_MATRIX_PACKED])
 def test_match_groups_exact_random(dev, q):
     say(f"case: group matching of random descriptors, 4 groups with ragged sizes and an empty one (variant {q})")
     g = np.random.default_rng(31)
@@ -111,8 +111,9 @@ def test_match_groups_variants_agree(dev, q):
         assert np.array_equal(pc[base:base + na * nb], counts) and tuple(best[gi].tolist()) == tuple(rb)
 
 
-def test_match_groups_many_query_views(dev):
-    say("case: matrix matcher, a group of 1100 query views (past the 1024 views whose query tiles a "
+@pytest.mark.parametrize("q", [X.MATCH_MATRIX, X.MATCH_MATRIX_PACKED])
+def test_match_groups_many_query_views(dev, q):
+    say(f"case: matrix matcher (variant {q}), a group of 1100 query views (past the 1024 views whose query tiles a "
         "block packs: one query view per block) and packed groups of 1024, 300 (block-wide count scans) "
         "and 256 views (one wave's scan), ragged counts, N = 64")
     g = np.random.default_rng(35)
@@ -129,7 +130,7 @@ def test_match_groups_many_query_views(dev):
     descs[2][:20] = descs[1100][:20] ^ np.uint8(8)
     D[2, :20] = descs[2][:20]
     groups = [(0, 1100, 1100, 3, 0), (3, 1024, 1100, 2, 3300), (5, 256, 1100, 1, 5348), (7, 300, 1101, 2, 5604)]
-    mp = X.plan_matches(np.array(groups, X.GROUP_DTYPE), N, X.MATCH_MATRIX)
+    mp = X.plan_matches(np.array(groups, X.GROUP_DTYPE), N, q)
     t = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
     m, pc, best = X.match_groups(mp, t(D), t(sizes.astype(np.int32)))
     torch.cuda.synchronize()
@@ -287,7 +288,8 @@ def test_batch_graph_replays(dev, pairs):
 def test_autotuner_picks_a_variant_and_caches_it(dev, pairs):
     """The library's matcher autotuner times every variant, keeps the winner per device and
     key, and a batch built with it gives the same bytes as batches with each fixed variant."""
-    say("case: matcher autotuner (popcount kernel with 1 / 2 / 4 queries per lane, matrix-core kernel) and its cache")
+    say("case: matcher autotuner (popcount kernel with 1 / 2 / 4 queries per lane, matrix-core kernel plain and "
+        "packed) and its cache")
     grid = _grid(1)
     pat = torch.from_numpy(synth.brief_pattern()).to(dev)
     imgs = [(p.A, np.ascontiguousarray(p.B)) for p in pairs[:2]]

@@ -60,8 +60,9 @@ def stress(dev):
     grid = [(float(r["t"]), float(r["phi"])) for r in grid_np]
     pattern_np = synth.brief_pattern()
     pattern = torch.from_numpy(pattern_np).to(dev)
+    # the packed matrix-core variant: the steep views hold far fewer keypoints than N
     run = X.BatchRunner([(A, B)], grid, SCALES, n_levels=LEVELS, n_features=N, fast_threshold=FAST_T,
-                        device=dev, queries_per_lane=X.MATCH_MATRIX)
+                        device=dev, queries_per_lane=X.MATCH_MATRIX_PACKED)
     assert len(run.chunks) == 1
     src0 = run.sources.clone()
     say(f"[stress] batch of {run.n_views} views, {run.mplan.total_pairs} view pairs, "
