@@ -47,9 +47,11 @@ MATCH_MATRIX_PACKED = -2          # the same with query tiles packed across view
 # file reports null.
 K_MATCH_TRAFFIC = {
     "source": "paper_2503_03479_amd/csrc/match.hip",
-    "sha256": "01fdb3ef6e4f425a61a95810aa87a1e0ca723ed2b7fbec565b21bd5ee669c64a",
+    "sha256": "792216b036e1111afcd02165b4596fe27886d1fa8471fd2291d60c908315dd4a",
     "fetch_scale": 2.0, "write_scale": 1.0,
-    "kib": {-1: (10937.1, 17123.9)},  # variant -> (fetch, write), variants measured on this source only
+    # variant -> (fetch, write), all measured on this source
+    "kib": {-1: (8162.3, 15619.2), -2: (10932.1, 17123.9), 1: (6714.1, 15745.8), 2: (8086.2, 15619.2),
+            4: (10855.9, 15555.9)},
 }
 
 
