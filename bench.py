@@ -47,7 +47,7 @@ MATCH_MATRIX_PACKED = -2          # the same with query tiles packed across view
 # file reports null.
 K_MATCH_TRAFFIC = {
     "source": "paper_2503_03479_amd/csrc/match.hip",
-    "sha256": "792216b036e1111afcd02165b4596fe27886d1fa8471fd2291d60c908315dd4a",
+    "sha256": "8dd7d16ff0868af1917bb00769c723d5f4249cbfd447d980ea4e0038aa13e703",
     "fetch_scale": 2.0, "write_scale": 1.0,
     # variant -> (fetch, write), all measured on this source
     "kib": {-1: (8162.3, 15619.2), -2: (10932.1, 17123.9), 1: (6714.1, 15745.8), 2: (8086.2, 15619.2),

@@ -212,7 +212,7 @@ k_match_mx(const uint32_t* __restrict__ desc_q, const int32_t* __restrict__ coun
     __shared__ uint4 tr[(kMxChunk / 32) * 4 * 64];
     __shared__ int s_pre[PACK ? kMxPackViews + 1 : 1];    // exclusive prefix of the query views' tiles
     __shared__ int s_cnt[PACK ? kMxPackViews : 1];        // the query views' clamped counts
-    __shared__ int s_wsum[kMxThreads / 64];
+    __shared__ int s_wsum[kMxThreads / 64];   // the count scan's wave sums (packed); [0] the block's count (plain)
     xa_match_group G = one;
     int local = blockIdx.x;
     if (groups) {
