@@ -82,6 +82,18 @@ def test_full_batch_equals_stages(full):
     say(f"[full] batch == stages; best {st.best.tolist()}, keypoints {int(run.count.sum())}")
 
 
+@pytest.mark.parametrize("q", [1, X.MATCH_MATRIX_PACKED])
+def test_full_matcher_variants_agree(full, q):
+    say(f"case: full-size pair, matcher variant {q} on the batch's own descriptors against the plain "
+        "matrix-core kernel the batch ran")
+    run = full["run"]
+    mp = X.plan_matches(run.mplan.groups, N, q)
+    m, pc, best = X.match_groups(mp, run.desc, run.count)
+    torch.cuda.synchronize()
+    assert torch.equal(m, run.matches) and torch.equal(pc, run.pair_count) and torch.equal(best, run.best)
+    say(f"[full] variant {q}: identical matches, counts and best pair {best[0].tolist()}")
+
+
 def _gpu_level0(plan, side, i):
     arena = side["arena"].cpu().numpy()
     mask = side["mask"].cpu().numpy()
