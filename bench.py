@@ -47,7 +47,7 @@ MATCH_MATRIX_PACKED = -2          # the same with query tiles packed across view
 # file reports null.
 K_MATCH_TRAFFIC = {
     "source": "paper_2503_03479_amd/csrc/match.hip",
-    "sha256": "8dd7d16ff0868af1917bb00769c723d5f4249cbfd447d980ea4e0038aa13e703",
+    "sha256": "8b70214ddfeb76df949cb1d274d3e94e0e95729e6216c522fc9172ede0600971",
     "fetch_scale": 2.0, "write_scale": 1.0,
     # variant -> (fetch, write), all measured on this source
     "kib": {-1: (8162.3, 15619.2), -2: (10932.1, 17123.9), 1: (6714.1, 15745.8), 2: (8086.2, 15619.2),
@@ -74,7 +74,7 @@ def k_match_traffic(queries_per_lane: int):
 K_WARP_TRAFFIC = {
     "sources": ["paper_2503_03479_amd/csrc/simulate.hip", "paper_2503_03479_amd/csrc/internal.h",
                 "paper_2503_03479_amd/csrc/lanczos.h"],
-    "sha256": "16de2adfe2511e81f8241d53159f92be07725c3c44eeaf4aae27f3d28a66195d",   # of the sources, concatenated
+    "sha256": "890a880b91694d9cd60d69d982a8926e567cfe6571c386653cdb33d4eec97525",   # of the sources, concatenated
     "warp_tiles": [32, 16, 8, 8, 8, 8, 8, 8],
     "fetch_scale": 2.0, "write_scale": 1.0,
     "kib": (109313.8, 67581.6),   # (fetch, write) per launch

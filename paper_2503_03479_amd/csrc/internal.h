@@ -195,9 +195,11 @@ constexpr int kStageBlur = 1, kStageWarp = 2;   // launch_simulate stage mask
 xa_status launch_simulate(const PlanView& ph, const PlanView& pd, const uint8_t* sources,
                           uint8_t* arena, uint8_t* mask, float* values, float* blurred, hipStream_t st,
                           int stages = kStageBlur | kStageWarp);
+// zero_extra (nullable): n_extra int32 counters the set-up launch clears as well (the matcher's
+// pair counts of a pipeline, which then skips its own clearing launch).
 xa_status launch_extract(const PlanView& ph, const PlanView& pd, uint8_t* arena, uint8_t* mask,
                          const int8_t* pattern, xa_keypoint* kp, uint8_t* desc, int32_t* count,
-                         uint8_t* ws, hipStream_t st);
+                         uint8_t* ws, hipStream_t st, int32_t* zero_extra = nullptr, int n_extra = 0);
 xa_status launch_scale(const void* splan_host, const void* splan_dev, uint8_t* d_sources, float* d_values,
                        void* d_ws, hipStream_t stream);
 bool is_scale_plan(const void* blob);
@@ -213,12 +215,13 @@ struct MatchPlanView {
     const MatchPlanHeader* h = nullptr;
 };
 xa_status match_plan_view(const void* blob, MatchPlanView* out);
+// counts_zeroed: pair_count is already zero on the stream (no clearing launch)
 xa_status launch_match_plan(const void* mplan_host, const void* mplan_dev, const uint8_t* desc, const int32_t* count,
                             int32_t num, int32_t den, xa_match* matches, int32_t* pair_count, int32_t* best,
-                            hipStream_t st);
+                            hipStream_t st, bool counts_zeroed = false);
 xa_status launch_match(const uint8_t* desc_a, const int32_t* count_a, int32_t n_a,
                        const uint8_t* desc_b, const int32_t* count_b, int32_t n_b, int32_t n_features,
                        int32_t num, int32_t den, xa_match* matches, int32_t* pair_count, int32_t* best,
-                       hipStream_t st);
+                       hipStream_t st, bool counts_zeroed = false);
 
 }  // namespace xa

@@ -555,9 +555,9 @@ xa_status launch_match_any(const uint8_t* desc_q, const int32_t* count_q, const 
                            const int32_t* count_t, const xa_match_group* groups_dev, const int32_t* prefix_dev,
                            int n_groups, const xa_match_group& one, long long total_pairs, long long total_blocks,
                            int N, int Q, int num, int den, xa_match* matches, int32_t* pair_count, int32_t* best,
-                           hipStream_t st) {
+                           hipStream_t st, bool counts_zeroed = false) {
     if (total_blocks > INT32_MAX || total_pairs > INT32_MAX) return fail(XA_EUNSUPPORTED, "too many view pairs");
-    if (total_pairs > 0)
+    if (total_pairs > 0 && !counts_zeroed)
         hipLaunchKernelGGL(k_fill_i32, dim3(unsigned((total_pairs + 255) / 256)), dim3(256), 0, st, pair_count,
                            int(total_pairs), 0);
     const uint32_t* dq = reinterpret_cast<const uint32_t*>(desc_q);
@@ -588,12 +588,13 @@ xa_status launch_match_any(const uint8_t* desc_q, const int32_t* count_q, const 
 
 xa_status launch_match(const uint8_t* desc_a, const int32_t* count_a, int32_t n_a, const uint8_t* desc_b,
                        const int32_t* count_b, int32_t n_b, int32_t N, int32_t num, int32_t den, xa_match* matches,
-                       int32_t* pair_count, int32_t* best, hipStream_t st) {
+                       int32_t* pair_count, int32_t* best, hipStream_t st, bool counts_zeroed) {
     const int Q = pick_q(N);
     const int qblocks = (N + block_queries(Q) - 1) / block_queries(Q);
     const xa_match_group one{0, n_a, 0, n_b, 0};
     return launch_match_any(desc_a, count_a, desc_b, count_b, nullptr, nullptr, 1, one, (long long)n_a * n_b,
-                            (long long)n_a * n_b * qblocks, N, Q, num, den, matches, pair_count, best, st);
+                            (long long)n_a * n_b * qblocks, N, Q, num, den, matches, pair_count, best, st,
+                            counts_zeroed);
 }
 
 // ------------------------------------------------------------------ match plans
@@ -608,13 +609,14 @@ xa_status match_plan_view(const void* blob, MatchPlanView* out) {
 
 xa_status launch_match_plan(const void* mplan_host, const void* mplan_dev, const uint8_t* desc, const int32_t* count,
                             int32_t num, int32_t den, xa_match* matches, int32_t* pair_count, int32_t* best,
-                            hipStream_t st) {
+                            hipStream_t st, bool counts_zeroed) {
     const auto* h = static_cast<const MatchPlanHeader*>(mplan_host);
     const char* d = static_cast<const char*>(mplan_dev);
     const xa_match_group one{0, 0, 0, 0, 0};
     return launch_match_any(desc, count, desc, count, reinterpret_cast<const xa_match_group*>(d + h->off_groups),
                             reinterpret_cast<const int32_t*>(d + h->off_prefix), h->n_groups, one, h->total_pairs,
-                            h->total_blocks, h->n_features, h->q, num, den, matches, pair_count, best, st);
+                            h->total_blocks, h->n_features, h->q, num, den, matches, pair_count, best, st,
+                            counts_zeroed);
 }
 
 }  // namespace xa

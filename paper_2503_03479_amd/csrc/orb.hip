@@ -6,6 +6,8 @@
 // between HBM and LDS in 16-byte chunks.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <climits>
 
 #include "internal.h"
@@ -670,10 +672,12 @@ __device__ __forceinline__ int rnd20(int v) {
 // The extraction's set-up in one launch: blocks 0 .. kOrientBins - 1 steer the pattern (block b:
 // bin b), the rest zero the n candidate counters.
 __global__ void __launch_bounds__(kBriefTests) k_steer(const int8_t* __restrict__ pattern, uint32_t* __restrict__ steer,
-                                                       int32_t* __restrict__ zero, int n) {
+                                                       int32_t* __restrict__ zero, int n, int32_t* __restrict__ zero2,
+                                                       int n2) {
     if (int(blockIdx.x) >= kOrientBins) {
         const int z = (blockIdx.x - kOrientBins) * kBriefTests + threadIdx.x;
         if (z < n) zero[z] = 0;
+        if (z < n2) zero2[z] = 0;
         return;
     }
     const int b = blockIdx.x, i = threadIdx.x;
@@ -863,7 +867,7 @@ __global__ void __launch_bounds__(256) k_orient_brief(const xa_view_desc* __rest
 
 xa_status launch_extract(const PlanView& ph, const PlanView& pd, uint8_t* arena, uint8_t* mask,
                          const int8_t* pattern, xa_keypoint* kp, uint8_t* desc, int32_t* count,
-                         uint8_t* ws, hipStream_t st) {
+                         uint8_t* ws, hipStream_t st, int32_t* zero_extra, int n_extra) {
     const xa_plan_header* h = ph.h;
     const int nv = h->n_views, L = h->n_levels, nvl = nv * L, N = h->n_features;
     const ExtractWs w = extract_ws_layout(h);
@@ -873,8 +877,10 @@ xa_status launch_extract(const PlanView& ph, const PlanView& pd, uint8_t* arena,
     int4* stage = reinterpret_cast<int4*>(ws + w.stage);
     int32_t* stage_count = reinterpret_cast<int32_t*>(ws + w.stage_count);
     uint32_t* steer = reinterpret_cast<uint32_t*>(ws + w.steer);
-    hipLaunchKernelGGL(k_steer, dim3(kOrientBins + (nvl + kBriefTests - 1) / kBriefTests), dim3(kBriefTests), 0, st,
-                       pattern, steer, cand_count, nvl);
+    if (!zero_extra) n_extra = 0;
+    const int nz = std::max(nvl, n_extra);   // the candidate counters, and the caller's counts to clear
+    hipLaunchKernelGGL(k_steer, dim3(kOrientBins + (nz + kBriefTests - 1) / kBriefTests), dim3(kBriefTests), 0, st,
+                       pattern, steer, cand_count, nvl, zero_extra, n_extra);
     for (int l = 1; l < L; ++l) {
         const int32_t* pre_h = ph.level_prefix + size_t(l) * (nv + 1);
         const int tiles = pre_h[nv];

@@ -69,14 +69,15 @@ extern "C" xa_status xa_match_pair(const void* plan_a_host, const void* plan_a_d
     s = launch_simulate(hb, db, d_b, ws + w.arena_b, ws + w.mask_b, nullptr,
                         reinterpret_cast<float*>(ws + w.sim_b), stream);
     if (s != XA_OK) return s;
+    // the first extraction's set-up launch also clears the matcher's pair counts
     s = launch_extract(ha, da, ws + w.arena_a, ws + w.mask_a, d_pattern, out->kp_a, out->desc_a, out->count_a,
-                       ws + w.ext_a, stream);
+                       ws + w.ext_a, stream, out->pair_count, ha.h->n_views * hb.h->n_views);
     if (s != XA_OK) return s;
     s = launch_extract(hb, db, ws + w.arena_b, ws + w.mask_b, d_pattern, out->kp_b, out->desc_b, out->count_b,
                        ws + w.ext_b, stream);
     if (s != XA_OK) return s;
     s = launch_match(out->desc_a, out->count_a, ha.h->n_views, out->desc_b, out->count_b, hb.h->n_views,
-                     ha.h->n_features, ratio_num, ratio_den, out->matches, out->pair_count, out->best, stream);
+                     ha.h->n_features, ratio_num, ratio_den, out->matches, out->pair_count, out->best, stream, true);
     return s == XA_OK ? ok() : s;
 }
 
@@ -170,19 +171,22 @@ xa_status batch_launch(const BatchArgs& a, const std::vector<PlanView>& ph, cons
     if (a.splan_host) s = launch_scale(a.splan_host, a.splan_dev, a.sources, nullptr, a.ws + w.scale, st);
     if (s != XA_OK) return s;
     const size_t N = size_t(ph[0].h->n_features);
+    const int n_pairs = int(static_cast<const MatchPlanHeader*>(a.mplan_host)->total_pairs);
     size_t v0 = 0;
     for (int c = 0; c < a.n_chunks; ++c) {
         const PlanView pd = plan_dev_view(a.vplan_hosts[c], a.vplan_devs[c]);
         s = launch_simulate(ph[c], pd, a.sources, a.ws + w.arena, a.ws + w.mask, nullptr,
                             reinterpret_cast<float*>(a.ws + w.sim), st);
         if (s != XA_OK) return s;
+        // the first chunk's extraction set-up also clears the matcher's pair counts
         s = launch_extract(ph[c], pd, a.ws + w.arena, a.ws + w.mask, a.pattern, a.out.kp + v0 * N,
-                           a.out.desc + v0 * N * 32, a.out.count + v0, a.ws + w.ext, st);
+                           a.out.desc + v0 * N * 32, a.out.count + v0, a.ws + w.ext, st,
+                           c == 0 ? a.out.pair_count : nullptr, c == 0 ? n_pairs : 0);
         if (s != XA_OK) return s;
         v0 += size_t(ph[c].h->n_views);
     }
     return launch_match_plan(a.mplan_host, a.mplan_dev, a.out.desc, a.out.count, a.num, a.den, a.out.matches,
-                             a.out.pair_count, a.out.best, st);
+                             a.out.pair_count, a.out.best, st, true);
 }
 
 }  // namespace
